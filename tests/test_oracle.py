@@ -1,0 +1,415 @@
+"""Pins of the FP64 CPU oracle against what the mathematics fixes (no GPU).
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, closed forms, invariants, special cases that reduce to
+a LAPACK routine (numpy.linalg), brute-force definitions on small inputs and
+finite differences.  A plausible slip in the oracle (dropped term, wrong
+sign, transposed operand, wrong index) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import sigma_rel_err, max_principal_angle, orth_err, align_signs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+def planted(M, N, sigma, seed=0, noise=0.0):
+    g = rng(seed)
+    Phi, _ = np.linalg.qr(g.standard_normal((M, len(sigma))))
+    C, _ = np.linalg.qr(g.standard_normal((N, len(sigma))))
+    A = Phi @ np.diag(sigma) @ C.T
+    if noise:
+        A = A + noise * g.standard_normal((M, N))
+    return np.asfortranarray(A), Phi, C
+
+
+# ----------------------------------------------------------------------------
+# Test-matrix generator (Philox4x32-10 + Box-Muller)
+# ----------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            rows.append([int(x, 16) for x in line.split()])
+    assert len(rows) == 3
+    for r in rows:
+        assert oracle.philox4x32_10(r[0:4], r[4:6]) == r[6:10]
+
+
+def test_omega_box_muller_definition():
+    # Element pairs (2t, 2t+1) are the Box-Muller transform of the two 53-bit
+    # uniforms built from Philox call t with counter (t, 0, batch, 0).
+    seed, batch, n, ell = 0x1234_5678_9ABC, 3, 7, 3
+    Om = oracle.omega(seed, batch, n, ell, oracle.PREC_F64).ravel(order="F")
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for t in range((n * ell + 1) // 2):
+        x = oracle.philox4x32_10([t, 0, batch, 0], key)
+        u1 = ((x[0] >> 5) * 2.0 ** 26 + (x[1] >> 6)) * 2.0 ** -53
+        u2 = ((x[2] >> 5) * 2.0 ** 26 + (x[3] >> 6)) * 2.0 ** -53
+        rad = math.sqrt(-2.0 * math.log(1.0 - u1))
+        z = [rad * math.cos(2 * math.pi * u2), rad * math.sin(2 * math.pi * u2)]
+        for h in range(2):
+            e = 2 * t + h
+            if e < n * ell:
+                assert abs(Om[e] - z[h]) <= 1e-15 * max(1.0, abs(z[h]))
+
+
+def test_omega_statistics_and_rounding():
+    Om = oracle.omega(7, 0, 400, 250, oracle.PREC_F64)
+    assert abs(Om.mean()) < 0.01 and abs(Om.std() - 1.0) < 0.01
+    # Different batches and seeds give different draws; the same key repeats.
+    assert not np.array_equal(Om, oracle.omega(7, 1, 400, 250, oracle.PREC_F64))
+    assert not np.array_equal(Om, oracle.omega(8, 0, 400, 250, oracle.PREC_F64))
+    assert np.array_equal(Om, oracle.omega(7, 0, 400, 250, oracle.PREC_F64))
+    # float32: round-to-nearest of the double.
+    O32 = oracle.omega(7, 0, 400, 250, oracle.PREC_F32)
+    assert np.array_equal(O32, Om.astype(np.float32).astype(np.float64))
+    # bfloat16: the float32 value rounded to 8 significant bits, ties to even.
+    Ob = oracle.omega(7, 0, 400, 250, oracle.PREC_BF16)
+    f = O32.astype(np.float32).view(np.uint32)
+    lsb = (f >> 16) & 1
+    ref = ((f + 0x7FFF + lsb) & 0xFFFF0000).astype(np.uint32).view(np.float32).astype(np.float64)
+    assert np.array_equal(Ob, ref)
+    assert np.all((Ob.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
+
+
+# ----------------------------------------------------------------------------
+# Householder QR
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n", [(200, 50), (64, 64), (1000, 1), (37, 20)])
+def test_hhqr_invariants_and_lapack(m, n):
+    A = rng(m + n).standard_normal((m, n))
+    Q, R = oracle.hhqr(A)
+    tol = 1e-14 * math.sqrt(n)
+    assert np.linalg.norm(A - Q @ R) / np.linalg.norm(A) <= tol
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= tol * 10
+    assert np.all(np.diag(R) >= 0) and np.allclose(np.tril(R, -1), 0)
+    # Uniqueness of the positive-diagonal factorisation against LAPACK.
+    Ql, Rl = np.linalg.qr(A)
+    sgn = np.sign(np.diag(Rl))
+    sgn[sgn == 0] = 1
+    Ql, Rl = Ql * sgn, (Rl.T * sgn).T
+    assert np.abs(R - Rl).max() <= 1e-12 * np.abs(Rl).max()
+    assert np.abs(Q - Ql).max() <= 1e-12
+
+
+def test_hhqr_rank_deficient_and_zero_column():
+    g = rng(3)
+    A = g.standard_normal((50, 6))
+    A[:, 3] = A[:, 1] * 2.0          # dependent column
+    A[:, 5] = 0.0                    # zero column
+    Q, R = oracle.hhqr(A)
+    assert np.linalg.norm(A - Q @ R) <= 1e-13 * np.linalg.norm(A)
+    assert np.linalg.norm(Q.T @ Q - np.eye(6)) <= 1e-13
+    assert abs(R[3, 3]) <= 1e-13 and abs(R[5, 5]) <= 1e-13
+
+
+# ----------------------------------------------------------------------------
+# One-sided Jacobi SVD
+# ----------------------------------------------------------------------------
+
+def test_jacobi_closed_forms():
+    # Diagonal matrix: singular values are |d| sorted, vectors are +-e_i.
+    d = np.array([0.5, -3.0, 2.0, 0.0, 1.0])
+    U, s, V = oracle.jacobi_svd(np.diag(d))
+    assert np.allclose(s, [3.0, 2.0, 1.0, 0.5, 0.0], atol=0, rtol=0)
+    # Rank one sigma u v^T.
+    g = rng(1)
+    u = g.standard_normal(30); u /= np.linalg.norm(u)
+    v = g.standard_normal(8); v /= np.linalg.norm(v)
+    U, s, V = oracle.jacobi_svd(4.5 * np.outer(u, v))
+    assert abs(s[0] - 4.5) <= 1e-14 * 4.5 and np.all(s[1:] <= 1e-14)
+    assert abs(abs(U[:, 0] @ u) - 1) <= 1e-14 and abs(abs(V[:, 0] @ v) - 1) <= 1e-14
+    # 2x2 closed form: singular values of [[a, b], [0, c]].
+    a, b, c = 3.0, 4.0, 2.0
+    fro2, det = a * a + b * b + c * c, a * c
+    s1 = math.sqrt((fro2 + math.sqrt(fro2 ** 2 - 4 * det * det)) / 2)
+    s2 = abs(det) / s1
+    _, s, _ = oracle.jacobi_svd(np.array([[a, b], [0.0, c]]))
+    assert abs(s[0] - s1) <= 1e-15 * s1 and abs(s[1] - s2) <= 1e-14 * s2
+
+
+@pytest.mark.parametrize("m,n", [(200, 50), (50, 50), (120, 7)])
+def test_jacobi_vs_lapack(m, n):
+    A = rng(10 + n).standard_normal((m, n)) @ np.diag(np.logspace(0, -6, n))
+    U, s, V = oracle.jacobi_svd(A)
+    sl = np.linalg.svd(A, compute_uv=False)
+    assert sigma_rel_err(s, sl) <= 1e-13 * 10
+    assert np.linalg.norm(A - (U * s) @ V.T) / np.linalg.norm(A) <= 1e-13
+    assert orth_err(U) <= 1e-13 and orth_err(V) <= 1e-13
+    assert np.all(np.diff(s) <= 0)
+
+
+def test_jacobi_sweep_limit_reports_nonconvergence():
+    A = rng(2).standard_normal((40, 30))
+    with pytest.raises(RuntimeError, match="-6"):
+        oracle.jacobi_svd(A, max_sweeps=1)
+
+
+# ----------------------------------------------------------------------------
+# Deterministic streaming (Algorithm 1)
+# ----------------------------------------------------------------------------
+
+def test_planted_spectrum_recovered_exactly():
+    sig = 2.0 ** (-np.arange(12) / 2.0)
+    A, Phi, _ = planted(600, 40, sig, seed=5)
+    so = oracle.StreamOracle(600, 12).incorporate(A)
+    assert sigma_rel_err(so.singular_values, sig) <= 1e-12
+    assert max_principal_angle(so.modes, Phi) <= 1e-11
+
+
+@pytest.mark.parametrize("nb", [1, 2, 4])
+def test_stream_ff1_equals_batch_svd(nb):
+    # No truncation loss (K >= total rank): any batch split gives the SVD of the concatenation.
+    sig = np.linspace(2.0, 0.2, 8)
+    A, _, _ = planted(500, 64, sig, seed=11)
+    so = oracle.StreamOracle(500, 10, ff=1.0)
+    for b in np.split(np.arange(64), nb):
+        so.incorporate(A[:, b])
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    assert sigma_rel_err(so.singular_values[:8], sl[:8]) <= 1e-12
+    assert max_principal_angle(so.modes[:, :8], Ul[:, :8]) <= 1e-10
+
+
+def test_stream_forget_factor_closed_form():
+    # With no truncation loss, batch i's weight after the last batch is ff^(last-i).
+    ff = 0.9
+    sig = np.linspace(3.0, 0.5, 6)
+    A, _, _ = planted(300, 30, sig, seed=12)
+    parts = [A[:, :10], A[:, 10:20], A[:, 20:]]
+    so = oracle.StreamOracle(300, 12, ff=ff)
+    for p in parts:
+        so.incorporate(p)
+    W = np.hstack([ff ** 2 * parts[0], ff * parts[1], parts[2]])
+    Ul, sl, _ = np.linalg.svd(W, full_matrices=False)
+    assert sigma_rel_err(so.singular_values[:6], sl[:6]) <= 1e-12
+    assert max_principal_angle(so.modes[:, :6], Ul[:, :6]) <= 1e-10
+
+
+def test_stream_each_step_is_topk_svd_of_panel():
+    # With truncation loss (rank 20 > K = 10) every step of Algorithm 1 is the
+    # rank-K truncated SVD of its panel [ff U diag(s) | A_i]; pin each step
+    # against LAPACK on the panel built from the oracle's own previous state.
+    w = synth.scaled(synth.c1_plain_fp64(), M=512)
+    batches = [synth.numpy_cm(t) for t in synth.planted_stream(w)]
+    so = oracle.StreamOracle(w.M, w.K, ff=0.8)
+    for A in batches:
+        C = A if so.r == 0 else np.hstack([0.8 * so.modes * so.singular_values, A])
+        so.incorporate(A)
+        Ul, sl, _ = np.linalg.svd(C, full_matrices=False)
+        k = so.r
+        assert k == min(w.K, C.shape[1])
+        assert sigma_rel_err(so.singular_values, sl[:k]) <= 1e-12
+        U = align_signs(so.modes, Ul[:, :k])
+        assert np.abs(U - Ul[:, :k]).max() <= 1e-9
+        assert orth_err(so.modes) <= 1e-13
+
+
+def test_stream_sign_rule():
+    # Each column of the small left factor has its largest-magnitude entry positive.
+    A, _, _ = planted(200, 20, np.linspace(1, 0.1, 5), seed=4)
+    so = oracle.StreamOracle(200, 5).incorporate(A[:, :10]).incorporate(A[:, 10:])
+    Ut = so.last_small_u
+    for j in range(Ut.shape[1]):
+        col = Ut[:, j]
+        assert col[np.argmax(np.abs(col))] > 0
+
+
+def test_stream_metamorphic():
+    g = rng(21)
+    A = np.asfortranarray(g.standard_normal((150, 12)) @ np.diag(np.logspace(0, -2, 12)))
+    base = oracle.StreamOracle(150, 6).incorporate(A[:, :6]).incorporate(A[:, 6:])
+    # Scaling the data scales the singular values.
+    sc = oracle.StreamOracle(150, 6).incorporate(3 * A[:, :6]).incorporate(3 * A[:, 6:])
+    assert sigma_rel_err(sc.singular_values, 3 * base.singular_values) <= 1e-13
+    # A right orthogonal transform of a batch leaves the left data unchanged.
+    O, _ = np.linalg.qr(g.standard_normal((6, 6)))
+    rt = oracle.StreamOracle(150, 6).incorporate(A[:, :6] @ O).incorporate(A[:, 6:] @ O)
+    assert sigma_rel_err(rt.singular_values, base.singular_values) <= 1e-12
+    assert max_principal_angle(rt.modes[:, :4], base.modes[:, :4]) <= 1e-9
+    # A row permutation permutes the rows of U.
+    p = g.permutation(150)
+    pm = oracle.StreamOracle(150, 6).incorporate(A[p, :6]).incorporate(A[p, 6:])
+    assert sigma_rel_err(pm.singular_values, base.singular_values) <= 1e-12
+    assert np.abs(align_signs(pm.modes, base.modes[p]) - base.modes[p]).max() <= 1e-9
+
+
+def test_stream_empty_batch_is_noop():
+    so = oracle.StreamOracle(50, 3).incorporate(rng(0).standard_normal((50, 4)))
+    U, s = so.modes.copy(), so.singular_values.copy()
+    so.incorporate(np.zeros((50, 0)))
+    assert np.array_equal(U, so.modes) and np.array_equal(s, so.singular_values)
+
+
+# ----------------------------------------------------------------------------
+# Randomized streaming (Eqs. (7)-(11))
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_randomized_exact_when_rank_fits_sketch(q):
+    # rank(C) <= ell: Q spans range(C) for any Gaussian test matrix, so the
+    # randomized step is exact whatever q is.
+    sig = np.logspace(0, -1, 9)
+    A, Phi, _ = planted(400, 60, sig, seed=31)
+    so = oracle.StreamOracle(400, 8, oversampling=4, power_iters=q, randomized=True, seed=5)
+    so.incorporate(A)
+    assert sigma_rel_err(so.singular_values, sig[:8]) <= 1e-12
+    assert max_principal_angle(so.modes, Phi[:, :8]) <= 1e-10
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_randomized_equals_ritz_of_power_sketch(q):
+    # Closed form of what the range finder computes: Q = orth((C C^T)^q C Omega)
+    # and (U, s) = the top-K SVD of Q Q^T C.  Rank(C) > ell, so q matters.
+    g = rng(40 + q)
+    M, N, K, p = 300, 40, 6, 4
+    C = np.asfortranarray(g.standard_normal((M, N)) @ np.diag(np.linspace(1.0, 0.3, N)))
+    so = oracle.StreamOracle(M, K, oversampling=p, power_iters=q, randomized=True, seed=9)
+    Om = oracle.omega(9, 0, N, K + p, oracle.PREC_F64)
+    so.incorporate(C)
+    Y = C @ Om
+    for _ in range(q):
+        Y = C @ (C.T @ Y)
+    Q, _ = np.linalg.qr(Y)
+    Ub, sb, _ = np.linalg.svd(Q.T @ C, full_matrices=False)
+    assert sigma_rel_err(so.singular_values, sb[:K]) <= 1e-11
+    U = align_signs(so.modes, Q @ Ub[:, :K])
+    assert np.abs(U - Q @ Ub[:, :K]).max() <= 1e-9
+
+
+def test_randomized_power_iterations_reduce_error():
+    # Halko-Martinsson-Tropp: power iterations sharpen the sketch on a slowly
+    # decaying spectrum (statistical sanity check, fixed seeds).
+    g = rng(50)
+    M, N, K, p = 500, 120, 10, 5
+    A = np.asfortranarray(g.standard_normal((M, N)) @ np.diag(1.0 / np.arange(1, N + 1) ** 0.5))
+    s_true = np.linalg.svd(A, compute_uv=False)[:K]
+    errs = []
+    for q in (0, 1, 2):
+        so = oracle.StreamOracle(M, K, oversampling=p, power_iters=q, randomized=True, seed=3).incorporate(A)
+        errs.append(sigma_rel_err(so.singular_values, s_true))
+    assert errs[0] > errs[1] > errs[2]
+    assert np.all(so.singular_values <= s_true * (1 + 1e-12))   # Ritz values interlace
+
+
+def test_randomized_falls_back_when_sketch_is_wide():
+    A, _, _ = planted(100, 10, np.linspace(1, 0.1, 10), seed=2)
+    a = oracle.StreamOracle(100, 5, oversampling=8, randomized=True).incorporate(A)
+    b = oracle.StreamOracle(100, 5).incorporate(A)
+    assert np.array_equal(a.singular_values, b.singular_values)
+
+
+# ----------------------------------------------------------------------------
+# APMOS (Algorithm 2)
+# ----------------------------------------------------------------------------
+
+def test_apmos_exact_when_local_rank_fits():
+    w = synth.scaled(synth.c4_apmos(), partitions=5, part_min=300, part_max=700, N=48)
+    sizes = synth.partition_sizes(w)
+    parts = [synth.numpy_cm(t) for t in synth.apmos_partitions(w, sizes=sizes)]
+    A = np.vstack(parts)
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    U, Lam, X = oracle.apmos(parts, 40, 20)           # r = 40 >= local rank 40
+    assert sigma_rel_err(Lam, sl[:20]) <= 1e-11
+    Us = np.vstack(U)
+    assert max_principal_angle(Us, Ul[:, :20]) <= 1e-9
+    assert orth_err(Us) <= 1e-10
+
+
+def test_apmos_single_partition_is_svd():
+    A = np.asfortranarray(rng(6).standard_normal((400, 30)) @ np.diag(np.logspace(0, -3, 30)))
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    U, Lam, X = oracle.apmos([A], 30, 10)
+    assert sigma_rel_err(Lam, sl[:10]) <= 1e-12
+    assert np.abs(align_signs(U[0], Ul[:, :10]) - Ul[:, :10]).max() <= 1e-10
+    # The lift divides by Lambda: U^i = A^i X diag(1/Lambda).
+    assert np.allclose(U[0], A @ X / Lam, atol=1e-14)
+
+
+def test_apmos_truncated_local_rank_is_gram_of_W():
+    # With r < local rank, the global step is the SVD of W = [V_i S_i]: check X, Lambda against
+    # the eigen-decomposition of W W^T built from LAPACK local SVDs.
+    g = rng(8)
+    parts = [np.asfortranarray(g.standard_normal((m, 16)) @ np.diag(np.logspace(0, -2, 16))) for m in (90, 120, 70)]
+    r, K = 5, 6
+    Ws = []
+    for Ai in parts:
+        _, si, Vt = np.linalg.svd(Ai, full_matrices=False)
+        Ws.append(Vt.T[:, :r] * si[:r])
+    W = np.hstack(Ws)
+    Xl, ll, _ = np.linalg.svd(W, full_matrices=False)
+    U, Lam, X = oracle.apmos(parts, r, K)
+    assert sigma_rel_err(Lam, ll[:K]) <= 1e-12
+    assert np.abs(align_signs(X, Xl[:, :K]) - Xl[:, :K]).max() <= 1e-10
+
+
+# ----------------------------------------------------------------------------
+# Loss and gradient
+# ----------------------------------------------------------------------------
+
+def test_gradient_single_batch_closed_form():
+    # One exact truncated SVD: L = ||A||^2 - sum s_j^2 + sum w_j s_j,
+    # dL/dA = 2A - U_K (2 S_K - diag(w)) V_K^T.
+    w = synth.scaled(synth.c5_gradient(), M=300, N=40, batches=1, K=5)
+    A = np.asfortranarray(synth.numpy_cm(synth.planted_stream(w)[0]))
+    wt = synth.loss_weights(w)
+    G = oracle.stream_grad(A, w.K, 1.0, 1, wt)
+    Ul, sl, Vt = np.linalg.svd(A, full_matrices=False)
+    K = w.K
+    ref = 2 * A - Ul[:, :K] @ np.diag(2 * sl[:K] - wt) @ Vt[:K]
+    assert np.linalg.norm(G - ref) / np.linalg.norm(ref) <= 1e-10
+    L, _, s = oracle.stream_loss(A, K, 1.0, 1, wt)
+    assert abs(L - (np.sum(A * A) - np.sum(sl[:K] ** 2) + wt @ sl[:K])) <= 1e-11 * abs(L)
+
+
+def test_gradient_stream_matches_finite_differences():
+    # Streaming with truncation: reverse mode against central differences
+    # along random directions (||D|| = ||A||, h = 1e-3 relative) and single coordinates.
+    w = synth.scaled(synth.c5_gradient(), M=512, N=16, batches=4, K=6)
+    A = np.hstack([synth.numpy_cm(t) for t in synth.planted_stream(w)])
+    A = np.asfortranarray(A)
+    wt = synth.loss_weights(w)
+    G = oracle.stream_grad(A, w.K, 1.0, w.batches, wt)
+    g = rng(77)
+    h = 1e-3
+    for t in range(8):
+        D = g.standard_normal(A.shape)
+        D *= np.linalg.norm(A) / np.linalg.norm(D)
+        lp = oracle.stream_loss(A + h * D, w.K, 1.0, w.batches, wt)[0]
+        lm = oracle.stream_loss(A - h * D, w.K, 1.0, w.batches, wt)[0]
+        fd = (lp - lm) / (2 * h)
+        an = float(np.sum(G * D))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (t, fd, an)
+    for t in range(8):
+        i, j = int(g.integers(A.shape[0])), int(g.integers(A.shape[1]))
+        hh = 1e-5
+        Ap = A.copy(); Ap[i, j] += hh
+        Am = A.copy(); Am[i, j] -= hh
+        fd = (oracle.stream_loss(Ap, w.K, 1.0, w.batches, wt)[0] - oracle.stream_loss(Am, w.K, 1.0, w.batches, wt)[0]) / (2 * hh)
+        assert abs(fd - G[i, j]) <= 1e-6 * max(1.0, np.abs(G).max()), (i, j, fd, G[i, j])
+
+
+def test_gradient_stream_with_forget_factor():
+    w = synth.scaled(synth.c5_gradient(), M=200, N=10, batches=3, K=4)
+    A = np.asfortranarray(np.hstack([synth.numpy_cm(t) for t in synth.planted_stream(w)]))
+    wt = synth.loss_weights(w)
+    ff = 0.9
+    G = oracle.stream_grad(A, w.K, ff, w.batches, wt)
+    D = rng(5).standard_normal(A.shape)
+    h = 1e-4
+    fd = (oracle.stream_loss(A + h * D, w.K, ff, w.batches, wt)[0] - oracle.stream_loss(A - h * D, w.K, ff, w.batches, wt)[0]) / (2 * h)
+    assert abs(fd - np.sum(G * D)) <= 1e-6 * max(1.0, abs(fd))
