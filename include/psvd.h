@@ -1,0 +1,231 @@
+/*
+ * psvd.h -- C ABI of the MI355X (gfx950) streaming / randomized / partitioned
+ * SVD library, after Maulik & Mengaldo, "PyParSVD: a streaming, distributed
+ * and randomized singular-value-decomposition library" (arXiv 2108.08845).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are column-major: element (i, j) of a matrix with leading
+ *    dimension ld is at base[i + j*ld]; each snapshot (column) is contiguous.
+ *    A contiguous torch tensor of shape (N, M) is the M x N matrix.
+ *  - Device pointers are HIP device memory owned by the caller unless stated
+ *    otherwise; host pointers are ordinary host memory.
+ *  - All device work is enqueued on the stream given at creation (NULL: the
+ *    default stream).  Calls that return host data synchronise that stream.
+ *  - Return value: PSVD_OK (0) or a negative psvd_status.  No exception
+ *    crosses the ABI.  A failed call leaves the handle's state unchanged; the
+ *    text of the last error is available from psvd_last_error().
+ *  - Errors detected on the device (non-finite data, a step that cannot
+ *    proceed) are reported by the call that detects them; with
+ *    PSVD_OPT_ASYNC set they surface at the next synchronising call.
+ *  - One handle is used by one host thread at a time.
+ */
+#ifndef PSVD_H
+#define PSVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psvd_handle psvd_handle;
+
+typedef enum psvd_status {
+    PSVD_OK = 0,
+    PSVD_E_INVAL = -1,      /* invalid argument value                            */
+    PSVD_E_SHAPE = -2,      /* inconsistent sizes / leading dimensions           */
+    PSVD_E_DTYPE = -3,      /* unsupported element type for this precision       */
+    PSVD_E_NOMEM = -4,      /* device or host allocation failed                  */
+    PSVD_E_NONFINITE = -5,  /* NaN or Inf reached the small factorisations       */
+    PSVD_E_NOCONV = -6,     /* Jacobi SVD did not converge within max_sweeps     */
+    PSVD_E_BREAKDOWN = -7,  /* Cholesky breakdown with the fallback disabled      */
+    PSVD_E_DEVICE = -8,     /* HIP runtime error                                 */
+    PSVD_E_STATE = -9       /* call not valid in the handle's current state      */
+} psvd_status;
+
+typedef enum psvd_dtype { PSVD_F32 = 1, PSVD_F64 = 2 } psvd_dtype;
+
+typedef enum psvd_method {
+    PSVD_DETERMINISTIC = 0, /* QR of the panel + SVD of R (Algorithm 1)          */
+    PSVD_RANDOMIZED = 1     /* randomized range finder on the panel (Eqs. 7-11)  */
+} psvd_method;
+
+typedef enum psvd_precision {
+    PSVD_PREC_FP64 = 0,     /* every product in FP64; state U in FP64            */
+    PSVD_PREC_FP32 = 1,     /* panel products in FP32 (MFMA), small core FP64    */
+    PSVD_PREC_MIXED = 2     /* power passes in BF16 (MFMA, FP32 accumulation),
+                               final projection and lift in FP32, small core FP64 */
+} psvd_precision;
+
+enum {
+    PSVD_OPT_ASYNC = 1,        /* do not synchronise at the end of each update     */
+    PSVD_OPT_NO_FALLBACK = 2,  /* report Cholesky breakdown instead of falling back */
+    PSVD_OPT_PROFILE = 4       /* time each tall-panel kernel with HIP events      */
+};
+
+/* Kernel classes timed with PSVD_OPT_PROFILE (index into psvd_stats_t arrays). */
+enum {
+    PSVD_KC_FUSED_BF16 = 0,    /* C^T (C X) in BF16 (power passes, mixed)         */
+    PSVD_KC_FUSED_F32 = 1,     /* C^T (C X) and (C X)^T (C X) in FP32             */
+    PSVD_KC_LIFT = 2,          /* U <- C T                                         */
+    PSVD_KC_TN = 3,            /* reductions over the tall rows (Gram, C^T Y)     */
+    PSVD_KC_NN = 4,            /* other tall products (C X written out)           */
+    PSVD_KC_SMALL = 5,         /* small-core kernels                              */
+    PSVD_KC_COUNT = 8
+};
+
+typedef struct psvd_options {
+    int32_t method;         /* psvd_method                                       */
+    int32_t precision;      /* psvd_precision                                    */
+    uint64_t seed;          /* key of the Gaussian test matrices                 */
+    void* stream;           /* hipStream_t; NULL = default stream                */
+    int32_t max_sweeps;     /* Jacobi sweep limit (default 60)                   */
+    int32_t flags;          /* PSVD_OPT_* bits                                   */
+    int32_t tile_rows;      /* 0 = autotuned / default row-tile height           */
+    int32_t reserved;
+} psvd_options;
+
+typedef struct psvd_stats_t {
+    int64_t batches;            /* updates applied                               */
+    int64_t fallbacks;          /* Cholesky breakdowns handled by the eigen route */
+    int32_t last_sweeps;        /* Jacobi sweeps of the last small SVD           */
+    int32_t last_path;          /* 0 deterministic, 1 randomized                 */
+    double last_update_ms;      /* device time of the last update (events)       */
+    int64_t kernel_launches[8]; /* per kernel class (PSVD_OPT_PROFILE)           */
+    double kernel_ms[8];        /* summed device time per kernel class           */
+} psvd_stats_t;
+
+/* Fill *opt with defaults: deterministic, FP64, seed 0, default stream. */
+void psvd_default_options(psvd_options* opt);
+
+/*
+ * Create a streaming-SVD state for snapshots of M rows keeping K modes
+ * (Algorithm 1 of Sec. 3.1: forget factor ff weights the previous modes,
+ * 0 < ff <= 1).  oversampling p and power_iters q configure the randomized
+ * range finder of Sec. 3.3 (sketch width K + p).  The state starts empty
+ * (rank r = 0).  The library owns U (M x K, double-buffered), the singular
+ * values and all workspace.  Errors: PSVD_E_INVAL (K < 1, K > M, ff outside
+ * (0, 1], p < 0, q < 0, unknown method/precision), PSVD_E_NOMEM.
+ */
+int psvd_initialize(psvd_handle** h, int64_t M, int32_t K, double ff, int32_t oversampling, int32_t power_iters,
+                    const psvd_options* opt);
+
+/*
+ * Ingest one batch A (M x N, device, column-major, leading dimension
+ * lda >= M, element type dtype).  With r = 0 this is the initialisation
+ * (steps I1-I2 of Algorithm 1: factor A alone); otherwise steps 1-5 on the
+ * panel [ff * U diag(s) | A].  Deterministic method: tall-skinny QR of the
+ * panel (Cholesky-QR twice, eigen route on breakdown), one-sided Jacobi SVD
+ * of R, keep K, U <- Q U~_K.  Randomized method with K + p < r + N: sketch
+ * Y = panel * Omega with the batch's Gaussian test matrix, q power
+ * iterations, projection B = Q^T panel, Jacobi SVD of B, U <- Q U~_K
+ * (Eqs. 7-11); otherwise the deterministic step.  Afterwards
+ * r = min(K, r + N).  A is read on the handle's stream and must stay valid
+ * until the stream passes this call.  N = 0 is a no-op.
+ * Errors: PSVD_E_SHAPE (M mismatch, lda < M, r + N > M), PSVD_E_DTYPE
+ * (PSVD_F64 data with a non-FP64 precision), PSVD_E_NONFINITE, PSVD_E_NOCONV,
+ * PSVD_E_BREAKDOWN, PSVD_E_DEVICE.
+ */
+int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, int64_t lda, int32_t dtype);
+
+/* Current rank r (0 before the first batch). */
+int psvd_rank(const psvd_handle* h, int32_t* r);
+
+/*
+ * Copy the r singular values (descending, FP64) to host memory out
+ * (capacity cap >= r); *r receives the rank.  Synchronises the stream.
+ */
+int psvd_singular_values(const psvd_handle* h, double* out, int32_t cap, int32_t* r);
+
+/*
+ * Copy the M x r modes U into caller device memory (leading dimension
+ * ldu >= M) converted to dtype.  Enqueued on the handle's stream.
+ */
+int psvd_modes(const psvd_handle* h, void* U, int64_t ldu, int32_t dtype);
+
+/*
+ * Borrowed pointer to the library's current U (M x r, column-major, leading
+ * dimension *ldu, element type *dtype).  Valid until the next update or
+ * psvd_finalize.
+ */
+int psvd_modes_ptr(const psvd_handle* h, const void** U, int64_t* ldu, int32_t* dtype);
+
+/*
+ * The Gaussian test matrix the handle uses for update number `batch` on a
+ * panel of n columns (n x (K + p), column-major, FP64 values exactly as the
+ * device consumes them) -- Sec. 3.3's random matrix, from the counter-based
+ * generator Philox4x32-10 (Salmon et al., SC'11) keyed by (seed, batch) and
+ * Box-Muller, rounded to the precision's input type.  out: host memory.
+ */
+int psvd_get_omega(const psvd_handle* h, int64_t batch, int64_t n, double* out);
+
+/* Metrics of the handle (host copy); synchronises the stream when profiling. */
+int psvd_stats(const psvd_handle* h, psvd_stats_t* out);
+
+/* Zero the counters of psvd_stats (not the state). */
+int psvd_reset_stats(psvd_handle* h);
+
+/* Text of the last error on this handle ("" if none).  Owned by the handle. */
+const char* psvd_last_error(const psvd_handle* h);
+
+/* Static name of a status code. */
+const char* psvd_status_string(int status);
+
+/* Release the handle and everything it owns (NULL is allowed). */
+void psvd_finalize(psvd_handle* h);
+
+/*
+ * Approximate partitioned method of snapshots (Algorithm 2, Eqs. 3-6) over P
+ * row partitions of one data set, all on this GPU, in one enqueued sequence:
+ *   1. G_i = A_i^T A_i (method of snapshots, the option of Sec. 3.2) and its
+ *      eigen-decomposition by one-sided Jacobi -> V_i, sigma_i;
+ *   2. W_i = V_i[:, :r] diag(sigma_i[:r]);  W = [W_1 ... W_P]  (N x P r);
+ *   3. W = X Lambda Y^T;  X~ = X[:, :K], Lambda~ = Lambda[:K];
+ *   4. U_i = A_i X~ diag(1 / Lambda~).
+ * A_parts[i]: device, M_parts[i] x N, leading dimension ld_parts[i] >= M_i,
+ * element type dtype (PSVD_F32 or PSVD_F64).  U_parts[i]: device output
+ * M_parts[i] x K (leading dimension ldu_parts[i], same dtype).  Lambda (K)
+ * and X (N x K, column-major) are host outputs (may be NULL).  Pointer
+ * arrays are host arrays.  Synchronises the stream.
+ * Errors: PSVD_E_INVAL (P < 1, r < 1, r > N, K < 1, K > min(N, P r),
+ * Lambda~_K <= N 2^-53 Lambda~_1), PSVD_E_SHAPE, PSVD_E_NOCONV, PSVD_E_NOMEM,
+ * PSVD_E_DEVICE.
+ */
+int psvd_apmos_batched(int32_t P, const void* const* A_parts, const int64_t* M_parts, const int64_t* ld_parts,
+                       int64_t N, int32_t dtype, int32_t r, int32_t K, void* const* U_parts,
+                       const int64_t* ldu_parts, double* Lambda, double* X, void* stream);
+
+/*
+ * Reverse-mode derivative of the deterministic stream (Algorithm 1 with the
+ * QR + SVD(R) step) over B equal batches of Nb columns of A (device,
+ * M x B*Nb, leading dimension lda, dtype) with K modes and forget factor ff:
+ * given cotangents U_bar (device, M x r, leading dimension M, dtype) of the
+ * final modes and s_bar (host, r values) of the final singular values,
+ * writes A_bar (device, M x B*Nb, leading dimension M, dtype).  Each batch's
+ * panel is recomputed from the stored incoming state (memory O(M K) per
+ * batch) and the adjoint of its thin SVD is applied,
+ *   C_bar = U [diag(s_bar) + (F o (U^T U_bar - U_bar^T U)) S] V^T
+ *           + (I - U U^T) U_bar S^-1 V^T,   F_ij = 1 / (s_j^2 - s_i^2),
+ * with F used only for pairs that touch a retained index and guarded at
+ * near-degenerate pairs.  Synchronises the stream.
+ */
+int psvd_stream_backward(const void* A, int64_t M, int64_t lda, int32_t dtype, int32_t B, int64_t Nb, int32_t K,
+                         double ff, const void* U_bar, const double* s_bar, void* A_bar, void* stream);
+
+/*
+ * Loss of the streamed truncated SVD and its gradient, entirely on the
+ * device: L = ||A - U U^T A||_F^2 + sum_{j<r} w_j s_j, with (U, s) the
+ * deterministic stream over B batches of Nb columns (K modes, ff), the
+ * residual evaluated as ||A||^2 - sum_b ||U^T A_b||^2.  w: host, K weights.
+ * loss: host scalar (may be NULL).  grad: device M x B*Nb (leading
+ * dimension M, dtype), may be NULL for the loss alone.  Synchronises.
+ */
+int psvd_loss_grad(const void* A, int64_t M, int64_t lda, int32_t dtype, int32_t B, int64_t Nb, int32_t K,
+                   double ff, const double* w, double* loss, void* grad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSVD_H */

@@ -108,7 +108,8 @@ static double round_bf16_from_float(float f)
  *   u1 = ((x0>>5)*2^26 + (x1>>6)) * 2^-53,  u2 likewise from (x2, x3),
  * and Box-Muller gives
  *   z0 = sqrt(-2 ln(1-u1)) cos(2 pi u2)   -> element 2t
- *   z1 = sqrt(-2 ln(1-u1)) sin(2 pi u2)   -> element 2t+1.
+ *   z1 = sqrt(-2 ln(1-u1)) sin(2 pi u2)   -> element 2t+1,
+ * with log, cos and sin from the C library, each by its own call.
  * precision 0 keeps the double, 1 rounds to float (RNE), 2 rounds to float
  * and then to bfloat16 (both RNE).
  */
@@ -125,7 +126,10 @@ void orc_omega(uint64_t seed, int64_t batch, int64_t n, int64_t ell, int precisi
         double u1 = ((double)(x[0] >> 5) * 67108864.0 + (double)(x[1] >> 6)) * (1.0 / 9007199254740992.0);
         double u2 = ((double)(x[2] >> 5) * 67108864.0 + (double)(x[3] >> 6)) * (1.0 / 9007199254740992.0);
         double rad = sqrt(-2.0 * log(1.0 - u1));
-        double z[2] = {rad * cos(two_pi * u2), rad * sin(two_pi * u2)};
+        /* cos and sin each by its own libm call (a volatile argument keeps the
+           compiler from merging them into sincos, whose last bit may differ). */
+        volatile double ang = two_pi * u2;
+        double z[2] = {rad * cos(ang), rad * sin(ang)};
         for (int h = 0; h < 2; ++h) {
             int64_t e = 2 * t + h;
             if (e >= total) break;

@@ -1,0 +1,244 @@
+"""MI355X streaming / randomized / partitioned SVD (after arXiv 2108.08845, "PyParSVD").
+
+Python surface over the C ABI of include/psvd.h.  Matrices follow the paper's
+orientation -- a batch A is M x N (rows are grid points, columns snapshots) --
+stored column-major on the GPU: pass `X.T` for a contiguous torch tensor X of
+shape (N, M).  PyTorch only provides device memory and the stream.
+
+    svd = StreamingSVD(M, K, ff=0.95, oversampling=10, power_iters=2,
+                       randomized=True, precision="mixed", seed=1)
+    svd.initialize(A0)             # Algorithm 1, steps I1-I2
+    svd.incorporate_data(A1)       # Algorithm 1, steps 1-5 (per batch)
+    U, s = svd.modes, svd.singular_values
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PsvdError
+
+__all__ = ["StreamingSVD", "apmos_batched", "PsvdError", "stream_backward", "loss_and_grad", "StreamingSVDFunction"]
+
+_PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32, "mixed": _lib.PREC_MIXED}
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _as_colmajor(A):
+    """(M, N) CUDA tensor -> (pointer, M, N, lda, dtype code, keep-alive tensor), column-major."""
+    if not isinstance(A, torch.Tensor) or not A.is_cuda:
+        raise TypeError("expected a CUDA tensor of shape (M, N)")
+    if A.dim() != 2:
+        raise ValueError("expected a 2-D (M, N) tensor")
+    if A.dtype not in (torch.float32, torch.float64):
+        raise TypeError("dtype must be float32 or float64")
+    M, N = A.shape
+    if not (A.stride(0) == 1 and (N <= 1 or A.stride(1) >= M)):
+        A = A.t().contiguous().t()          # layout copy only
+    lda = max(A.stride(1) if N > 1 else M, M)
+    code = _lib.PSVD_F64 if A.dtype == torch.float64 else _lib.PSVD_F32
+    return ctypes.c_void_p(A.data_ptr()), M, N, lda, code, A
+
+
+class StreamingSVD:
+    """Streaming truncated SVD of Algorithm 1 on one GPU (handle of the C library).
+
+    ff: forget factor in (0, 1].  randomized: use the randomized range finder
+    (sketch width K + oversampling, `power_iters` power iterations) whenever it
+    is narrower than the panel.  precision: "fp64", "fp32" or "mixed".
+    """
+
+    def __init__(self, M, K, ff=1.0, oversampling=0, power_iters=0, randomized=False, precision="fp64",
+                 seed=0, stream=None, async_updates=False, max_sweeps=60, fallback=True, profile=False):
+        self._libh = _lib.load()
+        opt = _lib.Options()
+        self._libh.psvd_default_options(ctypes.byref(opt))
+        opt.method = _lib.RANDOMIZED if randomized else _lib.DETERMINISTIC
+        opt.precision = _PREC[precision]
+        opt.seed = int(seed)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        opt.stream = _stream_ptr(self._stream).value
+        opt.max_sweeps = int(max_sweeps)
+        opt.flags = ((_lib.OPT_ASYNC if async_updates else 0) | (0 if fallback else _lib.OPT_NO_FALLBACK)
+                     | (_lib.OPT_PROFILE if profile else 0))
+        h = ctypes.c_void_p()
+        rc = self._libh.psvd_initialize(ctypes.byref(h), int(M), int(K), float(ff), int(oversampling),
+                                        int(power_iters), ctypes.byref(opt))
+        _lib.check(rc, None, "psvd_initialize")
+        self._h = h
+        self.M, self.K, self.ff = int(M), int(K), float(ff)
+        self.oversampling, self.power_iters = int(oversampling), int(power_iters)
+        self.randomized, self.precision, self.seed = bool(randomized), precision, int(seed)
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._libh.psvd_finalize(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def incorporate_data(self, A):
+        """Ingest one batch A (M x N CUDA tensor, column-major preferred)."""
+        ptr, M, N, lda, code, keep = _as_colmajor(A)
+        self._keep = keep   # the update reads A on the stream
+        rc = self._libh.psvd_incorporate_data(self._h, ptr, M, N, lda, code)
+        _lib.check(rc, self._h, "incorporate_data")
+        return self
+
+    def initialize(self, A):
+        """First batch (steps I1-I2 of Algorithm 1); same as incorporate_data on an empty state."""
+        if self.rank != 0:
+            raise PsvdError(-9, "initialize() on a non-empty state")
+        return self.incorporate_data(A)
+
+    @property
+    def rank(self):
+        r = ctypes.c_int32()
+        _lib.check(self._libh.psvd_rank(self._h, ctypes.byref(r)), self._h)
+        return int(r.value)
+
+    @property
+    def singular_values(self):
+        r = self.rank
+        out = np.zeros(max(r, 1), dtype=np.float64)
+        rr = ctypes.c_int32()
+        rc = self._libh.psvd_singular_values(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             out.size, ctypes.byref(rr))
+        _lib.check(rc, self._h, "singular_values")
+        return out[:rr.value].copy()
+
+    def modes_as(self, dtype=None):
+        r = self.rank
+        dt = dtype or (torch.float64 if self.precision == "fp64" else torch.float32)
+        out = torch.empty((r, self.M), dtype=dt, device="cuda")
+        if r:
+            code = _lib.PSVD_F64 if dt == torch.float64 else _lib.PSVD_F32
+            rc = self._libh.psvd_modes(self._h, ctypes.c_void_p(out.data_ptr()), self.M, code)
+            _lib.check(rc, self._h, "modes")
+        return out.t()
+
+    @property
+    def modes(self):
+        """M x r modes (column-major CUDA tensor, a copy)."""
+        return self.modes_as()
+
+    def omega(self, batch, n):
+        """The Gaussian test matrix of update `batch` on an n-column panel (numpy, n x (K + p))."""
+        ell = self.K + self.oversampling
+        out = np.zeros((ell, n), dtype=np.float64)   # column-major n x ell
+        rc = self._libh.psvd_get_omega(self._h, int(batch), int(n), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        _lib.check(rc, self._h, "get_omega")
+        return out.T
+
+    def stats(self):
+        s = _lib.Stats()
+        _lib.check(self._libh.psvd_stats(self._h, ctypes.byref(s)), self._h)
+        out = {k: getattr(s, k) for k, _ in _lib.Stats._fields_[:5]}
+        out["kernels"] = {name: {"launches": int(s.kernel_launches[i]), "ms": float(s.kernel_ms[i])}
+                          for i, name in enumerate(_lib.KERNEL_CLASSES)}
+        return out
+
+    def reset_stats(self):
+        _lib.check(self._libh.psvd_reset_stats(self._h), self._h)
+
+    @property
+    def last_error(self):
+        return self._libh.psvd_last_error(self._h).decode()
+
+
+def apmos_batched(parts, r, K, stream=None):
+    """Algorithm 2 over row partitions (list of M_i x N CUDA tensors, same dtype).
+
+    Returns (U_parts, Lambda, X): U_parts[i] is M_i x K (column-major),
+    Lambda the K global singular values, X the N x K right factor.
+    """
+    lib = _lib.load()
+    P = len(parts)
+    if P == 0:
+        raise ValueError("no partitions")
+    cols = [_as_colmajor(p) for p in parts]
+    N = cols[0][2]
+    code = cols[0][4]
+    dt = parts[0].dtype
+    outs = [torch.empty((K, c[1]), dtype=dt, device="cuda") for c in cols]
+    A_ptrs = (ctypes.c_void_p * P)(*[c[0].value for c in cols])
+    Ms = (ctypes.c_int64 * P)(*[c[1] for c in cols])
+    lds = (ctypes.c_int64 * P)(*[c[3] for c in cols])
+    U_ptrs = (ctypes.c_void_p * P)(*[o.data_ptr() for o in outs])
+    ldus = (ctypes.c_int64 * P)(*[c[1] for c in cols])
+    Lam = np.zeros(K)
+    X = np.zeros((K, N))
+    rc = lib.psvd_apmos_batched(P, A_ptrs, Ms, lds, N, code, int(r), int(K), U_ptrs, ldus,
+                                Lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(stream))
+    _lib.check(rc, None, "apmos_batched")
+    return [o.t() for o in outs], Lam, np.ascontiguousarray(X.T)
+
+
+def stream_backward(A, batches, K, ff, U_bar, s_bar, stream=None):
+    """dL/dA of the deterministic stream given cotangents of its final (U, s) (see psvd.h)."""
+    lib = _lib.load()
+    ptr, M, Nt, lda, code, keep = _as_colmajor(A)
+    dt = A.dtype
+    Ub = U_bar.to(dtype=dt).t().contiguous()            # (r, M) -> column-major M x r
+    sb = np.ascontiguousarray(np.asarray(s_bar, dtype=np.float64))
+    out = torch.empty((Nt, M), dtype=dt, device="cuda")
+    rc = lib.psvd_stream_backward(ptr, M, lda, code, int(batches), Nt // int(batches), int(K), float(ff),
+                                  ctypes.c_void_p(Ub.data_ptr()), sb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _lib.check(rc, None, "stream_backward")
+    return out.t()
+
+
+def loss_and_grad(A, batches, K, ff, w, want_grad=True, stream=None):
+    """L = ||A - U U^T A||^2 + sum w_j s_j of the deterministic stream, and dL/dA, on the device."""
+    lib = _lib.load()
+    ptr, M, Nt, lda, code, keep = _as_colmajor(A)
+    wv = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    L = ctypes.c_double(0.0)
+    out = torch.empty((Nt, M), dtype=A.dtype, device="cuda") if want_grad else None
+    rc = lib.psvd_loss_grad(ptr, M, lda, code, int(batches), Nt // int(batches), int(K), float(ff),
+                            wv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(L),
+                            ctypes.c_void_p(out.data_ptr()) if want_grad else None, _stream_ptr(stream))
+    _lib.check(rc, None, "loss_grad")
+    return L.value, (out.t() if want_grad else None)
+
+
+class StreamingSVDFunction(torch.autograd.Function):
+    """(U, s) = deterministic stream of A over `batches` equal batches; backward by the library's adjoint."""
+
+    @staticmethod
+    def forward(ctx, A, batches, K, ff):
+        M, Nt = A.shape
+        svd = StreamingSVD(M, K, ff=ff, precision="fp64" if A.dtype == torch.float64 else "fp32")
+        nb = Nt // batches
+        for b in range(batches):
+            svd.incorporate_data(A[:, b * nb:(b + 1) * nb])
+        U = svd.modes.clone()
+        s = torch.from_numpy(svd.singular_values).to(A.device)
+        svd.close()
+        ctx.save_for_backward(A)
+        ctx.batches, ctx.K, ctx.ff = batches, K, ff
+        return U, s
+
+    @staticmethod
+    def backward(ctx, U_bar, s_bar):
+        (A,) = ctx.saved_tensors
+        r = U_bar.shape[1]
+        if s_bar is None:
+            s_bar = torch.zeros(r, dtype=torch.float64)
+        if U_bar is None:
+            U_bar = torch.zeros((A.shape[0], r), dtype=A.dtype, device=A.device)
+        g = stream_backward(A, ctx.batches, ctx.K, ctx.ff, U_bar, s_bar.detach().double().cpu().numpy())
+        return g, None, None, None

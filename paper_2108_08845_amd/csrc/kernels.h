@@ -1,0 +1,182 @@
+// kernels.h -- argument blocks and launchers of the device kernels.
+#pragma once
+
+#include "psvd_internal.h"
+
+namespace psvd {
+
+constexpr int TN_OB = 64;   // output block edge of k_tn
+constexpr int FU_LB = 64;   // sketch columns per work-group of k_fused
+
+// Output block y of a blocked product -> (block row, block col).
+__host__ __device__ inline void block_coords(int y, int mbl, int sym, int* bi, int* bj) {
+    if (!sym) {
+        *bi = y % mbl;
+        *bj = y / mbl;
+        return;
+    }
+    int j = 0;
+    while ((j + 1) * (j + 2) / 2 <= y) ++j;
+    *bj = j;
+    *bi = y - j * (j + 1) / 2;
+}
+
+struct TnArgs {
+    PanelSeg lseg, rseg;     // single-segment operands (used when lsegs == nullptr)
+    const PanelSeg* lsegs;   // L operand segments (device array) or nullptr
+    const PanelSeg* rsegs;   // R operand segments
+    const WorkItem* items;   // explicit work items or nullptr: item i = rows [i*chunk, (i+1)*chunk)
+    int64_t chunk;
+    int32_t mbl;             // output blocks along the rows of the result (ceil(nl / 64))
+    int32_t sym;             // only blocks (i <= j) are computed
+    double* part;            // [item][ob] 64 x 64 column-major FP64
+    const int32_t* skip;     // if non-null and *skip & skip_mask: do nothing
+    int32_t skip_mask;
+    int32_t nob;
+};
+
+struct TnReduceArgs {
+    const double* row_scale;    // output rows gi < nscale multiplied by row_scale[gi] (not with sym)
+    int32_t nscale;
+    const double* part;
+    const int32_t* seg_item0;   // first item of each segment (size nseg + 1), or nullptr: items [0, nitems)
+    int32_t nitems;
+    int32_t mbl;
+    int32_t nob;
+    int32_t nl, nr;
+    int32_t sym;
+    double* out;                // nseg consecutive nl x nr matrices
+    const int32_t* skip;
+    int32_t skip_mask;
+};
+
+struct NnArgs {
+    PanelSeg seg;        // single segment (used when segs == nullptr)
+    const PanelSeg* segs;
+    const WorkItem* items;
+    int64_t chunk;
+    const double* row_scale;  // optional: output row i < nscale multiplied by row_scale[i]
+    int32_t nscale;
+    const double* X;     // n x nx, column-major, ld ldx (shared by all segments)
+    int64_t ldx;
+    int32_t n;           // rows of X used (= panel columns)
+    int32_t nx;          // output columns
+    const int32_t* skip;
+    int32_t skip_mask;
+};
+
+struct FusedArgs {
+    PanelSeg seg;            // panel (FP32 blocks)
+    const double* X;         // n x lx, ld ldx (logical operand, already scaled)
+    int64_t ldx;
+    int32_t n, np;           // panel columns, padded to 16
+    int32_t lx;              // columns of X
+    int32_t nlb;             // column blocks (ceil(lx / 64))
+    int32_t tm;              // rows per tile (16 or 32)
+    int32_t nwg;             // work-groups per column block
+    int64_t tiles;           // ceil(rows / tm)
+    float* partP;            // [wg][lb] np x 64 column-major
+    double* partG;           // [wg] 64 x 64 (only when nlb == 1 and G requested)
+    int32_t want_g;          // FP32 compute type only
+};
+
+struct FusedReduceArgs {
+    const double* row_scale;   // P rows i < nscale multiplied by row_scale[i] (may be null)
+    int32_t nscale;
+    const float* partP;
+    const double* partG;
+    int32_t nwg, nlb, np, n, lx;
+    int32_t want_g;
+    double* P;
+    double* G;
+};
+
+struct SmallArgs {
+    int32_t n;            // panel columns r + N
+    int32_t r;            // current rank (columns of the U part)
+    int32_t K;
+    int32_t l;            // sketch width (randomized)
+    int32_t max_sweeps;
+    int32_t allow_fallback;
+    const double* d;      // d[j] = ff * s_j, j < r (column scale of the U part)
+    double* G;            // n x n (deterministic Gram, then work)
+    double* G2;           // n x n
+    double* R1;           // n x n
+    double* Ri;           // n x n
+    double* Z;            // n x n Jacobi work
+    double* T;            // n x K  (lift operand, already scaled by D)
+    double* Xn;           // n x n  (pass-2 operand D R1^-1)
+    double* s_out;        // K new singular values
+    double* small_u;      // n x K small left factor after the sign rule (diagnostics)
+    double* vec;          // 4n scratch
+    int32_t* ivec;        // n scratch
+    int32_t* status;      // DevStatus bits
+    int32_t* sweeps;      // last Jacobi sweep count
+};
+
+struct CholArgs {
+    double* H;          // l x l input (overwritten by R)
+    double* Ri;         // l x l output R^-1
+    int32_t l;
+    int32_t* status;
+    int32_t flag_bit;   // status bit on breakdown
+};
+
+struct RandFinalArgs {
+    int32_t l, K;
+    int32_t max_sweeps;
+    const double* RY;     // l x l
+    const double* RYi;    // l x l
+    const double* R1;     // l x l  first Cholesky factor of P^T P
+    double* H2;           // l x l  second Gram (overwritten)
+    double* Z;            // l x l work
+    double* M2;           // l x K out: R_Y^-1 U~_K
+    double* s_out;        // K
+    double* small_u;      // l x K
+    double* vec;          // 2l
+    int32_t* ivec;        // l
+    int32_t* status;
+    int32_t* sweeps;
+};
+
+struct ApmosLocalArgs {
+    double* G;          // P consecutive N x N Grams (destroyed)
+    double* Wt;         // (P r) x N, column-major: row block i = W_i^T
+    int32_t N, r, P;
+    int32_t max_sweeps;
+    double* vec;        // P * 2N
+    int32_t* ivec;      // P * N
+    int32_t* status;
+    int32_t* sweeps;
+};
+
+struct ApmosGlobalArgs {
+    double* WW;         // N x N = W W^T (destroyed)
+    int32_t N, K;
+    int32_t max_sweeps;
+    double* T;          // N x K: X~ diag(1 / Lambda~)
+    double* Lam;        // K
+    double* X;          // N x K
+    double* vec;        // 2N
+    int32_t* ivec;      // N
+    int32_t* status;
+    int32_t* sweeps;
+};
+
+hipError_t launch_tn(bool fp64, const TnArgs& a, int nitems, hipStream_t st);
+hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st);
+hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st);
+bool fused_fits(bool bf16, int tm, int np);
+hipError_t launch_fused(bool bf16, const FusedArgs& a, hipStream_t st);
+hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st);
+
+hipError_t launch_small_det1(const SmallArgs& a, hipStream_t st);
+hipError_t launch_small_det2(const SmallArgs& a, hipStream_t st);
+hipError_t launch_small_chol(const CholArgs& a, hipStream_t st);
+hipError_t launch_small_rand_final(const RandFinalArgs& a, hipStream_t st);
+hipError_t launch_scale_rows(double* X, int n, int m, int ldx, const double* d, int r, int times, hipStream_t st);
+hipError_t launch_make_scale(double* d, const double* s, int r, double ff, hipStream_t st);
+hipError_t launch_apmos_local(const ApmosLocalArgs& a, hipStream_t st);
+hipError_t launch_apmos_global(const ApmosGlobalArgs& a, hipStream_t st);
+
+}  // namespace psvd

@@ -1,0 +1,528 @@
+// panel.hip -- tall-skinny panel kernels on the gfx950 matrix cores.
+//
+// A "panel" is up to three column-major column blocks sharing rows (see
+// PanelSeg).  Three kernels cover every pass over the tall data:
+//   k_tn     Z = L^T R over row ranges (Gram C^T C, projection C^T Y, Y^T Y):
+//            per-work-item partial sums, summed afterwards in a fixed order
+//            (no floating-point atomics; results are run-to-run identical).
+//   k_nn     Y = C X (sketch, lift U <- C T, APMOS lift), written per segment.
+//   k_fused  P = C^T (C X) [and G = (C X)^T (C X)] in one read of C: the
+//            row tile is staged once in LDS, Y_tile = C_tile X stays on chip
+//            and feeds P += C_tile^T Y_tile (the range-finder passes).
+// Row tiles are staged through LDS with coalesced column-segment loads; the
+// next tile is prefetched into registers while the matrix cores work.
+#include "kernels.h"
+
+namespace psvd {
+
+// ----------------------------------------------------------------------------
+// Column pointer lookup (block-uniform per column).
+// ----------------------------------------------------------------------------
+struct ColRef {
+    const char* base;  // column base
+    int32_t dtype;
+};
+
+__device__ __forceinline__ ColRef col_ref(const PanelSeg& s, int c) {
+    ColRef r{nullptr, PSVD_F32};
+    int cc = c;
+    for (int b = 0; b < s.nblk; ++b) {
+        const PanelBlock& B = s.blk[b];
+        if (cc < B.ncols) {
+            int esz = B.dtype == PSVD_F64 ? 8 : 4;
+            r.base = (const char*)B.ptr + (size_t)cc * (size_t)B.ld * esz;
+            r.dtype = B.dtype;
+            return r;
+        }
+        cc -= B.ncols;
+    }
+    return r;
+}
+
+__device__ __forceinline__ WorkItem get_item(const WorkItem* items, int64_t chunk, int64_t rows) {
+    if (items) return items[blockIdx.x];
+    WorkItem w;
+    w.seg = 0;
+    w.pad = 0;
+    w.row0 = (int64_t)blockIdx.x * chunk;
+    w.row1 = w.row0 + chunk < rows ? w.row0 + chunk : rows;
+    return w;
+}
+
+__device__ __forceinline__ double ld_col(const ColRef& r, int64_t i) {
+    return r.dtype == PSVD_F64 ? ((const double*)r.base)[i] : (double)((const float*)r.base)[i];
+}
+
+// ----------------------------------------------------------------------------
+// k_tn: partial[item][ob] = L[rows, lcols]^T R[rows, rcols], 64 x 64 blocks.
+// grid.x = work items, grid.y = output blocks (list in obl/obr).
+// ----------------------------------------------------------------------------
+constexpr int TN_TM = 64;
+constexpr int TN_PAD = 1;
+
+
+template <class CT>
+__global__ __launch_bounds__(256) void k_tn(TnArgs a) {
+    using MF = Mfma<CT>;
+    using E = typename MF::elem;
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    __shared__ E Ls[TN_OB * (TN_TM + TN_PAD)];
+    __shared__ E Rs[TN_OB * (TN_TM + TN_PAD)];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const WorkItem it = get_item(a.items, a.chunk, a.lseg.rows);
+    const PanelSeg& L = a.lsegs ? a.lsegs[it.seg] : a.lseg;
+    const PanelSeg& R = a.rsegs ? a.rsegs[it.seg] : a.rseg;
+    const int ob = blockIdx.y;
+    int obi, obj;
+    block_coords(ob, a.mbl, a.sym, &obi, &obj);
+    const int lc0 = obi * TN_OB, rc0 = obj * TN_OB;
+
+    typename MF::acc acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = typename MF::acc{0, 0, 0, 0};
+
+    // Per-thread load slots: 64 columns x 64 rows = 4096 elements per operand,
+    // 16 per thread; consecutive threads read consecutive rows of a column.
+    constexpr int PER = TN_OB * TN_TM / 256;
+    double pl[PER], pr[PER];
+    auto fetch = [&](int64_t r0) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int idx = e * 256 + tid;
+            int c = idx / TN_TM, rr = idx % TN_TM;
+            int64_t row = r0 + rr;
+            double vl = 0.0, vr = 0.0;
+            if (row < it.row1) {
+                if (lc0 + c < L.ncols) vl = ld_col(col_ref(L, lc0 + c), row);
+                if (rc0 + c < R.ncols) vr = ld_col(col_ref(R, rc0 + c), row);
+            }
+            pl[e] = vl;
+            pr[e] = vr;
+        }
+    };
+    fetch(it.row0);
+    for (int64_t r0 = it.row0; r0 < it.row1; r0 += TN_TM) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int idx = e * 256 + tid;
+            int c = idx / TN_TM, rr = idx % TN_TM;
+            Ls[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pl[e]);
+            Rs[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pr[e]);
+        }
+        __syncthreads();
+        if (r0 + TN_TM < it.row1) fetch(r0 + TN_TM);
+        // wave w: output tile row block w, column blocks 0..3
+#pragma unroll 4
+        for (int k0 = 0; k0 < TN_TM; k0 += MF::KSTEP) {
+            E av = Ls[(w * 16 + (lane & 15)) * (TN_TM + TN_PAD) + k0 + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                E bv = Rs[(j * 16 + (lane & 15)) * (TN_TM + TN_PAD) + k0 + (lane >> 4)];
+                acc[j] = MF::mma(av, bv, acc[j]);
+            }
+        }
+    }
+    double* out = a.part + ((size_t)blockIdx.x * a.nob + ob) * (TN_OB * TN_OB);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int row = w * 16 + MF::row_of(lane, v);
+            int col = j * 16 + (lane & 15);
+            out[row + col * TN_OB] = (double)acc[j][v];
+        }
+}
+
+// Sum the partials of all items of each segment in item order and scatter the
+// 64 x 64 blocks into dense FP64 outputs out[seg] (nl x nr, ld nl); Gram
+// (sym != 0): the lower block triangle is mirrored from the upper one.
+
+__global__ __launch_bounds__(256) void k_tn_reduce(TnReduceArgs a) {
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    const int seg = blockIdx.y, ob = blockIdx.z;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= TN_OB * TN_OB) return;
+    const int i = e % TN_OB, j = e / TN_OB;
+    int obi, obj;
+    block_coords(ob, a.mbl, a.sym, &obi, &obj);
+    const int gi = obi * TN_OB + i, gj = obj * TN_OB + j;
+    if (gi >= a.nl || gj >= a.nr) return;
+    double s = 0.0;
+    const int it0 = a.seg_item0 ? a.seg_item0[seg] : 0;
+    const int it1 = a.seg_item0 ? a.seg_item0[seg + 1] : a.nitems;
+    for (int it = it0; it < it1; ++it)
+        s += a.part[((size_t)it * a.nob + ob) * (TN_OB * TN_OB) + e];
+    double* o = a.out + (size_t)seg * a.nl * a.nr;
+    if (a.row_scale && gi < a.nscale) s *= a.row_scale[gi];
+    o[gi + (size_t)gj * a.nl] = s;
+    if (a.sym && obi != obj) o[gj + (size_t)gi * a.nl] = s;
+}
+
+// ----------------------------------------------------------------------------
+// k_nn: out[seg rows, ocols] = C[rows, :] X[:, ocols] (+ optional row scale).
+// grid.x = work items, grid.y = output column blocks of 64.
+// ----------------------------------------------------------------------------
+constexpr int NN_TM = 64;
+constexpr int NN_KC = 32;
+constexpr int NN_OB = 64;
+
+
+template <class CT>
+__global__ __launch_bounds__(256) void k_nn(NnArgs a) {
+    using MF = Mfma<CT>;
+    using E = typename MF::elem;
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    __shared__ E Cs[NN_KC * (NN_TM + 1)];
+    __shared__ E Xs[NN_OB * (NN_KC + 1)];
+    __shared__ double Os[NN_OB * (NN_TM + 1)];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const WorkItem it = get_item(a.items, a.chunk, a.seg.rows);
+    const PanelSeg& S = a.segs ? a.segs[it.seg] : a.seg;
+    const int oc0 = blockIdx.y * NN_OB;
+    for (int64_t r0 = it.row0; r0 < it.row1; r0 += NN_TM) {
+        typename MF::acc acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = typename MF::acc{0, 0, 0, 0};
+        for (int k0 = 0; k0 < a.n; k0 += NN_KC) {
+            __syncthreads();
+            // C chunk: 32 columns x 64 rows (8 per thread)
+#pragma unroll
+            for (int e = 0; e < NN_KC * NN_TM / 256; ++e) {
+                int idx = e * 256 + tid;
+                int c = idx / NN_TM, rr = idx % NN_TM;
+                int64_t row = r0 + rr;
+                double v = 0.0;
+                if (row < it.row1 && k0 + c < a.n) v = ld_col(col_ref(S, k0 + c), row);
+                Cs[c * (NN_TM + 1) + rr] = MF::from_double(v);
+            }
+            // X chunk: 32 rows x 64 columns
+#pragma unroll
+            for (int e = 0; e < NN_KC * NN_OB / 256; ++e) {
+                int idx = e * 256 + tid;
+                int k = idx % NN_KC, j = idx / NN_KC;
+                double v = 0.0;
+                if (k0 + k < a.n && oc0 + j < a.nx) v = a.X[(k0 + k) + (int64_t)(oc0 + j) * a.ldx];
+                Xs[j * (NN_KC + 1) + k] = MF::from_double(v);
+            }
+            __syncthreads();
+            // wave w: output row block w (16 rows), column blocks 0..3
+#pragma unroll
+            for (int kk = 0; kk < NN_KC; kk += MF::KSTEP) {
+                E av = Cs[(kk + (lane >> 4)) * (NN_TM + 1) + w * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    E bv = Xs[(j * 16 + (lane & 15)) * (NN_KC + 1) + kk + (lane >> 4)];
+                    acc[j] = MF::mma(av, bv, acc[j]);
+                }
+            }
+        }
+        // Stage the output tile through LDS for coalesced column stores.
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int row = w * 16 + MF::row_of(lane, v);
+                int col = j * 16 + (lane & 15);
+                Os[col * (NN_TM + 1) + row] = (double)acc[j][v];
+            }
+        __syncthreads();
+        for (int idx = tid; idx < NN_OB * NN_TM; idx += 256) {
+            int rr = idx % NN_TM, j = idx / NN_TM;
+            int64_t row = r0 + rr;
+            if (row < it.row1 && oc0 + j < a.nx) {
+                double v = Os[j * (NN_TM + 1) + rr];
+                if (a.row_scale && row < a.nscale) v *= a.row_scale[row];
+                size_t o = (size_t)row + (size_t)(oc0 + j) * (size_t)S.ldo;
+                if (S.out_dtype == PSVD_F64) ((double*)S.out)[o] = v;
+                else ((float*)S.out)[o] = (float)v;
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// k_fused: P = C^T (C X) and optionally G = (C X)^T (C X), one read of C.
+// CT = bf16_t (power passes of the mixed precision) or float.
+// One column block of LB = 64 columns of X per work-group (grid.y > 1 splits
+// wider sketches; consecutive blocks of a row range run on the same XCD).
+// ----------------------------------------------------------------------------
+
+
+template <class MF>
+__device__ __forceinline__ typename MF::frag lds_frag(const typename MF::elem* p) {
+    if constexpr (MF::KPL == 1) {
+        return *p;
+    } else {
+        uint64_t u = *(const uint64_t*)p;  // 4 bf16, 8-byte aligned by construction
+        return __builtin_bit_cast(s4_t, u);
+    }
+}
+
+template <class CT, int TM, int NTW, int NPMAX>
+__global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
+    using MF = Mfma<CT>;
+    using E = typename MF::elem;
+    constexpr int KPL = MF::KPL;
+    constexpr int KSTEP = MF::KSTEP;
+    constexpr bool ROWMAJOR_COPY = (KPL > 1);
+    constexpr bool CAN_G = (sizeof(E) == 4);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int np = a.np;
+    const int ldX = np + 4;        // X block: column-major, k contiguous
+    const int ldC = TM + 4;        // C tile: column-major (rows contiguous)
+    const int ldR = np + 4;        // C tile row-major copy (bf16 only)
+    const int ldY = TM + 4;        // Y tile: column-major
+    E* Xs = (E*)smem;
+    E* Cs = Xs + (size_t)FU_LB * ldX;
+    E* Cr = Cs + (size_t)np * ldC;
+    E* Ys = Cr + (ROWMAJOR_COPY ? (size_t)TM * ldR : 0);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // XCD-aware mapping: consecutive dispatch slots of one XCD take the column
+    // blocks of the same row range so the second read of a tile hits its L2.
+    const int b = blockIdx.x;
+    const int xcd = b & 7, local = b >> 3;
+    const int lb = local % a.nlb;
+    const int wg = (local / a.nlb) * 8 + xcd;
+    if (wg >= a.nwg) return;
+    const int c0 = lb * FU_LB;
+    const bool want_g = CAN_G && a.want_g;
+
+    // X block -> LDS (compute type), zero padded.
+    for (int idx = tid; idx < FU_LB * np; idx += 256) {
+        int k = idx % np, j = idx / np;
+        double v = 0.0;
+        if (k < a.n && c0 + j < a.lx) v = a.X[k + (int64_t)(c0 + j) * a.ldx];
+        Xs[j * ldX + k] = MF::from_double(v);
+    }
+
+    // P accumulators: wave w owns row blocks rb = w, w+4, ... and all 4 column blocks.
+    const int nrb = np / 16;
+    typename MF::acc accP[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) accP[t] = typename MF::acc{0, 0, 0, 0};
+    d4_t accG[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) accG[j] = d4_t{0, 0, 0, 0};
+
+    // Prefetch registers: the TM x np tile, consecutive threads on consecutive rows.
+    constexpr int PFMAX = (TM * NPMAX + 255) / 256;
+    float pf[PFMAX];
+    const int per = (TM * np + 255) / 256;
+    auto fetch = [&](int64_t t) {
+        int64_t r0 = t * TM;
+#pragma unroll
+        for (int e = 0; e < PFMAX; ++e) {
+            float v = 0.f;
+            if (e < per) {
+                int idx = e * 256 + tid;
+                int c = idx / TM, rr = idx % TM;
+                int64_t row = r0 + rr;
+                if (c < a.n && row < a.seg.rows) {
+                    ColRef cr = col_ref(a.seg, c);
+                    v = ((const float*)cr.base)[row];
+                }
+            }
+            pf[e] = v;
+        }
+    };
+
+    int64_t t = wg;
+    if (t < a.tiles) fetch(t);
+    for (; t < a.tiles; t += a.nwg) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < PFMAX; ++e) {
+            if (e < per) {
+                int idx = e * 256 + tid;
+                int c = idx / TM, rr = idx % TM;
+                if (c < np) {
+                    E v = MF::from_float(pf[e]);
+                    Cs[c * ldC + rr] = v;
+                    if (ROWMAJOR_COPY) Cr[rr * ldR + c] = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (t + a.nwg < a.tiles) fetch(t + a.nwg);
+
+        // Phase A: Y_tile (TM x 64) = C_tile (TM x np) X (np x 64);
+        // wave w computes column block w for all TM / 16 row blocks.
+        {
+            typename MF::acc accY[TM / 16];
+#pragma unroll
+            for (int i = 0; i < TM / 16; ++i) accY[i] = typename MF::acc{0, 0, 0, 0};
+            for (int k0 = 0; k0 < np; k0 += KSTEP) {
+                typename MF::frag bv = lds_frag<MF>(&Xs[(w * 16 + (lane & 15)) * ldX + k0 + (lane >> 4) * KPL]);
+#pragma unroll
+                for (int i = 0; i < TM / 16; ++i) {
+                    typename MF::frag av;
+                    if constexpr (KPL == 1) av = Cs[(k0 + (lane >> 4)) * ldC + i * 16 + (lane & 15)];
+                    else av = lds_frag<MF>(&Cr[(i * 16 + (lane & 15)) * ldR + k0 + (lane >> 4) * KPL]);
+                    accY[i] = MF::mma(av, bv, accY[i]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < TM / 16; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int row = i * 16 + MF::row_of(lane, v);
+                    int col = w * 16 + (lane & 15);
+                    Ys[col * ldY + row] = MF::from_acc(accY[i][v]);
+                }
+        }
+        __syncthreads();
+
+        // Phase B: P (np x 64) += C_tile^T Y_tile.
+#pragma unroll
+        for (int k0 = 0; k0 < TM; k0 += KSTEP) {
+            typename MF::frag bvs[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bvs[j] = lds_frag<MF>(&Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4) * KPL]);
+#pragma unroll
+            for (int q = 0; q < NTW / 4; ++q) {
+                int rb = w + 4 * q;
+                if (rb < nrb) {
+                    typename MF::frag av = lds_frag<MF>(&Cs[(rb * 16 + (lane & 15)) * ldC + k0 + (lane >> 4) * KPL]);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) accP[q * 4 + j] = MF::mma(av, bvs[j], accP[q * 4 + j]);
+                }
+            }
+        }
+        // G (64 x 64) += Y^T Y in FP64 on the FP32 values of the Y tile.
+        if constexpr (CAN_G) {
+            if (want_g) {
+#pragma unroll
+                for (int k0 = 0; k0 < TM; k0 += 4) {
+                    double av = (double)*(const float*)&Ys[(w * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        double bv = (double)*(const float*)&Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+                        accG[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accG[j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // Write this work-group's partials.
+    float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)np * FU_LB;
+#pragma unroll
+    for (int q = 0; q < NTW / 4; ++q) {
+        int rb = w + 4 * q;
+        if (rb < nrb) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int row = rb * 16 + MF::row_of(lane, v);
+                    int col = j * 16 + (lane & 15);
+                    outP[row + (size_t)col * np] = accP[q * 4 + j][v];
+                }
+        }
+    }
+    if (want_g) {
+        double* outG = a.partG + (size_t)wg * FU_LB * FU_LB;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int row = w * 16 + Mfma<double>::row_of(lane, v);
+                int col = j * 16 + (lane & 15);
+                outG[row + col * FU_LB] = accG[j][v];
+            }
+    }
+}
+
+// Fixed-order FP64 sum of the fused partials: P (n x lx, ld n) and G (lx x lx).
+
+__global__ __launch_bounds__(256) void k_fused_reduce(FusedReduceArgs a) {
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t totP = (int64_t)a.n * a.lx;
+    if (e < totP) {
+        int i = (int)(e % a.n), j = (int)(e / a.n);
+        int lb = j / FU_LB, jj = j % FU_LB;
+        double s = 0.0;
+        for (int g = 0; g < a.nwg; ++g) s += (double)a.partP[((size_t)g * a.nlb + lb) * (size_t)a.np * FU_LB + i + (size_t)jj * a.np];
+        if (a.row_scale && i < a.nscale) s *= a.row_scale[i];
+        a.P[i + (size_t)j * a.n] = s;
+    } else if (a.want_g && e < totP + (int64_t)a.lx * a.lx) {
+        int64_t f = e - totP;
+        int i = (int)(f % a.lx), j = (int)(f / a.lx);
+        double s = 0.0;
+        for (int g = 0; g < a.nwg; ++g) s += a.partG[(size_t)g * FU_LB * FU_LB + i + (size_t)j * FU_LB];
+        a.G[i + (size_t)j * a.lx] = s;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Host launchers.
+// ----------------------------------------------------------------------------
+size_t fused_lds_bytes(int ct_bytes, bool rowcopy, int tm, int np) {
+    size_t e = (size_t)FU_LB * (np + 4) + (size_t)np * (tm + 4) + (rowcopy ? (size_t)tm * (np + 4) : 0) +
+               (size_t)FU_LB * (tm + 4);
+    return e * ct_bytes;
+}
+
+hipError_t launch_tn(bool fp64, const TnArgs& a, int nitems, hipStream_t st) {
+    dim3 grid(nitems, a.nob);
+    if (fp64) hipLaunchKernelGGL(k_tn<double>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_tn<float>, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st) {
+    dim3 grid((TN_OB * TN_OB + 255) / 256, nseg, a.nob);
+    hipLaunchKernelGGL(k_tn_reduce, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
+    dim3 grid(nitems, (a.nx + NN_OB - 1) / NN_OB);
+    if (fp64) hipLaunchKernelGGL(k_nn<double>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_nn<float>, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <class CT, int TM, int NTW, int NPMAX>
+static hipError_t launch_fused_k(const FusedArgs& a, size_t lds, hipStream_t st) {
+    int blocks = ((a.nwg + 7) / 8) * 8 * a.nlb;
+    hipError_t e = hipFuncSetAttribute((const void*)k_fused<CT, TM, NTW, NPMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fused<CT, TM, NTW, NPMAX>), dim3(blocks), dim3(256), lds, st, a);
+    return hipGetLastError();
+}
+
+template <class CT, int TM>
+static hipError_t launch_fused_t(const FusedArgs& a, size_t lds, hipStream_t st) {
+    if (a.np <= 128) return launch_fused_k<CT, TM, 8, 128>(a, lds, st);
+    if (a.np <= 320) return launch_fused_k<CT, TM, 20, 320>(a, lds, st);
+    if (a.np <= 640) return launch_fused_k<CT, TM, 40, 640>(a, lds, st);
+    return hipErrorInvalidValue;
+}
+
+bool fused_fits(bool bf16, int tm, int np) {
+    return np <= 640 && fused_lds_bytes(bf16 ? 2 : 4, bf16, tm, np) <= 160 * 1024;
+}
+
+hipError_t launch_fused(bool bf16, const FusedArgs& a, hipStream_t st) {
+    size_t lds = fused_lds_bytes(bf16 ? 2 : 4, bf16, a.tm, a.np);
+    if (bf16) {
+        if (a.tm == 16) return launch_fused_t<bf16_t, 16>(a, lds, st);
+        return launch_fused_t<bf16_t, 32>(a, lds, st);
+    }
+    if (a.tm == 16) return launch_fused_t<float, 16>(a, lds, st);
+    return launch_fused_t<float, 32>(a, lds, st);
+}
+
+hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st) {
+    int64_t tot = (int64_t)a.n * a.lx + (a.want_g ? (int64_t)a.lx * a.lx : 0);
+    dim3 grid((unsigned)((tot + 255) / 256));
+    hipLaunchKernelGGL(k_fused_reduce, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace psvd

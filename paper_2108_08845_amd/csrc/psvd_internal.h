@@ -1,0 +1,148 @@
+// psvd_internal.h -- shared device/host definitions of the gfx950 library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/psvd.h"
+
+namespace psvd {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// ----------------------------------------------------------------------------
+// Matrix-core (MFMA) tiles, 16 x 16 output per wave.
+//   A operand (16 x K): lane l supplies row (l % 16), k = (l / 16) * KPL + v.
+//   B operand (K x 16): lane l supplies column (l % 16), same k.
+//   Result: lane l holds column (l % 16) and, for v = 0..3, row
+//     row_of(l, v) = 4 * (l / 16) + v          (f32 accumulators)
+//     row_of(l, v) = (l / 16) + 4 * v          (f64 accumulators)
+// (lane layouts checked on gfx950 hardware).
+// ----------------------------------------------------------------------------
+struct bf16_t {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <class CT>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+    using elem = double;
+    using acc = d4_t;
+    using frag = double;
+    static constexpr int KPL = 1;
+    static constexpr int KSTEP = 4;
+    __device__ static __forceinline__ acc mma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row_of(int lane, int v) { return (lane >> 4) + 4 * v; }
+    __device__ static __forceinline__ elem from_double(double x) { return x; }
+    __device__ static __forceinline__ elem from_float(float x) { return (double)x; }
+    __device__ static __forceinline__ elem from_acc(double x) { return x; }
+};
+
+template <>
+struct Mfma<float> {
+    using elem = float;
+    using acc = f4_t;
+    using frag = float;
+    static constexpr int KPL = 1;
+    static constexpr int KSTEP = 4;
+    __device__ static __forceinline__ acc mma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+    __device__ static __forceinline__ elem from_double(double x) { return (float)x; }
+    __device__ static __forceinline__ elem from_float(float x) { return x; }
+    __device__ static __forceinline__ elem from_acc(float x) { return x; }
+};
+
+template <>
+struct Mfma<bf16_t> {
+    using elem = uint16_t;
+    using acc = f4_t;
+    using frag = s4_t;
+    static constexpr int KPL = 4;
+    static constexpr int KSTEP = 16;
+    __device__ static __forceinline__ acc mma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+    __device__ static __forceinline__ elem from_double(double x) { return f32_to_bf16_rne((float)x); }
+    __device__ static __forceinline__ elem from_float(float x) { return f32_to_bf16_rne(x); }
+    __device__ static __forceinline__ elem from_acc(float x) { return f32_to_bf16_rne(x); }
+};
+
+// ----------------------------------------------------------------------------
+// Panels: up to three column blocks that share rows, e.g. [U | A] of the
+// streaming update, [C | U_bar] of the adjoint, or one partition A_i.
+// ----------------------------------------------------------------------------
+constexpr int kMaxBlocks = 3;
+
+struct PanelBlock {
+    const void* ptr;  // column-major
+    int64_t ld;
+    int32_t dtype;    // PSVD_F32 / PSVD_F64
+    int32_t ncols;
+};
+
+struct PanelSeg {
+    PanelBlock blk[kMaxBlocks];
+    int32_t nblk;
+    int32_t ncols;    // sum of blk[].ncols
+    int64_t rows;
+    void* out;        // output rows of this segment (lift), column-major
+    int64_t ldo;
+    int32_t out_dtype;
+    int32_t pad;
+};
+
+struct WorkItem {
+    int32_t seg;
+    int32_t pad;
+    int64_t row0;
+    int64_t row1;
+};
+
+template <class T>
+__device__ __forceinline__ double load_elem(const void* p, int64_t idx, int32_t dtype) {
+    return dtype == PSVD_F64 ? ((const double*)p)[idx] : (double)((const float*)p)[idx];
+}
+
+// Column c of the panel segment, row i (0 outside the segment's rows).
+__device__ __forceinline__ const PanelBlock* block_of(const PanelSeg& s, int c, int* local) {
+    int cc = c;
+    for (int b = 0; b < s.nblk; ++b) {
+        if (cc < s.blk[b].ncols) {
+            *local = cc;
+            return &s.blk[b];
+        }
+        cc -= s.blk[b].ncols;
+    }
+    *local = -1;
+    return nullptr;
+}
+
+// Status word shared by the kernels of one update.
+enum DevStatus : int32_t {
+    DEV_OK = 0,
+    DEV_FALLBACK = 1,     // Cholesky breakdown handled by the eigen route
+    DEV_NONFINITE = 2,
+    DEV_NOCONV = 4,
+    DEV_BREAKDOWN = 8,
+    DEV_SMALL_LAMBDA = 16
+};
+
+}  // namespace psvd

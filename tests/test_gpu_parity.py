@@ -1,0 +1,254 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Same seeded inputs on both sides; the randomized paths use the identical test
+matrices (bit-checked).  Tolerances (sigma relative error over modes above
+the numerical-rank floor):
+  FP64 path 1e-10, FP32 path 1e-4, mixed path 2e-3 on every mode and 1e-5 on
+  the modes the range finder resolves (relative gap to the sketch tail).
+Subspaces are compared by the largest principal angle over leading modes
+separated by a spectral gap; orthonormality ||U^T U - I||_F is checked on the
+output modes.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from conftest import sigma_rel_err, max_principal_angle, orth_err, gap_limited_k
+
+pytestmark = pytest.mark.gpu
+
+
+def lib():
+    import paper_2108_08845_amd as P
+    return P
+
+
+def to_gpu(t):
+    """(N, M) contiguous tensor -> (M, N) column-major CUDA view."""
+    return t.to("cuda").t()
+
+
+def run_gpu(w, batches, precision, randomized, M=None, seed=None, **kw):
+    P = lib()
+    svd = P.StreamingSVD(M or w.M, w.K, ff=w.ff, oversampling=w.oversampling, power_iters=w.power_iters,
+                         randomized=randomized, precision=precision, seed=w.seed if seed is None else seed, **kw)
+    for b in batches:
+        svd.incorporate_data(to_gpu(b))
+    U = svd.modes.double().cpu().numpy()
+    s = svd.singular_values
+    return svd, U, s
+
+
+def run_oracle(w, batches, randomized, omega_precision, seed=None):
+    so = oracle.StreamOracle(w.M, w.K, ff=w.ff, oversampling=w.oversampling, power_iters=w.power_iters,
+                             randomized=randomized, seed=w.seed if seed is None else seed,
+                             omega_precision=omega_precision)
+    for b in batches:
+        so.incorporate(synth.numpy_cm(b))
+    return so
+
+
+def compare(U, s, so, tol_sigma, tol_orth, name=""):
+    s_ref = so.singular_values
+    assert len(s) == len(s_ref), (name, len(s), len(s_ref))
+    e = sigma_rel_err(s, s_ref)
+    assert e <= tol_sigma, f"{name}: sigma rel err {e:.3e} > {tol_sigma:.1e}"
+    oe = orth_err(U)
+    assert oe <= tol_orth, f"{name}: ||U^T U - I|| {oe:.3e} > {tol_orth:.1e}"
+    k = gap_limited_k(s_ref, tol_sigma, len(s_ref))
+    if k > 0:
+        gap = (s_ref[k - 1] - s_ref[k]) / s_ref[0] if k < len(s_ref) else 1.0
+        ang = max_principal_angle(U[:, :k], so.modes[:, :k])
+        bound = max(10 * tol_sigma * s_ref[0] / gap, 1e-12)
+        assert ang <= bound, f"{name}: principal angle {ang:.3e} > {bound:.3e} (k={k})"
+    return e
+
+
+# ----------------------------------------------------------------------------
+# Test matrix parity (bit exact)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,prec_code", [("fp64", 0), ("fp32", 1), ("mixed", 2)])
+def test_omega_bit_identical(precision, prec_code):
+    P = lib()
+    svd = P.StreamingSVD(1000, 10, oversampling=5, randomized=True, precision=precision, seed=0xDEADBEEF12)
+    for batch, n in [(0, 40), (3, 77), (1 << 33, 15)]:
+        g = svd.omega(batch, n)
+        o = oracle.omega(0xDEADBEEF12, batch, n, 15, prec_code)
+        assert np.array_equal(g, o)
+
+
+# ----------------------------------------------------------------------------
+# Deterministic streaming (Algorithm 1)
+# ----------------------------------------------------------------------------
+
+def test_c1_fp64_full_size():
+    w = synth.c1_plain_fp64()
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "fp64", False)
+    so = run_oracle(w, batches, False, oracle.PREC_F64)
+    compare(U, s, so, 1e-10, 1e-12, "c1")
+
+
+@pytest.mark.parametrize("M,N,nb,K,ff", [(4097, 64, 4, 10, 1.0), (1000, 1, 12, 5, 0.9), (333, 37, 3, 40, 0.95),
+                                           (129, 64, 2, 64, 1.0)])
+def test_det_fp64_ragged(M, N, nb, K, ff):
+    w = synth.scaled(synth.c1_plain_fp64(), M=M, N=N, batches=nb, K=K, ff=ff)
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "fp64", False)
+    so = run_oracle(w, batches, False, oracle.PREC_F64)
+    compare(U, s, so, 1e-10, 1e-12, f"det M={M} N={N}")
+
+
+def test_det_fp32_c5_shape():
+    w = synth.scaled(synth.c5_gradient(), M=1 << 15)
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "fp32", False)
+    so = run_oracle(w, batches, False, oracle.PREC_F64)
+    compare(U, s, so, 1e-4, 1e-5, "det fp32")
+
+
+def test_det_rank_deficient_falls_back():
+    # Duplicate and zero snapshots make the first Gram singular: the eigen
+    # route must take over and still match the oracle on the nonzero modes.
+    g = torch.Generator().manual_seed(3)
+    M, K = 2000, 6
+    A = torch.randn((8, M), generator=g, dtype=torch.float64)
+    A = torch.cat([A, A[:3], torch.zeros((2, M), dtype=torch.float64)])   # 13 snapshots, rank 8
+    P = lib()
+    svd = P.StreamingSVD(M, K, precision="fp64")
+    svd.incorporate_data(to_gpu(A))
+    assert svd.stats()["fallbacks"] == 1
+    so = oracle.StreamOracle(M, K).incorporate(synth.numpy_cm(A))
+    U = svd.modes.cpu().numpy()
+    assert sigma_rel_err(svd.singular_values, so.singular_values) <= 1e-10
+    assert max_principal_angle(U, so.modes) <= 1e-8
+
+
+def test_det_errors_leave_state_unchanged():
+    P = lib()
+    M = 512
+    g = torch.Generator().manual_seed(1)
+    A = torch.randn((20, M), generator=g, dtype=torch.float64)
+    svd = P.StreamingSVD(M, 5, precision="fp64")
+    svd.incorporate_data(to_gpu(A))
+    U0, s0 = svd.modes.cpu().clone(), svd.singular_values.copy()
+    bad = A.clone()
+    bad[3, 7] = float("nan")
+    with pytest.raises(P.PsvdError) as ei:
+        svd.incorporate_data(to_gpu(bad))
+    assert ei.value.code == -5
+    with pytest.raises(P.PsvdError) as ei:
+        svd.incorporate_data(torch.zeros((M + 1, 3), dtype=torch.float64, device="cuda"))
+    assert ei.value.code == -2
+    with pytest.raises(P.PsvdError):
+        P.StreamingSVD(M, M + 1)
+    svd32 = P.StreamingSVD(M, 5, precision="fp32")
+    with pytest.raises(P.PsvdError) as ei:
+        svd32.incorporate_data(to_gpu(A))
+    assert ei.value.code == -3
+    assert torch.equal(svd.modes.cpu(), U0) and np.array_equal(svd.singular_values, s0)
+    svd.incorporate_data(torch.zeros((M, 0), dtype=torch.float64, device="cuda"))   # empty batch: no-op
+    assert np.array_equal(svd.singular_values, s0)
+
+
+def test_det_bitwise_deterministic():
+    w = synth.scaled(synth.c1_plain_fp64(), M=3000)
+    batches = synth.planted_stream(w)
+    _, U1, s1 = run_gpu(w, batches, "fp64", False)
+    _, U2, s2 = run_gpu(w, batches, "fp64", False)
+    assert np.array_equal(U1, U2) and np.array_equal(s1, s2)
+
+
+# ----------------------------------------------------------------------------
+# Randomized streaming (Eqs. (7)-(11))
+# ----------------------------------------------------------------------------
+
+def reduced_c2(M=1 << 14, batches=3):
+    return synth.scaled(synth.c2_randomized_fp32(), M=M, batches=batches)
+
+
+def test_randomized_fp64_matches_oracle():
+    w = reduced_c2()
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "fp64", True)
+    so = run_oracle(w, batches, True, oracle.PREC_F64)
+    compare(U, s, so, 1e-10, 1e-12, "rand fp64")
+
+
+def test_randomized_fp32_matches_oracle():
+    w = reduced_c2()
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "fp32", True)
+    so = run_oracle(w, batches, True, oracle.PREC_F32)
+    compare(U, s, so, 1e-4, 1e-5, "rand fp32")
+
+
+def resolved_modes(s_ref, ell, tol):
+    # Modes j with s_{ell}/s_j small enough that the sketch subspace resolves them.
+    s_ref = np.asarray(s_ref)
+    tail = s_ref[-1]
+    return int(np.sum(s_ref >= tail * 3.0))
+
+
+@pytest.mark.parametrize("cfg", ["c2", "c3"])
+def test_mixed_matches_oracle(cfg):
+    if cfg == "c2":
+        w = reduced_c2(M=1 << 14, batches=3)
+    else:
+        w = synth.scaled(synth.c3_mixed(), M=1 << 14, batches=2)
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "mixed", True)
+    so = run_oracle(w, batches, True, oracle.PREC_BF16)
+    s_ref = so.singular_values
+    e_all = sigma_rel_err(s, s_ref)
+    assert e_all <= 2e-3, e_all
+    k = resolved_modes(s_ref, w.K + w.oversampling, 1e-5)
+    assert k >= 10
+    e_res = sigma_rel_err(s[:k], s_ref[:k])
+    assert e_res <= 1e-5, (k, e_res)
+    assert orth_err(U) <= 1e-5
+
+
+def test_randomized_exact_low_rank_planted():
+    # rank <= sketch width and no noise: exact recovery of the planted spectrum.
+    j = np.arange(12)
+    w = synth.Workload("lowrank", M=5000, N=40, batches=2, K=10, oversampling=6, power_iters=1, ff=1.0,
+                       sigma=2.0 ** (-j / 3.0), noise=0.0, seed=9, dtype=torch.float64, randomized=True)
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "fp64", True)
+    assert sigma_rel_err(s, w.sigma[:10]) <= 1e-10
+
+
+# ----------------------------------------------------------------------------
+# APMOS (Algorithm 2)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
+def test_apmos_matches_oracle(dtype, tol):
+    w = synth.scaled(synth.c4_apmos(), partitions=8, part_min=500, part_max=3000, dtype=dtype)
+    sizes = synth.partition_sizes(w)
+    parts = synth.apmos_partitions(w, sizes=sizes)
+    P = lib()
+    U, Lam, X = P.apmos_batched([to_gpu(p) for p in parts], w.local_rank, w.K)
+    Uo, Lo, Xo = oracle.apmos([synth.numpy_cm(p) for p in parts], w.local_rank, w.K)
+    assert sigma_rel_err(Lam, Lo) <= tol
+    Ug = np.vstack([u.double().cpu().numpy() for u in U])
+    Ur = np.vstack(Uo)
+    k = gap_limited_k(Lo, tol, w.K)
+    assert max_principal_angle(Ug[:, :k], Ur[:, :k]) <= max(1e-9, 1e3 * tol)
+    assert np.abs(np.abs(X) - np.abs(Xo)).max() <= max(1e-9, 1e3 * tol)
+
+
+def test_apmos_exact_when_local_rank_fits():
+    w = synth.scaled(synth.c4_apmos(), partitions=5, part_min=300, part_max=900, N=48, dtype=torch.float64)
+    parts = synth.apmos_partitions(w)
+    A = np.vstack([synth.numpy_cm(p) for p in parts])
+    sl = np.linalg.svd(A, compute_uv=False)
+    P = lib()
+    U, Lam, X = P.apmos_batched([to_gpu(p) for p in parts], 40, 20)
+    assert sigma_rel_err(Lam, sl[:20]) <= 1e-10
