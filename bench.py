@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-rows", type=int, default=1 << 17, help="rows of the oracle sample")
+    ap.add_argument("--cpu-rows", type=int, default=1 << 19, help="rows of the oracle sample")
     ap.add_argument("--M", type=int, default=1 << 20)
     return ap.parse_args()
 

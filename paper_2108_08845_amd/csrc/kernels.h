@@ -62,7 +62,9 @@ struct NnArgs {
     int32_t n;           // rows of X used (= panel columns)
     int32_t nx;          // output columns
     const int32_t* skip;
-    int32_t skip_mask;
+    int32_t skip_mask;        // do nothing if (*skip & skip_mask)
+    int32_t need_mask;        // do nothing unless (*skip & need_mask) (when non-zero)
+    int32_t accumulate;       // out += result instead of out = result
 };
 
 struct FusedArgs {

@@ -173,6 +173,7 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
     using MF = Mfma<CT>;
     using E = typename MF::elem;
     if (a.skip && (*a.skip & a.skip_mask)) return;
+    if (a.skip && a.need_mask && !(*a.skip & a.need_mask)) return;
     __shared__ E Cs[NN_KC * (NN_TM + 1)];
     __shared__ E Xs[NN_OB * (NN_KC + 1)];
     __shared__ double Os[NN_OB * (NN_TM + 1)];
@@ -235,8 +236,13 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
                 double v = Os[j * (NN_TM + 1) + rr];
                 if (a.row_scale && row < a.nscale) v *= a.row_scale[row];
                 size_t o = (size_t)row + (size_t)(oc0 + j) * (size_t)S.ldo;
-                if (S.out_dtype == PSVD_F64) ((double*)S.out)[o] = v;
-                else ((float*)S.out)[o] = (float)v;
+                if (S.out_dtype == PSVD_F64) {
+                    double* po = (double*)S.out + o;
+                    *po = a.accumulate ? *po + v : v;
+                } else {
+                    float* po = (float*)S.out + o;
+                    *po = a.accumulate ? (float)((double)*po + v) : (float)v;
+                }
             }
         }
     }

@@ -371,7 +371,7 @@ static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool
 // out (rows x nx) = S X with X (S.ncols x nx, ld ldx) FP64.
 static int nn_product(psvd_handle* h, const PanelSeg& S, const double* X, int64_t ldx, int nx, bool fp64,
                       const double* row_scale, int nscale, const int32_t* skip, int skip_mask,
-                      int cls = PSVD_KC_NN) {
+                      int cls = PSVD_KC_NN, int need_mask = 0, int accumulate = 0) {
     int nbx = ceil_div(nx, 64);
     int64_t chunk = pick_chunk(S.rows, nbx, 64);
     int nitems = ceil_div(S.rows, chunk);
@@ -387,6 +387,8 @@ static int nn_product(psvd_handle* h, const PanelSeg& S, const double* X, int64_
     a.nx = nx;
     a.skip = skip;
     a.skip_mask = skip_mask;
+    a.need_mask = need_mask;
+    a.accumulate = accumulate;
     int pe = prof_begin(h, cls);
     HIPCHK(h, launch_nn(fp64, a, nitems, h->stream));
     prof_end(h, pe);
@@ -641,7 +643,16 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         rc = tn_product(h, Q1, Q1, true, true, L.G2, nullptr, 0, dstat, skipmask);
         if (rc) return rc;
         HIPCHK(h, launch_small_det2(sa, st));
-        rc = nn_product(h, C, L.T, n, rk, fp64, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN, PSVD_KC_LIFT);
+        // Lift: U = Q1 R2^-1 U~_rk from the kept Cholesky-QR factor; on the eigen
+        // route (no Q1) U = C D V_rk diag(1/sigma) straight from the panel.
+        PanelSeg Qs = Q1;
+        Qs.out = h->U[nxt].p;
+        Qs.ldo = h->ldu;
+        Qs.out_dtype = h->u_dtype;
+        rc = nn_product(h, Qs, L.T, n, rk, fp64, nullptr, 0, dstat, skipmask, PSVD_KC_LIFT);
+        if (rc) return rc;
+        rc = nn_product(h, C, L.T, n, rk, fp64, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN, PSVD_KC_LIFT,
+                        DEV_FALLBACK);
         if (rc) return rc;
     } else {
         // ---- randomized range finder ----

@@ -120,6 +120,11 @@ __device__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* ord
         }
         if (tid == 0) *sflag = 0;
         __syncthreads();
+        // columns below (m u)^2 of the largest carry only rounding noise: they
+        // are not rotated (they cannot be made more orthogonal).
+        double nmax = 0.0;
+        for (int j = 0; j < n; ++j) nmax = fmax(nmax, nrm[j]);
+        const double negl = nmax * tol * tol;
         if (sweep >= max_sweeps) {
             ++sweep;
             break;
@@ -137,7 +142,7 @@ __device__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* ord
                 for (int i = lane; i < m; i += 64) g += zp[i] * zq[i];
                 g = wave_sum(g);
                 double al = nrm[p], be = nrm[q];
-                if (!(al > 0.0) || !(be > 0.0)) continue;
+                if (!(al > negl) || !(be > negl)) continue;
                 if (fabs(g) <= tol * sqrt(al) * sqrt(be)) continue;
                 double zeta = (be - al) / (2.0 * g);
                 double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -327,21 +332,17 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
     for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sig[a.ivec[j]];
     __syncthreads();
     wg_sign_rule(a.small_u, n, rk, n, nullptr);
-    // T = R^-1 U~ (back substitution per column), then D scaling of rows.
-    const double* R = a.G;
+    // The lift reads Q1 = C D R1^-1 (the first Cholesky-QR factor, kept by the
+    // second Gram pass): U = Q1 R2^-1 U~_rk, so T = R2^-1 U~ (back substitution).
+    const double* R2 = a.G2;
     for (int j = tid; j < rk; j += SM_THREADS) {
         double* x = a.T + (size_t)j * n;
         const double* u = a.small_u + (size_t)j * n;
         for (int i = n - 1; i >= 0; --i) {
             double s = u[i];
-            for (int k = i + 1; k < n; ++k) s -= R[i + (size_t)k * n] * x[k];
-            x[i] = s / R[i + (size_t)i * n];
+            for (int k = i + 1; k < n; ++k) s -= R2[i + (size_t)k * n] * x[k];
+            x[i] = s / R2[i + (size_t)i * n];
         }
-    }
-    __syncthreads();
-    for (int e = tid; e < n * rk; e += SM_THREADS) {
-        int i = e % n;
-        a.T[e] *= dscale(a, i);
     }
 }
 
