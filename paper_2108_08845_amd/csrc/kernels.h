@@ -80,6 +80,7 @@ struct FusedArgs {
     float* partP;            // [wg][lb] np x 64 column-major
     double* partG;           // [wg] 64 x 64 (only when nlb == 1 and G requested)
     int32_t want_g;          // FP32 compute type only
+    int32_t vec;             // float4 loads/stores allowed (rows % 4 == 0, lds % 4 == 0, 16-byte bases)
 };
 
 struct FusedReduceArgs {
@@ -165,11 +166,33 @@ struct ApmosGlobalArgs {
     int32_t* sweeps;
 };
 
+struct GradCoreArgs {
+    int32_t n, r, rk;
+    const double* R;      // n x n upper Cholesky-QR factor of the panel
+    const double* Ut;     // n x n left singular vectors of R (sorted, sign rule)
+    const double* S;      // n singular values
+    const double* E;      // n x rk: C^T U_bar (C with its column scale)
+    const double* sbar;   // rk
+    const double* d;      // r column scale of the U part (ff * s_prev)
+    double* Tf;           // n x n work
+    double* V;            // n x n work
+    double* H;            // n x rk work
+    double* Wk;           // n x n work
+    double* Zt;           // n x n work
+    double* Zu;           // (n + rk) x r out (ld n + rk)
+    double* Za;           // (n + rk) x (n - r) out (ld n + rk)
+    int32_t* status;
+};
+
+hipError_t launch_grad_core(const GradCoreArgs& a, hipStream_t st);
+hipError_t launch_grad_sbar(const double* G, int r, const double* s_prev, double* sbar, hipStream_t st);
+
 hipError_t launch_tn(bool fp64, const TnArgs& a, int nitems, hipStream_t st);
 hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st);
 hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st);
 bool fused_fits(bool bf16, int tm, int np);
-hipError_t launch_fused(bool bf16, const FusedArgs& a, hipStream_t st);
+int fused_pick_tm(bool bf16, int np);
+hipError_t launch_fused(bool bf16, int mode, const FusedArgs& a, hipStream_t st);
 hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st);
 
 hipError_t launch_small_det1(const SmallArgs& a, hipStream_t st);

@@ -266,72 +266,88 @@ __device__ __forceinline__ typename MF::frag lds_frag(const typename MF::elem* p
     }
 }
 
-template <class CT, int TM, int NTW, int NPMAX>
-__global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
+// Column base pointer (FP32 panel) of column c.
+__device__ __forceinline__ const float* fcol(const PanelSeg& s, int c) {
+    int cc = c;
+    for (int b = 0; b < s.nblk; ++b) {
+        if (cc < s.blk[b].ncols) return (const float*)s.blk[b].ptr + (size_t)cc * (size_t)s.blk[b].ld;
+        cc -= s.blk[b].ncols;
+    }
+    return nullptr;
+}
+
+// Work-group of 512 threads (8 waves).  Tile = TM rows x np columns of the
+// panel.  Each thread moves float4 column segments: TPC = TM / 4 threads per
+// column, CPR = 512 / TPC columns per round.
+//   MODE 0: P += C^T (C X)             (power pass)
+//   MODE 1: P and G = (C X)^T (C X)    (final pass; FP32 only)
+//   MODE 2: out = C X                  (lift; FP32 only)
+template <class CT, int TM, int NRB, bool VEC, int MODE>
+__global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     using MF = Mfma<CT>;
     using E = typename MF::elem;
+    constexpr int NT = 512;
     constexpr int KPL = MF::KPL;
     constexpr int KSTEP = MF::KSTEP;
-    constexpr bool ROWMAJOR_COPY = (KPL > 1);
-    constexpr bool CAN_G = (sizeof(E) == 4);
+    constexpr bool ROWCOPY = (KPL > 1);
+    constexpr int TPC = TM / 4;
+    constexpr int CPR = NT / TPC;
+    constexpr int NPMAX = NRB * 8 * 16;
+    constexpr int RMAX = (NPMAX + CPR - 1) / CPR;
     extern __shared__ __align__(16) unsigned char smem[];
     const int np = a.np;
-    const int ldX = np + 4;        // X block: column-major, k contiguous
-    const int ldC = TM + 4;        // C tile: column-major (rows contiguous)
-    const int ldR = np + 4;        // C tile row-major copy (bf16 only)
-    const int ldY = TM + 4;        // Y tile: column-major
+    const int ldX = np + 4;
+    const int ldC = TM + 4;
+    const int ldR = np + 4;
+    const int ldY = TM + 4;
     E* Xs = (E*)smem;
     E* Cs = Xs + (size_t)FU_LB * ldX;
     E* Cr = Cs + (size_t)np * ldC;
-    E* Ys = Cr + (ROWMAJOR_COPY ? (size_t)TM * ldR : 0);
+    E* Ys = Cr + (ROWCOPY ? (size_t)TM * ldR : 0);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    // XCD-aware mapping: consecutive dispatch slots of one XCD take the column
-    // blocks of the same row range so the second read of a tile hits its L2.
     const int b = blockIdx.x;
     const int xcd = b & 7, local = b >> 3;
     const int lb = local % a.nlb;
     const int wg = (local / a.nlb) * 8 + xcd;
     if (wg >= a.nwg) return;
     const int c0 = lb * FU_LB;
-    const bool want_g = CAN_G && a.want_g;
 
-    // X block -> LDS (compute type), zero padded.
-    for (int idx = tid; idx < FU_LB * np; idx += 256) {
+    for (int idx = tid; idx < FU_LB * np; idx += NT) {
         int k = idx % np, j = idx / np;
         double v = 0.0;
         if (k < a.n && c0 + j < a.lx) v = a.X[k + (int64_t)(c0 + j) * a.ldx];
         Xs[j * ldX + k] = MF::from_double(v);
     }
 
-    // P accumulators: wave w owns row blocks rb = w, w+4, ... and all 4 column blocks.
     const int nrb = np / 16;
-    typename MF::acc accP[NTW];
+    typename MF::acc accP[MODE == 2 ? 1 : NRB * 4];
 #pragma unroll
-    for (int t = 0; t < NTW; ++t) accP[t] = typename MF::acc{0, 0, 0, 0};
-    d4_t accG[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) accG[j] = d4_t{0, 0, 0, 0};
+    for (int t = 0; t < (MODE == 2 ? 1 : NRB * 4); ++t) accP[t] = typename MF::acc{0, 0, 0, 0};
+    d4_t accG[2];
+    accG[0] = d4_t{0, 0, 0, 0};
+    accG[1] = d4_t{0, 0, 0, 0};
 
-    // Prefetch registers: the TM x np tile, consecutive threads on consecutive rows.
-    constexpr int PFMAX = (TM * NPMAX + 255) / 256;
-    float pf[PFMAX];
-    const int per = (TM * np + 255) / 256;
+    const int rounds = (np + CPR - 1) / CPR;
+    const int tsub = tid % TPC, tcol = tid / TPC;
+    f4_t pf[RMAX];
     auto fetch = [&](int64_t t) {
-        int64_t r0 = t * TM;
+        const int64_t row = t * TM + tsub * 4;
 #pragma unroll
-        for (int e = 0; e < PFMAX; ++e) {
-            float v = 0.f;
-            if (e < per) {
-                int idx = e * 256 + tid;
-                int c = idx / TM, rr = idx % TM;
-                int64_t row = r0 + rr;
-                if (c < a.n && row < a.seg.rows) {
-                    ColRef cr = col_ref(a.seg, c);
-                    v = ((const float*)cr.base)[row];
+        for (int rr = 0; rr < RMAX; ++rr) {
+            f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
+            const int c = rr * CPR + tcol;
+            if (rr < rounds && c < a.n) {
+                const float* p = fcol(a.seg, c);
+                if (VEC && row + 3 < a.seg.rows) {
+                    v = *(const f4_t*)(p + row);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (row + q < a.seg.rows) v[q] = p[row + q];
                 }
             }
-            pf[e] = v;
+            pf[rr] = v;
         }
     };
 
@@ -340,103 +356,124 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
     for (; t < a.tiles; t += a.nwg) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < PFMAX; ++e) {
-            if (e < per) {
-                int idx = e * 256 + tid;
-                int c = idx / TM, rr = idx % TM;
-                if (c < np) {
-                    E v = MF::from_float(pf[e]);
-                    Cs[c * ldC + rr] = v;
-                    if (ROWMAJOR_COPY) Cr[rr * ldR + c] = v;
+        for (int rr = 0; rr < RMAX; ++rr) {
+            const int c = rr * CPR + tcol;
+            if (rr < rounds && c < np) {
+                if constexpr (sizeof(E) == 4) {
+                    *(f4_t*)&Cs[c * ldC + tsub * 4] = pf[rr];
+                } else {
+                    uint16_t h0 = MF::from_float(pf[rr][0]), h1 = MF::from_float(pf[rr][1]);
+                    uint16_t h2 = MF::from_float(pf[rr][2]), h3 = MF::from_float(pf[rr][3]);
+                    uint64_t pk = (uint64_t)h0 | ((uint64_t)h1 << 16) | ((uint64_t)h2 << 32) | ((uint64_t)h3 << 48);
+                    *(uint64_t*)&Cs[c * ldC + tsub * 4] = pk;
+                    if (ROWCOPY) {
+                        Cr[(tsub * 4 + 0) * ldR + c] = h0;
+                        Cr[(tsub * 4 + 1) * ldR + c] = h1;
+                        Cr[(tsub * 4 + 2) * ldR + c] = h2;
+                        Cr[(tsub * 4 + 3) * ldR + c] = h3;
+                    }
                 }
             }
         }
         __syncthreads();
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
 
-        // Phase A: Y_tile (TM x 64) = C_tile (TM x np) X (np x 64);
-        // wave w computes column block w for all TM / 16 row blocks.
-        {
-            typename MF::acc accY[TM / 16];
-#pragma unroll
-            for (int i = 0; i < TM / 16; ++i) accY[i] = typename MF::acc{0, 0, 0, 0};
+        // Phase A: Y_tile (TM x 64) = C_tile X_blk.  (TM/16) x 4 output tiles over 8 waves.
+        constexpr int YT = (TM / 16) * 4;
+        for (int yt = w; yt < YT; yt += 8) {
+            const int ib = yt >> 2, jb = yt & 3;
+            typename MF::acc accY = typename MF::acc{0, 0, 0, 0};
             for (int k0 = 0; k0 < np; k0 += KSTEP) {
-                typename MF::frag bv = lds_frag<MF>(&Xs[(w * 16 + (lane & 15)) * ldX + k0 + (lane >> 4) * KPL]);
-#pragma unroll
-                for (int i = 0; i < TM / 16; ++i) {
-                    typename MF::frag av;
-                    if constexpr (KPL == 1) av = Cs[(k0 + (lane >> 4)) * ldC + i * 16 + (lane & 15)];
-                    else av = lds_frag<MF>(&Cr[(i * 16 + (lane & 15)) * ldR + k0 + (lane >> 4) * KPL]);
-                    accY[i] = MF::mma(av, bv, accY[i]);
-                }
+                typename MF::frag bv = lds_frag<MF>(&Xs[(jb * 16 + (lane & 15)) * ldX + k0 + (lane >> 4) * KPL]);
+                typename MF::frag av;
+                if constexpr (KPL == 1) av = Cs[(k0 + (lane >> 4)) * ldC + ib * 16 + (lane & 15)];
+                else av = lds_frag<MF>(&Cr[(ib * 16 + (lane & 15)) * ldR + k0 + (lane >> 4) * KPL]);
+                accY = MF::mma(av, bv, accY);
             }
 #pragma unroll
-            for (int i = 0; i < TM / 16; ++i)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    int row = i * 16 + MF::row_of(lane, v);
-                    int col = w * 16 + (lane & 15);
-                    Ys[col * ldY + row] = MF::from_acc(accY[i][v]);
-                }
+            for (int v = 0; v < 4; ++v) {
+                const int row = ib * 16 + MF::row_of(lane, v);
+                const int col = jb * 16 + (lane & 15);
+                Ys[col * ldY + row] = MF::from_acc(accY[v]);
+            }
         }
         __syncthreads();
 
-        // Phase B: P (np x 64) += C_tile^T Y_tile.
+        if constexpr (MODE == 2) {
+            // out[rows, c0 + j] = Y_tile (float4 column segments), j < nx
+            const int64_t row = t * TM + tsub * 4;
+            for (int j = tcol; j < FU_LB; j += CPR) {
+                if (c0 + j >= a.lx) continue;
+                f4_t v = *(const f4_t*)&Ys[j * ldY + tsub * 4];
+                float* o = (float*)a.seg.out + (size_t)(c0 + j) * (size_t)a.seg.ldo;
+                if (VEC && row + 3 < a.seg.rows) {
+                    *(f4_t*)(o + row) = v;
+                } else {
 #pragma unroll
-        for (int k0 = 0; k0 < TM; k0 += KSTEP) {
-            typename MF::frag bvs[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                bvs[j] = lds_frag<MF>(&Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4) * KPL]);
-#pragma unroll
-            for (int q = 0; q < NTW / 4; ++q) {
-                int rb = w + 4 * q;
-                if (rb < nrb) {
-                    typename MF::frag av = lds_frag<MF>(&Cs[(rb * 16 + (lane & 15)) * ldC + k0 + (lane >> 4) * KPL]);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) accP[q * 4 + j] = MF::mma(av, bvs[j], accP[q * 4 + j]);
+                    for (int q = 0; q < 4; ++q)
+                        if (row + q < a.seg.rows) o[row + q] = v[q];
                 }
             }
-        }
-        // G (64 x 64) += Y^T Y in FP64 on the FP32 values of the Y tile.
-        if constexpr (CAN_G) {
-            if (want_g) {
+        } else {
+            // Phase B: P (np x 64) += C_tile^T Y_tile; wave w owns row blocks w, w+8, ...
+#pragma unroll
+            for (int k0 = 0; k0 < TM; k0 += KSTEP) {
+                typename MF::frag bvs[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    bvs[j] = lds_frag<MF>(&Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4) * KPL]);
+#pragma unroll
+                for (int q = 0; q < NRB; ++q) {
+                    const int rb = w + 8 * q;
+                    if (rb < nrb) {
+                        typename MF::frag av =
+                            lds_frag<MF>(&Cs[(rb * 16 + (lane & 15)) * ldC + k0 + (lane >> 4) * KPL]);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) accP[q * 4 + j] = MF::mma(av, bvs[j], accP[q * 4 + j]);
+                    }
+                }
+            }
+            if constexpr (MODE == 1) {
+                // G (64 x 64) += Y^T Y in FP64 on the FP32 values; wave w: row block w/2, col blocks (w%2)*2 + {0,1}
+                const int gi = w >> 1, gj0 = (w & 1) * 2;
 #pragma unroll
                 for (int k0 = 0; k0 < TM; k0 += 4) {
-                    double av = (double)*(const float*)&Ys[(w * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+                    double av = (double)*(const float*)&Ys[(gi * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        double bv = (double)*(const float*)&Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+                    for (int j = 0; j < 2; ++j) {
+                        double bv = (double)*(const float*)&Ys[((gj0 + j) * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
                         accG[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accG[j], 0, 0, 0);
                     }
                 }
             }
         }
     }
-    // Write this work-group's partials.
-    float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)np * FU_LB;
+    if constexpr (MODE != 2) {
+        float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)np * FU_LB;
 #pragma unroll
-    for (int q = 0; q < NTW / 4; ++q) {
-        int rb = w + 4 * q;
-        if (rb < nrb) {
+        for (int q = 0; q < NRB; ++q) {
+            const int rb = w + 8 * q;
+            if (rb < nrb) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    int row = rb * 16 + MF::row_of(lane, v);
-                    int col = j * 16 + (lane & 15);
-                    outP[row + (size_t)col * np] = accP[q * 4 + j][v];
-                }
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = rb * 16 + MF::row_of(lane, v);
+                        const int col = j * 16 + (lane & 15);
+                        outP[row + (size_t)col * np] = accP[q * 4 + j][v];
+                    }
+            }
         }
     }
-    if (want_g) {
+    if constexpr (MODE == 1) {
         double* outG = a.partG + (size_t)wg * FU_LB * FU_LB;
+        const int gi = w >> 1, gj0 = (w & 1) * 2;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int row = w * 16 + Mfma<double>::row_of(lane, v);
-                int col = j * 16 + (lane & 15);
+                const int row = gi * 16 + Mfma<double>::row_of(lane, v);
+                const int col = (gj0 + j) * 16 + (lane & 15);
                 outG[row + col * FU_LB] = accG[j][v];
             }
     }
@@ -492,36 +529,51 @@ hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <class CT, int TM, int NTW, int NPMAX>
+template <class CT, int TM, int NRB, bool VEC, int MODE>
 static hipError_t launch_fused_k(const FusedArgs& a, size_t lds, hipStream_t st) {
     int blocks = ((a.nwg + 7) / 8) * 8 * a.nlb;
-    hipError_t e = hipFuncSetAttribute((const void*)k_fused<CT, TM, NTW, NPMAX>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_fused<CT, TM, NRB, VEC, MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fused<CT, TM, NTW, NPMAX>), dim3(blocks), dim3(256), lds, st, a);
+    hipLaunchKernelGGL((k_fused<CT, TM, NRB, VEC, MODE>), dim3(blocks), dim3(512), lds, st, a);
     return hipGetLastError();
 }
 
-template <class CT, int TM>
-static hipError_t launch_fused_t(const FusedArgs& a, size_t lds, hipStream_t st) {
-    if (a.np <= 128) return launch_fused_k<CT, TM, 8, 128>(a, lds, st);
-    if (a.np <= 320) return launch_fused_k<CT, TM, 20, 320>(a, lds, st);
-    if (a.np <= 640) return launch_fused_k<CT, TM, 40, 640>(a, lds, st);
+template <class CT, int TM, bool VEC, int MODE>
+static hipError_t launch_fused_n(const FusedArgs& a, size_t lds, hipStream_t st) {
+    if (a.np <= 128) return launch_fused_k<CT, TM, 1, VEC, MODE>(a, lds, st);
+    if (a.np <= 384) return launch_fused_k<CT, TM, 3, VEC, MODE>(a, lds, st);
+    if (a.np <= 640) return launch_fused_k<CT, TM, 5, VEC, MODE>(a, lds, st);
     return hipErrorInvalidValue;
 }
 
-bool fused_fits(bool bf16, int tm, int np) {
-    return np <= 640 && fused_lds_bytes(bf16 ? 2 : 4, bf16, tm, np) <= 160 * 1024;
+template <class CT, bool VEC, int MODE>
+static hipError_t launch_fused_m(const FusedArgs& a, size_t lds, hipStream_t st) {
+    if (a.tm == 16) return launch_fused_n<CT, 16, VEC, MODE>(a, lds, st);
+    if (a.tm == 32) return launch_fused_n<CT, 32, VEC, MODE>(a, lds, st);
+    return launch_fused_n<CT, 64, VEC, MODE>(a, lds, st);
 }
 
-hipError_t launch_fused(bool bf16, const FusedArgs& a, hipStream_t st) {
+// Largest tile height whose LDS footprint fits one CU (0: none fits).
+int fused_pick_tm(bool bf16, int np) {
+    if (np > 640) return 0;
+    for (int tm : {64, 32, 16})
+        if (fused_lds_bytes(bf16 ? 2 : 4, bf16, tm, np) <= 160 * 1024) return tm;
+    return 0;
+}
+
+bool fused_fits(bool bf16, int tm, int np) { return tm > 0 && np <= 640 && fused_lds_bytes(bf16 ? 2 : 4, bf16, tm, np) <= 160 * 1024; }
+
+hipError_t launch_fused(bool bf16, int mode, const FusedArgs& a, hipStream_t st) {
     size_t lds = fused_lds_bytes(bf16 ? 2 : 4, bf16, a.tm, a.np);
+    bool vec = a.vec != 0;
     if (bf16) {
-        if (a.tm == 16) return launch_fused_t<bf16_t, 16>(a, lds, st);
-        return launch_fused_t<bf16_t, 32>(a, lds, st);
+        if (mode != 0) return hipErrorInvalidValue;
+        return vec ? launch_fused_m<bf16_t, true, 0>(a, lds, st) : launch_fused_m<bf16_t, false, 0>(a, lds, st);
     }
-    if (a.tm == 16) return launch_fused_t<float, 16>(a, lds, st);
-    return launch_fused_t<float, 32>(a, lds, st);
+    if (mode == 0) return vec ? launch_fused_m<float, true, 0>(a, lds, st) : launch_fused_m<float, false, 0>(a, lds, st);
+    if (mode == 1) return vec ? launch_fused_m<float, true, 1>(a, lds, st) : launch_fused_m<float, false, 1>(a, lds, st);
+    return vec ? launch_fused_m<float, true, 2>(a, lds, st) : launch_fused_m<float, false, 2>(a, lds, st);
 }
 
 hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st) {

@@ -395,6 +395,52 @@ static int nn_product(psvd_handle* h, const PanelSeg& S, const double* X, int64_
     return PSVD_OK;
 }
 
+
+// float4 loads need 16-byte aligned column starts: rows % 4 == 0 and every
+// leading dimension a multiple of 4 with a 16-byte aligned base.
+static bool seg_vec_ok(const PanelSeg& S, bool check_out) {
+    if (S.rows % 4) return false;
+    for (int b = 0; b < S.nblk; ++b)
+        if ((S.blk[b].ld % 4) || ((uintptr_t)S.blk[b].ptr & 15)) return false;
+    if (check_out && ((S.ldo % 4) || ((uintptr_t)S.out & 15))) return false;
+    return true;
+}
+
+static bool seg_all_f32(const PanelSeg& S) {
+    for (int b = 0; b < S.nblk; ++b)
+        if (S.blk[b].dtype != PSVD_F32) return false;
+    return true;
+}
+
+// out (S.out) = S T with T (S.ncols x nx FP64): fused FP32 lift when the panel
+// is FP32 and fits, otherwise the generic product.
+static int lift_product(psvd_handle* h, const PanelSeg& S, const double* T, int64_t ldt, int nx, bool fp64,
+                        const int32_t* skip, int skip_mask, int need_mask) {
+    const int np = ((S.ncols + 15) / 16) * 16;
+    const int tm = fused_pick_tm(false, np);
+    if (!fp64 && tm > 0 && seg_all_f32(S) && S.out_dtype == PSVD_F32 && skip == nullptr) {
+        FusedArgs fa;
+        std::memset(&fa, 0, sizeof(fa));
+        fa.seg = S;
+        fa.X = T;
+        fa.ldx = ldt;
+        fa.n = S.ncols;
+        fa.np = np;
+        fa.lx = nx;
+        fa.nlb = ceil_div(nx, 64);
+        fa.tm = tm;
+        fa.nwg = 256;
+        fa.tiles = (S.rows + tm - 1) / tm;
+        if (fa.tiles < fa.nwg) fa.nwg = (int)fa.tiles;
+        fa.vec = seg_vec_ok(S, true) ? 1 : 0;
+        int pe = prof_begin(h, PSVD_KC_LIFT);
+        HIPCHK(h, launch_fused(false, 2, fa, h->stream));
+        prof_end(h, pe);
+        return PSVD_OK;
+    }
+    return nn_product(h, S, T, ldt, nx, fp64, nullptr, 0, skip, skip_mask, PSVD_KC_LIFT, need_mask);
+}
+
 static PanelSeg small_seg(const double* p, int rows, int cols, int ld, double* out = nullptr, int ldo = 0) {
     PanelSeg s = make_seg(rows);
     seg_add(s, make_block(p, ld, PSVD_F64, cols));
@@ -681,7 +727,8 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         const int nlb = ceil_div(l, 64);
         auto pass = [&](bool bf16, bool want_g) -> int {
             // P = D C'^T (C' X')  [+ G_Y = Y^T Y]
-            bool fuse_ok = !fp64 && fused_fits(bf16, bf16 ? (np > 320 ? 16 : 32) : 32, np) && (!want_g || nlb == 1);
+            const int tm = fused_pick_tm(bf16, np);
+            bool fuse_ok = !fp64 && tm > 0 && seg_all_f32(C) && (!want_g || nlb == 1);
             if (fuse_ok) {
                 FusedArgs fa;
                 std::memset(&fa, 0, sizeof(fa));
@@ -692,15 +739,16 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 fa.np = np;
                 fa.lx = l;
                 fa.nlb = nlb;
-                fa.tm = bf16 ? (np > 320 ? 16 : 32) : 32;
+                fa.tm = tm;
                 fa.nwg = 256;
                 fa.tiles = (M + fa.tm - 1) / fa.tm;
                 if (fa.tiles < fa.nwg) fa.nwg = (int)fa.tiles;
                 fa.partP = h->partP.as<float>();
                 fa.partG = h->partG.as<double>();
                 fa.want_g = want_g ? 1 : 0;
+                fa.vec = seg_vec_ok(C, false) ? 1 : 0;
                 int pe = prof_begin(h, bf16 ? PSVD_KC_FUSED_BF16 : PSVD_KC_FUSED_F32);
-                HIPCHK(h, launch_fused(bf16, fa, st));
+                HIPCHK(h, launch_fused(bf16, want_g ? 1 : 0, fa, st));
                 prof_end(h, pe);
                 FusedReduceArgs ra;
                 std::memset(&ra, 0, sizeof(ra));
@@ -788,7 +836,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         PanelSeg Xs = small_seg(L.X, n, l, n, L.T, n);
         rc = nn_product(h, Xs, L.M2, l, rk, true, nullptr, 0, nullptr, 0);
         if (rc) return rc;
-        rc = nn_product(h, C, L.T, n, rk, fp64, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN, PSVD_KC_LIFT);
+        rc = lift_product(h, C, L.T, n, rk, fp64, nullptr, 0, 0);
         if (rc) return rc;
     }
     HIPCHK(h, hipEventRecord(h->ev1, st));
@@ -876,3 +924,296 @@ int psvd_modes(const psvd_handle* hc, void* U, int64_t ldu, int32_t dtype) {
 }
 
 }  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Reverse mode of the deterministic stream.
+// ----------------------------------------------------------------------------
+namespace {
+
+struct GradCtx {
+    psvd_handle* h = nullptr;       // deterministic handle that runs the forward
+    int64_t M = 0;
+    int B = 0;
+    int64_t Nb = 0;
+    int K = 0;
+    int dt = PSVD_F32;
+    int esz = 4;
+    DevBuf Ust, sst;                // states entering every batch
+    std::vector<int> rst;
+    DevBuf Ubar[2];                 // cotangent of the current U (M x K)
+    DevBuf work;                    // small FP64 matrices
+    ~GradCtx() {
+        if (h) psvd_finalize(h);
+    }
+};
+
+// Forward pass storing the state that enters every batch.
+int grad_forward(GradCtx& g, const void* A, int64_t lda, double ff, hipStream_t st, bool store) {
+    psvd_options o;
+    psvd_default_options(&o);
+    o.method = PSVD_DETERMINISTIC;
+    o.precision = g.dt == PSVD_F64 ? PSVD_PREC_FP64 : PSVD_PREC_FP32;
+    o.stream = st;
+    o.flags = PSVD_OPT_NO_FALLBACK;
+    int rc = psvd_initialize(&g.h, g.M, g.K, ff, 0, 0, &o);
+    if (rc) return rc;
+    psvd_handle* h = g.h;
+    if (store) {
+        HIPCHK(h, g.Ust.ensure((size_t)g.B * h->ldu * g.K * g.esz));
+        HIPCHK(h, g.sst.ensure((size_t)g.B * g.K * sizeof(double)));
+        g.rst.assign(g.B, 0);
+    }
+    for (int b = 0; b < g.B; ++b) {
+        if (store) {
+            g.rst[b] = h->r;
+            HIPCHK(h, hipMemcpyAsync((char*)g.Ust.p + (size_t)b * h->ldu * g.K * g.esz, h->U[h->cur].p,
+                                     (size_t)h->ldu * g.K * g.esz, hipMemcpyDeviceToDevice, st));
+            HIPCHK(h, hipMemcpyAsync(g.sst.as<double>() + (size_t)b * g.K, h->s[h->cur].p, g.K * sizeof(double),
+                                     hipMemcpyDeviceToDevice, st));
+        }
+        const void* Ab = (const char*)A + (size_t)b * g.Nb * lda * g.esz;
+        rc = psvd_incorporate_data(h, Ab, g.M, g.Nb, lda, g.dt);
+        if (rc) return rc;
+    }
+    return PSVD_OK;
+}
+
+// Carry (U_bar, s_bar) of the final state back through every batch; the data
+// part of each panel cotangent is written (or added, accumulate) to A_bar.
+int grad_backward(GradCtx& g, const void* A, int64_t lda, double ff, const double* sbar_host, void* Abar,
+                  int accumulate, hipStream_t st) {
+    psvd_handle* h = g.h;
+    const int K = g.K;
+    const int nmax = K + (int)g.Nb;
+    int rc = ensure_workspace(h, nmax);
+    if (rc) return rc;
+    // work layout
+    size_t nn = (size_t)nmax * nmax, nk = (size_t)nmax * K, zz = (size_t)(nmax + K) * nmax;
+    const size_t words = 8 * nn + 2 * nk + 2 * zz + (size_t)K * K + 4 * (size_t)nmax + 256;
+    HIPCHK(h, g.work.ensure(words * sizeof(double)));
+    double* w = g.work.as<double>();
+    double *gR = w, *gUt = gR + nn, *gT = gUt + nn, *gTf = gT + nn, *gV = gTf + nn, *gWk = gV + nn, *gZt = gWk + nn;
+    double *gE = gZt + nn, *gH = gE + nk, *gZu = gH + nk, *gZa = gZu + zz, *gGrr = gZa + zz;
+    double *gS = gGrr + (size_t)K * K, *gsbar = gS + nmax, *gd = gsbar + nmax;
+    int32_t* dstat = h->status.as<int32_t>();
+    const bool fp64 = g.dt == PSVD_F64;
+    int r_fin = h->r;
+    HIPCHK(h, hipMemsetAsync(gsbar, 0, sizeof(double) * nmax, st));
+    HIPCHK(h, hipMemcpyAsync(gsbar, sbar_host, sizeof(double) * r_fin, hipMemcpyHostToDevice, st));
+    int cb = 0;   // Ubar[cb] holds the current cotangent
+    for (int b = g.B - 1; b >= 0; --b) {
+        const int r = g.rst[b];
+        const int n = r + (int)g.Nb;
+        const int rk = std::min(K, n);
+        const void* Ub = (const char*)g.Ust.p + (size_t)b * h->ldu * K * g.esz;
+        const double* sb = g.sst.as<double>() + (size_t)b * K;
+        const void* Ab = (const char*)A + (size_t)b * g.Nb * lda * g.esz;
+        HIPCHK(h, hipMemsetAsync(dstat, 0, 8, st));
+        HIPCHK(h, launch_make_scale(gd, sb, r, ff, st));
+        PanelSeg C = make_seg(g.M);
+        if (r > 0) seg_add(C, make_block(Ub, h->ldu, g.dt, r));
+        seg_add(C, make_block(Ab, lda, g.dt, (int)g.Nb));
+        SmallLayout L = small_layout(h->small.as<double>(), n, 0, K);
+        // Recompute the full thin SVD of the panel: Cholesky-QR2 + Jacobi of R.
+        rc = tn_product(h, C, C, true, true, L.G, nullptr, 0, nullptr, 0);
+        if (rc) return rc;
+        SmallArgs sa;
+        std::memset(&sa, 0, sizeof(sa));
+        sa.n = n;
+        sa.r = r;
+        sa.K = n;                 // keep every triplet
+        sa.max_sweeps = h->opt.max_sweeps;
+        sa.allow_fallback = 0;
+        sa.d = gd;
+        sa.G = gR;                // det1 scales G here; det2 leaves R = R2 R1 here
+        sa.G2 = L.G2;
+        sa.R1 = L.R1;
+        sa.Ri = L.Ri;
+        sa.Z = L.Z;
+        sa.T = gT;
+        sa.Xn = L.Xn;
+        sa.s_out = gS;
+        sa.small_u = gUt;
+        sa.vec = L.vec;
+        sa.ivec = h->ivec.as<int32_t>();
+        sa.status = dstat;
+        sa.sweeps = dstat + 1;
+        HIPCHK(h, hipMemcpyAsync(gR, L.G, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(h, launch_small_det1(sa, st));
+        PanelSeg Q = C;
+        Q.out = h->tall.p;
+        Q.ldo = g.M;
+        Q.out_dtype = h->u_dtype;
+        rc = nn_product(h, Q, L.Xn, n, n, fp64, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN);
+        if (rc) return rc;
+        PanelSeg Q1 = make_seg(g.M);
+        seg_add(Q1, make_block(h->tall.p, g.M, h->u_dtype, n));
+        rc = tn_product(h, Q1, Q1, true, true, L.G2, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN);
+        if (rc) return rc;
+        HIPCHK(h, launch_small_det2(sa, st));
+        // E = C^T U_bar (C with its column scale).
+        PanelSeg Ubs = make_seg(g.M);
+        seg_add(Ubs, make_block(g.Ubar[cb].p, g.M, g.dt, rk));
+        rc = tn_product(h, C, Ubs, false, true, gE, gd, r, nullptr, 0);
+        if (rc) return rc;
+        GradCoreArgs ga;
+        ga.n = n;
+        ga.r = r;
+        ga.rk = rk;
+        ga.R = gR;
+        ga.Ut = gUt;
+        ga.S = gS;
+        ga.E = gE;
+        ga.sbar = gsbar;
+        ga.d = gd;
+        ga.Tf = gTf;
+        ga.V = gV;
+        ga.H = gH;
+        ga.Wk = gWk;
+        ga.Zt = gZt;
+        ga.Zu = gZu;
+        ga.Za = gZa;
+        ga.status = dstat;
+        HIPCHK(h, launch_grad_core(ga, st));
+        // C_bar = [U_prev | A_b | U_bar] [Z]: data part -> A_bar, U part -> next cotangent.
+        PanelSeg P3 = C;
+        seg_add(P3, make_block(g.Ubar[cb].p, g.M, g.dt, rk));
+        P3.out = (char*)Abar + (size_t)b * g.Nb * g.M * g.esz;
+        P3.ldo = g.M;
+        P3.out_dtype = g.dt;
+        rc = nn_product(h, P3, gZa, n + rk, (int)g.Nb, fp64, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN | DEV_NOCONV,
+                        PSVD_KC_LIFT, 0, accumulate);
+        if (rc) return rc;
+        if (r > 0) {
+            PanelSeg P3u = P3;
+            P3u.out = g.Ubar[1 - cb].p;
+            rc = nn_product(h, P3u, gZu, n + rk, r, fp64, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN | DEV_NOCONV,
+                            PSVD_KC_LIFT);
+            if (rc) return rc;
+            PanelSeg Us = make_seg(g.M);
+            seg_add(Us, make_block(Ub, h->ldu, g.dt, r));
+            PanelSeg Un = make_seg(g.M);
+            seg_add(Un, make_block(g.Ubar[1 - cb].p, g.M, g.dt, r));
+            rc = tn_product(h, Us, Un, false, true, gGrr, nullptr, 0, nullptr, 0);
+            if (rc) return rc;
+            HIPCHK(h, hipMemsetAsync(gsbar, 0, sizeof(double) * nmax, st));
+            HIPCHK(h, launch_grad_sbar(gGrr, r, sb, gsbar, st));
+            cb = 1 - cb;
+        }
+        int32_t hs[2] = {0, 0};
+        HIPCHK(h, hipMemcpyAsync(hs, dstat, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipStreamSynchronize(st));
+        if (hs[0] & (DEV_BREAKDOWN | DEV_FALLBACK))
+            return fail(h, PSVD_E_BREAKDOWN, "rank-deficient panel: the adjoint needs a full-rank batch");
+        int code = finish_status(h, hs[0]);
+        if (code) return code;
+    }
+    return PSVD_OK;
+}
+
+int grad_setup(GradCtx& g, const void* A, int64_t M, int64_t lda, int32_t dtype, int32_t B, int64_t Nb, int32_t K) {
+    if (!A || M < 1 || B < 1 || Nb < 1 || K < 1 || K > M || lda < M) return PSVD_E_INVAL;
+    if (dtype != PSVD_F32 && dtype != PSVD_F64) return PSVD_E_DTYPE;
+    if ((int64_t)K + Nb > M) return PSVD_E_SHAPE;
+    g.M = M;
+    g.B = B;
+    g.Nb = Nb;
+    g.K = K;
+    g.dt = dtype;
+    g.esz = dtype == PSVD_F64 ? 8 : 4;
+    return PSVD_OK;
+}
+
+}  // namespace
+
+extern "C" int psvd_stream_backward(const void* A, int64_t M, int64_t lda, int32_t dtype, int32_t B, int64_t Nb,
+                                    int32_t K, double ff, const void* U_bar, const double* s_bar, void* A_bar,
+                                    void* stream) {
+    GradCtx g;
+    int rc = grad_setup(g, A, M, lda, dtype, B, Nb, K);
+    if (rc) return rc;
+    if (!U_bar || !s_bar || !A_bar || !(ff > 0.0 && ff <= 1.0)) return PSVD_E_INVAL;
+    hipStream_t st = (hipStream_t)stream;
+    rc = grad_forward(g, A, lda, ff, st, true);
+    if (rc) return rc;
+    psvd_handle* h = g.h;
+    const int r = h->r;
+    for (int b = 0; b < 2; ++b) HIPCHK(h, g.Ubar[b].ensure((size_t)M * K * g.esz));
+    HIPCHK(h, hipMemsetAsync(g.Ubar[0].p, 0, (size_t)M * K * g.esz, st));
+    HIPCHK(h, hipMemcpyAsync(g.Ubar[0].p, U_bar, (size_t)M * r * g.esz, hipMemcpyDeviceToDevice, st));
+    rc = grad_backward(g, A, lda, ff, s_bar, A_bar, 0, st);
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(st));
+    return PSVD_OK;
+}
+
+extern "C" int psvd_loss_grad(const void* A, int64_t M, int64_t lda, int32_t dtype, int32_t B, int64_t Nb,
+                              int32_t K, double ff, const double* w, double* loss, void* grad, void* stream) {
+    GradCtx g;
+    int rc = grad_setup(g, A, M, lda, dtype, B, Nb, K);
+    if (rc) return rc;
+    if (!w || !(ff > 0.0 && ff <= 1.0)) return PSVD_E_INVAL;
+    hipStream_t st = (hipStream_t)stream;
+    rc = grad_forward(g, A, lda, ff, st, grad != nullptr);
+    if (rc) return rc;
+    psvd_handle* h = g.h;
+    const int r = h->r;
+    const int Nt = B * (int)Nb;
+    // W = U^T A (r x Nt) and the column norms of A, both in FP64.
+    PanelSeg Us = make_seg(M);
+    seg_add(Us, make_block(h->U[h->cur].p, h->ldu, g.dt, r));
+    PanelSeg As = make_seg(M);
+    seg_add(As, make_block(A, lda, dtype, Nt));
+    DevBuf tmp;
+    HIPCHK(h, tmp.ensure(sizeof(double) * ((size_t)r * Nt + (size_t)Nt * Nt + (size_t)(Nt + r) * Nt + 64)));
+    double* dW = tmp.as<double>();
+    double* dAA = dW + (size_t)r * Nt;
+    double* dX = dAA + (size_t)Nt * Nt;
+    rc = tn_product(h, Us, As, false, true, dW, nullptr, 0, nullptr, 0);
+    if (rc) return rc;
+    rc = tn_product(h, As, As, true, true, dAA, nullptr, 0, nullptr, 0);
+    if (rc) return rc;
+    std::vector<double> W((size_t)r * Nt), AA((size_t)Nt * Nt), s(r);
+    HIPCHK(h, hipMemcpyAsync(W.data(), dW, sizeof(double) * W.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(AA.data(), dAA, sizeof(double) * AA.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(s.data(), h->s[h->cur].p, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    double a2 = 0.0, p2 = 0.0, ws = 0.0;
+    for (int j = 0; j < Nt; ++j) a2 += AA[(size_t)j * Nt + j];
+    for (double v : W) p2 += v * v;
+    for (int j = 0; j < r; ++j) ws += w[j] * s[j];
+    if (loss) *loss = a2 - p2 + ws;
+    if (!grad) return PSVD_OK;
+    // Direct term: grad = [A | U] [2 I; -2 W].
+    std::vector<double> X((size_t)(Nt + r) * Nt, 0.0);
+    for (int j = 0; j < Nt; ++j) {
+        X[(size_t)j * (Nt + r) + j] = 2.0;
+        for (int i = 0; i < r; ++i) X[(size_t)j * (Nt + r) + Nt + i] = -2.0 * W[(size_t)j * r + i];
+    }
+    HIPCHK(h, hipMemcpyAsync(dX, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice, st));
+    PanelSeg AU = As;
+    seg_add(AU, make_block(h->U[h->cur].p, h->ldu, g.dt, r));
+    AU.out = grad;
+    AU.ldo = M;
+    AU.out_dtype = dtype;
+    rc = nn_product(h, AU, dX, Nt + r, Nt, g.dt == PSVD_F64, nullptr, 0, nullptr, 0);
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(st));
+    // Final cotangents: U_bar = -2 A W^T, s_bar = w.
+    for (int b = 0; b < 2; ++b) HIPCHK(h, g.Ubar[b].ensure((size_t)M * K * g.esz));
+    std::vector<double> Wt((size_t)Nt * r);
+    for (int j = 0; j < Nt; ++j)
+        for (int i = 0; i < r; ++i) Wt[(size_t)i * Nt + j] = -2.0 * W[(size_t)j * r + i];
+    HIPCHK(h, hipMemcpyAsync(dX, Wt.data(), sizeof(double) * Wt.size(), hipMemcpyHostToDevice, st));
+    PanelSeg Ao = As;
+    Ao.out = g.Ubar[0].p;
+    Ao.ldo = M;
+    Ao.out_dtype = dtype;
+    rc = nn_product(h, Ao, dX, Nt, r, g.dt == PSVD_F64, nullptr, 0, nullptr, 0);
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(st));
+    rc = grad_backward(g, A, lda, ff, w, grad, 1, st);
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(st));
+    return PSVD_OK;
+}
