@@ -17,22 +17,39 @@ namespace psvd {
 
 constexpr int GR_THREADS = 1024;
 
+__device__ void grad_trsm_upper(const double* R, int n, const double* B, double* X) {
+    // X = R^-1 B (n x n), row by row from the bottom, all columns in parallel.
+    for (int i = n - 1; i >= 0; --i) {
+        const double rii = R[i + (size_t)i * n];
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            double s = B[i + (size_t)j * n];
+            for (int k = i + 1; k < n; ++k) s -= R[i + (size_t)k * n] * X[k + (size_t)j * n];
+            X[i + (size_t)j * n] = s / rii;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(GR_THREADS) void k_grad_core(GradCoreArgs a) {
+    extern __shared__ double lds[];
     const int n = a.n, rk = a.rk, r = a.r, tid = threadIdx.x;
     const double* R = a.R;
     const double* Ut = a.Ut;
     const double* S = a.S;
     if (*a.status & (DEV_FALLBACK | DEV_NONFINITE | DEV_BREAKDOWN | DEV_NOCONV)) return;
-    // T_f = R^-1 U~ (back substitution, one column per thread)
-    for (int j = tid; j < n; j += GR_THREADS) {
-        double* x = a.Tf + (size_t)j * n;
-        const double* u = Ut + (size_t)j * n;
-        for (int i = n - 1; i >= 0; --i) {
-            double s = u[i];
-            for (int k = i + 1; k < n; ++k) s -= R[i + (size_t)k * n] * x[k];
-            x[i] = s / R[i + (size_t)i * n];
-        }
+    // T_f = R^-1 U~ with R and the solution in LDS when they fit.
+    const bool in_lds = 2 * (size_t)n * n * sizeof(double) <= 150 * 1024;
+    if (in_lds) {
+        double* Rl = lds;
+        double* Xl = lds + (size_t)n * n;
+        for (int e = tid; e < n * n; e += GR_THREADS) Rl[e] = R[e];
+        __syncthreads();
+        grad_trsm_upper(Rl, n, Ut, Xl);
+        for (int e = tid; e < n * n; e += GR_THREADS) a.Tf[e] = Xl[e];
+    } else {
+        grad_trsm_upper(R, n, Ut, a.Tf);
     }
+    __syncthreads();
     // V = R^T U~ S^-1
     for (int e = tid; e < n * n; e += GR_THREADS) {
         int i = e % n, j = e / n;
@@ -101,7 +118,11 @@ __global__ void k_grad_sbar(const double* G, int r, const double* s_prev, double
 }
 
 hipError_t launch_grad_core(const GradCoreArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_grad_core, dim3(1), dim3(GR_THREADS), 0, st, a);
+    size_t lds = 2 * (size_t)a.n * a.n * sizeof(double);
+    if (lds > 150 * 1024) lds = 64;
+    hipError_t e = hipFuncSetAttribute((const void*)k_grad_core, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_core, dim3(1), dim3(GR_THREADS), lds, st, a);
     return hipGetLastError();
 }
 

@@ -192,6 +192,8 @@ hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st);
 hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st);
 bool fused_fits(bool bf16, int tm, int np);
 int fused_pick_tm(bool bf16, int np);
+int sketch_pick_tm(int np);
+hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st);
 hipError_t launch_fused(bool bf16, int mode, const FusedArgs& a, hipStream_t st);
 hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st);
 

@@ -479,24 +479,255 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     }
 }
 
+// ----------------------------------------------------------------------------
+// k_sketch_bf16: the BF16 power pass P += C^T (C X) with the 16x16x32 BF16
+// matrix-core instruction.  X (np x 64) lives in registers for the whole
+// launch; every tile is read once from HBM, converted to BF16 and written to
+// LDS twice (column-major for C^T Y, row-major for C X) with packed stores:
+// each thread moves a 4 x 4 block (four float4 column segments).
+// ----------------------------------------------------------------------------
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef short s8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ bf8_t lds_b128(const uint16_t* p) {
+    return __builtin_bit_cast(bf8_t, *(const s8_t*)p);   // 16-byte aligned by construction
+}
+
+template <int TM, int NRB, bool VEC>
+__global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
+    constexpr int NT = 512;
+    constexpr int JW = TM == 64 ? 2 : 1;            // column blocks of Y per wave in phase A
+    constexpr int NPMAX = NRB * 128;
+    constexpr int KS = NPMAX / 32;                  // k-steps of phase A
+    constexpr int RG = TM / 4;                      // row groups of 4
+    constexpr int CGR = NT / RG;                    // column groups (of 4) per round
+    constexpr int RMAX = (NPMAX / 4 + CGR - 1) / CGR;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int np = a.np;
+    const int ldC = TM + 8;
+    const int ldR = np + 8;
+    const int ldY = TM + 8;
+    uint16_t* Cs = (uint16_t*)smem;                 // np x TM, column-major
+    uint16_t* Cr = Cs + (size_t)np * ldC;           // TM x np, row-major
+    uint16_t* Ys = Cr + (size_t)TM * ldR;           // 64 x TM, column-major
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, local = b >> 3;
+    const int lb = local % a.nlb;
+    const int wg = (local / a.nlb) * 8 + xcd;
+    if (wg >= a.nwg) return;
+    const int c0 = lb * FU_LB;
+
+    // Phase-A unit of this wave: row block ib, column blocks jb0 .. jb0 + JW - 1.
+    const int ib = TM == 64 ? (w & 3) : (TM == 32 ? (w & 1) : 0);
+    const int jb0 = TM == 64 ? (w >> 2) * 2 : (TM == 32 ? (w >> 1) : w);
+    const bool a_active = (TM >= 32) || (w < 4);
+    bf8_t xf[JW][KS];
+#pragma unroll
+    for (int c = 0; c < JW; ++c)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            bf8_t v;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = ks * 32 + 8 * (lane >> 4) + q;
+                const int j = c0 + (jb0 + c) * 16 + (lane & 15);
+                double x = (k < a.n && j < a.lx) ? a.X[k + (int64_t)j * a.ldx] : 0.0;
+                v[q] = __builtin_bit_cast(__bf16, f32_to_bf16_rne((float)x));
+            }
+            xf[c][ks] = v;
+        }
+
+    const int nrb = np / 16;
+    f4_t accP[NRB * 4];
+#pragma unroll
+    for (int t = 0; t < NRB * 4; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int ncg = np / 4;
+    const int rounds = (ncg + CGR - 1) / CGR;
+    const int rg = tid % RG, cgl = tid / RG;
+    f4_t pf[RMAX][4];
+    auto fetch = [&](int64_t t) {
+        const int64_t row = t * TM + rg * 4;
+#pragma unroll
+        for (int rr = 0; rr < RMAX; ++rr) {
+            const int cg = rr * CGR + cgl;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
+                const int c = cg * 4 + q;
+                if (rr < rounds && c < a.n) {
+                    const float* p = fcol(a.seg, c);
+                    if (VEC && row + 3 < a.seg.rows) {
+                        v = *(const f4_t*)(p + row);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (row + e < a.seg.rows) v[e] = p[row + e];
+                    }
+                }
+                pf[rr][q] = v;
+            }
+        }
+    };
+
+    int64_t t = wg;
+    if (t < a.tiles) fetch(t);
+    for (; t < a.tiles; t += a.nwg) {
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < RMAX; ++rr) {
+            const int cg = rr * CGR + cgl;
+            if (rr < rounds && cg < ncg) {
+                uint16_t h[4][4];   // [column q][row e]
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) h[q][e] = f32_to_bf16_rne(pf[rr][q][e]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint64_t pk = (uint64_t)h[q][0] | ((uint64_t)h[q][1] << 16) | ((uint64_t)h[q][2] << 32) |
+                                  ((uint64_t)h[q][3] << 48);
+                    *(uint64_t*)&Cs[(cg * 4 + q) * ldC + rg * 4] = pk;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint64_t pk = (uint64_t)h[0][e] | ((uint64_t)h[1][e] << 16) | ((uint64_t)h[2][e] << 32) |
+                                  ((uint64_t)h[3][e] << 48);
+                    *(uint64_t*)&Cr[(rg * 4 + e) * ldR + cg * 4] = pk;
+                }
+            }
+        }
+        __syncthreads();
+        if (t + a.nwg < a.tiles) fetch(t + a.nwg);
+
+        // Phase A: Y_tile = C_tile X (X fragments in registers).
+        if (a_active) {
+            f4_t accY[JW];
+#pragma unroll
+            for (int c = 0; c < JW; ++c) accY[c] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks * 32 < np) {
+                    bf8_t av = lds_b128(&Cr[(ib * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4)]);
+#pragma unroll
+                    for (int c = 0; c < JW; ++c)
+                        accY[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[c][ks], accY[c], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < JW; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = ib * 16 + 4 * (lane >> 4) + v;
+                    const int col = (jb0 + c) * 16 + (lane & 15);
+                    Ys[col * ldY + row] = f32_to_bf16_rne(accY[c][v]);
+                }
+        }
+        __syncthreads();
+
+        // Phase B: P (np x 64) += C_tile^T Y_tile; wave w owns row blocks w, w + 8, ...
+#pragma unroll
+        for (int ks = 0; ks < TM / 32; ++ks) {
+            bf8_t bvs[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bvs[j] = lds_b128(&Ys[(j * 16 + (lane & 15)) * ldY + ks * 32 + 8 * (lane >> 4)]);
+#pragma unroll
+            for (int q = 0; q < NRB; ++q) {
+                const int rb = w + 8 * q;
+                if (rb < nrb) {
+                    bf8_t av = lds_b128(&Cs[(rb * 16 + (lane & 15)) * ldC + ks * 32 + 8 * (lane >> 4)]);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        accP[q * 4 + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bvs[j], accP[q * 4 + j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)np * FU_LB;
+#pragma unroll
+    for (int q = 0; q < NRB; ++q) {
+        const int rb = w + 8 * q;
+        if (rb < nrb) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rb * 16 + 4 * (lane >> 4) + v;
+                    const int col = j * 16 + (lane & 15);
+                    outP[row + (size_t)col * np] = accP[q * 4 + j][v];
+                }
+        }
+    }
+}
+
+size_t sketch_lds_bytes(int tm, int np) {
+    return ((size_t)np * (tm + 8) + (size_t)tm * (np + 8) + (size_t)FU_LB * (tm + 8)) * 2;
+}
+
+int sketch_pick_tm(int np) {
+    if (np > 640 || np % 32) return 0;
+    for (int tm : {64, 32})
+        if (sketch_lds_bytes(tm, np) <= 160 * 1024 && (np <= 384 || tm == 32)) return tm;
+    return 0;
+}
+
+template <int TM, int NRB, bool VEC>
+static hipError_t launch_sketch_k(const FusedArgs& a, hipStream_t st) {
+    size_t lds = sketch_lds_bytes(TM, a.np);
+    int blocks = ((a.nwg + 7) / 8) * 8 * a.nlb;
+    hipError_t e = hipFuncSetAttribute((const void*)k_sketch_bf16<TM, NRB, VEC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sketch_bf16<TM, NRB, VEC>), dim3(blocks), dim3(512), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st) {
+    const bool v = a.vec != 0;
+    if (a.tm == 64 && a.np <= 384) return v ? launch_sketch_k<64, 3, true>(a, st) : launch_sketch_k<64, 3, false>(a, st);
+    if (a.tm == 32 && a.np <= 384) return v ? launch_sketch_k<32, 3, true>(a, st) : launch_sketch_k<32, 3, false>(a, st);
+    if (a.tm == 32 && a.np <= 640) return v ? launch_sketch_k<32, 5, true>(a, st) : launch_sketch_k<32, 5, false>(a, st);
+    return hipErrorInvalidValue;
+}
+
 // Fixed-order FP64 sum of the fused partials: P (n x lx, ld n) and G (lx x lx).
 
+// 32 outputs per block, 8 threads per output each summing every 8th partial;
+// the 8 sums are combined in a fixed order (deterministic).
 __global__ __launch_bounds__(256) void k_fused_reduce(FusedReduceArgs a) {
-    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t totP = (int64_t)a.n * a.lx;
+    __shared__ double red[8][33];
+    const int lane_o = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int64_t e = (int64_t)blockIdx.x * 32 + lane_o;
+    const int64_t totP = (int64_t)a.n * a.lx;
+    const int64_t tot = totP + (a.want_g ? (int64_t)a.lx * a.lx : 0);
+    double s = 0.0;
     if (e < totP) {
-        int i = (int)(e % a.n), j = (int)(e / a.n);
-        int lb = j / FU_LB, jj = j % FU_LB;
-        double s = 0.0;
-        for (int g = 0; g < a.nwg; ++g) s += (double)a.partP[((size_t)g * a.nlb + lb) * (size_t)a.np * FU_LB + i + (size_t)jj * a.np];
-        if (a.row_scale && i < a.nscale) s *= a.row_scale[i];
-        a.P[i + (size_t)j * a.n] = s;
-    } else if (a.want_g && e < totP + (int64_t)a.lx * a.lx) {
-        int64_t f = e - totP;
-        int i = (int)(f % a.lx), j = (int)(f / a.lx);
-        double s = 0.0;
-        for (int g = 0; g < a.nwg; ++g) s += a.partG[(size_t)g * FU_LB * FU_LB + i + (size_t)j * FU_LB];
-        a.G[i + (size_t)j * a.lx] = s;
+        const int i = (int)(e % a.n), j = (int)(e / a.n);
+        const int lb = j / FU_LB, jj = j % FU_LB;
+        const size_t stride = (size_t)a.nlb * a.np * FU_LB;
+        const float* p = a.partP + (size_t)lb * a.np * FU_LB + i + (size_t)jj * a.np;
+        for (int g = grp; g < a.nwg; g += 8) s += (double)p[(size_t)g * stride];
+    } else if (e < tot) {
+        const int64_t f = e - totP;
+        const int i = (int)(f % a.lx), j = (int)(f / a.lx);
+        const double* p = a.partG + i + (size_t)j * FU_LB;
+        for (int g = grp; g < a.nwg; g += 8) s += p[(size_t)g * FU_LB * FU_LB];
+    }
+    red[grp][lane_o] = s;
+    __syncthreads();
+    if (grp == 0 && e < tot) {
+        double t = 0.0;
+        for (int q = 0; q < 8; ++q) t += red[q][lane_o];
+        if (e < totP) {
+            const int i = (int)(e % a.n), j = (int)(e / a.n);
+            if (a.row_scale && i < a.nscale) t *= a.row_scale[i];
+            a.P[i + (size_t)j * a.n] = t;
+        } else {
+            const int64_t f = e - totP;
+            a.G[(f % a.lx) + (size_t)(f / a.lx) * a.lx] = t;
+        }
     }
 }
 
@@ -578,7 +809,7 @@ hipError_t launch_fused(bool bf16, int mode, const FusedArgs& a, hipStream_t st)
 
 hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st) {
     int64_t tot = (int64_t)a.n * a.lx + (a.want_g ? (int64_t)a.lx * a.lx : 0);
-    dim3 grid((unsigned)((tot + 255) / 256));
+    dim3 grid((unsigned)((tot + 31) / 32));
     hipLaunchKernelGGL(k_fused_reduce, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }

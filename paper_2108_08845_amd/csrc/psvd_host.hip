@@ -305,7 +305,7 @@ static int ensure_workspace(psvd_handle* h, int n) {
     int nb = ceil_div(w, 64);
     size_t nob = (size_t)nb * nb;
     HIPCHK(h, h->part.ensure((size_t)(2048 + 2 * nob) * 64 * 64 * sizeof(double)));
-    int np = ((n + 15) / 16) * 16;
+    int np = ((n + 31) / 32) * 32;
     int nlb = ceil_div(std::max(l, 1), 64);
     HIPCHK(h, h->partP.ensure((size_t)256 * nlb * np * 64 * sizeof(float)));
     HIPCHK(h, h->partG.ensure((size_t)256 * 64 * 64 * sizeof(double)));
@@ -461,7 +461,11 @@ static int small_orth(psvd_handle* h, const SmallLayout& L, int n, int l, double
     ca.l = l;
     ca.status = (int32_t*)st;
     ca.flag_bit = DEV_FALLBACK;
-    HIPCHK(h, launch_small_chol(ca, h->stream));
+    {
+        int pes = prof_begin(h, PSVD_KC_SMALL);
+        HIPCHK(h, launch_small_chol(ca, h->stream));
+        prof_end(h, pes);
+    }
     Ps.out = Xout;
     Ps.ldo = n;
     rc = nn_product(h, Ps, L.RYi, l, l, true, h->d.as<double>(), h->r, nullptr, 0);
@@ -675,7 +679,11 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         sa.ivec = h->ivec.as<int32_t>();
         sa.status = dstat;
         sa.sweeps = dsweeps;
-        HIPCHK(h, launch_small_det1(sa, st));
+        {
+            int pes = prof_begin(h, PSVD_KC_SMALL);
+            HIPCHK(h, launch_small_det1(sa, st));
+            prof_end(h, pes);
+        }
         const int skipmask = DEV_FALLBACK | DEV_NONFINITE | DEV_BREAKDOWN;
         // Q1 = C D R1^-1 (tall temporary), G2 = Q1^T Q1.
         PanelSeg Q = C;
@@ -688,7 +696,11 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         seg_add(Q1, make_block(h->tall.p, M, tall_dtype, n));
         rc = tn_product(h, Q1, Q1, true, true, L.G2, nullptr, 0, dstat, skipmask);
         if (rc) return rc;
-        HIPCHK(h, launch_small_det2(sa, st));
+        {
+            int pes = prof_begin(h, PSVD_KC_SMALL);
+            HIPCHK(h, launch_small_det2(sa, st));
+            prof_end(h, pes);
+        }
         // Lift: U = Q1 R2^-1 U~_rk from the kept Cholesky-QR factor; on the eigen
         // route (no Q1) U = C D V_rk diag(1/sigma) straight from the panel.
         PanelSeg Qs = Q1;
@@ -724,10 +736,14 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         // X' = D Omega
         HIPCHK(h, launch_scale_rows(L.X, n, l, n, dsc, r, 1, st));
         const int np = ((n + 15) / 16) * 16;
+        const int np32 = ((n + 31) / 32) * 32;
         const int nlb = ceil_div(l, 64);
         auto pass = [&](bool bf16, bool want_g) -> int {
             // P = D C'^T (C' X')  [+ G_Y = Y^T Y]
-            const int tm = fused_pick_tm(bf16, np);
+            // BF16 power passes up to 384 columns use the 16x16x32 sketch kernel.
+            const bool sketch = bf16 && !want_g && np32 <= 384;
+            const int npk = sketch ? np32 : np;      // the sketch kernel steps k by 32
+            const int tm = sketch ? 32 : fused_pick_tm(bf16, np);
             bool fuse_ok = !fp64 && tm > 0 && seg_all_f32(C) && (!want_g || nlb == 1);
             if (fuse_ok) {
                 FusedArgs fa;
@@ -736,7 +752,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 fa.X = L.X;
                 fa.ldx = n;
                 fa.n = n;
-                fa.np = np;
+                fa.np = npk;
                 fa.lx = l;
                 fa.nlb = nlb;
                 fa.tm = tm;
@@ -748,7 +764,8 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 fa.want_g = want_g ? 1 : 0;
                 fa.vec = seg_vec_ok(C, false) ? 1 : 0;
                 int pe = prof_begin(h, bf16 ? PSVD_KC_FUSED_BF16 : PSVD_KC_FUSED_F32);
-                HIPCHK(h, launch_fused(bf16, want_g ? 1 : 0, fa, st));
+                if (sketch) HIPCHK(h, launch_sketch_bf16(fa, st));
+                else HIPCHK(h, launch_fused(bf16, want_g ? 1 : 0, fa, st));
                 prof_end(h, pe);
                 FusedReduceArgs ra;
                 std::memset(&ra, 0, sizeof(ra));
@@ -758,7 +775,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 ra.partG = h->partG.as<double>();
                 ra.nwg = fa.nwg;
                 ra.nlb = nlb;
-                ra.np = np;
+                ra.np = npk;
                 ra.n = n;
                 ra.lx = l;
                 ra.want_g = fa.want_g;
@@ -796,7 +813,11 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         cy.l = l;
         cy.status = dstat;
         cy.flag_bit = DEV_FALLBACK;
-        HIPCHK(h, launch_small_chol(cy, st));
+        {
+            int pes = prof_begin(h, PSVD_KC_SMALL);
+            HIPCHK(h, launch_small_chol(cy, st));
+            prof_end(h, pes);
+        }
         // R_P: Cholesky-QR2 of P.
         PanelSeg Ps = small_seg(L.P, n, l, n);
         rc = tn_product(h, Ps, Ps, true, true, L.H, nullptr, 0, nullptr, 0);
@@ -807,7 +828,11 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         c1.l = l;
         c1.status = dstat;
         c1.flag_bit = DEV_FALLBACK;
-        HIPCHK(h, launch_small_chol(c1, st));
+        {
+            int pes = prof_begin(h, PSVD_KC_SMALL);
+            HIPCHK(h, launch_small_chol(c1, st));
+            prof_end(h, pes);
+        }
         Ps.out = L.P1;
         Ps.ldo = n;
         rc = nn_product(h, Ps, L.R1b, l, l, true, nullptr, 0, nullptr, 0);
@@ -831,7 +856,11 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         rf.ivec = h->ivec.as<int32_t>();
         rf.status = dstat;
         rf.sweeps = dsweeps;
-        HIPCHK(h, launch_small_rand_final(rf, st));
+        {
+            int pes = prof_begin(h, PSVD_KC_SMALL);
+            HIPCHK(h, launch_small_rand_final(rf, st));
+            prof_end(h, pes);
+        }
         // T' = X' M2 (n x rk), U_new = C' T'.
         PanelSeg Xs = small_seg(L.X, n, l, n, L.T, n);
         rc = nn_product(h, Xs, L.M2, l, rk, true, nullptr, 0, nullptr, 0);
@@ -1039,7 +1068,11 @@ int grad_backward(GradCtx& g, const void* A, int64_t lda, double ff, const doubl
         sa.status = dstat;
         sa.sweeps = dstat + 1;
         HIPCHK(h, hipMemcpyAsync(gR, L.G, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
-        HIPCHK(h, launch_small_det1(sa, st));
+        {
+            int pes = prof_begin(h, PSVD_KC_SMALL);
+            HIPCHK(h, launch_small_det1(sa, st));
+            prof_end(h, pes);
+        }
         PanelSeg Q = C;
         Q.out = h->tall.p;
         Q.ldo = g.M;
@@ -1050,7 +1083,11 @@ int grad_backward(GradCtx& g, const void* A, int64_t lda, double ff, const doubl
         seg_add(Q1, make_block(h->tall.p, g.M, h->u_dtype, n));
         rc = tn_product(h, Q1, Q1, true, true, L.G2, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN);
         if (rc) return rc;
-        HIPCHK(h, launch_small_det2(sa, st));
+        {
+            int pes = prof_begin(h, PSVD_KC_SMALL);
+            HIPCHK(h, launch_small_det2(sa, st));
+            prof_end(h, pes);
+        }
         // E = C^T U_bar (C with its column scale).
         PanelSeg Ubs = make_seg(g.M);
         seg_add(Ubs, make_block(g.Ubar[cb].p, g.M, g.dt, rk));

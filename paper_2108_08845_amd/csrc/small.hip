@@ -40,24 +40,18 @@ __device__ bool wg_chol_upper(double* A, int n, int lda, int* sflag) {
         __syncthreads();
         if (*sflag) return false;
         const double rkk = A[k + (size_t)k * lda];
-        for (int j = k + 1 + tid; j < n; j += SM_THREADS) A[k + (size_t)j * lda] /= rkk;
+        for (int j = k + 1 + tid; j < n; j += blockDim.x) A[k + (size_t)j * lda] /= rkk;
         __syncthreads();
         // trailing update of the upper triangle: A[i][j] -= R[k][i] R[k][j], k < i <= j
         const int m = n - k - 1;
-        const int tot = m * (m + 1) / 2;
-        for (int e = tid; e < tot; e += SM_THREADS) {
-            // map e -> (i, j) with i <= j in the trailing block (column-wise packing)
-            int jj = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-            while ((jj + 1) * (jj + 2) / 2 <= e) ++jj;
-            while (jj * (jj + 1) / 2 > e) --jj;
-            int ii = e - jj * (jj + 1) / 2;
-            int i = k + 1 + ii, j = k + 1 + jj;
-            A[i + (size_t)j * lda] -= A[k + (size_t)i * lda] * A[k + (size_t)j * lda];
+        for (int e = tid; e < m * m; e += blockDim.x) {
+            const int i = k + 1 + e % m, j = k + 1 + e / m;
+            if (i <= j) A[i + (size_t)j * lda] -= A[k + (size_t)i * lda] * A[k + (size_t)j * lda];
         }
         __syncthreads();
     }
     // zero the strict lower triangle
-    for (int e = tid; e < n * n; e += SM_THREADS) {
+    for (int e = tid; e < n * n; e += blockDim.x) {
         int i = e % n, j = e / n;
         if (i > j) A[i + (size_t)j * lda] = 0.0;
     }
@@ -65,22 +59,38 @@ __device__ bool wg_chol_upper(double* A, int n, int lda, int* sflag) {
     return true;
 }
 
-// Ri = R^-1 for upper triangular R (n x n): column j solves R x = e_j.
-__device__ void wg_trinv_upper(const double* R, int n, int ldr, double* Ri, int ldi) {
+// X (n x nrhs) = R^-1 B for upper triangular R (n x n), row by row from the
+// bottom: step i fixes row i of X for every right-hand side in parallel, so no
+// thread ever waits on a value it has just stored.  B == nullptr means B = I
+// (X = R^-1, upper triangular).  X must not alias R or B.
+__device__ void wg_trsm_upper(const double* R, int ldr, int n, const double* B, int ldb, double* X, int ldx,
+                              int nrhs) {
     const int tid = threadIdx.x;
-    for (int j = tid; j < n; j += SM_THREADS) {
-        double* x = Ri + (size_t)j * ldi;
-        for (int i = n - 1; i >= 0; --i) {
-            if (i > j) {
-                x[i] = 0.0;
-                continue;
+    for (int i = n - 1; i >= 0; --i) {
+        const double rii = R[i + (size_t)i * ldr];
+        for (int j = tid; j < nrhs; j += blockDim.x) {
+            double s;
+            int kend = n;
+            if (B) {
+                s = B[i + (size_t)j * ldb];
+            } else {
+                s = (i == j) ? 1.0 : 0.0;
+                kend = j + 1;                       // rows k > j of column j of R^-1 are zero
+                if (i > j) {
+                    X[i + (size_t)j * ldx] = 0.0;
+                    continue;
+                }
             }
-            double s = (i == j) ? 1.0 : 0.0;
-            for (int k = i + 1; k <= j; ++k) s -= R[i + (size_t)k * ldr] * x[k];
-            x[i] = s / R[i + (size_t)i * ldr];
+            for (int k = i + 1; k < kend; ++k) s -= R[i + (size_t)k * ldr] * X[k + (size_t)j * ldx];
+            X[i + (size_t)j * ldx] = s / rii;
         }
+        __syncthreads();
     }
-    __syncthreads();
+}
+
+// Ri = R^-1 for upper triangular R (n x n).
+__device__ void wg_trinv_upper(const double* R, int n, int ldr, double* Ri, int ldi) {
+    wg_trsm_upper(R, ldr, n, nullptr, 0, Ri, ldi, n);
 }
 
 // C (m x n) = A (m x k) * B (k x n); all column-major, parallel over outputs.
@@ -225,34 +235,71 @@ __device__ void wg_sign_rule(double* X, int rows, int k, int ldx, double* flip) 
 // Workspace of the small core (device, FP64).
 // ---------------------------------------------------------------------------
 
+// Largest order whose n x n FP64 working matrix (plus 3 n scratch) fits in LDS.
+constexpr int SM_LDS_MAX_N = 140;
+
+// Two n x n working matrices when they fit (n <= 90), else one (n <= 140).
+constexpr int SM_LDS_TWO_N = 90;
+
+__host__ __device__ inline size_t small_lds_bytes(int n) {
+    if (n <= SM_LDS_TWO_N) return (2 * (size_t)n * n + 4 * (size_t)n + 8) * sizeof(double);
+    return n <= SM_LDS_MAX_N ? ((size_t)n * n + 4 * (size_t)n + 8) * sizeof(double) : 64;
+}
+
+// Start of the 3n-double vector scratch inside the LDS buffer.
+__device__ __forceinline__ double* lds_vecs(double* lds, int n) {
+    return lds + (n <= SM_LDS_TWO_N ? 2 : 1) * (size_t)n * n;
+}
+
+// Working copy of an n x n matrix: LDS when it fits, else the global buffer itself.
+__device__ __forceinline__ double* stage_in(double* lds, double* g, int n, bool in_lds) {
+    if (!in_lds) return g;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) lds[e] = g[e];
+    __syncthreads();
+    return lds;
+}
+
+__device__ __forceinline__ void stage_out(const double* w, double* g, int n, bool in_lds) {
+    if (!in_lds) return;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) g[e] = w[e];
+    __syncthreads();
+}
+
 __device__ __forceinline__ double dscale(const SmallArgs& a, int j) { return j < a.r ? a.d[j] : 1.0; }
 
 __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
+    extern __shared__ double lds[];
     __shared__ int sflag;
-    const int n = a.n, tid = threadIdx.x;
-    // G <- D G' D, NaN/Inf check
     __shared__ int nonfinite;
+    const int n = a.n, tid = threadIdx.x;
+    const bool in_lds = n <= SM_LDS_MAX_N;
+    double* W = in_lds ? lds : a.R1;
+    // G <- D G' D, NaN/Inf check
     if (tid == 0) nonfinite = 0;
     __syncthreads();
     for (int e = tid; e < n * n; e += SM_THREADS) {
-        int i = e % n, j = e / n;
-        double v = a.G[e] * dscale(a, i) * dscale(a, j);
+        const int i = e % n, j = e / n;
+        const double v = a.G[e] * dscale(a, i) * dscale(a, j);
         if (!finite_d(v)) nonfinite = 1;
         a.G[e] = v;
-        a.R1[e] = v;
+        W[e] = v;
     }
     __syncthreads();
     if (nonfinite) {
         if (tid == 0) *a.status |= DEV_NONFINITE;
         return;
     }
-    bool ok = wg_chol_upper(a.R1, n, n, &sflag);
+    bool ok = wg_chol_upper(W, n, n, &sflag);
     if (ok) {
-        wg_trinv_upper(a.R1, n, n, a.Ri, n);
-        // Xn = D R1^-1
+        stage_out(W, a.R1, n, in_lds);
+        double* X = (n <= SM_LDS_TWO_N) ? lds + (size_t)n * n : a.Ri;
+        wg_trinv_upper(in_lds ? W : a.R1, n, n, X, n);
+        // Ri and Xn = D R1^-1
         for (int e = tid; e < n * n; e += SM_THREADS) {
-            int i = e % n;
-            a.Xn[e] = a.Ri[e] * dscale(a, i);
+            const double v = X[e];
+            a.Ri[e] = v;
+            a.Xn[e] = v * dscale(a, e % n);
         }
         return;
     }
@@ -264,31 +311,30 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
     // (G V has orthogonal columns lambda_j v_j); sigma_j = sqrt(lambda_j),
     // U_new = C V_K diag(1 / sigma_K).
     if (tid == 0) *a.status |= DEV_FALLBACK;
-    for (int e = tid; e < n * n; e += SM_THREADS) a.Z[e] = a.G[e];
+    for (int e = tid; e < n * n; e += SM_THREADS) W[e] = a.G[e];
     __syncthreads();
-    double* sig = a.vec;
-    double* nrm = a.vec + n;
-    int sw = wg_jacobi(a.Z, n, n, n, sig, a.ivec, nrm, a.max_sweeps, &sflag);
+    double* sig = in_lds ? lds_vecs(lds, n) : a.vec;
+    double* nrm = sig + n;
+    int* ord = in_lds ? (int*)(nrm + n) : a.ivec;
+    int sw = wg_jacobi(W, n, n, n, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
     }
     const int rk = a.K < n ? a.K : n;
-    // sorted eigenvectors (normalised columns of Z) -> small_u, sign rule
     for (int e = tid; e < n * rk; e += SM_THREADS) {
-        int i = e % n, j = e / n;
-        a.small_u[i + (size_t)j * n] = a.Z[i + (size_t)a.ivec[j] * n];
+        const int i = e % n, j = e / n;
+        a.small_u[i + (size_t)j * n] = W[i + (size_t)ord[j] * n];
     }
-    __syncthreads();
-    wg_sign_rule(a.small_u, n, rk, n, nullptr);
     for (int j = tid; j < rk; j += SM_THREADS) {
-        double lam = sig[a.ivec[j]];
+        const double lam = sig[ord[j]];
         a.s_out[j] = sqrt(lam > 0.0 ? lam : 0.0);
     }
     __syncthreads();
+    wg_sign_rule(a.small_u, n, rk, n, nullptr);
     for (int e = tid; e < n * rk; e += SM_THREADS) {
-        int i = e % n, j = e / n;
-        double sj = a.s_out[j];
+        const int i = e % n, j = e / n;
+        const double sj = a.s_out[j];
         a.T[i + (size_t)j * n] = sj > 0.0 ? dscale(a, i) * a.small_u[i + (size_t)j * n] / sj : 0.0;
     }
 }
@@ -297,142 +343,161 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
 // R -> U~ (left vectors), S; sort, sign rule, keep rk = min(K, n);
 // T = D R^-1 U~_rk.
 __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
+    extern __shared__ double lds[];
     __shared__ int sflag;
     if (*a.status & (DEV_FALLBACK | DEV_NONFINITE | DEV_BREAKDOWN)) return;
     const int n = a.n, tid = threadIdx.x;
-    bool ok = wg_chol_upper(a.G2, n, n, &sflag);
+    const bool in_lds = n <= SM_LDS_MAX_N;
+    double* W = stage_in(lds, a.G2, n, in_lds);
+    bool ok = wg_chol_upper(W, n, n, &sflag);
     if (!ok) {
         // Q1 is orthonormal to working accuracy once the first factor exists;
         // a breakdown here means non-finite data.
         if (tid == 0) *a.status |= DEV_NONFINITE;
         return;
     }
-    // R = R2 R1 (upper) -> Z
+    const bool two = n <= SM_LDS_TWO_N;
+    double* R2 = two ? lds + (size_t)n * n : a.G2;     // R2 kept for the final solve
     for (int e = tid; e < n * n; e += SM_THREADS) {
-        int i = e % n, j = e / n;
-        double s = 0.0;
-        for (int k = i; k <= j; ++k) s += a.G2[i + (size_t)k * n] * a.R1[k + (size_t)j * n];
-        a.Z[e] = (i <= j) ? s : 0.0;
+        const double v = W[e];
+        if (two) R2[e] = v;
+        if (in_lds) a.G2[e] = v;
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += SM_THREADS) a.G[e] = a.Z[e];  // keep R
+    // R = R2 R1 (upper) -> a.G (kept) and the working matrix
+    for (int e = tid; e < n * n; e += SM_THREADS) {
+        const int i = e % n, j = e / n;
+        double s = 0.0;
+        for (int k = i; k <= j; ++k) s += R2[i + (size_t)k * n] * a.R1[k + (size_t)j * n];
+        a.G[e] = (i <= j) ? s : 0.0;
+    }
     __syncthreads();
-    double* sig = a.vec;
-    double* nrm = a.vec + n;
-    int sw = wg_jacobi(a.Z, n, n, n, sig, a.ivec, nrm, a.max_sweeps, &sflag);
+    W = in_lds ? lds : a.Z;
+    for (int e = tid; e < n * n; e += SM_THREADS) W[e] = a.G[e];
+    __syncthreads();
+    double* sig = in_lds ? lds_vecs(lds, n) : a.vec;
+    double* nrm = sig + n;
+    int* ord = in_lds ? (int*)(nrm + n) : a.ivec;
+    int sw = wg_jacobi(W, n, n, n, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
     }
     const int rk = a.K < n ? a.K : n;
     for (int e = tid; e < n * rk; e += SM_THREADS) {
-        int i = e % n, j = e / n;
-        a.small_u[i + (size_t)j * n] = a.Z[i + (size_t)a.ivec[j] * n];
+        const int i = e % n, j = e / n;
+        a.small_u[i + (size_t)j * n] = W[i + (size_t)ord[j] * n];
     }
-    for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sig[a.ivec[j]];
+    for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sig[ord[j]];
     __syncthreads();
     wg_sign_rule(a.small_u, n, rk, n, nullptr);
     // The lift reads Q1 = C D R1^-1 (the first Cholesky-QR factor, kept by the
-    // second Gram pass): U = Q1 R2^-1 U~_rk, so T = R2^-1 U~ (back substitution).
-    const double* R2 = a.G2;
-    for (int j = tid; j < rk; j += SM_THREADS) {
-        double* x = a.T + (size_t)j * n;
-        const double* u = a.small_u + (size_t)j * n;
-        for (int i = n - 1; i >= 0; --i) {
-            double s = u[i];
-            for (int k = i + 1; k < n; ++k) s -= R2[i + (size_t)k * n] * x[k];
-            x[i] = s / R2[i + (size_t)i * n];
-        }
-    }
+    // second Gram pass): U = Q1 R2^-1 U~_rk, so T = R2^-1 U~ (row-step solve;
+    // the working matrix is free again and holds the solution when in LDS).
+    double* X = in_lds ? W : a.T;
+    wg_trsm_upper(R2, n, n, a.small_u, n, X, n, rk);
+    if (in_lds)
+        for (int e = tid; e < n * rk; e += SM_THREADS) a.T[e] = X[e];
 }
 
 // ---------------------------------------------------------------------------
 // Randomized-path small kernels.
 // ---------------------------------------------------------------------------
 
-// R = chol(H) in place, Ri = R^-1.  On breakdown a diagonal shift
+// R = chol(H) (R overwrites H), Ri = R^-1.  On breakdown a diagonal shift
 // s = 11 (l^2 + l) 2^-53 ||H||_F (shifted Cholesky-QR of Fukaya et al. 2020)
 // is added and the factorisation repeated.
-__global__ __launch_bounds__(SM_THREADS) void k_small_chol(CholArgs a) {
+__global__ __launch_bounds__(256) void k_small_chol(CholArgs a) {
+    extern __shared__ double lds[];
     __shared__ int sflag;
     __shared__ double fro;
     const int l = a.l, tid = threadIdx.x;
     if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
-    if (tid == 0) fro = 0.0;
+    const bool in_lds = l <= SM_LDS_MAX_N;
+    double* W = in_lds ? lds : a.Ri;   // global fallback works in Ri and keeps H for the retry
+    for (int e = tid; e < l * l; e += blockDim.x) W[e] = a.H[e];
     __syncthreads();
-    // Keep a copy of H in Ri for the retry.
-    for (int e = tid; e < l * l; e += SM_THREADS) a.Ri[e] = a.H[e];
-    __syncthreads();
-    bool ok = wg_chol_upper(a.H, l, l, &sflag);
+    bool ok = wg_chol_upper(W, l, l, &sflag);
     if (!ok) {
         if (tid == 0) {
             double f = 0.0;
-            for (int e = 0; e < l * l; ++e) f += a.Ri[e] * a.Ri[e];
+            for (int e = 0; e < l * l; ++e) f += a.H[e] * a.H[e];
             fro = sqrt(f);
             *a.status |= a.flag_bit;
         }
         __syncthreads();
-        double shift = 11.0 * ((double)l * l + l) * 0x1p-53 * fro;
-        for (int e = tid; e < l * l; e += SM_THREADS) {
-            int i = e % l, j = e / l;
-            a.H[e] = a.Ri[e] + (i == j ? shift : 0.0);
+        const double shift = 11.0 * ((double)l * l + l) * 0x1p-53 * fro;
+        for (int e = tid; e < l * l; e += blockDim.x) {
+            const int i = e % l, j = e / l;
+            W[e] = a.H[e] + (i == j ? shift : 0.0);
         }
         __syncthreads();
-        ok = wg_chol_upper(a.H, l, l, &sflag);
+        ok = wg_chol_upper(W, l, l, &sflag);
         if (!ok) {
             if (tid == 0) *a.status |= DEV_NONFINITE;
             return;
         }
     }
-    wg_trinv_upper(a.H, l, l, a.Ri, l);
+    for (int e = tid; e < l * l; e += blockDim.x) a.H[e] = W[e];
+    __syncthreads();
+    if (l <= SM_LDS_TWO_N) {
+        double* X = lds + (size_t)l * l;
+        wg_trinv_upper(W, l, l, X, l);
+        for (int e = tid; e < l * l; e += blockDim.x) a.Ri[e] = X[e];
+    } else {
+        wg_trinv_upper(in_lds ? W : a.H, l, l, a.Ri, l);
+    }
 }
-
 
 // R_P = chol(H2) R1 (QR factor of P); R_b = R_P R_Y^-1; the left singular
 // vectors of B = R_Y^-T P^T are those of R_b^T: one-sided Jacobi on R_b^T.
 __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a) {
+    extern __shared__ double lds[];
     __shared__ int sflag;
     if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
     const int l = a.l, tid = threadIdx.x;
-    bool ok = wg_chol_upper(a.H2, l, l, &sflag);
+    const bool in_lds = l <= SM_LDS_MAX_N;
+    double* W = stage_in(lds, a.H2, l, in_lds);
+    bool ok = wg_chol_upper(W, l, l, &sflag);          // R2
     if (!ok) {
         if (tid == 0) *a.status |= DEV_NONFINITE;
         return;
     }
-    // M2 <- R_P = R2 R1 (upper), temporarily
+    // Z = R_P = R2 R1 (upper)
     for (int e = tid; e < l * l; e += SM_THREADS) {
-        int i = e % l, j = e / l;
+        const int i = e % l, j = e / l;
         double s = 0.0;
-        for (int k = i; k <= j; ++k) s += a.H2[i + (size_t)k * l] * a.R1[k + (size_t)j * l];
+        for (int k = i; k <= j; ++k) s += W[i + (size_t)k * l] * a.R1[k + (size_t)j * l];
         a.Z[e] = i <= j ? s : 0.0;
     }
     __syncthreads();
-    // R_b = R_P R_Y^-1 ; Z <- R_b^T
+    // W = R_b^T with R_b = R_P R_Y^-1
     for (int e = tid; e < l * l; e += SM_THREADS) {
-        int i = e % l, j = e / l;
+        const int i = e % l, j = e / l;
         double s = 0.0;
         for (int k = i; k <= j; ++k) s += a.Z[i + (size_t)k * l] * a.RYi[k + (size_t)j * l];
-        a.H2[j + (size_t)i * l] = i <= j ? s : 0.0;   // transpose into H2
+        W[j + (size_t)i * l] = i <= j ? s : 0.0;
     }
     __syncthreads();
-    double* sig = a.vec;
-    double* nrm = a.vec + l;
-    int sw = wg_jacobi(a.H2, l, l, l, sig, a.ivec, nrm, a.max_sweeps, &sflag);
+    double* sig = in_lds ? lds_vecs(lds, l) : a.vec;
+    double* nrm = sig + l;
+    int* ord = in_lds ? (int*)(nrm + l) : a.ivec;
+    int sw = wg_jacobi(W, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
     }
     const int rk = a.K < l ? a.K : l;
     for (int e = tid; e < l * rk; e += SM_THREADS) {
-        int i = e % l, j = e / l;
-        a.small_u[i + (size_t)j * l] = a.H2[i + (size_t)a.ivec[j] * l];
+        const int i = e % l, j = e / l;
+        a.small_u[i + (size_t)j * l] = W[i + (size_t)ord[j] * l];
     }
-    for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sig[a.ivec[j]];
+    for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sig[ord[j]];
     __syncthreads();
     wg_sign_rule(a.small_u, l, rk, l, nullptr);
     // M2 = R_Y^-1 U~_rk
     for (int e = tid; e < l * rk; e += SM_THREADS) {
-        int i = e % l, j = e / l;
+        const int i = e % l, j = e / l;
         double s = 0.0;
         for (int k = i; k < l; ++k) s += a.RYi[i + (size_t)k * l] * a.small_u[k + (size_t)j * l];
         a.M2[i + (size_t)j * l] = s;
@@ -465,12 +530,14 @@ __global__ void k_make_scale(double* d, const double* s, int r, double ff) {
 // One work-group per partition: eigen-decomposition of G_i by one-sided
 // Jacobi; W_i = V_i[:, :r] diag(sqrt(lambda_i[:r])) stored transposed.
 __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
+    extern __shared__ double lds[];
     __shared__ int sflag;
     const int i = blockIdx.x, N = a.N, tid = threadIdx.x;
-    double* G = a.G + (size_t)i * N * N;
-    double* sig = a.vec + (size_t)i * 2 * N;
+    const bool in_lds = N <= SM_LDS_MAX_N;
+    double* G = stage_in(lds, a.G + (size_t)i * N * N, N, in_lds);
+    double* sig = in_lds ? lds_vecs(lds, N) : a.vec + (size_t)i * 2 * N;
     double* nrm = sig + N;
-    int* ord = a.ivec + (size_t)i * N;
+    int* ord = in_lds ? (int*)(nrm + N) : a.ivec + (size_t)i * N;
     int sw = wg_jacobi(G, N, N, N, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0 && sw > a.max_sweeps) atomicOr(a.status, (int)DEV_NOCONV);
     if (tid == 0) atomicMax(a.sweeps, sw);
@@ -488,21 +555,25 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
 // W W^T = X Lambda^2 X^T by one-sided Jacobi; keep K; sign rule on X~;
 // T = X~ diag(1 / Lambda~) with the guard Lambda~_K > N 2^-53 Lambda~_1.
 __global__ __launch_bounds__(SM_THREADS) void k_apmos_global(ApmosGlobalArgs a) {
+    extern __shared__ double lds[];
     __shared__ int sflag;
     const int N = a.N, tid = threadIdx.x;
-    double* sig = a.vec;
-    double* nrm = a.vec + N;
-    int sw = wg_jacobi(a.WW, N, N, N, sig, a.ivec, nrm, a.max_sweeps, &sflag);
+    const bool in_lds = N <= SM_LDS_MAX_N;
+    double* WW = stage_in(lds, a.WW, N, in_lds);
+    double* sig = in_lds ? lds_vecs(lds, N) : a.vec;
+    double* nrm = sig + N;
+    int* ordv = in_lds ? (int*)(nrm + N) : a.ivec;
+    int sw = wg_jacobi(WW, N, N, N, sig, ordv, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         atomicMax(a.sweeps, sw);
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
     }
     for (int e = tid; e < N * a.K; e += SM_THREADS) {
         int k = e % N, j = e / N;
-        a.X[k + (size_t)j * N] = a.WW[k + (size_t)a.ivec[j] * N];
+        a.X[k + (size_t)j * N] = WW[k + (size_t)ordv[j] * N];
     }
     for (int j = tid; j < a.K; j += SM_THREADS) {
-        double lam = sig[a.ivec[j]];
+        double lam = sig[ordv[j]];
         a.Lam[j] = sqrt(lam > 0.0 ? lam : 0.0);
     }
     __syncthreads();
@@ -519,19 +590,31 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_global(ApmosGlobalArgs a) 
 // Host launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_small_det1(const SmallArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_small_det1, dim3(1), dim3(SM_THREADS), 0, st, a);
+    size_t lds = small_lds_bytes(a.n);
+    hipError_t e = hipFuncSetAttribute((const void*)k_small_det1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_small_det1, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_small_det2(const SmallArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_small_det2, dim3(1), dim3(SM_THREADS), 0, st, a);
+    size_t lds = small_lds_bytes(a.n);
+    hipError_t e = hipFuncSetAttribute((const void*)k_small_det2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_small_det2, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_small_chol(const CholArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(SM_THREADS), 0, st, a);
+    size_t lds = small_lds_bytes(a.l);
+    hipError_t e = hipFuncSetAttribute((const void*)k_small_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(256), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_small_rand_final(const RandFinalArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_small_rand_final, dim3(1), dim3(SM_THREADS), 0, st, a);
+    size_t lds = small_lds_bytes(a.l);
+    hipError_t e = hipFuncSetAttribute((const void*)k_small_rand_final, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_small_rand_final, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_scale_rows(double* X, int n, int m, int ldx, const double* d, int r, int times, hipStream_t st) {
@@ -545,11 +628,17 @@ hipError_t launch_make_scale(double* d, const double* s, int r, double ff, hipSt
     return hipGetLastError();
 }
 hipError_t launch_apmos_local(const ApmosLocalArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_apmos_local, dim3(a.P), dim3(SM_THREADS), 0, st, a);
+    size_t lds = small_lds_bytes(a.N);
+    hipError_t e = hipFuncSetAttribute((const void*)k_apmos_local, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_apmos_local, dim3(a.P), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_apmos_global(const ApmosGlobalArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_apmos_global, dim3(1), dim3(SM_THREADS), 0, st, a);
+    size_t lds = small_lds_bytes(a.N);
+    hipError_t e = hipFuncSetAttribute((const void*)k_apmos_global, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_apmos_global, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 
