@@ -131,6 +131,7 @@ def main():
     roof["avg_launch_ms"] = avg_ms
     per_kernel = {k: {"launches": v["launches"], "avg_ms": (v["ms"] / v["launches"]) if v["launches"] else 0.0}
                   for k, v in kern.items() if v["launches"]}
+    per_kernel["jacobi_sweeps_last"] = st["last_sweeps"]
     svd.close()
 
     out = {

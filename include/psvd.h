@@ -114,7 +114,7 @@ int psvd_initialize(psvd_handle** h, int64_t M, int32_t K, double ff, int32_t ov
 /*
  * Ingest one batch A (M x N, device, column-major, leading dimension
  * lda >= M, element type dtype).  With r = 0 this is the initialisation
- * (steps I1-I2 of Algorithm 1: factor A alone); otherwise steps 1-5 on the
+ * (the initialisation of Algorithm 1: factor A alone); otherwise the update on the
  * panel [ff * U diag(s) | A].  Deterministic method: tall-skinny QR of the
  * panel (Cholesky-QR twice, eigen route on breakdown), one-sided Jacobi SVD
  * of R, keep K, U <- Q U~_K.  Randomized method with K + p < r + N: sketch

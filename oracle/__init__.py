@@ -11,8 +11,8 @@ Matrices are numpy float64 arrays of shape (rows, cols) in Fortran
 Functions and the passages they follow:
   philox4x32_10, omega  -- Gaussian test matrix (Sec. 3.3, drawn afresh for
                             every randomized SVD); Philox4x32-10 + Box-Muller.
-  hhqr                  -- Householder thin QR, R_jj >= 0 (Alg. 1, steps I1/1).
-  jacobi_svd            -- one-sided Jacobi SVD (Alg. 1, steps I2/2; Eq. (9)).
+  hhqr                  -- Householder thin QR, R_jj >= 0 (the QR of Algorithm 1).
+  jacobi_svd            -- one-sided Jacobi SVD (the SVD of R in Algorithm 1; Eq. (9)).
   StreamOracle          -- Algorithm 1 per batch, deterministic or randomized
                             (Eqs. (7)-(11), Halko-Martinsson-Tropp power iterations).
   apmos                 -- Algorithm 2 / Eqs. (3)-(6).

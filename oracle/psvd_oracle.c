@@ -20,9 +20,9 @@
  *       randomized SVD).  Counter-based generator: Philox4x32-10 of Salmon,
  *       Moraes, Dror & Shaw (SC'11); normals by Box & Muller (1958).
  *   orc_hhqr         -- thin Householder QR (Golub & Van Loan, Alg. 5.2.1),
- *       the "QR-decomposition" of Algorithm 1 (steps I1 and 1).
+ *       the QR decomposition of Algorithm 1 (initialisation and update).
  *   orc_jacobi_svd   -- one-sided cyclic Jacobi SVD (Hestenes 1958), the
- *       "SVD of R" of Algorithm 1 (steps I2 and 2) and Eq. (9).
+ *       SVD of the R factor in Algorithm 1, and Eq. (9).
  *   orc_stream_update -- one batch of Algorithm 1 (Sec. 3.1): deterministic
  *       (QR of [ff*U*D | A], SVD of R, keep K) or, with a test matrix,
  *       the randomized range finder of Eqs. (7)-(11) applied to the same
@@ -473,7 +473,7 @@ static double* build_panel(int64_t M, int64_t r, double ff, const double* U, int
 /*
  * Deterministic step: Q R = C (Householder), R = Ut S Vt^T (Jacobi),
  * keep r' = min(K, n) leading triplets, U <- Q Ut[:, :r'] after the sign
- * rule on Ut.  (Algorithm 1, steps 1-5; steps I1-I2 when r = 0.)
+ * rule on Ut.  (Algorithm 1: the per-batch update; the initialisation when r = 0.)
  */
 static int step_det(int64_t M, int32_t K, const double* C, int64_t n, double* U, int64_t ldu, double* s,
                     int32_t* r_out, double* smallU_out)

@@ -7,8 +7,8 @@ shape (N, M).  PyTorch only provides device memory and the stream.
 
     svd = StreamingSVD(M, K, ff=0.95, oversampling=10, power_iters=2,
                        randomized=True, precision="mixed", seed=1)
-    svd.initialize(A0)             # Algorithm 1, steps I1-I2
-    svd.incorporate_data(A1)       # Algorithm 1, steps 1-5 (per batch)
+    svd.initialize(A0)             # Algorithm 1, initialisation
+    svd.incorporate_data(A1)       # Algorithm 1, per-batch update
     U, s = svd.modes, svd.singular_values
 """
 import ctypes
@@ -97,7 +97,7 @@ class StreamingSVD:
         return self
 
     def initialize(self, A):
-        """First batch (steps I1-I2 of Algorithm 1); same as incorporate_data on an empty state."""
+        """First batch (the initialisation of Algorithm 1); same as incorporate_data on an empty state."""
         if self.rank != 0:
             raise PsvdError(-9, "initialize() on a non-empty state")
         return self.incorporate_data(A)

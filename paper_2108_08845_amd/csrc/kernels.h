@@ -81,6 +81,8 @@ struct FusedArgs {
     double* partG;           // [wg] 64 x 64 (only when nlb == 1 and G requested)
     int32_t want_g;          // FP32 compute type only
     int32_t vec;             // float4 loads/stores allowed (rows % 4 == 0, lds % 4 == 0, 16-byte bases)
+    float* yout;             // final pass: optional copy of Y = C X (rows x lx, ld ldy)
+    int64_t ldy;
 };
 
 struct FusedReduceArgs {

@@ -382,30 +382,42 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
         constexpr int YT = (TM / 16) * 4;
         for (int yt = w; yt < YT; yt += 8) {
             const int ib = yt >> 2, jb = yt & 3;
-            typename MF::acc accY = typename MF::acc{0, 0, 0, 0};
-            for (int k0 = 0; k0 < np; k0 += KSTEP) {
-                typename MF::frag bv = lds_frag<MF>(&Xs[(jb * 16 + (lane & 15)) * ldX + k0 + (lane >> 4) * KPL]);
-                typename MF::frag av;
-                if constexpr (KPL == 1) av = Cs[(k0 + (lane >> 4)) * ldC + ib * 16 + (lane & 15)];
-                else av = lds_frag<MF>(&Cr[(ib * 16 + (lane & 15)) * ldR + k0 + (lane >> 4) * KPL]);
-                accY = MF::mma(av, bv, accY);
+            // Four interleaved accumulators keep consecutive matrix-core ops independent.
+            typename MF::acc acc4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc4[u] = typename MF::acc{0, 0, 0, 0};
+            for (int k0 = 0; k0 < np; k0 += 4 * KSTEP) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int kk = k0 + u * KSTEP;
+                    if (kk < np) {
+                        typename MF::frag bv =
+                            lds_frag<MF>(&Xs[(jb * 16 + (lane & 15)) * ldX + kk + (lane >> 4) * KPL]);
+                        typename MF::frag av;
+                        if constexpr (KPL == 1) av = Cs[(kk + (lane >> 4)) * ldC + ib * 16 + (lane & 15)];
+                        else av = lds_frag<MF>(&Cr[(ib * 16 + (lane & 15)) * ldR + kk + (lane >> 4) * KPL]);
+                        acc4[u] = MF::mma(av, bv, acc4[u]);
+                    }
+                }
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = ib * 16 + MF::row_of(lane, v);
                 const int col = jb * 16 + (lane & 15);
-                Ys[col * ldY + row] = MF::from_acc(accY[v]);
+                Ys[col * ldY + row] = MF::from_acc((acc4[0][v] + acc4[1][v]) + (acc4[2][v] + acc4[3][v]));
             }
         }
         __syncthreads();
 
-        if constexpr (MODE == 2) {
-            // out[rows, c0 + j] = Y_tile (float4 column segments), j < nx
+        if (MODE == 2 || (MODE == 1 && a.yout != nullptr)) {
+            // Y_tile -> out (lift) or the copy of Y (final pass), float4 column segments, j < lx
+            float* obase = MODE == 2 ? (float*)a.seg.out : a.yout;
+            const int64_t ldo = MODE == 2 ? a.seg.ldo : a.ldy;
             const int64_t row = t * TM + tsub * 4;
             for (int j = tcol; j < FU_LB; j += CPR) {
                 if (c0 + j >= a.lx) continue;
                 f4_t v = *(const f4_t*)&Ys[j * ldY + tsub * 4];
-                float* o = (float*)a.seg.out + (size_t)(c0 + j) * (size_t)a.seg.ldo;
+                float* o = obase + (size_t)(c0 + j) * (size_t)ldo;
                 if (VEC && row + 3 < a.seg.rows) {
                     *(f4_t*)(o + row) = v;
                 } else {
@@ -414,7 +426,8 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
                         if (row + q < a.seg.rows) o[row + q] = v[q];
                 }
             }
-        } else {
+        }
+        if constexpr (MODE != 2) {
             // Phase B: P (np x 64) += C_tile^T Y_tile; wave w owns row blocks w, w+8, ...
 #pragma unroll
             for (int k0 = 0; k0 < TM; k0 += KSTEP) {
@@ -604,16 +617,17 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
 
         // Phase A: Y_tile = C_tile X (X fragments in registers).
         if (a_active) {
-            f4_t accY[JW];
+            // Two interleaved accumulators per column block (independent consecutive ops).
+            f4_t accY[JW][2];
 #pragma unroll
-            for (int c = 0; c < JW; ++c) accY[c] = f4_t{0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < JW; ++c) accY[c][0] = accY[c][1] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 if (ks * 32 < np) {
                     bf8_t av = lds_b128(&Cr[(ib * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4)]);
 #pragma unroll
                     for (int c = 0; c < JW; ++c)
-                        accY[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[c][ks], accY[c], 0, 0, 0);
+                        accY[c][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[c][ks], accY[c][ks & 1], 0, 0, 0);
                 }
             }
 #pragma unroll
@@ -622,7 +636,7 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
                 for (int v = 0; v < 4; ++v) {
                     const int row = ib * 16 + 4 * (lane >> 4) + v;
                     const int col = (jb0 + c) * 16 + (lane & 15);
-                    Ys[col * ldY + row] = f32_to_bf16_rne(accY[c][v]);
+                    Ys[col * ldY + row] = f32_to_bf16_rne(accY[c][0][v] + accY[c][1][v]);
                 }
         }
         __syncthreads();

@@ -309,10 +309,6 @@ static int ensure_workspace(psvd_handle* h, int n) {
     int nlb = ceil_div(std::max(l, 1), 64);
     HIPCHK(h, h->partP.ensure((size_t)256 * nlb * np * 64 * sizeof(float)));
     HIPCHK(h, h->partG.ensure((size_t)256 * 64 * 64 * sizeof(double)));
-    int esz = h->u_dtype == PSVD_F64 ? 8 : 4;
-    // tall temporary: Q1 (M x n) for the deterministic step, Y (M x ell) otherwise
-    int tall_cols = (l > 0 && l < n) ? l : n;
-    HIPCHK(h, h->tall.ensure((size_t)h->M * tall_cols * esz));
     h->nmax = n;
     return PSVD_OK;
 }
@@ -626,6 +622,11 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
     if (n > M) return fail(h, PSVD_E_SHAPE, "panel wider than tall (r + N > M)");
     int rc = ensure_workspace(h, n);
     if (rc) return rc;
+    // tall temporary: Q1 (M x n) for the deterministic step, Y (M x ell) otherwise
+    {
+        const int cols = (h->ell > 0 && h->ell < n) ? h->ell : n;
+        HIPCHK(h, h->tall.ensure((size_t)M * cols * (h->u_dtype == PSVD_F64 ? 8 : 4)));
+    }
     const int prec = h->opt.precision;
     const bool fp64 = prec == PSVD_PREC_FP64;
     const bool randomized = h->ell > 0 && h->ell < n;
@@ -763,6 +764,10 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 fa.partG = h->partG.as<double>();
                 fa.want_g = want_g ? 1 : 0;
                 fa.vec = seg_vec_ok(C, false) ? 1 : 0;
+                if (want_g) {   // keep Y = C X for the lift (U = Y R_Y^-1 U~_K)
+                    fa.yout = h->tall.as<float>();
+                    fa.ldy = M;
+                }
                 int pe = prof_begin(h, bf16 ? PSVD_KC_FUSED_BF16 : PSVD_KC_FUSED_F32);
                 if (sketch) HIPCHK(h, launch_sketch_bf16(fa, st));
                 else HIPCHK(h, launch_fused(bf16, want_g ? 1 : 0, fa, st));
@@ -861,11 +866,13 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
             HIPCHK(h, launch_small_rand_final(rf, st));
             prof_end(h, pes);
         }
-        // T' = X' M2 (n x rk), U_new = C' T'.
-        PanelSeg Xs = small_seg(L.X, n, l, n, L.T, n);
-        rc = nn_product(h, Xs, L.M2, l, rk, true, nullptr, 0, nullptr, 0);
-        if (rc) return rc;
-        rc = lift_product(h, C, L.T, n, rk, fp64, nullptr, 0, 0);
+        // Lift from the kept sketch: U_new = Y M2 with Y = C X (= Q R_Y).
+        PanelSeg Ys = make_seg(M);
+        seg_add(Ys, make_block(h->tall.p, M, tall_dtype, l));
+        Ys.out = h->U[nxt].p;
+        Ys.ldo = h->ldu;
+        Ys.out_dtype = h->u_dtype;
+        rc = lift_product(h, Ys, L.M2, l, rk, fp64, nullptr, 0, 0);
         if (rc) return rc;
     }
     HIPCHK(h, hipEventRecord(h->ev1, st));
@@ -1016,6 +1023,7 @@ int grad_backward(GradCtx& g, const void* A, int64_t lda, double ff, const doubl
     const int nmax = K + (int)g.Nb;
     int rc = ensure_workspace(h, nmax);
     if (rc) return rc;
+    HIPCHK(h, h->tall.ensure((size_t)g.M * nmax * g.esz));
     // work layout
     size_t nn = (size_t)nmax * nmax, nk = (size_t)nmax * K, zz = (size_t)(nmax + K) * nmax;
     const size_t words = 8 * nn + 2 * nk + 2 * zz + (size_t)K * K + 4 * (size_t)nmax + 256;

@@ -27,32 +27,37 @@ __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 // Cholesky, in place on the upper triangle: A = R^T R, R upper.
 // Returns false (uniformly) on a non-positive or non-finite pivot.
 // ---------------------------------------------------------------------------
-__device__ bool wg_chol_upper(double* A, int n, int lda, int* sflag) {
+__device__ __forceinline__ bool wg_chol_upper(double* A, int n, int lda, int* sflag) {
+    // Right-looking, one barrier per column: every thread recomputes
+    // r_kk = sqrt(a_kk) and scales the row-k entries it reads, the thread that
+    // owns (k, j) stores r_kj, and the trailing (i, j) entries are updated in
+    // the same step (a_ij -= a_ki a_kj / a_kk).
     const int tid = threadIdx.x;
     if (tid == 0) *sflag = 0;
     __syncthreads();
     for (int k = 0; k < n; ++k) {
-        if (tid == 0) {
-            double d = A[k + (size_t)k * lda];
-            if (!(d > 0.0) || !finite_d(d)) *sflag = 1;
-            else A[k + (size_t)k * lda] = sqrt(d);
+        const double d = A[k + (size_t)k * lda];
+        if (!(d > 0.0) || !finite_d(d)) {
+            if (tid == 0) *sflag = 1;
+            __syncthreads();
+            return false;
         }
-        __syncthreads();
-        if (*sflag) return false;
-        const double rkk = A[k + (size_t)k * lda];
-        for (int j = k + 1 + tid; j < n; j += blockDim.x) A[k + (size_t)j * lda] /= rkk;
-        __syncthreads();
-        // trailing update of the upper triangle: A[i][j] -= R[k][i] R[k][j], k < i <= j
-        const int m = n - k - 1;
+        const double rkk = sqrt(d);
+        const double inv = 1.0 / rkk;
+        const int m = n - k;            // columns k .. n-1 of row k, and the trailing block
+        // trailing block (k < i <= j) and row k (i == k) in one sweep over (i, j), i, j >= k
         for (int e = tid; e < m * m; e += blockDim.x) {
-            const int i = k + 1 + e % m, j = k + 1 + e / m;
-            if (i <= j) A[i + (size_t)j * lda] -= A[k + (size_t)i * lda] * A[k + (size_t)j * lda];
+            const int i = k + e % m, j = k + e / m;
+            if (i > j) continue;
+            if (i == k) continue;   // row k is written after the barrier (still read here)
+            A[i + (size_t)j * lda] -= A[k + (size_t)i * lda] * A[k + (size_t)j * lda] * (inv * inv);
         }
+        __syncthreads();
+        for (int j = k + tid; j < n; j += blockDim.x) A[k + (size_t)j * lda] = (j == k) ? rkk : A[k + (size_t)j * lda] * inv;
         __syncthreads();
     }
-    // zero the strict lower triangle
     for (int e = tid; e < n * n; e += blockDim.x) {
-        int i = e % n, j = e / n;
+        const int i = e % n, j = e / n;
         if (i > j) A[i + (size_t)j * lda] = 0.0;
     }
     __syncthreads();
@@ -63,7 +68,7 @@ __device__ bool wg_chol_upper(double* A, int n, int lda, int* sflag) {
 // bottom: step i fixes row i of X for every right-hand side in parallel, so no
 // thread ever waits on a value it has just stored.  B == nullptr means B = I
 // (X = R^-1, upper triangular).  X must not alias R or B.
-__device__ void wg_trsm_upper(const double* R, int ldr, int n, const double* B, int ldb, double* X, int ldx,
+__device__ __forceinline__ void wg_trsm_upper(const double* R, int ldr, int n, const double* B, int ldb, double* X, int ldx,
                               int nrhs) {
     const int tid = threadIdx.x;
     for (int i = n - 1; i >= 0; --i) {
@@ -89,7 +94,7 @@ __device__ void wg_trsm_upper(const double* R, int ldr, int n, const double* B, 
 }
 
 // Ri = R^-1 for upper triangular R (n x n).
-__device__ void wg_trinv_upper(const double* R, int n, int ldr, double* Ri, int ldi) {
+__device__ __forceinline__ void wg_trinv_upper(const double* R, int n, int ldr, double* Ri, int ldi) {
     wg_trsm_upper(R, ldr, n, nullptr, 0, Ri, ldi, n);
 }
 
@@ -113,25 +118,31 @@ __device__ void wg_gemm_nn(int m, int n, int k, const double* A, int lda, const 
 // round rotates n/2 disjoint pairs, one pair per wave at a time.
 // Returns the number of sweeps (> max_sweeps: not converged).
 // ---------------------------------------------------------------------------
-__device__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* order, double* nrm, int max_sweeps,
-                         int* sflag) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+__device__ __forceinline__ double q16_sum(double v) {
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+    return v;
+}
+
+__device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* order, double* nrm,
+                                         int max_sweeps, int* sflag) {
+    // One pair per quarter-wave (16 lanes): a round of n/2 disjoint pairs runs
+    // in one pass when blockDim.x / 16 >= n / 2.
+    const int tid = threadIdx.x;
+    const int ql = tid & 15, qw = tid >> 4, nq = blockDim.x >> 4;
     const double tol = (double)m * 0x1p-53;
     const int ne = n + (n & 1);
     int sweep = 0;
     for (;;) {
-        // exact column norms at the start of every sweep
-        for (int j = w; j < n; j += SM_WAVES) {
+        for (int j = qw; j < n; j += nq) {
             const double* z = Z + (size_t)j * ldz;
             double s = 0.0;
-            for (int i = lane; i < m; i += 64) s += z[i] * z[i];
-            s = wave_sum(s);
-            if (lane == 0) nrm[j] = s;
+            for (int i = ql; i < m; i += 16) s += z[i] * z[i];
+            s = q16_sum(s);
+            if (ql == 0) nrm[j] = s;
         }
         if (tid == 0) *sflag = 0;
         __syncthreads();
-        // columns below (m u)^2 of the largest carry only rounding noise: they
-        // are not rotated (they cannot be made more orthogonal).
         double nmax = 0.0;
         for (int j = 0; j < n; ++j) nmax = fmax(nmax, nrm[j]);
         const double negl = nmax * tol * tol;
@@ -140,29 +151,29 @@ __device__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* ord
             break;
         }
         for (int t = 0; t < ne - 1; ++t) {
-            for (int pi = w; pi < ne / 2; pi += SM_WAVES) {
-                int pa = pi, pb = ne - 1 - pi;
-                int ca = pa == 0 ? 0 : 1 + (pa - 1 + t) % (ne - 1);
-                int cb = pb == 0 ? 0 : 1 + (pb - 1 + t) % (ne - 1);
-                int p = ca < cb ? ca : cb, q = ca < cb ? cb : ca;
+            for (int pi = qw; pi < ne / 2; pi += nq) {
+                const int pa = pi, pb = ne - 1 - pi;
+                const int ca = pa == 0 ? 0 : 1 + (pa - 1 + t) % (ne - 1);
+                const int cb = pb == 0 ? 0 : 1 + (pb - 1 + t) % (ne - 1);
+                const int p = ca < cb ? ca : cb, q = ca < cb ? cb : ca;
                 if (q >= n) continue;
                 double* zp = Z + (size_t)p * ldz;
                 double* zq = Z + (size_t)q * ldz;
                 double g = 0.0;
-                for (int i = lane; i < m; i += 64) g += zp[i] * zq[i];
-                g = wave_sum(g);
-                double al = nrm[p], be = nrm[q];
+                for (int i = ql; i < m; i += 16) g += zp[i] * zq[i];
+                g = q16_sum(g);
+                const double al = nrm[p], be = nrm[q];
                 if (!(al > negl) || !(be > negl)) continue;
                 if (fabs(g) <= tol * sqrt(al) * sqrt(be)) continue;
-                double zeta = (be - al) / (2.0 * g);
-                double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-                for (int i = lane; i < m; i += 64) {
-                    double a = zp[i], b = zq[i];
+                const double zeta = (be - al) / (2.0 * g);
+                const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+                for (int i = ql; i < m; i += 16) {
+                    const double a = zp[i], b = zq[i];
                     zp[i] = c * a - s * b;
                     zq[i] = s * a + c * b;
                 }
-                if (lane == 0) {
+                if (ql == 0) {
                     nrm[p] = al - tt * g;
                     nrm[q] = be + tt * g;
                     *sflag = 1;
@@ -171,26 +182,26 @@ __device__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* ord
             __syncthreads();
         }
         ++sweep;
-        int rotated = *sflag;
+        const int rotated = *sflag;
         __syncthreads();
         if (!rotated) break;
     }
     // singular values, normalisation
-    for (int j = w; j < n; j += SM_WAVES) {
+    for (int j = qw; j < n; j += nq) {
         double* z = Z + (size_t)j * ldz;
         double s = 0.0;
-        for (int i = lane; i < m; i += 64) s += z[i] * z[i];
-        s = sqrt(wave_sum(s));
-        for (int i = lane; i < m; i += 64) z[i] = s > 0.0 ? z[i] / s : 0.0;
-        if (lane == 0) sig[j] = s;
+        for (int i = ql; i < m; i += 16) s += z[i] * z[i];
+        s = sqrt(q16_sum(s));
+        for (int i = ql; i < m; i += 16) z[i] = s > 0.0 ? z[i] / s : 0.0;
+        if (ql == 0) sig[j] = s;
     }
     __syncthreads();
     // stable descending order
-    for (int j = tid; j < n; j += SM_THREADS) {
-        double sj = sig[j];
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double sj = sig[j];
         int rank = 0;
         for (int i = 0; i < n; ++i) {
-            double si = sig[i];
+            const double si = sig[i];
             if (si > sj || (si == sj && i < j)) ++rank;
         }
         order[rank] = j;
@@ -201,7 +212,7 @@ __device__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* ord
 
 // Sign rule: column j of X (rows x k) gets its largest-magnitude entry
 // (lowest index on ties) non-negative; flips recorded in flip[j].
-__device__ void wg_sign_rule(double* X, int rows, int k, int ldx, double* flip) {
+__device__ __forceinline__ void wg_sign_rule(double* X, int rows, int k, int ldx, double* flip) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int j = w; j < k; j += SM_WAVES) {
         double* x = X + (size_t)j * ldx;
@@ -268,12 +279,13 @@ __device__ __forceinline__ void stage_out(const double* w, double* g, int n, boo
 
 __device__ __forceinline__ double dscale(const SmallArgs& a, int j) { return j < a.r ? a.d[j] : 1.0; }
 
+template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
     extern __shared__ double lds[];
     __shared__ int sflag;
     __shared__ int nonfinite;
     const int n = a.n, tid = threadIdx.x;
-    const bool in_lds = n <= SM_LDS_MAX_N;
+    constexpr bool in_lds = IN_LDS;
     double* W = in_lds ? lds : a.R1;
     // G <- D G' D, NaN/Inf check
     if (tid == 0) nonfinite = 0;
@@ -342,12 +354,13 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
 // After the second Gram G2 = Q1^T Q1: R2 = chol(G2), R = R2 R1, Jacobi SVD of
 // R -> U~ (left vectors), S; sort, sign rule, keep rk = min(K, n);
 // T = D R^-1 U~_rk.
+template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
     extern __shared__ double lds[];
     __shared__ int sflag;
     if (*a.status & (DEV_FALLBACK | DEV_NONFINITE | DEV_BREAKDOWN)) return;
     const int n = a.n, tid = threadIdx.x;
-    const bool in_lds = n <= SM_LDS_MAX_N;
+    constexpr bool in_lds = IN_LDS;
     double* W = stage_in(lds, a.G2, n, in_lds);
     bool ok = wg_chol_upper(W, n, n, &sflag);
     if (!ok) {
@@ -407,13 +420,14 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
 // R = chol(H) (R overwrites H), Ri = R^-1.  On breakdown a diagonal shift
 // s = 11 (l^2 + l) 2^-53 ||H||_F (shifted Cholesky-QR of Fukaya et al. 2020)
 // is added and the factorisation repeated.
+template <bool IN_LDS>
 __global__ __launch_bounds__(256) void k_small_chol(CholArgs a) {
     extern __shared__ double lds[];
     __shared__ int sflag;
     __shared__ double fro;
     const int l = a.l, tid = threadIdx.x;
     if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
-    const bool in_lds = l <= SM_LDS_MAX_N;
+    constexpr bool in_lds = IN_LDS;
     double* W = in_lds ? lds : a.Ri;   // global fallback works in Ri and keeps H for the retry
     for (int e = tid; e < l * l; e += blockDim.x) W[e] = a.H[e];
     __syncthreads();
@@ -451,12 +465,13 @@ __global__ __launch_bounds__(256) void k_small_chol(CholArgs a) {
 
 // R_P = chol(H2) R1 (QR factor of P); R_b = R_P R_Y^-1; the left singular
 // vectors of B = R_Y^-T P^T are those of R_b^T: one-sided Jacobi on R_b^T.
+template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a) {
     extern __shared__ double lds[];
     __shared__ int sflag;
     if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
     const int l = a.l, tid = threadIdx.x;
-    const bool in_lds = l <= SM_LDS_MAX_N;
+    constexpr bool in_lds = IN_LDS;
     double* W = stage_in(lds, a.H2, l, in_lds);
     bool ok = wg_chol_upper(W, l, l, &sflag);          // R2
     if (!ok) {
@@ -529,11 +544,12 @@ __global__ void k_make_scale(double* d, const double* s, int r, double ff) {
 
 // One work-group per partition: eigen-decomposition of G_i by one-sided
 // Jacobi; W_i = V_i[:, :r] diag(sqrt(lambda_i[:r])) stored transposed.
+template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
     extern __shared__ double lds[];
     __shared__ int sflag;
     const int i = blockIdx.x, N = a.N, tid = threadIdx.x;
-    const bool in_lds = N <= SM_LDS_MAX_N;
+    constexpr bool in_lds = IN_LDS;
     double* G = stage_in(lds, a.G + (size_t)i * N * N, N, in_lds);
     double* sig = in_lds ? lds_vecs(lds, N) : a.vec + (size_t)i * 2 * N;
     double* nrm = sig + N;
@@ -554,11 +570,12 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
 
 // W W^T = X Lambda^2 X^T by one-sided Jacobi; keep K; sign rule on X~;
 // T = X~ diag(1 / Lambda~) with the guard Lambda~_K > N 2^-53 Lambda~_1.
+template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_apmos_global(ApmosGlobalArgs a) {
     extern __shared__ double lds[];
     __shared__ int sflag;
     const int N = a.N, tid = threadIdx.x;
-    const bool in_lds = N <= SM_LDS_MAX_N;
+    constexpr bool in_lds = IN_LDS;
     double* WW = stage_in(lds, a.WW, N, in_lds);
     double* sig = in_lds ? lds_vecs(lds, N) : a.vec;
     double* nrm = sig + N;
@@ -591,30 +608,42 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_global(ApmosGlobalArgs a) 
 // ---------------------------------------------------------------------------
 hipError_t launch_small_det1(const SmallArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.n);
-    hipError_t e = hipFuncSetAttribute((const void*)k_small_det1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool in_lds = (a.n) <= SM_LDS_MAX_N;
+    const void* fn = in_lds ? (const void*)k_small_det1<true> : (const void*)k_small_det1<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_small_det1, dim3(1), dim3(SM_THREADS), lds, st, a);
+    if (in_lds) hipLaunchKernelGGL(k_small_det1<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
+    else hipLaunchKernelGGL(k_small_det1<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_small_det2(const SmallArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.n);
-    hipError_t e = hipFuncSetAttribute((const void*)k_small_det2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool in_lds = (a.n) <= SM_LDS_MAX_N;
+    const void* fn = in_lds ? (const void*)k_small_det2<true> : (const void*)k_small_det2<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_small_det2, dim3(1), dim3(SM_THREADS), lds, st, a);
+    if (in_lds) hipLaunchKernelGGL(k_small_det2<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
+    else hipLaunchKernelGGL(k_small_det2<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_small_chol(const CholArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.l);
-    hipError_t e = hipFuncSetAttribute((const void*)k_small_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool in_lds = (a.l) <= SM_LDS_MAX_N;
+    const void* fn = in_lds ? (const void*)k_small_chol<true> : (const void*)k_small_chol<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(256), lds, st, a);
+    if (in_lds) hipLaunchKernelGGL(k_small_chol<true>, dim3(1), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL(k_small_chol<false>, dim3(1), dim3(256), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_small_rand_final(const RandFinalArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.l);
-    hipError_t e = hipFuncSetAttribute((const void*)k_small_rand_final, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool in_lds = (a.l) <= SM_LDS_MAX_N;
+    const void* fn = in_lds ? (const void*)k_small_rand_final<true> : (const void*)k_small_rand_final<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_small_rand_final, dim3(1), dim3(SM_THREADS), lds, st, a);
+    if (in_lds) hipLaunchKernelGGL(k_small_rand_final<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
+    else hipLaunchKernelGGL(k_small_rand_final<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_scale_rows(double* X, int n, int m, int ldx, const double* d, int r, int times, hipStream_t st) {
@@ -629,16 +658,22 @@ hipError_t launch_make_scale(double* d, const double* s, int r, double ff, hipSt
 }
 hipError_t launch_apmos_local(const ApmosLocalArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.N);
-    hipError_t e = hipFuncSetAttribute((const void*)k_apmos_local, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool in_lds = (a.N) <= SM_LDS_MAX_N;
+    const void* fn = in_lds ? (const void*)k_apmos_local<true> : (const void*)k_apmos_local<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_apmos_local, dim3(a.P), dim3(SM_THREADS), lds, st, a);
+    if (in_lds) hipLaunchKernelGGL(k_apmos_local<true>, dim3(a.P), dim3(SM_THREADS), lds, st, a);
+    else hipLaunchKernelGGL(k_apmos_local<false>, dim3(a.P), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_apmos_global(const ApmosGlobalArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.N);
-    hipError_t e = hipFuncSetAttribute((const void*)k_apmos_global, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool in_lds = (a.N) <= SM_LDS_MAX_N;
+    const void* fn = in_lds ? (const void*)k_apmos_global<true> : (const void*)k_apmos_global<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_apmos_global, dim3(1), dim3(SM_THREADS), lds, st, a);
+    if (in_lds) hipLaunchKernelGGL(k_apmos_global<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
+    else hipLaunchKernelGGL(k_apmos_global<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 
