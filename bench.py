@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
 
 
@@ -44,7 +45,28 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-rows", type=int, default=1 << 19, help="rows of the oracle sample")
     ap.add_argument("--M", type=int, default=1 << 20)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (calibration of the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(reps=4):
+    """A plain copy of known size: reads and writes COPY_BYTES per launch.  Under
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE it gives the factor between the
+    counters and HBM bytes."""
+    n = COPY_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": reps,
+                      "ms_per_copy": ms, "GB_per_s_read_plus_write": 2 * COPY_BYTES / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def run_stream(P, w, batches, precision, steps, warmup, profile):
@@ -90,6 +112,9 @@ def cpu_baseline(w, rows):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -126,7 +151,11 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": panel_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    # HBM bytes per launch from the committed counter record of this kernel, if
+    # its source has not changed since the counters were taken (else null).
+    from paper_2108_08845_amd import pmc_traffic
+    rec = pmc_traffic.load_current(os.path.join(ROOT, "profiles"), dom, w.name)
+    roof["traffic"] = rec["traffic_bytes_per_launch"] if rec else None
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms
     per_kernel = {k: {"launches": v["launches"], "avg_ms": (v["ms"] / v["launches"]) if v["launches"] else 0.0}

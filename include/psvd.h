@@ -23,6 +23,7 @@
 #ifndef PSVD_H
 #define PSVD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -82,8 +83,9 @@ typedef struct psvd_options {
     void* stream;           /* hipStream_t; NULL = default stream                */
     int32_t max_sweeps;     /* Jacobi sweep limit (default 60)                   */
     int32_t flags;          /* PSVD_OPT_* bits                                   */
-    int32_t tile_rows;      /* 0 = autotuned / default row-tile height           */
-    int32_t reserved;
+    int32_t tile_rows;      /* fused passes: row-tile height 16/32/64, 0 = default */
+    int32_t wg_per_cu;      /* fused passes: work-groups per compute unit 1..4,
+                               0 = default (1); see the autotuner               */
 } psvd_options;
 
 typedef struct psvd_stats_t {
@@ -166,7 +168,43 @@ int psvd_stats(const psvd_handle* h, psvd_stats_t* out);
 /* Zero the counters of psvd_stats (not the state). */
 int psvd_reset_stats(psvd_handle* h);
 
-/* Text of the last error on this handle ("" if none).  Owned by the handle. */
+/*
+ * Checkpoint of the streaming state (Algorithm 1 carries U, s and the batch
+ * count from one update to the next; nothing else is needed to resume).
+ * psvd_save_state writes a self-describing host buffer: a header with the
+ * configuration (M, K, ff, p, q, method, precision, seed), the rank r and
+ * the batch count, then K FP64 singular values (zero beyond r) and the r
+ * columns of U (M values each, in the state's element type).  buf == NULL
+ * only reports the size in *size.  Synchronises the stream.
+ * Errors: PSVD_E_INVAL (cap smaller than the state), PSVD_E_DEVICE.
+ *
+ * psvd_load_state restores such a buffer into a handle created with the same
+ * configuration; the next update then draws the Gaussian test matrix of the
+ * restored batch count, so a resumed stream reproduces the uninterrupted one
+ * bit for bit.  Errors: PSVD_E_INVAL (not a state buffer, truncated),
+ * PSVD_E_STATE (different configuration); the state is unchanged on error.
+ */
+int psvd_save_state(const psvd_handle* h, void* buf, size_t cap, size_t* size);
+int psvd_load_state(psvd_handle* h, const void* buf, size_t size);
+
+/*
+ * One-shot randomized SVD of one matrix (Sec. 3.3, Eqs. 7-11): the sketch
+ * Y = A Omega with an (N x (K+p)) Gaussian test matrix drawn from (seed,
+ * batch 0), q power iterations, B = Q^T A, B = U~ S V~^T, U = Q U~[:, :K],
+ * V = V~[:, :K], computed as one update of an empty randomized stream (the
+ * exact SVD when K + p >= N).  A: device, M x N, leading dimension lda,
+ * a_dtype (PSVD_F64 data needs PSVD_PREC_FP64).  Outputs (each may be NULL):
+ * U device M x rank (ldu, out_dtype); V device N x rank (ldv, out_dtype),
+ * V = A^T U diag(1/s); s host, K values; *rank = min(K, N).  Synchronises.
+ * Errors: PSVD_E_INVAL, PSVD_E_SHAPE, PSVD_E_DTYPE, PSVD_E_NOMEM,
+ * PSVD_E_NONFINITE, PSVD_E_DEVICE; the text is psvd_last_error(NULL).
+ */
+int psvd_rsvd(const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype, int32_t K, int32_t oversampling,
+              int32_t power_iters, uint64_t seed, int32_t precision, void* U, int64_t ldu, void* V, int64_t ldv,
+              int32_t out_dtype, double* s, int32_t* rank, void* stream);
+
+/* Text of the last error on this handle ("" if none).  Owned by the handle.
+ * With h == NULL: the last error of a psvd_rsvd call on this host thread. */
 const char* psvd_last_error(const psvd_handle* h);
 
 /* Static name of a status code. */

@@ -19,7 +19,8 @@ import torch
 from . import _lib
 from ._lib import PsvdError
 
-__all__ = ["StreamingSVD", "apmos_batched", "PsvdError", "stream_backward", "loss_and_grad", "StreamingSVDFunction"]
+__all__ = ["StreamingSVD", "apmos_batched", "PsvdError", "stream_backward", "loss_and_grad", "StreamingSVDFunction",
+           "rsvd"]
 
 _PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32, "mixed": _lib.PREC_MIXED}
 
@@ -55,7 +56,8 @@ class StreamingSVD:
     """
 
     def __init__(self, M, K, ff=1.0, oversampling=0, power_iters=0, randomized=False, precision="fp64",
-                 seed=0, stream=None, async_updates=False, max_sweeps=60, fallback=True, profile=False):
+                 seed=0, stream=None, async_updates=False, max_sweeps=60, fallback=True, profile=False,
+                 tile_rows=0, wg_per_cu=0):
         self._libh = _lib.load()
         opt = _lib.Options()
         self._libh.psvd_default_options(ctypes.byref(opt))
@@ -65,6 +67,8 @@ class StreamingSVD:
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         opt.stream = _stream_ptr(self._stream).value
         opt.max_sweeps = int(max_sweeps)
+        opt.tile_rows = int(tile_rows)
+        opt.wg_per_cu = int(wg_per_cu)
         opt.flags = ((_lib.OPT_ASYNC if async_updates else 0) | (0 if fallback else _lib.OPT_NO_FALLBACK)
                      | (_lib.OPT_PROFILE if profile else 0))
         h = ctypes.c_void_p()
@@ -155,6 +159,40 @@ class StreamingSVD:
     @property
     def last_error(self):
         return self._libh.psvd_last_error(self._h).decode()
+
+    def save_state(self):
+        """Checkpoint (bytes) of U, s, the rank and the batch count; see load_state."""
+        size = ctypes.c_size_t()
+        _lib.check(self._libh.psvd_save_state(self._h, None, 0, ctypes.byref(size)), self._h, "save_state")
+        buf = ctypes.create_string_buffer(size.value)
+        _lib.check(self._libh.psvd_save_state(self._h, buf, size.value, ctypes.byref(size)), self._h, "save_state")
+        return buf.raw
+
+    def load_state(self, state):
+        """Restore a checkpoint taken from a stream with the same configuration."""
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        _lib.check(self._libh.psvd_load_state(self._h, buf, len(state)), self._h, "load_state")
+        return self
+
+
+def rsvd(A, K, oversampling=10, power_iters=2, seed=0, precision="fp32", out_dtype=None, stream=None):
+    """One-shot randomized SVD of an M x N CUDA matrix (Eqs. (7)-(11)) -> (U (M x r), s (r,), V (N x r))."""
+    lib = _lib.load()
+    ptr, M, N, lda, code, keep = _as_colmajor(A)
+    dt = out_dtype or (torch.float64 if precision == "fp64" else torch.float32)
+    ocode = _lib.PSVD_F64 if dt == torch.float64 else _lib.PSVD_F32
+    r = min(int(K), N)
+    U = torch.empty((r, M), dtype=dt, device=A.device)
+    V = torch.empty((r, N), dtype=dt, device=A.device)
+    s = np.zeros(max(int(K), 1), dtype=np.float64)
+    rank = ctypes.c_int32()
+    rc = lib.psvd_rsvd(ptr, M, N, lda, code, int(K), int(oversampling), int(power_iters), ctypes.c_uint64(int(seed)),
+                       _PREC[precision], ctypes.c_void_p(U.data_ptr()), M, ctypes.c_void_p(V.data_ptr()), N, ocode,
+                       s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(rank), _stream_ptr(stream))
+    if rc != _lib.PSVD_OK:
+        raise PsvdError(rc, "rsvd " + lib.psvd_last_error(None).decode())
+    r = int(rank.value)
+    return U[:r].t(), s[:r].copy(), V[:r].t()
 
 
 def apmos_batched(parts, r, K, stream=None):

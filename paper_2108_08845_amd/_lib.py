@@ -15,6 +15,7 @@ STATUS = {
     0: "PSVD_OK", -1: "PSVD_E_INVAL", -2: "PSVD_E_SHAPE", -3: "PSVD_E_DTYPE", -4: "PSVD_E_NOMEM",
     -5: "PSVD_E_NONFINITE", -6: "PSVD_E_NOCONV", -7: "PSVD_E_BREAKDOWN", -8: "PSVD_E_DEVICE", -9: "PSVD_E_STATE",
 }
+globals().update({name: code for code, name in STATUS.items()})   # PSVD_E_INVAL = -1, ...
 PSVD_F32, PSVD_F64 = 1, 2
 DETERMINISTIC, RANDOMIZED = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
@@ -25,6 +26,7 @@ EXPORTS = [
     "psvd_default_options", "psvd_initialize", "psvd_incorporate_data", "psvd_rank", "psvd_singular_values",
     "psvd_modes", "psvd_modes_ptr", "psvd_get_omega", "psvd_stats", "psvd_last_error", "psvd_status_string",
     "psvd_finalize", "psvd_reset_stats", "psvd_apmos_batched", "psvd_stream_backward", "psvd_loss_grad",
+    "psvd_save_state", "psvd_load_state", "psvd_rsvd",
 ]
 
 
@@ -32,7 +34,7 @@ class Options(ctypes.Structure):
     _fields_ = [
         ("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_void_p), ("max_sweeps", ctypes.c_int32), ("flags", ctypes.c_int32),
-        ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
     ]
 
 
@@ -84,6 +86,10 @@ def load():
                                        i32, i32, ctypes.POINTER(vp), ctypes.POINTER(i64), dp, dp, vp]
     lib.psvd_stream_backward.argtypes = [vp, i64, i64, i32, i32, i64, i32, ctypes.c_double, vp, dp, vp, vp]
     lib.psvd_loss_grad.argtypes = [vp, i64, i64, i32, i32, i64, i32, ctypes.c_double, dp, dp, vp, vp]
+    lib.psvd_save_state.argtypes = [H, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    lib.psvd_load_state.argtypes = [H, vp, ctypes.c_size_t]
+    lib.psvd_rsvd.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, ctypes.c_uint64, i32, vp, i64, vp, i64, i32, dp,
+                              ctypes.POINTER(i32), vp]
     _lib = lib
     return lib
 

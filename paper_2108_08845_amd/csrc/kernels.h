@@ -7,6 +7,7 @@ namespace psvd {
 
 constexpr int TN_OB = 64;   // output block edge of k_tn
 constexpr int FU_LB = 64;   // sketch columns per work-group of k_fused
+constexpr int FU_MAX_WG = 1024;   // work-groups per column block of a fused pass (4 per CU)
 
 // Output block y of a blocked product -> (block row, block col).
 __host__ __device__ inline void block_coords(int y, int mbl, int sym, int* bi, int* bj) {
@@ -71,10 +72,10 @@ struct FusedArgs {
     PanelSeg seg;            // panel (FP32 blocks)
     const double* X;         // n x lx, ld ldx (logical operand, already scaled)
     int64_t ldx;
-    int32_t n, np;           // panel columns, padded to 16
+    int32_t n, np;           // panel columns; np = the kernel's padded width (FusedPlan)
     int32_t lx;              // columns of X
     int32_t nlb;             // column blocks (ceil(lx / 64))
-    int32_t tm;              // rows per tile (16 or 32)
+    int32_t tm;              // rows per tile (FusedPlan)
     int32_t nwg;             // work-groups per column block
     int64_t tiles;           // ceil(rows / tm)
     float* partP;            // [wg][lb] np x 64 column-major
@@ -119,27 +120,36 @@ struct SmallArgs {
     int32_t* sweeps;      // last Jacobi sweep count
 };
 
-struct CholArgs {
-    double* H;          // l x l input (overwritten by R)
-    double* Ri;         // l x l output R^-1
-    int32_t l;
+struct OrthArgs {
+    int32_t n, l;
+    const double* P;      // n x l (ld n)
+    double* G;            // l x l scratch: P^T P (kept for the shifted retry)
+    double* R;            // l x l scratch (used when the factors do not fit in LDS)
+    double* Ri;           // l x l scratch (same)
+    double* vec;          // 4 l scratch (same)
+    double* X;            // n x l out (ld n): D P R^-1
+    const double* d;      // row scale d[i], i < r
+    int32_t r;
     int32_t* status;
-    int32_t flag_bit;   // status bit on breakdown
+    int32_t flag_bit;     // status bit set on a shifted retry
 };
 
 struct RandFinalArgs {
-    int32_t l, K;
+    int32_t n, l, K;
     int32_t max_sweeps;
-    const double* RY;     // l x l
-    const double* RYi;    // l x l
-    const double* R1;     // l x l  first Cholesky factor of P^T P
-    double* H2;           // l x l  second Gram (overwritten)
-    double* Z;            // l x l work
+    const double* P;      // n x l (ld n): C^T Y
+    double* P1;           // n x l scratch: P R1^-1
+    const double* GY;     // l x l: Y^T Y
+    double* RY;           // l x l out: chol(Y^T Y)
+    double* RYi;          // l x l out: R_Y^-1
+    double* G1;           // l x l scratch: P^T P
+    double* R1;           // l x l scratch: chol(P^T P)
+    double* W;            // l x l scratch (used when the factors do not fit in LDS)
+    double* V;            // l x l scratch (same)
+    double* vec;          // 4 l scratch (same)
     double* M2;           // l x K out: R_Y^-1 U~_K
     double* s_out;        // K
     double* small_u;      // l x K
-    double* vec;          // 2l
-    int32_t* ivec;        // l
     int32_t* status;
     int32_t* sweeps;
 };
@@ -192,16 +202,25 @@ hipError_t launch_grad_sbar(const double* G, int r, const double* s_prev, double
 hipError_t launch_tn(bool fp64, const TnArgs& a, int nitems, hipStream_t st);
 hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st);
 hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st);
-bool fused_fits(bool bf16, int tm, int np);
-int fused_pick_tm(bool bf16, int np);
-int sketch_pick_tm(int np);
+// Compiled configuration of a fused pass: tile height, padded panel width
+// (the layout of the partial sums) and dynamic LDS bytes.
+struct FusedPlan {
+    int tm;
+    int np;
+    size_t lds;
+};
+// BF16 power pass (k_sketch_bf16) / FP32 passes (k_fused) for an n-column
+// panel; tile_rows = 0 picks the default height.  false: no compiled kernel.
+bool sketch_plan(int n, int tile_rows, FusedPlan* p);
+bool fused_plan(int n, int tile_rows, FusedPlan* p);
 hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st);
-hipError_t launch_fused(bool bf16, int mode, const FusedArgs& a, hipStream_t st);
+hipError_t launch_fused(int mode, const FusedArgs& a, hipStream_t st);   // FP32: 0 power, 1 final, 2 lift
 hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st);
 
 hipError_t launch_small_det1(const SmallArgs& a, hipStream_t st);
 hipError_t launch_small_det2(const SmallArgs& a, hipStream_t st);
-hipError_t launch_small_chol(const CholArgs& a, hipStream_t st);
+hipError_t launch_small_orth(const OrthArgs& a, hipStream_t st);
+hipError_t launch_status_fold(int32_t* st, hipStream_t stream);
 hipError_t launch_small_rand_final(const RandFinalArgs& a, hipStream_t st);
 hipError_t launch_scale_rows(double* X, int n, int m, int ldx, const double* d, int r, int times, hipStream_t st);
 hipError_t launch_make_scale(double* d, const double* s, int r, double ff, hipStream_t st);

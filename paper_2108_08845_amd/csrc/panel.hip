@@ -24,18 +24,23 @@ struct ColRef {
 };
 
 __device__ __forceinline__ ColRef col_ref(const PanelSeg& s, int c) {
-    ColRef r{nullptr, PSVD_F32};
+    // Compile-time block indices only: no run-time indexing of the block array.
+    uintptr_t p = 0;
+    int32_t dt = PSVD_F32;
     int cc = c;
-    for (int b = 0; b < s.nblk; ++b) {
+#pragma unroll
+    for (int b = 0; b < kMaxBlocks; ++b) {
         const PanelBlock& B = s.blk[b];
-        if (cc < B.ncols) {
-            int esz = B.dtype == PSVD_F64 ? 8 : 4;
-            r.base = (const char*)B.ptr + (size_t)cc * (size_t)B.ld * esz;
-            r.dtype = B.dtype;
-            return r;
-        }
+        const bool here = b < s.nblk && cc >= 0 && cc < B.ncols;
+        const int64_t esz = B.dtype == PSVD_F64 ? 8 : 4;
+        const uintptr_t q = (uintptr_t)B.ptr + (uintptr_t)((int64_t)cc * B.ld * esz);
+        p = here ? q : p;
+        dt = here ? B.dtype : dt;
         cc -= B.ncols;
     }
+    ColRef r;
+    r.base = (const char*)p;
+    r.dtype = dt;
     return r;
 }
 
@@ -57,7 +62,7 @@ __device__ __forceinline__ double ld_col(const ColRef& r, int64_t i) {
 // k_tn: partial[item][ob] = L[rows, lcols]^T R[rows, rcols], 64 x 64 blocks.
 // grid.x = work items, grid.y = output blocks (list in obl/obr).
 // ----------------------------------------------------------------------------
-constexpr int TN_TM = 64;
+constexpr int TN_TM = 64;   // == wave size: one column per wave and load slot
 constexpr int TN_PAD = 1;
 
 
@@ -68,7 +73,8 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     if (a.skip && (*a.skip & a.skip_mask)) return;
     __shared__ E Ls[TN_OB * (TN_TM + TN_PAD)];
     __shared__ E Rs[TN_OB * (TN_TM + TN_PAD)];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const WorkItem it = get_item(a.items, a.chunk, a.lseg.rows);
     const PanelSeg& L = a.lsegs ? a.lsegs[it.seg] : a.lseg;
     const PanelSeg& R = a.rsegs ? a.rsegs[it.seg] : a.rseg;
@@ -88,8 +94,7 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     auto fetch = [&](int64_t r0) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            int idx = e * 256 + tid;
-            int c = idx / TN_TM, rr = idx % TN_TM;
+            const int c = e * 4 + w, rr = lane;   // TN_TM == 64: wave-uniform column
             int64_t row = r0 + rr;
             double vl = 0.0, vr = 0.0;
             if (row < it.row1) {
@@ -105,8 +110,7 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            int idx = e * 256 + tid;
-            int c = idx / TN_TM, rr = idx % TN_TM;
+            const int c = e * 4 + w, rr = lane;   // TN_TM == 64: wave-uniform column
             Ls[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pl[e]);
             Rs[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pr[e]);
         }
@@ -177,7 +181,8 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
     __shared__ E Cs[NN_KC * (NN_TM + 1)];
     __shared__ E Xs[NN_OB * (NN_KC + 1)];
     __shared__ double Os[NN_OB * (NN_TM + 1)];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const WorkItem it = get_item(a.items, a.chunk, a.seg.rows);
     const PanelSeg& S = a.segs ? a.segs[it.seg] : a.seg;
     const int oc0 = blockIdx.y * NN_OB;
@@ -190,8 +195,7 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
             // C chunk: 32 columns x 64 rows (8 per thread)
 #pragma unroll
             for (int e = 0; e < NN_KC * NN_TM / 256; ++e) {
-                int idx = e * 256 + tid;
-                int c = idx / NN_TM, rr = idx % NN_TM;
+                const int c = e * 4 + w, rr = lane;   // NN_TM == 64: wave-uniform column
                 int64_t row = r0 + rr;
                 double v = 0.0;
                 if (row < it.row1 && k0 + c < a.n) v = ld_col(col_ref(S, k0 + c), row);
@@ -256,98 +260,120 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
 // ----------------------------------------------------------------------------
 
 
-template <class MF>
-__device__ __forceinline__ typename MF::frag lds_frag(const typename MF::elem* p) {
-    if constexpr (MF::KPL == 1) {
-        return *p;
-    } else {
-        uint64_t u = *(const uint64_t*)p;  // 4 bf16, 8-byte aligned by construction
-        return __builtin_bit_cast(s4_t, u);
-    }
-}
-
-// Column base pointer (FP32 panel) of column c.
+// Column base pointer (FP32 panel) of column c.  The block array is indexed
+// with compile-time indices only, so a panel passed by value stays in scalar
+// registers and the lookup costs a few selects (no memory access).
 __device__ __forceinline__ const float* fcol(const PanelSeg& s, int c) {
+    uintptr_t p = 0;
     int cc = c;
-    for (int b = 0; b < s.nblk; ++b) {
-        if (cc < s.blk[b].ncols) return (const float*)s.blk[b].ptr + (size_t)cc * (size_t)s.blk[b].ld;
+#pragma unroll
+    for (int b = 0; b < kMaxBlocks; ++b) {
+        const bool here = b < s.nblk && cc >= 0 && cc < s.blk[b].ncols;
+        const uintptr_t q = (uintptr_t)s.blk[b].ptr + (uintptr_t)((int64_t)cc * s.blk[b].ld * 4);
+        p = here ? q : p;
         cc -= s.blk[b].ncols;
     }
-    return nullptr;
+    return (const float*)p;
 }
 
-// Work-group of 512 threads (8 waves).  Tile = TM rows x np columns of the
-// panel.  Each thread moves float4 column segments: TPC = TM / 4 threads per
-// column, CPR = 512 / TPC columns per round.
-//   MODE 0: P += C^T (C X)             (power pass)
-//   MODE 1: P and G = (C X)^T (C X)    (final pass; FP32 only)
-//   MODE 2: out = C X                  (lift; FP32 only)
-template <class CT, int TM, int NRB, bool VEC, int MODE>
-__global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
-    using MF = Mfma<CT>;
-    using E = typename MF::elem;
-    constexpr int NT = 512;
-    constexpr int KPL = MF::KPL;
-    constexpr int KSTEP = MF::KSTEP;
-    constexpr bool ROWCOPY = (KPL > 1);
-    constexpr int TPC = TM / 4;
-    constexpr int CPR = NT / TPC;
-    constexpr int NPMAX = NRB * 8 * 16;
-    constexpr int RMAX = (NPMAX + CPR - 1) / CPR;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int np = a.np;
-    const int ldX = np + 4;
-    const int ldC = TM + 4;
-    const int ldR = np + 4;
-    const int ldY = TM + 4;
-    E* Xs = (E*)smem;
-    E* Cs = Xs + (size_t)FU_LB * ldX;
-    E* Cr = Cs + (size_t)np * ldC;
-    E* Ys = Cr + (ROWCOPY ? (size_t)TM * ldR : 0);
+// X (FP64, column-major) element (k, j), 0 outside n x lx; the load is
+// unconditional (clamped index) so consecutive loads are not serialised.
+__device__ __forceinline__ double x_elem(const FusedArgs& a, int k, int j) {
+    const int kk = k < a.n ? k : a.n - 1;
+    const int jj = j < a.lx ? j : a.lx - 1;
+    const double v = a.X[kk + (int64_t)jj * a.ldx];
+    return (k < a.n && j < a.lx) ? v : 0.0;
+}
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+// Work-group -> (row work-group wg, column block lb).  Consecutive hardware
+// slots of one XCD (block ids b, b + 8, ...) take the column blocks of the
+// same rows, so a row tile read by several blocks stays in that XCD's L2.
+struct FusedCoords {
+    int wg, lb;
+};
+__device__ __forceinline__ FusedCoords fused_coords(const FusedArgs& a) {
     const int b = blockIdx.x;
     const int xcd = b & 7, local = b >> 3;
-    const int lb = local % a.nlb;
-    const int wg = (local / a.nlb) * 8 + xcd;
-    if (wg >= a.nwg) return;
+    FusedCoords r;
+    r.lb = local % a.nlb;
+    r.wg = (local / a.nlb) * 8 + xcd;
+    return r;
+}
+
+// ----------------------------------------------------------------------------
+// k_fused: FP32 passes on the FP32 matrix cores (16x16x4), one read of C.
+// Work-group of 512 threads (8 waves); tile = TM rows x NP columns, NP a
+// multiple of 64 (columns n .. NP-1 are zero).  Each thread moves float4
+// column segments: TPC = TM / 4 threads per column, CPR = 512 / TPC columns
+// per round; the next tile is prefetched into registers during the matrix
+// work of the current one.
+//   MODE 0: P += C^T (C X)             (power pass, FP32 precision)
+//   MODE 1: P and G = (C X)^T (C X)    (final pass; Y optionally kept)
+//   MODE 2: out = C X                  (lift)
+// ----------------------------------------------------------------------------
+template <int TM, int NP, int MODE>
+__global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
+    constexpr int NT = 512;
+    constexpr int TPC = TM / 4;
+    constexpr int CPR = NT / TPC;
+    constexpr int RMAX = (NP + CPR - 1) / CPR;
+    constexpr int NRBLK = NP / 16;
+    constexpr int QB = (NRBLK + 7) / 8;
+    constexpr int ldX = NP + 4, ldC = TM + 4, ldY = TM + 4;
+    static_assert(NP % 64 == 0, "panel width padded to 64");
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* Xs = (float*)smem;              // X^T: row j = column j of X (64 x NP)
+    float* Cs = Xs + FU_LB * ldX;          // tile, column-major (NP x TM)
+    float* Ys = Cs + NP * ldC;             // Y tile, column-major (64 x TM)
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const FusedCoords fc = fused_coords(a);
+    if (fc.wg >= a.nwg) return;
+    const int wg = fc.wg, lb = fc.lb;
     const int c0 = lb * FU_LB;
 
-    for (int idx = tid; idx < FU_LB * np; idx += NT) {
-        int k = idx % np, j = idx / np;
-        double v = 0.0;
-        if (k < a.n && c0 + j < a.lx) v = a.X[k + (int64_t)(c0 + j) * a.ldx];
-        Xs[j * ldX + k] = MF::from_double(v);
+#pragma unroll 8
+    for (int idx = tid; idx < FU_LB * NP; idx += NT) {
+        const int k = idx % NP, j = idx / NP;
+        Xs[j * ldX + k] = (float)x_elem(a, k, c0 + j);
     }
 
-    const int nrb = np / 16;
-    typename MF::acc accP[MODE == 2 ? 1 : NRB * 4];
+    f4_t accP[MODE == 2 ? 1 : QB * 4];
 #pragma unroll
-    for (int t = 0; t < (MODE == 2 ? 1 : NRB * 4); ++t) accP[t] = typename MF::acc{0, 0, 0, 0};
+    for (int t = 0; t < (MODE == 2 ? 1 : QB * 4); ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
     d4_t accG[2];
     accG[0] = d4_t{0, 0, 0, 0};
     accG[1] = d4_t{0, 0, 0, 0};
 
-    const int rounds = (np + CPR - 1) / CPR;
+    // Per-thread column pointers (columns >= n point at column n - 1 and are zeroed).
     const int tsub = tid % TPC, tcol = tid / TPC;
+    const float* cp[RMAX];
+    bool cv[RMAX];
+#pragma unroll
+    for (int rr = 0; rr < RMAX; ++rr) {
+        const int c = rr * CPR + tcol;
+        cv[rr] = c < a.n;
+        cp[rr] = fcol(a.seg, c < a.n ? c : a.n - 1);
+    }
+    const int64_t rows = a.seg.rows;
     f4_t pf[RMAX];
     auto fetch = [&](int64_t t) {
         const int64_t row = t * TM + tsub * 4;
+        const bool full = a.vec && (t + 1) * TM <= rows;   // uniform
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
-            f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
-            const int c = rr * CPR + tcol;
-            if (rr < rounds && c < a.n) {
-                const float* p = fcol(a.seg, c);
-                if (VEC && row + 3 < a.seg.rows) {
-                    v = *(const f4_t*)(p + row);
+            if (rr * CPR + tcol < NP) {                      // uniform per wave
+                f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
+                if (full) {
+                    v = *(const f4_t*)(cp[rr] + row);
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (row + q < a.seg.rows) v[q] = p[row + q];
+                        if (row + q < rows) v[q] = cp[rr][row + q];
                 }
+                pf[rr] = cv[rr] ? v : f4_t{0.f, 0.f, 0.f, 0.f};
             }
-            pf[rr] = v;
         }
     };
 
@@ -358,91 +384,74 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int c = rr * CPR + tcol;
-            if (rr < rounds && c < np) {
-                if constexpr (sizeof(E) == 4) {
-                    *(f4_t*)&Cs[c * ldC + tsub * 4] = pf[rr];
-                } else {
-                    uint16_t h0 = MF::from_float(pf[rr][0]), h1 = MF::from_float(pf[rr][1]);
-                    uint16_t h2 = MF::from_float(pf[rr][2]), h3 = MF::from_float(pf[rr][3]);
-                    uint64_t pk = (uint64_t)h0 | ((uint64_t)h1 << 16) | ((uint64_t)h2 << 32) | ((uint64_t)h3 << 48);
-                    *(uint64_t*)&Cs[c * ldC + tsub * 4] = pk;
-                    if (ROWCOPY) {
-                        Cr[(tsub * 4 + 0) * ldR + c] = h0;
-                        Cr[(tsub * 4 + 1) * ldR + c] = h1;
-                        Cr[(tsub * 4 + 2) * ldR + c] = h2;
-                        Cr[(tsub * 4 + 3) * ldR + c] = h3;
-                    }
-                }
-            }
+            if (c < NP) *(f4_t*)&Cs[c * ldC + tsub * 4] = pf[rr];
         }
         __syncthreads();
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
 
-        // Phase A: Y_tile (TM x 64) = C_tile X_blk.  (TM/16) x 4 output tiles over 8 waves.
+        // Phase A: Y_tile (TM x 64) = C_tile X_blk; (TM/16) x 4 output blocks over 8 waves.
         constexpr int YT = (TM / 16) * 4;
-        for (int yt = w; yt < YT; yt += 8) {
-            const int ib = yt >> 2, jb = yt & 3;
-            // Four interleaved accumulators keep consecutive matrix-core ops independent.
-            typename MF::acc acc4[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc4[u] = typename MF::acc{0, 0, 0, 0};
-            for (int k0 = 0; k0 < np; k0 += 4 * KSTEP) {
+        for (int yt0 = 0; yt0 < YT; yt0 += 8) {
+            const int yt = yt0 + w;
+            if (YT >= 8 || yt < YT) {
+                const int ib = yt >> 2, jb = yt & 3;
+                f4_t acc4[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int kk = k0 + u * KSTEP;
-                    if (kk < np) {
-                        typename MF::frag bv =
-                            lds_frag<MF>(&Xs[(jb * 16 + (lane & 15)) * ldX + kk + (lane >> 4) * KPL]);
-                        typename MF::frag av;
-                        if constexpr (KPL == 1) av = Cs[(kk + (lane >> 4)) * ldC + ib * 16 + (lane & 15)];
-                        else av = lds_frag<MF>(&Cr[(ib * 16 + (lane & 15)) * ldR + kk + (lane >> 4) * KPL]);
-                        acc4[u] = MF::mma(av, bv, acc4[u]);
-                    }
+                for (int u = 0; u < 4; ++u) acc4[u] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kk = 0; kk < NP; kk += 4) {
+                    const float bv = Xs[(jb * 16 + (lane & 15)) * ldX + kk + (lane >> 4)];
+                    const float av = Cs[(kk + (lane >> 4)) * ldC + ib * 16 + (lane & 15)];
+                    acc4[(kk >> 2) & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc4[(kk >> 2) & 3], 0, 0, 0);
                 }
-            }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = ib * 16 + MF::row_of(lane, v);
-                const int col = jb * 16 + (lane & 15);
-                Ys[col * ldY + row] = MF::from_acc((acc4[0][v] + acc4[1][v]) + (acc4[2][v] + acc4[3][v]));
+                for (int v = 0; v < 4; ++v) {
+                    const int row = ib * 16 + 4 * (lane >> 4) + v;
+                    const int col = jb * 16 + (lane & 15);
+                    Ys[col * ldY + row] = (acc4[0][v] + acc4[1][v]) + (acc4[2][v] + acc4[3][v]);
+                }
             }
         }
         __syncthreads();
 
         if (MODE == 2 || (MODE == 1 && a.yout != nullptr)) {
-            // Y_tile -> out (lift) or the copy of Y (final pass), float4 column segments, j < lx
+            // Y_tile -> out (lift) or the kept copy of Y (final pass), float4 column segments, j < lx
             float* obase = MODE == 2 ? (float*)a.seg.out : a.yout;
             const int64_t ldo = MODE == 2 ? a.seg.ldo : a.ldy;
             const int64_t row = t * TM + tsub * 4;
-            for (int j = tcol; j < FU_LB; j += CPR) {
-                if (c0 + j >= a.lx) continue;
-                f4_t v = *(const f4_t*)&Ys[j * ldY + tsub * 4];
-                float* o = obase + (size_t)(c0 + j) * (size_t)ldo;
-                if (VEC && row + 3 < a.seg.rows) {
-                    *(f4_t*)(o + row) = v;
-                } else {
+            const bool full = a.vec && (t + 1) * TM <= rows;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (row + q < a.seg.rows) o[row + q] = v[q];
+            for (int j0 = 0; j0 < FU_LB; j0 += CPR) {
+                const int j = j0 + tcol;
+                if (j < FU_LB && c0 + j < a.lx) {
+                    const f4_t v = *(const f4_t*)&Ys[j * ldY + tsub * 4];
+                    float* o = obase + (size_t)(c0 + j) * (size_t)ldo;
+                    if (full) {
+                        *(f4_t*)(o + row) = v;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (row + q < rows) o[row + q] = v[q];
+                    }
                 }
             }
         }
         if constexpr (MODE != 2) {
-            // Phase B: P (np x 64) += C_tile^T Y_tile; wave w owns row blocks w, w+8, ...
+            // Phase B: P (NP x 64) += C_tile^T Y_tile; wave w owns row blocks w, w + 8, ...
 #pragma unroll
-            for (int k0 = 0; k0 < TM; k0 += KSTEP) {
-                typename MF::frag bvs[4];
+            for (int k0 = 0; k0 < TM; k0 += 4) {
+                float bvs[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    bvs[j] = lds_frag<MF>(&Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4) * KPL]);
+                for (int j = 0; j < 4; ++j) bvs[j] = Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
 #pragma unroll
-                for (int q = 0; q < NRB; ++q) {
+                for (int q = 0; q < QB; ++q) {
                     const int rb = w + 8 * q;
-                    if (rb < nrb) {
-                        typename MF::frag av =
-                            lds_frag<MF>(&Cs[(rb * 16 + (lane & 15)) * ldC + k0 + (lane >> 4) * KPL]);
+                    if (rb < NRBLK) {
+                        const float av = Cs[(rb * 16 + (lane & 15)) * ldC + k0 + (lane >> 4)];
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) accP[q * 4 + j] = MF::mma(av, bvs[j], accP[q * 4 + j]);
+                        for (int j = 0; j < 4; ++j)
+                            accP[q * 4 + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bvs[j], accP[q * 4 + j], 0, 0, 0);
                     }
                 }
             }
@@ -451,10 +460,10 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
                 const int gi = w >> 1, gj0 = (w & 1) * 2;
 #pragma unroll
                 for (int k0 = 0; k0 < TM; k0 += 4) {
-                    double av = (double)*(const float*)&Ys[(gi * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+                    const double av = (double)Ys[(gi * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
-                        double bv = (double)*(const float*)&Ys[((gj0 + j) * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+                        const double bv = (double)Ys[((gj0 + j) * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
                         accG[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accG[j], 0, 0, 0);
                     }
                 }
@@ -462,18 +471,18 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
         }
     }
     if constexpr (MODE != 2) {
-        float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)np * FU_LB;
+        float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
 #pragma unroll
-        for (int q = 0; q < NRB; ++q) {
+        for (int q = 0; q < QB; ++q) {
             const int rb = w + 8 * q;
-            if (rb < nrb) {
+            if (rb < NRBLK) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = rb * 16 + MF::row_of(lane, v);
+                        const int row = rb * 16 + 4 * (lane >> 4) + v;
                         const int col = j * 16 + (lane & 15);
-                        outP[row + (size_t)col * np] = accP[q * 4 + j][v];
+                        outP[row + (size_t)col * NP] = accP[q * 4 + j][v];
                     }
             }
         }
@@ -494,10 +503,11 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
 
 // ----------------------------------------------------------------------------
 // k_sketch_bf16: the BF16 power pass P += C^T (C X) with the 16x16x32 BF16
-// matrix-core instruction.  X (np x 64) lives in registers for the whole
-// launch; every tile is read once from HBM, converted to BF16 and written to
-// LDS twice (column-major for C^T Y, row-major for C X) with packed stores:
-// each thread moves a 4 x 4 block (four float4 column segments).
+// matrix-core instruction.  NP = 32 NKS columns (columns n .. NP-1 zero).
+// X (NP x 64) lives in registers for the whole launch; every tile is read
+// once from HBM, converted to BF16 and written to LDS twice (column-major for
+// C^T Y, row-major for C X) with packed stores: each thread moves a 4 x 4
+// block (four float4 column segments).
 // ----------------------------------------------------------------------------
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef short s8_t __attribute__((ext_vector_type(8)));
@@ -506,81 +516,85 @@ __device__ __forceinline__ bf8_t lds_b128(const uint16_t* p) {
     return __builtin_bit_cast(bf8_t, *(const s8_t*)p);   // 16-byte aligned by construction
 }
 
-template <int TM, int NRB, bool VEC>
+template <int TM, int NKS>
 __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
     constexpr int NT = 512;
-    constexpr int JW = TM == 64 ? 2 : 1;            // column blocks of Y per wave in phase A
-    constexpr int NPMAX = NRB * 128;
-    constexpr int KS = NPMAX / 32;                  // k-steps of phase A
+    constexpr int NP = NKS * 32;
+    constexpr int NCG = NP / 4;                     // column groups of 4
+    constexpr int JW = TM / 32;                     // column blocks of Y per wave in phase A
     constexpr int RG = TM / 4;                      // row groups of 4
-    constexpr int CGR = NT / RG;                    // column groups (of 4) per round
-    constexpr int RMAX = (NPMAX / 4 + CGR - 1) / CGR;
+    constexpr int CGR = NT / RG;                    // column groups per round
+    constexpr int RMAX = (NCG + CGR - 1) / CGR;
+    constexpr int NRBLK = NP / 16;                  // phase-B row blocks
+    constexpr int QB = (NRBLK + 7) / 8;
+    constexpr int ldC = TM + 8, ldR = NP + 8, ldY = TM + 8;
+    static_assert(TM == 32 || TM == 64, "tile height");
     extern __shared__ __align__(16) unsigned char smem[];
-    const int np = a.np;
-    const int ldC = TM + 8;
-    const int ldR = np + 8;
-    const int ldY = TM + 8;
-    uint16_t* Cs = (uint16_t*)smem;                 // np x TM, column-major
-    uint16_t* Cr = Cs + (size_t)np * ldC;           // TM x np, row-major
-    uint16_t* Ys = Cr + (size_t)TM * ldR;           // 64 x TM, column-major
+    uint16_t* Cs = (uint16_t*)smem;                 // NP x TM, column-major
+    uint16_t* Cr = Cs + NP * ldC;                   // TM x NP, row-major
+    uint16_t* Ys = Cr + TM * ldR;                   // 64 x TM, column-major
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int b = blockIdx.x;
-    const int xcd = b & 7, local = b >> 3;
-    const int lb = local % a.nlb;
-    const int wg = (local / a.nlb) * 8 + xcd;
-    if (wg >= a.nwg) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const FusedCoords fc = fused_coords(a);
+    if (fc.wg >= a.nwg) return;
+    const int wg = fc.wg, lb = fc.lb;
     const int c0 = lb * FU_LB;
 
     // Phase-A unit of this wave: row block ib, column blocks jb0 .. jb0 + JW - 1.
-    const int ib = TM == 64 ? (w & 3) : (TM == 32 ? (w & 1) : 0);
-    const int jb0 = TM == 64 ? (w >> 2) * 2 : (TM == 32 ? (w >> 1) : w);
-    const bool a_active = (TM >= 32) || (w < 4);
-    bf8_t xf[JW][KS];
+    const int ib = TM == 64 ? (w & 3) : (w & 1);
+    const int jb0 = TM == 64 ? (w >> 2) * 2 : (w >> 1);
+    bf8_t xf[JW][NKS];
 #pragma unroll
     for (int c = 0; c < JW; ++c)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
+        for (int ks = 0; ks < NKS; ++ks) {
             bf8_t v;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int k = ks * 32 + 8 * (lane >> 4) + q;
                 const int j = c0 + (jb0 + c) * 16 + (lane & 15);
-                double x = (k < a.n && j < a.lx) ? a.X[k + (int64_t)j * a.ldx] : 0.0;
-                v[q] = __builtin_bit_cast(__bf16, f32_to_bf16_rne((float)x));
+                v[q] = __builtin_bit_cast(__bf16, f32_to_bf16_rne((float)x_elem(a, k, j)));
             }
             xf[c][ks] = v;
         }
 
-    const int nrb = np / 16;
-    f4_t accP[NRB * 4];
+    f4_t accP[QB * 4];
 #pragma unroll
-    for (int t = 0; t < NRB * 4; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < QB * 4; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    const int ncg = np / 4;
-    const int rounds = (ncg + CGR - 1) / CGR;
+    // Per-thread column pointers: columns (rr * CGR + cgl) * 4 + q.
     const int rg = tid % RG, cgl = tid / RG;
+    const float* cp[RMAX][4];
+    bool cv[RMAX][4];
+#pragma unroll
+    for (int rr = 0; rr < RMAX; ++rr)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = (rr * CGR + cgl) * 4 + q;
+            cv[rr][q] = c < a.n;
+            cp[rr][q] = fcol(a.seg, c < a.n ? c : a.n - 1);
+        }
+    const int64_t rows = a.seg.rows;
     f4_t pf[RMAX][4];
     auto fetch = [&](int64_t t) {
         const int64_t row = t * TM + rg * 4;
+        const bool full = a.vec && (t + 1) * TM <= rows;   // uniform
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
-            const int cg = rr * CGR + cgl;
+            if (rr * CGR + cgl < NCG) {                      // uniform per wave
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
-                const int c = cg * 4 + q;
-                if (rr < rounds && c < a.n) {
-                    const float* p = fcol(a.seg, c);
-                    if (VEC && row + 3 < a.seg.rows) {
-                        v = *(const f4_t*)(p + row);
+                for (int q = 0; q < 4; ++q) {
+                    f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
+                    if (full) {
+                        v = *(const f4_t*)(cp[rr][q] + row);
                     } else {
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            if (row + e < a.seg.rows) v[e] = p[row + e];
+                            if (row + e < rows) v[e] = cp[rr][q][row + e];
                     }
+                    pf[rr][q] = cv[rr][q] ? v : f4_t{0.f, 0.f, 0.f, 0.f};
                 }
-                pf[rr][q] = v;
             }
         }
     };
@@ -592,22 +606,17 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int cg = rr * CGR + cgl;
-            if (rr < rounds && cg < ncg) {
-                uint16_t h[4][4];   // [column q][row e]
+            if (cg < NCG) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) h[q][e] = f32_to_bf16_rne(pf[rr][q][e]);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    uint64_t pk = (uint64_t)h[q][0] | ((uint64_t)h[q][1] << 16) | ((uint64_t)h[q][2] << 32) |
-                                  ((uint64_t)h[q][3] << 48);
+                for (int q = 0; q < 4; ++q) {   // column q, rows rg*4 .. rg*4+3
+                    const uint64_t pk = (uint64_t)pack_bf16x2(pf[rr][q][0], pf[rr][q][1]) |
+                                        ((uint64_t)pack_bf16x2(pf[rr][q][2], pf[rr][q][3]) << 32);
                     *(uint64_t*)&Cs[(cg * 4 + q) * ldC + rg * 4] = pk;
                 }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    uint64_t pk = (uint64_t)h[0][e] | ((uint64_t)h[1][e] << 16) | ((uint64_t)h[2][e] << 32) |
-                                  ((uint64_t)h[3][e] << 48);
+                for (int e = 0; e < 4; ++e) {   // row rg*4+e, columns cg*4 .. cg*4+3
+                    const uint64_t pk = (uint64_t)pack_bf16x2(pf[rr][0][e], pf[rr][1][e]) |
+                                        ((uint64_t)pack_bf16x2(pf[rr][2][e], pf[rr][3][e]) << 32);
                     *(uint64_t*)&Cr[(rg * 4 + e) * ldR + cg * 4] = pk;
                 }
             }
@@ -615,43 +624,39 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
         __syncthreads();
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
 
-        // Phase A: Y_tile = C_tile X (X fragments in registers).
-        if (a_active) {
-            // Two interleaved accumulators per column block (independent consecutive ops).
+        // Phase A: Y_tile = C_tile X (X fragments in registers), two interleaved accumulators.
+        {
             f4_t accY[JW][2];
 #pragma unroll
             for (int c = 0; c < JW; ++c) accY[c][0] = accY[c][1] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                if (ks * 32 < np) {
-                    bf8_t av = lds_b128(&Cr[(ib * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4)]);
+            for (int ks = 0; ks < NKS; ++ks) {
+                const bf8_t av = lds_b128(&Cr[(ib * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4)]);
 #pragma unroll
-                    for (int c = 0; c < JW; ++c)
-                        accY[c][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[c][ks], accY[c][ks & 1], 0, 0, 0);
-                }
+                for (int c = 0; c < JW; ++c)
+                    accY[c][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[c][ks], accY[c][ks & 1], 0, 0, 0);
             }
 #pragma unroll
-            for (int c = 0; c < JW; ++c)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = ib * 16 + 4 * (lane >> 4) + v;
-                    const int col = (jb0 + c) * 16 + (lane & 15);
-                    Ys[col * ldY + row] = f32_to_bf16_rne(accY[c][0][v] + accY[c][1][v]);
-                }
+            for (int c = 0; c < JW; ++c) {   // rows ib*16 + 4*(lane/16) .. +3 of column col: one 8-byte store
+                const int col = (jb0 + c) * 16 + (lane & 15);
+                const f4_t y = accY[c][0] + accY[c][1];
+                *(uint64_t*)&Ys[col * ldY + ib * 16 + 4 * (lane >> 4)] =
+                    (uint64_t)pack_bf16x2(y[0], y[1]) | ((uint64_t)pack_bf16x2(y[2], y[3]) << 32);
+            }
         }
         __syncthreads();
 
-        // Phase B: P (np x 64) += C_tile^T Y_tile; wave w owns row blocks w, w + 8, ...
+        // Phase B: P (NP x 64) += C_tile^T Y_tile; wave w owns row blocks w, w + 8, ...
 #pragma unroll
         for (int ks = 0; ks < TM / 32; ++ks) {
             bf8_t bvs[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) bvs[j] = lds_b128(&Ys[(j * 16 + (lane & 15)) * ldY + ks * 32 + 8 * (lane >> 4)]);
 #pragma unroll
-            for (int q = 0; q < NRB; ++q) {
+            for (int q = 0; q < QB; ++q) {
                 const int rb = w + 8 * q;
-                if (rb < nrb) {
-                    bf8_t av = lds_b128(&Cs[(rb * 16 + (lane & 15)) * ldC + ks * 32 + 8 * (lane >> 4)]);
+                if (rb < NRBLK) {
+                    const bf8_t av = lds_b128(&Cs[(rb * 16 + (lane & 15)) * ldC + ks * 32 + 8 * (lane >> 4)]);
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         accP[q * 4 + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bvs[j], accP[q * 4 + j], 0, 0, 0);
@@ -659,51 +664,115 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
             }
         }
     }
-    float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)np * FU_LB;
+    float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
 #pragma unroll
-    for (int q = 0; q < NRB; ++q) {
+    for (int q = 0; q < QB; ++q) {
         const int rb = w + 8 * q;
-        if (rb < nrb) {
+        if (rb < NRBLK) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = rb * 16 + 4 * (lane >> 4) + v;
                     const int col = j * 16 + (lane & 15);
-                    outP[row + (size_t)col * np] = accP[q * 4 + j][v];
+                    outP[row + (size_t)col * NP] = accP[q * 4 + j][v];
                 }
         }
     }
 }
 
-size_t sketch_lds_bytes(int tm, int np) {
+// ----------------------------------------------------------------------------
+// Plans and launchers of the fused passes.  The compiled (tile height, panel
+// width) pairs are listed here; a plan picks the narrowest compiled width that
+// holds the panel and the tallest tile that fits the LDS of one CU (or the
+// requested height when it is compiled).
+// ----------------------------------------------------------------------------
+static size_t sketch_lds(int tm, int np) {
     return ((size_t)np * (tm + 8) + (size_t)tm * (np + 8) + (size_t)FU_LB * (tm + 8)) * 2;
 }
-
-int sketch_pick_tm(int np) {
-    if (np > 640 || np % 32) return 0;
-    for (int tm : {64, 32})
-        if (sketch_lds_bytes(tm, np) <= 160 * 1024 && (np <= 384 || tm == 32)) return tm;
-    return 0;
+static size_t fused_lds(int tm, int np) {
+    return ((size_t)FU_LB * (np + 4) + (size_t)np * (tm + 4) + (size_t)FU_LB * (tm + 4)) * 4;
 }
 
-template <int TM, int NRB, bool VEC>
-static hipError_t launch_sketch_k(const FusedArgs& a, hipStream_t st) {
-    size_t lds = sketch_lds_bytes(TM, a.np);
-    int blocks = ((a.nwg + 7) / 8) * 8 * a.nlb;
-    hipError_t e = hipFuncSetAttribute((const void*)k_sketch_bf16<TM, NRB, VEC>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+static const int kSketchNks[] = {2, 4, 6, 8, 10, 12, 16, 20};
+static const int kFusedNp[] = {64, 128, 192, 256, 320, 384, 448};
+
+bool sketch_plan(int n, int tile_rows, FusedPlan* p) {
+    for (int nks : kSketchNks) {
+        if (nks * 32 < n) continue;
+        int tm = nks <= 6 ? 64 : 32;
+        if (tile_rows == 32) tm = 32;
+        p->np = nks * 32;
+        p->tm = tm;
+        p->lds = sketch_lds(tm, p->np);
+        return p->lds <= 160 * 1024;
+    }
+    return false;
+}
+
+static bool fused_compiled(int tm, int np) {
+    if (tm == 64) return np <= 256;
+    if (tm == 32) return np <= 384;
+    if (tm == 16) return np == 448;
+    return false;
+}
+
+bool fused_plan(int n, int tile_rows, FusedPlan* p) {
+    for (int np : kFusedNp) {
+        if (np < n) continue;
+        for (int tm : {64, 32, 16}) {
+            if (tile_rows && tm != tile_rows) continue;
+            if (!fused_compiled(tm, np) || fused_lds(tm, np) > 160 * 1024) continue;
+            p->np = np;
+            p->tm = tm;
+            p->lds = fused_lds(tm, np);
+            return true;
+        }
+        if (tile_rows) return fused_plan(n, 0, p);
+        return false;
+    }
+    return false;
+}
+
+template <class K>
+static hipError_t launch_512(K kern, const FusedArgs& a, size_t lds, hipStream_t st) {
+    const int blocks = ((a.nwg + 7) / 8) * 8 * a.nlb;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sketch_bf16<TM, NRB, VEC>), dim3(blocks), dim3(512), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(512), lds, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st) {
-    const bool v = a.vec != 0;
-    if (a.tm == 64 && a.np <= 384) return v ? launch_sketch_k<64, 3, true>(a, st) : launch_sketch_k<64, 3, false>(a, st);
-    if (a.tm == 32 && a.np <= 384) return v ? launch_sketch_k<32, 3, true>(a, st) : launch_sketch_k<32, 3, false>(a, st);
-    if (a.tm == 32 && a.np <= 640) return v ? launch_sketch_k<32, 5, true>(a, st) : launch_sketch_k<32, 5, false>(a, st);
+    const size_t lds = sketch_lds(a.tm, a.np);
+    const int nks = a.np / 32;
+    if (a.np % 32 || (a.tm != 32 && a.tm != 64)) return hipErrorInvalidValue;
+#define SK(TM_, NKS_) \
+    if (a.tm == TM_ && nks == NKS_) return launch_512(k_sketch_bf16<TM_, NKS_>, a, lds, st);
+    SK(64, 2) SK(64, 4) SK(64, 6)
+    SK(32, 2) SK(32, 4) SK(32, 6) SK(32, 8) SK(32, 10) SK(32, 12) SK(32, 16) SK(32, 20)
+#undef SK
     return hipErrorInvalidValue;
+}
+
+template <int MODE>
+static hipError_t launch_fused_mode(const FusedArgs& a, size_t lds, hipStream_t st) {
+#define FU(TM_, NP_) \
+    if (a.tm == TM_ && a.np == NP_) return launch_512(k_fused<TM_, NP_, MODE>, a, lds, st);
+    FU(64, 64) FU(64, 128) FU(64, 192) FU(64, 256)
+    FU(32, 64) FU(32, 128) FU(32, 192) FU(32, 256) FU(32, 320) FU(32, 384)
+    FU(16, 448)
+#undef FU
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused(int mode, const FusedArgs& a, hipStream_t st) {
+    if (!fused_compiled(a.tm, a.np)) return hipErrorInvalidValue;
+    const size_t lds = fused_lds(a.tm, a.np);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (mode == 0) return launch_fused_mode<0>(a, lds, st);
+    if (mode == 1) return launch_fused_mode<1>(a, lds, st);
+    return launch_fused_mode<2>(a, lds, st);
 }
 
 // Fixed-order FP64 sum of the fused partials: P (n x lx, ld n) and G (lx x lx).
@@ -748,12 +817,6 @@ __global__ __launch_bounds__(256) void k_fused_reduce(FusedReduceArgs a) {
 // ----------------------------------------------------------------------------
 // Host launchers.
 // ----------------------------------------------------------------------------
-size_t fused_lds_bytes(int ct_bytes, bool rowcopy, int tm, int np) {
-    size_t e = (size_t)FU_LB * (np + 4) + (size_t)np * (tm + 4) + (rowcopy ? (size_t)tm * (np + 4) : 0) +
-               (size_t)FU_LB * (tm + 4);
-    return e * ct_bytes;
-}
-
 hipError_t launch_tn(bool fp64, const TnArgs& a, int nitems, hipStream_t st) {
     dim3 grid(nitems, a.nob);
     if (fp64) hipLaunchKernelGGL(k_tn<double>, grid, dim3(256), 0, st, a);
@@ -772,53 +835,6 @@ hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
     if (fp64) hipLaunchKernelGGL(k_nn<double>, grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL(k_nn<float>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
-}
-
-template <class CT, int TM, int NRB, bool VEC, int MODE>
-static hipError_t launch_fused_k(const FusedArgs& a, size_t lds, hipStream_t st) {
-    int blocks = ((a.nwg + 7) / 8) * 8 * a.nlb;
-    hipError_t e = hipFuncSetAttribute((const void*)k_fused<CT, TM, NRB, VEC, MODE>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fused<CT, TM, NRB, VEC, MODE>), dim3(blocks), dim3(512), lds, st, a);
-    return hipGetLastError();
-}
-
-template <class CT, int TM, bool VEC, int MODE>
-static hipError_t launch_fused_n(const FusedArgs& a, size_t lds, hipStream_t st) {
-    if (a.np <= 128) return launch_fused_k<CT, TM, 1, VEC, MODE>(a, lds, st);
-    if (a.np <= 384) return launch_fused_k<CT, TM, 3, VEC, MODE>(a, lds, st);
-    if (a.np <= 640) return launch_fused_k<CT, TM, 5, VEC, MODE>(a, lds, st);
-    return hipErrorInvalidValue;
-}
-
-template <class CT, bool VEC, int MODE>
-static hipError_t launch_fused_m(const FusedArgs& a, size_t lds, hipStream_t st) {
-    if (a.tm == 16) return launch_fused_n<CT, 16, VEC, MODE>(a, lds, st);
-    if (a.tm == 32) return launch_fused_n<CT, 32, VEC, MODE>(a, lds, st);
-    return launch_fused_n<CT, 64, VEC, MODE>(a, lds, st);
-}
-
-// Largest tile height whose LDS footprint fits one CU (0: none fits).
-int fused_pick_tm(bool bf16, int np) {
-    if (np > 640) return 0;
-    for (int tm : {64, 32, 16})
-        if (fused_lds_bytes(bf16 ? 2 : 4, bf16, tm, np) <= 160 * 1024) return tm;
-    return 0;
-}
-
-bool fused_fits(bool bf16, int tm, int np) { return tm > 0 && np <= 640 && fused_lds_bytes(bf16 ? 2 : 4, bf16, tm, np) <= 160 * 1024; }
-
-hipError_t launch_fused(bool bf16, int mode, const FusedArgs& a, hipStream_t st) {
-    size_t lds = fused_lds_bytes(bf16 ? 2 : 4, bf16, a.tm, a.np);
-    bool vec = a.vec != 0;
-    if (bf16) {
-        if (mode != 0) return hipErrorInvalidValue;
-        return vec ? launch_fused_m<bf16_t, true, 0>(a, lds, st) : launch_fused_m<bf16_t, false, 0>(a, lds, st);
-    }
-    if (mode == 0) return vec ? launch_fused_m<float, true, 0>(a, lds, st) : launch_fused_m<float, false, 0>(a, lds, st);
-    if (mode == 1) return vec ? launch_fused_m<float, true, 1>(a, lds, st) : launch_fused_m<float, false, 1>(a, lds, st);
-    return vec ? launch_fused_m<float, true, 2>(a, lds, st) : launch_fused_m<float, false, 2>(a, lds, st);
 }
 
 hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st) {

@@ -188,6 +188,7 @@ struct psvd_handle {
     size_t omega_host_cap = 0;
 
     psvd_stats_t stats;
+    int32_t async_fallbacks_seen = 0;
     std::string err;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
@@ -236,6 +237,9 @@ static void prof_end(psvd_handle* h, int e) {
     if (e >= 0) (void)hipEventRecord(h->prof_ev[e + 1], h->stream);
 }
 
+// Last error of a call without a handle (psvd_rsvd), per host thread.
+static thread_local std::string g_call_err;
+
 static int fail(psvd_handle* h, int code, const std::string& msg) {
     if (h) h->err = std::string(status_name(code)) + ": " + msg;
     return code;
@@ -245,6 +249,8 @@ static int hip_fail(psvd_handle* h, hipError_t e, const char* what) {
     return fail(h, e == hipErrorOutOfMemory ? PSVD_E_NOMEM : PSVD_E_DEVICE,
                 std::string(what) + ": " + hipGetErrorString(e));
 }
+
+static int sync_async(psvd_handle* h);
 
 #define HIPCHK(h, expr)                                   \
     do {                                                  \
@@ -294,6 +300,13 @@ static SmallLayout small_layout(double* base, int n, int l, int K) {
     return L;
 }
 
+// Work-groups of a fused pass: wg_per_cu per compute unit (256 CUs), at most one per tile.
+static int fused_wgs(const psvd_handle* h, int64_t tiles) {
+    const int per_cu = h->opt.wg_per_cu > 0 ? h->opt.wg_per_cu : 1;
+    const int64_t nwg = std::min<int64_t>((int64_t)256 * per_cu, FU_MAX_WG);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nwg, tiles));
+}
+
 static int ensure_workspace(psvd_handle* h, int n) {
     if (n <= h->nmax) return PSVD_OK;
     int l = h->ell;
@@ -305,10 +318,16 @@ static int ensure_workspace(psvd_handle* h, int n) {
     int nb = ceil_div(w, 64);
     size_t nob = (size_t)nb * nb;
     HIPCHK(h, h->part.ensure((size_t)(2048 + 2 * nob) * 64 * 64 * sizeof(double)));
-    int np = ((n + 31) / 32) * 32;
+    // fused-pass partials: one NP x 64 block per (work-group, column block)
+    int np = ((n + 63) / 64) * 64;
+    FusedPlan sp;
+    for (int tr : {0, 32})
+        if (sketch_plan(n, tr, &sp)) np = std::max(np, sp.np);
+    if (fused_plan(n, h->opt.tile_rows, &sp)) np = std::max(np, sp.np);
     int nlb = ceil_div(std::max(l, 1), 64);
-    HIPCHK(h, h->partP.ensure((size_t)256 * nlb * np * 64 * sizeof(float)));
-    HIPCHK(h, h->partG.ensure((size_t)256 * 64 * 64 * sizeof(double)));
+    const size_t wgs = (size_t)fused_wgs(h, INT64_MAX);
+    HIPCHK(h, h->partP.ensure(wgs * nlb * np * 64 * sizeof(float)));
+    HIPCHK(h, h->partG.ensure(wgs * 64 * 64 * sizeof(double)));
     h->nmax = n;
     return PSVD_OK;
 }
@@ -412,25 +431,24 @@ static bool seg_all_f32(const PanelSeg& S) {
 // is FP32 and fits, otherwise the generic product.
 static int lift_product(psvd_handle* h, const PanelSeg& S, const double* T, int64_t ldt, int nx, bool fp64,
                         const int32_t* skip, int skip_mask, int need_mask) {
-    const int np = ((S.ncols + 15) / 16) * 16;
-    const int tm = fused_pick_tm(false, np);
-    if (!fp64 && tm > 0 && seg_all_f32(S) && S.out_dtype == PSVD_F32 && skip == nullptr) {
+    FusedPlan fp;
+    if (!fp64 && seg_all_f32(S) && S.out_dtype == PSVD_F32 && skip == nullptr &&
+        fused_plan(S.ncols, h->opt.tile_rows, &fp)) {
         FusedArgs fa;
         std::memset(&fa, 0, sizeof(fa));
         fa.seg = S;
         fa.X = T;
         fa.ldx = ldt;
         fa.n = S.ncols;
-        fa.np = np;
+        fa.np = fp.np;
         fa.lx = nx;
         fa.nlb = ceil_div(nx, 64);
-        fa.tm = tm;
-        fa.nwg = 256;
-        fa.tiles = (S.rows + tm - 1) / tm;
-        if (fa.tiles < fa.nwg) fa.nwg = (int)fa.tiles;
+        fa.tm = fp.tm;
+        fa.tiles = (S.rows + fp.tm - 1) / fp.tm;
+        fa.nwg = fused_wgs(h, fa.tiles);
         fa.vec = seg_vec_ok(S, true) ? 1 : 0;
         int pe = prof_begin(h, PSVD_KC_LIFT);
-        HIPCHK(h, launch_fused(false, 2, fa, h->stream));
+        HIPCHK(h, launch_fused(2, fa, h->stream));
         prof_end(h, pe);
         return PSVD_OK;
     }
@@ -447,25 +465,25 @@ static PanelSeg small_seg(const double* p, int rows, int cols, int ld, double* o
 }
 
 // X_new = orth(P) = P chol(P^T P)^-1 (P: n x l FP64), then rows scaled by D.
-static int small_orth(psvd_handle* h, const SmallLayout& L, int n, int l, double* Xout, const int32_t* st) {
-    PanelSeg Ps = small_seg(L.P, n, l, n);
-    int rc = tn_product(h, Ps, Ps, true, true, L.H, nullptr, 0, nullptr, 0);
-    if (rc) return rc;
-    CholArgs ca;
-    ca.H = L.H;
-    ca.Ri = L.RYi;   // scratch R^-1
-    ca.l = l;
-    ca.status = (int32_t*)st;
-    ca.flag_bit = DEV_FALLBACK;
-    {
-        int pes = prof_begin(h, PSVD_KC_SMALL);
-        HIPCHK(h, launch_small_chol(ca, h->stream));
-        prof_end(h, pes);
-    }
-    Ps.out = Xout;
-    Ps.ldo = n;
-    rc = nn_product(h, Ps, L.RYi, l, l, true, h->d.as<double>(), h->r, nullptr, 0);
-    return rc;
+static int small_orth(psvd_handle* h, const SmallLayout& L, int n, int l, double* Xout, int32_t* st) {
+    OrthArgs oa;
+    std::memset(&oa, 0, sizeof(oa));
+    oa.n = n;
+    oa.l = l;
+    oa.P = L.P;
+    oa.G = L.H;
+    oa.R = L.H2;
+    oa.Ri = L.RYi;
+    oa.vec = L.vec;
+    oa.X = Xout;
+    oa.d = h->d.as<double>();
+    oa.r = h->r;
+    oa.status = st;
+    oa.flag_bit = DEV_FALLBACK;
+    int pes = prof_begin(h, PSVD_KC_SMALL);
+    HIPCHK(h, launch_small_orth(oa, h->stream));
+    prof_end(h, pes);
+    return PSVD_OK;
 }
 
 // ----------------------------------------------------------------------------
@@ -487,7 +505,7 @@ void psvd_default_options(psvd_options* opt) {
 
 const char* psvd_status_string(int status) { return status_name(status); }
 
-const char* psvd_last_error(const psvd_handle* h) { return h ? h->err.c_str() : "null handle"; }
+const char* psvd_last_error(const psvd_handle* h) { return h ? h->err.c_str() : g_call_err.c_str(); }
 
 int psvd_initialize(psvd_handle** out, int64_t M, int32_t K, double ff, int32_t oversampling, int32_t power_iters,
                     const psvd_options* opt) {
@@ -499,7 +517,9 @@ int psvd_initialize(psvd_handle** out, int64_t M, int32_t K, double ff, int32_t 
     if (o.max_sweeps <= 0) o.max_sweeps = 60;
     if (M < 1 || K < 1 || K > M || !(ff > 0.0 && ff <= 1.0) || oversampling < 0 || power_iters < 0 ||
         (o.method != PSVD_DETERMINISTIC && o.method != PSVD_RANDOMIZED) ||
-        (o.precision < PSVD_PREC_FP64 || o.precision > PSVD_PREC_MIXED))
+        (o.precision < PSVD_PREC_FP64 || o.precision > PSVD_PREC_MIXED) ||
+        (o.tile_rows != 0 && o.tile_rows != 16 && o.tile_rows != 32 && o.tile_rows != 64) ||
+        o.wg_per_cu < 0 || o.wg_per_cu > FU_MAX_WG / 256)
         return PSVD_E_INVAL;
     psvd_handle* h = new (std::nothrow) psvd_handle();
     if (!h) return PSVD_E_NOMEM;
@@ -522,6 +542,7 @@ int psvd_initialize(psvd_handle** out, int64_t M, int32_t K, double ff, int32_t 
     }
     if (e == hipSuccess) e = h->d.ensure((size_t)K * sizeof(double));
     if (e == hipSuccess) e = h->status.ensure(64);
+    if (e == hipSuccess) e = hipMemset(h->status.p, 0, 64);
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->status_host, 64, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&h->ev0);
     if (e == hipSuccess) e = hipEventCreate(&h->ev1);
@@ -581,6 +602,7 @@ int psvd_get_omega(const psvd_handle* h, int64_t batch, int64_t n, double* out) 
 int psvd_stats(const psvd_handle* hc, psvd_stats_t* out) {
     psvd_handle* h = const_cast<psvd_handle*>(hc);
     if (!h || !out) return PSVD_E_INVAL;
+    if (int rc = sync_async(h)) return rc;
     if (profiling(h)) {
         HIPCHK(h, hipStreamSynchronize(h->stream));
         prof_resolve(h);
@@ -604,6 +626,26 @@ static int finish_status(psvd_handle* h, int32_t st) {
     if (st & DEV_NONFINITE) return fail(h, PSVD_E_NONFINITE, "non-finite values reached the small factorisation");
     if (st & DEV_BREAKDOWN) return fail(h, PSVD_E_BREAKDOWN, "Cholesky breakdown (fallback disabled)");
     if (st & DEV_NOCONV) return fail(h, PSVD_E_NOCONV, "Jacobi SVD did not converge within max_sweeps");
+    return PSVD_OK;
+}
+
+// Synchronising calls of an asynchronous handle: wait for the stream, take the
+// folded status of the updates since the last such call, and report the first
+// device error (the state then holds the results of the failed update).
+static int sync_async(psvd_handle* h) {
+    if (!(h->opt.flags & PSVD_OPT_ASYNC)) return PSVD_OK;
+    int32_t* dstat = h->status.as<int32_t>();
+    HIPCHK(h, hipMemcpyAsync(h->status_host, dstat, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const int32_t sticky = h->status_host[2];
+    h->stats.last_sweeps = h->status_host[3];
+    h->stats.fallbacks += h->status_host[4] - h->async_fallbacks_seen;
+    h->async_fallbacks_seen = h->status_host[4];
+    if (sticky) {
+        HIPCHK(h, hipMemsetAsync(dstat + 2, 0, sizeof(int32_t), h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return finish_status(h, sticky);
+    }
     return PSVD_OK;
 }
 
@@ -736,16 +778,12 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         HIPCHK(h, hipEventRecord(h->omega_ev[ob], st));
         // X' = D Omega
         HIPCHK(h, launch_scale_rows(L.X, n, l, n, dsc, r, 1, st));
-        const int np = ((n + 15) / 16) * 16;
-        const int np32 = ((n + 31) / 32) * 32;
         const int nlb = ceil_div(l, 64);
         auto pass = [&](bool bf16, bool want_g) -> int {
             // P = D C'^T (C' X')  [+ G_Y = Y^T Y]
-            // BF16 power passes up to 384 columns use the 16x16x32 sketch kernel.
-            const bool sketch = bf16 && !want_g && np32 <= 384;
-            const int npk = sketch ? np32 : np;      // the sketch kernel steps k by 32
-            const int tm = sketch ? 32 : fused_pick_tm(bf16, np);
-            bool fuse_ok = !fp64 && tm > 0 && seg_all_f32(C) && (!want_g || nlb == 1);
+            FusedPlan fp;
+            const bool planned = bf16 ? sketch_plan(n, h->opt.tile_rows, &fp) : fused_plan(n, h->opt.tile_rows, &fp);
+            bool fuse_ok = !fp64 && planned && seg_all_f32(C) && (!want_g || nlb == 1) && !(bf16 && want_g);
             if (fuse_ok) {
                 FusedArgs fa;
                 std::memset(&fa, 0, sizeof(fa));
@@ -753,13 +791,12 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 fa.X = L.X;
                 fa.ldx = n;
                 fa.n = n;
-                fa.np = npk;
+                fa.np = fp.np;
                 fa.lx = l;
                 fa.nlb = nlb;
-                fa.tm = tm;
-                fa.nwg = 256;
+                fa.tm = fp.tm;
                 fa.tiles = (M + fa.tm - 1) / fa.tm;
-                if (fa.tiles < fa.nwg) fa.nwg = (int)fa.tiles;
+                fa.nwg = fused_wgs(h, fa.tiles);
                 fa.partP = h->partP.as<float>();
                 fa.partG = h->partG.as<double>();
                 fa.want_g = want_g ? 1 : 0;
@@ -769,8 +806,8 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                     fa.ldy = M;
                 }
                 int pe = prof_begin(h, bf16 ? PSVD_KC_FUSED_BF16 : PSVD_KC_FUSED_F32);
-                if (sketch) HIPCHK(h, launch_sketch_bf16(fa, st));
-                else HIPCHK(h, launch_fused(bf16, want_g ? 1 : 0, fa, st));
+                if (bf16) HIPCHK(h, launch_sketch_bf16(fa, st));
+                else HIPCHK(h, launch_fused(want_g ? 1 : 0, fa, st));
                 prof_end(h, pe);
                 FusedReduceArgs ra;
                 std::memset(&ra, 0, sizeof(ra));
@@ -780,7 +817,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 ra.partG = h->partG.as<double>();
                 ra.nwg = fa.nwg;
                 ra.nlb = nlb;
-                ra.np = npk;
+                ra.np = fa.np;
                 ra.n = n;
                 ra.lx = l;
                 ra.want_g = fa.want_g;
@@ -811,54 +848,26 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         }
         rc = pass(false, true);
         if (rc) return rc;
-        // R_Y = chol(G_Y)
-        CholArgs cy;
-        cy.H = L.G_Y;
-        cy.Ri = L.RYi;
-        cy.l = l;
-        cy.status = dstat;
-        cy.flag_bit = DEV_FALLBACK;
-        {
-            int pes = prof_begin(h, PSVD_KC_SMALL);
-            HIPCHK(h, launch_small_chol(cy, st));
-            prof_end(h, pes);
-        }
-        // R_P: Cholesky-QR2 of P.
-        PanelSeg Ps = small_seg(L.P, n, l, n);
-        rc = tn_product(h, Ps, Ps, true, true, L.H, nullptr, 0, nullptr, 0);
-        if (rc) return rc;
-        CholArgs c1;
-        c1.H = L.H;          // -> R1
-        c1.Ri = L.R1b;       // R1^-1
-        c1.l = l;
-        c1.status = dstat;
-        c1.flag_bit = DEV_FALLBACK;
-        {
-            int pes = prof_begin(h, PSVD_KC_SMALL);
-            HIPCHK(h, launch_small_chol(c1, st));
-            prof_end(h, pes);
-        }
-        Ps.out = L.P1;
-        Ps.ldo = n;
-        rc = nn_product(h, Ps, L.R1b, l, l, true, nullptr, 0, nullptr, 0);
-        if (rc) return rc;
-        PanelSeg P1s = small_seg(L.P1, n, l, n);
-        rc = tn_product(h, P1s, P1s, true, true, L.H2, nullptr, 0, nullptr, 0);
-        if (rc) return rc;
+        // R_Y, Cholesky-QR2 of P, the small SVD and M2 in one work-group.
         RandFinalArgs rf;
+        std::memset(&rf, 0, sizeof(rf));
+        rf.n = n;
         rf.l = l;
         rf.K = h->K;
         rf.max_sweeps = h->opt.max_sweeps;
-        rf.RY = L.G_Y;
+        rf.P = L.P;
+        rf.P1 = L.P1;
+        rf.GY = L.G_Y;
+        rf.RY = L.RY;
         rf.RYi = L.RYi;
-        rf.R1 = L.H;
-        rf.H2 = L.H2;
-        rf.Z = L.Z;
+        rf.G1 = L.H;
+        rf.R1 = L.R1b;
+        rf.W = L.H2;
+        rf.V = L.Z;
+        rf.vec = L.vec;
         rf.M2 = L.M2;
         rf.s_out = s_new;
         rf.small_u = L.sm_u;
-        rf.vec = L.vec;
-        rf.ivec = h->ivec.as<int32_t>();
         rf.status = dstat;
         rf.sweeps = dsweeps;
         {
@@ -883,6 +892,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
     h->batch += 1;
     h->stats.batches += 1;
     h->stats.last_path = randomized ? 1 : 0;
+    if (h->opt.flags & PSVD_OPT_ASYNC) HIPCHK(h, launch_status_fold(dstat, st));
     if (!(h->opt.flags & PSVD_OPT_ASYNC)) {
         hipError_t e = hipMemcpyAsync(h->status_host, dstat, 8, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -915,6 +925,7 @@ int psvd_singular_values(const psvd_handle* hc, double* out, int32_t cap, int32_
     psvd_handle* h = const_cast<psvd_handle*>(hc);
     if (!h) return PSVD_E_INVAL;
     if (r) *r = h->r;
+    if (int rc = sync_async(h)) return rc;
     if (h->r == 0) return PSVD_OK;
     if (!out || cap < h->r) return fail(h, PSVD_E_INVAL, "output capacity below the rank");
     HIPCHK(h, hipMemcpyAsync(out, h->s[h->cur].p, (size_t)h->r * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -935,6 +946,7 @@ int psvd_modes(const psvd_handle* hc, void* U, int64_t ldu, int32_t dtype) {
     if (!h || (!U && h->r > 0)) return PSVD_E_INVAL;
     if (ldu < h->M) return fail(h, PSVD_E_SHAPE, "ldu < M");
     if (dtype != PSVD_F32 && dtype != PSVD_F64) return fail(h, PSVD_E_DTYPE, "unknown dtype");
+    if (int rc = sync_async(h)) return rc;
     if (h->r == 0) return PSVD_OK;
     if (dtype == h->u_dtype) {
         int esz = dtype == PSVD_F64 ? 8 : 4;
@@ -957,6 +969,177 @@ int psvd_modes(const psvd_handle* hc, void* U, int64_t ldu, int32_t dtype) {
     HIPCHK(h, hipStreamSynchronize(h->stream));
     tmp.release();
     return rc;
+}
+
+}  // extern "C"
+
+
+// ----------------------------------------------------------------------------
+// One-shot randomized SVD and checkpoints of the streaming state.
+// ----------------------------------------------------------------------------
+namespace {
+
+// V[i, j] = VS[i, j] / s[j] (0 where s[j] == 0), converted to the output type.
+__global__ void k_div_cols(const double* VS, int64_t n, int r, const double* s, void* V, int64_t ldv, int32_t dt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * r) return;
+    const int64_t i = e % n;
+    const int j = (int)(e / n);
+    const double v = s[j] > 0.0 ? VS[e] / s[j] : 0.0;
+    if (dt == PSVD_F64) ((double*)V)[i + (size_t)j * ldv] = v;
+    else ((float*)V)[i + (size_t)j * ldv] = (float)v;
+}
+
+constexpr char kStateMagic[8] = {'P', 'S', 'V', 'D', 'S', 'T', '0', '1'};
+
+struct StateHeader {
+    char magic[8];
+    int64_t M;
+    int32_t K, r;
+    double ff;
+    int32_t p, q, ell, u_dtype;
+    int64_t batch;
+    int32_t method, precision;
+    uint64_t seed;
+    int64_t payload;   // bytes after the header: K doubles (s) + r columns of M (U)
+};
+
+}  // namespace
+
+extern "C" {
+
+int psvd_rsvd(const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype, int32_t K, int32_t oversampling,
+              int32_t power_iters, uint64_t seed, int32_t precision, void* U, int64_t ldu, void* V, int64_t ldv,
+              int32_t out_dtype, double* s, int32_t* rank, void* stream) {
+    g_call_err.clear();
+    auto bad = [](int code, const char* msg) {
+        g_call_err = std::string(status_name(code)) + ": " + msg;
+        return code;
+    };
+    if (!A || M < 1 || N < 1 || K < 1 || K > std::min<int64_t>(M, N) || oversampling < 0 || power_iters < 0)
+        return bad(PSVD_E_INVAL, "invalid sizes or null data");
+    if (lda < M || (U && ldu < M) || (V && ldv < N)) return bad(PSVD_E_SHAPE, "leading dimension too small");
+    if (out_dtype != PSVD_F32 && out_dtype != PSVD_F64) return bad(PSVD_E_DTYPE, "unknown output dtype");
+    psvd_options o;
+    psvd_default_options(&o);
+    o.method = PSVD_RANDOMIZED;
+    o.precision = precision;
+    o.seed = seed;
+    o.stream = stream;
+    psvd_handle* h = nullptr;
+    int rc = psvd_initialize(&h, M, K, 1.0, oversampling, power_iters, &o);
+    if (rc) return bad(rc, "initialisation failed");
+    auto finish = [&](int code) {
+        if (code) g_call_err = h->err;
+        psvd_finalize(h);
+        return code;
+    };
+    rc = psvd_incorporate_data(h, A, M, N, lda, a_dtype);
+    if (rc) return finish(rc);
+    const int r = h->r;
+    if (rank) *rank = r;
+    if (U) {
+        rc = psvd_modes(h, U, ldu, out_dtype);
+        if (rc) return finish(rc);
+    }
+    if (V) {
+        // V_K = A^T U_K diag(1 / s): the right factor of Eqs. (9)-(11), since
+        // A^T Q U~ = B^T U~ = V~ S for B = Q^T A.
+        PanelSeg L = make_seg(M);
+        seg_add(L, make_block(A, lda, a_dtype, (int)N));
+        PanelSeg R = make_seg(M);
+        seg_add(R, make_block(h->U[h->cur].p, h->ldu, h->u_dtype, r));
+        DevBuf vs;
+        struct Release {
+            DevBuf& b;
+            ~Release() { b.release(); }
+        } release_vs{vs};
+        if (vs.ensure((size_t)N * r * sizeof(double)) != hipSuccess) return finish(fail(h, PSVD_E_NOMEM, "V workspace"));
+        const size_t need = (size_t)(2048 + 2 * (size_t)ceil_div((int)N, 64) * ceil_div(r, 64)) * 64 * 64 * sizeof(double);
+        if (h->part.ensure(need) != hipSuccess) return finish(fail(h, PSVD_E_NOMEM, "partials"));
+        rc = tn_product(h, L, R, false, precision == PSVD_PREC_FP64, vs.as<double>(), nullptr, 0, nullptr, 0);
+        if (rc) return finish(rc);
+        const int64_t tot = N * r;
+        hipLaunchKernelGGL(k_div_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream, vs.as<double>(), N,
+                           r, h->s[h->cur].as<double>(), V, ldv, out_dtype);
+        if (hipGetLastError() != hipSuccess) return finish(fail(h, PSVD_E_DEVICE, "V scaling launch"));
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return finish(fail(h, PSVD_E_DEVICE, "V scaling"));
+    }
+    if (s) {
+        rc = psvd_singular_values(h, s, K, nullptr);
+        if (rc) return finish(rc);
+    }
+    return finish(PSVD_OK);
+}
+
+int psvd_save_state(const psvd_handle* hc, void* buf, size_t cap, size_t* size) {
+    psvd_handle* h = const_cast<psvd_handle*>(hc);
+    if (!h) return PSVD_E_INVAL;
+    const int esz = h->u_dtype == PSVD_F64 ? 8 : 4;
+    const size_t payload = (size_t)h->K * sizeof(double) + (size_t)h->r * h->M * esz;
+    const size_t total = sizeof(StateHeader) + payload;
+    if (size) *size = total;
+    if (!buf) return PSVD_OK;
+    if (int rc = sync_async(h)) return rc;
+    if (cap < total) return fail(h, PSVD_E_INVAL, "buffer smaller than the state");
+    StateHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    std::memcpy(hd.magic, kStateMagic, 8);
+    hd.M = h->M;
+    hd.K = h->K;
+    hd.r = h->r;
+    hd.ff = h->ff;
+    hd.p = h->p;
+    hd.q = h->q;
+    hd.ell = h->ell;
+    hd.u_dtype = h->u_dtype;
+    hd.batch = h->batch;
+    hd.method = h->opt.method;
+    hd.precision = h->opt.precision;
+    hd.seed = h->opt.seed;
+    hd.payload = (int64_t)payload;
+    char* out = (char*)buf;
+    std::memcpy(out, &hd, sizeof(hd));
+    double* sv = (double*)(out + sizeof(hd));
+    std::memset(sv, 0, (size_t)h->K * sizeof(double));
+    if (h->r > 0) {
+        HIPCHK(h, hipMemcpyAsync(sv, h->s[h->cur].p, (size_t)h->r * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpy2DAsync(out + sizeof(hd) + (size_t)h->K * sizeof(double), (size_t)h->M * esz, h->U[h->cur].p,
+                                   (size_t)h->ldu * esz, (size_t)h->M * esz, h->r, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return PSVD_OK;
+}
+
+int psvd_load_state(psvd_handle* h, const void* buf, size_t size) {
+    if (!h || !buf) return PSVD_E_INVAL;
+    h->err.clear();
+    StateHeader hd;
+    if (size < sizeof(hd)) return fail(h, PSVD_E_INVAL, "buffer shorter than the state header");
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (std::memcmp(hd.magic, kStateMagic, 8) != 0) return fail(h, PSVD_E_INVAL, "not a state buffer");
+    if (hd.M != h->M || hd.K != h->K || hd.ff != h->ff || hd.p != h->p || hd.q != h->q || hd.ell != h->ell ||
+        hd.u_dtype != h->u_dtype || hd.method != h->opt.method || hd.precision != h->opt.precision ||
+        hd.seed != h->opt.seed)
+        return fail(h, PSVD_E_STATE, "state saved with a different configuration");
+    const int esz = h->u_dtype == PSVD_F64 ? 8 : 4;
+    if (hd.r < 0 || hd.r > h->K || hd.batch < 0) return fail(h, PSVD_E_INVAL, "corrupt state header");
+    const size_t payload = (size_t)h->K * sizeof(double) + (size_t)hd.r * h->M * esz;
+    if ((size_t)hd.payload != payload || size < sizeof(hd) + payload) return fail(h, PSVD_E_INVAL, "truncated state");
+    const char* in = (const char*)buf + sizeof(hd);
+    // write into the idle buffer pair, then make it current (the state changes only on success)
+    const int nxt = 1 - h->cur;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (hd.r > 0) {
+        HIPCHK(h, hipMemcpyAsync(h->s[nxt].p, in, (size_t)hd.r * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpy2DAsync(h->U[nxt].p, (size_t)h->ldu * esz, in + (size_t)h->K * sizeof(double),
+                                   (size_t)h->M * esz, (size_t)h->M * esz, hd.r, hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->cur = nxt;
+    h->r = hd.r;
+    h->batch = hd.batch;
+    return PSVD_OK;
 }
 
 }  // extern "C"

@@ -25,41 +25,38 @@ __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
 // ---------------------------------------------------------------------------
 // Cholesky, in place on the upper triangle: A = R^T R, R upper.
-// Returns false (uniformly) on a non-positive or non-finite pivot.
+// Right-looking with one barrier per column: step k updates the trailing
+// block (a_ij -= a_ki a_kj / a_kk, k < i <= j) from the still unscaled row k,
+// and scales row k - 1 (which no thread reads in that step).  Threads form a
+// 32 x (blockDim / 32) grid over (i, j).  Returns false (uniformly) on a
+// non-positive or non-finite pivot; A is then partially overwritten.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool wg_chol_upper(double* A, int n, int lda, int* sflag) {
-    // Right-looking, one barrier per column: every thread recomputes
-    // r_kk = sqrt(a_kk) and scales the row-k entries it reads, the thread that
-    // owns (k, j) stores r_kj, and the trailing (i, j) entries are updated in
-    // the same step (a_ij -= a_ki a_kj / a_kk).
+__device__ __forceinline__ bool wg_chol_upper(double* A, int n, int lda) {
     const int tid = threadIdx.x;
-    if (tid == 0) *sflag = 0;
-    __syncthreads();
+    const int ti = tid & 31, tj = tid >> 5, TJ = blockDim.x >> 5;
+    double d_prev = 1.0;
     for (int k = 0; k < n; ++k) {
         const double d = A[k + (size_t)k * lda];
         if (!(d > 0.0) || !finite_d(d)) {
-            if (tid == 0) *sflag = 1;
             __syncthreads();
             return false;
         }
-        const double rkk = sqrt(d);
-        const double inv = 1.0 / rkk;
-        const int m = n - k;            // columns k .. n-1 of row k, and the trailing block
-        // trailing block (k < i <= j) and row k (i == k) in one sweep over (i, j), i, j >= k
-        for (int e = tid; e < m * m; e += blockDim.x) {
-            const int i = k + e % m, j = k + e / m;
-            if (i > j) continue;
-            if (i == k) continue;   // row k is written after the barrier (still read here)
-            A[i + (size_t)j * lda] -= A[k + (size_t)i * lda] * A[k + (size_t)j * lda] * (inv * inv);
+        if (k > 0) {
+            const double rp = sqrt(d_prev), ip = 1.0 / rp;
+            for (int j = k - 1 + tid; j < n; j += blockDim.x)
+                A[(k - 1) + (size_t)j * lda] = (j == k - 1) ? rp : A[(k - 1) + (size_t)j * lda] * ip;
+        }
+        const double invd = 1.0 / d;
+        for (int j = k + 1 + tj; j < n; j += TJ) {
+            const double akj = A[k + (size_t)j * lda] * invd;
+            for (int i = k + 1 + ti; i <= j; i += 32) A[i + (size_t)j * lda] -= A[k + (size_t)i * lda] * akj;
         }
         __syncthreads();
-        for (int j = k + tid; j < n; j += blockDim.x) A[k + (size_t)j * lda] = (j == k) ? rkk : A[k + (size_t)j * lda] * inv;
-        __syncthreads();
+        d_prev = d;
     }
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int i = e % n, j = e / n;
-        if (i > j) A[i + (size_t)j * lda] = 0.0;
-    }
+    if (tid == 0 && n > 0) A[(n - 1) + (size_t)(n - 1) * lda] = sqrt(d_prev);
+    for (int j = tj; j < n; j += TJ)
+        for (int i = j + 1 + ti; i < n; i += 32) A[i + (size_t)j * lda] = 0.0;
     __syncthreads();
     return true;
 }
@@ -93,9 +90,92 @@ __device__ __forceinline__ void wg_trsm_upper(const double* R, int ldr, int n, c
     }
 }
 
-// Ri = R^-1 for upper triangular R (n x n).
-__device__ __forceinline__ void wg_trinv_upper(const double* R, int n, int ldr, double* Ri, int ldi) {
-    wg_trsm_upper(R, ldr, n, nullptr, 0, Ri, ldi, n);
+// Sum over the 16 lanes of a row (quarter-wave) by DPP row rotations (8, 4,
+// 2, 1): every lane ends with the same value (each step adds the same two
+// partial sums on both lanes of a pair).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double q16_sum(double v) {
+    v += dpp_d<0x128>(v);   // row_ror:8
+    v += dpp_d<0x124>(v);   // row_ror:4
+    v += dpp_d<0x122>(v);   // row_ror:2
+    v += dpp_d<0x121>(v);   // row_ror:1
+    return v;
+}
+
+// Ri = R^-1 for upper triangular R (n x n); one quarter-wave per column j
+// runs the back substitution R x = e_j (rows j .. 0), the partial sums of
+// each row split over its 16 lanes.  Every lane stores the (identical) x_i,
+// so each later read is of a value the reading lane wrote itself.
+// rinv: n doubles of scratch.  R, Ri, rinv distinct.
+__device__ __forceinline__ void wg_trinv_upper(const double* R, int n, int ldr, double* Ri, int ldi, double* rinv) {
+    const int tid = threadIdx.x, ql = tid & 15, qw = tid >> 4, nq = blockDim.x >> 4;
+    for (int i = tid; i < n; i += blockDim.x) rinv[i] = 1.0 / R[i + (size_t)i * ldr];
+    __syncthreads();
+    for (int j = qw; j < n; j += nq) {
+        double* x = Ri + (size_t)j * ldi;
+        for (int i = j + 1 + ql; i < n; i += 16) x[i] = 0.0;
+        for (int i = j; i >= 0; --i) {
+            double s = 0.0;
+            for (int k = i + 1 + ql; k <= j; k += 16) s += R[i + (size_t)k * ldr] * x[k];
+            s = q16_sum(s);
+            x[i] = ((i == j ? 1.0 : 0.0) - s) * rinv[i];
+        }
+    }
+    __syncthreads();
+}
+
+// C = op(A) B over one work-group on the FP64 16x16x4 matrix cores.
+// op(A)(i, k) = A[i * a_i + k * a_k];  B(k, j) = B[k * b_k + j * b_j];
+// C(i, j) -> C[i * c_i + j * c_j], multiplied by rs[i] for i < nrs when rs is
+// given.  16 x 16 output tiles are dealt to the waves round-robin; the sum
+// over k runs in a fixed order (two interleaved accumulators, added last).
+// Operands may live in LDS or global memory; C must not alias them.
+__device__ __noinline__ void wg_gemm_f64(int m, int n, int k, const double* A, int a_i, int a_k, const double* B,
+                                         int b_k, int b_j, double* C, int c_i, int c_j, const double* rs, int nrs) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int mt = (m + 15) >> 4, nt = (n + 15) >> 4;
+    const int kl = lane >> 4;
+    for (int t = w; t < mt * nt; t += nw) {
+        const int ib = t % mt, jb = t / mt;
+        const int i = ib * 16 + (lane & 15), j = jb * 16 + (lane & 15);
+        const int ic = i < m ? i : m - 1, jc = j < n ? j : n - 1;
+        d4_t acc0 = d4_t{0.0, 0.0, 0.0, 0.0}, acc1 = d4_t{0.0, 0.0, 0.0, 0.0};
+        // KU k-steps of 4 per batch: all their loads are issued before the matrix-core work
+        constexpr int KU = 16;
+        for (int k0 = 0; k0 < k; k0 += 4 * KU) {
+            double av[KU], bv[KU];
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int kk = k0 + 4 * u + kl;
+                const int kc = kk < k ? kk : k - 1;
+                av[u] = A[(size_t)ic * a_i + (size_t)kc * a_k];
+                bv[u] = B[(size_t)kc * b_k + (size_t)jc * b_j];
+            }
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int kk = k0 + 4 * u + kl;
+                const double a0 = (i < m && kk < k) ? av[u] : 0.0;
+                const double b0 = (j < n && kk < k) ? bv[u] : 0.0;
+                if (u & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc1, 0, 0, 0);
+                else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = ib * 16 + kl + 4 * v, col = jb * 16 + (lane & 15);
+            if (row < m && col < n) {
+                double x = acc0[v] + acc1[v];
+                if (rs && row < nrs) x *= rs[row];
+                C[(size_t)row * c_i + (size_t)col * c_j] = x;
+            }
+        }
+    }
+    __syncthreads();
 }
 
 // C (m x n) = A (m x k) * B (k x n); all column-major, parallel over outputs.
@@ -118,12 +198,6 @@ __device__ void wg_gemm_nn(int m, int n, int k, const double* A, int lda, const 
 // round rotates n/2 disjoint pairs, one pair per wave at a time.
 // Returns the number of sweeps (> max_sweeps: not converged).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double q16_sum(double v) {
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
-    return v;
-}
-
 __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* order, double* nrm,
                                          int max_sweeps, int* sflag) {
     // One pair per quarter-wave (16 lanes): a round of n/2 disjoint pairs runs
@@ -159,19 +233,46 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
                 if (q >= n) continue;
                 double* zp = Z + (size_t)p * ldz;
                 double* zq = Z + (size_t)q * ldz;
+                // columns of at most 64 rows stay in registers (4 entries per lane)
+                double xp[4], xq[4];
                 double g = 0.0;
-                for (int i = ql; i < m; i += 16) g += zp[i] * zq[i];
+                if (m <= 64) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = ql + 16 * u;
+                        const int ic = i < m ? i : m - 1;
+                        xp[u] = zp[ic];
+                        xq[u] = zq[ic];
+                        if (i >= m) xp[u] = xq[u] = 0.0;
+                        g += xp[u] * xq[u];
+                    }
+                } else {
+                    for (int i = ql; i < m; i += 16) g += zp[i] * zq[i];
+                }
                 g = q16_sum(g);
                 const double al = nrm[p], be = nrm[q];
                 if (!(al > negl) || !(be > negl)) continue;
                 if (fabs(g) <= tol * sqrt(al) * sqrt(be)) continue;
-                const double zeta = (be - al) / (2.0 * g);
-                const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-                for (int i = ql; i < m; i += 16) {
-                    const double a = zp[i], b = zq[i];
-                    zp[i] = c * a - s * b;
-                    zq[i] = s * a + c * b;
+                // tan of the rotation angle, |angle| <= pi/4:
+                //   t = sign(be - al) 2 g / (|be - al| + sqrt((be - al)^2 + 4 g^2))
+                const double dif = be - al;
+                const double tt = (dif >= 0.0 ? 2.0 * g : -2.0 * g) / (fabs(dif) + sqrt(dif * dif + 4.0 * g * g));
+                const double c = rsqrt(1.0 + tt * tt), s = c * tt;
+                if (m <= 64) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = ql + 16 * u;
+                        if (i < m) {
+                            zp[i] = c * xp[u] - s * xq[u];
+                            zq[i] = s * xp[u] + c * xq[u];
+                        }
+                    }
+                } else {
+                    for (int i = ql; i < m; i += 16) {
+                        const double a = zp[i], b = zq[i];
+                        zp[i] = c * a - s * b;
+                        zq[i] = s * a + c * b;
+                    }
                 }
                 if (ql == 0) {
                     nrm[p] = al - tt * g;
@@ -302,11 +403,11 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
         if (tid == 0) *a.status |= DEV_NONFINITE;
         return;
     }
-    bool ok = wg_chol_upper(W, n, n, &sflag);
+    bool ok = wg_chol_upper(W, n, n);
     if (ok) {
         stage_out(W, a.R1, n, in_lds);
         double* X = (n <= SM_LDS_TWO_N) ? lds + (size_t)n * n : a.Ri;
-        wg_trinv_upper(in_lds ? W : a.R1, n, n, X, n);
+        wg_trinv_upper(in_lds ? W : a.R1, n, n, X, n, in_lds ? lds_vecs(lds, n) : a.vec);
         // Ri and Xn = D R1^-1
         for (int e = tid; e < n * n; e += SM_THREADS) {
             const double v = X[e];
@@ -362,7 +463,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
     const int n = a.n, tid = threadIdx.x;
     constexpr bool in_lds = IN_LDS;
     double* W = stage_in(lds, a.G2, n, in_lds);
-    bool ok = wg_chol_upper(W, n, n, &sflag);
+    bool ok = wg_chol_upper(W, n, n);
     if (!ok) {
         // Q1 is orthonormal to working accuracy once the first factor exists;
         // a breakdown here means non-finite data.
@@ -414,90 +515,101 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Randomized-path small kernels.
+// Randomized-path small kernels (one work-group each; P, n x l, is the
+// projection C^T Y or D C'^T (C' X) summed by the fused pass).
 // ---------------------------------------------------------------------------
 
-// R = chol(H) (R overwrites H), Ri = R^-1.  On breakdown a diagonal shift
-// s = 11 (l^2 + l) 2^-53 ||H||_F (shifted Cholesky-QR of Fukaya et al. 2020)
-// is added and the factorisation repeated.
-template <bool IN_LDS>
-__global__ __launch_bounds__(256) void k_small_chol(CholArgs a) {
-    extern __shared__ double lds[];
-    __shared__ int sflag;
-    __shared__ double fro;
-    const int l = a.l, tid = threadIdx.x;
-    if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
-    constexpr bool in_lds = IN_LDS;
-    double* W = in_lds ? lds : a.Ri;   // global fallback works in Ri and keeps H for the retry
-    for (int e = tid; e < l * l; e += blockDim.x) W[e] = a.H[e];
+// Cholesky of the l x l Gram G (in LDS or global scratch W, copied from Gsrc)
+// with the shifted retry of Fukaya et al. 2020 on breakdown: shift
+// 11 (l^2 + l) 2^-53 ||G||_F on the diagonal, flag_bit set in the status.
+// Returns false if the shifted factorisation fails too.
+__device__ bool chol_shifted(const double* Gsrc, double* W, int l, int32_t* status, int flag_bit, double* red) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < l * l; e += blockDim.x) W[e] = Gsrc[e];
     __syncthreads();
-    bool ok = wg_chol_upper(W, l, l, &sflag);
-    if (!ok) {
-        if (tid == 0) {
-            double f = 0.0;
-            for (int e = 0; e < l * l; ++e) f += a.H[e] * a.H[e];
-            fro = sqrt(f);
-            *a.status |= a.flag_bit;
-        }
-        __syncthreads();
-        const double shift = 11.0 * ((double)l * l + l) * 0x1p-53 * fro;
-        for (int e = tid; e < l * l; e += blockDim.x) {
-            const int i = e % l, j = e / l;
-            W[e] = a.H[e] + (i == j ? shift : 0.0);
-        }
-        __syncthreads();
-        ok = wg_chol_upper(W, l, l, &sflag);
-        if (!ok) {
-            if (tid == 0) *a.status |= DEV_NONFINITE;
-            return;
-        }
-    }
-    for (int e = tid; e < l * l; e += blockDim.x) a.H[e] = W[e];
+    if (wg_chol_upper(W, l, l)) return true;
+    // ||G||_F by a fixed-order sum (per-thread partials, then thread 0)
+    double f = 0.0;
+    for (int e = tid; e < l * l; e += blockDim.x) f += Gsrc[e] * Gsrc[e];
+    red[tid] = f;
     __syncthreads();
-    if (l <= SM_LDS_TWO_N) {
-        double* X = lds + (size_t)l * l;
-        wg_trinv_upper(W, l, l, X, l);
-        for (int e = tid; e < l * l; e += blockDim.x) a.Ri[e] = X[e];
-    } else {
-        wg_trinv_upper(in_lds ? W : a.H, l, l, a.Ri, l);
+    if (tid == 0) {
+        double t = 0.0;
+        for (int q = 0; q < (int)blockDim.x; ++q) t += red[q];
+        red[0] = sqrt(t);
+        *status |= flag_bit;
     }
+    __syncthreads();
+    const double shift = 11.0 * ((double)l * l + l) * 0x1p-53 * red[0];
+    __syncthreads();
+    for (int e = tid; e < l * l; e += blockDim.x) {
+        const int i = e % l, j = e / l;
+        W[e] = Gsrc[e] + (i == j ? shift : 0.0);
+    }
+    __syncthreads();
+    return wg_chol_upper(W, l, l);
 }
 
-// R_P = chol(H2) R1 (QR factor of P); R_b = R_P R_Y^-1; the left singular
-// vectors of B = R_Y^-T P^T are those of R_b^T: one-sided Jacobi on R_b^T.
+// Power-iteration re-orthonormalisation X = D P R^-1 with R = chol(P^T P).
+template <bool IN_LDS>
+__global__ __launch_bounds__(SM_THREADS) void k_small_orth(OrthArgs a) {
+    extern __shared__ double lds[];
+    __shared__ double red[SM_THREADS];
+    if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
+    const int l = a.l, n = a.n;
+    constexpr bool in_lds = IN_LDS;
+    double* R = in_lds ? lds : a.R;
+    double* Ri = in_lds ? lds + (size_t)l * l : a.Ri;
+    double* rinv = in_lds ? lds + 2 * (size_t)l * l : a.vec;
+    // G = P^T P (global scratch, kept for the shifted retry)
+    wg_gemm_f64(l, l, n, a.P, n, 1, a.P, 1, n, a.G, 1, l, nullptr, 0);
+    if (!chol_shifted(a.G, R, l, a.status, a.flag_bit, red)) {
+        if (threadIdx.x == 0) *a.status |= DEV_NONFINITE;
+        return;
+    }
+    wg_trinv_upper(R, l, l, Ri, l, rinv);
+    wg_gemm_f64(n, l, l, a.P, 1, n, Ri, 1, l, a.X, 1, n, a.d, a.r);
+}
+
+// Everything after the final pass:
+//   R_Y = chol(G_Y), R_Y^-1;  Cholesky-QR2 of P: R1 = chol(P^T P),
+//   P1 = P R1^-1, R2 = chol(P1^T P1), R_P = R2 R1;  R_b = R_P R_Y^-1;
+//   one-sided Jacobi on R_b^T -> U~ (left singular vectors of B = Q^T C),
+//   S;  sort, sign rule, keep rk = min(K, l);  M2 = R_Y^-1 U~_rk.
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a) {
     extern __shared__ double lds[];
+    __shared__ double red[SM_THREADS];
     __shared__ int sflag;
     if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
-    const int l = a.l, tid = threadIdx.x;
+    const int l = a.l, n = a.n, tid = threadIdx.x;
     constexpr bool in_lds = IN_LDS;
-    double* W = stage_in(lds, a.H2, l, in_lds);
-    bool ok = wg_chol_upper(W, l, l, &sflag);          // R2
-    if (!ok) {
+    double* W = in_lds ? lds : a.W;                      // working l x l
+    double* V = in_lds ? lds + (size_t)l * l : a.V;      // second l x l
+    double* vec = in_lds ? lds + 2 * (size_t)l * l : a.vec;   // 2 l doubles + l ints
+    auto bail = [&]() {
         if (tid == 0) *a.status |= DEV_NONFINITE;
-        return;
-    }
-    // Z = R_P = R2 R1 (upper)
-    for (int e = tid; e < l * l; e += SM_THREADS) {
-        const int i = e % l, j = e / l;
-        double s = 0.0;
-        for (int k = i; k <= j; ++k) s += W[i + (size_t)k * l] * a.R1[k + (size_t)j * l];
-        a.Z[e] = i <= j ? s : 0.0;
-    }
-    __syncthreads();
-    // W = R_b^T with R_b = R_P R_Y^-1
-    for (int e = tid; e < l * l; e += SM_THREADS) {
-        const int i = e % l, j = e / l;
-        double s = 0.0;
-        for (int k = i; k <= j; ++k) s += a.Z[i + (size_t)k * l] * a.RYi[k + (size_t)j * l];
-        W[j + (size_t)i * l] = i <= j ? s : 0.0;
-    }
-    __syncthreads();
-    double* sig = in_lds ? lds_vecs(lds, l) : a.vec;
+    };
+    // R_Y and R_Y^-1
+    if (!chol_shifted(a.GY, W, l, a.status, DEV_FALLBACK, red)) return bail();
+    for (int e = tid; e < l * l; e += SM_THREADS) a.RY[e] = W[e];
+    wg_trinv_upper(W, l, l, a.RYi, l, vec);
+    // R1 = chol(P^T P), R1^-1, P1 = P R1^-1
+    wg_gemm_f64(l, l, n, a.P, n, 1, a.P, 1, n, a.G1, 1, l, nullptr, 0);
+    if (!chol_shifted(a.G1, W, l, a.status, DEV_FALLBACK, red)) return bail();
+    for (int e = tid; e < l * l; e += SM_THREADS) a.R1[e] = W[e];
+    wg_trinv_upper(W, l, l, V, l, vec);
+    wg_gemm_f64(n, l, l, a.P, 1, n, V, 1, l, a.P1, 1, n, nullptr, 0);
+    // R2 = chol(P1^T P1)
+    wg_gemm_f64(l, l, n, a.P1, n, 1, a.P1, 1, n, W, 1, l, nullptr, 0);
+    if (!wg_chol_upper(W, l, l)) return bail();
+    // R_P = R2 R1 -> V;  W = R_b^T = (R_P R_Y^-1)^T
+    wg_gemm_f64(l, l, l, W, 1, l, a.R1, 1, l, V, 1, l, nullptr, 0);
+    wg_gemm_f64(l, l, l, V, 1, l, a.RYi, 1, l, W, l, 1, nullptr, 0);
+    double* sig = vec;
     double* nrm = sig + l;
-    int* ord = in_lds ? (int*)(nrm + l) : a.ivec;
-    int sw = wg_jacobi(W, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
+    int* ord = (int*)(nrm + l);
+    const int sw = wg_jacobi(W, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
@@ -510,12 +622,17 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sig[ord[j]];
     __syncthreads();
     wg_sign_rule(a.small_u, l, rk, l, nullptr);
-    // M2 = R_Y^-1 U~_rk
-    for (int e = tid; e < l * rk; e += SM_THREADS) {
-        const int i = e % l, j = e / l;
-        double s = 0.0;
-        for (int k = i; k < l; ++k) s += a.RYi[i + (size_t)k * l] * a.small_u[k + (size_t)j * l];
-        a.M2[i + (size_t)j * l] = s;
+    wg_gemm_f64(l, rk, l, a.RYi, 1, l, a.small_u, 1, l, a.M2, 1, l, nullptr, 0);
+}
+
+// Asynchronous updates: fold the status word of the update into the sticky
+// word read at the next synchronising call (st[2] errors, st[3] sweeps of the
+// last small SVD, st[4] count of Cholesky fallbacks).
+__global__ void k_status_fold(int32_t* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st[2] |= st[0] & ~(int32_t)DEV_FALLBACK;
+        st[3] = st[1];
+        if (st[0] & DEV_FALLBACK) st[4] += 1;
     }
 }
 
@@ -626,24 +743,32 @@ hipError_t launch_small_det2(const SmallArgs& a, hipStream_t st) {
     else hipLaunchKernelGGL(k_small_det2<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
-hipError_t launch_small_chol(const CholArgs& a, hipStream_t st) {
-    size_t lds = small_lds_bytes(a.l);
-    const bool in_lds = (a.l) <= SM_LDS_MAX_N;
-    const void* fn = in_lds ? (const void*)k_small_chol<true> : (const void*)k_small_chol<false>;
+// LDS of the randomized small kernels: two l x l matrices and 3 l vectors.
+static size_t rand_lds_bytes(int l) { return (2 * (size_t)l * l + 3 * (size_t)l + 8) * sizeof(double); }
+static bool rand_in_lds(int l) { return rand_lds_bytes(l) <= 150 * 1024; }
+
+hipError_t launch_small_orth(const OrthArgs& a, hipStream_t st) {
+    const bool in_lds = rand_in_lds(a.l);
+    const size_t lds = in_lds ? rand_lds_bytes(a.l) : 64;
+    const void* fn = in_lds ? (const void*)k_small_orth<true> : (const void*)k_small_orth<false>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    if (in_lds) hipLaunchKernelGGL(k_small_chol<true>, dim3(1), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL(k_small_chol<false>, dim3(1), dim3(256), lds, st, a);
+    if (in_lds) hipLaunchKernelGGL(k_small_orth<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
+    else hipLaunchKernelGGL(k_small_orth<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();
 }
 hipError_t launch_small_rand_final(const RandFinalArgs& a, hipStream_t st) {
-    size_t lds = small_lds_bytes(a.l);
-    const bool in_lds = (a.l) <= SM_LDS_MAX_N;
+    const bool in_lds = rand_in_lds(a.l);
+    const size_t lds = in_lds ? rand_lds_bytes(a.l) : 64;
     const void* fn = in_lds ? (const void*)k_small_rand_final<true> : (const void*)k_small_rand_final<false>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (in_lds) hipLaunchKernelGGL(k_small_rand_final<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
     else hipLaunchKernelGGL(k_small_rand_final<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_status_fold(int32_t* st, hipStream_t stream) {
+    hipLaunchKernelGGL(k_status_fold, dim3(1), dim3(64), 0, stream, st);
     return hipGetLastError();
 }
 hipError_t launch_scale_rows(double* X, int n, int m, int ldx, const double* d, int r, int times, hipStream_t st) {
