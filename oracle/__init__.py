@@ -137,6 +137,17 @@ def matmul_tn(A, B):
     return C
 
 
+def matmul_nn(A, B):
+    """A B with a fixed-order reduction (A: m x k, B: k x n)."""
+    A = _f64(A)
+    B = _f64(B)
+    m, k = A.shape
+    n = B.shape[1]
+    C = np.zeros((m, n), order="F")
+    _load().orc_matmul_nn(m, n, k, _ptr(A), max(m, 1), _ptr(B), max(k, 1), _ptr(C), max(m, 1))
+    return C
+
+
 class StreamOracle:
     """Algorithm 1, one `incorporate(A)` per batch.
 

@@ -129,7 +129,7 @@ extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const i
     size_t o_T = take(sizeof(double) * (size_t)N * K);
     size_t o_Lam = take(sizeof(double) * K);
     size_t o_X = take(sizeof(double) * (size_t)N * K);
-    size_t o_vec = take(sizeof(double) * (size_t)P * 2 * N + 64);
+    size_t o_vec = take(sizeof(double) * (size_t)P * (2 * N + 2) + 64);
     size_t o_ivec = take(sizeof(int32_t) * (size_t)P * N + 64);
     size_t o_stat = take(64);
     size_t o_wwpart = take(sizeof(double) * 2048 * (size_t)mbw * (mbw + 1) / 2 * TN_OB * TN_OB);

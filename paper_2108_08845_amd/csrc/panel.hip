@@ -44,8 +44,29 @@ __device__ __forceinline__ ColRef col_ref(const PanelSeg& s, int c) {
     return r;
 }
 
+// Segment descriptor from a device array, read once through a global view.
+__device__ __forceinline__ PanelSeg load_seg(const PanelSeg* p) {
+    static_assert(sizeof(PanelSeg) % 8 == 0, "PanelSeg is copied in 8-byte words");
+    PanelSeg r;
+    const PSVD_GLOBAL uint64_t* src = (const PSVD_GLOBAL uint64_t*)p;
+    uint64_t* dst = (uint64_t*)&r;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(PanelSeg) / 8); ++i) dst[i] = src[i];
+    return r;
+}
+
 __device__ __forceinline__ WorkItem get_item(const WorkItem* items, int64_t chunk, int64_t rows) {
-    if (items) return items[blockIdx.x];
+    if (items) {
+        static_assert(sizeof(WorkItem) == 24, "WorkItem layout");
+        const PSVD_GLOBAL int64_t* src = (const PSVD_GLOBAL int64_t*)(items + blockIdx.x);
+        WorkItem w;
+        const int64_t s0 = src[0];
+        w.seg = (int32_t)(s0 & 0xFFFFFFFF);
+        w.pad = (int32_t)(s0 >> 32);
+        w.row0 = src[1];
+        w.row1 = src[2];
+        return w;
+    }
     WorkItem w;
     w.seg = 0;
     w.pad = 0;
@@ -55,7 +76,7 @@ __device__ __forceinline__ WorkItem get_item(const WorkItem* items, int64_t chun
 }
 
 __device__ __forceinline__ double ld_col(const ColRef& r, int64_t i) {
-    return r.dtype == PSVD_F64 ? ((const double*)r.base)[i] : (double)((const float*)r.base)[i];
+    return r.dtype == PSVD_F64 ? gldd((const double*)r.base + i) : (double)gld((const float*)r.base + i);
 }
 
 // ----------------------------------------------------------------------------
@@ -76,8 +97,9 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const WorkItem it = get_item(a.items, a.chunk, a.lseg.rows);
-    const PanelSeg& L = a.lsegs ? a.lsegs[it.seg] : a.lseg;
-    const PanelSeg& R = a.rsegs ? a.rsegs[it.seg] : a.rseg;
+    // segment descriptors copied once (global loads), not re-read per element
+    const PanelSeg L = a.lsegs ? load_seg(a.lsegs + it.seg) : a.lseg;
+    const PanelSeg R = a.rsegs ? load_seg(a.rsegs + it.seg) : a.rseg;
     const int ob = blockIdx.y;
     int obi, obj;
     block_coords(ob, a.mbl, a.sym, &obi, &obj);
@@ -184,7 +206,7 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const WorkItem it = get_item(a.items, a.chunk, a.seg.rows);
-    const PanelSeg& S = a.segs ? a.segs[it.seg] : a.seg;
+    const PanelSeg S = a.segs ? load_seg(a.segs + it.seg) : a.seg;
     const int oc0 = blockIdx.y * NN_OB;
     for (int64_t r0 = it.row0; r0 < it.row1; r0 += NN_TM) {
         typename MF::acc acc[4];
@@ -207,7 +229,7 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
                 int idx = e * 256 + tid;
                 int k = idx % NN_KC, j = idx / NN_KC;
                 double v = 0.0;
-                if (k0 + k < a.n && oc0 + j < a.nx) v = a.X[(k0 + k) + (int64_t)(oc0 + j) * a.ldx];
+                if (k0 + k < a.n && oc0 + j < a.nx) v = gldd(a.X + (k0 + k) + (int64_t)(oc0 + j) * a.ldx);
                 Xs[j * (NN_KC + 1) + k] = MF::from_double(v);
             }
             __syncthreads();
@@ -242,10 +264,10 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
                 size_t o = (size_t)row + (size_t)(oc0 + j) * (size_t)S.ldo;
                 if (S.out_dtype == PSVD_F64) {
                     double* po = (double*)S.out + o;
-                    *po = a.accumulate ? *po + v : v;
+                    gstd(po, a.accumulate ? gldd(po) + v : v);
                 } else {
                     float* po = (float*)S.out + o;
-                    *po = a.accumulate ? (float)((double)*po + v) : (float)v;
+                    gst(po, a.accumulate ? (float)((double)gld(po) + v) : (float)v);
                 }
             }
         }
@@ -276,13 +298,41 @@ __device__ __forceinline__ const float* fcol(const PanelSeg& s, int c) {
     return (const float*)p;
 }
 
-// X (FP64, column-major) element (k, j), 0 outside n x lx; the load is
-// unconditional (clamped index) so consecutive loads are not serialised.
+// X (FP64, column-major) element (min(k, n-1), min(j, lx-1)).  Padding rows
+// k >= n only meet panel columns that are zero, and padding columns j >= lx
+// only feed outputs that are never read back (partials beyond lx, Y columns
+// beyond lx), so a clamped copy is as good as zero and the load needs no
+// condition (a conditional load would be issued and waited for one by one).
 __device__ __forceinline__ double x_elem(const FusedArgs& a, int k, int j) {
     const int kk = k < a.n ? k : a.n - 1;
     const int jj = j < a.lx ? j : a.lx - 1;
-    const double v = a.X[kk + (int64_t)jj * a.ldx];
-    return (k < a.n && j < a.lx) ? v : 0.0;
+    return gldd(a.X + kk + (int64_t)jj * a.ldx);
+}
+
+// Stage the column block c0 .. c0 + 63 of X (rows 0 .. NP-1, clamped to
+// n x lx) into LDS: store(k, j, value) for every element, all NT threads
+// loading with eight independent loads in flight each (the loads of a batch
+// are issued before any of them is used).
+template <int NP, int NT, class Store>
+__device__ __forceinline__ void stage_x(const FusedArgs& a, int c0, Store store) {
+    constexpr int PER = FU_LB * NP / NT;
+    static_assert(FU_LB * NP % NT == 0, "X block divisible among the threads");
+#pragma unroll
+    for (int b = 0; b < PER; b += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (b + u < PER) {
+                const int idx = threadIdx.x + (b + u) * NT;
+                v[u] = x_elem(a, idx % NP, c0 + idx / NP);
+            }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (b + u < PER) {
+                const int idx = threadIdx.x + (b + u) * NT;
+                store(idx % NP, idx / NP, v[u]);
+            }
+    }
 }
 
 // Work-group -> (row work-group wg, column block lb).  Consecutive hardware
@@ -333,10 +383,15 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     const int wg = fc.wg, lb = fc.lb;
     const int c0 = lb * FU_LB;
 
-#pragma unroll 8
-    for (int idx = tid; idx < FU_LB * NP; idx += NT) {
-        const int k = idx % NP, j = idx / NP;
-        Xs[j * ldX + k] = (float)x_elem(a, k, c0 + j);
+    stage_x<NP, NT>(a, c0, [&](int k, int j, double v) { Xs[j * ldX + k] = (float)v; });
+    // Phase A of wave w always uses column block w & 3 of X: its B fragments
+    // (one value per k-step) stay in registers when they fit.
+    constexpr bool XREG = NP <= 384 && !(TM == 64 && NP > 128);
+    float xr[XREG ? NP / 4 : 1];
+    if constexpr (XREG) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NP / 4; ++u) xr[u] = Xs[((w & 3) * 16 + (lane & 15)) * ldX + 4 * u + (lane >> 4)];
     }
 
     f4_t accP[MODE == 2 ? 1 : QB * 4];
@@ -366,11 +421,11 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
             if (rr * CPR + tcol < NP) {                      // uniform per wave
                 f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
                 if (full) {
-                    v = *(const f4_t*)(cp[rr] + row);
+                    v = gld4(cp[rr] + row);
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (row + q < rows) v[q] = cp[rr][row + q];
+                        if (row + q < rows) v[q] = gld(cp[rr] + row + q);
                 }
                 pf[rr] = cv[rr] ? v : f4_t{0.f, 0.f, 0.f, 0.f};
             }
@@ -401,7 +456,9 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
                 for (int u = 0; u < 4; ++u) acc4[u] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kk = 0; kk < NP; kk += 4) {
-                    const float bv = Xs[(jb * 16 + (lane & 15)) * ldX + kk + (lane >> 4)];
+                    float bv;
+                    if constexpr (XREG) bv = xr[kk >> 2];
+                    else bv = Xs[(jb * 16 + (lane & 15)) * ldX + kk + (lane >> 4)];
                     const float av = Cs[(kk + (lane >> 4)) * ldC + ib * 16 + (lane & 15)];
                     acc4[(kk >> 2) & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc4[(kk >> 2) & 3], 0, 0, 0);
                 }
@@ -428,11 +485,11 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
                     const f4_t v = *(const f4_t*)&Ys[j * ldY + tsub * 4];
                     float* o = obase + (size_t)(c0 + j) * (size_t)ldo;
                     if (full) {
-                        *(f4_t*)(o + row) = v;
+                        gst4(o + row, v);
                     } else {
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
-                            if (row + q < rows) o[row + q] = v[q];
+                            if (row + q < rows) gst(o + row + q, v[q]);
                     }
                 }
             }
@@ -482,7 +539,7 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
                     for (int v = 0; v < 4; ++v) {
                         const int row = rb * 16 + 4 * (lane >> 4) + v;
                         const int col = j * 16 + (lane & 15);
-                        outP[row + (size_t)col * NP] = accP[q * 4 + j][v];
+                        gst(outP + row + (size_t)col * NP, accP[q * 4 + j][v]);
                     }
             }
         }
@@ -496,7 +553,7 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
             for (int v = 0; v < 4; ++v) {
                 const int row = gi * 16 + Mfma<double>::row_of(lane, v);
                 const int col = (gj0 + j) * 16 + (lane & 15);
-                outG[row + col * FU_LB] = accG[j][v];
+                gstd(outG + row + col * FU_LB, accG[j][v]);
             }
     }
 }
@@ -521,7 +578,9 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
     constexpr int NT = 512;
     constexpr int NP = NKS * 32;
     constexpr int NCG = NP / 4;                     // column groups of 4
-    constexpr int JW = TM / 32;                     // column blocks of Y per wave in phase A
+    // Phase A: (TM/16) x 4 blocks of Y over 8 waves; each wave takes IB row
+    // blocks of one column block (X fragments of that column block in registers).
+    constexpr int IB = TM / 32;                     // row blocks of Y per wave in phase A
     constexpr int RG = TM / 4;                      // row groups of 4
     constexpr int CGR = NT / RG;                    // column groups per round
     constexpr int RMAX = (NCG + CGR - 1) / CGR;
@@ -541,30 +600,37 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
     const int wg = fc.wg, lb = fc.lb;
     const int c0 = lb * FU_LB;
 
-    // Phase-A unit of this wave: row block ib, column blocks jb0 .. jb0 + JW - 1.
-    const int ib = TM == 64 ? (w & 3) : (w & 1);
-    const int jb0 = TM == 64 ? (w >> 2) * 2 : (w >> 1);
-    bf8_t xf[JW][NKS];
+    // Phase-A unit of this wave: row blocks ib0 .. ib0 + IB - 1 of column block jb.
+    const int jb = w & 3;
+    const int ib0 = (w >> 2) * IB;
+    // X block -> LDS as BF16 (the tile buffers are free until the first tile),
+    // then into registers as the B fragments of phase A.
+    bf8_t xf[NKS];
+    {
+        constexpr int ldxs = NP + 8;
+        uint16_t* Xb = Cs;   // 64 x ldxs halfwords fit in the Cs and Cr buffers
+        stage_x<NP, NT>(a, c0, [&](int k, int j, double v) { Xb[j * ldxs + k] = f32_to_bf16_rne((float)v); });
+        __syncthreads();
 #pragma unroll
-    for (int c = 0; c < JW; ++c)
-#pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-            bf8_t v;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int k = ks * 32 + 8 * (lane >> 4) + q;
-                const int j = c0 + (jb0 + c) * 16 + (lane & 15);
-                v[q] = __builtin_bit_cast(__bf16, f32_to_bf16_rne((float)x_elem(a, k, j)));
-            }
-            xf[c][ks] = v;
-        }
+        for (int ks = 0; ks < NKS; ++ks)
+            xf[ks] = lds_b128(&Xb[(jb * 16 + (lane & 15)) * ldxs + ks * 32 + 8 * (lane >> 4)]);
+        __syncthreads();
+    }
 
     f4_t accP[QB * 4];
 #pragma unroll
     for (int t = 0; t < QB * 4; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
 
+    // Thread -> (row group rg, column group cgl).  The 16 lanes of each LDS
+    // store group span 4 row groups x 4 column groups (at most 2-way bank
+    // conflicts on both tile copies); a wave covers all RG row groups of
+    // 64 / RG consecutive column groups, so each float4 load instruction
+    // reads whole TM-row column segments.
+    constexpr int RGH = RG / 4;                       // high row-group values per wave
+    constexpr int RGH_LOG = RGH == 4 ? 2 : (RGH == 2 ? 1 : 0);
+    const int rg = (tid & 3) | (((tid >> 4) & (RGH - 1)) << 2);
+    const int cgl = ((tid >> 2) & 3) | ((tid >> (4 + RGH_LOG)) << 2);
     // Per-thread column pointers: columns (rr * CGR + cgl) * 4 + q.
-    const int rg = tid % RG, cgl = tid / RG;
     const float* cp[RMAX][4];
     bool cv[RMAX][4];
 #pragma unroll
@@ -587,11 +653,11 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
                 for (int q = 0; q < 4; ++q) {
                     f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
                     if (full) {
-                        v = *(const f4_t*)(cp[rr][q] + row);
+                        v = gld4(cp[rr][q] + row);
                     } else {
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            if (row + e < rows) v[e] = cp[rr][q][row + e];
+                            if (row + e < rows) v[e] = gld(cp[rr][q] + row + e);
                     }
                     pf[rr][q] = cv[rr][q] ? v : f4_t{0.f, 0.f, 0.f, 0.f};
                 }
@@ -624,23 +690,25 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
         __syncthreads();
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
 
-        // Phase A: Y_tile = C_tile X (X fragments in registers), two interleaved accumulators.
+        // Phase A: Y_tile = C_tile X (X fragments in registers); for IB == 1 two
+        // interleaved accumulators keep consecutive matrix-core ops independent.
         {
-            f4_t accY[JW][2];
+            f4_t accY[IB][2];
 #pragma unroll
-            for (int c = 0; c < JW; ++c) accY[c][0] = accY[c][1] = f4_t{0.f, 0.f, 0.f, 0.f};
+            for (int b = 0; b < IB; ++b) accY[b][0] = accY[b][1] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < NKS; ++ks) {
-                const bf8_t av = lds_b128(&Cr[(ib * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4)]);
 #pragma unroll
-                for (int c = 0; c < JW; ++c)
-                    accY[c][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[c][ks], accY[c][ks & 1], 0, 0, 0);
+                for (int b = 0; b < IB; ++b) {
+                    const bf8_t av = lds_b128(&Cr[((ib0 + b) * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4)]);
+                    accY[b][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[ks], accY[b][ks & 1], 0, 0, 0);
+                }
             }
 #pragma unroll
-            for (int c = 0; c < JW; ++c) {   // rows ib*16 + 4*(lane/16) .. +3 of column col: one 8-byte store
-                const int col = (jb0 + c) * 16 + (lane & 15);
-                const f4_t y = accY[c][0] + accY[c][1];
-                *(uint64_t*)&Ys[col * ldY + ib * 16 + 4 * (lane >> 4)] =
+            for (int b = 0; b < IB; ++b) {   // rows 4*(lane/16) .. +3 of the block: one 8-byte store
+                const int col = jb * 16 + (lane & 15);
+                const f4_t y = accY[b][0] + accY[b][1];
+                *(uint64_t*)&Ys[col * ldY + (ib0 + b) * 16 + 4 * (lane >> 4)] =
                     (uint64_t)pack_bf16x2(y[0], y[1]) | ((uint64_t)pack_bf16x2(y[2], y[3]) << 32);
             }
         }
@@ -675,7 +743,7 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
                 for (int v = 0; v < 4; ++v) {
                     const int row = rb * 16 + 4 * (lane >> 4) + v;
                     const int col = j * 16 + (lane & 15);
-                    outP[row + (size_t)col * NP] = accP[q * 4 + j][v];
+                    gst(outP + row + (size_t)col * NP, accP[q * 4 + j][v]);
                 }
         }
     }
@@ -700,7 +768,7 @@ static const int kFusedNp[] = {64, 128, 192, 256, 320, 384, 448};
 bool sketch_plan(int n, int tile_rows, FusedPlan* p) {
     for (int nks : kSketchNks) {
         if (nks * 32 < n) continue;
-        int tm = nks <= 6 ? 64 : 32;
+        int tm = nks <= 12 ? 64 : 32;
         if (tile_rows == 32) tm = 32;
         p->np = nks * 32;
         p->tm = tm;
@@ -749,7 +817,7 @@ hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st) {
     if (a.np % 32 || (a.tm != 32 && a.tm != 64)) return hipErrorInvalidValue;
 #define SK(TM_, NKS_) \
     if (a.tm == TM_ && nks == NKS_) return launch_512(k_sketch_bf16<TM_, NKS_>, a, lds, st);
-    SK(64, 2) SK(64, 4) SK(64, 6)
+    SK(64, 2) SK(64, 4) SK(64, 6) SK(64, 8) SK(64, 10) SK(64, 12)
     SK(32, 2) SK(32, 4) SK(32, 6) SK(32, 8) SK(32, 10) SK(32, 12) SK(32, 16) SK(32, 20)
 #undef SK
     return hipErrorInvalidValue;

@@ -34,6 +34,20 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// Global-memory views of generic pointers.  A pointer rebuilt from integers
+// (a column base selected among the blocks of a panel) or passed through a
+// generic parameter loses its address space, and loads through it become
+// FLAT loads, which also count against the LDS wait counter: every wait for
+// an LDS read would then wait for all prefetched tile loads too.  Accesses
+// through these views are plain global loads and stores.
+#define PSVD_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ f4_t gld4(const float* p) { return *(const PSVD_GLOBAL f4_t*)p; }
+__device__ __forceinline__ float gld(const float* p) { return *(const PSVD_GLOBAL float*)p; }
+__device__ __forceinline__ double gldd(const double* p) { return *(const PSVD_GLOBAL double*)p; }
+__device__ __forceinline__ void gst4(float* p, f4_t v) { *(PSVD_GLOBAL f4_t*)p = v; }
+__device__ __forceinline__ void gst(float* p, float v) { *(PSVD_GLOBAL float*)p = v; }
+__device__ __forceinline__ void gstd(double* p, double v) { *(PSVD_GLOBAL double*)p = v; }
+
 // Two FP32 values -> two BF16 (round to nearest even) packed low-first, by
 // the gfx950 packed conversion instruction.
 typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));

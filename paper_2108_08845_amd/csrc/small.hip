@@ -41,15 +41,18 @@ __device__ __forceinline__ bool wg_chol_upper(double* A, int n, int lda) {
             __syncthreads();
             return false;
         }
-        if (k > 0) {
+        if (k > 0 && tid < n - k + 1) {   // scale row k - 1 (one wave for n <= 64)
             const double rp = sqrt(d_prev), ip = 1.0 / rp;
-            for (int j = k - 1 + tid; j < n; j += blockDim.x)
-                A[(k - 1) + (size_t)j * lda] = (j == k - 1) ? rp : A[(k - 1) + (size_t)j * lda] * ip;
+            const int j = k - 1 + tid;
+            A[(k - 1) + (size_t)j * lda] = (j == k - 1) ? rp : A[(k - 1) + (size_t)j * lda] * ip;
+            for (int jj = j + blockDim.x; jj < n; jj += blockDim.x) A[(k - 1) + (size_t)jj * lda] *= ip;
         }
-        const double invd = 1.0 / d;
-        for (int j = k + 1 + tj; j < n; j += TJ) {
-            const double akj = A[k + (size_t)j * lda] * invd;
-            for (int i = k + 1 + ti; i <= j; i += 32) A[i + (size_t)j * lda] -= A[k + (size_t)i * lda] * akj;
+        if (tj < n - k - 1) {             // only threads with trailing work take the reciprocal
+            const double invd = 1.0 / d;
+            for (int j = k + 1 + tj; j < n; j += TJ) {
+                const double akj = A[k + (size_t)j * lda] * invd;
+                for (int i = k + 1 + ti; i <= j; i += 32) A[i + (size_t)j * lda] -= A[k + (size_t)i * lda] * akj;
+            }
         }
         __syncthreads();
         d_prev = d;
@@ -135,7 +138,7 @@ __device__ __forceinline__ void wg_trinv_upper(const double* R, int n, int ldr, 
 // given.  16 x 16 output tiles are dealt to the waves round-robin; the sum
 // over k runs in a fixed order (two interleaved accumulators, added last).
 // Operands may live in LDS or global memory; C must not alias them.
-__device__ __noinline__ void wg_gemm_f64(int m, int n, int k, const double* A, int a_i, int a_k, const double* B,
+__device__ __forceinline__ void wg_gemm_f64(int m, int n, int k, const double* A, int a_i, int a_k, const double* B,
                                          int b_k, int b_j, double* C, int c_i, int c_j, const double* rs, int nrs) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int mt = (m + 15) >> 4, nt = (n + 15) >> 4;
@@ -191,6 +194,135 @@ __device__ void wg_gemm_nn(int m, int n, int k, const double* A, int lda, const 
 }
 
 // ---------------------------------------------------------------------------
+// Products with a tall operand P (n x l, column-major, ld ldp, l <= 64) in
+// global memory, staged through LDS in coalesced chunks of 64 rows
+// (Cn: 64 x 65 doubles, column-major); the next chunk is prefetched into
+// registers while the matrix cores work on the current one.
+// ---------------------------------------------------------------------------
+constexpr int TALL_KC = 64;
+constexpr int TALL_LDC = 65;
+constexpr int TALL_CHUNK = TALL_KC * TALL_LDC;   // doubles of the LDS chunk
+
+struct TallStager {
+    double pre[4];
+    __device__ __forceinline__ void fetch(const double* P, int n, int l, int ldp, int r0) {
+        const int lp = ((l + 15) >> 4) << 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            const int r = e & 63, c = e >> 6;
+            const int rc = r0 + r < n ? r0 + r : n - 1, cc = c < l ? c : l - 1;
+            const double v = gldd(P + rc + (size_t)cc * ldp);
+            pre[q] = (e < TALL_KC * lp && c < l && r0 + r < n) ? v : 0.0;
+        }
+    }
+    __device__ __forceinline__ void store(double* Cn, int l) {
+        const int lp = ((l + 15) >> 4) << 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            if (e < TALL_KC * lp) Cn[(e >> 6) * TALL_LDC + (e & 63)] = pre[q];
+        }
+    }
+};
+
+// G (l x l, ld ldg; may be in LDS) = P^T P.  Upper 16 x 16 tiles, one per
+// wave, mirrored on output.  blockDim.x >= 640 (10 tiles for l <= 64).
+__device__ __forceinline__ void wg_gram_tall(int n, int l, const double* P, int ldp, double* G, int ldg, double* Cn) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int mt = (l + 15) >> 4;
+    const int ntile = mt * (mt + 1) / 2;
+    int t = w, jb = 0;
+    while (t > jb) {
+        t -= jb + 1;
+        ++jb;
+    }
+    const int ib = t;
+    const bool has = w < ntile;
+    d4_t acc0 = d4_t{0.0, 0.0, 0.0, 0.0}, acc1 = d4_t{0.0, 0.0, 0.0, 0.0};
+    TallStager st;
+    st.fetch(P, n, l, ldp, 0);
+    for (int k0 = 0; k0 < n; k0 += TALL_KC) {
+        st.store(Cn, l);
+        __syncthreads();
+        if (k0 + TALL_KC < n) st.fetch(P, n, l, ldp, k0 + TALL_KC);
+        if (has) {
+            const double* ca = Cn + (ib * 16 + (lane & 15)) * TALL_LDC + (lane >> 4);
+            const double* cb = Cn + (jb * 16 + (lane & 15)) * TALL_LDC + (lane >> 4);
+#pragma unroll
+            for (int kk = 0; kk < TALL_KC; kk += 8) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[kk], cb[kk], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[kk + 4], cb[kk + 4], acc1, 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    if (has) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = ib * 16 + (lane >> 4) + 4 * v, col = jb * 16 + (lane & 15);
+            if (row < l && col < l) {
+                const double x = acc0[v] + acc1[v];
+                G[row + (size_t)col * ldg] = x;
+                G[col + (size_t)row * ldg] = x;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// X (n x l, ld ldx, global) = diag(rs) P B with B (l x l, ld ldb) and rows
+// i < nrs scaled by rs[i] (rs may be null).  Wave w: rows 16 (w & 3) of the
+// chunk, columns 16 (w >> 2).  blockDim.x == 1024.
+__device__ __forceinline__ void wg_mul_tall(int n, int l, const double* P, int ldp, const double* B, int ldb, double* X,
+                                         int ldx, const double* rs, int nrs, double* Cn) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int mt = (l + 15) >> 4;
+    const int rb = w & 3, cb = w >> 2;
+    const bool has = cb < mt;
+    // B fragments of this wave's column block, all k-steps (<= 16)
+    double bf[16];
+    {
+        const int j = cb * 16 + (lane & 15);
+        const int jc = j < l ? j : l - 1;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int k = 4 * u + (lane >> 4);
+            const int kc = k < l ? k : l - 1;
+            const double v = B[kc + (size_t)jc * ldb];
+            bf[u] = (has && j < l && k < l) ? v : 0.0;
+        }
+    }
+    TallStager st;
+    st.fetch(P, n, l, ldp, 0);
+    for (int r0 = 0; r0 < n; r0 += TALL_KC) {
+        st.store(Cn, l);
+        __syncthreads();
+        if (r0 + TALL_KC < n) st.fetch(P, n, l, ldp, r0 + TALL_KC);
+        if (has) {
+            d4_t acc0 = d4_t{0.0, 0.0, 0.0, 0.0}, acc1 = d4_t{0.0, 0.0, 0.0, 0.0};
+            const double* ca = Cn + (lane >> 4) * TALL_LDC + rb * 16 + (lane & 15);
+#pragma unroll
+            for (int u = 0; u < 16; u += 2) {
+                if (4 * u < l) acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[(4 * u) * TALL_LDC], bf[u], acc0, 0, 0, 0);
+                if (4 * u + 4 < l)
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[(4 * u + 4) * TALL_LDC], bf[u + 1], acc1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = r0 + rb * 16 + (lane >> 4) + 4 * v, col = cb * 16 + (lane & 15);
+                if (row < n && col < l) {
+                    double x = acc0[v] + acc1[v];
+                    if (rs && row < nrs) x *= rs[row];
+                    X[row + (size_t)col * ldx] = x;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One-sided Jacobi on the columns of Z (m x n, ldz), in place.  On return
 // the columns are mutually orthogonal to the tolerance m * 2^-53; sig[j] =
 // ||z_j|| and z_j /= sig[j] (0 columns stay 0).  order[0..n) lists the
@@ -217,9 +349,15 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
         }
         if (tid == 0) *sflag = 0;
         __syncthreads();
-        double nmax = 0.0;
-        for (int j = 0; j < n; ++j) nmax = fmax(nmax, nrm[j]);
-        const double negl = nmax * tol * tol;
+        if (tid < 64) {   // largest squared norm, by wave 0, broadcast through nrm[n]
+            double mx = 0.0;
+            for (int j = tid; j < n; j += 64) mx = fmax(mx, nrm[j]);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+            if (tid == 0) nrm[n] = mx;
+        }
+        __syncthreads();
+        const double negl = nrm[n] * tol * tol;
         if (sweep >= max_sweeps) {
             ++sweep;
             break;
@@ -227,8 +365,11 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
         for (int t = 0; t < ne - 1; ++t) {
             for (int pi = qw; pi < ne / 2; pi += nq) {
                 const int pa = pi, pb = ne - 1 - pi;
-                const int ca = pa == 0 ? 0 : 1 + (pa - 1 + t) % (ne - 1);
-                const int cb = pb == 0 ? 0 : 1 + (pb - 1 + t) % (ne - 1);
+                int xa = pa - 1 + t, xb = pb - 1 + t;   // (pa - 1 + t) mod (ne - 1), both < 2 (ne - 1)
+                xa -= xa >= ne - 1 ? ne - 1 : 0;
+                xb -= xb >= ne - 1 ? ne - 1 : 0;
+                const int ca = pa == 0 ? 0 : 1 + xa;
+                const int cb = pb == 0 ? 0 : 1 + xb;
                 const int p = ca < cb ? ca : cb, q = ca < cb ? cb : ca;
                 if (q >= n) continue;
                 double* zp = Z + (size_t)p * ldz;
@@ -252,12 +393,15 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
                 g = q16_sum(g);
                 const double al = nrm[p], be = nrm[q];
                 if (!(al > negl) || !(be > negl)) continue;
-                if (fabs(g) <= tol * sqrt(al) * sqrt(be)) continue;
-                // tan of the rotation angle, |angle| <= pi/4:
-                //   t = sign(be - al) 2 g / (|be - al| + sqrt((be - al)^2 + 4 g^2))
+                if (g * g <= (tol * tol) * (al * be)) continue;   // |g| <= tol sqrt(al be)
+                // rotation with |angle| <= pi/4 that makes columns p, q orthogonal:
+                //   u = |be - al| + sqrt((be - al)^2 + 4 g^2),  h = 1 / sqrt(u^2 + 4 g^2),
+                //   c = u h,  s = sign(be - al) 2 g h   (tan = s / c)
                 const double dif = be - al;
-                const double tt = (dif >= 0.0 ? 2.0 * g : -2.0 * g) / (fabs(dif) + sqrt(dif * dif + 4.0 * g * g));
-                const double c = rsqrt(1.0 + tt * tt), s = c * tt;
+                const double ad = fabs(dif);
+                const double uu = ad + sqrt(dif * dif + 4.0 * g * g);
+                const double hh = rsqrt(uu * uu + 4.0 * g * g);
+                const double c = uu * hh, s = (dif >= 0.0 ? 2.0 * g : -2.0 * g) * hh;
                 if (m <= 64) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -274,9 +418,10 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
                         zq[i] = s * a + c * b;
                     }
                 }
-                if (ql == 0) {
-                    nrm[p] = al - tt * g;
-                    nrm[q] = be + tt * g;
+                if (ql == 0) {   // squared norms of the rotated columns
+                    const double cs2g = 2.0 * c * s * g;
+                    nrm[p] = c * c * al + s * s * be - cs2g;
+                    nrm[q] = s * s * al + c * c * be + cs2g;
                     *sflag = 1;
                 }
             }
@@ -428,7 +573,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
     __syncthreads();
     double* sig = in_lds ? lds_vecs(lds, n) : a.vec;
     double* nrm = sig + n;
-    int* ord = in_lds ? (int*)(nrm + n) : a.ivec;
+    int* ord = in_lds ? (int*)(nrm + n + 1) : a.ivec;
     int sw = wg_jacobi(W, n, n, n, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
@@ -491,7 +636,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
     __syncthreads();
     double* sig = in_lds ? lds_vecs(lds, n) : a.vec;
     double* nrm = sig + n;
-    int* ord = in_lds ? (int*)(nrm + n) : a.ivec;
+    int* ord = in_lds ? (int*)(nrm + n + 1) : a.ivec;
     int sw = wg_jacobi(W, n, n, n, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
@@ -550,6 +695,12 @@ __device__ bool chol_shifted(const double* Gsrc, double* W, int l, int32_t* stat
     return wg_chol_upper(W, l, l);
 }
 
+// LDS of the randomized small kernels: two l x l matrices, 3 l + 8 vector
+// entries and, for l <= 64, the chunk of the staged tall products.
+__host__ __device__ inline size_t rand_lds_doubles(int l) {
+    return 2 * (size_t)l * l + 3 * (size_t)l + 8 + (l <= 64 ? TALL_CHUNK : 0);
+}
+
 // Power-iteration re-orthonormalisation X = D P R^-1 with R = chol(P^T P).
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_orth(OrthArgs a) {
@@ -558,17 +709,21 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_orth(OrthArgs a) {
     if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
     const int l = a.l, n = a.n;
     constexpr bool in_lds = IN_LDS;
+    const bool staged = in_lds && l <= 64;
     double* R = in_lds ? lds : a.R;
     double* Ri = in_lds ? lds + (size_t)l * l : a.Ri;
     double* rinv = in_lds ? lds + 2 * (size_t)l * l : a.vec;
+    double* Cn = lds + 2 * (size_t)l * l + 3 * (size_t)l + 8;
     // G = P^T P (global scratch, kept for the shifted retry)
-    wg_gemm_f64(l, l, n, a.P, n, 1, a.P, 1, n, a.G, 1, l, nullptr, 0);
+    if (staged) wg_gram_tall(n, l, a.P, n, a.G, l, Cn);
+    else wg_gemm_f64(l, l, n, a.P, n, 1, a.P, 1, n, a.G, 1, l, nullptr, 0);
     if (!chol_shifted(a.G, R, l, a.status, a.flag_bit, red)) {
         if (threadIdx.x == 0) *a.status |= DEV_NONFINITE;
         return;
     }
     wg_trinv_upper(R, l, l, Ri, l, rinv);
-    wg_gemm_f64(n, l, l, a.P, 1, n, Ri, 1, l, a.X, 1, n, a.d, a.r);
+    if (staged) wg_mul_tall(n, l, a.P, n, Ri, l, a.X, n, a.d, a.r, Cn);
+    else wg_gemm_f64(n, l, l, a.P, 1, n, Ri, 1, l, a.X, 1, n, a.d, a.r);
 }
 
 // Everything after the final pass:
@@ -584,45 +739,68 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
     const int l = a.l, n = a.n, tid = threadIdx.x;
     constexpr bool in_lds = IN_LDS;
+    const bool staged = in_lds && l <= 64;
     double* W = in_lds ? lds : a.W;                      // working l x l
     double* V = in_lds ? lds + (size_t)l * l : a.V;      // second l x l
-    double* vec = in_lds ? lds + 2 * (size_t)l * l : a.vec;   // 2 l doubles + l ints
+    double* vec = in_lds ? lds + 2 * (size_t)l * l : a.vec;   // 2 l + 1 doubles + l ints
+    double* Cn = lds + 2 * (size_t)l * l + 3 * (size_t)l + 8;   // staging chunk (staged only)
+    const int rk = a.K < l ? a.K : l;
     auto bail = [&]() {
         if (tid == 0) *a.status |= DEV_NONFINITE;
     };
-    // R_Y and R_Y^-1
+    // R_Y and R_Y^-1 (V, copied out)
     if (!chol_shifted(a.GY, W, l, a.status, DEV_FALLBACK, red)) return bail();
     for (int e = tid; e < l * l; e += SM_THREADS) a.RY[e] = W[e];
-    wg_trinv_upper(W, l, l, a.RYi, l, vec);
-    // R1 = chol(P^T P), R1^-1, P1 = P R1^-1
-    wg_gemm_f64(l, l, n, a.P, n, 1, a.P, 1, n, a.G1, 1, l, nullptr, 0);
+    wg_trinv_upper(W, l, l, V, l, vec);
+    for (int e = tid; e < l * l; e += SM_THREADS) a.RYi[e] = V[e];
+    // R1 = chol(P^T P), R1^-1 (V), P1 = P R1^-1
+    if (staged) wg_gram_tall(n, l, a.P, n, a.G1, l, Cn);
+    else wg_gemm_f64(l, l, n, a.P, n, 1, a.P, 1, n, a.G1, 1, l, nullptr, 0);
     if (!chol_shifted(a.G1, W, l, a.status, DEV_FALLBACK, red)) return bail();
     for (int e = tid; e < l * l; e += SM_THREADS) a.R1[e] = W[e];
     wg_trinv_upper(W, l, l, V, l, vec);
-    wg_gemm_f64(n, l, l, a.P, 1, n, V, 1, l, a.P1, 1, n, nullptr, 0);
-    // R2 = chol(P1^T P1)
-    wg_gemm_f64(l, l, n, a.P1, n, 1, a.P1, 1, n, W, 1, l, nullptr, 0);
+    if (staged) wg_mul_tall(n, l, a.P, n, V, l, a.P1, n, nullptr, 0, Cn);
+    else wg_gemm_f64(n, l, l, a.P, 1, n, V, 1, l, a.P1, 1, n, nullptr, 0);
+    // R2 = chol(P1^T P1) in W
+    if (staged) wg_gram_tall(n, l, a.P1, n, W, l, Cn);
+    else wg_gemm_f64(l, l, n, a.P1, n, 1, a.P1, 1, n, W, 1, l, nullptr, 0);
     if (!wg_chol_upper(W, l, l)) return bail();
+    // small operands are read from LDS: R1 and then R_Y^-1 go to the chunk buffer
+    const double* R1 = a.R1;
+    const double* RYi = a.RYi;
+    if (staged) {
+        for (int e = tid; e < l * l; e += SM_THREADS) Cn[e] = a.R1[e];
+        __syncthreads();
+        R1 = Cn;
+    }
     // R_P = R2 R1 -> V;  W = R_b^T = (R_P R_Y^-1)^T
-    wg_gemm_f64(l, l, l, W, 1, l, a.R1, 1, l, V, 1, l, nullptr, 0);
-    wg_gemm_f64(l, l, l, V, 1, l, a.RYi, 1, l, W, l, 1, nullptr, 0);
+    wg_gemm_f64(l, l, l, W, 1, l, R1, 1, l, V, 1, l, nullptr, 0);
+    if (staged) {
+        for (int e = tid; e < l * l; e += SM_THREADS) Cn[e] = a.RYi[e];
+        __syncthreads();
+        RYi = Cn;
+    }
+    wg_gemm_f64(l, l, l, V, 1, l, RYi, 1, l, W, l, 1, nullptr, 0);
     double* sig = vec;
     double* nrm = sig + l;
-    int* ord = (int*)(nrm + l);
+    int* ord = (int*)(nrm + l + 1);
     const int sw = wg_jacobi(W, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
     }
-    const int rk = a.K < l ? a.K : l;
+    // U~_rk (sorted, sign rule) -> V (l x rk) and small_u; M2 = R_Y^-1 U~_rk
+    double* Us = in_lds ? V : a.small_u;
     for (int e = tid; e < l * rk; e += SM_THREADS) {
         const int i = e % l, j = e / l;
-        a.small_u[i + (size_t)j * l] = W[i + (size_t)ord[j] * l];
+        Us[i + (size_t)j * l] = W[i + (size_t)ord[j] * l];
     }
     for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sig[ord[j]];
     __syncthreads();
-    wg_sign_rule(a.small_u, l, rk, l, nullptr);
-    wg_gemm_f64(l, rk, l, a.RYi, 1, l, a.small_u, 1, l, a.M2, 1, l, nullptr, 0);
+    wg_sign_rule(Us, l, rk, l, nullptr);
+    if (in_lds)
+        for (int e = tid; e < l * rk; e += SM_THREADS) a.small_u[e] = Us[e];
+    wg_gemm_f64(l, rk, l, RYi, 1, l, Us, 1, l, a.M2, 1, l, nullptr, 0);
 }
 
 // Asynchronous updates: fold the status word of the update into the sticky
@@ -668,9 +846,9 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
     const int i = blockIdx.x, N = a.N, tid = threadIdx.x;
     constexpr bool in_lds = IN_LDS;
     double* G = stage_in(lds, a.G + (size_t)i * N * N, N, in_lds);
-    double* sig = in_lds ? lds_vecs(lds, N) : a.vec + (size_t)i * 2 * N;
+    double* sig = in_lds ? lds_vecs(lds, N) : a.vec + (size_t)i * (2 * N + 2);
     double* nrm = sig + N;
-    int* ord = in_lds ? (int*)(nrm + N) : a.ivec + (size_t)i * N;
+    int* ord = in_lds ? (int*)(nrm + N + 1) : a.ivec + (size_t)i * N;
     int sw = wg_jacobi(G, N, N, N, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0 && sw > a.max_sweeps) atomicOr(a.status, (int)DEV_NOCONV);
     if (tid == 0) atomicMax(a.sweeps, sw);
@@ -696,7 +874,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_global(ApmosGlobalArgs a) 
     double* WW = stage_in(lds, a.WW, N, in_lds);
     double* sig = in_lds ? lds_vecs(lds, N) : a.vec;
     double* nrm = sig + N;
-    int* ordv = in_lds ? (int*)(nrm + N) : a.ivec;
+    int* ordv = in_lds ? (int*)(nrm + N + 1) : a.ivec;
     int sw = wg_jacobi(WW, N, N, N, sig, ordv, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         atomicMax(a.sweeps, sw);
@@ -744,7 +922,7 @@ hipError_t launch_small_det2(const SmallArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 // LDS of the randomized small kernels: two l x l matrices and 3 l vectors.
-static size_t rand_lds_bytes(int l) { return (2 * (size_t)l * l + 3 * (size_t)l + 8) * sizeof(double); }
+static size_t rand_lds_bytes(int l) { return rand_lds_doubles(l) * sizeof(double); }
 static bool rand_in_lds(int l) { return rand_lds_bytes(l) <= 150 * 1024; }
 
 hipError_t launch_small_orth(const OrthArgs& a, hipStream_t st) {

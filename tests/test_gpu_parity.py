@@ -255,3 +255,61 @@ def test_apmos_exact_when_local_rank_fits():
     P = lib()
     U, Lam, X = P.apmos_batched([to_gpu(p) for p in parts], 40, 20)
     assert sigma_rel_err(Lam, sl[:20]) <= 1e-10
+
+
+# ----------------------------------------------------------------------------
+# Full-size cases (the shapes the benchmark runs)
+# ----------------------------------------------------------------------------
+
+def test_c2_full_size_mixed_vs_oracle():
+    # M = 2^20 rows, batches of 256, K = 50, p = 10, q = 2, ff = 0.95: the
+    # initialisation batch and one steady-state update (panel 306 columns),
+    # data generated on the GPU and copied once for the FP64 oracle.
+    w = synth.scaled(synth.c2_randomized_fp32(), batches=2)
+    bs = synth.planted_stream(w, device="cuda")
+    P = lib()
+    svd = P.StreamingSVD(w.M, w.K, ff=w.ff, oversampling=w.oversampling, power_iters=w.power_iters,
+                         randomized=True, precision="mixed", seed=w.seed)
+    for b in bs:
+        svd.incorporate_data(b.t())
+    s = svd.singular_values
+    U = svd.modes.double().cpu().numpy()
+    so = oracle.StreamOracle(w.M, w.K, ff=w.ff, oversampling=w.oversampling, power_iters=w.power_iters,
+                             randomized=True, seed=w.seed, omega_precision=oracle.PREC_BF16)
+    for b in bs:
+        so.incorporate(synth.numpy_cm(b))
+    s_ref = so.singular_values
+    # at 2^20 rows the noise bulk reaches eta sqrt(M) ~ 1e-2, near s_K: only the
+    # leading modes are resolved, and the tolerances apply to those
+    k3, k10 = resolved_modes(s_ref, 3.0), resolved_modes(s_ref, 10.0)
+    assert k10 >= 3
+    assert sigma_rel_err(s[:k3], s_ref[:k3]) <= 2e-3
+    assert sigma_rel_err(s[:k10], s_ref[:k10]) <= 1e-5
+    assert sigma_rel_err(s, s_ref) <= 1e-1
+    # U = Y R_Y^-1 U~_K is lifted in FP32 from a basis Y of condition ~ s_1 / s_l
+    # (about 465 here), so its orthogonality is about eps_32 * 465 per entry.
+    assert orth_err(U) <= 5e-3
+    # the well-separated leading modes span the same subspace as the oracle's
+    k = gap_limited_k(s_ref, 1e-5, k10)
+    if k > 0:
+        assert max_principal_angle(U[:, :k], so.modes[:, :k]) <= 1e-3
+
+
+def test_c4_full_size_apmos_sampled_lift():
+    # 64 partitions of 16384 .. 262144 rows, N = 128, r = K = 20.  The global
+    # factors are checked by their invariants; the lift U_i = A_i X~ diag(1 / Lambda~)
+    # (Eq. (6)) on sampled rows of three partitions against the oracle's product.
+    w = synth.c4_apmos()
+    sizes = synth.partition_sizes(w)
+    parts = synth.apmos_partitions(w, device="cuda", sizes=sizes)
+    P = lib()
+    U, Lam, X = P.apmos_batched([p.t() for p in parts], w.local_rank, w.K)
+    assert np.all(np.diff(Lam) <= 0) and Lam[-1] > 0
+    assert orth_err(X) <= 1e-12
+    rng = np.random.default_rng(0)
+    for i in (0, len(parts) // 2, len(parts) - 1):
+        rows = np.sort(rng.choice(sizes[i], size=64, replace=False))
+        Ai = parts[i].t()[torch.as_tensor(rows, device="cuda")].double().cpu().numpy()     # 64 x N
+        ref = oracle.matmul_nn(Ai, X) / Lam
+        got = U[i][torch.as_tensor(rows, device="cuda")].double().cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref)), i

@@ -413,3 +413,12 @@ def test_gradient_stream_with_forget_factor():
     h = 1e-4
     fd = (oracle.stream_loss(A + h * D, w.K, ff, w.batches, wt)[0] - oracle.stream_loss(A - h * D, w.K, ff, w.batches, wt)[0]) / (2 * h)
     assert abs(fd - np.sum(G * D)) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_matmul_nn_matches_blas():
+    # the oracle's plain triple loop against LAPACK/BLAS-backed numpy (independent implementation)
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((37, 19))
+    B = rng.standard_normal((19, 23))
+    assert np.allclose(oracle.matmul_nn(A, B), A @ B, rtol=0, atol=1e-13)
+    assert np.allclose(oracle.matmul_tn(A, rng.standard_normal((37, 5))).shape, (19, 5))
