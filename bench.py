@@ -141,6 +141,10 @@ def main():
     panel_bytes = w.M * n * 4
     if dom == "fused_bf16":
         roof = {"bound": "hbm", "achieved": panel_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif dom == "fused_f32" and args.precision == "mixed":
+        # split-BF16 final pass: reads the panel, writes the kept sketch Y (M x l FP32)
+        roof = {"bound": "hbm", "achieved": (panel_bytes + w.M * ell * 4) / (avg_ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     elif dom == "fused_f32":
         flops = 4.0 * w.M * n * ell + 2.0 * w.M * ell * ell
         roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS["f32"],

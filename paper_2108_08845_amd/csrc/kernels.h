@@ -212,8 +212,11 @@ struct FusedPlan {
 // BF16 power pass (k_sketch_bf16) / FP32 passes (k_fused) for an n-column
 // panel; tile_rows = 0 picks the default height.  false: no compiled kernel.
 bool sketch_plan(int n, int tile_rows, FusedPlan* p);
-bool fused_plan(int n, int tile_rows, FusedPlan* p);
+bool fused_plan(int n, int tile_rows, FusedPlan* p, bool lift = false);
 hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st);
+// Final pass of the mixed precision with split-BF16 products (one column block).
+bool split_plan(int n, FusedPlan* p);
+hipError_t launch_final_split(const FusedArgs& a, hipStream_t st);
 hipError_t launch_fused(int mode, const FusedArgs& a, hipStream_t st);   // FP32: 0 power, 1 final, 2 lift
 hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st);
 

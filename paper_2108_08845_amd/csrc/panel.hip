@@ -454,13 +454,31 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
                 f4_t acc4[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) acc4[u] = f4_t{0.f, 0.f, 0.f, 0.f};
+                // A fragments in batches of BA k-steps, double-buffered: the reads
+                // of the next batch are in flight while this batch's MFMAs issue.
+                constexpr int NS = NP / 4, BA = 4;
+                float ab[2][BA], xb[2][BA];
+                auto load_a = [&](int buf, int s0) {
 #pragma unroll
-                for (int kk = 0; kk < NP; kk += 4) {
-                    float bv;
-                    if constexpr (XREG) bv = xr[kk >> 2];
-                    else bv = Xs[(jb * 16 + (lane & 15)) * ldX + kk + (lane >> 4)];
-                    const float av = Cs[(kk + (lane >> 4)) * ldC + ib * 16 + (lane & 15)];
-                    acc4[(kk >> 2) & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc4[(kk >> 2) & 3], 0, 0, 0);
+                    for (int u = 0; u < BA; ++u)
+                        if (s0 + u < NS) {
+                            ab[buf][u] = Cs[(4 * (s0 + u) + (lane >> 4)) * ldC + ib * 16 + (lane & 15)];
+                            if constexpr (!XREG) xb[buf][u] = Xs[(jb * 16 + (lane & 15)) * ldX + 4 * (s0 + u) + (lane >> 4)];
+                        }
+                };
+                load_a(0, 0);
+#pragma unroll
+                for (int s0 = 0; s0 < NS; s0 += BA) {
+                    const int cb = (s0 / BA) & 1;
+                    if (s0 + BA < NS) load_a(cb ^ 1, s0 + BA);
+#pragma unroll
+                    for (int u = 0; u < BA; ++u)
+                        if (s0 + u < NS) {
+                            float bv;
+                            if constexpr (XREG) bv = xr[s0 + u];
+                            else bv = xb[cb][u];
+                            acc4[u & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[cb][u], bv, acc4[u & 3], 0, 0, 0);
+                        }
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -496,19 +514,28 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
         }
         if constexpr (MODE != 2) {
             // Phase B: P (NP x 64) += C_tile^T Y_tile; wave w owns row blocks w, w + 8, ...
+            // fragments of k-step s + 1 are read while the MFMAs of k-step s issue
+            float bb[2][4], aa[2][QB];
+            auto load_b = [&](int buf, int k0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bb[buf][j] = Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+#pragma unroll
+                for (int q = 0; q < QB; ++q)
+                    if (w + 8 * q < NRBLK) aa[buf][q] = Cs[((w + 8 * q) * 16 + (lane & 15)) * ldC + k0 + (lane >> 4)];
+            };
+            load_b(0, 0);
 #pragma unroll
             for (int k0 = 0; k0 < TM; k0 += 4) {
-                float bvs[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bvs[j] = Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+                const int cb = (k0 >> 2) & 1;
+                if (k0 + 4 < TM) load_b(cb ^ 1, k0 + 4);
 #pragma unroll
                 for (int q = 0; q < QB; ++q) {
                     const int rb = w + 8 * q;
                     if (rb < NRBLK) {
-                        const float av = Cs[(rb * 16 + (lane & 15)) * ldC + k0 + (lane >> 4)];
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
-                            accP[q * 4 + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bvs[j], accP[q * 4 + j], 0, 0, 0);
+                            accP[q * 4 + j] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(aa[cb][q], bb[cb][j], accP[q * 4 + j], 0, 0, 0);
                     }
                 }
             }
@@ -750,6 +777,253 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// k_final_split: the final pass of the mixed precision with FP32-accurate
+// products from split BF16 operands.  Every FP32 value v is split as
+// v = hi + lo + O(2^-18 |v|) with hi = bf16(v), lo = bf16(v - hi); a product is
+// hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo_a lo_b term is O(2^-18)), three
+// 16x16x32 BF16 MFMAs with FP32 accumulation.  Per tile (32 rows):
+//   Y_tile = C_tile X   (split products; the FP32 result is written to the kept
+//                        copy of Y and split again for the two products below)
+//   P     += C_tile^T Y_tile   (split products)
+//   G     += Y_tile^T Y_tile   (all four hi/lo products, exact in FP32; FP64 across tiles)
+// Loads, LDS copies and the X fragments follow k_sketch_bf16 (hi and lo copies).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t* hi, uint32_t* lo) {
+    const uint32_t h = pack_bf16x2(a, b);
+    const float ha = __uint_as_float(h << 16), hb = __uint_as_float(h & 0xFFFF0000u);
+    *hi = h;
+    *lo = pack_bf16x2(a - ha, b - hb);
+}
+
+template <int NKS>
+__global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
+    constexpr int TM = 32, NT = 512;
+    constexpr int NP = NKS * 32;
+    constexpr int NCG = NP / 4;
+    constexpr int RG = TM / 4;                      // 8 row groups of 4
+    constexpr int CGR = NT / RG;                    // 64 column groups per round
+    constexpr int RMAX = (NCG + CGR - 1) / CGR;
+    constexpr int NRBLK = NP / 16;
+    constexpr int QB = (NRBLK + 7) / 8;
+    constexpr int ldC = TM + 8, ldR = NP + 8, ldY = TM + 8;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* Csh = (uint16_t*)smem;                // NP x TM, column-major (hi)
+    uint16_t* Csl = Csh + NP * ldC;                 //                        (lo)
+    uint16_t* Crh = Csl + NP * ldC;                 // TM x NP, row-major    (hi)
+    uint16_t* Crl = Crh + TM * ldR;                 //                        (lo)
+    uint16_t* Ysh = Crl + TM * ldR;                 // 64 x TM, column-major (hi)
+    uint16_t* Ysl = Ysh + FU_LB * ldY;              //                        (lo)
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const FusedCoords fc = fused_coords(a);
+    if (fc.wg >= a.nwg) return;
+    const int wg = fc.wg, lb = fc.lb;
+    const int c0 = lb * FU_LB;
+    const int jb = w & 3, ib = w >> 2;              // phase-A block of this wave
+
+    // X block -> LDS (FP32, in the tile buffers, free until the first tile),
+    // then the hi / lo B fragments of phase A into registers.
+    bf8_t xh[NKS], xl[NKS];
+    {
+        constexpr int ldxs = NP + 4;
+        float* Xf = (float*)smem;                   // 64 x ldxs floats fit in Csh .. Crl
+        stage_x<NP, NT>(a, c0, [&](int k, int j, double v) { Xf[j * ldxs + k] = (float)v; });
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            const float* xp = Xf + (jb * 16 + (lane & 15)) * ldxs + ks * 32 + 8 * (lane >> 4);
+            uint32_t h[4], l[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) split_bf16x2(xp[2 * u], xp[2 * u + 1], &h[u], &l[u]);
+            xh[ks] = __builtin_bit_cast(bf8_t, (s8_t){(short)(h[0] & 0xFFFF), (short)(h[0] >> 16), (short)(h[1] & 0xFFFF),
+                                                     (short)(h[1] >> 16), (short)(h[2] & 0xFFFF), (short)(h[2] >> 16),
+                                                     (short)(h[3] & 0xFFFF), (short)(h[3] >> 16)});
+            xl[ks] = __builtin_bit_cast(bf8_t, (s8_t){(short)(l[0] & 0xFFFF), (short)(l[0] >> 16), (short)(l[1] & 0xFFFF),
+                                                     (short)(l[1] >> 16), (short)(l[2] & 0xFFFF), (short)(l[2] >> 16),
+                                                     (short)(l[3] & 0xFFFF), (short)(l[3] >> 16)});
+        }
+        __syncthreads();
+    }
+
+    f4_t accP[QB * 4];
+#pragma unroll
+    for (int t = 0; t < QB * 4; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    d4_t accG[2];
+    accG[0] = d4_t{0, 0, 0, 0};
+    accG[1] = d4_t{0, 0, 0, 0};
+
+    // thread -> (row group, column group) as in k_sketch_bf16 (TM = 32: RGH = 2)
+    const int rg = (tid & 3) | (((tid >> 4) & 1) << 2);
+    const int cgl = ((tid >> 2) & 3) | ((tid >> 5) << 2);
+    const float* cp[RMAX][4];
+    bool cv[RMAX][4];
+#pragma unroll
+    for (int rr = 0; rr < RMAX; ++rr)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = (rr * CGR + cgl) * 4 + q;
+            cv[rr][q] = c < a.n;
+            cp[rr][q] = fcol(a.seg, c < a.n ? c : a.n - 1);
+        }
+    const int64_t rows = a.seg.rows;
+    f4_t pf[RMAX][4];
+    auto fetch = [&](int64_t t) {
+        const int64_t row = t * TM + rg * 4;
+        const bool full = a.vec && (t + 1) * TM <= rows;
+#pragma unroll
+        for (int rr = 0; rr < RMAX; ++rr) {
+            if (rr * CGR + cgl < NCG) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
+                    if (full) {
+                        v = gld4(cp[rr][q] + row);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (row + e < rows) v[e] = gld(cp[rr][q] + row + e);
+                    }
+                    pf[rr][q] = cv[rr][q] ? v : f4_t{0.f, 0.f, 0.f, 0.f};
+                }
+            }
+        }
+    };
+
+    int64_t t = wg;
+    if (t < a.tiles) fetch(t);
+    for (; t < a.tiles; t += a.nwg) {
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < RMAX; ++rr) {
+            const int cg = rr * CGR + cgl;
+            if (cg < NCG) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {   // column q, rows rg*4 .. rg*4+3
+                    uint32_t h0, l0, h1, l1;
+                    split_bf16x2(pf[rr][q][0], pf[rr][q][1], &h0, &l0);
+                    split_bf16x2(pf[rr][q][2], pf[rr][q][3], &h1, &l1);
+                    *(uint64_t*)&Csh[(cg * 4 + q) * ldC + rg * 4] = (uint64_t)h0 | ((uint64_t)h1 << 32);
+                    *(uint64_t*)&Csl[(cg * 4 + q) * ldC + rg * 4] = (uint64_t)l0 | ((uint64_t)l1 << 32);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {   // row rg*4+e, columns cg*4 .. cg*4+3
+                    uint32_t h0, l0, h1, l1;
+                    split_bf16x2(pf[rr][0][e], pf[rr][1][e], &h0, &l0);
+                    split_bf16x2(pf[rr][2][e], pf[rr][3][e], &h1, &l1);
+                    *(uint64_t*)&Crh[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)h0 | ((uint64_t)h1 << 32);
+                    *(uint64_t*)&Crl[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)l0 | ((uint64_t)l1 << 32);
+                }
+            }
+        }
+        __syncthreads();
+        if (t + a.nwg < a.tiles) fetch(t + a.nwg);
+
+        // Phase A: Y block (ib, jb) = C_tile X with split products, three chains.
+        {
+            f4_t acc0 = f4_t{0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0;
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+                const int off = (ib * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4);
+                const bf8_t ah = lds_b128(&Crh[off]), al = lds_b128(&Crl[off]);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xh[ks], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xl[ks], acc1, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, xh[ks], acc2, 0, 0, 0);
+            }
+            const f4_t y = acc0 + (acc1 + acc2);
+            const int col = jb * 16 + (lane & 15), r0 = ib * 16 + 4 * (lane >> 4);
+            uint32_t h0, l0, h1, l1;
+            split_bf16x2(y[0], y[1], &h0, &l0);
+            split_bf16x2(y[2], y[3], &h1, &l1);
+            *(uint64_t*)&Ysh[col * ldY + r0] = (uint64_t)h0 | ((uint64_t)h1 << 32);
+            *(uint64_t*)&Ysl[col * ldY + r0] = (uint64_t)l0 | ((uint64_t)l1 << 32);
+            // the kept copy of Y (columns < lx): rows r0 .. r0+3 of column col from registers
+            if (a.yout != nullptr && c0 + col < a.lx) {
+                const int64_t row = t * TM + r0;
+                float* o = a.yout + (size_t)(c0 + col) * (size_t)a.ldy + row;
+                if (a.vec && row + 3 < rows) {
+                    gst4(o, y);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (row + q < rows) gst(o + q, y[q]);
+                }
+            }
+        }
+        __syncthreads();
+
+        // Phase B: P (NP x 64) += C_tile^T Y_tile with split products.
+        {
+            const int koff = 8 * (lane >> 4);
+#pragma unroll
+            for (int q = 0; q < QB; ++q) {
+                const int rb = w + 8 * q;
+                if (rb < NRBLK) {
+                    const int aoff = (rb * 16 + (lane & 15)) * ldC + koff;
+                    const bf8_t ah = lds_b128(&Csh[aoff]), al = lds_b128(&Csl[aoff]);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int boff = (j * 16 + (lane & 15)) * ldY + koff;
+                        const bf8_t bh = lds_b128(&Ysh[boff]), bl = lds_b128(&Ysl[boff]);
+                        f4_t acc = accP[q * 4 + j];
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+                        accP[q * 4 + j] = acc;
+                    }
+                }
+            }
+        }
+        // G (64 x 64) += Y^T Y: the four hi/lo products of every pair are exact in
+        // FP32; each tile's 32-row sum is added to the FP64 accumulators.
+        // Wave w: row block w/2, column blocks (w%2)*2 + {0,1}.
+        {
+            const int gi = w >> 1, gj0 = (w & 1) * 2;
+            const int koff = 8 * (lane >> 4);
+            const int aoff = (gi * 16 + (lane & 15)) * ldY + koff;
+            const bf8_t ah = lds_b128(&Ysh[aoff]), al = lds_b128(&Ysl[aoff]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int boff = ((gj0 + j) * 16 + (lane & 15)) * ldY + koff;
+                const bf8_t bh = lds_b128(&Ysh[boff]), bl = lds_b128(&Ysl[boff]);
+                f4_t g = f4_t{0.f, 0.f, 0.f, 0.f};
+                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl, g, 0, 0, 0);
+                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, g, 0, 0, 0);
+                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, g, 0, 0, 0);
+                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, g, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) accG[j][v] += (double)g[v];
+            }
+        }
+    }
+    float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        const int rb = w + 8 * q;
+        if (rb < NRBLK) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rb * 16 + 4 * (lane >> 4) + v;
+                    const int col = j * 16 + (lane & 15);
+                    gst(outP + row + (size_t)col * NP, accP[q * 4 + j][v]);
+                }
+        }
+    }
+    double* outG = a.partG + (size_t)wg * FU_LB * FU_LB;
+    const int gi = w >> 1, gj0 = (w & 1) * 2;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = gi * 16 + 4 * (lane >> 4) + v;   // FP32 MFMA output layout
+            const int col = (gj0 + j) * 16 + (lane & 15);
+            gstd(outG + row + col * FU_LB, accG[j][v]);
+        }
+}
+
+// ----------------------------------------------------------------------------
 // Plans and launchers of the fused passes.  The compiled (tile height, panel
 // width) pairs are listed here; a plan picks the narrowest compiled width that
 // holds the panel and the tallest tile that fits the LDS of one CU (or the
@@ -763,6 +1037,9 @@ static size_t fused_lds(int tm, int np) {
 }
 
 static const int kSketchNks[] = {2, 4, 6, 8, 10, 12, 16, 20};
+static const int kSplitNks[] = {2, 4, 6, 8, 10, 12};
+
+
 static const int kFusedNp[] = {64, 128, 192, 256, 320, 384, 448};
 
 bool sketch_plan(int n, int tile_rows, FusedPlan* p) {
@@ -785,18 +1062,21 @@ static bool fused_compiled(int tm, int np) {
     return false;
 }
 
-bool fused_plan(int n, int tile_rows, FusedPlan* p) {
+bool fused_plan(int n, int tile_rows, FusedPlan* p, bool lift) {
     for (int np : kFusedNp) {
         if (np < n) continue;
         for (int tm : {64, 32, 16}) {
             if (tile_rows && tm != tile_rows) continue;
+            // passes with partial sums keep 64-row tiles for narrow panels only
+            // (wider ones would not fit the registers); the lift takes the tallest tile
+            if (!tile_rows && !lift && tm == 64 && np > 128) continue;
             if (!fused_compiled(tm, np) || fused_lds(tm, np) > 160 * 1024) continue;
             p->np = np;
             p->tm = tm;
             p->lds = fused_lds(tm, np);
             return true;
         }
-        if (tile_rows) return fused_plan(n, 0, p);
+        if (tile_rows) return fused_plan(n, 0, p, lift);
         return false;
     }
     return false;
@@ -820,6 +1100,33 @@ hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st) {
     SK(64, 2) SK(64, 4) SK(64, 6) SK(64, 8) SK(64, 10) SK(64, 12)
     SK(32, 2) SK(32, 4) SK(32, 6) SK(32, 8) SK(32, 10) SK(32, 12) SK(32, 16) SK(32, 20)
 #undef SK
+    return hipErrorInvalidValue;
+}
+
+static size_t split_lds(int np) {
+    constexpr int tm = 32;
+    return ((size_t)2 * np * (tm + 8) + (size_t)2 * tm * (np + 8) + (size_t)2 * FU_LB * (tm + 8)) * 2;
+}
+
+bool split_plan(int n, FusedPlan* p) {
+    for (int nks : kSplitNks) {
+        if (nks * 32 < n) continue;
+        p->np = nks * 32;
+        p->tm = 32;
+        p->lds = split_lds(p->np);
+        return p->lds <= 160 * 1024;
+    }
+    return false;
+}
+
+hipError_t launch_final_split(const FusedArgs& a, hipStream_t st) {
+    if (a.tm != 32 || a.np % 32 || a.nlb != 1) return hipErrorInvalidValue;
+    const size_t lds = split_lds(a.np);
+    const int nks = a.np / 32;
+#define FS(NKS_) \
+    if (nks == NKS_) return launch_512(k_final_split<NKS_>, a, lds, st);
+    FS(2) FS(4) FS(6) FS(8) FS(10) FS(12)
+#undef FS
     return hipErrorInvalidValue;
 }
 

@@ -301,8 +301,11 @@ static SmallLayout small_layout(double* base, int n, int l, int K) {
 }
 
 // Work-groups of a fused pass: wg_per_cu per compute unit (256 CUs), at most one per tile.
-static int fused_wgs(const psvd_handle* h, int64_t tiles) {
-    const int per_cu = h->opt.wg_per_cu > 0 ? h->opt.wg_per_cu : 1;
+// The lift has no partial sums; by default it runs as many work-groups per CU
+// as its LDS allows (up to 4), so more tile loads are in flight.
+static int fused_wgs(const psvd_handle* h, int64_t tiles, size_t lift_lds = 0) {
+    int per_cu = h->opt.wg_per_cu > 0 ? h->opt.wg_per_cu : 1;
+    if (h->opt.wg_per_cu == 0 && lift_lds > 0) per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / lift_lds));
     const int64_t nwg = std::min<int64_t>((int64_t)256 * per_cu, FU_MAX_WG);
     return (int)std::max<int64_t>(1, std::min<int64_t>(nwg, tiles));
 }
@@ -324,6 +327,7 @@ static int ensure_workspace(psvd_handle* h, int n) {
     for (int tr : {0, 32})
         if (sketch_plan(n, tr, &sp)) np = std::max(np, sp.np);
     if (fused_plan(n, h->opt.tile_rows, &sp)) np = std::max(np, sp.np);
+    if (split_plan(n, &sp)) np = std::max(np, sp.np);
     int nlb = ceil_div(std::max(l, 1), 64);
     const size_t wgs = (size_t)fused_wgs(h, INT64_MAX);
     HIPCHK(h, h->partP.ensure(wgs * nlb * np * 64 * sizeof(float)));
@@ -433,7 +437,7 @@ static int lift_product(psvd_handle* h, const PanelSeg& S, const double* T, int6
                         const int32_t* skip, int skip_mask, int need_mask) {
     FusedPlan fp;
     if (!fp64 && seg_all_f32(S) && S.out_dtype == PSVD_F32 && skip == nullptr &&
-        fused_plan(S.ncols, h->opt.tile_rows, &fp)) {
+        fused_plan(S.ncols, h->opt.tile_rows, &fp, true)) {
         FusedArgs fa;
         std::memset(&fa, 0, sizeof(fa));
         fa.seg = S;
@@ -445,7 +449,7 @@ static int lift_product(psvd_handle* h, const PanelSeg& S, const double* T, int6
         fa.nlb = ceil_div(nx, 64);
         fa.tm = fp.tm;
         fa.tiles = (S.rows + fp.tm - 1) / fp.tm;
-        fa.nwg = fused_wgs(h, fa.tiles);
+        fa.nwg = fused_wgs(h, fa.tiles, fp.lds);
         fa.vec = seg_vec_ok(S, true) ? 1 : 0;
         int pe = prof_begin(h, PSVD_KC_LIFT);
         HIPCHK(h, launch_fused(2, fa, h->stream));
@@ -781,8 +785,10 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         const int nlb = ceil_div(l, 64);
         auto pass = [&](bool bf16, bool want_g) -> int {
             // P = D C'^T (C' X')  [+ G_Y = Y^T Y]
+            // final pass of the mixed precision: split-BF16 products (FP32-accurate)
             FusedPlan fp;
-            const bool planned = bf16 ? sketch_plan(n, h->opt.tile_rows, &fp) : fused_plan(n, h->opt.tile_rows, &fp);
+            const bool split = !bf16 && want_g && prec == PSVD_PREC_MIXED && nlb == 1 && split_plan(n, &fp);
+            const bool planned = split || (bf16 ? sketch_plan(n, h->opt.tile_rows, &fp) : fused_plan(n, h->opt.tile_rows, &fp));
             bool fuse_ok = !fp64 && planned && seg_all_f32(C) && (!want_g || nlb == 1) && !(bf16 && want_g);
             if (fuse_ok) {
                 FusedArgs fa;
@@ -807,6 +813,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 }
                 int pe = prof_begin(h, bf16 ? PSVD_KC_FUSED_BF16 : PSVD_KC_FUSED_F32);
                 if (bf16) HIPCHK(h, launch_sketch_bf16(fa, st));
+                else if (split) HIPCHK(h, launch_final_split(fa, st));
                 else HIPCHK(h, launch_fused(want_g ? 1 : 0, fa, st));
                 prof_end(h, pe);
                 FusedReduceArgs ra;
