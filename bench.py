@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
+FP64_VECTOR_TFLOPS = 78.6      # MI355X vector FP64 (256 CUs at 2.4 GHz)
 
 
 def log(msg):
@@ -152,6 +153,16 @@ def main():
     elif dom == "lift":
         roof = {"bound": "hbm", "achieved": (panel_bytes + w.M * w.K * 4) / (avg_ms * 1e-3) / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif dom in ("small", "small_svd"):
+        # one work-group FP64 kernels: counted FP64 flops against the vector FP64 peak
+        ncol = n
+        if dom == "small":      # Cholesky-QR re-orthonormalisation of the n x l sketch
+            flops = 4.0 * ncol * ell * ell + 2.0 * ell ** 3 / 3.0
+        else:                   # final small SVD: three n x l products, Cholesky, inverses, Jacobi sweeps
+            flops = (6.0 * ncol * ell * ell + 5.0 * ell ** 3 / 3.0 + 6.0 * ell ** 3
+                     + 4.0 * max(1, st["last_sweeps"]) * ell ** 3)
+        roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": panel_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]

@@ -72,7 +72,8 @@ enum {
     PSVD_KC_LIFT = 2,          /* U <- C T                                         */
     PSVD_KC_TN = 3,            /* reductions over the tall rows (Gram, C^T Y)     */
     PSVD_KC_NN = 4,            /* other tall products (C X written out)           */
-    PSVD_KC_SMALL = 5,         /* small-core kernels                              */
+    PSVD_KC_SMALL = 5,         /* small-core kernels without an SVD (Cholesky-QR) */
+    PSVD_KC_SMALL_SVD = 6,     /* small-core kernels with the one-sided Jacobi SVD */
     PSVD_KC_COUNT = 8
 };
 

@@ -20,7 +20,7 @@ PSVD_F32, PSVD_F64 = 1, 2
 DETERMINISTIC, RANDOMIZED = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
 OPT_ASYNC, OPT_NO_FALLBACK, OPT_PROFILE = 1, 2, 4
-KERNEL_CLASSES = ["fused_bf16", "fused_f32", "lift", "tn", "nn", "small"]
+KERNEL_CLASSES = ["fused_bf16", "fused_f32", "lift", "tn", "nn", "small", "small_svd"]
 
 EXPORTS = [
     "psvd_default_options", "psvd_initialize", "psvd_incorporate_data", "psvd_rank", "psvd_singular_values",

@@ -727,7 +727,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         sa.status = dstat;
         sa.sweeps = dsweeps;
         {
-            int pes = prof_begin(h, PSVD_KC_SMALL);
+            int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
             HIPCHK(h, launch_small_det1(sa, st));
             prof_end(h, pes);
         }
@@ -744,7 +744,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         rc = tn_product(h, Q1, Q1, true, true, L.G2, nullptr, 0, dstat, skipmask);
         if (rc) return rc;
         {
-            int pes = prof_begin(h, PSVD_KC_SMALL);
+            int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
             HIPCHK(h, launch_small_det2(sa, st));
             prof_end(h, pes);
         }
@@ -878,7 +878,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         rf.status = dstat;
         rf.sweeps = dsweeps;
         {
-            int pes = prof_begin(h, PSVD_KC_SMALL);
+            int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
             HIPCHK(h, launch_small_rand_final(rf, st));
             prof_end(h, pes);
         }
@@ -1267,7 +1267,7 @@ int grad_backward(GradCtx& g, const void* A, int64_t lda, double ff, const doubl
         sa.sweeps = dstat + 1;
         HIPCHK(h, hipMemcpyAsync(gR, L.G, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
         {
-            int pes = prof_begin(h, PSVD_KC_SMALL);
+            int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
             HIPCHK(h, launch_small_det1(sa, st));
             prof_end(h, pes);
         }
@@ -1282,7 +1282,7 @@ int grad_backward(GradCtx& g, const void* A, int64_t lda, double ff, const doubl
         rc = tn_product(h, Q1, Q1, true, true, L.G2, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN);
         if (rc) return rc;
         {
-            int pes = prof_begin(h, PSVD_KC_SMALL);
+            int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
             HIPCHK(h, launch_small_det2(sa, st));
             prof_end(h, pes);
         }

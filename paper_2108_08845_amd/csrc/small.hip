@@ -456,6 +456,137 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
     return sweep;
 }
 
+// One-sided Jacobi for at most 64 rows and 64 columns, Z in LDS with leading
+// dimension 64 and rows m..63 zero: every load and store of a pair is
+// unconditional and the column norms are read before the dot product.  The
+// same round-robin pairs, tests and rotation as wg_jacobi, with two changes:
+//  - the angle term sqrt((be - al)^2 + 4 g^2) takes the hardware square root
+//    (it only sets the angle; the rotation stays orthogonal to rounding since
+//    c and s share one correctly rounded reciprocal square root), and
+//  - a sweep whose largest squared cosine g^2 / (al be) is at most tol ends the
+//    iteration: convergence is quadratic, so the sweep after it would only
+//    confirm cosines near tol.
+// mx: 65 doubles of scratch.  Returns the sweep count (> max_sweeps: not
+// converged); results as wg_jacobi.
+__device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* sig, int* order, double* nrm,
+                                               int max_sweeps, int* sflag, double* mx) {
+    constexpr int ldz = 64;
+    const int tid = threadIdx.x;
+    const int ql = tid & 15, qw = tid >> 4, nq = blockDim.x >> 4;
+    const double tol = (double)m * 0x1p-53;
+    const int ne = n + (n & 1);
+    // quarter-wave qw < ne / 2 holds round-robin positions qw and ne - 1 - qw
+    const int pa = qw, pb = ne - 1 - qw;
+    const bool has_pair = qw < ne / 2;
+    int sweep = 0;
+    for (;;) {
+        for (int j = qw; j < n; j += nq) {
+            const double* z = Z + j * ldz + ql;
+            double s0 = z[0] * z[0], s1 = z[16] * z[16];
+            s0 = fma(z[32], z[32], s0);
+            s1 = fma(z[48], z[48], s1);
+            const double s = q16_sum(s0 + s1);
+            if (ql == 0) nrm[j] = s;
+        }
+        if (tid == 0) *sflag = 0;
+        __syncthreads();
+        if (tid < 64) {   // largest squared norm, broadcast through nrm[n]
+            double v = 0.0;
+            for (int j = tid; j < n; j += 64) v = fmax(v, nrm[j]);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+            if (tid == 0) nrm[n] = v;
+        }
+        __syncthreads();
+        const double negl = nrm[n] * tol * tol;
+        if (sweep >= max_sweeps) {
+            ++sweep;
+            break;
+        }
+        double cmax = 0.0;   // largest g^2 / (al be) this quarter-wave met
+        for (int t = 0; t < ne - 1; ++t) {
+            if (has_pair) {
+                int xa = pa - 1 + t, xb = pb - 1 + t;   // (pos - 1 + t) mod (ne - 1), both < 2 (ne - 1)
+                xa -= xa >= ne - 1 ? ne - 1 : 0;
+                xb -= xb >= ne - 1 ? ne - 1 : 0;
+                const int ca = pa == 0 ? 0 : 1 + xa;
+                const int cb = 1 + xb;                   // pb >= ne / 2 > 0
+                const int p = ca < cb ? ca : cb, q = ca < cb ? cb : ca;
+                if (q < n) {
+                    double* zp = Z + p * ldz + ql;
+                    double* zq = Z + q * ldz + ql;
+                    const double al = nrm[p], be = nrm[q];
+                    double xp[4], xq[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        xp[u] = zp[16 * u];
+                        xq[u] = zq[16 * u];
+                    }
+                    double g0 = xp[0] * xq[0], g1 = xp[1] * xq[1];
+                    g0 = fma(xp[2], xq[2], g0);
+                    g1 = fma(xp[3], xq[3], g1);
+                    const double g = q16_sum(g0 + g1);
+                    if (al > negl && be > negl) {
+                        const double gg = g * g, ab = al * be;
+                        cmax = fmax(cmax, gg / ab);
+                        if (gg > (tol * tol) * ab) {
+                            const double dif = be - al;
+                            const double uu = fabs(dif) + __builtin_amdgcn_sqrt(fma(dif, dif, 4.0 * gg));
+                            const double hh = rsqrt(fma(uu, uu, 4.0 * gg));
+                            const double c = uu * hh, s = (dif >= 0.0 ? 2.0 * g : -2.0 * g) * hh;
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                zp[16 * u] = c * xp[u] - s * xq[u];
+                                zq[16 * u] = s * xp[u] + c * xq[u];
+                            }
+                            if (ql == 0) {
+                                const double cs2g = 2.0 * c * s * g;
+                                nrm[p] = c * c * al + s * s * be - cs2g;
+                                nrm[q] = s * s * al + c * c * be + cs2g;
+                                *sflag = 1;
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (ql == 0 && qw < 64) mx[qw] = cmax;
+        __syncthreads();
+        if (tid < 64) {
+            double v = tid < nq ? mx[tid] : 0.0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+            if (tid == 0) mx[64] = v;
+        }
+        ++sweep;
+        __syncthreads();
+        const bool done = !*sflag || mx[64] <= tol;
+        __syncthreads();
+        if (done) break;
+    }
+    for (int j = qw; j < n; j += nq) {
+        double* z = Z + j * ldz;
+        double s = 0.0;
+        for (int i = ql; i < m; i += 16) s += z[i] * z[i];
+        s = sqrt(q16_sum(s));
+        for (int i = ql; i < m; i += 16) z[i] = s > 0.0 ? z[i] / s : 0.0;
+        if (ql == 0) sig[j] = s;
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double sj = sig[j];
+        int rank = 0;
+        for (int i = 0; i < n; ++i) {
+            const double si = sig[i];
+            if (si > sj || (si == sj && i < j)) ++rank;
+        }
+        order[rank] = j;
+    }
+    __syncthreads();
+    return sweep;
+}
+
 // Sign rule: column j of X (rows x k) gets its largest-magnitude entry
 // (lowest index on ties) non-negative; flips recorded in flip[j].
 __device__ __forceinline__ void wg_sign_rule(double* X, int rows, int k, int ldx, double* flip) {
@@ -695,10 +826,12 @@ __device__ bool chol_shifted(const double* Gsrc, double* W, int l, int32_t* stat
     return wg_chol_upper(W, l, l);
 }
 
-// LDS of the randomized small kernels: two l x l matrices, 3 l + 8 vector
-// entries and, for l <= 64, the chunk of the staged tall products.
+// LDS of the randomized small kernels: two l x l matrices (the first with
+// leading dimension 64 when l <= 64), 3 l + 8 vector entries and, for
+// l <= 64, the chunk of the staged tall products.
 __host__ __device__ inline size_t rand_lds_doubles(int l) {
-    return 2 * (size_t)l * l + 3 * (size_t)l + 8 + (l <= 64 ? TALL_CHUNK : 0);
+    return l <= 64 ? 64 * (size_t)l + (size_t)l * l + 3 * (size_t)l + 8 + TALL_CHUNK
+                   : 2 * (size_t)l * l + 3 * (size_t)l + 8;
 }
 
 // Power-iteration re-orthonormalisation X = D P R^-1 with R = chol(P^T P).
@@ -740,10 +873,12 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     const int l = a.l, n = a.n, tid = threadIdx.x;
     constexpr bool in_lds = IN_LDS;
     const bool staged = in_lds && l <= 64;
+    // staged: W spans 64 x l so that R_b^T can take leading dimension 64
+    const size_t wsz = staged ? 64 * (size_t)l : (size_t)l * l;
     double* W = in_lds ? lds : a.W;                      // working l x l
-    double* V = in_lds ? lds + (size_t)l * l : a.V;      // second l x l
-    double* vec = in_lds ? lds + 2 * (size_t)l * l : a.vec;   // 2 l + 1 doubles + l ints
-    double* Cn = lds + 2 * (size_t)l * l + 3 * (size_t)l + 8;   // staging chunk (staged only)
+    double* V = in_lds ? lds + wsz : a.V;                // second l x l
+    double* vec = in_lds ? lds + wsz + (size_t)l * l : a.vec;   // 2 l + 1 doubles + l ints
+    double* Cn = lds + wsz + (size_t)l * l + 3 * (size_t)l + 8;   // staging chunk (staged only)
     const int rk = a.K < l ? a.K : l;
     auto bail = [&]() {
         if (tid == 0) *a.status |= DEV_NONFINITE;
@@ -780,11 +915,17 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
         __syncthreads();
         RYi = Cn;
     }
-    wg_gemm_f64(l, l, l, V, 1, l, RYi, 1, l, W, l, 1, nullptr, 0);
+    const int ldw = staged ? 64 : l;
+    if (staged) {   // rows l..63 of the padded W are zero
+        for (int e = tid; e < 64 * l; e += SM_THREADS) W[e] = 0.0;
+        __syncthreads();
+    }
+    wg_gemm_f64(l, l, l, V, 1, l, RYi, 1, l, W, ldw, 1, nullptr, 0);
     double* sig = vec;
     double* nrm = sig + l;
     int* ord = (int*)(nrm + l + 1);
-    const int sw = wg_jacobi(W, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
+    const int sw = staged ? wg_jacobi_pad64(W, l, l, sig, ord, nrm, a.max_sweeps, &sflag, red)
+                          : wg_jacobi(W, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
@@ -793,7 +934,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     double* Us = in_lds ? V : a.small_u;
     for (int e = tid; e < l * rk; e += SM_THREADS) {
         const int i = e % l, j = e / l;
-        Us[i + (size_t)j * l] = W[i + (size_t)ord[j] * l];
+        Us[i + (size_t)j * l] = W[i + (size_t)ord[j] * ldw];
     }
     for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sig[ord[j]];
     __syncthreads();

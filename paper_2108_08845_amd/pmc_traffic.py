@@ -130,8 +130,12 @@ def main(argv=None):
     ap.add_argument("--kclass", required=True, choices=sorted(KERNEL_SOURCES))
     ap.add_argument("--workload", required=True)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--command", action="append", default=[],
+                    help="a command that produced the counter runs (repeatable; stored in the record)")
     a = ap.parse_args(argv)
     rec = compute(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, a.kclass, a.workload)
+    if a.command:
+        rec["commands"] = list(a.command)
     with open(a.out, "w") as f:
         json.dump(rec, f, indent=1)
     json.dump(rec, sys.stdout, indent=1)
