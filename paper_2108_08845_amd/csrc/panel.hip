@@ -786,13 +786,39 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
 //                        copy of Y and split again for the two products below)
 //   P     += C_tile^T Y_tile   (split products)
 //   G     += Y_tile^T Y_tile   (all four hi/lo products, exact in FP32; FP64 across tiles)
-// Loads, LDS copies and the X fragments follow k_sketch_bf16 (hi and lo copies).
+// The tile is stored once, row-major (hi and lo), in one of two LDS buffers:
+// C X reads row fragments; C^T Y reads column fragments of the same copy with
+// the 16-bit transpose load (ds_read_b64_tr_b16).  Double buffering lets the
+// split and store of the next tile run between the same two barriers as the
+// C^T Y and Y^T Y products of this one.
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t* hi, uint32_t* lo) {
     const uint32_t h = pack_bf16x2(a, b);
     const float ha = __uint_as_float(h << 16), hb = __uint_as_float(h & 0xFFFF0000u);
     *hi = h;
     *lo = pack_bf16x2(a - ha, b - hb);
+}
+
+typedef short s4v_t __attribute__((__vector_size__(4 * sizeof(short))));
+typedef __attribute__((address_space(3))) s4v_t lds_s4v_t;
+
+// Transpose load of 16-bit data.  Within each group of 16 lanes, lane i gets
+// element i % 4 of the 8-byte chunks addressed by lanes i / 4, 4 + i / 4,
+// 8 + i / 4 and 12 + i / 4 of the group (in that order).
+__device__ __forceinline__ s4v_t lds_tr16(const uint16_t* p) {
+    return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4v_t*)(__attribute__((address_space(3))) uint16_t*)p);
+}
+
+// Column fragment of the 16x16x32 A operand of C^T Y: lane (l, g) = (lane & 15,
+// lane >> 4) receives rows 8 g .. 8 g + 7 of column c0 + l of the row-major tile
+// (leading dimension ld).  Two transpose loads of four rows each; lane (l, g)
+// addresses row 8 g + 4 h + l / 4, columns c0 + 4 (l % 4) .. + 3.
+__device__ __forceinline__ bf8_t lds_colfrag(const uint16_t* tile, int ld, int c0, int lane) {
+    const int l = lane & 15, g = lane >> 4;
+    const uint16_t* p = tile + (8 * g + (l >> 2)) * ld + c0 + 4 * (l & 3);
+    const s4v_t lo4 = lds_tr16(p), hi4 = lds_tr16(p + 4 * ld);
+    const s8_t v = (s8_t){lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
+    return __builtin_bit_cast(bf8_t, v);
 }
 
 template <int NKS>
@@ -803,15 +829,13 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
     constexpr int RG = TM / 4;                      // 8 row groups of 4
     constexpr int CGR = NT / RG;                    // 64 column groups per round
     constexpr int RMAX = (NCG + CGR - 1) / CGR;
-    constexpr int NRBLK = NP / 16;
-    constexpr int QB = (NRBLK + 7) / 8;
-    constexpr int ldC = TM + 8, ldR = NP + 8, ldY = TM + 8;
+    constexpr int NIT = NKS / 2;                    // C^T Y items per wave: (16-row block, 32-column pair)
+    static_assert(NKS % 2 == 0, "an even number of 32-column slices");
+    constexpr int ldR = NP + 8, ldY = TM + 8;
+    constexpr int CBUF = 2 * TM * ldR;              // one buffer: hi (TM x ldR) then lo
     extern __shared__ __align__(16) unsigned char smem[];
-    uint16_t* Csh = (uint16_t*)smem;                // NP x TM, column-major (hi)
-    uint16_t* Csl = Csh + NP * ldC;                 //                        (lo)
-    uint16_t* Crh = Csl + NP * ldC;                 // TM x NP, row-major    (hi)
-    uint16_t* Crl = Crh + TM * ldR;                 //                        (lo)
-    uint16_t* Ysh = Crl + TM * ldR;                 // 64 x TM, column-major (hi)
+    uint16_t* Cb = (uint16_t*)smem;                 // two tile buffers, row-major
+    uint16_t* Ysh = Cb + 2 * CBUF;                  // 64 x TM, column-major (hi)
     uint16_t* Ysl = Ysh + FU_LB * ldY;              //                        (lo)
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -827,7 +851,8 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
     bf8_t xh[NKS], xl[NKS];
     {
         constexpr int ldxs = NP + 4;
-        float* Xf = (float*)smem;                   // 64 x ldxs floats fit in Csh .. Crl
+        static_assert(FU_LB * ldxs * 4 <= 2 * CBUF * 2, "X staging must fit the tile buffers");
+        float* Xf = (float*)smem;
         stage_x<NP, NT>(a, c0, [&](int k, int j, double v) { Xf[j * ldxs + k] = (float)v; });
         __syncthreads();
 #pragma unroll
@@ -846,9 +871,9 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
         __syncthreads();
     }
 
-    f4_t accP[QB * 4];
+    f4_t accP[NIT * 2];
 #pragma unroll
-    for (int t = 0; t < QB * 4; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < NIT * 2; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
     d4_t accG[2];
     accG[0] = d4_t{0, 0, 0, 0};
     accG[1] = d4_t{0, 0, 0, 0};
@@ -889,25 +914,16 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
             }
         }
     };
-
-    int64_t t = wg;
-    if (t < a.tiles) fetch(t);
-    for (; t < a.tiles; t += a.nwg) {
-        __syncthreads();
+    // split the fetched tile into buffer b: row rg*4+e, columns cg*4 .. cg*4+3
+    auto store_tile = [&](int b) {
+        uint16_t* Crh = Cb + b * CBUF;
+        uint16_t* Crl = Crh + TM * ldR;
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int cg = rr * CGR + cgl;
             if (cg < NCG) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {   // column q, rows rg*4 .. rg*4+3
-                    uint32_t h0, l0, h1, l1;
-                    split_bf16x2(pf[rr][q][0], pf[rr][q][1], &h0, &l0);
-                    split_bf16x2(pf[rr][q][2], pf[rr][q][3], &h1, &l1);
-                    *(uint64_t*)&Csh[(cg * 4 + q) * ldC + rg * 4] = (uint64_t)h0 | ((uint64_t)h1 << 32);
-                    *(uint64_t*)&Csl[(cg * 4 + q) * ldC + rg * 4] = (uint64_t)l0 | ((uint64_t)l1 << 32);
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {   // row rg*4+e, columns cg*4 .. cg*4+3
+                for (int e = 0; e < 4; ++e) {
                     uint32_t h0, l0, h1, l1;
                     split_bf16x2(pf[rr][0][e], pf[rr][1][e], &h0, &l0);
                     split_bf16x2(pf[rr][2][e], pf[rr][3][e], &h1, &l1);
@@ -916,8 +932,18 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
                 }
             }
         }
-        __syncthreads();
+    };
+
+    int64_t t = wg;
+    if (t < a.tiles) {
+        fetch(t);
+        store_tile(0);
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
+    }
+    __syncthreads();
+    for (int b = 0; t < a.tiles; t += a.nwg, b ^= 1) {
+        const uint16_t* Crh = Cb + b * CBUF;
+        const uint16_t* Crl = Crh + TM * ldR;
 
         // Phase A: Y block (ib, jb) = C_tile X with split products, three chains.
         {
@@ -952,25 +978,34 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
         }
         __syncthreads();
 
-        // Phase B: P (NP x 64) += C_tile^T Y_tile with split products.
+        // The next tile: split into the other buffer (read by no wave in this
+        // interval), then the loads of the one after it.
+        if (t + a.nwg < a.tiles) {
+            store_tile(b ^ 1);
+            if (t + 2 * (int64_t)a.nwg < a.tiles) fetch(t + 2 * (int64_t)a.nwg);
+        }
+
+        // Phase B: P (NP x 64) += C_tile^T Y_tile with split products; the
+        // column fragments come from the row-major tile by transpose loads.
+        // Item it = w NIT + u is row block it / 2 with column blocks 2 (it % 2) + {0, 1}:
+        // every wave does NIT items.
         {
             const int koff = 8 * (lane >> 4);
 #pragma unroll
-            for (int q = 0; q < QB; ++q) {
-                const int rb = w + 8 * q;
-                if (rb < NRBLK) {
-                    const int aoff = (rb * 16 + (lane & 15)) * ldC + koff;
-                    const bf8_t ah = lds_b128(&Csh[aoff]), al = lds_b128(&Csl[aoff]);
+            for (int u = 0; u < NIT; ++u) {
+                const int it = w * NIT + u, rb = it >> 1, jp = it & 1;
+                const bf8_t ah = lds_colfrag(Crh, ldR, rb * 16, lane);
+                const bf8_t al = lds_colfrag(Crl, ldR, rb * 16, lane);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int boff = (j * 16 + (lane & 15)) * ldY + koff;
-                        const bf8_t bh = lds_b128(&Ysh[boff]), bl = lds_b128(&Ysl[boff]);
-                        f4_t acc = accP[q * 4 + j];
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-                        accP[q * 4 + j] = acc;
-                    }
+                for (int jj = 0; jj < 2; ++jj) {
+                    const int boff = ((2 * jp + jj) * 16 + (lane & 15)) * ldY + koff;
+                    const bf8_t bh = lds_b128(&Ysh[boff]), bl = lds_b128(&Ysl[boff]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    f4_t acc = accP[u * 2 + jj];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+                    accP[u * 2 + jj] = acc;
                 }
             }
         }
@@ -995,21 +1030,20 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
                 for (int v = 0; v < 4; ++v) accG[j][v] += (double)g[v];
             }
         }
+        __syncthreads();
     }
     float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
 #pragma unroll
-    for (int q = 0; q < QB; ++q) {
-        const int rb = w + 8 * q;
-        if (rb < NRBLK) {
+    for (int u = 0; u < NIT; ++u) {
+        const int it = w * NIT + u, rb = it >> 1, jp = it & 1;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+        for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = rb * 16 + 4 * (lane >> 4) + v;
-                    const int col = j * 16 + (lane & 15);
-                    gst(outP + row + (size_t)col * NP, accP[q * 4 + j][v]);
-                }
-        }
+            for (int v = 0; v < 4; ++v) {
+                const int row = rb * 16 + 4 * (lane >> 4) + v;
+                const int col = (2 * jp + jj) * 16 + (lane & 15);
+                gst(outP + row + (size_t)col * NP, accP[u * 2 + jj][v]);
+            }
     }
     double* outG = a.partG + (size_t)wg * FU_LB * FU_LB;
     const int gi = w >> 1, gj0 = (w & 1) * 2;
@@ -1105,7 +1139,7 @@ hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st) {
 
 static size_t split_lds(int np) {
     constexpr int tm = 32;
-    return ((size_t)2 * np * (tm + 8) + (size_t)2 * tm * (np + 8) + (size_t)2 * FU_LB * (tm + 8)) * 2;
+    return ((size_t)4 * tm * (np + 8) + (size_t)2 * FU_LB * (tm + 8)) * 2;   // two hi/lo tile buffers, Y hi/lo
 }
 
 bool split_plan(int n, FusedPlan* p) {

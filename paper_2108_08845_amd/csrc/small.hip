@@ -64,6 +64,62 @@ __device__ __forceinline__ bool wg_chol_upper(double* A, int n, int lda) {
     return true;
 }
 
+// Cholesky for n <= 64 on 1024 threads (a 32 x 32 grid, up to 2 x 2 trailing
+// entries per thread): out = R with G + shift I = R^T R (G read from src, n x n,
+// leading dimension n; out may be src).  The factorisation runs on a copy in S
+// (64 x 65 doubles of LDS; the odd leading dimension spreads a row over the
+// banks) with the same step order as wg_chol_upper, but every LDS read of a
+// step is issued before its arithmetic, so a step costs one LDS round trip
+// and one barrier.  Returns false (uniformly) on a non-positive or
+// non-finite pivot.
+constexpr int CHOL64_LD = 65;
+__device__ __forceinline__ bool wg_chol64(const double* src, int n, double shift, double* S, double* out) {
+    constexpr int ld = CHOL64_LD;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e % n, j = e / n;
+        S[i + j * ld] = src[e] + (i == j ? shift : 0.0);
+    }
+    __syncthreads();
+    const int ti = tid & 31, tj = tid >> 5;
+    const int i0 = ti, i1 = ti + 32, j0 = tj, j1 = tj + 32;
+    const int i0c = i0 < n ? i0 : n - 1, i1c = i1 < n ? i1 : n - 1;
+    const int j0c = j0 < n ? j0 : n - 1, j1c = j1 < n ? j1 : n - 1;
+    double d_prev = 1.0;
+    bool ok = true;
+    for (int k = 0; k < n; ++k) {
+        const double d = S[k + k * ld];
+        const double aki0 = S[k + i0c * ld], aki1 = S[k + i1c * ld];
+        const double akj0 = S[k + j0c * ld], akj1 = S[k + j1c * ld];
+        const double a00 = S[i0c + j0c * ld], a01 = S[i0c + j1c * ld];
+        const double a10 = S[i1c + j0c * ld], a11 = S[i1c + j1c * ld];
+        const int js = k - 1 + tid;                  // row k - 1 is scaled by threads 0 .. n - k
+        const int jsc = js < n ? js : n - 1;
+        const double sv = S[(k > 0 ? k - 1 : 0) + jsc * ld];
+        ok = ok && (d > 0.0) && finite_d(d);
+        const double invd = 1.0 / d;
+        const double f0 = akj0 * invd, f1 = akj1 * invd;
+        if (k < i0 && i0 <= j0 && j0 < n) S[i0 + j0 * ld] = fma(-aki0, f0, a00);
+        if (k < i0 && i0 <= j1 && j1 < n) S[i0 + j1 * ld] = fma(-aki0, f1, a01);
+        if (k < i1 && i1 <= j0 && j0 < n) S[i1 + j0 * ld] = fma(-aki1, f0, a10);
+        if (k < i1 && i1 <= j1 && j1 < n) S[i1 + j1 * ld] = fma(-aki1, f1, a11);
+        if (k > 0 && js < n) {
+            const double rp = sqrt(d_prev);
+            S[(k - 1) + js * ld] = (js == k - 1) ? rp : sv / rp;
+        }
+        __syncthreads();
+        d_prev = d;
+    }
+    if (tid == 0 && n > 0) S[(n - 1) + (n - 1) * ld] = sqrt(d_prev);
+    __syncthreads();
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e % n, j = e / n;
+        out[e] = i <= j ? S[i + j * ld] : 0.0;
+    }
+    __syncthreads();
+    return ok;
+}
+
 // X (n x nrhs) = R^-1 B for upper triangular R (n x n), row by row from the
 // bottom: step i fixes row i of X for every right-hand side in parallel, so no
 // thread ever waits on a value it has just stored.  B == nullptr means B = I
@@ -202,6 +258,7 @@ __device__ void wg_gemm_nn(int m, int n, int k, const double* A, int lda, const 
 constexpr int TALL_KC = 64;
 constexpr int TALL_LDC = 65;
 constexpr int TALL_CHUNK = TALL_KC * TALL_LDC;   // doubles of the LDS chunk
+static_assert(TALL_CHUNK >= 64 * CHOL64_LD, "the chunk also holds the n <= 64 Cholesky copy");
 
 struct TallStager {
     double pre[4];
@@ -799,11 +856,17 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
 // with the shifted retry of Fukaya et al. 2020 on breakdown: shift
 // 11 (l^2 + l) 2^-53 ||G||_F on the diagonal, flag_bit set in the status.
 // Returns false if the shifted factorisation fails too.
-__device__ bool chol_shifted(const double* Gsrc, double* W, int l, int32_t* status, int flag_bit, double* red) {
+__device__ __forceinline__ bool chol_shifted(const double* Gsrc, double* W, int l, int32_t* status, int flag_bit, double* red,
+                             double* S = nullptr) {
     const int tid = threadIdx.x;
-    for (int e = tid; e < l * l; e += blockDim.x) W[e] = Gsrc[e];
-    __syncthreads();
-    if (wg_chol_upper(W, l, l)) return true;
+    const bool fast = S != nullptr && l <= 64 && blockDim.x == 1024;   // S: 64 x 65 doubles of LDS
+    if (fast) {
+        if (wg_chol64(Gsrc, l, 0.0, S, W)) return true;
+    } else {
+        for (int e = tid; e < l * l; e += blockDim.x) W[e] = Gsrc[e];
+        __syncthreads();
+        if (wg_chol_upper(W, l, l)) return true;
+    }
     // ||G||_F by a fixed-order sum (per-thread partials, then thread 0)
     double f = 0.0;
     for (int e = tid; e < l * l; e += blockDim.x) f += Gsrc[e] * Gsrc[e];
@@ -818,6 +881,7 @@ __device__ bool chol_shifted(const double* Gsrc, double* W, int l, int32_t* stat
     __syncthreads();
     const double shift = 11.0 * ((double)l * l + l) * 0x1p-53 * red[0];
     __syncthreads();
+    if (fast) return wg_chol64(Gsrc, l, shift, S, W);
     for (int e = tid; e < l * l; e += blockDim.x) {
         const int i = e % l, j = e / l;
         W[e] = Gsrc[e] + (i == j ? shift : 0.0);
@@ -850,7 +914,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_orth(OrthArgs a) {
     // G = P^T P (global scratch, kept for the shifted retry)
     if (staged) wg_gram_tall(n, l, a.P, n, a.G, l, Cn);
     else wg_gemm_f64(l, l, n, a.P, n, 1, a.P, 1, n, a.G, 1, l, nullptr, 0);
-    if (!chol_shifted(a.G, R, l, a.status, a.flag_bit, red)) {
+    if (!chol_shifted(a.G, R, l, a.status, a.flag_bit, red, staged ? Cn : nullptr)) {
         if (threadIdx.x == 0) *a.status |= DEV_NONFINITE;
         return;
     }
@@ -884,14 +948,14 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
         if (tid == 0) *a.status |= DEV_NONFINITE;
     };
     // R_Y and R_Y^-1 (V, copied out)
-    if (!chol_shifted(a.GY, W, l, a.status, DEV_FALLBACK, red)) return bail();
+    if (!chol_shifted(a.GY, W, l, a.status, DEV_FALLBACK, red, staged ? Cn : nullptr)) return bail();
     for (int e = tid; e < l * l; e += SM_THREADS) a.RY[e] = W[e];
     wg_trinv_upper(W, l, l, V, l, vec);
     for (int e = tid; e < l * l; e += SM_THREADS) a.RYi[e] = V[e];
     // R1 = chol(P^T P), R1^-1 (V), P1 = P R1^-1
     if (staged) wg_gram_tall(n, l, a.P, n, a.G1, l, Cn);
     else wg_gemm_f64(l, l, n, a.P, n, 1, a.P, 1, n, a.G1, 1, l, nullptr, 0);
-    if (!chol_shifted(a.G1, W, l, a.status, DEV_FALLBACK, red)) return bail();
+    if (!chol_shifted(a.G1, W, l, a.status, DEV_FALLBACK, red, staged ? Cn : nullptr)) return bail();
     for (int e = tid; e < l * l; e += SM_THREADS) a.R1[e] = W[e];
     wg_trinv_upper(W, l, l, V, l, vec);
     if (staged) wg_mul_tall(n, l, a.P, n, V, l, a.P1, n, nullptr, 0, Cn);
@@ -899,7 +963,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     // R2 = chol(P1^T P1) in W
     if (staged) wg_gram_tall(n, l, a.P1, n, W, l, Cn);
     else wg_gemm_f64(l, l, n, a.P1, n, 1, a.P1, 1, n, W, 1, l, nullptr, 0);
-    if (!wg_chol_upper(W, l, l)) return bail();
+    if (!(staged ? wg_chol64(W, l, 0.0, Cn, W) : wg_chol_upper(W, l, l))) return bail();
     // small operands are read from LDS: R1 and then R_Y^-1 go to the chunk buffer
     const double* R1 = a.R1;
     const double* RYi = a.RYi;
