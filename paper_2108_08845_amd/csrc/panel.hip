@@ -129,14 +129,14 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     };
     fetch(it.row0);
     for (int64_t r0 = it.row0; r0 < it.row1; r0 += TN_TM) {
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int c = e * 4 + w, rr = lane;   // TN_TM == 64: wave-uniform column
             Ls[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pl[e]);
             Rs[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pr[e]);
         }
-        __syncthreads();
+        lds_barrier();
         if (r0 + TN_TM < it.row1) fetch(r0 + TN_TM);
         // wave w: output tile row block w, column blocks 0..3
 #pragma unroll 4
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] = typename MF::acc{0, 0, 0, 0};
         for (int k0 = 0; k0 < a.n; k0 += NN_KC) {
-            __syncthreads();
+            lds_barrier();
             // C chunk: 32 columns x 64 rows (8 per thread)
 #pragma unroll
             for (int e = 0; e < NN_KC * NN_TM / 256; ++e) {
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
                 if (k0 + k < a.n && oc0 + j < a.nx) v = gldd(a.X + (k0 + k) + (int64_t)(oc0 + j) * a.ldx);
                 Xs[j * (NN_KC + 1) + k] = MF::from_double(v);
             }
-            __syncthreads();
+            lds_barrier();
             // wave w: output row block w (16 rows), column blocks 0..3
 #pragma unroll
             for (int kk = 0; kk < NN_KC; kk += MF::KSTEP) {
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
             }
         }
         // Stage the output tile through LDS for coalesced column stores.
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
                 int col = j * 16 + (lane & 15);
                 Os[col * (NN_TM + 1) + row] = (double)acc[j][v];
             }
-        __syncthreads();
+        lds_barrier();
         for (int idx = tid; idx < NN_OB * NN_TM; idx += 256) {
             int rr = idx % NN_TM, j = idx / NN_TM;
             int64_t row = r0 + rr;
@@ -413,21 +413,25 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     }
     const int64_t rows = a.seg.rows;
     f4_t pf[RMAX];
+    // The loads only: nothing here reads the loaded values, so they stay in
+    // flight until the tile is stored (columns >= n are zeroed there).  The
+    // full-tile test is one branch around all loads.
     auto fetch = [&](int64_t t) {
         const int64_t row = t * TM + tsub * 4;
-        const bool full = a.vec && (t + 1) * TM <= rows;   // uniform
+        if (a.vec && (t + 1) * TM <= rows) {                 // uniform
 #pragma unroll
-        for (int rr = 0; rr < RMAX; ++rr) {
-            if (rr * CPR + tcol < NP) {                      // uniform per wave
-                f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
-                if (full) {
-                    v = gld4(cp[rr] + row);
-                } else {
+            for (int rr = 0; rr < RMAX; ++rr)
+                if (rr * CPR + tcol < NP) pf[rr] = gld4(cp[rr] + row);   // uniform per wave
+        } else {
+#pragma unroll
+            for (int rr = 0; rr < RMAX; ++rr) {
+                if (rr * CPR + tcol < NP) {
+                    f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                         if (row + q < rows) v[q] = gld(cp[rr] + row + q);
+                    pf[rr] = v;
                 }
-                pf[rr] = cv[rr] ? v : f4_t{0.f, 0.f, 0.f, 0.f};
             }
         }
     };
@@ -435,13 +439,13 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     int64_t t = wg;
     if (t < a.tiles) fetch(t);
     for (; t < a.tiles; t += a.nwg) {
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int c = rr * CPR + tcol;
-            if (c < NP) *(f4_t*)&Cs[c * ldC + tsub * 4] = pf[rr];
+            if (c < NP) *(f4_t*)&Cs[c * ldC + tsub * 4] = cv[rr] ? pf[rr] : f4_t{0.f, 0.f, 0.f, 0.f};
         }
-        __syncthreads();
+        lds_barrier();
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
 
         // Phase A: Y_tile (TM x 64) = C_tile X_blk; (TM/16) x 4 output blocks over 8 waves.
@@ -488,7 +492,7 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
 
         if (MODE == 2 || (MODE == 1 && a.yout != nullptr)) {
             // Y_tile -> out (lift) or the kept copy of Y (final pass), float4 column segments, j < lx
@@ -670,23 +674,29 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
         }
     const int64_t rows = a.seg.rows;
     f4_t pf[RMAX][4];
+    // The loads only: nothing here reads the loaded values, so they stay in
+    // flight until the tile is converted (columns >= n are zeroed there).  The
+    // full-tile test is one branch around all loads.
     auto fetch = [&](int64_t t) {
         const int64_t row = t * TM + rg * 4;
-        const bool full = a.vec && (t + 1) * TM <= rows;   // uniform
+        if (a.vec && (t + 1) * TM <= rows) {                 // uniform
 #pragma unroll
-        for (int rr = 0; rr < RMAX; ++rr) {
-            if (rr * CGR + cgl < NCG) {                      // uniform per wave
+            for (int rr = 0; rr < RMAX; ++rr)
+                if (rr * CGR + cgl < NCG)                    // uniform per wave
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
-                    if (full) {
-                        v = gld4(cp[rr][q] + row);
-                    } else {
+                    for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + row);
+        } else {
+#pragma unroll
+            for (int rr = 0; rr < RMAX; ++rr) {
+                if (rr * CGR + cgl < NCG) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
                             if (row + e < rows) v[e] = gld(cp[rr][q] + row + e);
+                        pf[rr][q] = v;
                     }
-                    pf[rr][q] = cv[rr][q] ? v : f4_t{0.f, 0.f, 0.f, 0.f};
                 }
             }
         }
@@ -695,26 +705,29 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
     int64_t t = wg;
     if (t < a.tiles) fetch(t);
     for (; t < a.tiles; t += a.nwg) {
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int cg = rr * CGR + cgl;
             if (cg < NCG) {
+                f4_t v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = cv[rr][q] ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {   // column q, rows rg*4 .. rg*4+3
-                    const uint64_t pk = (uint64_t)pack_bf16x2(pf[rr][q][0], pf[rr][q][1]) |
-                                        ((uint64_t)pack_bf16x2(pf[rr][q][2], pf[rr][q][3]) << 32);
+                    const uint64_t pk = (uint64_t)pack_bf16x2(v[q][0], v[q][1]) |
+                                        ((uint64_t)pack_bf16x2(v[q][2], v[q][3]) << 32);
                     *(uint64_t*)&Cs[(cg * 4 + q) * ldC + rg * 4] = pk;
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {   // row rg*4+e, columns cg*4 .. cg*4+3
-                    const uint64_t pk = (uint64_t)pack_bf16x2(pf[rr][0][e], pf[rr][1][e]) |
-                                        ((uint64_t)pack_bf16x2(pf[rr][2][e], pf[rr][3][e]) << 32);
+                    const uint64_t pk = (uint64_t)pack_bf16x2(v[0][e], v[1][e]) |
+                                        ((uint64_t)pack_bf16x2(v[2][e], v[3][e]) << 32);
                     *(uint64_t*)&Cr[(rg * 4 + e) * ldR + cg * 4] = pk;
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
 
         // Phase A: Y_tile = C_tile X (X fragments in registers); for IB == 1 two
@@ -739,7 +752,7 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
                     (uint64_t)pack_bf16x2(y[0], y[1]) | ((uint64_t)pack_bf16x2(y[2], y[3]) << 32);
             }
         }
-        __syncthreads();
+        lds_barrier();
 
         // Phase B: P (NP x 64) += C_tile^T Y_tile; wave w owns row blocks w, w + 8, ...
 #pragma unroll
@@ -893,23 +906,29 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
         }
     const int64_t rows = a.seg.rows;
     f4_t pf[RMAX][4];
+    // The loads only: nothing here reads the loaded values, so they stay in
+    // flight until the tile is converted (columns >= n are zeroed there).  The
+    // full-tile test is one branch around all loads.
     auto fetch = [&](int64_t t) {
         const int64_t row = t * TM + rg * 4;
-        const bool full = a.vec && (t + 1) * TM <= rows;
+        if (a.vec && (t + 1) * TM <= rows) {                 // uniform
 #pragma unroll
-        for (int rr = 0; rr < RMAX; ++rr) {
-            if (rr * CGR + cgl < NCG) {
+            for (int rr = 0; rr < RMAX; ++rr)
+                if (rr * CGR + cgl < NCG)                    // uniform per wave
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
-                    if (full) {
-                        v = gld4(cp[rr][q] + row);
-                    } else {
+                    for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + row);
+        } else {
+#pragma unroll
+            for (int rr = 0; rr < RMAX; ++rr) {
+                if (rr * CGR + cgl < NCG) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
                             if (row + e < rows) v[e] = gld(cp[rr][q] + row + e);
+                        pf[rr][q] = v;
                     }
-                    pf[rr][q] = cv[rr][q] ? v : f4_t{0.f, 0.f, 0.f, 0.f};
                 }
             }
         }
@@ -922,11 +941,14 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
         for (int rr = 0; rr < RMAX; ++rr) {
             const int cg = rr * CGR + cgl;
             if (cg < NCG) {
+                f4_t v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = cv[rr][q] ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     uint32_t h0, l0, h1, l1;
-                    split_bf16x2(pf[rr][0][e], pf[rr][1][e], &h0, &l0);
-                    split_bf16x2(pf[rr][2][e], pf[rr][3][e], &h1, &l1);
+                    split_bf16x2(v[0][e], v[1][e], &h0, &l0);
+                    split_bf16x2(v[2][e], v[3][e], &h1, &l1);
                     *(uint64_t*)&Crh[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)h0 | ((uint64_t)h1 << 32);
                     *(uint64_t*)&Crl[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)l0 | ((uint64_t)l1 << 32);
                 }
@@ -940,7 +962,7 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
         store_tile(0);
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
     }
-    __syncthreads();
+    lds_barrier();
     for (int b = 0; t < a.tiles; t += a.nwg, b ^= 1) {
         const uint16_t* Crh = Cb + b * CBUF;
         const uint16_t* Crl = Crh + TM * ldR;
@@ -976,7 +998,7 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
 
         // The next tile: split into the other buffer (read by no wave in this
         // interval), then the loads of the one after it.
@@ -1030,7 +1052,7 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
                 for (int v = 0; v < 4; ++v) accG[j][v] += (double)g[v];
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
 #pragma unroll

@@ -40,6 +40,20 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 // FLAT loads, which also count against the LDS wait counter: every wait for
 // an LDS read would then wait for all prefetched tile loads too.  Accesses
 // through these views are plain global loads and stores.
+// Work-group barrier for LDS hand-offs only: waits for this wave's LDS
+// operations (lgkmcnt(0); the vector-memory and export counters are left at
+// their maximum), then s_barrier.  __syncthreads() also waits for every
+// outstanding global load, which would end the prefetch of the next tile at
+// each barrier; the tall-panel kernels exchange data between waves only
+// through LDS, so this barrier is enough for them.  The signal fences keep
+// the compiler from moving memory operations across it.
+__device__ __forceinline__ void lds_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // gfx9 encoding: vmcnt 63, expcnt 7, lgkmcnt 0
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 #define PSVD_GLOBAL __attribute__((address_space(1)))
 __device__ __forceinline__ f4_t gld4(const float* p) { return *(const PSVD_GLOBAL f4_t*)p; }
 __device__ __forceinline__ float gld(const float* p) { return *(const PSVD_GLOBAL float*)p; }
