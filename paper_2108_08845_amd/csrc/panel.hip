@@ -361,7 +361,7 @@ __device__ __forceinline__ FusedCoords fused_coords(const FusedArgs& a) {
 //   MODE 1: P and G = (C X)^T (C X)    (final pass; Y optionally kept)
 //   MODE 2: out = C X                  (lift)
 // ----------------------------------------------------------------------------
-template <int TM, int NP, int MODE>
+template <int TM, int NP, int MODE, bool VEC>
 __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     constexpr int NT = 512;
     constexpr int TPC = TM / 4;
@@ -418,10 +418,13 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     // full-tile test is one branch around all loads.
     auto fetch = [&](int64_t t) {
         const int64_t row = t * TM + tsub * 4;
-        if (a.vec && (t + 1) * TM <= rows) {                 // uniform
+        if constexpr (VEC) {
+            // rows % 4 == 0: a float4 is all inside or all past the end; past
+            // the end it reads the last rows again and is zeroed at the store
+            const int64_t rowc = row < rows ? row : rows - 4;
 #pragma unroll
             for (int rr = 0; rr < RMAX; ++rr)
-                if (rr * CPR + tcol < NP) pf[rr] = gld4(cp[rr] + row);   // uniform per wave
+                if (rr * CPR + tcol < NP) pf[rr] = gld4(cp[rr] + rowc);   // uniform per wave
         } else {
 #pragma unroll
             for (int rr = 0; rr < RMAX; ++rr) {
@@ -440,10 +443,11 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     if (t < a.tiles) fetch(t);
     for (; t < a.tiles; t += a.nwg) {
         lds_barrier();
+        const bool rv = t * TM + tsub * 4 < rows;
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int c = rr * CPR + tcol;
-            if (c < NP) *(f4_t*)&Cs[c * ldC + tsub * 4] = cv[rr] ? pf[rr] : f4_t{0.f, 0.f, 0.f, 0.f};
+            if (c < NP) *(f4_t*)&Cs[c * ldC + tsub * 4] = (cv[rr] && rv) ? pf[rr] : f4_t{0.f, 0.f, 0.f, 0.f};
         }
         lds_barrier();
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
@@ -499,7 +503,7 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
             float* obase = MODE == 2 ? (float*)a.seg.out : a.yout;
             const int64_t ldo = MODE == 2 ? a.seg.ldo : a.ldy;
             const int64_t row = t * TM + tsub * 4;
-            const bool full = a.vec && (t + 1) * TM <= rows;
+            const bool full = VEC && row < rows;   // VEC: rows % 4 == 0, a float4 is whole in or out
 #pragma unroll
             for (int j0 = 0; j0 < FU_LB; j0 += CPR) {
                 const int j = j0 + tcol;
@@ -508,7 +512,7 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
                     float* o = obase + (size_t)(c0 + j) * (size_t)ldo;
                     if (full) {
                         gst4(o + row, v);
-                    } else {
+                    } else if (!VEC) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
                             if (row + q < rows) gst(o + row + q, v[q]);
@@ -604,7 +608,7 @@ __device__ __forceinline__ bf8_t lds_b128(const uint16_t* p) {
     return __builtin_bit_cast(bf8_t, *(const s8_t*)p);   // 16-byte aligned by construction
 }
 
-template <int TM, int NKS>
+template <int TM, int NKS, bool VEC>
 __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
     constexpr int NT = 512;
     constexpr int NP = NKS * 32;
@@ -679,12 +683,15 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
     // full-tile test is one branch around all loads.
     auto fetch = [&](int64_t t) {
         const int64_t row = t * TM + rg * 4;
-        if (a.vec && (t + 1) * TM <= rows) {                 // uniform
+        if constexpr (VEC) {
+            // rows % 4 == 0: a float4 is all inside or all past the end; past
+            // the end it reads the last rows again and is zeroed at the store
+            const int64_t rowc = row < rows ? row : rows - 4;
 #pragma unroll
             for (int rr = 0; rr < RMAX; ++rr)
                 if (rr * CGR + cgl < NCG)                    // uniform per wave
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + row);
+                    for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + rowc);
         } else {
 #pragma unroll
             for (int rr = 0; rr < RMAX; ++rr) {
@@ -706,13 +713,14 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
     if (t < a.tiles) fetch(t);
     for (; t < a.tiles; t += a.nwg) {
         lds_barrier();
+        const bool rv = t * TM + rg * 4 < rows;
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int cg = rr * CGR + cgl;
             if (cg < NCG) {
                 f4_t v[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = cv[rr][q] ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
+                for (int q = 0; q < 4; ++q) v[q] = (cv[rr][q] && rv) ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {   // column q, rows rg*4 .. rg*4+3
                     const uint64_t pk = (uint64_t)pack_bf16x2(v[q][0], v[q][1]) |
@@ -743,6 +751,9 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
                     const bf8_t av = lds_b128(&Cr[((ib0 + b) * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4)]);
                     accY[b][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[ks], accY[b][ks & 1], 0, 0, 0);
                 }
+                // at most two k-steps of A fragments live at a time: the registers of
+                // the prefetched tile stay its own across the products
+                if (ks & 1) __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int b = 0; b < IB; ++b) {   // rows 4*(lane/16) .. +3 of the block: one 8-byte store
@@ -834,7 +845,7 @@ __device__ __forceinline__ bf8_t lds_colfrag(const uint16_t* tile, int ld, int c
     return __builtin_bit_cast(bf8_t, v);
 }
 
-template <int NKS>
+template <int NKS, bool VEC>
 __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
     constexpr int TM = 32, NT = 512;
     constexpr int NP = NKS * 32;
@@ -911,12 +922,15 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
     // full-tile test is one branch around all loads.
     auto fetch = [&](int64_t t) {
         const int64_t row = t * TM + rg * 4;
-        if (a.vec && (t + 1) * TM <= rows) {                 // uniform
+        if constexpr (VEC) {
+            // rows % 4 == 0: a float4 is all inside or all past the end; past
+            // the end it reads the last rows again and is zeroed at the store
+            const int64_t rowc = row < rows ? row : rows - 4;
 #pragma unroll
             for (int rr = 0; rr < RMAX; ++rr)
                 if (rr * CGR + cgl < NCG)                    // uniform per wave
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + row);
+                    for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + rowc);
         } else {
 #pragma unroll
             for (int rr = 0; rr < RMAX; ++rr) {
@@ -933,17 +947,18 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
             }
         }
     };
-    // split the fetched tile into buffer b: row rg*4+e, columns cg*4 .. cg*4+3
-    auto store_tile = [&](int b) {
+    // split the fetched tile (index tl) into buffer b: row rg*4+e, columns cg*4 .. cg*4+3
+    auto store_tile = [&](int b, int64_t tl) {
         uint16_t* Crh = Cb + b * CBUF;
         uint16_t* Crl = Crh + TM * ldR;
+        const bool rv = tl * TM + rg * 4 < rows;
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int cg = rr * CGR + cgl;
             if (cg < NCG) {
                 f4_t v[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = cv[rr][q] ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
+                for (int q = 0; q < 4; ++q) v[q] = (cv[rr][q] && rv) ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     uint32_t h0, l0, h1, l1;
@@ -959,7 +974,7 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
     int64_t t = wg;
     if (t < a.tiles) {
         fetch(t);
-        store_tile(0);
+        store_tile(0, t);
         if (t + a.nwg < a.tiles) fetch(t + a.nwg);
     }
     lds_barrier();
@@ -989,9 +1004,9 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
             if (a.yout != nullptr && c0 + col < a.lx) {
                 const int64_t row = t * TM + r0;
                 float* o = a.yout + (size_t)(c0 + col) * (size_t)a.ldy + row;
-                if (a.vec && row + 3 < rows) {
+                if (VEC ? row < rows : row + 3 < rows) {   // VEC: rows % 4 == 0
                     gst4(o, y);
-                } else {
+                } else if (!VEC) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                         if (row + q < rows) gst(o + q, y[q]);
@@ -1003,7 +1018,7 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
         // The next tile: split into the other buffer (read by no wave in this
         // interval), then the loads of the one after it.
         if (t + a.nwg < a.tiles) {
-            store_tile(b ^ 1);
+            store_tile(b ^ 1, t + a.nwg);
             if (t + 2 * (int64_t)a.nwg < a.tiles) fetch(t + 2 * (int64_t)a.nwg);
         }
 
@@ -1152,7 +1167,9 @@ hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st) {
     const int nks = a.np / 32;
     if (a.np % 32 || (a.tm != 32 && a.tm != 64)) return hipErrorInvalidValue;
 #define SK(TM_, NKS_) \
-    if (a.tm == TM_ && nks == NKS_) return launch_512(k_sketch_bf16<TM_, NKS_>, a, lds, st);
+    if (a.tm == TM_ && nks == NKS_) \
+        return a.vec ? launch_512(k_sketch_bf16<TM_, NKS_, true>, a, lds, st) \
+                     : launch_512(k_sketch_bf16<TM_, NKS_, false>, a, lds, st);
     SK(64, 2) SK(64, 4) SK(64, 6) SK(64, 8) SK(64, 10) SK(64, 12)
     SK(32, 2) SK(32, 4) SK(32, 6) SK(32, 8) SK(32, 10) SK(32, 12) SK(32, 16) SK(32, 20)
 #undef SK
@@ -1180,16 +1197,18 @@ hipError_t launch_final_split(const FusedArgs& a, hipStream_t st) {
     const size_t lds = split_lds(a.np);
     const int nks = a.np / 32;
 #define FS(NKS_) \
-    if (nks == NKS_) return launch_512(k_final_split<NKS_>, a, lds, st);
+    if (nks == NKS_) \
+        return a.vec ? launch_512(k_final_split<NKS_, true>, a, lds, st) \
+                     : launch_512(k_final_split<NKS_, false>, a, lds, st);
     FS(2) FS(4) FS(6) FS(8) FS(10) FS(12)
 #undef FS
     return hipErrorInvalidValue;
 }
 
-template <int MODE>
+template <int MODE, bool VEC>
 static hipError_t launch_fused_mode(const FusedArgs& a, size_t lds, hipStream_t st) {
 #define FU(TM_, NP_) \
-    if (a.tm == TM_ && a.np == NP_) return launch_512(k_fused<TM_, NP_, MODE>, a, lds, st);
+    if (a.tm == TM_ && a.np == NP_) return launch_512(k_fused<TM_, NP_, MODE, VEC>, a, lds, st);
     FU(64, 64) FU(64, 128) FU(64, 192) FU(64, 256)
     FU(32, 64) FU(32, 128) FU(32, 192) FU(32, 256) FU(32, 320) FU(32, 384)
     FU(16, 448)
@@ -1201,9 +1220,14 @@ hipError_t launch_fused(int mode, const FusedArgs& a, hipStream_t st) {
     if (!fused_compiled(a.tm, a.np)) return hipErrorInvalidValue;
     const size_t lds = fused_lds(a.tm, a.np);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    if (mode == 0) return launch_fused_mode<0>(a, lds, st);
-    if (mode == 1) return launch_fused_mode<1>(a, lds, st);
-    return launch_fused_mode<2>(a, lds, st);
+    if (a.vec) {
+        if (mode == 0) return launch_fused_mode<0, true>(a, lds, st);
+        if (mode == 1) return launch_fused_mode<1, true>(a, lds, st);
+        return launch_fused_mode<2, true>(a, lds, st);
+    }
+    if (mode == 0) return launch_fused_mode<0, false>(a, lds, st);
+    if (mode == 1) return launch_fused_mode<1, false>(a, lds, st);
+    return launch_fused_mode<2, false>(a, lds, st);
 }
 
 // Fixed-order FP64 sum of the fused partials: P (n x lx, ld n) and G (lx x lx).
