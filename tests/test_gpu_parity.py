@@ -216,6 +216,27 @@ def test_mixed_matches_oracle(cfg):
     assert orth_err(U) <= 1e-5
 
 
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+@pytest.mark.parametrize("M", [3000, 5001])
+def test_randomized_ragged_rows(M, precision):
+    # M = 3000: float4-aligned panel with a partial last tile (the clamped
+    # loads past the end must be zeroed); M = 5001: not a multiple of 4, so the
+    # panel is not float4-aligned and the fused passes take their per-element path.
+    w = reduced_c2(M=M, batches=3)
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, precision, True)
+    so = run_oracle(w, batches, True, oracle.PREC_F32 if precision == "fp32" else oracle.PREC_BF16)
+    if precision == "fp32":
+        compare(U, s, so, 1e-4, 1e-5, f"rand fp32 M={M}")
+    else:
+        s_ref = so.singular_values
+        k10 = resolved_modes(s_ref, 10.0)
+        assert k10 >= 3
+        assert sigma_rel_err(s[:k10], s_ref[:k10]) <= 1e-5, sigma_rel_err(s[:k10], s_ref[:k10])
+        assert sigma_rel_err(s, s_ref) <= 1e-1
+        assert orth_err(U) <= 1e-5
+
+
 def test_randomized_exact_low_rank_planted():
     # rank <= sketch width, K >= rank, no noise: no truncation loss, so every
     # update is exact and the stream recovers the planted spectrum.
