@@ -733,10 +733,22 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
                                         ((uint64_t)pack_bf16x2(v[2][e], v[3][e]) << 32);
                     *(uint64_t*)&Cr[(rg * 4 + e) * ldR + cg * 4] = pk;
                 }
+                if constexpr (VEC) {
+                    // this group's registers are free: its loads of the next tile
+                    // go out now, so memory stays busy through the store
+                    const int64_t tn = t + a.nwg;
+                    if (tn < a.tiles) {
+                        const int64_t row = tn * TM + rg * 4;
+                        const int64_t rowc = row < rows ? row : rows - 4;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + rowc);
+                    }
+                }
             }
         }
         lds_barrier();
-        if (t + a.nwg < a.tiles) fetch(t + a.nwg);
+        if constexpr (!VEC)
+            if (t + a.nwg < a.tiles) fetch(t + a.nwg);
 
         // Phase A: Y_tile = C_tile X (X fragments in registers); for IB == 1 two
         // interleaved accumulators keep consecutive matrix-core ops independent.
