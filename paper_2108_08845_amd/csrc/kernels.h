@@ -137,6 +137,7 @@ struct OrthArgs {
 struct RandFinalArgs {
     int32_t n, l, K;
     int32_t max_sweeps;
+    double stop_cos2;     // Jacobi (l <= 64) ends after a sweep with largest cos^2 <= this (0: m 2^-53)
     const double* P;      // n x l (ld n): C^T Y
     double* P1;           // n x l scratch: P R1^-1
     const double* GY;     // l x l: Y^T Y
@@ -227,6 +228,8 @@ hipError_t launch_status_fold(int32_t* st, hipStream_t stream);
 hipError_t launch_small_rand_final(const RandFinalArgs& a, hipStream_t st);
 hipError_t launch_scale_rows(double* X, int n, int m, int ldx, const double* d, int r, int times, hipStream_t st);
 hipError_t launch_make_scale(double* d, const double* s, int r, double ff, hipStream_t st);
+hipError_t launch_rand_begin(int32_t* status, double* d, const double* s, int r, double ff, double* X,
+                             const double* Om, int n, int l, hipStream_t st);
 hipError_t launch_apmos_local(const ApmosLocalArgs& a, hipStream_t st);
 hipError_t launch_apmos_global(const ApmosGlobalArgs& a, hipStream_t st);
 

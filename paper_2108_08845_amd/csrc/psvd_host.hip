@@ -184,7 +184,10 @@ struct psvd_handle {
     DevBuf status;      // int32 x 2: status, sweeps
     int32_t* status_host = nullptr;  // pinned
     double* omega_host[2] = {nullptr, nullptr};  // pinned staging, alternating per update
-    hipEvent_t omega_ev[2] = {nullptr, nullptr};
+    hipEvent_t omega_ev[2] = {nullptr, nullptr};  // upload of buffer b done (copy stream)
+    hipEvent_t omega_used[2] = {nullptr, nullptr};  // device buffer b read by its update (main stream)
+    DevBuf omega_dev[2];                          // device copies, alternating per update
+    hipStream_t cstream = nullptr;                // uploads of the test matrix
     size_t omega_host_cap = 0;
 
     psvd_stats_t stats;
@@ -550,8 +553,11 @@ int psvd_initialize(psvd_handle** out, int64_t M, int32_t K, double ff, int32_t 
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->status_host, 64, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&h->ev0);
     if (e == hipSuccess) e = hipEventCreate(&h->ev1);
-    if (e == hipSuccess) e = hipEventCreate(&h->omega_ev[0]);
-    if (e == hipSuccess) e = hipEventCreate(&h->omega_ev[1]);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = hipEventCreateWithFlags(&h->omega_ev[b], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->omega_used[b], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cstream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMemsetAsync(h->U[0].p, 0, h->U[0].bytes, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->U[1].p, 0, h->U[1].bytes, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->s[0].p, 0, h->s[0].bytes, h->stream);
@@ -581,9 +587,15 @@ void psvd_finalize(psvd_handle* h) {
     h->ivec.release();
     h->status.release();
     if (h->status_host) (void)hipHostFree(h->status_host);
+    if (h->cstream) {
+        (void)hipStreamSynchronize(h->cstream);
+        (void)hipStreamDestroy(h->cstream);
+    }
     for (int b = 0; b < 2; ++b) {
         if (h->omega_host[b]) (void)hipHostFree(h->omega_host[b]);
         if (h->omega_ev[b]) (void)hipEventDestroy(h->omega_ev[b]);
+        if (h->omega_used[b]) (void)hipEventDestroy(h->omega_used[b]);
+        h->omega_dev[b].release();
     }
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -687,8 +699,10 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
     double* s_new = h->s[nxt].as<double>();
 
     HIPCHK(h, hipEventRecord(h->ev0, st));
-    HIPCHK(h, hipMemsetAsync(dstat, 0, 8, st));
-    HIPCHK(h, launch_make_scale(h->d.as<double>(), s_cur, r, h->ff, st));
+    if (!randomized) {   // the randomized start does both in one launch (k_rand_begin)
+        HIPCHK(h, hipMemsetAsync(dstat, 0, 8, st));
+        HIPCHK(h, launch_make_scale(h->d.as<double>(), s_cur, r, h->ff, st));
+    }
 
     // Panel [U | A] (unscaled) and its lift output.
     PanelSeg C = make_seg(M);
@@ -761,27 +775,40 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         if (rc) return rc;
     } else {
         // ---- randomized range finder ----
+        // Omega is generated on the host (the published Philox4x32-10 / Box-Muller
+        // definition, bit-identical to the reference generator) and uploaded on
+        // a copy stream into one of two device buffers, so the copy overlaps the
+        // previous update; the main stream waits for it before k_rand_begin.
         size_t need = (size_t)n * l;
         const int ob = (int)(h->batch & 1);
         if (need > h->omega_host_cap) {
             HIPCHK(h, hipStreamSynchronize(st));
+            HIPCHK(h, hipStreamSynchronize(h->cstream));
             for (int b = 0; b < 2; ++b) {
                 if (h->omega_host[b]) (void)hipHostFree(h->omega_host[b]);
                 h->omega_host[b] = nullptr;
             }
             h->omega_host_cap = 0;
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < 2; ++b) {
                 HIPCHK(h, hipHostMalloc((void**)&h->omega_host[b], need * sizeof(double), hipHostMallocDefault));
+                HIPCHK(h, h->omega_dev[b].ensure(need * sizeof(double)));
+            }
             h->omega_host_cap = need;
         } else {
-            // the update two batches back may still be copying from this buffer
+            // the upload two batches back may still be reading this host buffer
             HIPCHK(h, hipEventSynchronize(h->omega_ev[ob]));
         }
         gen_omega(h->opt.seed, h->batch, n, l, omega_rounding(prec), h->omega_host[ob]);
-        HIPCHK(h, hipMemcpyAsync(L.X, h->omega_host[ob], need * sizeof(double), hipMemcpyHostToDevice, st));
-        HIPCHK(h, hipEventRecord(h->omega_ev[ob], st));
-        // X' = D Omega
-        HIPCHK(h, launch_scale_rows(L.X, n, l, n, dsc, r, 1, st));
+        // the device buffer is free once the update two batches back has read it
+        HIPCHK(h, hipStreamWaitEvent(h->cstream, h->omega_used[ob], 0));
+        HIPCHK(h, hipMemcpyAsync(h->omega_dev[ob].p, h->omega_host[ob], need * sizeof(double), hipMemcpyHostToDevice,
+                                 h->cstream));
+        HIPCHK(h, hipEventRecord(h->omega_ev[ob], h->cstream));
+        HIPCHK(h, hipStreamWaitEvent(st, h->omega_ev[ob], 0));
+        // status cleared, d = ff s, X' = D Omega
+        HIPCHK(h, launch_rand_begin(dstat, h->d.as<double>(), s_cur, r, h->ff, L.X, h->omega_dev[ob].as<double>(), n,
+                                    l, st));
+        HIPCHK(h, hipEventRecord(h->omega_used[ob], st));
         const int nlb = ceil_div(l, 64);
         auto pass = [&](bool bf16, bool want_g) -> int {
             // P = D C'^T (C' X')  [+ G_Y = Y^T Y]
@@ -862,6 +889,9 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         rf.l = l;
         rf.K = h->K;
         rf.max_sweeps = h->opt.max_sweeps;
+        // FP32 / mixed results carry FP32 rounding: the small SVD stops once a sweep's
+        // cosines are below 2^-15 (the next sweep would leave ~2^-30); FP64 runs to m 2^-53
+        rf.stop_cos2 = fp64 ? 0.0 : 0x1p-30;
         rf.P = L.P;
         rf.P1 = L.P1;
         rf.GY = L.G_Y;

@@ -520,17 +520,19 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
 //  - the angle term sqrt((be - al)^2 + 4 g^2) takes the hardware square root
 //    (it only sets the angle; the rotation stays orthogonal to rounding since
 //    c and s share one correctly rounded reciprocal square root), and
-//  - a sweep whose largest squared cosine g^2 / (al be) is at most tol ends the
-//    iteration: convergence is quadratic, so the sweep after it would only
-//    confirm cosines near tol.
+//  - a sweep whose largest squared cosine g^2 / (al be) is at most
+//    max(stop_cos2, tol) ends the iteration: convergence is quadratic, so the
+//    next sweep would take the cosines to about the square of that bound
+//    (tol: the sweep after it would only confirm cosines near tol).
 // mx: 65 doubles of scratch.  Returns the sweep count (> max_sweeps: not
 // converged); results as wg_jacobi.
 __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* sig, int* order, double* nrm,
-                                               int max_sweeps, int* sflag, double* mx) {
+                                               int max_sweeps, int* sflag, double* mx, double stop_cos2) {
     constexpr int ldz = 64;
     const int tid = threadIdx.x;
     const int ql = tid & 15, qw = tid >> 4, nq = blockDim.x >> 4;
     const double tol = (double)m * 0x1p-53;
+    const double stop = stop_cos2 > tol ? stop_cos2 : tol;
     const int ne = n + (n & 1);
     // quarter-wave qw < ne / 2 holds round-robin positions qw and ne - 1 - qw
     const int pa = qw, pb = ne - 1 - qw;
@@ -618,7 +620,7 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
         }
         ++sweep;
         __syncthreads();
-        const bool done = !*sflag || mx[64] <= tol;
+        const bool done = !*sflag || mx[64] <= stop;
         __syncthreads();
         if (done) break;
     }
@@ -988,7 +990,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     double* sig = vec;
     double* nrm = sig + l;
     int* ord = (int*)(nrm + l + 1);
-    const int sw = staged ? wg_jacobi_pad64(W, l, l, sig, ord, nrm, a.max_sweeps, &sflag, red)
+    const int sw = staged ? wg_jacobi_pad64(W, l, l, sig, ord, nrm, a.max_sweeps, &sflag, red, a.stop_cos2)
                           : wg_jacobi(W, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
@@ -1029,6 +1031,24 @@ __global__ void k_scale_rows(double* X, int n, int m, int ldx, const double* d, 
         double v = X[i + (size_t)j * ldx];
         for (int t = 0; t < times; ++t) v *= f;
         X[i + (size_t)j * ldx] = v;
+    }
+}
+
+// Start of a randomized update, one launch: the status words are cleared,
+// d[j] = ff s[j] (j < r) and X = D Omega (rows i < r of the n x l test matrix
+// multiplied by d[i]; Omega and X column-major with leading dimension n).
+__global__ void k_rand_begin(int32_t* st, double* d, const double* s, int r, double ff, double* X,
+                             const double* Om, int n, int l) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) {
+        st[0] = 0;
+        st[1] = 0;
+    }
+    if (e < r) d[e] = ff * s[e];
+    if (e < n * l) {
+        const int i = e % n;
+        const double v = Om[e];
+        X[e] = i < r ? (ff * s[i]) * v : v;
     }
 }
 
@@ -1157,6 +1177,12 @@ hipError_t launch_status_fold(int32_t* st, hipStream_t stream) {
 hipError_t launch_scale_rows(double* X, int n, int m, int ldx, const double* d, int r, int times, hipStream_t st) {
     if (r <= 0 || n * m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scale_rows, dim3((n * m + 255) / 256), dim3(256), 0, st, X, n, m, ldx, d, r, times);
+    return hipGetLastError();
+}
+hipError_t launch_rand_begin(int32_t* status, double* d, const double* s, int r, double ff, double* X,
+                             const double* Om, int n, int l, hipStream_t st) {
+    const int total = n * l > r ? n * l : (r > 0 ? r : 1);
+    hipLaunchKernelGGL(k_rand_begin, dim3((total + 255) / 256), dim3(256), 0, st, status, d, s, r, ff, X, Om, n, l);
     return hipGetLastError();
 }
 hipError_t launch_make_scale(double* d, const double* s, int r, double ff, hipStream_t st) {
