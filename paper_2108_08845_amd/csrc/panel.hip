@@ -597,9 +597,13 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
 // k_sketch_bf16: the BF16 power pass P += C^T (C X) with the 16x16x32 BF16
 // matrix-core instruction.  NP = 32 NKS columns (columns n .. NP-1 zero).
 // X (NP x 64) lives in registers for the whole launch; every tile is read
-// once from HBM, converted to BF16 and written to LDS twice (column-major for
-// C^T Y, row-major for C X) with packed stores: each thread moves a 4 x 4
-// block (four float4 column segments).
+// once from HBM, converted to BF16 and written to LDS once, row-major, with
+// packed stores (each thread moves a 4 x 4 block: four float4 column
+// segments).  C X reads row fragments of that copy, C^T Y column fragments by
+// transpose loads.  Two tile buffers: the conversion and store of the next
+// tile, with the loads of the tile after it (issued group by group as the
+// registers are stored, on float4-aligned panels), share the barrier interval
+// of this tile's C^T Y.
 // ----------------------------------------------------------------------------
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef short s8_t __attribute__((ext_vector_type(8)));
@@ -608,25 +612,45 @@ __device__ __forceinline__ bf8_t lds_b128(const uint16_t* p) {
     return __builtin_bit_cast(bf8_t, *(const s8_t*)p);   // 16-byte aligned by construction
 }
 
+typedef short s4v_t __attribute__((__vector_size__(4 * sizeof(short))));
+typedef __attribute__((address_space(3))) s4v_t lds_s4v_t;
+
+// Transpose load of 16-bit data.  Within each group of 16 lanes, lane i gets
+// element i % 4 of the 8-byte chunks addressed by lanes i / 4, 4 + i / 4,
+// 8 + i / 4 and 12 + i / 4 of the group (in that order).
+__device__ __forceinline__ s4v_t lds_tr16(const uint16_t* p) {
+    return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4v_t*)(__attribute__((address_space(3))) uint16_t*)p);
+}
+
+// Column fragment of the 16x16x32 A operand of C^T Y: lane (l, g) = (lane & 15,
+// lane >> 4) receives rows 8 g .. 8 g + 7 of column c0 + l of the row-major tile
+// (leading dimension ld).  Two transpose loads of four rows each; lane (l, g)
+// addresses row 8 g + 4 h + l / 4, columns c0 + 4 (l % 4) .. + 3.
+__device__ __forceinline__ bf8_t lds_colfrag(const uint16_t* tile, int ld, int c0, int lane) {
+    const int l = lane & 15, g = lane >> 4;
+    const uint16_t* p = tile + (8 * g + (l >> 2)) * ld + c0 + 4 * (l & 3);
+    const s4v_t lo4 = lds_tr16(p), hi4 = lds_tr16(p + 4 * ld);
+    const s8_t v = (s8_t){lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
+    return __builtin_bit_cast(bf8_t, v);
+}
+
 template <int TM, int NKS, bool VEC>
 __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
     constexpr int NT = 512;
     constexpr int NP = NKS * 32;
-    constexpr int NCG = NP / 4;                     // column groups of 4
-    // Phase A: (TM/16) x 4 blocks of Y over 8 waves; each wave takes IB row
-    // blocks of one column block (X fragments of that column block in registers).
-    constexpr int IB = TM / 32;                     // row blocks of Y per wave in phase A
-    constexpr int RG = TM / 4;                      // row groups of 4
-    constexpr int CGR = NT / RG;                    // column groups per round
+    constexpr int NCG = NP / 4;
+    constexpr int IB = TM / 32;
+    constexpr int RG = TM / 4;
+    constexpr int CGR = NT / RG;
     constexpr int RMAX = (NCG + CGR - 1) / CGR;
-    constexpr int NRBLK = NP / 16;                  // phase-B row blocks
-    constexpr int QB = (NRBLK + 7) / 8;
-    constexpr int ldC = TM + 8, ldR = NP + 8, ldY = TM + 8;
+    constexpr int NIT = NKS / 2;                    // C^T Y items per wave: (16-row block, 32-column pair)
+    static_assert(NKS % 2 == 0, "an even number of 32-column slices");
+    constexpr int ldR = NP + 8, ldY = TM + 8;
+    constexpr int CBUF = TM * ldR;
     static_assert(TM == 32 || TM == 64, "tile height");
     extern __shared__ __align__(16) unsigned char smem[];
-    uint16_t* Cs = (uint16_t*)smem;                 // NP x TM, column-major
-    uint16_t* Cr = Cs + NP * ldC;                   // TM x NP, row-major
-    uint16_t* Ys = Cr + TM * ldR;                   // 64 x TM, column-major
+    uint16_t* Cb = (uint16_t*)smem;                 // two TM x NP row-major tile buffers
+    uint16_t* Ys = Cb + 2 * CBUF;                   // 64 x TM, column-major
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -634,16 +658,13 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
     if (fc.wg >= a.nwg) return;
     const int wg = fc.wg, lb = fc.lb;
     const int c0 = lb * FU_LB;
-
-    // Phase-A unit of this wave: row blocks ib0 .. ib0 + IB - 1 of column block jb.
     const int jb = w & 3;
     const int ib0 = (w >> 2) * IB;
-    // X block -> LDS as BF16 (the tile buffers are free until the first tile),
-    // then into registers as the B fragments of phase A.
     bf8_t xf[NKS];
     {
         constexpr int ldxs = NP + 8;
-        uint16_t* Xb = Cs;   // 64 x ldxs halfwords fit in the Cs and Cr buffers
+        static_assert(FU_LB * ldxs <= 2 * CBUF, "X staging must fit the tile buffers");
+        uint16_t* Xb = Cb;
         stage_x<NP, NT>(a, c0, [&](int k, int j, double v) { Xb[j * ldxs + k] = f32_to_bf16_rne((float)v); });
         __syncthreads();
 #pragma unroll
@@ -652,20 +673,14 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
         __syncthreads();
     }
 
-    f4_t accP[QB * 4];
+    f4_t accP[NIT * 2];
 #pragma unroll
-    for (int t = 0; t < QB * 4; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < NIT * 2; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    // Thread -> (row group rg, column group cgl).  The 16 lanes of each LDS
-    // store group span 4 row groups x 4 column groups (at most 2-way bank
-    // conflicts on both tile copies); a wave covers all RG row groups of
-    // 64 / RG consecutive column groups, so each float4 load instruction
-    // reads whole TM-row column segments.
-    constexpr int RGH = RG / 4;                       // high row-group values per wave
+    constexpr int RGH = RG / 4;
     constexpr int RGH_LOG = RGH == 4 ? 2 : (RGH == 2 ? 1 : 0);
     const int rg = (tid & 3) | (((tid >> 4) & (RGH - 1)) << 2);
     const int cgl = ((tid >> 2) & 3) | ((tid >> (4 + RGH_LOG)) << 2);
-    // Per-thread column pointers: columns (rr * CGR + cgl) * 4 + q.
     const float* cp[RMAX][4];
     bool cv[RMAX][4];
 #pragma unroll
@@ -678,18 +693,13 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
         }
     const int64_t rows = a.seg.rows;
     f4_t pf[RMAX][4];
-    // The loads only: nothing here reads the loaded values, so they stay in
-    // flight until the tile is converted (columns >= n are zeroed there).  The
-    // full-tile test is one branch around all loads.
     auto fetch = [&](int64_t t) {
         const int64_t row = t * TM + rg * 4;
         if constexpr (VEC) {
-            // rows % 4 == 0: a float4 is all inside or all past the end; past
-            // the end it reads the last rows again and is zeroed at the store
             const int64_t rowc = row < rows ? row : rows - 4;
 #pragma unroll
             for (int rr = 0; rr < RMAX; ++rr)
-                if (rr * CGR + cgl < NCG)                    // uniform per wave
+                if (rr * CGR + cgl < NCG)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + rowc);
         } else {
@@ -708,12 +718,11 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
             }
         }
     };
-
-    int64_t t = wg;
-    if (t < a.tiles) fetch(t);
-    for (; t < a.tiles; t += a.nwg) {
-        lds_barrier();
-        const bool rv = t * TM + rg * 4 < rows;
+    // tile tl (in pf) -> buffer b as BF16, row rg*4+e, columns cg*4 .. cg*4+3; on
+    // aligned panels each group's loads of tile tn go out once its registers are stored
+    auto store_tile = [&](int b, int64_t tl, int64_t tn) {
+        uint16_t* Cr = Cb + b * CBUF;
+        const bool rv = tl * TM + rg * 4 < rows;
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int cg = rr * CGR + cgl;
@@ -722,21 +731,12 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v[q] = (cv[rr][q] && rv) ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {   // column q, rows rg*4 .. rg*4+3
-                    const uint64_t pk = (uint64_t)pack_bf16x2(v[q][0], v[q][1]) |
-                                        ((uint64_t)pack_bf16x2(v[q][2], v[q][3]) << 32);
-                    *(uint64_t*)&Cs[(cg * 4 + q) * ldC + rg * 4] = pk;
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {   // row rg*4+e, columns cg*4 .. cg*4+3
+                for (int e = 0; e < 4; ++e) {
                     const uint64_t pk = (uint64_t)pack_bf16x2(v[0][e], v[1][e]) |
                                         ((uint64_t)pack_bf16x2(v[2][e], v[3][e]) << 32);
                     *(uint64_t*)&Cr[(rg * 4 + e) * ldR + cg * 4] = pk;
                 }
                 if constexpr (VEC) {
-                    // this group's registers are free: its loads of the next tile
-                    // go out now, so memory stays busy through the store
-                    const int64_t tn = t + a.nwg;
                     if (tn < a.tiles) {
                         const int64_t row = tn * TM + rg * 4;
                         const int64_t rowc = row < rows ? row : rows - 4;
@@ -746,69 +746,72 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
                 }
             }
         }
-        lds_barrier();
+    };
+
+    int64_t t = wg;
+    if (t < a.tiles) {
+        fetch(t);
+        store_tile(0, t, t + a.nwg);
         if constexpr (!VEC)
             if (t + a.nwg < a.tiles) fetch(t + a.nwg);
-
-        // Phase A: Y_tile = C_tile X (X fragments in registers); for IB == 1 two
-        // interleaved accumulators keep consecutive matrix-core ops independent.
+    }
+    __syncthreads();
+    for (int b = 0; t < a.tiles; t += a.nwg, b ^= 1) {
+        const uint16_t* Cr = Cb + b * CBUF;
         {
             f4_t accY[IB][2];
 #pragma unroll
-            for (int b = 0; b < IB; ++b) accY[b][0] = accY[b][1] = f4_t{0.f, 0.f, 0.f, 0.f};
+            for (int bb = 0; bb < IB; ++bb) accY[bb][0] = accY[bb][1] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < NKS; ++ks) {
 #pragma unroll
-                for (int b = 0; b < IB; ++b) {
-                    const bf8_t av = lds_b128(&Cr[((ib0 + b) * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4)]);
-                    accY[b][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[ks], accY[b][ks & 1], 0, 0, 0);
+                for (int bb = 0; bb < IB; ++bb) {
+                    const bf8_t av = lds_b128(&Cr[((ib0 + bb) * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4)]);
+                    accY[bb][ks & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xf[ks], accY[bb][ks & 1], 0, 0, 0);
                 }
-                // at most two k-steps of A fragments live at a time: the registers of
-                // the prefetched tile stay its own across the products
-                if (ks & 1) __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
-            for (int b = 0; b < IB; ++b) {   // rows 4*(lane/16) .. +3 of the block: one 8-byte store
+            for (int bb = 0; bb < IB; ++bb) {
                 const int col = jb * 16 + (lane & 15);
-                const f4_t y = accY[b][0] + accY[b][1];
-                *(uint64_t*)&Ys[col * ldY + (ib0 + b) * 16 + 4 * (lane >> 4)] =
+                const f4_t y = accY[bb][0] + accY[bb][1];
+                *(uint64_t*)&Ys[col * ldY + (ib0 + bb) * 16 + 4 * (lane >> 4)] =
                     (uint64_t)pack_bf16x2(y[0], y[1]) | ((uint64_t)pack_bf16x2(y[2], y[3]) << 32);
             }
         }
         lds_barrier();
-
-        // Phase B: P (NP x 64) += C_tile^T Y_tile; wave w owns row blocks w, w + 8, ...
+        if (t + a.nwg < a.tiles) {
+            store_tile(b ^ 1, t + a.nwg, t + 2 * (int64_t)a.nwg);
+            if constexpr (!VEC)
+                if (t + 2 * (int64_t)a.nwg < a.tiles) fetch(t + 2 * (int64_t)a.nwg);
+        }
 #pragma unroll
         for (int ks = 0; ks < TM / 32; ++ks) {
             bf8_t bvs[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) bvs[j] = lds_b128(&Ys[(j * 16 + (lane & 15)) * ldY + ks * 32 + 8 * (lane >> 4)]);
 #pragma unroll
-            for (int q = 0; q < QB; ++q) {
-                const int rb = w + 8 * q;
-                if (rb < NRBLK) {
-                    const bf8_t av = lds_b128(&Cs[(rb * 16 + (lane & 15)) * ldC + ks * 32 + 8 * (lane >> 4)]);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        accP[q * 4 + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bvs[j], accP[q * 4 + j], 0, 0, 0);
-                }
+            for (int u = 0; u < NIT; ++u) {
+                const int it = w * NIT + u, rb = it >> 1, jp = it & 1;
+                const bf8_t av = lds_colfrag(Cr + ks * 32 * ldR, ldR, rb * 16, lane);
+                const bf8_t b0 = jp ? bvs[2] : bvs[0], b1 = jp ? bvs[3] : bvs[1];   // no dynamic register index
+                accP[u * 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, accP[u * 2], 0, 0, 0);
+                accP[u * 2 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1, accP[u * 2 + 1], 0, 0, 0);
             }
         }
+        lds_barrier();
     }
     float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
 #pragma unroll
-    for (int q = 0; q < QB; ++q) {
-        const int rb = w + 8 * q;
-        if (rb < NRBLK) {
+    for (int u = 0; u < NIT; ++u) {
+        const int it = w * NIT + u, rb = it >> 1, jp = it & 1;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+        for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = rb * 16 + 4 * (lane >> 4) + v;
-                    const int col = j * 16 + (lane & 15);
-                    gst(outP + row + (size_t)col * NP, accP[q * 4 + j][v]);
-                }
-        }
+            for (int v = 0; v < 4; ++v) {
+                const int row = rb * 16 + 4 * (lane >> 4) + v;
+                const int col = (2 * jp + jj) * 16 + (lane & 15);
+                gst(outP + row + (size_t)col * NP, accP[u * 2 + jj][v]);
+            }
     }
 }
 
@@ -833,28 +836,6 @@ __device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t* hi, uin
     const float ha = __uint_as_float(h << 16), hb = __uint_as_float(h & 0xFFFF0000u);
     *hi = h;
     *lo = pack_bf16x2(a - ha, b - hb);
-}
-
-typedef short s4v_t __attribute__((__vector_size__(4 * sizeof(short))));
-typedef __attribute__((address_space(3))) s4v_t lds_s4v_t;
-
-// Transpose load of 16-bit data.  Within each group of 16 lanes, lane i gets
-// element i % 4 of the 8-byte chunks addressed by lanes i / 4, 4 + i / 4,
-// 8 + i / 4 and 12 + i / 4 of the group (in that order).
-__device__ __forceinline__ s4v_t lds_tr16(const uint16_t* p) {
-    return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4v_t*)(__attribute__((address_space(3))) uint16_t*)p);
-}
-
-// Column fragment of the 16x16x32 A operand of C^T Y: lane (l, g) = (lane & 15,
-// lane >> 4) receives rows 8 g .. 8 g + 7 of column c0 + l of the row-major tile
-// (leading dimension ld).  Two transpose loads of four rows each; lane (l, g)
-// addresses row 8 g + 4 h + l / 4, columns c0 + 4 (l % 4) .. + 3.
-__device__ __forceinline__ bf8_t lds_colfrag(const uint16_t* tile, int ld, int c0, int lane) {
-    const int l = lane & 15, g = lane >> 4;
-    const uint16_t* p = tile + (8 * g + (l >> 2)) * ld + c0 + 4 * (l & 3);
-    const s4v_t lo4 = lds_tr16(p), hi4 = lds_tr16(p + 4 * ld);
-    const s8_t v = (s8_t){lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
-    return __builtin_bit_cast(bf8_t, v);
 }
 
 template <int NKS, bool VEC>
@@ -1113,7 +1094,7 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
 // requested height when it is compiled).
 // ----------------------------------------------------------------------------
 static size_t sketch_lds(int tm, int np) {
-    return ((size_t)np * (tm + 8) + (size_t)tm * (np + 8) + (size_t)FU_LB * (tm + 8)) * 2;
+    return ((size_t)2 * tm * (np + 8) + (size_t)FU_LB * (tm + 8)) * 2;   // two row-major tile buffers, Y
 }
 static size_t fused_lds(int tm, int np) {
     return ((size_t)FU_LB * (np + 4) + (size_t)np * (tm + 4) + (size_t)FU_LB * (tm + 4)) * 4;
