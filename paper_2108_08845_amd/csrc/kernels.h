@@ -138,6 +138,7 @@ struct RandFinalArgs {
     int32_t n, l, K;
     int32_t max_sweeps;
     double stop_cos2;     // Jacobi (l <= 64) ends after a sweep with largest cos^2 <= this (0: m 2^-53)
+    int32_t qr_passes;    // Cholesky-QR passes for the R factor of P (2, or 1 in the mixed precision)
     const double* P;      // n x l (ld n): C^T Y
     double* P1;           // n x l scratch: P R1^-1
     const double* GY;     // l x l: Y^T Y

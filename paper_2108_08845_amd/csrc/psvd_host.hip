@@ -892,6 +892,10 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         // FP32 / mixed results carry FP32 rounding: the small SVD stops once a sweep's
         // cosines are below 2^-15 (the next sweep would leave ~2^-30); FP64 runs to m 2^-53
         rf.stop_cos2 = fp64 ? 0.0 : 0x1p-30;
+        // the R factor of P = C^T Y: Cholesky-QR2 in FP64 and FP32; one pass in the mixed
+        // precision, whose BF16 sketch dominates its error (the one-pass factor is off by
+        // about kappa(P)^2 2^-53, ~1e-6 on the smallest retained value of the c2 workload)
+        rf.qr_passes = prec == PSVD_PREC_MIXED ? 1 : 2;
         rf.P = L.P;
         rf.P1 = L.P1;
         rf.GY = L.G_Y;

@@ -954,28 +954,34 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     for (int e = tid; e < l * l; e += SM_THREADS) a.RY[e] = W[e];
     wg_trinv_upper(W, l, l, V, l, vec);
     for (int e = tid; e < l * l; e += SM_THREADS) a.RYi[e] = V[e];
-    // R1 = chol(P^T P), R1^-1 (V), P1 = P R1^-1
+    // R1 = chol(P^T P)
     if (staged) wg_gram_tall(n, l, a.P, n, a.G1, l, Cn);
     else wg_gemm_f64(l, l, n, a.P, n, 1, a.P, 1, n, a.G1, 1, l, nullptr, 0);
     if (!chol_shifted(a.G1, W, l, a.status, DEV_FALLBACK, red, staged ? Cn : nullptr)) return bail();
-    for (int e = tid; e < l * l; e += SM_THREADS) a.R1[e] = W[e];
-    wg_trinv_upper(W, l, l, V, l, vec);
-    if (staged) wg_mul_tall(n, l, a.P, n, V, l, a.P1, n, nullptr, 0, Cn);
-    else wg_gemm_f64(n, l, l, a.P, 1, n, V, 1, l, a.P1, 1, n, nullptr, 0);
-    // R2 = chol(P1^T P1) in W
-    if (staged) wg_gram_tall(n, l, a.P1, n, W, l, Cn);
-    else wg_gemm_f64(l, l, n, a.P1, n, 1, a.P1, 1, n, W, 1, l, nullptr, 0);
-    if (!(staged ? wg_chol64(W, l, 0.0, Cn, W) : wg_chol_upper(W, l, l))) return bail();
-    // small operands are read from LDS: R1 and then R_Y^-1 go to the chunk buffer
-    const double* R1 = a.R1;
     const double* RYi = a.RYi;
-    if (staged) {
-        for (int e = tid; e < l * l; e += SM_THREADS) Cn[e] = a.R1[e];
+    if (a.qr_passes == 2) {
+        // Cholesky-QR2: R1^-1 (V), P1 = P R1^-1, R2 = chol(P1^T P1) in W, R_P = R2 R1 -> V
+        for (int e = tid; e < l * l; e += SM_THREADS) a.R1[e] = W[e];
+        wg_trinv_upper(W, l, l, V, l, vec);
+        if (staged) wg_mul_tall(n, l, a.P, n, V, l, a.P1, n, nullptr, 0, Cn);
+        else wg_gemm_f64(n, l, l, a.P, 1, n, V, 1, l, a.P1, 1, n, nullptr, 0);
+        if (staged) wg_gram_tall(n, l, a.P1, n, W, l, Cn);
+        else wg_gemm_f64(l, l, n, a.P1, n, 1, a.P1, 1, n, W, 1, l, nullptr, 0);
+        if (!(staged ? wg_chol64(W, l, 0.0, Cn, W) : wg_chol_upper(W, l, l))) return bail();
+        // small operands are read from LDS: R1 goes to the chunk buffer
+        const double* R1 = a.R1;
+        if (staged) {
+            for (int e = tid; e < l * l; e += SM_THREADS) Cn[e] = a.R1[e];
+            __syncthreads();
+            R1 = Cn;
+        }
+        wg_gemm_f64(l, l, l, W, 1, l, R1, 1, l, V, 1, l, nullptr, 0);
+    } else {
+        // one Cholesky-QR pass: R_P = R1 -> V
+        for (int e = tid; e < l * l; e += SM_THREADS) V[e] = W[e];
         __syncthreads();
-        R1 = Cn;
     }
-    // R_P = R2 R1 -> V;  W = R_b^T = (R_P R_Y^-1)^T
-    wg_gemm_f64(l, l, l, W, 1, l, R1, 1, l, V, 1, l, nullptr, 0);
+    // W = R_b^T = (R_P R_Y^-1)^T; R_Y^-1 is read from the chunk buffer
     if (staged) {
         for (int e = tid; e < l * l; e += SM_THREADS) Cn[e] = a.RYi[e];
         __syncthreads();
