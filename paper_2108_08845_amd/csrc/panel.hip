@@ -821,15 +821,20 @@ __global__ __launch_bounds__(512) void k_sketch_bf16(FusedArgs a) {
 // v = hi + lo + O(2^-18 |v|) with hi = bf16(v), lo = bf16(v - hi); a product is
 // hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo_a lo_b term is O(2^-18)), three
 // 16x16x32 BF16 MFMAs with FP32 accumulation.  Per tile (32 rows):
-//   Y_tile = C_tile X   (split products; the FP32 result is written to the kept
-//                        copy of Y and split again for the two products below)
+//   Y_tile = C_tile X~  with X~ = bf16(X): the test matrix of this pass is
+//                       X rounded to BF16 (any basis of the power-iterated
+//                       range serves; Y, P and G below are FP32-accurate for
+//                       X~), so C_tile X~ = C_hi X~ + C_lo X~ is two products.
+//                       The FP32 result is written to the kept copy of Y and
+//                       split for the products below.
 //   P     += C_tile^T Y_tile   (split products)
 //   G     += Y_tile^T Y_tile   (all four hi/lo products, exact in FP32; FP64 across tiles)
 // The tile is stored once, row-major (hi and lo), in one of two LDS buffers:
 // C X reads row fragments; C^T Y reads column fragments of the same copy with
 // the 16-bit transpose load (ds_read_b64_tr_b16).  Double buffering lets the
 // split and store of the next tile run between the same two barriers as the
-// C^T Y and Y^T Y products of this one.
+// C^T Y and Y^T Y products of this one.  Two register sets hold the loads of
+// the next two tiles, so two tiles per CU are in flight from HBM.
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t* hi, uint32_t* lo) {
     const uint32_t h = pack_bf16x2(a, b);
@@ -844,16 +849,19 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
     constexpr int NP = NKS * 32;
     constexpr int NCG = NP / 4;
     constexpr int RG = TM / 4;                      // 8 row groups of 4
-    constexpr int CGR = NT / RG;                    // 64 column groups per round
-    constexpr int RMAX = (NCG + CGR - 1) / CGR;
+    constexpr int CGR = NT / RG;                    // 64 column groups of 4 x 4 blocks
+    constexpr int NC0 = NCG < CGR ? NCG : CGR;      // column groups in 4 x 4 blocks
+    constexpr int NX = NCG > CGR ? (NP - 4 * CGR) / 64 : 0;   // further float4 per thread
+    static_assert(NCG <= CGR || (NP - 4 * CGR) % 64 == 0, "columns past 256 in groups of 64");
     constexpr int NIT = NKS / 2;                    // C^T Y items per wave: (16-row block, 32-column pair)
     static_assert(NKS % 2 == 0, "an even number of 32-column slices");
-    constexpr int ldR = NP + 8, ldY = TM + 8;
+    constexpr int ldR = NP + 8, ldY = TM + 8, LDG = FU_LB + 1;
     constexpr int CBUF = 2 * TM * ldR;              // one buffer: hi (TM x ldR) then lo
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* Cb = (uint16_t*)smem;                 // two tile buffers, row-major
     uint16_t* Ysh = Cb + 2 * CBUF;                  // 64 x TM, column-major (hi)
     uint16_t* Ysl = Ysh + FU_LB * ldY;              //                        (lo)
+    double* Gs = (double*)(Ysl + FU_LB * ldY);      // FP64 sums of G, 64 x 64, leading dimension LDG
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -863,130 +871,156 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
     const int c0 = lb * FU_LB;
     const int jb = w & 3, ib = w >> 2;              // phase-A block of this wave
 
-    // X block -> LDS (FP32, in the tile buffers, free until the first tile),
-    // then the hi / lo B fragments of phase A into registers.
-    bf8_t xh[NKS], xl[NKS];
+    // X~ = bf16(X) block -> LDS (in the tile buffers, free until the first
+    // tile), then the B fragments of phase A into registers.
+    bf8_t xh[NKS];
     {
-        constexpr int ldxs = NP + 4;
-        static_assert(FU_LB * ldxs * 4 <= 2 * CBUF * 2, "X staging must fit the tile buffers");
-        float* Xf = (float*)smem;
-        stage_x<NP, NT>(a, c0, [&](int k, int j, double v) { Xf[j * ldxs + k] = (float)v; });
+        constexpr int ldxs = NP + 8;
+        static_assert(FU_LB * ldxs <= 2 * CBUF, "X staging must fit the tile buffers");
+        uint16_t* Xb = Cb;
+        stage_x<NP, NT>(a, c0, [&](int k, int j, double v) { Xb[j * ldxs + k] = f32_to_bf16_rne((float)v); });
         __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-            const float* xp = Xf + (jb * 16 + (lane & 15)) * ldxs + ks * 32 + 8 * (lane >> 4);
-            uint32_t h[4], l[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) split_bf16x2(xp[2 * u], xp[2 * u + 1], &h[u], &l[u]);
-            xh[ks] = __builtin_bit_cast(bf8_t, (s8_t){(short)(h[0] & 0xFFFF), (short)(h[0] >> 16), (short)(h[1] & 0xFFFF),
-                                                     (short)(h[1] >> 16), (short)(h[2] & 0xFFFF), (short)(h[2] >> 16),
-                                                     (short)(h[3] & 0xFFFF), (short)(h[3] >> 16)});
-            xl[ks] = __builtin_bit_cast(bf8_t, (s8_t){(short)(l[0] & 0xFFFF), (short)(l[0] >> 16), (short)(l[1] & 0xFFFF),
-                                                     (short)(l[1] >> 16), (short)(l[2] & 0xFFFF), (short)(l[2] >> 16),
-                                                     (short)(l[3] & 0xFFFF), (short)(l[3] >> 16)});
-        }
+        for (int ks = 0; ks < NKS; ++ks)
+            xh[ks] = lds_b128(&Xb[(jb * 16 + (lane & 15)) * ldxs + ks * 32 + 8 * (lane >> 4)]);
         __syncthreads();
     }
 
     f4_t accP[NIT * 2];
 #pragma unroll
     for (int t = 0; t < NIT * 2; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
-    d4_t accG[2];
-    accG[0] = d4_t{0, 0, 0, 0};
-    accG[1] = d4_t{0, 0, 0, 0};
+    // G accumulates in LDS: each lane reads and writes only its own entries.
+    const int gi = w >> 1, gj0 = (w & 1) * 2;
+    double* gsl = Gs + (gi * 16 + 4 * (lane >> 4)) + (size_t)(gj0 * 16 + (lane & 15)) * LDG;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gsl[v + j * 16 * LDG] = 0.0;
 
-    // thread -> (row group, column group) as in k_sketch_bf16 (TM = 32: RGH = 2)
+    // Tile loads.  Columns 0 .. 255: thread -> (row group rg, column group
+    // cgl), a 4 x 4 block (four float4 of one column each); columns 256 ..
+    // NP - 1: thread -> one float4 of column 256 + 64 x + (tid >> 3), rows
+    // 4 (tid & 7) .. + 3, so every thread holds the same number of loads.
     const int rg = (tid & 3) | (((tid >> 4) & 1) << 2);
     const int cgl = ((tid >> 2) & 3) | ((tid >> 5) << 2);
-    const float* cp[RMAX][4];
-    bool cv[RMAX][4];
+    const int rgx = tid & 7, cxl = CGR * 4 + (tid >> 3);
+    const float* cp[4];
+    bool cv[4];
 #pragma unroll
-    for (int rr = 0; rr < RMAX; ++rr)
+    for (int q = 0; q < 4; ++q) {
+        const int c = cgl * 4 + q;
+        cv[q] = c < a.n;
+        cp[q] = fcol(a.seg, c < a.n ? c : a.n - 1);
+    }
+    const float* cpx[NX > 0 ? NX : 1];
+    bool cvx[NX > 0 ? NX : 1];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = (rr * CGR + cgl) * 4 + q;
-            cv[rr][q] = c < a.n;
-            cp[rr][q] = fcol(a.seg, c < a.n ? c : a.n - 1);
-        }
+    for (int x = 0; x < NX; ++x) {
+        const int c = cxl + 64 * x;
+        cvx[x] = c < a.n;
+        cpx[x] = fcol(a.seg, c < a.n ? c : a.n - 1);
+    }
     const int64_t rows = a.seg.rows;
-    f4_t pf[RMAX][4];
+    // A register set: the 4 x 4 block and the further float4.
+    struct LoadSet {
+        f4_t b[4];
+        f4_t x[NX > 0 ? NX : 1];
+    };
+    // DEPTH register sets of loads in flight: at the top of the iteration for
+    // tile t the set that will be stored next holds tile t + nwg and, with two
+    // sets, the other holds tile t + 2 nwg.  Two sets fit the registers up to
+    // 320 columns with the float4 loads.
+    constexpr int DEPTH = (VEC && NKS <= 10) ? 2 : 1;
+    LoadSet pf0, pf1;
     // The loads only: nothing here reads the loaded values, so they stay in
-    // flight until the tile is converted (columns >= n are zeroed there).  The
-    // full-tile test is one branch around all loads.
-    auto fetch = [&](int64_t t) {
-        const int64_t row = t * TM + rg * 4;
+    // flight until the tile is converted (columns >= n are zeroed there).
+    auto fetch = [&](LoadSet& pf, int64_t t) {
+        const int64_t row = t * TM + rg * 4, rowx = t * TM + rgx * 4;
         if constexpr (VEC) {
             // rows % 4 == 0: a float4 is all inside or all past the end; past
             // the end it reads the last rows again and is zeroed at the store
-            const int64_t rowc = row < rows ? row : rows - 4;
+            const int64_t rowc = row < rows ? row : rows - 4, rowxc = rowx < rows ? rowx : rows - 4;
+            if (NC0 == CGR || cgl < NC0)                     // uniform per wave
 #pragma unroll
-            for (int rr = 0; rr < RMAX; ++rr)
-                if (rr * CGR + cgl < NCG)                    // uniform per wave
+                for (int q = 0; q < 4; ++q) pf.b[q] = gld4(cp[q] + rowc);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + rowc);
+            for (int x = 0; x < NX; ++x) pf.x[x] = gld4(cpx[x] + rowxc);
         } else {
+            if (cgl < NC0) {
 #pragma unroll
-            for (int rr = 0; rr < RMAX; ++rr) {
-                if (rr * CGR + cgl < NCG) {
+                for (int q = 0; q < 4; ++q) {
+                    f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (row + e < rows) v[e] = gld(cp[rr][q] + row + e);
-                        pf[rr][q] = v;
-                    }
+                    for (int e = 0; e < 4; ++e)
+                        if (row + e < rows) v[e] = gld(cp[q] + row + e);
+                    pf.b[q] = v;
                 }
+            }
+#pragma unroll
+            for (int x = 0; x < NX; ++x) {
+                f4_t v = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (rowx + e < rows) v[e] = gld(cpx[x] + rowx + e);
+                pf.x[x] = v;
             }
         }
     };
-    // split the fetched tile (index tl) into buffer b: row rg*4+e, columns cg*4 .. cg*4+3
-    auto store_tile = [&](int b, int64_t tl) {
+    // split the fetched tile (index tl) into buffer b
+    auto store_tile = [&](int b, int64_t tl, const LoadSet& pf) {
         uint16_t* Crh = Cb + b * CBUF;
         uint16_t* Crl = Crh + TM * ldR;
-        const bool rv = tl * TM + rg * 4 < rows;
+        if (NC0 == CGR || cgl < NC0) {
+            // rows rg*4+e, columns cgl*4 .. cgl*4+3: one 8-byte store per row
+            const bool rv = tl * TM + rg * 4 < rows;
+            f4_t v[4];
 #pragma unroll
-        for (int rr = 0; rr < RMAX; ++rr) {
-            const int cg = rr * CGR + cgl;
-            if (cg < NCG) {
-                f4_t v[4];
+            for (int q = 0; q < 4; ++q) v[q] = (cv[q] && rv) ? pf.b[q] : f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = (cv[rr][q] && rv) ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
+            for (int e = 0; e < 4; ++e) {
+                uint32_t h0, l0, h1, l1;
+                split_bf16x2(v[0][e], v[1][e], &h0, &l0);
+                split_bf16x2(v[2][e], v[3][e], &h1, &l1);
+                *(uint64_t*)&Crh[(rg * 4 + e) * ldR + cgl * 4] = (uint64_t)h0 | ((uint64_t)h1 << 32);
+                *(uint64_t*)&Crl[(rg * 4 + e) * ldR + cgl * 4] = (uint64_t)l0 | ((uint64_t)l1 << 32);
+            }
+        }
+        // rows rgx*4+e of one column: 2-byte stores
+        const bool rvx = tl * TM + rgx * 4 < rows;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    uint32_t h0, l0, h1, l1;
-                    split_bf16x2(v[0][e], v[1][e], &h0, &l0);
-                    split_bf16x2(v[2][e], v[3][e], &h1, &l1);
-                    *(uint64_t*)&Crh[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)h0 | ((uint64_t)h1 << 32);
-                    *(uint64_t*)&Crl[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)l0 | ((uint64_t)l1 << 32);
-                }
+        for (int x = 0; x < NX; ++x) {
+            const f4_t v = (cvx[x] && rvx) ? pf.x[x] : f4_t{0.f, 0.f, 0.f, 0.f};
+            const int c = cxl + 64 * x;
+#pragma unroll
+            for (int e = 0; e < 4; e += 2) {
+                uint32_t h, l;
+                split_bf16x2(v[e], v[e + 1], &h, &l);
+                Crh[(rgx * 4 + e) * ldR + c] = (uint16_t)(h & 0xFFFF);
+                Crh[(rgx * 4 + e + 1) * ldR + c] = (uint16_t)(h >> 16);
+                Crl[(rgx * 4 + e) * ldR + c] = (uint16_t)(l & 0xFFFF);
+                Crl[(rgx * 4 + e + 1) * ldR + c] = (uint16_t)(l >> 16);
             }
         }
     };
 
-    int64_t t = wg;
-    if (t < a.tiles) {
-        fetch(t);
-        store_tile(0, t);
-        if (t + a.nwg < a.tiles) fetch(t + a.nwg);
-    }
-    lds_barrier();
-    for (int b = 0; t < a.tiles; t += a.nwg, b ^= 1) {
+    // One tile: Y, then (with the next tile's split and store and the loads
+    // of the tile three strides ahead) P and G.  pf holds tile t + nwg.
+    const int64_t nwg = a.nwg;
+    auto tile_step = [&](int b, int64_t t, LoadSet& pf) {
         const uint16_t* Crh = Cb + b * CBUF;
         const uint16_t* Crl = Crh + TM * ldR;
 
-        // Phase A: Y block (ib, jb) = C_tile X with split products, three chains.
+        // Phase A: Y block (ib, jb) = C_tile X~ = C_hi X~ + C_lo X~, two chains.
         {
-            f4_t acc0 = f4_t{0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0;
+            f4_t acc0 = f4_t{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
 #pragma unroll
             for (int ks = 0; ks < NKS; ++ks) {
                 const int off = (ib * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4);
                 const bf8_t ah = lds_b128(&Crh[off]), al = lds_b128(&Crl[off]);
                 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xh[ks], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xl[ks], acc1, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, xh[ks], acc2, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, xh[ks], acc1, 0, 0, 0);
             }
-            const f4_t y = acc0 + (acc1 + acc2);
+            const f4_t y = acc0 + acc1;
             const int col = jb * 16 + (lane & 15), r0 = ib * 16 + 4 * (lane >> 4);
             uint32_t h0, l0, h1, l1;
             split_bf16x2(y[0], y[1], &h0, &l0);
@@ -1009,63 +1043,91 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
         lds_barrier();
 
         // The next tile: split into the other buffer (read by no wave in this
-        // interval), then the loads of the one after it.
-        if (t + a.nwg < a.tiles) {
-            store_tile(b ^ 1, t + a.nwg);
-            if (t + 2 * (int64_t)a.nwg < a.tiles) fetch(t + 2 * (int64_t)a.nwg);
+        // interval), then the loads of the tile DEPTH + 1 strides ahead into
+        // the registers it leaves free.  With float4 loads both run for every
+        // tile: a tile past the end reads the last rows again (in bounds) and
+        // stores zeros into a buffer no wave reads.  Loads that are issued on
+        // every path let the compiler wait for exactly the set it converts;
+        // a load skipped on some path made it wait for all loads in flight.
+        if (VEC || t + nwg < a.tiles) {
+            store_tile(b ^ 1, t + nwg, pf);
+            if (VEC || t + (DEPTH + 1) * nwg < a.tiles) fetch(pf, t + (DEPTH + 1) * nwg);
         }
 
         // Phase B: P (NP x 64) += C_tile^T Y_tile with split products; the
         // column fragments come from the row-major tile by transpose loads.
-        // Item it = w NIT + u is row block it / 2 with column blocks 2 (it % 2) + {0, 1}:
-        // every wave does NIT items.
-        {
-            const int koff = 8 * (lane >> 4);
+        // Wave w: column blocks 2 (w % 2) + {0, 1} of P (its Y fragments are
+        // read once per tile), row blocks (w / 2) NIT + u, u < NIT.
+        const int jp = w & 1, rb0 = (w >> 1) * NIT;
+        const int koff = 8 * (lane >> 4);
+        bf8_t yh[2], yl[2];
 #pragma unroll
-            for (int u = 0; u < NIT; ++u) {
-                const int it = w * NIT + u, rb = it >> 1, jp = it & 1;
-                const bf8_t ah = lds_colfrag(Crh, ldR, rb * 16, lane);
-                const bf8_t al = lds_colfrag(Crl, ldR, rb * 16, lane);
+        for (int jj = 0; jj < 2; ++jj) {
+            const int boff = ((2 * jp + jj) * 16 + (lane & 15)) * ldY + koff;
+            yh[jj] = lds_b128(&Ysh[boff]);
+            yl[jj] = lds_b128(&Ysl[boff]);
+        }
 #pragma unroll
-                for (int jj = 0; jj < 2; ++jj) {
-                    const int boff = ((2 * jp + jj) * 16 + (lane & 15)) * ldY + koff;
-                    const bf8_t bh = lds_b128(&Ysh[boff]), bl = lds_b128(&Ysl[boff]);
-                    __builtin_amdgcn_sched_barrier(0);
-                    f4_t acc = accP[u * 2 + jj];
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-                    accP[u * 2 + jj] = acc;
-                }
+        for (int u = 0; u < NIT; ++u) {
+            const bf8_t ah = lds_colfrag(Crh, ldR, (rb0 + u) * 16, lane);
+            const bf8_t al = lds_colfrag(Crl, ldR, (rb0 + u) * 16, lane);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) {
+                f4_t acc = accP[u * 2 + jj];
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, yh[jj], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yl[jj], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yh[jj], acc, 0, 0, 0);
+                accP[u * 2 + jj] = acc;
             }
         }
         // G (64 x 64) += Y^T Y: the four hi/lo products of every pair are exact in
-        // FP32; each tile's 32-row sum is added to the FP64 accumulators.
-        // Wave w: row block w/2, column blocks (w%2)*2 + {0,1}.
+        // FP32; each tile's 32-row sum is added to the FP64 sums.
+        // Wave w: row block w / 2, column blocks 2 (w % 2) + {0, 1} (the B
+        // fragments of phase B).
         {
-            const int gi = w >> 1, gj0 = (w & 1) * 2;
-            const int koff = 8 * (lane >> 4);
             const int aoff = (gi * 16 + (lane & 15)) * ldY + koff;
-            const bf8_t ah = lds_b128(&Ysh[aoff]), al = lds_b128(&Ysl[aoff]);
+            const bf8_t gh = lds_b128(&Ysh[aoff]), gl = lds_b128(&Ysl[aoff]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int boff = ((gj0 + j) * 16 + (lane & 15)) * ldY + koff;
-                const bf8_t bh = lds_b128(&Ysh[boff]), bl = lds_b128(&Ysl[boff]);
+            for (int jj = 0; jj < 2; ++jj) {
                 f4_t g = f4_t{0.f, 0.f, 0.f, 0.f};
-                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl, g, 0, 0, 0);
-                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, g, 0, 0, 0);
-                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, g, 0, 0, 0);
-                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, g, 0, 0, 0);
+                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl, yl[jj], g, 0, 0, 0);
+                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl, yh[jj], g, 0, 0, 0);
+                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, yl[jj], g, 0, 0, 0);
+                g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, yh[jj], g, 0, 0, 0);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) accG[j][v] += (double)g[v];
+                for (int v = 0; v < 4; ++v) gsl[v + jj * 16 * LDG] += (double)g[v];
             }
         }
         lds_barrier();
+    };
+
+    // Prologue: tile t into buffer 0; two sets: loads of t + nwg (pf1) and
+    // t + 2 nwg (pf0); one set: loads of t + nwg (pf0).
+    int64_t t = wg;
+    if (t < a.tiles) {
+        fetch(pf0, t);
+        if (DEPTH == 2 && (VEC || t + nwg < a.tiles)) fetch(pf1, t + nwg);
+        store_tile(0, t, pf0);
+        if (VEC || t + DEPTH * nwg < a.tiles) fetch(pf0, t + DEPTH * nwg);
+        lds_barrier();
+        // Two tiles per trip so that the buffers and register sets alternate
+        // statically.  The loop has no exit between the two tiles and is
+        // entered only through the loads above, so every path into a tile
+        // carries the same loads in flight.
+        const int64_t ntl = (a.tiles - t + nwg - 1) / nwg;   // tiles of this work-group
+        for (int64_t p = 0; p < ntl / 2; ++p) {
+            tile_step(0, t, DEPTH == 2 ? pf1 : pf0);
+            t += nwg;
+            tile_step(1, t, pf0);
+            t += nwg;
+        }
+        if (ntl & 1) tile_step(0, t, DEPTH == 2 ? pf1 : pf0);
     }
     float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
 #pragma unroll
     for (int u = 0; u < NIT; ++u) {
-        const int it = w * NIT + u, rb = it >> 1, jp = it & 1;
+        const int jp = w & 1, rb = (w >> 1) * NIT + u;
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
@@ -1076,14 +1138,13 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
             }
     }
     double* outG = a.partG + (size_t)wg * FU_LB * FU_LB;
-    const int gi = w >> 1, gj0 = (w & 1) * 2;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = gi * 16 + 4 * (lane >> 4) + v;   // FP32 MFMA output layout
             const int col = (gj0 + j) * 16 + (lane & 15);
-            gstd(outG + row + col * FU_LB, accG[j][v]);
+            gstd(outG + row + col * FU_LB, gsl[v + j * 16 * LDG]);
         }
 }
 
@@ -1171,7 +1232,8 @@ hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st) {
 
 static size_t split_lds(int np) {
     constexpr int tm = 32;
-    return ((size_t)4 * tm * (np + 8) + (size_t)2 * FU_LB * (tm + 8)) * 2;   // two hi/lo tile buffers, Y hi/lo
+    // two hi/lo tile buffers, Y hi/lo (16-bit), then the FP64 sums of G
+    return ((size_t)4 * tm * (np + 8) + (size_t)2 * FU_LB * (tm + 8)) * 2 + (size_t)FU_LB * (FU_LB + 1) * 8;
 }
 
 bool split_plan(int n, FusedPlan* p) {
