@@ -16,6 +16,10 @@ Functions and the passages they follow:
   StreamOracle          -- Algorithm 1 per batch, deterministic or randomized
                             (Eqs. (7)-(11), Halko-Martinsson-Tropp power iterations).
   apmos                 -- Algorithm 2 / Eqs. (3)-(6).
+  PartitionedStreamOracle -- the parallel streaming of Sec. 3 over row
+                            partitions: APMOS initialisation, then per batch
+                            local QR of each partition's panel, QR of the
+                            stacked R factors, SVD of the combined R, local lift.
   stream_loss, stream_grad -- loss ||A - U U^T A||^2 + sum w_j s_j of the
                             streamed truncated SVD and its reverse-mode gradient.
 """
@@ -58,6 +62,8 @@ def _load():
     lib.orc_stream_update.argtypes = [_i64, _i32, ctypes.c_double, _i32, _i32, _dp, _i64, _dp,
                                       ctypes.POINTER(_i32), _dp, _i64, _i64, _dp, _dp]
     lib.orc_apmos.argtypes = [_i32, ctypes.POINTER(_i64), _i64, _i32, _i32, _dp, _dp, _dp, _dp]
+    lib.orc_pstream_update.argtypes = [_i32, ctypes.POINTER(_i64), _i32, ctypes.c_double, _dp, _dp,
+                                       ctypes.POINTER(_i32), _dp, _i64]
     lib.orc_stream_loss.argtypes = [_i64, _i32, ctypes.c_double, _i32, _i64, _dp, _i64, _dp, _dp, _dp, _dp]
     lib.orc_stream_grad.argtypes = [_i64, _i32, ctypes.c_double, _i32, _i64, _dp, _i64, _dp, _dp]
     lib.orc_matmul_nn.argtypes = [_i64, _i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64]
@@ -224,6 +230,67 @@ def apmos(parts, r, K):
         out.append(U_all[off: off + m * K].reshape((m, K), order="F"))
         off += m * K
     return out, Lam, X
+
+
+class PartitionedStreamOracle:
+    """The parallel streaming SVD of Sec. 3 on P row partitions (M_i rows each).
+
+    The first batch initialises the state with APMOS (Algorithm 2 with local
+    truncation `r_local`, K global modes); every later batch runs the
+    partitioned update `orc_pstream_update` (local QR per partition, QR of
+    the stacked R factors, SVD of the combined R, U^i = Q^i Q_g^i U~_K).
+    `modes` is the stacked U (sum M_i x r), `modes_part(i)` one partition's.
+    """
+
+    def __init__(self, M_parts, K, ff=1.0, r_local=None):
+        self.Ms = np.array([int(m) for m in M_parts], dtype=np.int64)
+        self.P, self.K, self.ff = len(self.Ms), int(K), float(ff)
+        self.r_local = r_local
+        self.U_all = np.zeros(int(self.Ms.sum()) * self.K)
+        self.s = np.zeros(self.K)
+        self.r = 0
+
+    def _stack(self, parts):
+        parts = [_f64(p) for p in parts]
+        assert len(parts) == self.P and all(p.shape[0] == m for p, m in zip(parts, self.Ms))
+        return parts, np.concatenate([p.ravel(order="F") for p in parts])
+
+    def incorporate(self, parts):
+        parts, A_all = self._stack(parts)
+        N = parts[0].shape[1]
+        if N == 0:
+            return self
+        if self.r == 0:
+            rl = int(self.r_local) if self.r_local is not None else min(self.K, N)
+            Us, lam, _ = apmos(parts, rl, self.K)
+            off = 0
+            for u, m in zip(Us, self.Ms):
+                self.U_all[off: off + m * self.K] = u.ravel(order="F")
+                off += m * self.K
+            self.s[:] = lam
+            self.r = self.K
+            return self
+        r = _i32(self.r)
+        rc = _load().orc_pstream_update(self.P, self.Ms.ctypes.data_as(ctypes.POINTER(_i64)), self.K, self.ff,
+                                        _ptr(self.U_all), _ptr(self.s), ctypes.byref(r), _ptr(A_all), N)
+        _check(rc, "pstream_update")
+        self.r = int(r.value)
+        return self
+
+    initialize = incorporate
+
+    def modes_part(self, i):
+        off = int(self.Ms[:i].sum()) * self.K
+        m = int(self.Ms[i])
+        return self.U_all[off: off + m * self.K].reshape((m, self.K), order="F")[:, : self.r]
+
+    @property
+    def modes(self):
+        return np.vstack([self.modes_part(i) for i in range(self.P)])
+
+    @property
+    def singular_values(self):
+        return self.s[: self.r].copy()
 
 
 def stream_loss(A, K, ff, batches, w):

@@ -686,6 +686,95 @@ int orc_apmos(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_
 }
 
 /* ------------------------------------------------------------------------ */
+/* Partitioned streaming: the parallel update of Section 3 (row partitions). */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * One batch of the partitioned streaming SVD over P row partitions.  State:
+ * U_all holds U^i (M_i x K capacity, ld M_i) stacked one after another, s (K),
+ * *r the current rank.  A_all holds the batch partitions A^i (M_i x N, ld M_i)
+ * stacked the same way.  Per batch:
+ *   1. local panels C^i = [ff U^i diag(s) | A^i] and local Householder QR
+ *      C^i = Q^i R^i (R^i: n x n; requires M_i >= n);
+ *   2. the R^i stacked (P n x n) and factored again, [R^1; ..; R^P] = Q_g R_f;
+ *   3. R_f = U~ S V~^T (Jacobi), descending; keep r' = min(K, n) triplets,
+ *      sign rule on U~;
+ *   4. U^i <- Q^i Q_g^i U~[:, :r'], with Q_g^i the i-th n-row block of Q_g.
+ * In exact arithmetic this is the serial update of the stacked panel: R_f
+ * is the R factor of the whole panel (both with a non-negative diagonal).
+ */
+int orc_pstream_update(int32_t P, const int64_t* M_parts, int32_t K, double ff, double* U_all, double* s, int32_t* r,
+                       const double* A_all, int64_t N)
+{
+    if (P < 1 || K < 1 || N < 0 || !(ff > 0.0 && ff <= 1.0)) return ORC_EINVAL;
+    const int64_t r0 = *r, n = r0 + N;
+    if (N == 0) return ORC_OK;
+    for (int32_t i = 0; i < P; ++i)
+        if (M_parts[i] < n) return ORC_EINVAL;
+    const int64_t pn = (int64_t)P * n;
+    double* Rs = (double*)calloc((size_t)pn * (size_t)n, sizeof(double));
+    double** Qs = (double**)calloc((size_t)P, sizeof(double*));
+    double* Qg = (double*)malloc((size_t)pn * (size_t)n * sizeof(double));
+    double* Rf = (double*)malloc((size_t)n * (size_t)n * sizeof(double));
+    double* Ut = (double*)malloc((size_t)n * (size_t)n * sizeof(double));
+    double* S = (double*)malloc((size_t)n * sizeof(double));
+    int rc = (Rs && Qs && Qg && Rf && Ut && S) ? ORC_OK : ORC_ENOMEM;
+    /* 1. local panels and local QR */
+    int64_t off = 0, uoff = 0;
+    for (int32_t i = 0; i < P && rc == ORC_OK; ++i) {
+        const int64_t Mi = M_parts[i];
+        double* C = build_panel(Mi, r0, ff, U_all + uoff, Mi, s, A_all + off, N, Mi);
+        double* R = (double*)malloc((size_t)n * (size_t)n * sizeof(double));
+        Qs[i] = (double*)malloc((size_t)Mi * (size_t)n * sizeof(double));
+        if (!C || !R || !Qs[i]) rc = ORC_ENOMEM;
+        if (rc == ORC_OK) rc = orc_hhqr(Mi, n, C, Mi, Qs[i], R);
+        if (rc == ORC_OK)
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t a = 0; a < n; ++a) Rs[IDX((int64_t)i * n + a, j, pn)] = R[IDX(a, j, n)];
+        free(C);
+        free(R);
+        off += Mi * N;
+        uoff += Mi * K;
+    }
+    /* 2. QR of the stacked R factors */
+    if (rc == ORC_OK) rc = orc_hhqr(pn, n, Rs, pn, Qg, Rf);
+    /* 3. SVD of the combined R */
+    if (rc == ORC_OK) rc = orc_jacobi_svd(n, n, Rf, n, Ut, S, NULL, 60, NULL);
+    if (rc == ORC_OK) {
+        const int64_t rk = K < n ? K : n;
+        sign_rule(n, rk, Ut, n, NULL);
+        /* 4. U^i = Q^i (Q_g^i U~_rk) */
+        double* T = (double*)malloc((size_t)n * (size_t)rk * sizeof(double));
+        double* Qgi = (double*)malloc((size_t)n * (size_t)n * sizeof(double));
+        if (!T || !Qgi) rc = ORC_ENOMEM;
+        uoff = 0;
+        for (int32_t i = 0; i < P && rc == ORC_OK; ++i) {
+            const int64_t Mi = M_parts[i];
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t a = 0; a < n; ++a) Qgi[IDX(a, j, n)] = Qg[IDX((int64_t)i * n + a, j, pn)];
+            mm_nn(n, rk, n, Qgi, n, Ut, n, T, n);
+            mm_nn(Mi, rk, n, Qs[i], Mi, T, n, U_all + uoff, Mi);
+            uoff += Mi * K;
+        }
+        free(T);
+        free(Qgi);
+        if (rc == ORC_OK) {
+            for (int64_t j = 0; j < rk; ++j) s[j] = S[j];
+            *r = (int32_t)rk;
+        }
+    }
+    if (Qs)
+        for (int32_t i = 0; i < P; ++i) free(Qs[i]);
+    free(Qs);
+    free(Rs);
+    free(Qg);
+    free(Rf);
+    free(Ut);
+    free(S);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Loss and its reverse-mode gradient through the deterministic stream.     */
 /* ------------------------------------------------------------------------ */
 

@@ -361,6 +361,93 @@ def test_apmos_truncated_local_rank_is_gram_of_W():
 # Loss and gradient
 # ----------------------------------------------------------------------------
 
+# ----------------------------------------------------------------------------
+# Partitioned streaming (the parallel variant of Sec. 3 on row partitions)
+# ----------------------------------------------------------------------------
+
+def _split_rows(A, sizes):
+    out, o = [], 0
+    for m in sizes:
+        out.append(np.asfortranarray(A[o: o + m]))
+        o += m
+    return out
+
+
+def test_pstream_update_equals_serial_update():
+    # One partitioned update from the same state as the serial oracle: the
+    # stacked R factors re-factored give the R of the whole panel, so the
+    # update is the serial Algorithm 1 step of the stacked panel.  Pinned
+    # against the serial oracle, itself pinned to LAPACK above; uneven
+    # partitions, truncation loss (rank 20 > K = 10) and ff < 1.
+    w = synth.scaled(synth.c1_plain_fp64(), M=600)
+    batches = [synth.numpy_cm(t) for t in synth.planted_stream(w)]
+    sizes = [120, 97, 200, 183]
+    so = oracle.StreamOracle(w.M, w.K, ff=0.9)
+    so.incorporate(batches[0])
+    po = oracle.PartitionedStreamOracle(sizes, w.K, ff=0.9)
+    U0 = so.modes.copy()
+    off = 0
+    for i, m in enumerate(sizes):
+        po.U_all[off * w.K: (off + m) * w.K] = np.asfortranarray(U0[sum(sizes[:i]): sum(sizes[:i]) + m]).ravel(order="F")
+        off += m
+    po.s[:] = so.singular_values
+    po.r = so.r
+    for A in batches[1:]:
+        so.incorporate(A)
+        po.incorporate(_split_rows(A, sizes))
+        assert po.r == so.r
+        assert sigma_rel_err(po.singular_values, so.singular_values) <= 1e-12
+        assert np.abs(po.modes - so.modes).max() <= 1e-10     # same sign rule on the same U~
+        assert orth_err(po.modes) <= 1e-13
+
+
+def test_pstream_partition_block_is_that_partitions_rows():
+    # Each partition's modes are the rows of the stacked modes (a wrong block
+    # index in the local lift would move rows between partitions).
+    sig = np.linspace(2.0, 0.3, 6)
+    A, _, _ = planted(400, 24, sig, seed=21)
+    sizes = [100, 180, 120]
+    po = oracle.PartitionedStreamOracle(sizes, 6, ff=1.0, r_local=8)
+    po.incorporate(_split_rows(A[:, :12], sizes)).incorporate(_split_rows(A[:, 12:], sizes))
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    Us = align_signs(po.modes, Ul[:, :6])
+    o = 0
+    for i, m in enumerate(sizes):
+        assert np.abs(align_signs(po.modes_part(i)[:, :6], Ul[o: o + m, :6]) - Us[o: o + m, :6]).max() <= 1e-10
+        o += m
+
+
+def test_pstream_exact_without_truncation():
+    # Rank 6 = K, ff = 1, local truncation r_local >= local rank: the APMOS
+    # initialisation and every partitioned update are exact, so the state is
+    # the SVD of the concatenation of all batches (LAPACK).
+    sig = np.linspace(3.0, 0.4, 6)
+    A, _, _ = planted(700, 40, sig, seed=22)
+    sizes = [150, 250, 300]
+    po = oracle.PartitionedStreamOracle(sizes, 6, ff=1.0, r_local=10)
+    for b in np.split(np.arange(40), 4):
+        po.incorporate(_split_rows(A[:, b], sizes))
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    assert sigma_rel_err(po.singular_values[:6], sl[:6]) <= 1e-12
+    assert max_principal_angle(po.modes[:, :6], Ul[:, :6]) <= 1e-10
+
+
+def test_pstream_forget_factor_closed_form():
+    # ff < 1 without truncation loss (rank 5 = K): batch j is weighted by ff^(last - j).
+    ff = 0.85
+    sig = np.linspace(2.5, 0.5, 5)
+    A, _, _ = planted(360, 30, sig, seed=23)
+    parts = [A[:, :10], A[:, 10:20], A[:, 20:]]
+    sizes = [90, 130, 140]
+    po = oracle.PartitionedStreamOracle(sizes, 5, ff=ff, r_local=10)
+    for p in parts:
+        po.incorporate(_split_rows(p, sizes))
+    W = np.hstack([ff ** 2 * parts[0], ff * parts[1], parts[2]])
+    Ul, sl, _ = np.linalg.svd(W, full_matrices=False)
+    assert sigma_rel_err(po.singular_values[:5], sl[:5]) <= 1e-12
+    assert max_principal_angle(po.modes[:, :5], Ul[:, :5]) <= 1e-10
+
+
 def test_gradient_single_batch_closed_form():
     # One exact truncated SVD: L = ||A||^2 - sum s_j^2 + sum w_j s_j,
     # dL/dA = 2A - U_K (2 S_K - diag(w)) V_K^T.
