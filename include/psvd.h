@@ -236,6 +236,49 @@ int psvd_apmos_batched(int32_t P, const void* const* A_parts, const int64_t* M_p
                        const int64_t* ldu_parts, double* Lambda, double* X, void* stream);
 
 /*
+ * Partitioned streaming: the parallel streaming SVD of Section 3 (the
+ * initialisation by APMOS, Algorithm 2, and the batch update with a QR over
+ * row partitions) with P row partitions of the data, all on this GPU.
+ * M_parts[i] >= 1 rows per partition; K modes; ff in (0, 1]; r_local the
+ * local truncation of the APMOS initialisation (0: min(K, N)).  opt: the
+ * deterministic method with PSVD_PREC_FP64 (FP64 data and state) or
+ * PSVD_PREC_FP32 (FP32 data and state).  The handle works with
+ * psvd_pstream_incorporate / psvd_pstream_modes_ptr and psvd_rank,
+ * psvd_singular_values, psvd_stats, psvd_last_error, psvd_finalize; the
+ * single-panel calls (incorporate_data, modes, checkpoints) return
+ * PSVD_E_STATE on it.
+ * Errors: PSVD_E_INVAL (P < 1, M_i < 1, K < 1, K > sum M_i, ff, options),
+ * PSVD_E_NOMEM, PSVD_E_DEVICE.
+ */
+int psvd_pstream_initialize(psvd_handle** h, int32_t P, const int64_t* M_parts, int32_t K, double ff,
+                            int32_t r_local, const psvd_options* opt);
+
+/*
+ * One batch of N columns, partition i in A_parts[i] (device, M_i x N,
+ * leading dimension ld_parts[i] >= M_i, element type dtype = the state's).
+ * First batch (rank 0): APMOS over the partitions (needs K <= N and
+ * r_local <= N), U_i = A_i X~ diag(1 / Lambda~), s = Lambda~.  Later
+ * batches: panels C_i = [ff U_i diag(s) | A_i] (M_i >= r + N rows each), the
+ * R factor of the stacked panel from the partitions' Gram sum (the R factor
+ * of the stacked local R factors), Jacobi SVD of R with the stable
+ * descending sort and sign rule of Algorithm 1, U_i = C_i R^-1 U~_K, kept
+ * rank min(K, r + N).  Host pointer arrays; synchronises the stream.
+ * Errors: PSVD_E_STATE (not a partitioned handle), PSVD_E_INVAL, PSVD_E_SHAPE,
+ * PSVD_E_DTYPE, PSVD_E_NONFINITE, PSVD_E_NOCONV, PSVD_E_NOMEM, PSVD_E_DEVICE;
+ * on error the state is unchanged.
+ */
+int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const int64_t* ld_parts, int64_t N,
+                             int32_t dtype);
+
+/* Borrowed pointer to partition part's modes (M_part x rank, leading dimension
+ * *ldu = M_part, element type *dtype), valid until the next mutating call. */
+int psvd_pstream_modes_ptr(const psvd_handle* h, int32_t part, const void** U, int64_t* ldu, int32_t* dtype);
+
+/* Copy of partition part's modes into U (device, M_part x rank, leading
+ * dimension ldu >= M_part, the state's element type), stream-ordered. */
+int psvd_pstream_modes(const psvd_handle* h, int32_t part, void* U, int64_t ldu);
+
+/*
  * Reverse-mode derivative of the deterministic stream (Algorithm 1 with the
  * QR + SVD(R) step) over B equal batches of Nb columns of A (device,
  * M x B*Nb, leading dimension lda, dtype) with K modes and forget factor ff:

@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import PsvdError
 
-__all__ = ["StreamingSVD", "apmos_batched", "PsvdError", "stream_backward", "loss_and_grad", "StreamingSVDFunction",
+__all__ = ["StreamingSVD", "PartitionedStreamingSVD", "apmos_batched", "PsvdError", "stream_backward", "loss_and_grad", "StreamingSVDFunction",
            "rsvd"]
 
 _PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32, "mixed": _lib.PREC_MIXED}
@@ -173,6 +173,104 @@ class StreamingSVD:
         buf = ctypes.create_string_buffer(bytes(state), len(state))
         _lib.check(self._libh.psvd_load_state(self._h, buf, len(state)), self._h, "load_state")
         return self
+
+
+class PartitionedStreamingSVD:
+    """Partitioned streaming SVD (the parallel variant of Sec. 3) over row partitions on one GPU.
+
+    M_parts: rows of each partition.  The first batch initialises the modes by
+    APMOS (local truncation `r_local`, 0 = min(K, N)); later batches combine the
+    partitions' QR factors.  precision "fp64" (FP64 data) or "fp32" (FP32 data).
+    """
+
+    def __init__(self, M_parts, K, ff=1.0, r_local=0, precision="fp64", stream=None, max_sweeps=60, profile=False):
+        self._libh = _lib.load()
+        opt = _lib.Options()
+        self._libh.psvd_default_options(ctypes.byref(opt))
+        opt.method = _lib.DETERMINISTIC
+        opt.precision = _PREC[precision]
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        opt.stream = _stream_ptr(self._stream).value
+        opt.max_sweeps = int(max_sweeps)
+        opt.flags = _lib.OPT_PROFILE if profile else 0
+        self.M_parts = [int(m) for m in M_parts]
+        P = len(self.M_parts)
+        Ms = (ctypes.c_int64 * P)(*self.M_parts)
+        h = ctypes.c_void_p()
+        rc = self._libh.psvd_pstream_initialize(ctypes.byref(h), P, Ms, int(K), float(ff), int(r_local),
+                                                ctypes.byref(opt))
+        _lib.check(rc, None, "psvd_pstream_initialize")
+        self._h = h
+        self.K, self.ff, self.precision = int(K), float(ff), precision
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._libh.psvd_finalize(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def incorporate_data(self, parts):
+        """Ingest one batch given as its row partitions (list of M_i x N CUDA tensors)."""
+        P = len(self.M_parts)
+        if len(parts) != P:
+            raise ValueError("one tensor per partition")
+        cols = [_as_colmajor(p) for p in parts]
+        for c, m in zip(cols, self.M_parts):
+            if c[1] != m:
+                raise ValueError("partition row count differs from M_parts")
+        N = cols[0][2]
+        self._keep = [c[5] for c in cols]
+        A_ptrs = (ctypes.c_void_p * P)(*[c[0].value for c in cols])
+        lds = (ctypes.c_int64 * P)(*[c[3] for c in cols])
+        rc = self._libh.psvd_pstream_incorporate(self._h, A_ptrs, lds, int(N), cols[0][4])
+        _lib.check(rc, self._h, "pstream_incorporate")
+        return self
+
+    initialize = incorporate_data
+
+    @property
+    def rank(self):
+        r = ctypes.c_int32()
+        _lib.check(self._libh.psvd_rank(self._h, ctypes.byref(r)), self._h)
+        return int(r.value)
+
+    @property
+    def singular_values(self):
+        r = self.rank
+        out = np.zeros(max(r, 1), dtype=np.float64)
+        rr = ctypes.c_int32()
+        rc = self._libh.psvd_singular_values(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             out.size, ctypes.byref(rr))
+        _lib.check(rc, self._h, "singular_values")
+        return out[:rr.value].copy()
+
+    def modes_part(self, i):
+        """M_i x r modes of partition i (a copy, column-major CUDA tensor)."""
+        r = self.rank
+        dt = torch.float64 if self.precision == "fp64" else torch.float32
+        m = self.M_parts[i]
+        out = torch.empty((r, m), dtype=dt, device="cuda")
+        if r:
+            rc = self._libh.psvd_pstream_modes(self._h, int(i), ctypes.c_void_p(out.data_ptr()), m)
+            _lib.check(rc, self._h, "pstream_modes")
+        return out.t()
+
+    @property
+    def modes(self):
+        """Stacked modes (sum M_i x r)."""
+        return torch.cat([self.modes_part(i) for i in range(len(self.M_parts))], dim=0)
+
+    def stats(self):
+        return StreamingSVD.stats(self)
+
+    def reset_stats(self):
+        _lib.check(self._libh.psvd_reset_stats(self._h), self._h)
 
 
 def rsvd(A, K, oversampling=10, power_iters=2, seed=0, precision="fp32", out_dtype=None, stream=None):

@@ -199,6 +199,12 @@ struct psvd_handle {
     std::vector<hipEvent_t> prof_ev;
     std::vector<int> prof_pending;   // (class, event index) pairs, flattened
     int prof_next = 0;
+
+    // Partitioned streaming (psvd_pstream_*): row counts of the partitions and
+    // their first row; the state U holds partition i's M_i x K block at element
+    // offset poff[i] * K with leading dimension M_i.  Empty: one M-row panel.
+    std::vector<int64_t> parts, poff;
+    int32_t r_local = 0;
 };
 
 static bool profiling(const psvd_handle* h) { return (h->opt.flags & PSVD_OPT_PROFILE) != 0; }
@@ -668,6 +674,7 @@ static int sync_async(psvd_handle* h) {
 int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, int64_t lda, int32_t dtype) {
     if (!h) return PSVD_E_INVAL;
     h->err.clear();
+    if (!h->parts.empty()) return fail(h, PSVD_E_STATE, "partitioned handle: use psvd_pstream_incorporate");
     if (N < 0 || (N > 0 && !A)) return fail(h, PSVD_E_INVAL, "N < 0 or null data");
     if (M != h->M) return fail(h, PSVD_E_SHAPE, "row count differs from the handle's M");
     if (lda < M) return fail(h, PSVD_E_SHAPE, "lda < M");
@@ -976,6 +983,7 @@ int psvd_singular_values(const psvd_handle* hc, double* out, int32_t cap, int32_
 
 int psvd_modes_ptr(const psvd_handle* h, const void** U, int64_t* ldu, int32_t* dtype) {
     if (!h || !U) return PSVD_E_INVAL;
+    if (!h->parts.empty()) return PSVD_E_STATE;   // partitioned: psvd_pstream_modes_ptr
     *U = h->U[h->cur].p;
     if (ldu) *ldu = h->ldu;
     if (dtype) *dtype = h->u_dtype;
@@ -985,6 +993,7 @@ int psvd_modes_ptr(const psvd_handle* h, const void** U, int64_t* ldu, int32_t* 
 int psvd_modes(const psvd_handle* hc, void* U, int64_t ldu, int32_t dtype) {
     psvd_handle* h = const_cast<psvd_handle*>(hc);
     if (!h || (!U && h->r > 0)) return PSVD_E_INVAL;
+    if (!h->parts.empty()) return fail(h, PSVD_E_STATE, "partitioned handle: use psvd_pstream_modes_ptr");
     if (ldu < h->M) return fail(h, PSVD_E_SHAPE, "ldu < M");
     if (dtype != PSVD_F32 && dtype != PSVD_F64) return fail(h, PSVD_E_DTYPE, "unknown dtype");
     if (int rc = sync_async(h)) return rc;
@@ -1116,6 +1125,7 @@ int psvd_rsvd(const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype,
 int psvd_save_state(const psvd_handle* hc, void* buf, size_t cap, size_t* size) {
     psvd_handle* h = const_cast<psvd_handle*>(hc);
     if (!h) return PSVD_E_INVAL;
+    if (!h->parts.empty()) return fail(h, PSVD_E_STATE, "checkpoints cover single-panel handles");
     const int esz = h->u_dtype == PSVD_F64 ? 8 : 4;
     const size_t payload = (size_t)h->K * sizeof(double) + (size_t)h->r * h->M * esz;
     const size_t total = sizeof(StateHeader) + payload;
@@ -1155,6 +1165,7 @@ int psvd_save_state(const psvd_handle* hc, void* buf, size_t cap, size_t* size) 
 int psvd_load_state(psvd_handle* h, const void* buf, size_t size) {
     if (!h || !buf) return PSVD_E_INVAL;
     h->err.clear();
+    if (!h->parts.empty()) return fail(h, PSVD_E_STATE, "checkpoints cover single-panel handles");
     StateHeader hd;
     if (size < sizeof(hd)) return fail(h, PSVD_E_INVAL, "buffer shorter than the state header");
     std::memcpy(&hd, buf, sizeof(hd));
@@ -1486,3 +1497,280 @@ extern "C" int psvd_loss_grad(const void* A, int64_t M, int64_t lda, int32_t dty
     HIPCHK(h, hipStreamSynchronize(st));
     return PSVD_OK;
 }
+
+// ----------------------------------------------------------------------------
+// Partitioned streaming: the parallel streaming SVD of Section 3 with the P
+// row partitions on this device.  The first batch initialises U and s with
+// APMOS (Algorithm 2); each later batch combines the partitions' QR factors.
+// With the Cholesky-based QR the R factor of partition i comes from its Gram
+// G_i = C_i^T C_i, and the QR of the stacked R factors [R_1; ..; R_P] has
+// the R factor of their Gram sum_i R_i^T R_i = sum_i G_i: the partitions'
+// Gram partials are summed in one fixed-order reduction (the all-reduce of a
+// distributed run), the small core is the serial one, and every partition's
+// lift uses the same small factor (Q_g^i = R_i R_f^-1, so Q_i Q_g^i = C_i R_f^-1).
+// ----------------------------------------------------------------------------
+namespace {
+
+// One panel per partition: [U_i | A_i] with output rows of U_new_i.
+std::vector<PanelSeg> part_panels(const psvd_handle* h, int r, const void* const* A, const int64_t* ld, int32_t dt,
+                                  int N, const void* Ucur, void* Unew) {
+    const int esz = h->u_dtype == PSVD_F64 ? 8 : 4;
+    std::vector<PanelSeg> segs(h->parts.size());
+    for (size_t i = 0; i < h->parts.size(); ++i) {
+        const int64_t Mi = h->parts[i];
+        PanelSeg C = make_seg(Mi);
+        if (r > 0) seg_add(C, make_block((const char*)Ucur + (size_t)h->poff[i] * h->K * esz, Mi, h->u_dtype, r));
+        seg_add(C, make_block(A[i], ld[i], dt, N));
+        C.out = (char*)Unew + (size_t)h->poff[i] * h->K * esz;
+        C.ldo = Mi;
+        C.out_dtype = h->u_dtype;
+        segs[i] = C;
+    }
+    return segs;
+}
+
+}  // namespace
+
+// out (nl x nl FP64, symmetric) = sum_i S_i^T S_i: every partition's row
+// chunks write their own partials, one reduction sums all of them in order.
+static int tn_product_parts(psvd_handle* h, const std::vector<PanelSeg>& S, bool fp64, double* out,
+                            const int32_t* skip, int skip_mask) {
+    const int nl = S[0].ncols;
+    const int mbl = ceil_div(nl, 64);
+    const int nob = mbl * (mbl + 1) / 2;
+    const int64_t chunk = pick_chunk(h->M, nob, 64);
+    std::vector<int> items(S.size());
+    size_t total = 0;
+    for (size_t i = 0; i < S.size(); ++i) {
+        items[i] = ceil_div(S[i].rows, chunk);
+        total += items[i];
+    }
+    HIPCHK(h, h->part.ensure(total * nob * 64 * 64 * sizeof(double)));
+    size_t item0 = 0;
+    for (size_t i = 0; i < S.size(); ++i) {
+        TnArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.lseg = S[i];
+        a.rseg = S[i];
+        a.chunk = chunk;
+        a.mbl = mbl;
+        a.sym = 1;
+        a.part = h->part.as<double>() + item0 * nob * 64 * 64;
+        a.skip = skip;
+        a.skip_mask = skip_mask;
+        a.nob = nob;
+        int pe = prof_begin(h, PSVD_KC_TN);
+        HIPCHK(h, launch_tn(fp64, a, items[i], h->stream));
+        prof_end(h, pe);
+        item0 += items[i];
+    }
+    TnReduceArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.part = h->part.as<double>();
+    ra.seg_item0 = nullptr;
+    ra.nitems = (int)total;
+    ra.mbl = mbl;
+    ra.nob = nob;
+    ra.nl = nl;
+    ra.nr = nl;
+    ra.sym = 1;
+    ra.out = out;
+    ra.skip = skip;
+    ra.skip_mask = skip_mask;
+    HIPCHK(h, launch_tn_reduce(ra, 1, h->stream));
+    return PSVD_OK;
+}
+
+extern "C" {
+
+int psvd_pstream_initialize(psvd_handle** out, int32_t P, const int64_t* M_parts, int32_t K, double ff,
+                            int32_t r_local, const psvd_options* opt) {
+    if (!out) return PSVD_E_INVAL;
+    *out = nullptr;
+    if (P < 1 || !M_parts || K < 1 || r_local < 0) return PSVD_E_INVAL;
+    int64_t M = 0;
+    for (int i = 0; i < P; ++i) {
+        if (M_parts[i] < 1) return PSVD_E_INVAL;
+        M += M_parts[i];
+    }
+    psvd_options o;
+    psvd_default_options(&o);
+    if (opt) o = *opt;
+    if (o.method != PSVD_DETERMINISTIC || o.precision == PSVD_PREC_MIXED) return PSVD_E_INVAL;
+    psvd_handle* h = nullptr;
+    int rc = psvd_initialize(&h, M, K, ff, 0, 0, &o);
+    if (rc) return rc;
+    h->parts.assign(M_parts, M_parts + P);
+    h->poff.resize(P);
+    int64_t off = 0;
+    for (int i = 0; i < P; ++i) {
+        h->poff[i] = off;
+        off += M_parts[i];
+    }
+    h->r_local = r_local;
+    *out = h;
+    return PSVD_OK;
+}
+
+int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const int64_t* ld_parts, int64_t N,
+                             int32_t dtype) {
+    if (!h) return PSVD_E_INVAL;
+    h->err.clear();
+    if (h->parts.empty()) return fail(h, PSVD_E_STATE, "not a partitioned handle");
+    const int P = (int)h->parts.size();
+    if (N < 0 || (N > 0 && (!A_parts || !ld_parts))) return fail(h, PSVD_E_INVAL, "N < 0 or null data");
+    if (dtype != h->u_dtype) return fail(h, PSVD_E_DTYPE, "partition data must have the state's element type");
+    if (N == 0) return PSVD_OK;
+    if (N > 1 << 20) return fail(h, PSVD_E_SHAPE, "batch too wide");
+    for (int i = 0; i < P; ++i) {
+        if (!A_parts[i]) return fail(h, PSVD_E_INVAL, "null partition");
+        if (ld_parts[i] < h->parts[i]) return fail(h, PSVD_E_SHAPE, "partition leading dimension < M_i");
+    }
+    if (int rc = sync_async(h)) return rc;
+    const int esz = h->u_dtype == PSVD_F64 ? 8 : 4;
+    hipStream_t st = h->stream;
+    if (h->r == 0) {
+        // ---- initialisation: APMOS over the partitions ----
+        const int rl = h->r_local > 0 ? h->r_local : (int)std::min<int64_t>(h->K, N);
+        if (h->K > N || rl > N) return fail(h, PSVD_E_SHAPE, "the first batch needs K <= N and r_local <= N");
+        std::vector<void*> Up(P);
+        std::vector<int64_t> ldu(P);
+        for (int i = 0; i < P; ++i) {
+            Up[i] = (char*)h->U[h->cur].p + (size_t)h->poff[i] * h->K * esz;
+            ldu[i] = h->parts[i];
+        }
+        std::vector<double> lam(h->K);
+        int rc = psvd_apmos_batched(P, A_parts, h->parts.data(), ld_parts, N, dtype, rl, h->K, Up.data(), ldu.data(),
+                                    lam.data(), nullptr, st);
+        if (rc) return fail(h, rc, std::string("APMOS initialisation: ") + psvd_status_string(rc));
+        HIPCHK(h, hipMemcpyAsync(h->s[h->cur].p, lam.data(), sizeof(double) * h->K, hipMemcpyHostToDevice, st));
+        HIPCHK(h, hipStreamSynchronize(st));
+        h->r = h->K;
+        h->batch += 1;
+        h->stats.batches += 1;
+        return PSVD_OK;
+    }
+    // ---- update: Cholesky-QR2 of the partitioned panel + Jacobi SVD of R ----
+    const int r = h->r;
+    const int n = r + (int)N;
+    for (int i = 0; i < P; ++i)
+        if (h->parts[i] < n) return fail(h, PSVD_E_SHAPE, "a partition has fewer rows than the panel has columns");
+    int rc = ensure_workspace(h, n);
+    if (rc) return rc;
+    HIPCHK(h, h->tall.ensure((size_t)h->M * n * esz));
+    const bool fp64 = h->opt.precision == PSVD_PREC_FP64;
+    const int rk = std::min<int>(h->K, n);
+    SmallLayout L = small_layout(h->small.as<double>(), n, 0, h->K);
+    int32_t* dstat = h->status.as<int32_t>();
+    const int cur = h->cur, nxt = 1 - cur;
+    double* s_cur = h->s[cur].as<double>();
+    double* s_new = h->s[nxt].as<double>();
+    HIPCHK(h, hipEventRecord(h->ev0, st));
+    HIPCHK(h, hipMemsetAsync(dstat, 0, 8, st));
+    HIPCHK(h, launch_make_scale(h->d.as<double>(), s_cur, r, h->ff, st));
+    std::vector<PanelSeg> C = part_panels(h, r, A_parts, ld_parts, dtype, (int)N, h->U[cur].p, h->U[nxt].p);
+    // Q1_i (tall temporary, partition i at rows poff[i] with leading dimension M_i)
+    std::vector<PanelSeg> Q1(P), Qin(P);
+    for (int i = 0; i < P; ++i) {
+        char* q = (char*)h->tall.p + (size_t)h->poff[i] * n * esz;
+        Qin[i] = C[i];
+        Qin[i].out = q;
+        Qin[i].ldo = h->parts[i];
+        Qin[i].out_dtype = h->u_dtype;
+        Q1[i] = make_seg(h->parts[i]);
+        seg_add(Q1[i], make_block(q, h->parts[i], h->u_dtype, n));
+        Q1[i].out = C[i].out;
+        Q1[i].ldo = C[i].ldo;
+        Q1[i].out_dtype = h->u_dtype;
+    }
+    rc = tn_product_parts(h, C, true, L.G, nullptr, 0);
+    if (rc) return rc;
+    SmallArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.n = n;
+    sa.r = r;
+    sa.K = h->K;
+    sa.l = 0;
+    sa.max_sweeps = h->opt.max_sweeps;
+    sa.allow_fallback = (h->opt.flags & PSVD_OPT_NO_FALLBACK) ? 0 : 1;
+    sa.d = h->d.as<double>();
+    sa.G = L.G;
+    sa.G2 = L.G2;
+    sa.R1 = L.R1;
+    sa.Ri = L.Ri;
+    sa.Z = L.Z;
+    sa.T = L.T;
+    sa.Xn = L.Xn;
+    sa.s_out = s_new;
+    sa.small_u = L.sm_u;
+    sa.vec = L.vec;
+    sa.ivec = h->ivec.as<int32_t>();
+    sa.status = dstat;
+    sa.sweeps = dstat + 1;
+    {
+        int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
+        HIPCHK(h, launch_small_det1(sa, st));
+        prof_end(h, pes);
+    }
+    const int skipmask = DEV_FALLBACK | DEV_NONFINITE | DEV_BREAKDOWN;
+    for (int i = 0; i < P; ++i) {
+        rc = nn_product(h, Qin[i], L.Xn, n, n, fp64, nullptr, 0, dstat, skipmask);
+        if (rc) return rc;
+    }
+    rc = tn_product_parts(h, Q1, true, L.G2, dstat, skipmask);
+    if (rc) return rc;
+    {
+        int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
+        HIPCHK(h, launch_small_det2(sa, st));
+        prof_end(h, pes);
+    }
+    // lift of every partition with the shared small factor (the eigen route
+    // of a Cholesky breakdown lifts from the panel itself)
+    for (int i = 0; i < P; ++i) {
+        rc = nn_product(h, Q1[i], L.T, n, rk, fp64, nullptr, 0, dstat, skipmask, PSVD_KC_LIFT);
+        if (rc) return rc;
+        rc = nn_product(h, C[i], L.T, n, rk, fp64, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN, PSVD_KC_LIFT,
+                        DEV_FALLBACK);
+        if (rc) return rc;
+    }
+    HIPCHK(h, hipEventRecord(h->ev1, st));
+    HIPCHK(h, hipMemcpyAsync(h->status_host, dstat, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    const int32_t sv = h->status_host[0];
+    if (profiling(h)) prof_resolve(h);
+    h->stats.last_sweeps = h->status_host[1];
+    if (sv & DEV_FALLBACK) h->stats.fallbacks += 1;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->stats.last_update_ms = ms;
+    if (int code = finish_status(h, sv)) return code;
+    h->cur = nxt;
+    h->r = rk;
+    h->batch += 1;
+    h->stats.batches += 1;
+    h->stats.last_path = 0;
+    return PSVD_OK;
+}
+
+int psvd_pstream_modes_ptr(const psvd_handle* h, int32_t part, const void** U, int64_t* ldu, int32_t* dtype) {
+    if (!h || !U || h->parts.empty() || part < 0 || part >= (int32_t)h->parts.size()) return PSVD_E_INVAL;
+    const int esz = h->u_dtype == PSVD_F64 ? 8 : 4;
+    *U = (const char*)h->U[h->cur].p + (size_t)h->poff[part] * h->K * esz;
+    if (ldu) *ldu = h->parts[part];
+    if (dtype) *dtype = h->u_dtype;
+    return PSVD_OK;
+}
+
+int psvd_pstream_modes(const psvd_handle* hc, int32_t part, void* U, int64_t ldu) {
+    psvd_handle* h = const_cast<psvd_handle*>(hc);
+    if (!h || h->parts.empty() || part < 0 || part >= (int32_t)h->parts.size()) return PSVD_E_INVAL;
+    if (h->r == 0) return PSVD_OK;
+    if (!U) return PSVD_E_INVAL;
+    const int64_t Mi = h->parts[part];
+    if (ldu < Mi) return fail(h, PSVD_E_SHAPE, "ldu < M_part");
+    const int esz = h->u_dtype == PSVD_F64 ? 8 : 4;
+    const char* src = (const char*)h->U[h->cur].p + (size_t)h->poff[part] * h->K * esz;
+    HIPCHK(h, hipMemcpy2DAsync(U, ldu * esz, src, Mi * esz, Mi * esz, h->r, hipMemcpyDeviceToDevice, h->stream));
+    return PSVD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+"""GPU parity of the partitioned streaming SVD (the parallel variant of Sec. 3 on
+row partitions of one GPU) against the FP64 oracle's partitioned stream.
+
+Same seeded batches on both sides, split into uneven row partitions.  The
+oracle initialises by APMOS and updates by local Householder QR per
+partition, QR of the stacked R factors and SVD of the combined R; the library
+sums the partitions' Gram partials into one Cholesky-QR2.  Tolerances: FP64
+1e-10 (sigma), FP32 1e-4, as for the single-panel stream.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from conftest import sigma_rel_err, orth_err, align_signs, max_principal_angle
+
+pytestmark = pytest.mark.gpu
+
+
+def lib():
+    import paper_2108_08845_amd as P
+    return P
+
+
+def split_gpu(b, sizes):
+    """(N, M) contiguous tensor on the GPU -> row partitions as (M_i, N) column-major views."""
+    out, o = [], 0
+    for m in sizes:
+        out.append(b[:, o: o + m].t())
+        o += m
+    return out
+
+
+def split_np(A, sizes):
+    out, o = [], 0
+    for m in sizes:
+        out.append(np.asfortranarray(A[o: o + m]))
+        o += m
+    return out
+
+
+def run_both(w, sizes, precision, r_local, ff):
+    P = lib()
+    batches = synth.planted_stream(w)
+    svd = P.PartitionedStreamingSVD(sizes, w.K, ff=ff, r_local=r_local, precision=precision)
+    po = oracle.PartitionedStreamOracle(sizes, w.K, ff=ff, r_local=r_local)
+    for b in batches:
+        bg = b.to("cuda")
+        svd.incorporate_data(split_gpu(bg, sizes))
+        po.incorporate(split_np(synth.numpy_cm(b), sizes))
+    return svd, po
+
+
+@pytest.mark.parametrize("precision,dtype,tol", [("fp64", torch.float64, 1e-10), ("fp32", torch.float32, 1e-4)])
+def test_pstream_matches_partitioned_oracle(precision, dtype, tol):
+    # c1 shape (N = 64 per batch, K = 10, rank 20 > K: truncation loss) at 600
+    # rows in four uneven partitions (one not a multiple of 4), ff = 0.9.
+    w = synth.scaled(synth.c1_plain_fp64(), M=600, dtype=dtype)
+    sizes = [150, 97, 203, 150]
+    svd, po = run_both(w, sizes, precision, r_local=10, ff=0.9)
+    s, s_ref = svd.singular_values, po.singular_values
+    assert len(s) == len(s_ref) == w.K
+    assert sigma_rel_err(s, s_ref) <= tol, sigma_rel_err(s, s_ref)
+    U = svd.modes.double().cpu().numpy()
+    assert orth_err(U) <= (1e-12 if precision == "fp64" else 1e-5)
+    # the same sign rule on both sides: modes agree entry by entry, partition by partition
+    etol = 1e-9 if precision == "fp64" else 2e-3
+    for i in range(len(sizes)):
+        Ui = svd.modes_part(i).double().cpu().numpy()
+        assert np.abs(Ui - po.modes_part(i)).max() <= etol, i
+
+
+def test_pstream_single_partition_equals_single_panel_stream():
+    # P = 1 with r_local = N: the APMOS initialisation is the exact SVD of the
+    # first batch (local rank 20 <= 64), so the stream equals the single-panel one.
+    w = synth.scaled(synth.c1_plain_fp64(), M=800)
+    batches = synth.planted_stream(w)
+    P = lib()
+    ps = P.PartitionedStreamingSVD([w.M], w.K, ff=0.95, r_local=w.N, precision="fp64")
+    ss = P.StreamingSVD(w.M, w.K, ff=0.95, precision="fp64")
+    for b in batches:
+        bg = b.to("cuda")
+        ps.incorporate_data([bg.t()])
+        ss.incorporate_data(bg.t())
+    assert sigma_rel_err(ps.singular_values, ss.singular_values) <= 1e-10
+    Up = ps.modes.double().cpu().numpy()
+    Us = ss.modes.double().cpu().numpy()
+    assert np.abs(align_signs(Up, Us) - Us).max() <= 1e-8
+
+
+def test_pstream_exact_low_rank():
+    # rank 6 = K, ff = 1, no noise: every step is exact, the state is the SVD
+    # of all batches (LAPACK), on uneven FP64 partitions.
+    j = np.arange(6)
+    w = synth.Workload("lowrank", M=900, N=30, batches=3, K=6, oversampling=0, power_iters=0, ff=1.0,
+                       sigma=2.0 ** (-j / 2.0), noise=0.0, seed=5, dtype=torch.float64, randomized=False,
+                       precision="fp64")
+    sizes = [300, 275, 325]
+    batches = synth.planted_stream(w)
+    P = lib()
+    ps = P.PartitionedStreamingSVD(sizes, w.K, ff=1.0, r_local=8, precision="fp64")
+    for b in batches:
+        ps.incorporate_data(split_gpu(b.to("cuda"), sizes))
+    A = np.hstack([synth.numpy_cm(b) for b in batches])
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    assert sigma_rel_err(ps.singular_values, sl[:6]) <= 1e-11
+    assert max_principal_angle(ps.modes.double().cpu().numpy(), Ul[:, :6]) <= 1e-9
+
+
+def test_pstream_errors():
+    import ctypes
+    P = lib()
+    from paper_2108_08845_amd import _lib
+    w = synth.scaled(synth.c1_plain_fp64(), M=400)
+    b = synth.planted_stream(w)[0].to("cuda")
+    # a partition with fewer rows than the second panel has columns (K + N = 74)
+    ps = P.PartitionedStreamingSVD([340, 60], w.K, ff=1.0, r_local=10, precision="fp64")
+    ps.incorporate_data(split_gpu(b, [340, 60]))            # APMOS initialisation: fine
+    with pytest.raises(P.PsvdError) as e:
+        ps.incorporate_data(split_gpu(b, [340, 60]))
+    assert e.value.code == -2                                # PSVD_E_SHAPE
+    assert ps.rank == w.K                                    # state unchanged
+    # single-panel calls are refused on a partitioned handle
+    h = ps._h
+    rc = _lib.load().psvd_incorporate_data(h, ctypes.c_void_p(b.data_ptr()), 400, 64, 400, _lib.PSVD_F64)
+    assert rc == -9                                          # PSVD_E_STATE
+    # FP32 data on an FP64 handle
+    with pytest.raises(P.PsvdError):
+        ps.incorporate_data([t.float() for t in split_gpu(b, [340, 60])])
