@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the oracle sample (0: all M rows)")
     ap.add_argument("--M", type=int, default=1 << 20)
+    ap.add_argument("--workload", default="randomized", choices=["randomized", "partitioned"],
+                    help="randomized: the headline mixed-precision randomized stream; partitioned: the "
+                         "partitioned streaming SVD (APMOS initialisation, partition QR combination)")
+    ap.add_argument("--partitions", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibration of the HBM byte counters)")
     return ap.parse_args()
@@ -117,6 +121,106 @@ def cpu_baseline(w, rows, min_seconds=10.0, max_updates=8):
             "seconds": dt, "updates": n}
 
 
+PART_CPU_ROWS = 1 << 17
+
+
+def partition_sizes(M, P, seed=7):
+    """Uneven row partitions summing to M (each within +-25% of M / P, multiples of 4)."""
+    g = np.random.default_rng(seed)
+    w = g.uniform(0.75, 1.25, P)
+    sizes = [int(4 * round(M * x / w.sum() / 4)) for x in w]
+    sizes[-1] += M - sum(sizes)
+    return sizes
+
+
+def bench_partitioned(args):
+    """Partitioned streaming SVD (the parallel variant over row partitions) on one
+    GPU: FP32 deterministic updates (the QR + SVD(R) step of Algorithm 1, as the
+    parallel variant runs it) with batches of 64 snapshots and K = 10 (the
+    deterministic workload's panel, n = 74) on M = 2^20 rows in uneven row
+    partitions; one JSON line."""
+    import synth
+    import paper_2108_08845_amd as P
+    w = synth.scaled(synth.c1_plain_fp64(), M=args.M, batches=16, ff=0.95, dtype=torch.float32, precision="fp32")
+    sizes = partition_sizes(w.M, args.partitions)
+    log(f"generating {w.batches} batches of {w.M} x {w.N}; partitions {sizes}")
+    batches = synth.planted_stream(w, device="cuda")
+    views = []
+    for b in batches:
+        o, parts = 0, []
+        for m in sizes:
+            parts.append(b[:, o: o + m].t())
+            o += m
+        views.append(parts)
+    torch.cuda.synchronize()
+    svd = P.PartitionedStreamingSVD(sizes, w.K, ff=w.ff, r_local=w.K, precision="fp32", profile=True)
+    nb = len(views)
+    for i in range(args.warmup + 1):               # the first call is the APMOS initialisation
+        svd.incorporate_data(views[i % nb])
+    torch.cuda.synchronize()
+    svd.reset_stats()
+    t0 = time.perf_counter()
+    for i in range(args.warmup + 1, args.warmup + 1 + args.steps):
+        svd.incorporate_data(views[i % nb])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    st = svd.stats()
+    kern = st["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    avg_ms = kern[dom]["ms"] / max(1, kern[dom]["launches"])
+    n = w.K + w.N
+    if dom == "tn":      # FP64 Gram of the panel (or of Q1): M n (n + 1) flops per pass, FP64 matrix cores
+        roof = {"bound": "mfma", "achieved": w.M * n * (n + 1) / (avg_ms * 1e-3) / 1e12,
+                "peak": MFMA_PEAK_TFLOPS["f64"], "unit": "TFLOP/s"}
+    elif dom == "nn":    # Q1 = C R1^-1 over all partitions: reads the panel, writes Q1 (FP32)
+        roof = {"bound": "hbm", "achieved": 2 * w.M * n * 4 / (avg_ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:                # lift U_i = Q1_i T: reads Q1, writes U
+        roof = {"bound": "hbm", "achieved": w.M * (n + w.K) * 4 / (avg_ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = avg_ms
+    per_kernel = {k: {"launches": v["launches"], "avg_ms": (v["ms"] / v["launches"]) if v["launches"] else 0.0}
+                  for k, v in kern.items() if v["launches"]}
+    svd.close()
+    value = w.M * w.N * 4 / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "snapshot GB/s ingested (partitioned streaming SVD)",
+        "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 data / f64 grams and small core", "data": "synthetic",
+        "config": {"workload": f"partitioned_streaming_M{w.M}_P{len(sizes)}_N{w.N}x{w.batches}_K{w.K}_fp32", "M": w.M,
+                   "partitions": sizes, "N": w.N, "K": w.K, "ff": w.ff, "parallelism": "single GPU"},
+        "roofline": roof, "kernels": per_kernel,
+    }
+    del batches, views
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        import oracle
+        rows = args.cpu_rows or PART_CPU_ROWS
+        ws = synth.scaled(w, M=rows, batches=3)
+        psz = partition_sizes(rows, args.partitions)
+        bs = [synth.numpy_cm(b) for b in synth.planted_stream(ws)]
+        po = oracle.PartitionedStreamOracle(psz, w.K, ff=w.ff, r_local=w.K)
+        split = lambda A: [np.asfortranarray(A[sum(psz[:i]): sum(psz[:i]) + m]) for i, m in enumerate(psz)]
+        po.incorporate(split(bs[0]))
+        dt, nup = 0.0, 0
+        while nup < 6 and (nup == 0 or dt < 10.0):
+            t0 = time.perf_counter()
+            po.incorporate(split(bs[1 + nup % 2]))
+            dt += time.perf_counter() - t0
+            nup += 1
+        out["cpu_baseline"] = {"value": nup * rows * w.N * 4 / dt / 1e9, "unit": "GB/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{nup} partitioned updates on {rows} of the {w.M} rows ({len(psz)} "
+                                         f"partitions, panel {w.K}+{w.N} columns); {dt:.2f} s in total"}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -125,6 +229,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "partitioned":
+        bench_partitioned(args)
+        return
     import synth
     import paper_2108_08845_amd as P
 

@@ -205,6 +205,7 @@ struct psvd_handle {
     // offset poff[i] * K with leading dimension M_i.  Empty: one M-row panel.
     std::vector<int64_t> parts, poff;
     int32_t r_local = 0;
+    DevBuf pdesc;       // partition panels and row-chunk work lists of one update
 };
 
 static bool profiling(const psvd_handle* h) { return (h->opt.flags & PSVD_OPT_PROFILE) != 0; }
@@ -586,6 +587,7 @@ void psvd_finalize(psvd_handle* h) {
     }
     h->d.release();
     h->part.release();
+    h->pdesc.release();
     h->partP.release();
     h->partG.release();
     h->tall.release();
@@ -1531,53 +1533,87 @@ std::vector<PanelSeg> part_panels(const psvd_handle* h, int r, const void* const
 
 }  // namespace
 
-// out (nl x nl FP64, symmetric) = sum_i S_i^T S_i: every partition's row
-// chunks write their own partials, one reduction sums all of them in order.
-static int tn_product_parts(psvd_handle* h, const std::vector<PanelSeg>& S, bool fp64, double* out,
-                            const int32_t* skip, int skip_mask) {
-    const int nl = S[0].ncols;
-    const int mbl = ceil_div(nl, 64);
-    const int nob = mbl * (mbl + 1) / 2;
-    const int64_t chunk = pick_chunk(h->M, nob, 64);
-    std::vector<int> items(S.size());
-    size_t total = 0;
-    for (size_t i = 0; i < S.size(); ++i) {
-        items[i] = ceil_div(S[i].rows, chunk);
-        total += items[i];
-    }
-    HIPCHK(h, h->part.ensure(total * nob * 64 * 64 * sizeof(double)));
-    size_t item0 = 0;
-    for (size_t i = 0; i < S.size(); ++i) {
-        TnArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.lseg = S[i];
-        a.rseg = S[i];
-        a.chunk = chunk;
-        a.mbl = mbl;
-        a.sym = 1;
-        a.part = h->part.as<double>() + item0 * nob * 64 * 64;
-        a.skip = skip;
-        a.skip_mask = skip_mask;
-        a.nob = nob;
-        int pe = prof_begin(h, PSVD_KC_TN);
-        HIPCHK(h, launch_tn(fp64, a, items[i], h->stream));
-        prof_end(h, pe);
-        item0 += items[i];
-    }
+// Device copies of the partition panels and of their row chunks: one launch
+// covers every partition (a chunk is (partition, first row, end row)).
+struct PartLists {
+    const PanelSeg* segs = nullptr;
+    const WorkItem* items = nullptr;
+    int nitems = 0;
+    int64_t chunk = 0;
+};
+
+static std::vector<WorkItem> part_items(const psvd_handle* h, int64_t chunk) {
+    std::vector<WorkItem> it;
+    for (size_t i = 0; i < h->parts.size(); ++i)
+        for (int64_t r0 = 0; r0 < h->parts[i]; r0 += chunk) {
+            WorkItem w;
+            w.seg = (int32_t)i;
+            w.pad = 0;
+            w.row0 = r0;
+            w.row1 = std::min<int64_t>(r0 + chunk, h->parts[i]);
+            it.push_back(w);
+        }
+    return it;
+}
+
+// out (nl x nl FP64, symmetric) = sum_i S_i^T S_i: the partials of every
+// partition's row chunks are summed in one fixed-order reduction.
+static int tn_product_parts(psvd_handle* h, const PanelSeg& S0, const PartLists& pl, int nob, int mbl, bool fp64,
+                            double* out, const int32_t* skip, int skip_mask) {
+    HIPCHK(h, h->part.ensure((size_t)pl.nitems * nob * 64 * 64 * sizeof(double)));
+    TnArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.lseg = S0;
+    a.rseg = S0;
+    a.lsegs = pl.segs;
+    a.rsegs = pl.segs;
+    a.items = pl.items;
+    a.chunk = pl.chunk;
+    a.mbl = mbl;
+    a.sym = 1;
+    a.part = h->part.as<double>();
+    a.skip = skip;
+    a.skip_mask = skip_mask;
+    a.nob = nob;
+    int pe = prof_begin(h, PSVD_KC_TN);
+    HIPCHK(h, launch_tn(fp64, a, pl.nitems, h->stream));
+    prof_end(h, pe);
     TnReduceArgs ra;
     std::memset(&ra, 0, sizeof(ra));
     ra.part = h->part.as<double>();
     ra.seg_item0 = nullptr;
-    ra.nitems = (int)total;
+    ra.nitems = pl.nitems;
     ra.mbl = mbl;
     ra.nob = nob;
-    ra.nl = nl;
-    ra.nr = nl;
+    ra.nl = S0.ncols;
+    ra.nr = S0.ncols;
     ra.sym = 1;
     ra.out = out;
     ra.skip = skip;
     ra.skip_mask = skip_mask;
     HIPCHK(h, launch_tn_reduce(ra, 1, h->stream));
+    return PSVD_OK;
+}
+
+// out_i (partition panels' outputs) = S_i X for every partition in one launch.
+static int nn_product_parts(psvd_handle* h, const PanelSeg& S0, const PartLists& pl, const double* X, int64_t ldx,
+                            int nx, bool fp64, const int32_t* skip, int skip_mask, int cls, int need_mask = 0) {
+    NnArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.seg = S0;
+    a.segs = pl.segs;
+    a.items = pl.items;
+    a.chunk = pl.chunk;
+    a.X = X;
+    a.ldx = ldx;
+    a.n = S0.ncols;
+    a.nx = nx;
+    a.skip = skip;
+    a.skip_mask = skip_mask;
+    a.need_mask = need_mask;
+    int pe = prof_begin(h, cls);
+    HIPCHK(h, launch_nn(fp64, a, pl.nitems, h->stream));
+    prof_end(h, pe);
     return PSVD_OK;
 }
 
@@ -1683,7 +1719,35 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
         Q1[i].ldo = C[i].ldo;
         Q1[i].out_dtype = h->u_dtype;
     }
-    rc = tn_product_parts(h, C, true, L.G, nullptr, 0);
+    // descriptors: [C panels | Q1 panels | C panels writing Q1 | Gram chunks | product chunks]
+    const int mbl = ceil_div(n, 64), nob = mbl * (mbl + 1) / 2;
+    const std::vector<WorkItem> tit = part_items(h, pick_chunk(h->M, nob, 64));
+    const int64_t nchunk = pick_chunk(h->M, ceil_div(n, 64), 64);
+    const std::vector<WorkItem> nit = part_items(h, nchunk);
+    {
+        const size_t bytes = sizeof(PanelSeg) * 3 * P + sizeof(WorkItem) * (tit.size() + nit.size());
+        HIPCHK(h, h->pdesc.ensure(bytes));
+        std::vector<unsigned char> host(bytes);
+        unsigned char* q = host.data();
+        std::memcpy(q, C.data(), sizeof(PanelSeg) * P);
+        std::memcpy(q + sizeof(PanelSeg) * P, Q1.data(), sizeof(PanelSeg) * P);
+        std::memcpy(q + sizeof(PanelSeg) * 2 * P, Qin.data(), sizeof(PanelSeg) * P);
+        std::memcpy(q + sizeof(PanelSeg) * 3 * P, tit.data(), sizeof(WorkItem) * tit.size());
+        std::memcpy(q + sizeof(PanelSeg) * 3 * P + sizeof(WorkItem) * tit.size(), nit.data(),
+                    sizeof(WorkItem) * nit.size());
+        HIPCHK(h, hipMemcpyAsync(h->pdesc.p, host.data(), bytes, hipMemcpyHostToDevice, st));
+        HIPCHK(h, hipStreamSynchronize(st));   // the host staging vector goes out of scope
+    }
+    const PanelSeg* dC = h->pdesc.as<PanelSeg>();
+    const PanelSeg* dQ = dC + P;
+    const PanelSeg* dQin = dQ + P;
+    const WorkItem* dT = (const WorkItem*)(dQin + P);
+    const WorkItem* dN = dT + tit.size();
+    const int64_t tchunk = pick_chunk(h->M, nob, 64);
+    PartLists cg{dC, dT, (int)tit.size(), tchunk}, qg{dQ, dT, (int)tit.size(), tchunk};
+    PartLists cn{dC, dN, (int)nit.size(), nchunk}, qn{dQ, dN, (int)nit.size(), nchunk};
+    PartLists qin{dQin, dN, (int)nit.size(), nchunk};
+    rc = tn_product_parts(h, C[0], cg, nob, mbl, true, L.G, nullptr, 0);
     if (rc) return rc;
     SmallArgs sa;
     std::memset(&sa, 0, sizeof(sa));
@@ -1713,11 +1777,9 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
         prof_end(h, pes);
     }
     const int skipmask = DEV_FALLBACK | DEV_NONFINITE | DEV_BREAKDOWN;
-    for (int i = 0; i < P; ++i) {
-        rc = nn_product(h, Qin[i], L.Xn, n, n, fp64, nullptr, 0, dstat, skipmask);
-        if (rc) return rc;
-    }
-    rc = tn_product_parts(h, Q1, true, L.G2, dstat, skipmask);
+    rc = nn_product_parts(h, Qin[0], qin, L.Xn, n, n, fp64, dstat, skipmask, PSVD_KC_NN);
+    if (rc) return rc;
+    rc = tn_product_parts(h, Q1[0], qg, nob, mbl, true, L.G2, dstat, skipmask);
     if (rc) return rc;
     {
         int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
@@ -1726,13 +1788,11 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     }
     // lift of every partition with the shared small factor (the eigen route
     // of a Cholesky breakdown lifts from the panel itself)
-    for (int i = 0; i < P; ++i) {
-        rc = nn_product(h, Q1[i], L.T, n, rk, fp64, nullptr, 0, dstat, skipmask, PSVD_KC_LIFT);
-        if (rc) return rc;
-        rc = nn_product(h, C[i], L.T, n, rk, fp64, nullptr, 0, dstat, DEV_NONFINITE | DEV_BREAKDOWN, PSVD_KC_LIFT,
-                        DEV_FALLBACK);
-        if (rc) return rc;
-    }
+    rc = nn_product_parts(h, Q1[0], qn, L.T, n, rk, fp64, dstat, skipmask, PSVD_KC_LIFT);
+    if (rc) return rc;
+    rc = nn_product_parts(h, C[0], cn, L.T, n, rk, fp64, dstat, DEV_NONFINITE | DEV_BREAKDOWN, PSVD_KC_LIFT,
+                          DEV_FALLBACK);
+    if (rc) return rc;
     HIPCHK(h, hipEventRecord(h->ev1, st));
     HIPCHK(h, hipMemcpyAsync(h->status_host, dstat, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
