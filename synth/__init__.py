@@ -165,3 +165,22 @@ def loss_weights(w: Workload) -> np.ndarray:
 def numpy_cm(t: torch.Tensor) -> np.ndarray:
     """(N, M) contiguous tensor -> (M, N) float64 Fortran-ordered numpy array (same column-major matrix)."""
     return np.asfortranarray(t.detach().to("cpu", torch.float64).numpy().T)
+
+
+def burgers_snapshots(nx: int = 16384, nt: int = 800, Re: float = 1000.0, L: float = 1.0, tf: float = 2.0,
+                      dtype=torch.float64, device="cpu") -> torch.Tensor:
+    """Snapshots of the viscous Burgers equation from its closed-form solution
+    (the paper's first experiment, Eq. (13)): u(x, t) = (x / (t + 1)) /
+    (1 + sqrt((t + 1) / t0) exp(Re x^2 / (4 t + 4))), t0 = exp(Re / 8), on nx
+    equispaced points of [0, L] and nt equispaced times of [0, tf].
+
+    Evaluated in float64 with the square root folded into the exponent
+    (exp(Re x^2 / (4t + 4) + ln(t + 1) / 2 - Re / 16)), whose largest
+    argument (x = L, t = 0) is Re / 4 - Re / 16, finite in float64; then cast
+    to `dtype`.  Returns an (nt, nx) tensor: the nx x nt snapshot matrix in
+    column-major order (one snapshot per column)."""
+    x = torch.linspace(0.0, L, nx, dtype=torch.float64, device=device)
+    t = torch.linspace(0.0, tf, nt, dtype=torch.float64, device=device)[:, None]
+    e = Re * x[None, :] ** 2 / (4.0 * t + 4.0) + 0.5 * torch.log(t + 1.0) - Re / 16.0
+    u = (x[None, :] / (t + 1.0)) / (1.0 + torch.exp(e))
+    return u.to(dtype).contiguous()

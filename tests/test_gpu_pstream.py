@@ -128,3 +128,35 @@ def test_pstream_errors():
     # FP32 data on an FP64 handle
     with pytest.raises(P.PsvdError):
         ps.incorporate_data([t.float() for t in split_gpu(b, [340, 60])])
+
+
+def test_burgers_partitioned_stream_vs_serial():
+    # The paper's first experiment at its size: Burgers snapshots of Eq. (13),
+    # 16384 grid points x 800 snapshots (FP64), streamed in 8 batches of 100
+    # with K = 20, ff = 1, on 4 row partitions against the single-panel stream
+    # (serial) and the oracle's partitioned stream; modes 1 and 2 against the
+    # SVD of the whole matrix (LAPACK).
+    P = lib()
+    u = synth.burgers_snapshots(16384, 800)              # (800, 16384): column-major 16384 x 800
+    sizes = [4096] * 4
+    K, nb = 20, 100
+    ps = P.PartitionedStreamingSVD(sizes, K, ff=1.0, r_local=nb, precision="fp64")
+    ss = P.StreamingSVD(16384, K, ff=1.0, precision="fp64")
+    po = oracle.PartitionedStreamOracle(sizes, K, ff=1.0, r_local=nb)
+    ug = u.to("cuda")
+    A = synth.numpy_cm(u)
+    for b in range(8):
+        blk = ug[b * nb:(b + 1) * nb]                    # (nb, 16384) contiguous
+        ps.incorporate_data(split_gpu(blk, sizes))
+        ss.incorporate_data(blk.t())
+        po.incorporate(split_np(np.asfortranarray(A[:, b * nb:(b + 1) * nb]), sizes))
+    s_p, s_s, s_o = ps.singular_values, ss.singular_values, po.singular_values
+    assert sigma_rel_err(s_p, s_o) <= 1e-10
+    assert sigma_rel_err(s_p, s_s) <= 1e-10
+    Up = ps.modes.double().cpu().numpy()
+    Us = ss.modes.double().cpu().numpy()
+    assert np.abs(Up[:, :2] - po.modes[:, :2]).max() <= 1e-9
+    assert np.abs(align_signs(Up[:, :2], Us[:, :2]) - Us[:, :2]).max() <= 1e-9
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    assert sigma_rel_err(s_p[:2], sl[:2]) <= 1e-6           # truncation of the stream at K = 20
+    assert np.abs(align_signs(Up[:, :2], Ul[:, :2]) - Ul[:, :2]).max() <= 1e-6

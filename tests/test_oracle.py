@@ -362,6 +362,33 @@ def test_apmos_truncated_local_rank_is_gram_of_W():
 # ----------------------------------------------------------------------------
 
 # ----------------------------------------------------------------------------
+# Burgers snapshots (the paper's first experiment, Eq. (13))
+# ----------------------------------------------------------------------------
+
+def test_burgers_generator_matches_closed_form():
+    # a few entries of the generator against the closed form written directly
+    u = synth.numpy_cm(synth.burgers_snapshots(513, 41))
+    Re, t0 = 1000.0, math.exp(1000.0 / 8.0)
+    for xi, ti in [(0, 0), (100, 0), (256, 7), (400, 40), (512, 20)]:
+        x, t = xi / 512.0, 2.0 * ti / 40.0
+        ref = (x / (t + 1.0)) / (1.0 + math.sqrt((t + 1.0) / t0) * math.exp(Re * x * x / (4.0 * t + 4.0)))
+        assert abs(u[xi, ti] - ref) <= 1e-15 * max(1.0, abs(ref))
+    assert np.isfinite(u).all() and u[0].max() == 0.0   # u(0, t) = 0
+
+
+def test_burgers_partitioned_modes_match_serial():
+    # Serial SVD (LAPACK) against APMOS over 4 row partitions with the
+    # paper's local truncation r1 = 50: the first two modes agree.
+    A = synth.numpy_cm(synth.burgers_snapshots(4096, 200))
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    parts = [np.asfortranarray(p) for p in np.split(A, 4)]
+    Us, lam, _ = oracle.apmos(parts, 50, 5)
+    Ua = np.vstack(Us)
+    assert sigma_rel_err(lam[:2], sl[:2]) <= 1e-12
+    assert np.abs(align_signs(Ua[:, :2], Ul[:, :2]) - Ul[:, :2]).max() <= 1e-12
+
+
+# ----------------------------------------------------------------------------
 # Partitioned streaming (the parallel variant of Sec. 3 on row partitions)
 # ----------------------------------------------------------------------------
 
