@@ -46,9 +46,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the oracle sample (0: all M rows)")
     ap.add_argument("--M", type=int, default=1 << 20)
-    ap.add_argument("--workload", default="randomized", choices=["randomized", "partitioned"],
+    ap.add_argument("--workload", default="randomized", choices=["randomized", "partitioned", "burgers"],
                     help="randomized: the headline mixed-precision randomized stream; partitioned: the "
-                         "partitioned streaming SVD (APMOS initialisation, partition QR combination)")
+                         "partitioned streaming SVD (APMOS initialisation, partition QR combination); burgers: "
+                         "the partitioned stream over the closed-form Burgers snapshots (16384 x 800, FP64)")
     ap.add_argument("--partitions", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibration of the HBM byte counters)")
@@ -221,6 +222,92 @@ def bench_partitioned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_burgers(args):
+    """The paper's first experiment: Burgers snapshots (Eq. (13), 16384 points x
+    800 snapshots, FP64) streamed in 8 batches of 100 on 4 row partitions (K =
+    20, ff = 1): APMOS initialisation, then 7 partitioned updates.  A step is one
+    whole pass over the 800 snapshots; one JSON line."""
+    import synth
+    import paper_2108_08845_amd as P
+    nx, nt, nb, K, parts = 16384, 800, 100, 20, 4
+    sizes = [nx // parts] * parts
+    u = synth.burgers_snapshots(nx, nt).to("cuda")
+    blocks = []
+    for b in range(nt // nb):
+        blk = u[b * nb:(b + 1) * nb]
+        blocks.append([blk[:, i * sizes[0]:(i + 1) * sizes[0]].t() for i in range(parts)])
+    torch.cuda.synchronize()
+
+    def one_pass(profile):
+        svd = P.PartitionedStreamingSVD(sizes, K, ff=1.0, r_local=nb, precision="fp64", profile=profile)
+        for bl in blocks:
+            svd.incorporate_data(bl)
+        return svd
+
+    for _ in range(args.warmup):
+        one_pass(False).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        svd = one_pass(False)
+        s = svd.singular_values
+        svd.close()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    svd = one_pass(True)
+    st = svd.stats()
+    kern = st["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    avg_ms = kern[dom]["ms"] / max(1, kern[dom]["launches"])
+    n = K + nb
+    if dom == "small_svd":   # Cholesky + Jacobi SVD of the n x n R in one work-group (per launch, two per update)
+        flops = 2.0 * n ** 3 + 4.0 * max(1, st["last_sweeps"]) * n ** 3
+        roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s"}
+    elif dom == "tn":
+        roof = {"bound": "mfma", "achieved": nx * n * (n + 1) / (avg_ms * 1e-3) / 1e12,
+                "peak": MFMA_PEAK_TFLOPS["f64"], "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": nx * n * 8 * 2 / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms})
+    per_kernel = {k: {"launches": v["launches"], "avg_ms": (v["ms"] / v["launches"]) if v["launches"] else 0.0}
+                  for k, v in kern.items() if v["launches"]}
+    svd.close()
+    out = {
+        "metric": "snapshot GB/s ingested (partitioned streaming SVD, Burgers snapshots)",
+        "value": nx * nt * 8 / (ms * 1e-3) / 1e9, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64", "data": "closed-form Burgers solution (Eq. 13)",
+        "config": {"workload": f"burgers_partitioned_stream_{nx}x{nt}_P{parts}_batches{nb}_K{K}_fp64",
+                   "grid_points": nx, "snapshots": nt, "batch": nb, "partitions": sizes, "K": K, "ff": 1.0,
+                   "parallelism": "single GPU"},
+        "sigma_1_2": [float(x) for x in s[:2]],
+        "roofline": roof, "kernels": per_kernel,
+    }
+    del blocks, u
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        import oracle
+        A = synth.numpy_cm(synth.burgers_snapshots(nx, nt))
+        dt, npass = 0.0, 0
+        while npass < 20 and (npass == 0 or dt < 10.0):
+            po = oracle.PartitionedStreamOracle(sizes, K, ff=1.0, r_local=nb)
+            t0 = time.perf_counter()
+            for b in range(nt // nb):
+                po.incorporate([np.asfortranarray(A[i * sizes[0]:(i + 1) * sizes[0], b * nb:(b + 1) * nb])
+                                for i in range(parts)])
+            dt += time.perf_counter() - t0
+            npass += 1
+        out["cpu_baseline"] = {"value": npass * nx * nt * 8 / dt / 1e9, "unit": "GB/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{npass} whole passes of the oracle's partitioned stream over the same "
+                                         f"snapshots; {dt:.2f} s in total"}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -231,6 +318,9 @@ def main():
         sys.exit(2)
     if args.workload == "partitioned":
         bench_partitioned(args)
+        return
+    if args.workload == "burgers":
+        bench_burgers(args)
         return
     import synth
     import paper_2108_08845_amd as P
