@@ -332,9 +332,14 @@ def main():
     bytes_per_step = w.M * w.N * 4
 
     log(f"timing {args.precision}: warmup {args.warmup}, steps {args.steps}")
-    ms, svd, st = run_stream(P, w, batches, args.precision, args.steps, args.warmup, profile=True)
+    ms, svd, _ = run_stream(P, w, batches, args.precision, args.steps, args.warmup, profile=False)
     s_main = svd.singular_values
+    svd.close()
     value = bytes_per_step / (ms * 1e-3) / 1e9
+    # Per-kernel device times from a second run of the same steps with the
+    # library's event pairs around its launches (kept out of the timed run).
+    log("per-kernel times (event-timed run)")
+    _, svd, st = run_stream(P, w, batches, args.precision, args.steps, args.warmup, profile=True)
 
     # Roofline of the dominant kernel class (largest total device time).
     n = w.K + w.N

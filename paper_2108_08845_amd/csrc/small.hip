@@ -261,24 +261,27 @@ constexpr int TALL_CHUNK = TALL_KC * TALL_LDC;   // doubles of the LDS chunk
 static_assert(TALL_CHUNK >= 64 * CHOL64_LD, "the chunk also holds the n <= 64 Cholesky copy");
 
 struct TallStager {
+    // Loads only (at clamped, always valid addresses): nothing reads the
+    // loaded values before `store`, so the loads of the next chunk stay in
+    // flight while the matrix cores work on the current one; the mask of rows
+    // past n and columns past l is applied at the store.
     double pre[4];
     __device__ __forceinline__ void fetch(const double* P, int n, int l, int ldp, int r0) {
-        const int lp = ((l + 15) >> 4) << 4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = threadIdx.x + q * blockDim.x;
             const int r = e & 63, c = e >> 6;
             const int rc = r0 + r < n ? r0 + r : n - 1, cc = c < l ? c : l - 1;
-            const double v = gldd(P + rc + (size_t)cc * ldp);
-            pre[q] = (e < TALL_KC * lp && c < l && r0 + r < n) ? v : 0.0;
+            pre[q] = gldd(P + rc + (size_t)cc * ldp);
         }
     }
-    __device__ __forceinline__ void store(double* Cn, int l) {
+    __device__ __forceinline__ void store(double* Cn, int n, int l, int r0) {
         const int lp = ((l + 15) >> 4) << 4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = threadIdx.x + q * blockDim.x;
-            if (e < TALL_KC * lp) Cn[(e >> 6) * TALL_LDC + (e & 63)] = pre[q];
+            const int r = e & 63, c = e >> 6;
+            if (e < TALL_KC * lp) Cn[c * TALL_LDC + r] = (c < l && r0 + r < n) ? pre[q] : 0.0;
         }
     }
 };
@@ -300,8 +303,8 @@ __device__ __forceinline__ void wg_gram_tall(int n, int l, const double* P, int 
     TallStager st;
     st.fetch(P, n, l, ldp, 0);
     for (int k0 = 0; k0 < n; k0 += TALL_KC) {
-        st.store(Cn, l);
-        __syncthreads();
+        st.store(Cn, n, l, k0);
+        lds_barrier();   // waves exchange only the LDS chunk: the prefetch stays in flight
         if (k0 + TALL_KC < n) st.fetch(P, n, l, ldp, k0 + TALL_KC);
         if (has) {
             const double* ca = Cn + (ib * 16 + (lane & 15)) * TALL_LDC + (lane >> 4);
@@ -312,7 +315,7 @@ __device__ __forceinline__ void wg_gram_tall(int n, int l, const double* P, int 
                 acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[kk + 4], cb[kk + 4], acc1, 0, 0, 0);
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     if (has) {
 #pragma unroll
@@ -353,8 +356,8 @@ __device__ __forceinline__ void wg_mul_tall(int n, int l, const double* P, int l
     TallStager st;
     st.fetch(P, n, l, ldp, 0);
     for (int r0 = 0; r0 < n; r0 += TALL_KC) {
-        st.store(Cn, l);
-        __syncthreads();
+        st.store(Cn, n, l, r0);
+        lds_barrier();
         if (r0 + TALL_KC < n) st.fetch(P, n, l, ldp, r0 + TALL_KC);
         if (has) {
             d4_t acc0 = d4_t{0.0, 0.0, 0.0, 0.0}, acc1 = d4_t{0.0, 0.0, 0.0, 0.0};
@@ -375,8 +378,9 @@ __device__ __forceinline__ void wg_mul_tall(int n, int l, const double* P, int l
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
+    __syncthreads();   // X complete before the caller reads it
 }
 
 // ---------------------------------------------------------------------------
