@@ -1149,6 +1149,248 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// k_final_split64: the split-BF16 final pass with 64-row tiles (float4-aligned
+// panels, NP <= 320).  Each column of a tile is one 256-byte segment (against
+// 128 bytes for 32-row tiles), which the HBM stream of this pass needs.  The
+// hi / lo tile fills one LDS buffer (two would exceed a CU's LDS), so a tile
+// takes three barriers: Y = C X~ (phase A) | P += C^T Y and G += Y^T Y
+// (phase B) | split and store of the next tile, whose loads were issued one
+// tile earlier and stay in flight through phases A and B.
+// ----------------------------------------------------------------------------
+template <int NKS>
+__global__ __launch_bounds__(512) void k_final_split64(FusedArgs a) {
+    constexpr int TM = 64, NT = 512;
+    constexpr int NP = NKS * 32;
+    constexpr int RG = TM / 4;                      // 16 row groups
+    constexpr int CGR = NT / RG;                    // 32 column groups of 4 x 4 blocks per round
+    constexpr int NC0 = NP / 4 < 64 ? NP / 4 : 64;
+    constexpr int R0 = (NC0 + CGR - 1) / CGR;
+    constexpr int NX = NP > 256 ? (NP - 256) / CGR : 0;
+    static_assert(NP <= 256 || (NP - 256) % CGR == 0, "columns past 256 in whole rounds");
+    constexpr int NIT = NKS / 2;                    // P row blocks per wave (2 NKS blocks over 4 wave pairs)
+    static_assert(NKS % 2 == 0, "an even number of 32-column slices");
+    constexpr int ldR = NP + 8, ldY = TM + 8, LDG = FU_LB + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* Crh = (uint16_t*)smem;                // hi, TM x ldR row-major
+    uint16_t* Crl = Crh + TM * ldR;                 // lo
+    uint16_t* Ysh = Crl + TM * ldR;                 // 64 x TM, column-major (hi)
+    uint16_t* Ysl = Ysh + FU_LB * ldY;              //                        (lo)
+    double* Gs = (double*)(Ysl + FU_LB * ldY);      // FP64 sums of G, 64 x 64, leading dimension LDG
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const FusedCoords fc = fused_coords(a);
+    if (fc.wg >= a.nwg) return;
+    const int wg = fc.wg, lb = fc.lb;
+    const int c0 = lb * FU_LB;
+    const int jb = w & 3, ibA = w >> 2;             // phase A: row blocks ibA, ibA + 2 of column block jb
+
+    // X~ = bf16(X) -> LDS (in the tile buffer, free until the first tile), then
+    // the B fragments of phase A into registers
+    bf8_t xh[NKS];
+    {
+        constexpr int ldxs = NP + 8;
+        uint16_t* Xb = Crh;
+        stage_x<NP, NT>(a, c0, [&](int k, int j, double v) { Xb[j * ldxs + k] = f32_to_bf16_rne((float)v); });
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks)
+            xh[ks] = lds_b128(&Xb[(jb * 16 + (lane & 15)) * ldxs + ks * 32 + 8 * (lane >> 4)]);
+        __syncthreads();
+    }
+
+    f4_t accP[NIT * 2];
+#pragma unroll
+    for (int t = 0; t < NIT * 2; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    const int gi = w >> 1, gj0 = (w & 1) * 2;
+    double* gsl = Gs + (gi * 16 + 4 * (lane >> 4)) + (size_t)(gj0 * 16 + (lane & 15)) * LDG;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gsl[v + j * 16 * LDG] = 0.0;
+
+    // tile loads: 4 x 4 blocks for columns 0 .. 255, single-column float4 beyond
+    const int rg = (tid & 3) | (((tid >> 4) & 3) << 2);
+    const int cgl = ((tid >> 2) & 3) | ((tid >> 6) << 2);
+    const int rgx = tid & 15, cxl = tid >> 4;
+    const float* cp[R0][4];
+    bool cv[R0][4];
+#pragma unroll
+    for (int rr = 0; rr < R0; ++rr)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = (rr * CGR + cgl) * 4 + q;
+            cv[rr][q] = c < a.n;
+            cp[rr][q] = fcol(a.seg, c < a.n ? c : a.n - 1);
+        }
+    const float* cpx[NX > 0 ? NX : 1];
+    bool cvx[NX > 0 ? NX : 1];
+#pragma unroll
+    for (int x = 0; x < NX; ++x) {
+        const int c = 256 + CGR * x + cxl;
+        cvx[x] = c < a.n;
+        cpx[x] = fcol(a.seg, c < a.n ? c : a.n - 1);
+    }
+    const int64_t rows = a.seg.rows;
+    f4_t pf[R0][4];
+    f4_t pfx[NX > 0 ? NX : 1];
+    auto round_on = [&](int rr) { return (rr + 1) * CGR <= NC0 || rr * CGR + cgl < NC0; };
+    // loads only, rows % 4 == 0: past the end a float4 re-reads the last rows
+    auto fetch = [&](int64_t t) {
+        const int64_t row = t * TM + rg * 4, rowx = t * TM + rgx * 4;
+        const int64_t rowc = row < rows ? row : rows - 4, rowxc = rowx < rows ? rowx : rows - 4;
+#pragma unroll
+        for (int rr = 0; rr < R0; ++rr)
+            if (round_on(rr))
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + rowc);
+#pragma unroll
+        for (int x = 0; x < NX; ++x) pfx[x] = gld4(cpx[x] + rowxc);
+    };
+    auto store_tile = [&](int64_t tl) {
+        const bool rv = tl * TM + rg * 4 < rows;
+#pragma unroll
+        for (int rr = 0; rr < R0; ++rr) {
+            const int cg = rr * CGR + cgl;
+            if (round_on(rr)) {
+                f4_t v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (cv[rr][q] && rv) ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t h0, l0, h1, l1;
+                    split_bf16x2(v[0][e], v[1][e], &h0, &l0);
+                    split_bf16x2(v[2][e], v[3][e], &h1, &l1);
+                    *(uint64_t*)&Crh[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)h0 | ((uint64_t)h1 << 32);
+                    *(uint64_t*)&Crl[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)l0 | ((uint64_t)l1 << 32);
+                }
+            }
+        }
+        const bool rvx = tl * TM + rgx * 4 < rows;
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+            const f4_t v = (cvx[x] && rvx) ? pfx[x] : f4_t{0.f, 0.f, 0.f, 0.f};
+            const int c = 256 + CGR * x + cxl;
+#pragma unroll
+            for (int e = 0; e < 4; e += 2) {
+                uint32_t h, l;
+                split_bf16x2(v[e], v[e + 1], &h, &l);
+                Crh[(rgx * 4 + e) * ldR + c] = (uint16_t)(h & 0xFFFF);
+                Crh[(rgx * 4 + e + 1) * ldR + c] = (uint16_t)(h >> 16);
+                Crl[(rgx * 4 + e) * ldR + c] = (uint16_t)(l & 0xFFFF);
+                Crl[(rgx * 4 + e + 1) * ldR + c] = (uint16_t)(l >> 16);
+            }
+        }
+    };
+
+    const int64_t nwg = a.nwg;
+    int64_t t = wg;
+    if (t < a.tiles) {
+        fetch(t);
+        store_tile(t);
+        fetch(t + nwg);
+        lds_barrier();
+        for (; t < a.tiles; t += nwg) {
+            // Phase A: Y rows 16 ib .. of column block jb = C_tile X~ = C_hi X~ + C_lo X~
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ib = ibA + 2 * h;
+                f4_t acc0 = f4_t{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) {
+                    const int off = (ib * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4);
+                    const bf8_t ah = lds_b128(&Crh[off]), al = lds_b128(&Crl[off]);
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xh[ks], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, xh[ks], acc1, 0, 0, 0);
+                }
+                const f4_t y = acc0 + acc1;
+                const int col = jb * 16 + (lane & 15), r0 = ib * 16 + 4 * (lane >> 4);
+                uint32_t h0, l0, h1, l1;
+                split_bf16x2(y[0], y[1], &h0, &l0);
+                split_bf16x2(y[2], y[3], &h1, &l1);
+                *(uint64_t*)&Ysh[col * ldY + r0] = (uint64_t)h0 | ((uint64_t)h1 << 32);
+                *(uint64_t*)&Ysl[col * ldY + r0] = (uint64_t)l0 | ((uint64_t)l1 << 32);
+                if (a.yout != nullptr && c0 + col < a.lx) {
+                    const int64_t row = t * TM + r0;
+                    if (row < rows) gst4(a.yout + (size_t)(c0 + col) * (size_t)a.ldy + row, y);
+                }
+            }
+            lds_barrier();
+            // Phase B: P += C_tile^T Y (k = 64 rows: two steps) and G += Y^T Y.
+            // Wave w: column blocks 2 (w % 2) + {0, 1}, row blocks (w / 2) NIT + u.
+            {
+                const int jp = w & 1, rb0 = (w >> 1) * NIT;
+                const int koff = 8 * (lane >> 4);
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    bf8_t yh[2], yl[2];
+#pragma unroll
+                    for (int jj = 0; jj < 2; ++jj) {
+                        const int boff = ((2 * jp + jj) * 16 + (lane & 15)) * ldY + ks * 32 + koff;
+                        yh[jj] = lds_b128(&Ysh[boff]);
+                        yl[jj] = lds_b128(&Ysl[boff]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < NIT; ++u) {
+                        const bf8_t ah = lds_colfrag(Crh + ks * 32 * ldR, ldR, (rb0 + u) * 16, lane);
+                        const bf8_t al = lds_colfrag(Crl + ks * 32 * ldR, ldR, (rb0 + u) * 16, lane);
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int jj = 0; jj < 2; ++jj) {
+                            f4_t acc = accP[u * 2 + jj];
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, yh[jj], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yl[jj], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yh[jj], acc, 0, 0, 0);
+                            accP[u * 2 + jj] = acc;
+                        }
+                    }
+                    // G: row block w / 2 against the column blocks of this wave
+                    const int aoff = (gi * 16 + (lane & 15)) * ldY + ks * 32 + koff;
+                    const bf8_t gh = lds_b128(&Ysh[aoff]), gl = lds_b128(&Ysl[aoff]);
+#pragma unroll
+                    for (int jj = 0; jj < 2; ++jj) {
+                        f4_t g = f4_t{0.f, 0.f, 0.f, 0.f};
+                        g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl, yl[jj], g, 0, 0, 0);
+                        g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl, yh[jj], g, 0, 0, 0);
+                        g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, yl[jj], g, 0, 0, 0);
+                        g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh, yh[jj], g, 0, 0, 0);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) gsl[v + jj * 16 * LDG] += (double)g[v];
+                    }
+                }
+            }
+            lds_barrier();
+            // the next tile into the buffer, then the loads of the one after it
+            store_tile(t + nwg);
+            fetch(t + 2 * nwg);
+            lds_barrier();
+        }
+    }
+    float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+        const int jp = w & 1, rb = (w >> 1) * NIT + u;
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rb * 16 + 4 * (lane >> 4) + v;
+                const int col = (2 * jp + jj) * 16 + (lane & 15);
+                gst(outP + row + (size_t)col * NP, accP[u * 2 + jj][v]);
+            }
+    }
+    double* outG = a.partG + (size_t)wg * FU_LB * FU_LB;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = gi * 16 + 4 * (lane >> 4) + v;
+            const int col = (gj0 + j) * 16 + (lane & 15);
+            gstd(outG + row + col * FU_LB, gsl[v + j * 16 * LDG]);
+        }
+}
+
+// ----------------------------------------------------------------------------
 // Plans and launchers of the fused passes.  The compiled (tile height, panel
 // width) pairs are listed here; a plan picks the narrowest compiled width that
 // holds the panel and the tallest tile that fits the LDS of one CU (or the
@@ -1210,7 +1452,7 @@ bool fused_plan(int n, int tile_rows, FusedPlan* p, bool lift) {
 template <class K>
 static hipError_t launch_512(K kern, const FusedArgs& a, size_t lds, hipStream_t st) {
     const int blocks = ((a.nwg + 7) / 8) * 8 * a.nlb;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_lds_attr((const void*)kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(512), lds, st, a);
     return hipGetLastError();
@@ -1247,10 +1489,27 @@ bool split_plan(int n, FusedPlan* p) {
     return false;
 }
 
+static size_t split64_lds(int np) {
+    // hi / lo tile (64 rows), Y hi / lo (16-bit), FP64 sums of G
+    return ((size_t)2 * 64 * (np + 8) + (size_t)2 * FU_LB * (64 + 8)) * 2 + (size_t)FU_LB * (FU_LB + 1) * 8;
+}
+
 hipError_t launch_final_split(const FusedArgs& a, hipStream_t st) {
     if (a.tm != 32 || a.np % 32 || a.nlb != 1) return hipErrorInvalidValue;
     const size_t lds = split_lds(a.np);
     const int nks = a.np / 32;
+    if (a.vec && nks <= 10 && split64_lds(a.np) <= 160 * 1024) {
+        // 64-row tiles: the tile count of the plan (32-row tiles) halves; work
+        // groups past the last tile write zero partials
+        FusedArgs b = a;
+        b.tm = 64;
+        b.tiles = (a.seg.rows + 63) / 64;
+        const size_t l64 = split64_lds(a.np);
+#define FS64(NKS_) \
+        if (nks == NKS_) return launch_512(k_final_split64<NKS_>, b, l64, st);
+        FS64(2) FS64(4) FS64(6) FS64(8) FS64(10)
+#undef FS64
+    }
 #define FS(NKS_) \
     if (nks == NKS_) \
         return a.vec ? launch_512(k_final_split<NKS_, true>, a, lds, st) \

@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -63,10 +64,10 @@ inline double bf16_round(float f) {
 }
 
 // precision: 0 keep FP64, 1 round to FP32, 2 round to FP32 then BF16 (RNE).
-void gen_omega(uint64_t seed, int64_t batch, int64_t n, int64_t l, int rounding, double* out) {
-    const int64_t total = n * l;
+// Pairs [t0, t1) of the n x l matrix (entry 2 t + h from counter t).
+void gen_omega_range(uint64_t seed, int64_t batch, int64_t total, int rounding, double* out, int64_t t0, int64_t t1) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    for (int64_t t = 0; 2 * t < total; ++t) {
+    for (int64_t t = t0; t < t1; ++t) {
         uint32_t c[4] = {(uint32_t)t, (uint32_t)((uint64_t)t >> 32), (uint32_t)batch, (uint32_t)((uint64_t)batch >> 32)};
         philox10(c, k0, k1);
         const double s53 = 1.0 / 9007199254740992.0;
@@ -84,6 +85,26 @@ void gen_omega(uint64_t seed, int64_t batch, int64_t n, int64_t l, int rounding,
             out[2 * t + h] = v;
         }
     }
+}
+
+// Every entry depends only on its own counter, so the pairs are split over a
+// few host threads (the result does not depend on the split).
+void gen_omega(uint64_t seed, int64_t batch, int64_t n, int64_t l, int rounding, double* out) {
+    const int64_t total = n * l, pairs = (total + 1) / 2;
+    const int64_t per = 2048;   // pairs per thread (~0.15 ms of work)
+    int nt = (int)std::min<int64_t>(8, (pairs + per - 1) / per);
+    if (nt <= 1) {
+        gen_omega_range(seed, batch, total, rounding, out, 0, pairs);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (pairs + nt - 1) / nt;
+    for (int i = 1; i < nt; ++i) {
+        const int64_t t0 = i * chunk, t1 = std::min<int64_t>(pairs, t0 + chunk);
+        if (t0 < t1) th.emplace_back(gen_omega_range, seed, batch, total, rounding, out, t0, t1);
+    }
+    gen_omega_range(seed, batch, total, rounding, out, 0, std::min<int64_t>(pairs, chunk));
+    for (auto& x : th) x.join();
 }
 
 int omega_rounding(int precision) { return precision == PSVD_PREC_FP64 ? 0 : (precision == PSVD_PREC_FP32 ? 1 : 2); }

@@ -1,12 +1,33 @@
 // psvd_internal.h -- shared device/host definitions of the gfx950 library.
 #pragma once
 
+#include <map>
+#include <mutex>
+#include <utility>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/psvd.h"
 
 namespace psvd {
+
+// Dynamic-LDS limit of a kernel, raised with hipFuncSetAttribute only when a
+// launch needs more than was set before on this device (the attribute call is
+// a host API round trip; steady-state launches skip it).
+inline hipError_t ensure_lds_attr(const void* fn, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, size_t> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& cur = done[{dev, fn}];
+    if (lds <= cur) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) cur = lds;
+    return e;
+}
+
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef double d4_t __attribute__((ext_vector_type(4)));

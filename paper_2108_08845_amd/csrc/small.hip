@@ -1140,7 +1140,7 @@ hipError_t launch_small_det1(const SmallArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.n);
     const bool in_lds = (a.n) <= SM_LDS_MAX_N;
     const void* fn = in_lds ? (const void*)k_small_det1<true> : (const void*)k_small_det1<false>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_lds_attr(fn, lds);
     if (e != hipSuccess) return e;
     if (in_lds) hipLaunchKernelGGL(k_small_det1<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
     else hipLaunchKernelGGL(k_small_det1<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
@@ -1150,7 +1150,7 @@ hipError_t launch_small_det2(const SmallArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.n);
     const bool in_lds = (a.n) <= SM_LDS_MAX_N;
     const void* fn = in_lds ? (const void*)k_small_det2<true> : (const void*)k_small_det2<false>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_lds_attr(fn, lds);
     if (e != hipSuccess) return e;
     if (in_lds) hipLaunchKernelGGL(k_small_det2<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
     else hipLaunchKernelGGL(k_small_det2<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
@@ -1164,7 +1164,7 @@ hipError_t launch_small_orth(const OrthArgs& a, hipStream_t st) {
     const bool in_lds = rand_in_lds(a.l);
     const size_t lds = in_lds ? rand_lds_bytes(a.l) : 64;
     const void* fn = in_lds ? (const void*)k_small_orth<true> : (const void*)k_small_orth<false>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_lds_attr(fn, lds);
     if (e != hipSuccess) return e;
     if (in_lds) hipLaunchKernelGGL(k_small_orth<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
     else hipLaunchKernelGGL(k_small_orth<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
@@ -1174,7 +1174,7 @@ hipError_t launch_small_rand_final(const RandFinalArgs& a, hipStream_t st) {
     const bool in_lds = rand_in_lds(a.l);
     const size_t lds = in_lds ? rand_lds_bytes(a.l) : 64;
     const void* fn = in_lds ? (const void*)k_small_rand_final<true> : (const void*)k_small_rand_final<false>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_lds_attr(fn, lds);
     if (e != hipSuccess) return e;
     if (in_lds) hipLaunchKernelGGL(k_small_rand_final<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
     else hipLaunchKernelGGL(k_small_rand_final<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
@@ -1204,7 +1204,7 @@ hipError_t launch_apmos_local(const ApmosLocalArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.N);
     const bool in_lds = (a.N) <= SM_LDS_MAX_N;
     const void* fn = in_lds ? (const void*)k_apmos_local<true> : (const void*)k_apmos_local<false>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_lds_attr(fn, lds);
     if (e != hipSuccess) return e;
     if (in_lds) hipLaunchKernelGGL(k_apmos_local<true>, dim3(a.P), dim3(SM_THREADS), lds, st, a);
     else hipLaunchKernelGGL(k_apmos_local<false>, dim3(a.P), dim3(SM_THREADS), lds, st, a);
@@ -1214,7 +1214,7 @@ hipError_t launch_apmos_global(const ApmosGlobalArgs& a, hipStream_t st) {
     size_t lds = small_lds_bytes(a.N);
     const bool in_lds = (a.N) <= SM_LDS_MAX_N;
     const void* fn = in_lds ? (const void*)k_apmos_global<true> : (const void*)k_apmos_global<false>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_lds_attr(fn, lds);
     if (e != hipSuccess) return e;
     if (in_lds) hipLaunchKernelGGL(k_apmos_global<true>, dim3(1), dim3(SM_THREADS), lds, st, a);
     else hipLaunchKernelGGL(k_apmos_global<false>, dim3(1), dim3(SM_THREADS), lds, st, a);
