@@ -82,18 +82,39 @@ __device__ __forceinline__ double ld_col(const ColRef& r, int64_t i) {
 // ----------------------------------------------------------------------------
 // k_tn: partial[item][ob] = L[rows, lcols]^T R[rows, rcols], 64 x 64 blocks.
 // grid.x = work items, grid.y = output blocks (list in obl/obr).
+// sym: L and R are the same panel and only the upper block triangle is
+// formed; in a diagonal block the tile is staged once and the 16 x 16
+// sub-blocks below its diagonal are not formed (k_tn_reduce mirrors them).
+// Sub-blocks whose rows or columns lie past the panel's last column are
+// skipped.  Skipped products are exact zeros or exact transposes (a Gram's
+// products commute and the k order is the same).
 // ----------------------------------------------------------------------------
 constexpr int TN_TM = 64;   // == wave size: one column per wave and load slot
 constexpr int TN_PAD = 1;
 
+
+// One staged 64-row tile: acc[j] += A^T B_j for NJ column sub-blocks starting
+// at j0 (A: this wave's 16 L columns, B: the R tile, both k-contiguous).
+template <class MF, int NJ>
+__device__ __forceinline__ void tn_tile(const typename MF::elem* LR, int aoff, int boff, int lane, int j0,
+                                        typename MF::acc* acc) {
+#pragma unroll
+    for (int k0 = 0; k0 < TN_TM; k0 += MF::KSTEP) {
+        const typename MF::elem av = LR[aoff + (lane & 15) * (TN_TM + TN_PAD) + k0 + (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const typename MF::elem bv = LR[boff + ((j0 + j) * 16 + (lane & 15)) * (TN_TM + TN_PAD) + k0 + (lane >> 4)];
+            acc[j] = MF::mma(av, bv, acc[j]);
+        }
+    }
+}
 
 template <class CT>
 __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     using MF = Mfma<CT>;
     using E = typename MF::elem;
     if (a.skip && (*a.skip & a.skip_mask)) return;
-    __shared__ E Ls[TN_OB * (TN_TM + TN_PAD)];
-    __shared__ E Rs[TN_OB * (TN_TM + TN_PAD)];
+    __shared__ E LR[2 * TN_OB * (TN_TM + TN_PAD)];   // L tile, then R tile (a diagonal block uses the L tile twice)
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const WorkItem it = get_item(a.items, a.chunk, a.lseg.rows);
@@ -104,6 +125,12 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     int obi, obj;
     block_coords(ob, a.mbl, a.sym, &obi, &obj);
     const int lc0 = obi * TN_OB, rc0 = obj * TN_OB;
+    const bool diag = a.sym && obi == obj;               // R tile == L tile
+    const bool wact = lc0 + w * 16 < L.ncols;             // this wave's rows exist
+    const int jr = (R.ncols - rc0 + 15) >> 4;
+    const int jn = jr < 4 ? jr : 4;                       // column sub-blocks with columns
+    const int j0 = diag ? w : 0;                          // upper triangle of a diagonal block
+    const int cnt = jn - j0;                              // acc[j] holds column sub-block j0 + j
 
     typename MF::acc acc[4];
 #pragma unroll
@@ -111,6 +138,7 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
 
     // Per-thread load slots: 64 columns x 64 rows = 4096 elements per operand,
     // 16 per thread; consecutive threads read consecutive rows of a column.
+    constexpr int TSZ = TN_OB * (TN_TM + TN_PAD);
     constexpr int PER = TN_OB * TN_TM / 256;
     double pl[PER], pr[PER];
     auto fetch = [&](int64_t r0) {
@@ -121,42 +149,46 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
             double vl = 0.0, vr = 0.0;
             if (row < it.row1) {
                 if (lc0 + c < L.ncols) vl = ld_col(col_ref(L, lc0 + c), row);
-                if (rc0 + c < R.ncols) vr = ld_col(col_ref(R, rc0 + c), row);
+                if (!diag && rc0 + c < R.ncols) vr = ld_col(col_ref(R, rc0 + c), row);
             }
             pl[e] = vl;
             pr[e] = vr;
         }
     };
+    const int aoff = w * 16 * (TN_TM + TN_PAD), boff = diag ? 0 : TSZ;
     fetch(it.row0);
     for (int64_t r0 = it.row0; r0 < it.row1; r0 += TN_TM) {
         lds_barrier();
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            const int c = e * 4 + w, rr = lane;   // TN_TM == 64: wave-uniform column
-            Ls[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pl[e]);
-            Rs[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pr[e]);
+            const int c = e * 4 + w, rr = lane;
+            LR[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pl[e]);
+            if (!diag) LR[TSZ + c * (TN_TM + TN_PAD) + rr] = MF::from_double(pr[e]);
         }
         lds_barrier();
         if (r0 + TN_TM < it.row1) fetch(r0 + TN_TM);
-        // wave w: output tile row block w, column blocks 0..3
-#pragma unroll 4
-        for (int k0 = 0; k0 < TN_TM; k0 += MF::KSTEP) {
-            E av = Ls[(w * 16 + (lane & 15)) * (TN_TM + TN_PAD) + k0 + (lane >> 4)];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                E bv = Rs[(j * 16 + (lane & 15)) * (TN_TM + TN_PAD) + k0 + (lane >> 4)];
-                acc[j] = MF::mma(av, bv, acc[j]);
-            }
+        // wave w: output tile row block w, column sub-blocks j0 .. jn - 1
+        // (a compile-time count per case; the tile loop is fully unrolled)
+        switch (wact ? cnt : 0) {
+        case 4: tn_tile<MF, 4>(LR, aoff, boff, lane, j0, acc); break;
+        case 3: tn_tile<MF, 3>(LR, aoff, boff, lane, j0, acc); break;
+        case 2: tn_tile<MF, 2>(LR, aoff, boff, lane, j0, acc); break;
+        case 1: tn_tile<MF, 1>(LR, aoff, boff, lane, j0, acc); break;
+        default: break;
         }
     }
+    // Sub-blocks not formed are not written: k_tn_reduce reads none of them
+    // (rows or columns past the panel, or mirrored from the upper triangle).
     double* out = a.part + ((size_t)blockIdx.x * a.nob + ob) * (TN_OB * TN_OB);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
+        if (wact && j < cnt) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            int row = w * 16 + MF::row_of(lane, v);
-            int col = j * 16 + (lane & 15);
-            out[row + col * TN_OB] = (double)acc[j][v];
+            for (int v = 0; v < 4; ++v) {
+                const int row = w * 16 + MF::row_of(lane, v);
+                const int col = (j0 + j) * 16 + (lane & 15);
+                out[row + col * TN_OB] = (double)acc[j][v];
+            }
         }
 }
 
@@ -174,11 +206,13 @@ __global__ __launch_bounds__(256) void k_tn_reduce(TnReduceArgs a) {
     block_coords(ob, a.mbl, a.sym, &obi, &obj);
     const int gi = obi * TN_OB + i, gj = obj * TN_OB + j;
     if (gi >= a.nl || gj >= a.nr) return;
+    // diagonal block of a Gram: sub-blocks below the diagonal were not formed
+    const int es = (a.sym && obi == obj && (i >> 4) > (j >> 4)) ? j + i * TN_OB : e;
     double s = 0.0;
     const int it0 = a.seg_item0 ? a.seg_item0[seg] : 0;
     const int it1 = a.seg_item0 ? a.seg_item0[seg + 1] : a.nitems;
     for (int it = it0; it < it1; ++it)
-        s += a.part[((size_t)it * a.nob + ob) * (TN_OB * TN_OB) + e];
+        s += a.part[((size_t)it * a.nob + ob) * (TN_OB * TN_OB) + es];
     double* o = a.out + (size_t)seg * a.nl * a.nr;
     if (a.row_scale && gi < a.nscale) s *= a.row_scale[gi];
     o[gi + (size_t)gj * a.nl] = s;

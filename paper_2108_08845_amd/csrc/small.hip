@@ -383,12 +383,84 @@ __device__ __forceinline__ void wg_mul_tall(int n, int l, const double* P, int l
     __syncthreads();   // X complete before the caller reads it
 }
 
+// One Jacobi pair (columns zp, zq of m rows, squared norms al, be) by one
+// quarter-wave: the inner product, the tests and, unless the pair is already
+// orthogonal to tol or a column is negligible, the rotation with |angle| <=
+// pi/4 that makes the columns orthogonal:
+//   u = |be - al| + sqrt((be - al)^2 + 4 g^2),  h = 1 / sqrt(u^2 + 4 g^2),
+//   c = u h,  s = sign(be - al) 2 g h   (tan = s / c),
+// and the squared norms of the rotated columns (lane 0 of the group).
+// jac_pair_regs holds columns of at most 16 E rows in registers (E entries
+// per lane, clamped reads masked to zero); jac_pair_loop takes any m.
+__device__ __forceinline__ void jac_rotate_norms(double c, double s, double g, double al, double be, double* np,
+                                                 double* nq, int* sflag) {
+    const double cs2g = 2.0 * c * s * g;
+    *np = c * c * al + s * s * be - cs2g;
+    *nq = s * s * al + c * c * be + cs2g;
+    *sflag = 1;
+}
+
+__device__ __forceinline__ bool jac_angle(double g, double al, double be, double negl, double tol, double* c,
+                                          double* s) {
+    if (!(al > negl) || !(be > negl)) return false;
+    if (g * g <= (tol * tol) * (al * be)) return false;   // |g| <= tol sqrt(al be)
+    const double dif = be - al;
+    const double uu = fabs(dif) + sqrt(dif * dif + 4.0 * g * g);
+    const double hh = rsqrt(uu * uu + 4.0 * g * g);
+    *c = uu * hh;
+    *s = (dif >= 0.0 ? 2.0 * g : -2.0 * g) * hh;
+    return true;
+}
+
+template <int E>
+__device__ __forceinline__ void jac_pair_regs(double* zp, double* zq, int m, int ql, double al, double be, double negl,
+                                              double tol, double* np, double* nq, int* sflag) {
+    double xp[E], xq[E];
+    double g = 0.0;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        const int i = ql + 16 * u;
+        const int ic = i < m ? i : m - 1;
+        xp[u] = zp[ic];
+        xq[u] = zq[ic];
+        if (i >= m) xp[u] = xq[u] = 0.0;
+        g += xp[u] * xq[u];
+    }
+    g = q16_sum(g);
+    double c, s;
+    if (!jac_angle(g, al, be, negl, tol, &c, &s)) return;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        const int i = ql + 16 * u;
+        if (i < m) {
+            zp[i] = c * xp[u] - s * xq[u];
+            zq[i] = s * xp[u] + c * xq[u];
+        }
+    }
+    if (ql == 0) jac_rotate_norms(c, s, g, al, be, np, nq, sflag);
+}
+
+__device__ __forceinline__ void jac_pair_loop(double* zp, double* zq, int m, int ql, double al, double be, double negl,
+                                              double tol, double* np, double* nq, int* sflag) {
+    double g = 0.0;
+    for (int i = ql; i < m; i += 16) g += zp[i] * zq[i];
+    g = q16_sum(g);
+    double c, s;
+    if (!jac_angle(g, al, be, negl, tol, &c, &s)) return;
+    for (int i = ql; i < m; i += 16) {
+        const double a = zp[i], b = zq[i];
+        zp[i] = c * a - s * b;
+        zq[i] = s * a + c * b;
+    }
+    if (ql == 0) jac_rotate_norms(c, s, g, al, be, np, nq, sflag);
+}
+
 // ---------------------------------------------------------------------------
 // One-sided Jacobi on the columns of Z (m x n, ldz), in place.  On return
 // the columns are mutually orthogonal to the tolerance m * 2^-53; sig[j] =
 // ||z_j|| and z_j /= sig[j] (0 columns stay 0).  order[0..n) lists the
 // columns by descending sig (stable).  Parallel round-robin ordering: each
-// round rotates n/2 disjoint pairs, one pair per wave at a time.
+// round rotates n/2 disjoint pairs, one pair per quarter-wave (16 lanes) at a time.
 // Returns the number of sweeps (> max_sweeps: not converged).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* order, double* nrm,
@@ -435,56 +507,10 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
                 if (q >= n) continue;
                 double* zp = Z + (size_t)p * ldz;
                 double* zq = Z + (size_t)q * ldz;
-                // columns of at most 64 rows stay in registers (4 entries per lane)
-                double xp[4], xq[4];
-                double g = 0.0;
-                if (m <= 64) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int i = ql + 16 * u;
-                        const int ic = i < m ? i : m - 1;
-                        xp[u] = zp[ic];
-                        xq[u] = zq[ic];
-                        if (i >= m) xp[u] = xq[u] = 0.0;
-                        g += xp[u] * xq[u];
-                    }
-                } else {
-                    for (int i = ql; i < m; i += 16) g += zp[i] * zq[i];
-                }
-                g = q16_sum(g);
                 const double al = nrm[p], be = nrm[q];
-                if (!(al > negl) || !(be > negl)) continue;
-                if (g * g <= (tol * tol) * (al * be)) continue;   // |g| <= tol sqrt(al be)
-                // rotation with |angle| <= pi/4 that makes columns p, q orthogonal:
-                //   u = |be - al| + sqrt((be - al)^2 + 4 g^2),  h = 1 / sqrt(u^2 + 4 g^2),
-                //   c = u h,  s = sign(be - al) 2 g h   (tan = s / c)
-                const double dif = be - al;
-                const double ad = fabs(dif);
-                const double uu = ad + sqrt(dif * dif + 4.0 * g * g);
-                const double hh = rsqrt(uu * uu + 4.0 * g * g);
-                const double c = uu * hh, s = (dif >= 0.0 ? 2.0 * g : -2.0 * g) * hh;
-                if (m <= 64) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int i = ql + 16 * u;
-                        if (i < m) {
-                            zp[i] = c * xp[u] - s * xq[u];
-                            zq[i] = s * xp[u] + c * xq[u];
-                        }
-                    }
-                } else {
-                    for (int i = ql; i < m; i += 16) {
-                        const double a = zp[i], b = zq[i];
-                        zp[i] = c * a - s * b;
-                        zq[i] = s * a + c * b;
-                    }
-                }
-                if (ql == 0) {   // squared norms of the rotated columns
-                    const double cs2g = 2.0 * c * s * g;
-                    nrm[p] = c * c * al + s * s * be - cs2g;
-                    nrm[q] = s * s * al + c * c * be + cs2g;
-                    *sflag = 1;
-                }
+                if (m <= 64) jac_pair_regs<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                else if (m <= 128) jac_pair_regs<8>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                else jac_pair_loop(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
             }
             __syncthreads();
         }
@@ -566,7 +592,7 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
             ++sweep;
             break;
         }
-        double cmax = 0.0;   // largest g^2 / (al be) this quarter-wave met
+        bool far = false;   // a pair of this quarter-wave had g^2 > stop al be
         for (int t = 0; t < ne - 1; ++t) {
             if (has_pair) {
                 int xa = pa - 1 + t, xb = pb - 1 + t;   // (pos - 1 + t) mod (ne - 1), both < 2 (ne - 1)
@@ -591,7 +617,7 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
                     const double g = q16_sum(g0 + g1);
                     if (al > negl && be > negl) {
                         const double gg = g * g, ab = al * be;
-                        cmax = fmax(cmax, gg / ab);
+                        far = far || gg > stop * ab;
                         if (gg > (tol * tol) * ab) {
                             const double dif = be - al;
                             const double uu = fabs(dif) + __builtin_amdgcn_sqrt(fma(dif, dif, 4.0 * gg));
@@ -614,7 +640,7 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
             }
             __syncthreads();
         }
-        if (ql == 0 && qw < 64) mx[qw] = cmax;
+        if (ql == 0 && qw < 64) mx[qw] = far ? 1.0 : 0.0;
         __syncthreads();
         if (tid < 64) {
             double v = tid < nq ? mx[tid] : 0.0;
@@ -624,7 +650,7 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
         }
         ++sweep;
         __syncthreads();
-        const bool done = !*sflag || mx[64] <= stop;
+        const bool done = !*sflag || mx[64] == 0.0;
         __syncthreads();
         if (done) break;
     }
