@@ -34,6 +34,7 @@ struct TnArgs {
     const int32_t* skip;     // if non-null and *skip & skip_mask: do nothing
     int32_t skip_mask;
     int32_t nob;
+    int32_t nitems;          // work items (set by launch_tn)
 };
 
 struct TnReduceArgs {

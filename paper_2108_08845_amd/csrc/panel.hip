@@ -55,10 +55,10 @@ __device__ __forceinline__ PanelSeg load_seg(const PanelSeg* p) {
     return r;
 }
 
-__device__ __forceinline__ WorkItem get_item(const WorkItem* items, int64_t chunk, int64_t rows) {
+__device__ __forceinline__ WorkItem get_item(const WorkItem* items, int64_t chunk, int64_t rows, int64_t idx) {
     if (items) {
         static_assert(sizeof(WorkItem) == 24, "WorkItem layout");
-        const PSVD_GLOBAL int64_t* src = (const PSVD_GLOBAL int64_t*)(items + blockIdx.x);
+        const PSVD_GLOBAL int64_t* src = (const PSVD_GLOBAL int64_t*)(items + idx);
         WorkItem w;
         const int64_t s0 = src[0];
         w.seg = (int32_t)(s0 & 0xFFFFFFFF);
@@ -70,13 +70,31 @@ __device__ __forceinline__ WorkItem get_item(const WorkItem* items, int64_t chun
     WorkItem w;
     w.seg = 0;
     w.pad = 0;
-    w.row0 = (int64_t)blockIdx.x * chunk;
+    w.row0 = idx * chunk;
     w.row1 = w.row0 + chunk < rows ? w.row0 + chunk : rows;
     return w;
 }
 
 __device__ __forceinline__ double ld_col(const ColRef& r, int64_t i) {
     return r.dtype == PSVD_F64 ? gldd((const double*)r.base + i) : (double)gld((const float*)r.base + i);
+}
+
+// Element i of a column as raw bits (FP64, or FP32 in the low word), and its
+// value.  The prefetching kernels load raw bits and convert when the tile is
+// written to LDS.  The loads are the same two 32-bit loads for either dtype
+// (the second re-reads the first word of an FP32 element), so no load sits in
+// a dtype branch: a branch around loads makes the compiler wait for every
+// earlier load before the next one issues.
+__device__ __forceinline__ uint64_t ld_col_raw(const ColRef& r, int64_t i) {
+    const bool f64 = r.dtype == PSVD_F64;
+    const uint32_t* p = (const uint32_t*)(r.base + i * (f64 ? 8 : 4));
+    const uint32_t lo = *(const PSVD_GLOBAL uint32_t*)p;
+    const uint32_t hi = *(const PSVD_GLOBAL uint32_t*)(p + (f64 ? 1 : 0));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double raw_value(uint64_t raw, bool f64) {
+    return f64 ? __longlong_as_double((long long)raw) : (double)__uint_as_float((uint32_t)raw);
 }
 
 // ----------------------------------------------------------------------------
@@ -117,11 +135,17 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     __shared__ E LR[2 * TN_OB * (TN_TM + TN_PAD)];   // L tile, then R tile (a diagonal block uses the L tile twice)
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const WorkItem it = get_item(a.items, a.chunk, a.lseg.rows);
+    // XCD-aware order: consecutive work-group ids go to the 8 XCDs in turn; the
+    // nob output blocks of one row chunk take consecutive slots of one XCD, so
+    // they run together and share the chunk's rows through that XCD's L2.
+    const int64_t bid = blockIdx.x, slot = bid >> 3;
+    const int64_t item = (slot / a.nob) * 8 + (bid & 7);
+    const int ob = (int)(slot % a.nob);
+    if (item >= a.nitems) return;
+    const WorkItem it = get_item(a.items, a.chunk, a.lseg.rows, item);
     // segment descriptors copied once (global loads), not re-read per element
     const PanelSeg L = a.lsegs ? load_seg(a.lsegs + it.seg) : a.lseg;
     const PanelSeg R = a.rsegs ? load_seg(a.rsegs + it.seg) : a.rseg;
-    const int ob = blockIdx.y;
     int obi, obj;
     block_coords(ob, a.mbl, a.sym, &obi, &obj);
     const int lc0 = obi * TN_OB, rc0 = obj * TN_OB;
@@ -140,16 +164,23 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     // 16 per thread; consecutive threads read consecutive rows of a column.
     constexpr int TSZ = TN_OB * (TN_TM + TN_PAD);
     constexpr int PER = TN_OB * TN_TM / 256;
-    double pl[PER], pr[PER];
+    uint64_t pl[PER], pr[PER];   // raw bits (see ld_col_raw)
+    bool fl[PER], fr[PER];       // column is FP64 (wave-uniform)
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int c = e * 4 + w;
+        fl[e] = lc0 + c < L.ncols && col_ref(L, lc0 + c).dtype == PSVD_F64;
+        fr[e] = rc0 + c < R.ncols && col_ref(R, rc0 + c).dtype == PSVD_F64;
+    }
     auto fetch = [&](int64_t r0) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int c = e * 4 + w, rr = lane;   // TN_TM == 64: wave-uniform column
             int64_t row = r0 + rr;
-            double vl = 0.0, vr = 0.0;
+            uint64_t vl = 0, vr = 0;
             if (row < it.row1) {
-                if (lc0 + c < L.ncols) vl = ld_col(col_ref(L, lc0 + c), row);
-                if (!diag && rc0 + c < R.ncols) vr = ld_col(col_ref(R, rc0 + c), row);
+                if (lc0 + c < L.ncols) vl = ld_col_raw(col_ref(L, lc0 + c), row);
+                if (!diag && rc0 + c < R.ncols) vr = ld_col_raw(col_ref(R, rc0 + c), row);
             }
             pl[e] = vl;
             pr[e] = vr;
@@ -162,8 +193,8 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int c = e * 4 + w, rr = lane;
-            LR[c * (TN_TM + TN_PAD) + rr] = MF::from_double(pl[e]);
-            if (!diag) LR[TSZ + c * (TN_TM + TN_PAD) + rr] = MF::from_double(pr[e]);
+            LR[c * (TN_TM + TN_PAD) + rr] = MF::from_double(raw_value(pl[e], fl[e]));
+            if (!diag) LR[TSZ + c * (TN_TM + TN_PAD) + rr] = MF::from_double(raw_value(pr[e], fr[e]));
         }
         lds_barrier();
         if (r0 + TN_TM < it.row1) fetch(r0 + TN_TM);
@@ -179,7 +210,7 @@ __global__ __launch_bounds__(256) void k_tn(TnArgs a) {
     }
     // Sub-blocks not formed are not written: k_tn_reduce reads none of them
     // (rows or columns past the panel, or mirrored from the upper triangle).
-    double* out = a.part + ((size_t)blockIdx.x * a.nob + ob) * (TN_OB * TN_OB);
+    double* out = a.part + ((size_t)item * a.nob + ob) * (TN_OB * TN_OB);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
         if (wact && j < cnt) {
@@ -239,34 +270,57 @@ __global__ __launch_bounds__(256) void k_nn(NnArgs a) {
     __shared__ double Os[NN_OB * (NN_TM + 1)];
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const WorkItem it = get_item(a.items, a.chunk, a.seg.rows);
+    const WorkItem it = get_item(a.items, a.chunk, a.seg.rows, blockIdx.x);
     const PanelSeg S = a.segs ? load_seg(a.segs + it.seg) : a.seg;
     const int oc0 = blockIdx.y * NN_OB;
+    // Register staging of one (row tile, column chunk) step: the next step's
+    // C chunk and X chunk are loaded while the matrix cores work on this one.
+    constexpr int PC = NN_KC * NN_TM / 256, PX = NN_KC * NN_OB / 256;
+    uint64_t pc[PC];   // raw bits of the C chunk (see ld_col_raw)
+    bool pf[PC];       // column is FP64 (wave-uniform)
+    double px[PX];
+    auto fetch = [&](int64_t r0, int k0) {
+#pragma unroll
+        for (int e = 0; e < PC; ++e) {
+            const int c = e * 4 + w;   // NN_TM == 64: wave-uniform column
+            const int64_t row = r0 + lane;
+            const bool have = k0 + c < a.n;
+            const ColRef cr = col_ref(S, have ? k0 + c : 0);
+            pf[e] = have && cr.dtype == PSVD_F64;
+            uint64_t v = 0;
+            if (row < it.row1 && have) v = ld_col_raw(cr, row);
+            pc[e] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < PX; ++e) {
+            const int idx = e * 256 + tid;
+            const int k = idx % NN_KC, j = idx / NN_KC;
+            double v = 0.0;
+            if (k0 + k < a.n && oc0 + j < a.nx) v = gldd(a.X + (k0 + k) + (int64_t)(oc0 + j) * a.ldx);
+            px[e] = v;
+        }
+    };
+    if (it.row0 < it.row1) fetch(it.row0, 0);
     for (int64_t r0 = it.row0; r0 < it.row1; r0 += NN_TM) {
         typename MF::acc acc[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] = typename MF::acc{0, 0, 0, 0};
         for (int k0 = 0; k0 < a.n; k0 += NN_KC) {
             lds_barrier();
-            // C chunk: 32 columns x 64 rows (8 per thread)
+            // C chunk: 32 columns x 64 rows; X chunk: 32 rows x 64 columns
 #pragma unroll
-            for (int e = 0; e < NN_KC * NN_TM / 256; ++e) {
-                const int c = e * 4 + w, rr = lane;   // NN_TM == 64: wave-uniform column
-                int64_t row = r0 + rr;
-                double v = 0.0;
-                if (row < it.row1 && k0 + c < a.n) v = ld_col(col_ref(S, k0 + c), row);
-                Cs[c * (NN_TM + 1) + rr] = MF::from_double(v);
-            }
-            // X chunk: 32 rows x 64 columns
+            for (int e = 0; e < PC; ++e) Cs[(e * 4 + w) * (NN_TM + 1) + lane] = MF::from_double(raw_value(pc[e], pf[e]));
 #pragma unroll
-            for (int e = 0; e < NN_KC * NN_OB / 256; ++e) {
-                int idx = e * 256 + tid;
-                int k = idx % NN_KC, j = idx / NN_KC;
-                double v = 0.0;
-                if (k0 + k < a.n && oc0 + j < a.nx) v = gldd(a.X + (k0 + k) + (int64_t)(oc0 + j) * a.ldx);
-                Xs[j * (NN_KC + 1) + k] = MF::from_double(v);
+            for (int e = 0; e < PX; ++e) {
+                const int idx = e * 256 + tid;
+                Xs[(idx / NN_KC) * (NN_KC + 1) + idx % NN_KC] = MF::from_double(px[e]);
             }
             lds_barrier();
+            {   // next step: the next chunk of this tile, else the first chunk of the next tile
+                const bool last = k0 + NN_KC >= a.n;
+                const int64_t nr0 = last ? r0 + NN_TM : r0;
+                if (nr0 < it.row1) fetch(nr0, last ? 0 : k0 + NN_KC);
+            }
             // wave w: output row block w (16 rows), column blocks 0..3
 #pragma unroll
             for (int kk = 0; kk < NN_KC; kk += MF::KSTEP) {
@@ -1620,8 +1674,14 @@ __global__ __launch_bounds__(256) void k_fused_reduce(FusedReduceArgs a) {
 // ----------------------------------------------------------------------------
 // Host launchers.
 // ----------------------------------------------------------------------------
-hipError_t launch_tn(bool fp64, const TnArgs& a, int nitems, hipStream_t st) {
-    dim3 grid(nitems, a.nob);
+hipError_t launch_tn(bool fp64, const TnArgs& args, int nitems, hipStream_t st) {
+    TnArgs a = args;
+    a.nitems = nitems;
+    // one work-group per (item, output block), items rounded up to a multiple of 8
+    const int64_t nwg = (int64_t)((nitems + 7) / 8) * 8 * a.nob;
+    if (nitems <= 0 || a.nob <= 0) return hipSuccess;
+    if (nwg > INT32_MAX) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nwg);
     if (fp64) hipLaunchKernelGGL(k_tn<double>, grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL(k_tn<float>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
