@@ -170,7 +170,11 @@ def bench_partitioned(args):
     dom = max(kern, key=lambda k: kern[k]["ms"])
     avg_ms = kern[dom]["ms"] / max(1, kern[dom]["launches"])
     n = w.K + w.N
-    if dom == "tn":      # FP64 Gram of the panel (or of Q1): M n (n + 1) flops per pass, FP64 matrix cores
+    if dom == "small_svd":   # Cholesky + Jacobi SVD of the n x n R in one work-group (per launch, two per update)
+        flops = 2.0 * n ** 3 + 4.0 * max(1, st["last_sweeps"]) * n ** 3
+        roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s"}
+    elif dom == "tn":    # FP64 Gram of the panel (or of Q1): M n (n + 1) flops per pass, FP64 matrix cores
         roof = {"bound": "mfma", "achieved": w.M * n * (n + 1) / (avg_ms * 1e-3) / 1e12,
                 "peak": MFMA_PEAK_TFLOPS["f64"], "unit": "TFLOP/s"}
     elif dom == "nn":    # Q1 = C R1^-1 over all partitions: reads the panel, writes Q1 (FP32)
