@@ -242,8 +242,18 @@ __global__ __launch_bounds__(256) void k_tn_reduce(TnReduceArgs a) {
     double s = 0.0;
     const int it0 = a.seg_item0 ? a.seg_item0[seg] : 0;
     const int it1 = a.seg_item0 ? a.seg_item0[seg + 1] : a.nitems;
-    for (int it = it0; it < it1; ++it)
-        s += a.part[((size_t)it * a.nob + ob) * (TN_OB * TN_OB) + es];
+    // item order; eight loads are issued before their (ordered) additions
+    const size_t stride = (size_t)a.nob * (TN_OB * TN_OB);
+    const double* p = a.part + ((size_t)it0 * a.nob + ob) * (TN_OB * TN_OB) + es;
+    int it = it0;
+    for (; it + 8 <= it1; it += 8, p += 8 * stride) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = gldd(p + u * stride);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; it < it1; ++it, p += stride) s += gldd(p);
     double* o = a.out + (size_t)seg * a.nl * a.nr;
     if (a.row_scale && gi < a.nscale) s *= a.row_scale[gi];
     o[gi + (size_t)gj * a.nl] = s;
