@@ -104,6 +104,18 @@ def test_det_fp64_ragged(M, N, nb, K, ff):
     compare(U, s, so, 1e-10, 1e-12, f"det M={M} N={N}")
 
 
+@pytest.mark.parametrize("M,N,K", [(2000, 8, 8), (2000, 9, 8), (3000, 33, 32), (3000, 48, 32), (4000, 65, 64)])
+def test_det_fp64_gram_block_edges(M, N, K):
+    """Panels of n = K + N = 16, 17, 65, 80 and 129 columns: the Gram kernel's 16-column
+    sub-blocks past the last column, the mirrored lower sub-blocks of diagonal 64 x 64
+    blocks and a last block of one column, against the oracle."""
+    w = synth.scaled(synth.c1_plain_fp64(), M=M, N=N, batches=3, K=K, ff=0.95)
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "fp64", False)
+    so = run_oracle(w, batches, False, oracle.PREC_F64)
+    compare(U, s, so, 1e-10, 1e-12, f"det n={K + N}")
+
+
 def test_det_fp32_c5_shape():
     w = synth.scaled(synth.c5_gradient(), M=1 << 15)
     batches = synth.planted_stream(w)
