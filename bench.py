@@ -318,7 +318,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this library runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "partitioned":
         bench_partitioned(args)
