@@ -1658,12 +1658,30 @@ __global__ __launch_bounds__(256) void k_fused_reduce(FusedReduceArgs a) {
         const int lb = j / FU_LB, jj = j % FU_LB;
         const size_t stride = (size_t)a.nlb * a.np * FU_LB;
         const float* p = a.partP + (size_t)lb * a.np * FU_LB + i + (size_t)jj * a.np;
-        for (int g = grp; g < a.nwg; g += 8) s += (double)p[(size_t)g * stride];
+        // partials g, g + 8, ... in order; eight loads are issued before their additions
+        int g = grp;
+        for (; g + 56 < a.nwg; g += 64) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(g + 8 * u) * stride];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += (double)v[u];
+        }
+        for (; g < a.nwg; g += 8) s += (double)p[(size_t)g * stride];
     } else if (e < tot) {
         const int64_t f = e - totP;
         const int i = (int)(f % a.lx), j = (int)(f / a.lx);
         const double* p = a.partG + i + (size_t)j * FU_LB;
-        for (int g = grp; g < a.nwg; g += 8) s += p[(size_t)g * FU_LB * FU_LB];
+        const size_t stride = (size_t)FU_LB * FU_LB;
+        int g = grp;
+        for (; g + 56 < a.nwg; g += 64) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(g + 8 * u) * stride];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; g < a.nwg; g += 8) s += p[(size_t)g * stride];
     }
     red[grp][lane_o] = s;
     __syncthreads();
