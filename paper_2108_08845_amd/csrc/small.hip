@@ -843,11 +843,23 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
         if (in_lds) a.G2[e] = v;
     }
     __syncthreads();
-    // R = R2 R1 (upper) -> a.G (kept) and the working matrix
+    // R = R2 R1 (upper) -> a.G (kept) and the working matrix; k ascending,
+    // eight pairs of loads issued before their multiply-adds
     for (int e = tid; e < n * n; e += SM_THREADS) {
         const int i = e % n, j = e / n;
         double s = 0.0;
-        for (int k = i; k <= j; ++k) s += R2[i + (size_t)k * n] * a.R1[k + (size_t)j * n];
+        int k = i;
+        for (; k + 8 <= j + 1; k += 8) {
+            double r2[8], r1[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                r2[u] = R2[i + (size_t)(k + u) * n];
+                r1[u] = a.R1[k + u + (size_t)j * n];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += r2[u] * r1[u];
+        }
+        for (; k <= j; ++k) s += R2[i + (size_t)k * n] * a.R1[k + (size_t)j * n];
         a.G[e] = (i <= j) ? s : 0.0;
     }
     __syncthreads();
