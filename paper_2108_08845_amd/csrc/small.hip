@@ -405,7 +405,10 @@ __device__ __forceinline__ bool jac_angle(double g, double al, double be, double
     if (!(al > negl) || !(be > negl)) return false;
     if (g * g <= (tol * tol) * (al * be)) return false;   // |g| <= tol sqrt(al be)
     const double dif = be - al;
-    const double uu = fabs(dif) + sqrt(dif * dif + 4.0 * g * g);
+    // the hardware square root sets the angle only; c and s share one
+    // correctly rounded reciprocal square root, so the rotation stays
+    // orthogonal to rounding
+    const double uu = fabs(dif) + __builtin_amdgcn_sqrt(dif * dif + 4.0 * g * g);
     const double hh = rsqrt(uu * uu + 4.0 * g * g);
     *c = uu * hh;
     *s = (dif >= 0.0 ? 2.0 * g : -2.0 * g) * hh;
