@@ -549,14 +549,12 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
 // One-sided Jacobi for at most 64 rows and 64 columns, Z in LDS with leading
 // dimension 64 and rows m..63 zero: every load and store of a pair is
 // unconditional and the column norms are read before the dot product.  The
-// same round-robin pairs, tests and rotation as wg_jacobi, with two changes:
-//  - the angle term sqrt((be - al)^2 + 4 g^2) takes the hardware square root
-//    (it only sets the angle; the rotation stays orthogonal to rounding since
-//    c and s share one correctly rounded reciprocal square root), and
-//  - a sweep whose largest squared cosine g^2 / (al be) is at most
-//    max(stop_cos2, tol) ends the iteration: convergence is quadratic, so the
-//    next sweep would take the cosines to about the square of that bound
-//    (tol: the sweep after it would only confirm cosines near tol).
+// same round-robin pairs, tests and rotation as wg_jacobi (both take the
+// hardware square root for the angle term), with one change: a sweep whose
+// largest squared cosine g^2 / (al be) is at most max(stop_cos2, tol) ends
+// the iteration: convergence is quadratic, so the next sweep would take the
+// cosines to about the square of that bound (tol: the sweep after it would
+// only confirm cosines near tol).
 // mx: 65 doubles of scratch.  Returns the sweep count (> max_sweeps: not
 // converged); results as wg_jacobi.
 __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* sig, int* order, double* nrm,
