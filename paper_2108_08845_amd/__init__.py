@@ -365,13 +365,13 @@ class StreamingSVDFunction(torch.autograd.Function):
         s = torch.from_numpy(svd.singular_values).to(A.device)
         svd.close()
         ctx.save_for_backward(A)
-        ctx.batches, ctx.K, ctx.ff = batches, K, ff
+        ctx.batches, ctx.K, ctx.ff, ctx.r = batches, K, ff, U.shape[1]
         return U, s
 
     @staticmethod
     def backward(ctx, U_bar, s_bar):
         (A,) = ctx.saved_tensors
-        r = U_bar.shape[1]
+        r = ctx.r   # rank of the forward result (either cotangent may be absent)
         if s_bar is None:
             s_bar = torch.zeros(r, dtype=torch.float64)
         if U_bar is None:

@@ -536,3 +536,56 @@ def test_matmul_nn_matches_blas():
     B = rng.standard_normal((19, 23))
     assert np.allclose(oracle.matmul_nn(A, B), A @ B, rtol=0, atol=1e-13)
     assert np.allclose(oracle.matmul_tn(A, rng.standard_normal((37, 5))).shape, (19, 5))
+
+
+@pytest.mark.parametrize("k", [0, 300, 8193, 70000, 4_200_003])
+def test_matmul_tn_chunked_reduction_exact(k):
+    # Integer-valued operands keep every partial sum exact in FP64, so the
+    # oracle's chunked reduction over the long dimension (chunks of 8192 rows,
+    # widened beyond 512 chunks) must equal the integer product bit for bit:
+    # a dropped, repeated or shifted chunk changes the result.
+    rng = np.random.default_rng(11 + k % 97)
+    m, n = (3, 2) if k > 100_000 else (19, 5)
+    A = rng.integers(-8, 9, size=(k, m))
+    B = rng.integers(-8, 9, size=(k, n))
+    C = oracle.matmul_tn(A.astype(np.float64), B.astype(np.float64))
+    ref = (A.T @ B).astype(np.float64)
+    assert C.shape == (m, n)
+    assert np.array_equal(C, ref)
+
+
+def test_matmul_tn_against_blas_real_values():
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((70001, 7))
+    B = rng.standard_normal((70001, 4))
+    C = oracle.matmul_tn(A, B)
+    bound = 70001 * 2.0 ** -52 * (np.abs(A).T @ np.abs(B))
+    assert np.all(np.abs(C - A.T @ B) <= bound)
+
+
+@pytest.mark.parametrize("m", [255, 256, 257, 600])
+def test_matmul_nn_row_blocks_exact(m):
+    # rows are split into blocks of 256: ragged and exact multiples, integer data (exact sums)
+    rng = np.random.default_rng(13 + m)
+    A = rng.integers(-8, 9, size=(m, 33))
+    B = rng.integers(-8, 9, size=(33, 6))
+    assert np.array_equal(oracle.matmul_nn(A.astype(np.float64), B.astype(np.float64)), (A @ B).astype(np.float64))
+
+
+@pytest.mark.parametrize("m", [65536, 65537, 2 * 65536 + 5])
+def test_hhqr_long_columns_chunked_norm(m):
+    # The Householder vector norm is a sum of squares in chunks of 65536 entries.
+    # Integer columns: the first column's squared norm is an exact integer, so
+    # R_00 must be its correctly rounded square root; the rest is checked
+    # against LAPACK after the sign normalisation (R_jj >= 0).
+    rng = np.random.default_rng(14)
+    A = rng.integers(-5, 6, size=(m, 3)).astype(np.float64)
+    A[m - 1, 0] = 7.0   # an entry in the last (ragged) chunk
+    Q, R = oracle.hhqr(A)
+    exact = int(np.sum(A[:, 0].astype(np.int64) ** 2))
+    assert R[0, 0] == np.sqrt(float(exact))
+    Ql, Rl = np.linalg.qr(A)
+    sg = np.sign(np.diag(Rl))
+    Rl = sg[:, None] * Rl
+    assert np.max(np.abs(R - Rl)) <= 1e-12 * np.abs(Rl).max()
+    assert np.linalg.norm(Q.T @ Q - np.eye(3)) <= 1e-13
