@@ -15,7 +15,9 @@ Functions and the passages they follow:
   jacobi_svd            -- one-sided Jacobi SVD (the SVD of R in Algorithm 1; Eq. (9)).
   StreamOracle          -- Algorithm 1 per batch, deterministic or randomized
                             (Eqs. (7)-(11), Halko-Martinsson-Tropp power iterations).
-  apmos                 -- Algorithm 2 / Eqs. (3)-(6).
+  apmos                 -- Algorithm 2 / Eqs. (3)-(6); with `omega` the global
+                            SVD of W is the low-rank SVD (the paper's placement).
+  low_rank_svd          -- Eqs. (7)-(11) on a small matrix with a given test matrix.
   PartitionedStreamOracle -- the parallel streaming of Sec. 3 over row
                             partitions: APMOS initialisation, then per batch
                             local QR of each partition's panel, QR of the
@@ -66,6 +68,10 @@ def _load():
                                        ctypes.POINTER(_i32), _dp, _i64]
     lib.orc_stream_loss.argtypes = [_i64, _i32, ctypes.c_double, _i32, _i64, _dp, _i64, _dp, _dp, _dp, _dp]
     lib.orc_stream_grad.argtypes = [_i64, _i32, ctypes.c_double, _i32, _i64, _dp, _i64, _dp, _dp]
+    lib.orc_low_rank_svd.argtypes = [_i64, _i64, _dp, _i64, _i32, _dp, _i64, _dp, _i64, _dp, ctypes.POINTER(_i32)]
+    lib.orc_apmos_lr.argtypes = [_i32, ctypes.POINTER(_i64), _i64, _i32, _i32, _dp, _dp, _i64, _dp, _dp, _dp]
+    lib.orc_pstream_update_lr.argtypes = [_i32, ctypes.POINTER(_i64), _i32, ctypes.c_double, _dp, _dp,
+                                          ctypes.POINTER(_i32), _dp, _i64, _dp, _i64]
     lib.orc_matmul_nn.argtypes = [_i64, _i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64]
     lib.orc_matmul_nn.restype = None
     lib.orc_matmul_tn.argtypes = [_i64, _i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64]
@@ -212,8 +218,25 @@ class StreamOracle:
         return self.s[: self.r].copy()
 
 
-def apmos(parts, r, K):
-    """Algorithm 2 on a list of (M_i x N) partitions -> (list of U^i, Lambda~ (K), X~ (N x K))."""
+def low_rank_svd(A, K, Om):
+    """Low-rank SVD of a small matrix A (m x n) with test matrix Om (n x ell):
+    Eqs. (7)-(11) without power iterations -> (U (m x k), s (k)), k = min(K, ell)."""
+    A = _f64(A)
+    Om = _f64(Om)
+    m, n = A.shape
+    ell = Om.shape[1]
+    k = min(int(K), ell)
+    U = np.zeros((m, k), order="F")
+    s = np.zeros(max(k, 1))
+    kk = _i32(0)
+    rc = _load().orc_low_rank_svd(m, n, _ptr(A), m, int(K), _ptr(Om), ell, _ptr(U), m, _ptr(s), ctypes.byref(kk))
+    _check(rc, "low_rank_svd")
+    return U[:, : kk.value], s[: kk.value].copy()
+
+
+def apmos(parts, r, K, omega=None):
+    """Algorithm 2 on a list of (M_i x N) partitions -> (list of U^i, Lambda~ (K), X~ (N x K)).
+    With `omega` (P r x ell) the SVD of W is the low-rank SVD of Eqs. (7)-(11)."""
     parts = [_f64(p) for p in parts]
     P = len(parts)
     N = parts[0].shape[1]
@@ -222,8 +245,14 @@ def apmos(parts, r, K):
     U_all = np.zeros(int(Ms.sum()) * K)
     Lam = np.zeros(K)
     X = np.zeros((N, K), order="F")
-    rc = _load().orc_apmos(P, Ms.ctypes.data_as(ctypes.POINTER(_i64)), N, r, K, _ptr(A_all), _ptr(U_all),
-                           _ptr(Lam), _ptr(X))
+    if omega is None:
+        rc = _load().orc_apmos(P, Ms.ctypes.data_as(ctypes.POINTER(_i64)), N, r, K, _ptr(A_all), _ptr(U_all),
+                               _ptr(Lam), _ptr(X))
+    else:
+        Om = _f64(omega)
+        assert Om.shape[0] == P * r
+        rc = _load().orc_apmos_lr(P, Ms.ctypes.data_as(ctypes.POINTER(_i64)), N, r, K, _ptr(A_all), _ptr(Om),
+                                  Om.shape[1], _ptr(U_all), _ptr(Lam), _ptr(X))
     _check(rc, "apmos")
     out, off = [], 0
     for m in Ms:
@@ -242,13 +271,18 @@ class PartitionedStreamOracle:
     `modes` is the stacked U (sum M_i x r), `modes_part(i)` one partition's.
     """
 
-    def __init__(self, M_parts, K, ff=1.0, r_local=None):
+    def __init__(self, M_parts, K, ff=1.0, r_local=None, low_rank=False, seed=0, omega_precision=PREC_F64):
         self.Ms = np.array([int(m) for m in M_parts], dtype=np.int64)
         self.P, self.K, self.ff = len(self.Ms), int(K), float(ff)
         self.r_local = r_local
         self.U_all = np.zeros(int(self.Ms.sum()) * self.K)
         self.s = np.zeros(self.K)
         self.r = 0
+        # the paper's placement of randomization: the SVD of W (initialisation)
+        # and of the combined R factor (updates) by the low-rank SVD with a
+        # K-column test matrix, drawn for update b from (seed, b)
+        self.low_rank, self.seed, self.omega_precision = bool(low_rank), int(seed), int(omega_precision)
+        self.batch = 0
 
     def _stack(self, parts):
         parts = [_f64(p) for p in parts]
@@ -262,19 +296,29 @@ class PartitionedStreamOracle:
             return self
         if self.r == 0:
             rl = int(self.r_local) if self.r_local is not None else min(self.K, N)
-            Us, lam, _ = apmos(parts, rl, self.K)
+            om = omega(self.seed, self.batch, self.P * rl, self.K, self.omega_precision) if self.low_rank else None
+            Us, lam, _ = apmos(parts, rl, self.K, omega=om)
             off = 0
             for u, m in zip(Us, self.Ms):
                 self.U_all[off: off + m * self.K] = u.ravel(order="F")
                 off += m * self.K
             self.s[:] = lam
             self.r = self.K
+            self.batch += 1
             return self
         r = _i32(self.r)
-        rc = _load().orc_pstream_update(self.P, self.Ms.ctypes.data_as(ctypes.POINTER(_i64)), self.K, self.ff,
-                                        _ptr(self.U_all), _ptr(self.s), ctypes.byref(r), _ptr(A_all), N)
+        if self.low_rank:
+            n = self.r + N
+            om = omega(self.seed, self.batch, n, min(self.K, n), self.omega_precision)
+            rc = _load().orc_pstream_update_lr(self.P, self.Ms.ctypes.data_as(ctypes.POINTER(_i64)), self.K, self.ff,
+                                               _ptr(self.U_all), _ptr(self.s), ctypes.byref(r), _ptr(A_all), N,
+                                               _ptr(om), om.shape[1])
+        else:
+            rc = _load().orc_pstream_update(self.P, self.Ms.ctypes.data_as(ctypes.POINTER(_i64)), self.K, self.ff,
+                                            _ptr(self.U_all), _ptr(self.s), ctypes.byref(r), _ptr(A_all), N)
         _check(rc, "pstream_update")
         self.r = int(r.value)
+        self.batch += 1
         return self
 
     initialize = incorporate

@@ -28,6 +28,10 @@
  *       the randomized range finder of Eqs. (7)-(11) applied to the same
  *       panel (power iterations per Halko, Martinsson & Tropp 2011, Alg. 4.4).
  *   orc_apmos        -- Algorithm 2 / Eqs. (3)-(6) (Sec. 3.2) on P partitions.
+ *   orc_low_rank_svd -- the low-rank SVD of Eqs. (7)-(11) applied to a small
+ *       matrix, where the parallel variant of Sec. 3 randomizes: the SVD of
+ *       W in Algorithm 2 (orc_apmos_lr) and of the combined R factor of the
+ *       partitioned update (orc_pstream_update_lr).
  *   orc_stream_grad  -- reverse-mode derivative of the loss
  *       ||A - U U^T A||_F^2 + sum_j w_j s_j through the deterministic
  *       streaming recursion (adjoint of the thin SVD; the paper is silent).
@@ -587,6 +591,25 @@ int orc_stream_update(int64_t M, int32_t K, double ff, int32_t ell, int32_t q, d
     return rc;
 }
 
+/*
+ * Low-rank SVD of a small m x n matrix A (ld lda), Eqs. (7)-(11) without power
+ * iterations, with the Gaussian test matrix Om (n x ell, 1 <= ell <= min(m, n)):
+ * Y = A Om, Q = qr(Y), B = Q^T A, B = Ut S Vt^T (Jacobi on B^T), U = Q Ut[:, :k]
+ * and s = S[:k] with k = min(K, ell), the sign rule on Ut.  (The randomized step
+ * of the stream with q = 0.)  Exact when rank(A) <= ell.
+ */
+int orc_low_rank_svd(int64_t m, int64_t n, const double* A, int64_t lda, int32_t K, const double* Om, int64_t ell,
+                     double* U, int64_t ldu, double* s, int32_t* k_out)
+{
+    if (m < 1 || n < 1 || K < 1 || ell < 1 || ell > m || ell > n || lda < m) return ORC_EINVAL;
+    double* C = (double*)malloc((size_t)m * (size_t)n * sizeof(double));
+    if (!C) return ORC_ENOMEM;
+    for (int64_t j = 0; j < n; ++j) memcpy(C + IDX(0, j, m), A + IDX(0, j, lda), (size_t)m * sizeof(double));
+    int rc = step_rand(m, K, 0, C, n, Om, ell, U, ldu, s, k_out, NULL);
+    free(C);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* APMOS: Algorithm 2, Eqs. (3)-(6).                                        */
 /* ------------------------------------------------------------------------ */
@@ -599,12 +622,13 @@ int orc_stream_update(int64_t M, int32_t K, double ff, int32_t ell, int32_t q, d
  *   4. U^i = A^i X~ diag(1 / Lambda~)   (written stacked into U_all, ld M_i).
  * Returns ORC_EINVAL if Lambda~_K <= N * 2^-53 * Lambda~_1.
  */
-int orc_apmos(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_t K, const double* A_all,
-              double* U_all, double* Lambda, double* X_out)
+static int apmos_impl(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_t K, const double* A_all,
+                      const double* Om, int64_t ell, double* U_all, double* Lambda, double* X_out)
 {
     if (P < 1 || N < 1 || rloc < 1 || rloc > N || K < 1 || K > N) return ORC_EINVAL;
     int64_t wcols = (int64_t)P * rloc;
     if (K > wcols) return ORC_EINVAL;
+    if (Om && (ell < K || ell > N || ell > wcols)) return ORC_EINVAL;
     double* Wm = (double*)calloc((size_t)N * (size_t)wcols, sizeof(double));
     if (!Wm) return ORC_ENOMEM;
     int rc = ORC_OK;
@@ -622,6 +646,9 @@ int orc_apmos(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_
         if (!Q || !R || !S || !V) rc = ORC_ENOMEM;
         if (rc == ORC_OK) rc = orc_hhqr(Mi, N, A_all + off, Mi, Q, R);
         if (rc == ORC_OK) rc = orc_jacobi_svd(N, N, R, N, NULL, S, V, 60, NULL);
+        /* the sign rule on the kept right vectors: W's column signs do not change
+         * W W^T (the exact SVD of W), but they do change the low-rank SVD's sketch W Om */
+        if (rc == ORC_OK) sign_rule(N, rloc, V, N, NULL);
         if (rc == ORC_OK)
             for (int32_t j = 0; j < rloc; ++j)
                 for (int64_t k = 0; k < N; ++k) Wm[IDX(k, (int64_t)i * rloc + j, N)] = V[IDX(k, j, N)] * S[j];
@@ -638,7 +665,11 @@ int orc_apmos(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_
         int64_t nl = wcols < N ? wcols : N;
         Lf = (double*)malloc((size_t)N * sizeof(double));
         if (!Xf || !Lf) rc = ORC_ENOMEM;
-        if (rc == ORC_OK) {
+        if (rc == ORC_OK && Om) {
+            /* the low-rank SVD of W (sign rule on its small factor) */
+            int32_t kk = 0;
+            rc = orc_low_rank_svd(N, wcols, Wm, N, K, Om, ell, Xf, N, Lf, &kk);
+        } else if (rc == ORC_OK) {
             if (wcols >= N) {
                 /* W^T (wcols x N) = Uw S Vw^T  =>  W = Vw S Uw^T: X = Vw. */
                 double* Wt = (double*)malloc((size_t)wcols * (size_t)N * sizeof(double));
@@ -660,7 +691,7 @@ int orc_apmos(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_
         if (!(Lf[K - 1] > (double)N * ldexp(1.0, -53) * Lf[0])) rc = ORC_EINVAL;
     }
     if (rc == ORC_OK) {
-        sign_rule(N, K, Xf, N, NULL);
+        if (!Om) sign_rule(N, K, Xf, N, NULL);
         double* T = (double*)malloc((size_t)N * (size_t)K * sizeof(double));
         if (!T) rc = ORC_ENOMEM;
         else {
@@ -685,6 +716,24 @@ int orc_apmos(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_
     return rc;
 }
 
+int orc_apmos(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_t K, const double* A_all,
+              double* U_all, double* Lambda, double* X_out)
+{
+    return apmos_impl(P, M_parts, N, rloc, K, A_all, NULL, 0, U_all, Lambda, X_out);
+}
+
+/*
+ * Algorithm 2 with the global SVD of W (step 4) taken by the low-rank SVD of
+ * Eqs. (7)-(11) with the test matrix Om (P*rloc x ell, K <= ell <= N), as the
+ * paper's parallel listing does when randomization is on.
+ */
+int orc_apmos_lr(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_t K, const double* A_all,
+                 const double* Om, int64_t ell, double* U_all, double* Lambda, double* X_out)
+{
+    if (!Om) return ORC_EINVAL;
+    return apmos_impl(P, M_parts, N, rloc, K, A_all, Om, ell, U_all, Lambda, X_out);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Partitioned streaming: the parallel update of Section 3 (row partitions). */
 /* ------------------------------------------------------------------------ */
@@ -703,12 +752,13 @@ int orc_apmos(int32_t P, const int64_t* M_parts, int64_t N, int32_t rloc, int32_
  * In exact arithmetic this is the serial update of the stacked panel: R_f
  * is the R factor of the whole panel (both with a non-negative diagonal).
  */
-int orc_pstream_update(int32_t P, const int64_t* M_parts, int32_t K, double ff, double* U_all, double* s, int32_t* r,
-                       const double* A_all, int64_t N)
+static int pstream_impl(int32_t P, const int64_t* M_parts, int32_t K, double ff, double* U_all, double* s,
+                        int32_t* r, const double* A_all, int64_t N, const double* Om, int64_t ell)
 {
     if (P < 1 || K < 1 || N < 0 || !(ff > 0.0 && ff <= 1.0)) return ORC_EINVAL;
     const int64_t r0 = *r, n = r0 + N;
     if (N == 0) return ORC_OK;
+    if (Om && (ell < 1 || ell > n)) return ORC_EINVAL;
     for (int32_t i = 0; i < P; ++i)
         if (M_parts[i] < n) return ORC_EINVAL;
     const int64_t pn = (int64_t)P * n;
@@ -738,11 +788,18 @@ int orc_pstream_update(int32_t P, const int64_t* M_parts, int32_t K, double ff, 
     }
     /* 2. QR of the stacked R factors */
     if (rc == ORC_OK) rc = orc_hhqr(pn, n, Rs, pn, Qg, Rf);
-    /* 3. SVD of the combined R */
-    if (rc == ORC_OK) rc = orc_jacobi_svd(n, n, Rf, n, Ut, S, NULL, 60, NULL);
+    /* 3. SVD of the combined R: exact (Jacobi), or the low-rank SVD of
+     * Eqs. (7)-(11) with the test matrix Om (n x ell; sign rule on its small factor) */
+    int64_t rk = K < n ? K : n;
+    if (rc == ORC_OK && Om) {
+        int32_t kk = 0;
+        rc = orc_low_rank_svd(n, n, Rf, n, K, Om, ell, Ut, n, S, &kk);
+        rk = kk;
+    } else if (rc == ORC_OK) {
+        rc = orc_jacobi_svd(n, n, Rf, n, Ut, S, NULL, 60, NULL);
+        if (rc == ORC_OK) sign_rule(n, rk, Ut, n, NULL);
+    }
     if (rc == ORC_OK) {
-        const int64_t rk = K < n ? K : n;
-        sign_rule(n, rk, Ut, n, NULL);
         /* 4. U^i = Q^i (Q_g^i U~_rk) */
         double* T = (double*)malloc((size_t)n * (size_t)rk * sizeof(double));
         double* Qgi = (double*)malloc((size_t)n * (size_t)n * sizeof(double));
@@ -772,6 +829,25 @@ int orc_pstream_update(int32_t P, const int64_t* M_parts, int32_t K, double ff, 
     free(Ut);
     free(S);
     return rc;
+}
+
+int orc_pstream_update(int32_t P, const int64_t* M_parts, int32_t K, double ff, double* U_all, double* s, int32_t* r,
+                       const double* A_all, int64_t N)
+{
+    return pstream_impl(P, M_parts, K, ff, U_all, s, r, A_all, N, NULL, 0);
+}
+
+/*
+ * The partitioned update with the SVD of the combined R factor (step 3) taken
+ * by the low-rank SVD of Eqs. (7)-(11) with the test matrix Om (n x ell),
+ * n = r + N, as the paper's parallel QR listing does when randomization is on.
+ * The rank kept is min(K, ell).
+ */
+int orc_pstream_update_lr(int32_t P, const int64_t* M_parts, int32_t K, double ff, double* U_all, double* s,
+                          int32_t* r, const double* A_all, int64_t N, const double* Om, int64_t ell)
+{
+    if (!Om) return ORC_EINVAL;
+    return pstream_impl(P, M_parts, K, ff, U_all, s, r, A_all, N, Om, ell);
 }
 
 /* ------------------------------------------------------------------------ */

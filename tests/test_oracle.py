@@ -11,6 +11,7 @@ import os
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import synth
@@ -355,6 +356,119 @@ def test_apmos_truncated_local_rank_is_gram_of_W():
     U, Lam, X = oracle.apmos(parts, r, K)
     assert sigma_rel_err(Lam, ll[:K]) <= 1e-12
     assert np.abs(align_signs(X, Xl[:, :K]) - Xl[:, :K]).max() <= 1e-10
+
+
+# ----------------------------------------------------------------------------
+# The paper's placement of randomization: the low-rank SVD (Eqs. (7)-(11)) of
+# W in Algorithm 2 and of the combined R factor of the partitioned update
+# ----------------------------------------------------------------------------
+
+def test_low_rank_svd_exact_when_rank_fits_sketch():
+    # rank 5 <= ell: range(A Om) = range(A), so the low-rank SVD is the SVD
+    sig = np.array([3.0, 1.5, 0.9, 0.4, 0.2])
+    A, _, _ = planted(60, 45, sig, seed=31)
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    for ell in (5, 7):
+        U, s = oracle.low_rank_svd(A, 5, oracle.omega(3, 0, 45, ell, oracle.PREC_F64))
+        assert sigma_rel_err(s, sl[:5]) <= 1e-12
+        assert max_principal_angle(U, Ul[:, :5]) <= 1e-10
+        assert orth_err(U) <= 1e-13
+
+
+def test_low_rank_svd_is_ritz_of_the_sketch():
+    # general A, ell < rank: the values are the singular values of Q^T A with
+    # Q an orthonormal basis of A Om (LAPACK), so none exceeds the true one
+    g = rng(32)
+    A = np.asfortranarray(g.standard_normal((50, 40)) @ np.diag(np.logspace(0, -2, 40)))
+    Om = oracle.omega(5, 2, 40, 8, oracle.PREC_F64)
+    U, s = oracle.low_rank_svd(A, 6, Om)
+    Q, _ = np.linalg.qr(A @ Om)
+    Ub, sb, _ = np.linalg.svd(Q.T @ A)
+    sl = np.linalg.svd(A, compute_uv=False)
+    assert len(s) == 6
+    assert sigma_rel_err(s, sb[:6]) <= 1e-12
+    assert max_principal_angle(U, Q @ Ub[:, :6]) <= 1e-10
+    assert np.all(s <= sl[:6] * (1 + 1e-12))
+    assert s[0] < sl[0]                       # a sketch of 8 columns misses part of the top mode
+
+
+def test_apmos_low_rank_exact_when_W_rank_fits_sketch():
+    # W has rank 20 (the planted spectrum has 20 modes), ell = K = 20: the
+    # low-rank SVD of W is exact, so APMOS matches its exact form
+    w = synth.scaled(synth.c4_apmos(), partitions=4, part_min=200, part_max=500, N=48, sigma=2.0 ** (-np.arange(20) / 3.0),
+                     dtype=torch.float64)
+    parts = [synth.numpy_cm(t) for t in synth.apmos_partitions(w)]
+    U, Lam, X = oracle.apmos(parts, 25, 20)
+    Om = oracle.omega(7, 0, 4 * 25, 20, oracle.PREC_F64)
+    U2, Lam2, X2 = oracle.apmos(parts, 25, 20, omega=Om)
+    assert sigma_rel_err(Lam2, Lam) <= 1e-11
+    assert np.abs(align_signs(X2, X) - X).max() <= 1e-9
+    assert max_principal_angle(np.vstack(U2), np.vstack(U)) <= 1e-9
+
+
+def test_apmos_low_rank_is_low_rank_svd_of_W():
+    # Truncated local ranks and ell < rank(W): X~ and Lambda~ are the low-rank
+    # SVD of W = [V_i S_i] with the same test matrix.  Partitions [diag(d_i); 0]
+    # make W known without any SVD: the local right singular vectors are the
+    # coordinate vectors of the r largest d_i (positive, descending), so
+    # W_i = [d_i,pi(1) e_pi(1), ..., d_i,pi(r) e_pi(r)]; Q, B = Q^T W and the SVD
+    # of B are taken with LAPACK.
+    g = rng(33)
+    N, r, K, ell = 16, 5, 4, 6
+    parts, Ws = [], []
+    for m in (90, 120, 70):
+        d = g.uniform(0.1, 2.0, N)
+        Ai = np.zeros((m, N))
+        Ai[:N, :N] = np.diag(d)
+        parts.append(np.asfortranarray(Ai))
+        Wi = np.zeros((N, r))
+        for j, c in enumerate(np.argsort(-d, kind="stable")[:r]):
+            Wi[c, j] = d[c]
+        Ws.append(Wi)
+    W = np.hstack(Ws)
+    Om = oracle.omega(9, 0, 3 * r, ell, oracle.PREC_F64)
+    Q, _ = np.linalg.qr(W @ Om)
+    Ub, sb, _ = np.linalg.svd(Q.T @ W)
+    U, Lam, X = oracle.apmos(parts, r, K, omega=Om)
+    assert sigma_rel_err(Lam, sb[:K]) <= 1e-12
+    assert np.abs(align_signs(X, (Q @ Ub)[:, :K]) - (Q @ Ub)[:, :K]).max() <= 1e-10
+    sw = np.linalg.svd(W, compute_uv=False)
+    assert np.all(Lam <= sw[:K] * (1 + 1e-12))          # Ritz values of a sketch of W
+
+
+def test_pstream_low_rank_exact_when_rank_fits():
+    # rank 6 = K = ell, ff = 1, no local truncation loss: the low-rank SVDs of
+    # W and of every combined R are exact, so the stream is the SVD of the
+    # concatenation (LAPACK)
+    sig = np.linspace(3.0, 0.4, 6)
+    A, _, _ = planted(700, 40, sig, seed=34)
+    sizes = [150, 250, 300]
+    po = oracle.PartitionedStreamOracle(sizes, 6, ff=1.0, r_local=10, low_rank=True, seed=5)
+    for b in np.split(np.arange(40), 4):
+        po.incorporate(_split_rows(A[:, b], sizes))
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    assert sigma_rel_err(po.singular_values[:6], sl[:6]) <= 1e-12
+    assert max_principal_angle(po.modes[:, :6], Ul[:, :6]) <= 1e-10
+
+
+def test_pstream_low_rank_update_is_low_rank_svd_of_R():
+    # one low-rank partitioned update from a given state: the kept values are
+    # the low-rank SVD (same test matrix) of the R factor of the stacked panel
+    w = synth.scaled(synth.c1_plain_fp64(), M=600)
+    batches = [synth.numpy_cm(t) for t in synth.planted_stream(w)]
+    sizes = [120, 97, 200, 183]
+    po = oracle.PartitionedStreamOracle(sizes, w.K, ff=0.9, low_rank=True, seed=4)
+    po.incorporate(_split_rows(batches[0], sizes))
+    U0, s0 = po.modes.copy(), po.singular_values.copy()
+    C = np.hstack([0.9 * U0 * s0, batches[1]])
+    _, R = np.linalg.qr(C)
+    R = np.diag(np.sign(np.diag(R))) @ R                 # non-negative diagonal
+    Om = oracle.omega(4, 1, C.shape[1], w.K, oracle.PREC_F64)
+    Q, _ = np.linalg.qr(R @ Om)
+    sb = np.linalg.svd(Q.T @ R, compute_uv=False)
+    po.incorporate(_split_rows(batches[1], sizes))
+    assert sigma_rel_err(po.singular_values, sb[:w.K]) <= 1e-11
+    assert orth_err(po.modes) <= 1e-12
 
 
 # ----------------------------------------------------------------------------
