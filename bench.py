@@ -41,15 +41,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "bf16", "fp32", "fp64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the oracle sample (0: all M rows)")
     ap.add_argument("--M", type=int, default=1 << 20)
-    ap.add_argument("--workload", default="randomized", choices=["randomized", "partitioned", "burgers"],
-                    help="randomized: the headline mixed-precision randomized stream; partitioned: the "
+    ap.add_argument("--workload", default="randomized",
+                    choices=["randomized", "mixed_wide", "partitioned", "burgers", "gradient"],
+                    help="randomized: the headline mixed-precision randomized stream (M = 2^20, batches of "
+                         "256, K = 50, p = 10, q = 2); mixed_wide: the widest mixed-precision configuration "
+                         "(M = 2^22, batches of 512, K = 100, p = 20, q = 1); partitioned: the "
                          "partitioned streaming SVD (APMOS initialisation, partition QR combination); burgers: "
-                         "the partitioned stream over the closed-form Burgers snapshots (16384 x 800, FP64)")
+                         "the partitioned stream over the closed-form Burgers snapshots (16384 x 800, FP64); "
+                         "gradient: loss and reverse-mode gradient of the streamed truncated SVD (M = 2^18, "
+                         "4 batches of 64, K = 20, FP32)")
     ap.add_argument("--partitions", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibration of the HBM byte counters)")
@@ -76,9 +81,12 @@ def copy_probe(reps=4):
 
 
 def run_stream(P, w, batches, precision, steps, warmup, profile):
-    """Warm up, then time exactly `steps` updates; returns (ms/step, svd, stats)."""
+    """Warm up, then time exactly `steps` updates; returns (ms/step, svd, stats).
+    Every precision draws the same BF16-valued test matrices, so their results
+    differ only by their arithmetic."""
     svd = P.StreamingSVD(w.M, w.K, ff=w.ff, oversampling=w.oversampling, power_iters=w.power_iters,
-                         randomized=True, precision=precision, seed=w.seed, async_updates=True, profile=profile)
+                         randomized=True, precision=precision, seed=w.seed, async_updates=True, profile=profile,
+                         omega_bf16=True)
     nb = len(batches)
     views = [b.t() for b in batches]
     for i in range(warmup):
@@ -312,6 +320,56 @@ def bench_burgers(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_gradient(args):
+    """Loss L = ||A - U U^T A||_F^2 + sum_j w_j s_j of the deterministic stream and
+    its gradient dL/dA (M = 2^18 rows, 4 batches of 64 FP32 snapshots, K = 20,
+    spectral gap s_20 / s_21 = 4): forward (loss only) and forward + backward
+    (the backward recomputes every batch's panel from the stored incoming state)
+    timed on the device; one JSON line (time-like: lower is better)."""
+    import synth
+    import paper_2108_08845_amd as P
+    w = synth.c5_gradient()
+    bs = synth.planted_stream(w, device="cuda")
+    A = torch.cat(bs, dim=0).t()                  # M x (B Nb), column-major
+    wt = synth.loss_weights(w)
+    del bs
+    torch.cuda.synchronize()
+
+    def timed(want_grad):
+        for _ in range(args.warmup):
+            P.loss_and_grad(A, w.batches, w.K, w.ff, wt, want_grad=want_grad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            L, G = P.loss_and_grad(A, w.batches, w.K, w.ff, wt, want_grad=want_grad)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, L
+
+    fwd_ms, L = timed(False)
+    fb_ms, _ = timed(True)
+    n = w.K + w.N
+    panel = w.M * n * 4
+    # stored between the passes: the state entering every batch (U: M x K FP32, s: K FP64)
+    stored = w.batches * (w.M * w.K * 4 + w.K * 8)
+    # algorithmic bytes of the forward: per batch the Gram, the second Gram (Q1), the
+    # Q1 product and the lift read the panel (4 reads; Q1 written and read once more)
+    fwd_bytes = w.batches * (4 * panel + 2 * w.M * n * 4)
+    out = {
+        "metric": "loss + gradient of the streamed truncated SVD, ms per stream (forward + backward)",
+        "value": fb_ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": fb_ms, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32 (tall products) / f64 small core", "data": "synthetic",
+        "config": {"workload": w.name, "M": w.M, "N": w.N, "batches": w.batches, "K": w.K, "ff": w.ff,
+                   "parallelism": "single GPU"},
+        "forward_ms": fwd_ms, "forward_backward_ms": fb_ms, "stored_state_bytes": stored, "loss": L,
+        "roofline": {"bound": "hbm", "achieved": fwd_bytes / (fwd_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": fwd_bytes / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole forward stream (algorithmic bytes of its tall passes / stream time)"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -326,10 +384,19 @@ def main():
     if args.workload == "burgers":
         bench_burgers(args)
         return
+    if args.workload == "gradient":
+        bench_gradient(args)
+        return
     import synth
     import paper_2108_08845_amd as P
 
-    w = synth.scaled(synth.c2_randomized_fp32(), M=args.M)
+    if args.workload == "mixed_wide":
+        # 8 batches of 2^22 x 512 FP32 (69 GB) resident; fewer steps (tens of ms each)
+        w = synth.c3_mixed()
+        args.steps = min(args.steps, 8)
+        args.warmup = min(args.warmup, 2)
+    else:
+        w = synth.scaled(synth.c2_randomized_fp32(), M=args.M)
     log(f"generating {w.batches} batches of {w.M} x {w.N} on the GPU")
     batches = synth.planted_stream(w, device="cuda")
     torch.cuda.synchronize()
@@ -354,14 +421,24 @@ def main():
     panel_bytes = w.M * n * 4
     if dom == "fused_bf16":
         roof = {"bound": "hbm", "achieved": panel_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    elif dom == "fused_f32" and args.precision == "mixed":
+    elif dom == "split":
         # split-BF16 final pass: reads the panel, writes the kept sketch Y (M x l FP32)
         roof = {"bound": "hbm", "achieved": (panel_bytes + w.M * ell * 4) / (avg_ms * 1e-3) / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     elif dom == "fused_f32":
-        flops = 4.0 * w.M * n * ell + 2.0 * w.M * ell * ell
+        # power passes P = C^T (C X) on the FP32 matrix cores (the class average; the
+        # FP32 precision's final pass adds 2 M l^2 for G, not counted)
+        flops = 4.0 * w.M * n * ell
         roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s"}
+    elif dom == "nn":
+        # generic Y = C X (panel read, sketch written)
+        roof = {"bound": "hbm", "achieved": (panel_bytes + w.M * ell * 4) / (avg_ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif dom == "tn":
+        # generic reductions over the rows: C^T Y (panel and sketch read) and Y^T Y
+        roof = {"bound": "hbm", "achieved": (panel_bytes + w.M * ell * 4) / (avg_ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     elif dom == "lift":
         roof = {"bound": "hbm", "achieved": (panel_bytes + w.M * w.K * 4) / (avg_ms * 1e-3) / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
@@ -401,7 +478,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "bf16+f32 (mfma) / f64 small core", "fp32": "f32 (mfma) / f64 small core",
+        "dtype": {"mixed": "bf16 pairs (mfma, f32 accumulate) / f64 small core",
+                  "bf16": "bf16+f32 (mfma) / f64 small core", "fp32": "f32 (mfma) / f64 small core",
                   "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "M": w.M, "N": w.N, "batches_cycled": w.batches, "K": w.K,
@@ -413,23 +491,32 @@ def main():
     }
 
     if not args.no_fp64 and args.precision != "fp64":
+        # "At fixed sigma error": the FP64 path runs the same algorithm on the same
+        # test matrices; the sigma difference over every retained mode is the
+        # error of this precision, reported beside the speedup.
         log("timing the FP64 GPU path on the same batches")
         ms64, svd64, st64 = run_stream(P, w, batches, "fp64", args.steps, args.warmup, profile=False)
         s64 = svd64.singular_values
         svd64.close()
-        k = int(np.sum(s64 >= 3.0 * s64[-1]))
         out["fp64_ms_per_step"] = ms64
         out["speedup_vs_fp64"] = ms64 / ms
-        out["sigma_rel_diff_vs_fp64_path"] = {
-            "resolved_modes": k,
-            "max_resolved": float(np.max(np.abs(s_main[:k] - s64[:k]) / s64[:k])) if k else None,
-            "max_all": float(np.max(np.abs(s_main - s64) / s64)),
-        }
+        out["sigma_rel_diff_vs_fp64_path"] = {"modes": int(len(s64)),
+                                              "max_all": float(np.max(np.abs(s_main - s64) / s64))}
+        if args.precision == "mixed":
+            # the unrefined BF16 sketch (plain BF16 power passes), for comparison
+            log("timing the unrefined BF16 sketch on the same batches")
+            msb, svdb, _ = run_stream(P, w, batches, "bf16", args.steps, args.warmup, profile=False)
+            sb = svdb.singular_values
+            svdb.close()
+            out["bf16_sketch"] = {"ms_per_step": msb, "GB_per_s": bytes_per_step / (msb * 1e-3) / 1e9,
+                                  "speedup_vs_fp64": ms64 / msb,
+                                  "sigma_rel_diff_vs_fp64_path_max_all": float(np.max(np.abs(sb - s64) / s64))}
 
     del batches
     torch.cuda.empty_cache()
     if not args.no_cpu:
-        rows = args.cpu_rows or w.M
+        # the wide workload's oracle update takes ~90 s on all 2^22 rows: a 2^16-row sample
+        rows = args.cpu_rows or (w.M if args.workload == "randomized" else 1 << 16)
         log(f"oracle CPU baseline on {rows} rows")
         out["cpu_baseline"] = cpu_baseline(w, rows)
     else:

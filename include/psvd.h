@@ -55,25 +55,37 @@ typedef enum psvd_method {
 typedef enum psvd_precision {
     PSVD_PREC_FP64 = 0,     /* every product in FP64; state U in FP64            */
     PSVD_PREC_FP32 = 1,     /* panel products in FP32 (MFMA), small core FP64    */
-    PSVD_PREC_MIXED = 2     /* power passes in BF16 (MFMA, FP32 accumulation),
-                               final projection and lift in FP32, small core FP64 */
+    PSVD_PREC_MIXED = 2,    /* power passes on the FP32 matrix cores; the final
+                               projection on the BF16 matrix cores with every
+                               operand split into a BF16 pair (hi + lo), FP32
+                               accumulation; Grams summed in FP64, small core
+                               FP64; lift FP32                                  */
+    PSVD_PREC_BF16 = 3      /* power passes on plain BF16 operands (the
+                               unrefined sketch), the final projection as in
+                               MIXED but with a BF16-rounded test matrix: faster,
+                               with the BF16 sketch's error                      */
 } psvd_precision;
 
 enum {
     PSVD_OPT_ASYNC = 1,        /* do not synchronise at the end of each update     */
     PSVD_OPT_NO_FALLBACK = 2,  /* report Cholesky breakdown instead of falling back */
-    PSVD_OPT_PROFILE = 4       /* time each tall-panel kernel with HIP events      */
+    PSVD_OPT_PROFILE = 4,      /* time each tall-panel kernel with HIP events      */
+    PSVD_OPT_OMEGA_BF16 = 8    /* test matrices rounded to BF16 values whatever the
+                                  precision (the values MIXED and BF16 use), so
+                                  precisions can be compared on identical ones    */
 };
 
 /* Kernel classes timed with PSVD_OPT_PROFILE (index into psvd_stats_t arrays). */
 enum {
-    PSVD_KC_FUSED_BF16 = 0,    /* C^T (C X) in BF16 (power passes, mixed)         */
-    PSVD_KC_FUSED_F32 = 1,     /* C^T (C X) and (C X)^T (C X) in FP32             */
+    PSVD_KC_FUSED_BF16 = 0,    /* C^T (C X) in BF16 (power passes, BF16 precision) */
+    PSVD_KC_FUSED_F32 = 1,     /* C^T (C X) [and (C X)^T (C X)] on the FP32 matrix
+                                  cores (power passes of FP32 and mixed, FP32 final) */
     PSVD_KC_LIFT = 2,          /* U <- C T                                         */
     PSVD_KC_TN = 3,            /* reductions over the tall rows (Gram, C^T Y)     */
     PSVD_KC_NN = 4,            /* other tall products (C X written out)           */
     PSVD_KC_SMALL = 5,         /* small-core kernels without an SVD (Cholesky-QR) */
     PSVD_KC_SMALL_SVD = 6,     /* small-core kernels with the one-sided Jacobi SVD */
+    PSVD_KC_SPLIT = 7,         /* final passes on split-BF16 operands (C^T Y, Y kept) */
     PSVD_KC_COUNT = 8
 };
 
@@ -87,6 +99,10 @@ typedef struct psvd_options {
     int32_t tile_rows;      /* fused passes: row-tile height 16/32/64, 0 = default */
     int32_t wg_per_cu;      /* fused passes: work-groups per compute unit 1..4,
                                0 = default (1); see the autotuner               */
+    int32_t panel_width;    /* fused passes: plan for a panel at least this wide
+                               (a wider compiled tile width), 0 = the panel's   */
+    int32_t split_m;        /* generic tall products: work items the rows are
+                               split into (times output blocks), 0 = 1024       */
 } psvd_options;
 
 typedef struct psvd_stats_t {
@@ -163,6 +179,15 @@ int psvd_modes_ptr(const psvd_handle* h, const void** U, int64_t* ldu, int32_t* 
  */
 int psvd_get_omega(const psvd_handle* h, int64_t batch, int64_t n, double* out);
 
+/*
+ * Launch parameters of the tall-panel kernels (the fields tile_rows, wg_per_cu,
+ * panel_width and split_m of psvd_options, with the same meaning and ranges),
+ * set on an existing handle, e.g. from an autotuner's cache once the batch
+ * width is known.  They change the grouping of the fixed-order partial sums
+ * (results agree to rounding), not what is computed.  Errors: PSVD_E_INVAL.
+ */
+int psvd_set_tuning(psvd_handle* h, int32_t tile_rows, int32_t wg_per_cu, int32_t panel_width, int32_t split_m);
+
 /* Metrics of the handle (host copy); synchronises the stream when profiling. */
 int psvd_stats(const psvd_handle* h, psvd_stats_t* out);
 
@@ -236,13 +261,30 @@ int psvd_apmos_batched(int32_t P, const void* const* A_parts, const int64_t* M_p
                        const int64_t* ldu_parts, double* Lambda, double* X, void* stream);
 
 /*
+ * Algorithm 2 as psvd_apmos_batched, with the SVD of W in step 3 taken by the
+ * low-rank SVD of Sec. 3.3 (Eqs. 7-11 without power iterations): Y = W Om
+ * with the Gaussian test matrix Om (P r x ell, FP64 values of the generator of
+ * psvd_get_omega keyed by (seed, 0)), Q = orth(Y), B = Q^T W = U~ S V~^T,
+ * X~ = Q U~[:, :K], Lambda~ = S[:K] -- where the paper's parallel listing
+ * randomizes.  K <= ell <= min(N, P r).  Exact when rank(W) <= ell.
+ * Arguments, outputs and errors as psvd_apmos_batched.
+ */
+int psvd_apmos_low_rank(int32_t P, const void* const* A_parts, const int64_t* M_parts, const int64_t* ld_parts,
+                        int64_t N, int32_t dtype, int32_t r, int32_t K, int32_t ell, uint64_t seed,
+                        void* const* U_parts, const int64_t* ldu_parts, double* Lambda, double* X, void* stream);
+
+/*
  * Partitioned streaming: the parallel streaming SVD of Section 3 (the
  * initialisation by APMOS, Algorithm 2, and the batch update with a QR over
  * row partitions) with P row partitions of the data, all on this GPU.
  * M_parts[i] >= 1 rows per partition; K modes; ff in (0, 1]; r_local the
- * local truncation of the APMOS initialisation (0: min(K, N)).  opt: the
- * deterministic method with PSVD_PREC_FP64 (FP64 data and state) or
- * PSVD_PREC_FP32 (FP32 data and state).  The handle works with
+ * local truncation of the APMOS initialisation (0: min(K, N)).  opt:
+ * PSVD_PREC_FP64 (FP64 data and state) or PSVD_PREC_FP32 (FP32 data and
+ * state); method PSVD_DETERMINISTIC takes exact SVDs of W and of the combined
+ * R factor, PSVD_RANDOMIZED the paper's placement of randomization in the
+ * parallel variant: both by the low-rank SVD of Sec. 3.3 (Eqs. 7-11) with a
+ * K-column Gaussian test matrix, FP64 values keyed by (opt.seed, b) for batch
+ * b (the initialisation is batch 0).  The handle works with
  * psvd_pstream_incorporate / psvd_pstream_modes_ptr and psvd_rank,
  * psvd_singular_values, psvd_stats, psvd_last_error, psvd_finalize; the
  * single-panel calls (incorporate_data, modes, checkpoints) return

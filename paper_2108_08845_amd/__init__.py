@@ -22,7 +22,7 @@ from ._lib import PsvdError
 __all__ = ["StreamingSVD", "PartitionedStreamingSVD", "apmos_batched", "PsvdError", "stream_backward", "loss_and_grad", "StreamingSVDFunction",
            "rsvd"]
 
-_PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32, "mixed": _lib.PREC_MIXED}
+_PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32, "mixed": _lib.PREC_MIXED, "bf16": _lib.PREC_BF16}
 
 
 def _stream_ptr(stream):
@@ -52,12 +52,14 @@ class StreamingSVD:
 
     ff: forget factor in (0, 1].  randomized: use the randomized range finder
     (sketch width K + oversampling, `power_iters` power iterations) whenever it
-    is narrower than the panel.  precision: "fp64", "fp32" or "mixed".
+    is narrower than the panel.  precision: "fp64", "fp32", "mixed" (FP32 power
+    passes, split-BF16 final projection) or "bf16" (BF16 power passes, the
+    unrefined sketch).
     """
 
     def __init__(self, M, K, ff=1.0, oversampling=0, power_iters=0, randomized=False, precision="fp64",
                  seed=0, stream=None, async_updates=False, max_sweeps=60, fallback=True, profile=False,
-                 tile_rows=0, wg_per_cu=0):
+                 tile_rows=0, wg_per_cu=0, omega_bf16=False, panel_width=0, split_m=0, autotuned=True):
         self._libh = _lib.load()
         opt = _lib.Options()
         self._libh.psvd_default_options(ctypes.byref(opt))
@@ -69,14 +71,21 @@ class StreamingSVD:
         opt.max_sweeps = int(max_sweeps)
         opt.tile_rows = int(tile_rows)
         opt.wg_per_cu = int(wg_per_cu)
+        opt.panel_width = int(panel_width)
+        opt.split_m = int(split_m)
         opt.flags = ((_lib.OPT_ASYNC if async_updates else 0) | (0 if fallback else _lib.OPT_NO_FALLBACK)
-                     | (_lib.OPT_PROFILE if profile else 0))
+                     | (_lib.OPT_PROFILE if profile else 0) | (_lib.OPT_OMEGA_BF16 if omega_bf16 else 0))
         h = ctypes.c_void_p()
         rc = self._libh.psvd_initialize(ctypes.byref(h), int(M), int(K), float(ff), int(oversampling),
                                         int(power_iters), ctypes.byref(opt))
         _lib.check(rc, None, "psvd_initialize")
         self._h = h
         self.M, self.K, self.ff = int(M), int(K), float(ff)
+        # launch parameters from the autotuner's cache, applied once the batch
+        # width is known, unless the caller set any of them
+        self._tune_pending = bool(autotuned) and not (tile_rows or wg_per_cu or panel_width or split_m)
+        self.tuning = None
+        self._tune_key = (int(oversampling), int(power_iters), precision, bool(randomized))
         self.oversampling, self.power_iters = int(oversampling), int(power_iters)
         self.randomized, self.precision, self.seed = bool(randomized), precision, int(seed)
         self._keep = None
@@ -92,9 +101,27 @@ class StreamingSVD:
         except Exception:
             pass
 
+    def apply_tuning(self, tile_rows=0, wg_per_cu=0, panel_width=0, split_m=0):
+        """Set the launch parameters of the tall-panel kernels (psvd_set_tuning)."""
+        rc = self._libh.psvd_set_tuning(self._h, int(tile_rows), int(wg_per_cu), int(panel_width), int(split_m))
+        _lib.check(rc, self._h, "set_tuning")
+
+    def _apply_cached_tuning(self, N):
+        self._tune_pending = False
+        p, q, precision, randomized = self._tune_key
+        if not randomized:
+            return
+        from . import autotune
+        opts = autotune.cached_options(self.M, N, self.K, p, q, precision)
+        if opts is not None:
+            self.apply_tuning(**opts)
+            self.tuning = opts
+
     def incorporate_data(self, A):
         """Ingest one batch A (M x N CUDA tensor, column-major preferred)."""
         ptr, M, N, lda, code, keep = _as_colmajor(A)
+        if self._tune_pending:
+            self._apply_cached_tuning(N)
         self._keep = keep   # the update reads A on the stream
         rc = self._libh.psvd_incorporate_data(self._h, ptr, M, N, lda, code)
         _lib.check(rc, self._h, "incorporate_data")
@@ -181,13 +208,17 @@ class PartitionedStreamingSVD:
     M_parts: rows of each partition.  The first batch initialises the modes by
     APMOS (local truncation `r_local`, 0 = min(K, N)); later batches combine the
     partitions' QR factors.  precision "fp64" (FP64 data) or "fp32" (FP32 data).
+    low_rank: the paper's placement of randomization -- the SVD of W and of the
+    combined R factor by the low-rank SVD with a K-column test matrix (seed).
     """
 
-    def __init__(self, M_parts, K, ff=1.0, r_local=0, precision="fp64", stream=None, max_sweeps=60, profile=False):
+    def __init__(self, M_parts, K, ff=1.0, r_local=0, precision="fp64", stream=None, max_sweeps=60, profile=False,
+                 low_rank=False, seed=0):
         self._libh = _lib.load()
         opt = _lib.Options()
         self._libh.psvd_default_options(ctypes.byref(opt))
-        opt.method = _lib.DETERMINISTIC
+        opt.method = _lib.RANDOMIZED if low_rank else _lib.DETERMINISTIC
+        opt.seed = int(seed)
         opt.precision = _PREC[precision]
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         opt.stream = _stream_ptr(self._stream).value
@@ -293,11 +324,14 @@ def rsvd(A, K, oversampling=10, power_iters=2, seed=0, precision="fp32", out_dty
     return U[:r].t(), s[:r].copy(), V[:r].t()
 
 
-def apmos_batched(parts, r, K, stream=None):
+def apmos_batched(parts, r=50, K=5, stream=None, low_rank_ell=0, seed=0):
     """Algorithm 2 over row partitions (list of M_i x N CUDA tensors, same dtype).
 
-    Returns (U_parts, Lambda, X): U_parts[i] is M_i x K (column-major),
-    Lambda the K global singular values, X the N x K right factor.
+    r, K: the local and global truncations (the paper's defaults r1 = 50 and
+    r2 = 5; r is clamped to N).  low_rank_ell > 0: the SVD of W is the paper's
+    low-rank SVD with an ell-column test matrix keyed by `seed`
+    (psvd_apmos_low_rank).  Returns (U_parts, Lambda, X): U_parts[i] is M_i x K
+    (column-major), Lambda the K global singular values, X the N x K right factor.
     """
     lib = _lib.load()
     P = len(parts)
@@ -315,9 +349,16 @@ def apmos_batched(parts, r, K, stream=None):
     ldus = (ctypes.c_int64 * P)(*[c[1] for c in cols])
     Lam = np.zeros(K)
     X = np.zeros((K, N))
-    rc = lib.psvd_apmos_batched(P, A_ptrs, Ms, lds, N, code, int(r), int(K), U_ptrs, ldus,
-                                Lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(stream))
+    r = min(int(r), N)
+    if low_rank_ell:
+        rc = lib.psvd_apmos_low_rank(P, A_ptrs, Ms, lds, N, code, r, int(K), int(low_rank_ell),
+                                     ctypes.c_uint64(int(seed)), U_ptrs, ldus,
+                                     Lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(stream))
+    else:
+        rc = lib.psvd_apmos_batched(P, A_ptrs, Ms, lds, N, code, r, int(K), U_ptrs, ldus,
+                                    Lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(stream))
     _lib.check(rc, None, "apmos_batched")
     return [o.t() for o in outs], Lam, np.ascontiguousarray(X.T)
 

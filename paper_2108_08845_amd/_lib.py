@@ -18,16 +18,17 @@ STATUS = {
 globals().update({name: code for code, name in STATUS.items()})   # PSVD_E_INVAL = -1, ...
 PSVD_F32, PSVD_F64 = 1, 2
 DETERMINISTIC, RANDOMIZED = 0, 1
-PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
-OPT_ASYNC, OPT_NO_FALLBACK, OPT_PROFILE = 1, 2, 4
-KERNEL_CLASSES = ["fused_bf16", "fused_f32", "lift", "tn", "nn", "small", "small_svd"]
+PREC_FP64, PREC_FP32, PREC_MIXED, PREC_BF16 = 0, 1, 2, 3
+OPT_ASYNC, OPT_NO_FALLBACK, OPT_PROFILE, OPT_OMEGA_BF16 = 1, 2, 4, 8
+KERNEL_CLASSES = ["fused_bf16", "fused_f32", "lift", "tn", "nn", "small", "small_svd", "split"]
 
 EXPORTS = [
     "psvd_default_options", "psvd_initialize", "psvd_incorporate_data", "psvd_rank", "psvd_singular_values",
     "psvd_modes", "psvd_modes_ptr", "psvd_get_omega", "psvd_stats", "psvd_last_error", "psvd_status_string",
     "psvd_finalize", "psvd_reset_stats", "psvd_apmos_batched", "psvd_stream_backward", "psvd_loss_grad",
     "psvd_save_state", "psvd_load_state", "psvd_rsvd", "psvd_pstream_initialize", "psvd_pstream_incorporate",
-    "psvd_pstream_modes_ptr", "psvd_pstream_modes",
+    "psvd_pstream_modes_ptr", "psvd_pstream_modes", "psvd_apmos_low_rank",
+    "psvd_set_tuning",
 ]
 
 
@@ -35,7 +36,8 @@ class Options(ctypes.Structure):
     _fields_ = [
         ("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_void_p), ("max_sweeps", ctypes.c_int32), ("flags", ctypes.c_int32),
-        ("tile_rows", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("panel_width", ctypes.c_int32),
+        ("split_m", ctypes.c_int32),
     ]
 
 
@@ -76,6 +78,7 @@ def load():
     lib.psvd_modes_ptr.argtypes = [H, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.psvd_get_omega.argtypes = [H, i64, i64, dp]
     lib.psvd_stats.argtypes = [H, ctypes.POINTER(Stats)]
+    lib.psvd_set_tuning.argtypes = [H, i32, i32, i32, i32]
     lib.psvd_reset_stats.argtypes = [H]
     lib.psvd_last_error.argtypes = [H]
     lib.psvd_last_error.restype = ctypes.c_char_p
@@ -85,6 +88,9 @@ def load():
     lib.psvd_finalize.restype = None
     lib.psvd_apmos_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64), i64, i32,
                                        i32, i32, ctypes.POINTER(vp), ctypes.POINTER(i64), dp, dp, vp]
+    lib.psvd_apmos_low_rank.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64), i64, i32,
+                                        i32, i32, i32, ctypes.c_uint64, ctypes.POINTER(vp), ctypes.POINTER(i64), dp, dp,
+                                        vp]
     lib.psvd_stream_backward.argtypes = [vp, i64, i64, i32, i32, i64, i32, ctypes.c_double, vp, dp, vp, vp]
     lib.psvd_loss_grad.argtypes = [vp, i64, i64, i32, i32, i64, i32, ctypes.c_double, dp, dp, vp, vp]
     lib.psvd_save_state.argtypes = [H, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]

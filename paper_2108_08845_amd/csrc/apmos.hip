@@ -10,6 +10,9 @@
 //   3. W W^T = sum_i W_i W_i^T (k_tn on W^T) and its Jacobi eigen-decomposition
 //      -> X~, Lambda~ (the SVD of W of Eq. 5, truncated to K);
 //   4. k_nn over the same work list: U_i = A_i X~ diag(1 / Lambda~)  (Eq. 6).
+// With the paper's placement of randomization (psvd_apmos_low_rank), step 3 is
+// the low-rank SVD of W instead (k_low_rank_small: Eqs. 7-11 on W with an
+// ell-column Gaussian test matrix).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +25,25 @@
 using namespace psvd;
 
 namespace {
+
+// Sign rule on the columns of W = the rows of W^T (rows x cols, leading
+// dimension ld): each gets its largest-magnitude entry (lowest index on ties)
+// non-negative.  The exact SVD of W does not see column signs (W W^T does not
+// change); its low-rank SVD does (the sketch is W Om), so both sides fix them.
+__global__ void k_wt_row_signs(double* Wt, int rows, int cols, int ld) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    double best = -1.0, v = 0.0;
+    for (int k = 0; k < cols; ++k) {
+        const double x = Wt[i + (size_t)k * ld];
+        if (fabs(x) > best) {
+            best = fabs(x);
+            v = x;
+        }
+    }
+    if (v < 0.0)
+        for (int k = 0; k < cols; ++k) Wt[i + (size_t)k * ld] = -Wt[i + (size_t)k * ld];
+}
 
 struct ApmosWork {
     std::mutex mu;
@@ -44,12 +66,14 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const int64_t* M_parts,
-                                  const int64_t* ld_parts, int64_t N, int32_t dtype, int32_t r, int32_t K,
-                                  void* const* U_parts, const int64_t* ldu_parts, double* Lambda, double* X,
-                                  void* stream) {
+// Algorithm 2 with the exact SVD of W (ell = 0) or its low-rank SVD with the
+// test matrix of (seed, batch) with ell columns, FP64 values.
+static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_parts, const int64_t* ld_parts,
+                     int64_t N, int32_t dtype, int32_t r, int32_t K, int32_t ell, uint64_t seed, int64_t batch,
+                     void* const* U_parts, const int64_t* ldu_parts, double* Lambda, double* X, void* stream) {
     if (P < 1 || N < 1 || r < 1 || r > N || K < 1 || K > N || (int64_t)K > (int64_t)P * r || N > 4096)
         return PSVD_E_INVAL;
+    if (ell < 0 || (ell > 0 && (ell < K || ell > N || (int64_t)ell > (int64_t)P * r))) return PSVD_E_INVAL;
     if (!A_parts || !M_parts || !ld_parts || !U_parts || !ldu_parts) return PSVD_E_INVAL;
     if (dtype != PSVD_F32 && dtype != PSVD_F64) return PSVD_E_DTYPE;
     int64_t Mtot = 0;
@@ -133,6 +157,8 @@ extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const i
     size_t o_ivec = take(sizeof(int32_t) * (size_t)P * N + 64);
     size_t o_stat = take(64);
     size_t o_wwpart = take(sizeof(double) * 2048 * (size_t)mbw * (mbw + 1) / 2 * TN_OB * TN_OB);
+    size_t o_om = take(sizeof(double) * (size_t)pr * std::max(ell, 1));
+    size_t o_lr = take(sizeof(double) * (ell > 0 ? low_rank_work_doubles((int)N, pr, ell) : 1));
     const size_t total = off;
 
     ApmosWork& W = work_for_device();
@@ -166,6 +192,8 @@ extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const i
     int32_t* d_ivec = (int32_t*)(base + o_ivec);
     int32_t* d_stat = (int32_t*)(base + o_stat);
     double* d_wwpart = (double*)(base + o_wwpart);
+    double* d_om = (double*)(base + o_om);
+    double* d_lr = (double*)(base + o_lr);
 
     // Descriptors (synchronous upload; the call is synchronous anyway).
     e = hipMemcpyAsync(d_segs, segs.data(), sizeof(PanelSeg) * P, hipMemcpyHostToDevice, st);
@@ -174,11 +202,17 @@ extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const i
         e = hipMemcpyAsync(d_litems, litems.data(), sizeof(WorkItem) * nlitems, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_si0, seg_item0.data(), sizeof(int32_t) * (P + 1), hipMemcpyHostToDevice, st);
+    std::vector<double> om;
+    if (ell > 0) {
+        om.resize((size_t)pr * ell);
+        host_omega(seed, batch, pr, ell, 0, om.data());
+        if (e == hipSuccess) e = hipMemcpyAsync(d_om, om.data(), sizeof(double) * om.size(), hipMemcpyHostToDevice, st);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(d_stat, 0, 64, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return PSVD_E_DEVICE;
 
-    std::vector<int64_t> key = {P, N, r, K, dtype, nitems, nlitems, (int64_t)(uintptr_t)W.buf, (int64_t)total};
+    std::vector<int64_t> key = {P, N, r, K, dtype, nitems, nlitems, (int64_t)(uintptr_t)W.buf, (int64_t)total, ell};
     for (int i = 0; i < P; ++i) key.push_back(M_parts[i]);
     const bool reuse = W.exec && W.key == key && W.key_stream == st;
 
@@ -221,7 +255,34 @@ extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const i
             la.status = d_stat;
             la.sweeps = d_stat + 1;
             if (ce == hipSuccess) ce = launch_apmos_local(la, s2);
-            // 3. W W^T and the global eigen-decomposition
+            if (ce == hipSuccess) {
+                hipLaunchKernelGGL(k_wt_row_signs, dim3((pr + 255) / 256), dim3(256), 0, s2, d_Wt, pr, (int)N, pr);
+                ce = hipGetLastError();
+            }
+            // 3. the SVD of W: the low-rank SVD (Eqs. 7-11 on W = (W^T)^T) ...
+            if (ell > 0) {
+                LowRankArgs lr;
+                std::memset(&lr, 0, sizeof(lr));
+                lr.m = (int)N;
+                lr.n = pr;
+                lr.l = ell;
+                lr.K = K;
+                lr.A = d_Wt;          // W(i, j) = W^T(j, i) at d_Wt[j + i pr]
+                lr.a_i = pr;
+                lr.a_j = 1;
+                lr.Om = d_om;
+                lr.max_sweeps = 60;
+                lr.work = d_lr;
+                lr.U = d_X;
+                lr.ldu = N;
+                lr.s = d_Lam;
+                lr.post = 2;
+                lr.T = d_T;
+                lr.status = d_stat;
+                lr.sweeps = d_stat + 1;
+                if (ce == hipSuccess) ce = launch_low_rank_small(lr, s2);
+            }
+            // ... or W W^T and its Jacobi eigen-decomposition
             PanelSeg ws;
             std::memset(&ws, 0, sizeof(ws));
             ws.rows = pr;
@@ -243,7 +304,7 @@ extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const i
             wa.sym = 1;
             wa.part = d_wwpart;
             wa.nob = nobw;
-            if (ce == hipSuccess) ce = launch_tn(true, wa, nwitems, s2);
+            if (ce == hipSuccess && ell == 0) ce = launch_tn(true, wa, nwitems, s2);
             TnReduceArgs wr;
             std::memset(&wr, 0, sizeof(wr));
             wr.part = d_wwpart;
@@ -254,7 +315,7 @@ extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const i
             wr.nr = (int)N;
             wr.sym = 1;
             wr.out = d_WW;
-            if (ce == hipSuccess) ce = launch_tn_reduce(wr, 1, s2);
+            if (ce == hipSuccess && ell == 0) ce = launch_tn_reduce(wr, 1, s2);
             ApmosGlobalArgs ga;
             ga.WW = d_WW;
             ga.N = (int)N;
@@ -267,7 +328,7 @@ extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const i
             ga.ivec = d_ivec;
             ga.status = d_stat;
             ga.sweeps = d_stat + 1;
-            if (ce == hipSuccess) ce = launch_apmos_global(ga, s2);
+            if (ce == hipSuccess && ell == 0) ce = launch_apmos_global(ga, s2);
             // 4. lift over all partitions
             NnArgs na;
             std::memset(&na, 0, sizeof(na));
@@ -320,3 +381,28 @@ extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const i
     if (hstat[0] & DEV_SMALL_LAMBDA) return PSVD_E_INVAL;
     return PSVD_OK;
 }
+
+extern "C" int psvd_apmos_batched(int32_t P, const void* const* A_parts, const int64_t* M_parts,
+                                  const int64_t* ld_parts, int64_t N, int32_t dtype, int32_t r, int32_t K,
+                                  void* const* U_parts, const int64_t* ldu_parts, double* Lambda, double* X,
+                                  void* stream) {
+    return apmos_run(P, A_parts, M_parts, ld_parts, N, dtype, r, K, 0, 0, 0, U_parts, ldu_parts, Lambda, X, stream);
+}
+
+extern "C" int psvd_apmos_low_rank(int32_t P, const void* const* A_parts, const int64_t* M_parts,
+                                   const int64_t* ld_parts, int64_t N, int32_t dtype, int32_t r, int32_t K,
+                                   int32_t ell, uint64_t seed, void* const* U_parts, const int64_t* ldu_parts,
+                                   double* Lambda, double* X, void* stream) {
+    if (ell < 1) return PSVD_E_INVAL;
+    return apmos_run(P, A_parts, M_parts, ld_parts, N, dtype, r, K, ell, seed, 0, U_parts, ldu_parts, Lambda, X,
+                     stream);
+}
+
+namespace psvd {
+int apmos_internal(int32_t P, const void* const* A_parts, const int64_t* M_parts, const int64_t* ld_parts, int64_t N,
+                   int32_t dtype, int32_t r, int32_t K, int32_t ell, uint64_t seed, int64_t batch,
+                   void* const* U_parts, const int64_t* ldu_parts, double* Lambda, double* X, void* stream) {
+    return apmos_run(P, A_parts, M_parts, ld_parts, N, dtype, r, K, ell, seed, batch, U_parts, ldu_parts, Lambda, X,
+                     stream);
+}
+}  // namespace psvd

@@ -119,6 +119,7 @@ struct SmallArgs {
     int32_t* ivec;        // n scratch
     int32_t* status;      // DevStatus bits
     int32_t* sweeps;      // last Jacobi sweep count
+    int32_t skip_svd;     // k_small_det2 stops after R = R2 R1 (the caller takes the SVD of R)
 };
 
 struct OrthArgs {
@@ -181,6 +182,27 @@ struct ApmosGlobalArgs {
     int32_t* sweeps;
 };
 
+// The paper's low-rank SVD of a small matrix (k_low_rank_small): Eqs. (7)-(11)
+// without power iterations, one work-group.
+struct LowRankArgs {
+    int32_t m, n, l, K;        // A is m x n; test matrix n x l; k = min(K, l) triplets kept
+    const double* A;           // element (i, j) at A[i * a_i + j * a_j]
+    int64_t a_i, a_j;
+    const double* Om;          // n x l, column-major (ld n)
+    int32_t max_sweeps;
+    double* work;              // low_rank_work_doubles(m, n, l)
+    double* U;                 // m x k out (ld ldu): the left singular vectors Q U~_k
+    int64_t ldu;
+    double* s;                 // k out
+    int32_t post;              // 0: none; 1: T = R^-1 U with R = post_R (m x m upper, ld m);
+                               // 2: T = U diag(1 / s) with the small-value check
+    const double* post_R;
+    double* T;                 // m x k out (ld m) for post 1 and 2
+    int32_t* status;
+    int32_t* sweeps;
+};
+size_t low_rank_work_doubles(int m, int n, int l);
+
 struct GradCoreArgs {
     int32_t n, r, rk;
     const double* R;      // n x n upper Cholesky-QR factor of the panel
@@ -221,6 +243,13 @@ hipError_t launch_sketch_bf16(const FusedArgs& a, hipStream_t st);
 bool split_plan(int n, FusedPlan* p);
 hipError_t launch_final_split(const FusedArgs& a, hipStream_t st);
 hipError_t launch_fused(int mode, const FusedArgs& a, hipStream_t st);   // FP32: 0 power, 1 final, 2 lift
+// Final pass of the mixed precision with split-BF16 operands (k_split64) on
+// float4-aligned panels, one column block: P = C^T (C X) and the kept Y
+// (a.yout, a BF16 pair per value).
+bool split64_plan(int n, FusedPlan* p);
+hipError_t launch_split64(const FusedArgs& a, hipStream_t st);
+// G = Y^T Y of the kept sketch into nwg FP64 64 x 64 partials (k_gram_kept).
+hipError_t launch_gram_kept(const float* Y, int64_t rows, int64_t ldy, int lx, int nwg, double* part, hipStream_t st);
 hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st);
 
 hipError_t launch_small_det1(const SmallArgs& a, hipStream_t st);
@@ -229,10 +258,12 @@ hipError_t launch_small_orth(const OrthArgs& a, hipStream_t st);
 hipError_t launch_status_fold(int32_t* st, hipStream_t stream);
 hipError_t launch_small_rand_final(const RandFinalArgs& a, hipStream_t st);
 hipError_t launch_scale_rows(double* X, int n, int m, int ldx, const double* d, int r, int times, hipStream_t st);
-hipError_t launch_make_scale(double* d, const double* s, int r, double ff, hipStream_t st);
+// status (may be null): the status words are cleared in the same launch
+hipError_t launch_make_scale(int32_t* status, double* d, const double* s, int r, double ff, hipStream_t st);
 hipError_t launch_rand_begin(int32_t* status, double* d, const double* s, int r, double ff, double* X,
                              const double* Om, int n, int l, hipStream_t st);
 hipError_t launch_apmos_local(const ApmosLocalArgs& a, hipStream_t st);
+hipError_t launch_low_rank_small(const LowRankArgs& a, hipStream_t st);
 hipError_t launch_apmos_global(const ApmosGlobalArgs& a, hipStream_t st);
 
 }  // namespace psvd

@@ -1125,16 +1125,22 @@ __global__ __launch_bounds__(512) void k_final_split(FusedArgs a) {
             split_bf16x2(y[2], y[3], &h1, &l1);
             *(uint64_t*)&Ysh[col * ldY + r0] = (uint64_t)h0 | ((uint64_t)h1 << 32);
             *(uint64_t*)&Ysl[col * ldY + r0] = (uint64_t)l0 | ((uint64_t)l1 << 32);
-            // the kept copy of Y (columns < lx): rows r0 .. r0+3 of column col from registers
+            // the kept copy of Y (columns < lx): rows r0 .. r0+3 of column col from
+            // registers, as the pair sums the products of P and G use
             if (a.yout != nullptr && c0 + col < a.lx) {
                 const int64_t row = t * TM + r0;
                 float* o = a.yout + (size_t)(c0 + col) * (size_t)a.ldy + row;
+                f4_t yp;
+                yp[0] = __uint_as_float(h0 << 16) + __uint_as_float(l0 << 16);
+                yp[1] = __uint_as_float(h0 & 0xFFFF0000u) + __uint_as_float(l0 & 0xFFFF0000u);
+                yp[2] = __uint_as_float(h1 << 16) + __uint_as_float(l1 << 16);
+                yp[3] = __uint_as_float(h1 & 0xFFFF0000u) + __uint_as_float(l1 & 0xFFFF0000u);
                 if (VEC ? row < rows : row + 3 < rows) {   // VEC: rows % 4 == 0
-                    gst4(o, y);
+                    gst4(o, yp);
                 } else if (!VEC) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (row + q < rows) gst(o + q, y[q]);
+                        if (row + q < rows) gst(o + q, yp[q]);
                 }
             }
         }
@@ -1410,7 +1416,13 @@ __global__ __launch_bounds__(512) void k_final_split64(FusedArgs a) {
                 *(uint64_t*)&Ysl[col * ldY + r0] = (uint64_t)l0 | ((uint64_t)l1 << 32);
                 if (a.yout != nullptr && c0 + col < a.lx) {
                     const int64_t row = t * TM + r0;
-                    if (row < rows) gst4(a.yout + (size_t)(c0 + col) * (size_t)a.ldy + row, y);
+                    // the kept value is the pair sum, which the products of P and G use
+                    f4_t yp;
+                    yp[0] = __uint_as_float(h0 << 16) + __uint_as_float(l0 << 16);
+                    yp[1] = __uint_as_float(h0 & 0xFFFF0000u) + __uint_as_float(l0 & 0xFFFF0000u);
+                    yp[2] = __uint_as_float(h1 << 16) + __uint_as_float(l1 << 16);
+                    yp[3] = __uint_as_float(h1 & 0xFFFF0000u) + __uint_as_float(l1 & 0xFFFF0000u);
+                    if (row < rows) gst4(a.yout + (size_t)(c0 + col) * (size_t)a.ldy + row, yp);
                 }
             }
             lds_barrier();
@@ -1485,6 +1497,324 @@ __global__ __launch_bounds__(512) void k_final_split64(FusedArgs a) {
             const int row = gi * 16 + 4 * (lane >> 4) + v;
             const int col = (gj0 + j) * 16 + (lane & 15);
             gstd(outG + row + col * FU_LB, gsl[v + j * 16 * LDG]);
+        }
+}
+
+// ----------------------------------------------------------------------------
+// k_split64: the final pass of the mixed precision on the BF16 matrix cores,
+// 64-row tiles (float4-aligned panels, NP <= 320).  Every operand v is split
+// into a BF16 pair v = hi + lo (hi = bf16(v), lo = bf16(v - hi)) and a product
+// a b is taken as a_hi b_hi + a_lo b_hi + a_hi b_lo with FP32 accumulation; the
+// dropped a_lo b_lo and the pairs' own rounding are about 2^-16 |a| |b|.  The
+// test matrix is split too, so the sketched range is that of X itself (not of
+// a BF16-rounded copy).  Per tile:
+//   Y_tile = C_tile X          (three products: X_hi in registers, X_lo in LDS)
+//   P     += C_tile^T Y_tile   (three products on the split Y_tile)
+// and the pair sum Y_hi + Y_lo -- the value the products of P use -- goes to
+// the kept copy of Y (its Gram is formed from that copy by k_gram_kept).  The
+// tile buffer, barriers and load pipeline are those of k_final_split64: Y |
+// C^T Y | split and store of the next tile, whose loads were issued one tile
+// earlier.
+// ----------------------------------------------------------------------------
+template <int NKS>
+__global__ __launch_bounds__(512) void k_split64(FusedArgs a) {
+    constexpr int TM = 64, NT = 512;
+    constexpr int NP = NKS * 32;
+    constexpr int RG = TM / 4;                      // 16 row groups
+    constexpr int CGR = NT / RG;                    // 32 column groups of 4 x 4 blocks per round
+    constexpr int NC0 = NP / 4 < 64 ? NP / 4 : 64;
+    constexpr int R0 = (NC0 + CGR - 1) / CGR;
+    constexpr int NX = NP > 256 ? (NP - 256) / CGR : 0;
+    static_assert(NP <= 256 || (NP - 256) % CGR == 0, "columns past 256 in whole rounds");
+    constexpr int NIT = NKS / 2;
+    static_assert(NKS % 2 == 0, "an even number of 32-column slices");
+    constexpr int ldR = NP + 8, ldY = TM + 8, ldX = NP + 8;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* Crh = (uint16_t*)smem;                // hi, TM x ldR row-major
+    uint16_t* Crl = Crh + TM * ldR;                 // lo
+    uint16_t* Ysh = Crl + TM * ldR;                 // 64 x TM, column-major (hi)
+    uint16_t* Ysl = Ysh + FU_LB * ldY;              //                        (lo)
+    uint16_t* Xl = Ysl + FU_LB * ldY;               // X_lo, 64 columns x ldX (column j at j ldX)
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const FusedCoords fc = fused_coords(a);
+    if (fc.wg >= a.nwg) return;
+    const int wg = fc.wg, lb = fc.lb;
+    const int c0 = lb * FU_LB;
+    const int jb = w & 3, ibA = w >> 2;
+
+    // X = X_hi + X_lo: X_hi through the tile buffer into B-fragment registers,
+    // X_lo kept in LDS for the whole launch
+    bf8_t xh[NKS];
+    {
+        uint16_t* Xb = Crh;
+        stage_x<NP, NT>(a, c0, [&](int k, int j, double v) {
+            const float f = (float)v;
+            const uint16_t hb = f32_to_bf16_rne(f);
+            Xb[j * ldX + k] = hb;
+            Xl[j * ldX + k] = f32_to_bf16_rne(f - __uint_as_float((uint32_t)hb << 16));
+        });
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks)
+            xh[ks] = lds_b128(&Xb[(jb * 16 + (lane & 15)) * ldX + ks * 32 + 8 * (lane >> 4)]);
+        __syncthreads();
+    }
+
+    f4_t accP[NIT * 2];
+#pragma unroll
+    for (int t = 0; t < NIT * 2; ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int rg = (tid & 3) | (((tid >> 4) & 3) << 2);
+    const int cgl = ((tid >> 2) & 3) | ((tid >> 6) << 2);
+    const int rgx = tid & 15, cxl = tid >> 4;
+    const float* cp[R0][4];
+    bool cv[R0][4];
+#pragma unroll
+    for (int rr = 0; rr < R0; ++rr)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = (rr * CGR + cgl) * 4 + q;
+            cv[rr][q] = c < a.n;
+            cp[rr][q] = fcol(a.seg, c < a.n ? c : a.n - 1);
+        }
+    const float* cpx[NX > 0 ? NX : 1];
+    bool cvx[NX > 0 ? NX : 1];
+#pragma unroll
+    for (int x = 0; x < NX; ++x) {
+        const int c = 256 + CGR * x + cxl;
+        cvx[x] = c < a.n;
+        cpx[x] = fcol(a.seg, c < a.n ? c : a.n - 1);
+    }
+    const int64_t rows = a.seg.rows;
+    f4_t pf[R0][4];
+    f4_t pfx[NX > 0 ? NX : 1];
+    auto round_on = [&](int rr) { return (rr + 1) * CGR <= NC0 || rr * CGR + cgl < NC0; };
+    // loads only, rows % 4 == 0: past the end a float4 re-reads the last rows
+    auto fetch = [&](int64_t t) {
+        const int64_t row = t * TM + rg * 4, rowx = t * TM + rgx * 4;
+        const int64_t rowc = row < rows ? row : rows - 4, rowxc = rowx < rows ? rowx : rows - 4;
+#pragma unroll
+        for (int rr = 0; rr < R0; ++rr)
+            if (round_on(rr))
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + rowc);
+#pragma unroll
+        for (int x = 0; x < NX; ++x) pfx[x] = gld4(cpx[x] + rowxc);
+    };
+    auto store_tile = [&](int64_t tl) {
+        const bool rv = tl * TM + rg * 4 < rows;
+#pragma unroll
+        for (int rr = 0; rr < R0; ++rr) {
+            const int cg = rr * CGR + cgl;
+            if (round_on(rr)) {
+                f4_t v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (cv[rr][q] && rv) ? pf[rr][q] : f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t h0, l0, h1, l1;
+                    split_bf16x2(v[0][e], v[1][e], &h0, &l0);
+                    split_bf16x2(v[2][e], v[3][e], &h1, &l1);
+                    *(uint64_t*)&Crh[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)h0 | ((uint64_t)h1 << 32);
+                    *(uint64_t*)&Crl[(rg * 4 + e) * ldR + cg * 4] = (uint64_t)l0 | ((uint64_t)l1 << 32);
+                }
+            }
+        }
+        const bool rvx = tl * TM + rgx * 4 < rows;
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+            const f4_t v = (cvx[x] && rvx) ? pfx[x] : f4_t{0.f, 0.f, 0.f, 0.f};
+            const int c = 256 + CGR * x + cxl;
+#pragma unroll
+            for (int e = 0; e < 4; e += 2) {
+                uint32_t h, l;
+                split_bf16x2(v[e], v[e + 1], &h, &l);
+                Crh[(rgx * 4 + e) * ldR + c] = (uint16_t)(h & 0xFFFF);
+                Crh[(rgx * 4 + e + 1) * ldR + c] = (uint16_t)(h >> 16);
+                Crl[(rgx * 4 + e) * ldR + c] = (uint16_t)(l & 0xFFFF);
+                Crl[(rgx * 4 + e + 1) * ldR + c] = (uint16_t)(l >> 16);
+            }
+        }
+    };
+
+    const int64_t nwg = a.nwg;
+    int64_t t = wg;
+    if (t < a.tiles) {
+        fetch(t);
+        store_tile(t);
+        fetch(t + nwg);
+        lds_barrier();
+        for (; t < a.tiles; t += nwg) {
+            // Y rows 16 ib .. of column block jb = C_hi X_hi + C_lo X_hi + C_hi X_lo
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ib = ibA + 2 * h;
+                f4_t acc0 = f4_t{0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0;
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) {
+                    const int off = (ib * 16 + (lane & 15)) * ldR + ks * 32 + 8 * (lane >> 4);
+                    const bf8_t ah = lds_b128(&Crh[off]), al = lds_b128(&Crl[off]);
+                    const bf8_t xl = lds_b128(&Xl[(jb * 16 + (lane & 15)) * ldX + ks * 32 + 8 * (lane >> 4)]);
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xh[ks], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, xh[ks], acc1, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xl, acc2, 0, 0, 0);
+                }
+                const f4_t y = acc0 + (acc1 + acc2);
+                const int col = jb * 16 + (lane & 15), r0 = ib * 16 + 4 * (lane >> 4);
+                uint32_t h0, l0, h1, l1;
+                split_bf16x2(y[0], y[1], &h0, &l0);
+                split_bf16x2(y[2], y[3], &h1, &l1);
+                *(uint64_t*)&Ysh[col * ldY + r0] = (uint64_t)h0 | ((uint64_t)h1 << 32);
+                *(uint64_t*)&Ysl[col * ldY + r0] = (uint64_t)l0 | ((uint64_t)l1 << 32);
+                if (c0 + col < a.lx) {
+                    const int64_t row = t * TM + r0;
+                    f4_t yp;
+                    yp[0] = __uint_as_float(h0 << 16) + __uint_as_float(l0 << 16);
+                    yp[1] = __uint_as_float(h0 & 0xFFFF0000u) + __uint_as_float(l0 & 0xFFFF0000u);
+                    yp[2] = __uint_as_float(h1 << 16) + __uint_as_float(l1 << 16);
+                    yp[3] = __uint_as_float(h1 & 0xFFFF0000u) + __uint_as_float(l1 & 0xFFFF0000u);
+                    if (row < rows) gst4(a.yout + (size_t)(c0 + col) * (size_t)a.ldy + row, yp);
+                }
+            }
+            lds_barrier();
+            // P += C_tile^T Y (k = 64 rows: two steps).  Wave w: column blocks
+            // 2 (w % 2) + {0, 1}, row blocks (w / 2) NIT + u.
+            {
+                const int jp = w & 1, rb0 = (w >> 1) * NIT;
+                const int koff = 8 * (lane >> 4);
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    bf8_t yh[2], yl[2];
+#pragma unroll
+                    for (int jj = 0; jj < 2; ++jj) {
+                        const int boff = ((2 * jp + jj) * 16 + (lane & 15)) * ldY + ks * 32 + koff;
+                        yh[jj] = lds_b128(&Ysh[boff]);
+                        yl[jj] = lds_b128(&Ysl[boff]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < NIT; ++u) {
+                        const bf8_t ah = lds_colfrag(Crh + ks * 32 * ldR, ldR, (rb0 + u) * 16, lane);
+                        const bf8_t al = lds_colfrag(Crl + ks * 32 * ldR, ldR, (rb0 + u) * 16, lane);
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int jj = 0; jj < 2; ++jj) {
+                            f4_t acc = accP[u * 2 + jj];
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, yh[jj], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yl[jj], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yh[jj], acc, 0, 0, 0);
+                            accP[u * 2 + jj] = acc;
+                        }
+                    }
+                }
+            }
+            lds_barrier();
+            store_tile(t + nwg);
+            fetch(t + 2 * nwg);
+            lds_barrier();
+        }
+    }
+    float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+        const int jp = w & 1, rb = (w >> 1) * NIT + u;
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rb * 16 + 4 * (lane >> 4) + v;
+                const int col = (2 * jp + jj) * 16 + (lane & 15);
+                gst(outP + row + (size_t)col * NP, accP[u * 2 + jj][v]);
+            }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// k_gram_kept: G = Y^T Y of the kept sketch (rows x lx FP32, lx <= 64,
+// column-major with leading dimension ldy; rows and ldy multiples of 4 and a
+// 16-byte aligned base).  Every kept value is a BF16 pair (hi + lo exactly,
+// as k_split64 writes it), so the four pair products are exact in FP32; they
+// are summed in FP32 within a 64-row tile and in FP64 across tiles.  Work-
+// group g takes tiles g, g + nwg, ... (256 threads; the next tile's loads are
+// in flight while the current one is multiplied) and writes its 64 x 64 FP64
+// sum (entries past lx zero) to part + g 64 64.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gram_kept(const float* Y, int64_t rows, int64_t ldy, int lx, int64_t tiles,
+                                                   int nwg, double* part) {
+    constexpr int TM = 64, ldT = TM + 8;
+    __shared__ __align__(16) uint16_t Th[FU_LB * ldT];
+    __shared__ __align__(16) uint16_t Tl[FU_LB * ldT];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = blockIdx.x;
+    if (g >= nwg) return;
+    // loads: row group rg (4 rows), columns cg + 16 q, q < 4
+    const int rg = tid & 15, cg = tid >> 4;
+    const float* colp[4];
+    bool colv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = cg + 16 * q;
+        colv[q] = c < lx;
+        colp[q] = Y + (size_t)(c < lx ? c : lx - 1) * (size_t)ldy;
+    }
+    f4_t pf[4];
+    auto fetch = [&](int64_t t) {
+        const int64_t row = t * TM + rg * 4;
+        const int64_t rc = row < rows ? row : rows - 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pf[q] = gld4(colp[q] + rc);
+    };
+    double gs[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gs[j][v] = 0.0;
+    int64_t t = g;
+    if (t < tiles) fetch(t);
+    for (; t < tiles; t += nwg) {
+        const bool rv = t * TM + rg * 4 < rows;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const f4_t v = (colv[q] && rv) ? pf[q] : f4_t{0.f, 0.f, 0.f, 0.f};
+            uint32_t h0, l0, h1, l1;
+            split_bf16x2(v[0], v[1], &h0, &l0);
+            split_bf16x2(v[2], v[3], &h1, &l1);
+            const int c = cg + 16 * q;
+            *(uint64_t*)&Th[c * ldT + rg * 4] = (uint64_t)h0 | ((uint64_t)h1 << 32);
+            *(uint64_t*)&Tl[c * ldT + rg * 4] = (uint64_t)l0 | ((uint64_t)l1 << 32);
+        }
+        if (t + nwg < tiles) fetch(t + nwg);
+        lds_barrier();
+        // wave w: block row w against block columns 0..3
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            f4_t acc = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int ao = (w * 16 + (lane & 15)) * ldT + ks * 32 + 8 * (lane >> 4);
+                const int bo = (j * 16 + (lane & 15)) * ldT + ks * 32 + 8 * (lane >> 4);
+                const bf8_t ah = lds_b128(&Th[ao]), al = lds_b128(&Tl[ao]);
+                const bf8_t bh = lds_b128(&Th[bo]), bl = lds_b128(&Tl[bo]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gs[j][v] += (double)acc[v];
+        }
+        lds_barrier();
+    }
+    double* out = part + (size_t)g * FU_LB * FU_LB;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = w * 16 + 4 * (lane >> 4) + v;
+            const int col = j * 16 + (lane & 15);
+            gstd(out + row + (size_t)col * FU_LB, gs[j][v]);
         }
 }
 
@@ -1615,6 +1945,41 @@ hipError_t launch_final_split(const FusedArgs& a, hipStream_t st) {
     FS(2) FS(4) FS(6) FS(8) FS(10) FS(12)
 #undef FS
     return hipErrorInvalidValue;
+}
+
+static size_t splitpass64_lds(int np) {
+    // hi / lo tile (64 rows), Y hi / lo, X_lo (16-bit each)
+    return ((size_t)2 * 64 * (np + 8) + (size_t)2 * FU_LB * (64 + 8) + (size_t)FU_LB * (np + 8)) * 2;
+}
+
+bool split64_plan(int n, FusedPlan* p) {
+    for (int nks : kSplitNks) {
+        if (nks * 32 < n || nks > 10) continue;
+        p->np = nks * 32;
+        p->tm = 64;
+        p->lds = splitpass64_lds(p->np);
+        return p->lds <= 160 * 1024;
+    }
+    return false;
+}
+
+hipError_t launch_split64(const FusedArgs& a, hipStream_t st) {
+    if (a.tm != 64 || a.np % 64 || a.nlb != 1 || !a.vec || a.yout == nullptr) return hipErrorInvalidValue;
+    const size_t lds = splitpass64_lds(a.np);
+    const int nks = a.np / 32;
+#define SP(NKS_) \
+    if (nks == NKS_) return launch_512(k_split64<NKS_>, a, lds, st);
+    SP(2) SP(4) SP(6) SP(8) SP(10)
+#undef SP
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gram_kept(const float* Y, int64_t rows, int64_t ldy, int lx, int nwg, double* part, hipStream_t st) {
+    if (lx < 1 || lx > FU_LB || rows < 4 || (rows % 4) || (ldy % 4) || ((uintptr_t)Y & 15) || nwg < 1)
+        return hipErrorInvalidValue;
+    const int64_t tiles = (rows + 63) / 64;
+    hipLaunchKernelGGL(k_gram_kept, dim3(nwg), dim3(256), 0, st, Y, rows, ldy, lx, tiles, nwg, part);
+    return hipGetLastError();
 }
 
 template <int MODE, bool VEC>

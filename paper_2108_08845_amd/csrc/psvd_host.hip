@@ -107,6 +107,7 @@ void gen_omega(uint64_t seed, int64_t batch, int64_t n, int64_t l, int rounding,
     for (auto& x : th) x.join();
 }
 
+// Test-matrix entries: FP64 as drawn, FP32, or BF16 (the mixed and BF16 precisions).
 int omega_rounding(int precision) { return precision == PSVD_PREC_FP64 ? 0 : (precision == PSVD_PREC_FP32 ? 1 : 2); }
 
 const char* status_name(int s) {
@@ -125,12 +126,21 @@ const char* status_name(int s) {
     }
 }
 
-// Device allocation that grows on demand.
+// Device allocation that grows on demand.  A borrowed buffer (a region of
+// memory the handle does not own) never allocates or frees: a request beyond
+// its size fails with hipErrorOutOfMemory.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;
+    void borrow(void* q, size_t b) {
+        p = q;
+        bytes = b;
+        borrowed = true;
+    }
     hipError_t ensure(size_t b) {
         if (b <= bytes) return hipSuccess;
+        if (borrowed) return hipErrorOutOfMemory;
         if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
@@ -139,9 +149,10 @@ struct DevBuf {
         return e;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !borrowed) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        borrowed = false;
     }
     template <class T>
     T* as() const { return (T*)p; }
@@ -227,9 +238,14 @@ struct psvd_handle {
     std::vector<int64_t> parts, poff;
     int32_t r_local = 0;
     DevBuf pdesc;       // partition panels and row-chunk work lists of one update
+    DevBuf lrwork, lrom;   // low-rank SVD of the combined R: scratch, test matrix
 };
 
 static bool profiling(const psvd_handle* h) { return (h->opt.flags & PSVD_OPT_PROFILE) != 0; }
+
+static int handle_omega_rounding(const psvd_handle* h) {
+    return (h->opt.flags & PSVD_OPT_OMEGA_BF16) ? 2 : omega_rounding(h->opt.precision);
+}
 
 // Resolve the recorded event pairs (the stream must have passed them).
 static void prof_resolve(psvd_handle* h) {
@@ -331,6 +347,11 @@ static SmallLayout small_layout(double* base, int n, int l, int K) {
     return L;
 }
 
+// Work items of the generic tall products (times output blocks).
+static int split_items(const psvd_handle* h) { return h->opt.split_m > 0 ? h->opt.split_m : 1024; }
+// Width the fused passes are planned for (at least the panel's).
+static int plan_width(const psvd_handle* h, int n) { return std::max(n, (int)h->opt.panel_width); }
+
 // Work-groups of a fused pass: wg_per_cu per compute unit (256 CUs), at most one per tile.
 // The lift has no partial sums; by default it runs as many work-groups per CU
 // as its LDS allows (up to 4), so more tile loads are in flight.
@@ -351,14 +372,15 @@ static int ensure_workspace(psvd_handle* h, int n) {
     // k_tn partials: items x output blocks stays near 1024 (see pick_chunk)
     int nb = ceil_div(w, 64);
     size_t nob = (size_t)nb * nb;
-    HIPCHK(h, h->part.ensure((size_t)(2048 + 2 * nob) * 64 * 64 * sizeof(double)));
+    HIPCHK(h, h->part.ensure((size_t)(2 * std::max(1024, split_items(h)) + 2 * nob) * 64 * 64 * sizeof(double)));
     // fused-pass partials: one NP x 64 block per (work-group, column block)
-    int np = ((n + 63) / 64) * 64;
+    const int pw = plan_width(h, n);
+    int np = ((pw + 63) / 64) * 64;
     FusedPlan sp;
     for (int tr : {0, 32})
-        if (sketch_plan(n, tr, &sp)) np = std::max(np, sp.np);
-    if (fused_plan(n, h->opt.tile_rows, &sp)) np = std::max(np, sp.np);
-    if (split_plan(n, &sp)) np = std::max(np, sp.np);
+        if (sketch_plan(pw, tr, &sp)) np = std::max(np, sp.np);
+    if (fused_plan(pw, h->opt.tile_rows, &sp)) np = std::max(np, sp.np);
+    if (split_plan(pw, &sp)) np = std::max(np, sp.np);
     int nlb = ceil_div(std::max(l, 1), 64);
     const size_t wgs = (size_t)fused_wgs(h, INT64_MAX);
     HIPCHK(h, h->partP.ensure(wgs * nlb * np * 64 * sizeof(float)));
@@ -370,9 +392,9 @@ static int ensure_workspace(psvd_handle* h, int n) {
 // ----------------------------------------------------------------------------
 // Panel helpers (launch + fixed-order reduction into a dense FP64 result).
 // ----------------------------------------------------------------------------
-static int64_t pick_chunk(int64_t rows, int nob, int tm) {
-    int64_t target = std::max<int64_t>(1, 1024 / std::max(1, nob));
-    target = std::min<int64_t>(target, 1024);
+static int64_t pick_chunk(int64_t rows, int nob, int tm, int items = 1024) {
+    int64_t target = std::max<int64_t>(1, items / std::max(1, nob));
+    target = std::min<int64_t>(target, items);
     int64_t chunk = (rows + target - 1) / target;
     chunk = ((chunk + tm - 1) / tm) * tm;
     return std::max<int64_t>(chunk, tm);
@@ -383,7 +405,7 @@ static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool
                       const double* row_scale, int nscale, const int32_t* skip, int skip_mask) {
     const int mbl = ceil_div(L.ncols, 64), mbr = ceil_div(R.ncols, 64);
     const int nob = sym ? mbl * (mbl + 1) / 2 : mbl * mbr;
-    int64_t chunk = pick_chunk(L.rows, nob, 64);
+    int64_t chunk = pick_chunk(L.rows, nob, 64, split_items(h));
     int nitems = ceil_div(L.rows, chunk);
     TnArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -423,7 +445,7 @@ static int nn_product(psvd_handle* h, const PanelSeg& S, const double* X, int64_
                       const double* row_scale, int nscale, const int32_t* skip, int skip_mask,
                       int cls = PSVD_KC_NN, int need_mask = 0, int accumulate = 0) {
     int nbx = ceil_div(nx, 64);
-    int64_t chunk = pick_chunk(S.rows, nbx, 64);
+    int64_t chunk = pick_chunk(S.rows, nbx, 64, split_items(h));
     int nitems = ceil_div(S.rows, chunk);
     NnArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -542,6 +564,24 @@ const char* psvd_status_string(int status) { return status_name(status); }
 
 const char* psvd_last_error(const psvd_handle* h) { return h ? h->err.c_str() : g_call_err.c_str(); }
 
+static bool tuning_ok(int32_t tile_rows, int32_t wg_per_cu, int32_t panel_width, int32_t split_m) {
+    return (tile_rows == 0 || tile_rows == 16 || tile_rows == 32 || tile_rows == 64) && wg_per_cu >= 0 &&
+           wg_per_cu <= FU_MAX_WG / 256 && panel_width >= 0 && panel_width <= 640 && split_m >= 0 &&
+           split_m <= 8192 && (split_m == 0 || split_m >= 8);
+}
+
+int psvd_set_tuning(psvd_handle* h, int32_t tile_rows, int32_t wg_per_cu, int32_t panel_width, int32_t split_m) {
+    if (!h || !tuning_ok(tile_rows, wg_per_cu, panel_width, split_m)) return PSVD_E_INVAL;
+    if (int rc = sync_async(h)) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));   // no update in flight uses the workspace
+    h->opt.tile_rows = tile_rows;
+    h->opt.wg_per_cu = wg_per_cu;
+    h->opt.panel_width = panel_width;
+    h->opt.split_m = split_m;
+    h->nmax = 0;   // the workspace is re-sized for the new plans at the next update
+    return PSVD_OK;
+}
+
 int psvd_initialize(psvd_handle** out, int64_t M, int32_t K, double ff, int32_t oversampling, int32_t power_iters,
                     const psvd_options* opt) {
     if (!out) return PSVD_E_INVAL;
@@ -552,9 +592,8 @@ int psvd_initialize(psvd_handle** out, int64_t M, int32_t K, double ff, int32_t 
     if (o.max_sweeps <= 0) o.max_sweeps = 60;
     if (M < 1 || K < 1 || K > M || !(ff > 0.0 && ff <= 1.0) || oversampling < 0 || power_iters < 0 ||
         (o.method != PSVD_DETERMINISTIC && o.method != PSVD_RANDOMIZED) ||
-        (o.precision < PSVD_PREC_FP64 || o.precision > PSVD_PREC_MIXED) ||
-        (o.tile_rows != 0 && o.tile_rows != 16 && o.tile_rows != 32 && o.tile_rows != 64) ||
-        o.wg_per_cu < 0 || o.wg_per_cu > FU_MAX_WG / 256)
+        (o.precision < PSVD_PREC_FP64 || o.precision > PSVD_PREC_BF16) ||
+        !tuning_ok(o.tile_rows, o.wg_per_cu, o.panel_width, o.split_m))
         return PSVD_E_INVAL;
     psvd_handle* h = new (std::nothrow) psvd_handle();
     if (!h) return PSVD_E_NOMEM;
@@ -609,6 +648,8 @@ void psvd_finalize(psvd_handle* h) {
     h->d.release();
     h->part.release();
     h->pdesc.release();
+    h->lrwork.release();
+    h->lrom.release();
     h->partP.release();
     h->partG.release();
     h->tall.release();
@@ -640,7 +681,7 @@ int psvd_rank(const psvd_handle* h, int32_t* r) {
 
 int psvd_get_omega(const psvd_handle* h, int64_t batch, int64_t n, double* out) {
     if (!h || !out || batch < 0 || n < 1 || h->ell < 1) return PSVD_E_INVAL;
-    gen_omega(h->opt.seed, batch, n, h->ell, omega_rounding(h->opt.precision), out);
+    gen_omega(h->opt.seed, batch, n, h->ell, handle_omega_rounding(h), out);
     return PSVD_OK;
 }
 
@@ -728,10 +769,9 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
     double* s_cur = h->s[cur].as<double>();
     double* s_new = h->s[nxt].as<double>();
 
-    HIPCHK(h, hipEventRecord(h->ev0, st));
-    if (!randomized) {   // the randomized start does both in one launch (k_rand_begin)
-        HIPCHK(h, hipMemsetAsync(dstat, 0, 8, st));
-        HIPCHK(h, launch_make_scale(h->d.as<double>(), s_cur, r, h->ff, st));
+    if (h->ev0) HIPCHK(h, hipEventRecord(h->ev0, st));
+    if (!randomized) {   // status cleared and d = ff s (the randomized start does this in k_rand_begin)
+        HIPCHK(h, launch_make_scale(dstat, h->d.as<double>(), s_cur, r, h->ff, st));
     }
 
     // Panel [U | A] (unscaled) and its lift output.
@@ -810,44 +850,75 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         // a copy stream into one of two device buffers, so the copy overlaps the
         // previous update; the main stream waits for it before k_rand_begin.
         size_t need = (size_t)n * l;
-        const int ob = (int)(h->batch & 1);
-        if (need > h->omega_host_cap) {
-            HIPCHK(h, hipStreamSynchronize(st));
-            HIPCHK(h, hipStreamSynchronize(h->cstream));
-            for (int b = 0; b < 2; ++b) {
-                if (h->omega_host[b]) (void)hipHostFree(h->omega_host[b]);
-                h->omega_host[b] = nullptr;
-            }
-            h->omega_host_cap = 0;
-            for (int b = 0; b < 2; ++b) {
-                HIPCHK(h, hipHostMalloc((void**)&h->omega_host[b], need * sizeof(double), hipHostMallocDefault));
-                HIPCHK(h, h->omega_dev[b].ensure(need * sizeof(double)));
-            }
-            h->omega_host_cap = need;
+        const int ob = h->cstream ? (int)(h->batch & 1) : 0;
+        if (!h->cstream) {
+            // a handle without a copy stream (the allocation-free entry point): the
+            // test matrix is generated into its fixed host buffer on this thread and
+            // uploaded on the main stream
+            if (need > h->omega_host_cap || need * sizeof(double) > h->omega_dev[0].bytes)
+                return fail(h, PSVD_E_NOMEM, "test matrix larger than its fixed buffers");
+            gen_omega_range(h->opt.seed, h->batch, (int64_t)need, handle_omega_rounding(h), h->omega_host[0], 0,
+                            ((int64_t)need + 1) / 2);
+            HIPCHK(h, hipMemcpyAsync(h->omega_dev[0].p, h->omega_host[0], need * sizeof(double), hipMemcpyHostToDevice,
+                                     st));
         } else {
-            // the upload two batches back may still be reading this host buffer
-            HIPCHK(h, hipEventSynchronize(h->omega_ev[ob]));
+            if (need > h->omega_host_cap) {
+                HIPCHK(h, hipStreamSynchronize(st));
+                HIPCHK(h, hipStreamSynchronize(h->cstream));
+                for (int b = 0; b < 2; ++b) {
+                    if (h->omega_host[b]) (void)hipHostFree(h->omega_host[b]);
+                    h->omega_host[b] = nullptr;
+                }
+                h->omega_host_cap = 0;
+                for (int b = 0; b < 2; ++b) {
+                    HIPCHK(h, hipHostMalloc((void**)&h->omega_host[b], need * sizeof(double), hipHostMallocDefault));
+                    HIPCHK(h, h->omega_dev[b].ensure(need * sizeof(double)));
+                }
+                h->omega_host_cap = need;
+            } else {
+                // the upload two batches back may still be reading this host buffer
+                HIPCHK(h, hipEventSynchronize(h->omega_ev[ob]));
+            }
+            gen_omega(h->opt.seed, h->batch, n, l, handle_omega_rounding(h), h->omega_host[ob]);
+            // the device buffer is free once the update two batches back has read it
+            HIPCHK(h, hipStreamWaitEvent(h->cstream, h->omega_used[ob], 0));
+            HIPCHK(h, hipMemcpyAsync(h->omega_dev[ob].p, h->omega_host[ob], need * sizeof(double),
+                                     hipMemcpyHostToDevice, h->cstream));
+            HIPCHK(h, hipEventRecord(h->omega_ev[ob], h->cstream));
+            HIPCHK(h, hipStreamWaitEvent(st, h->omega_ev[ob], 0));
         }
-        gen_omega(h->opt.seed, h->batch, n, l, omega_rounding(prec), h->omega_host[ob]);
-        // the device buffer is free once the update two batches back has read it
-        HIPCHK(h, hipStreamWaitEvent(h->cstream, h->omega_used[ob], 0));
-        HIPCHK(h, hipMemcpyAsync(h->omega_dev[ob].p, h->omega_host[ob], need * sizeof(double), hipMemcpyHostToDevice,
-                                 h->cstream));
-        HIPCHK(h, hipEventRecord(h->omega_ev[ob], h->cstream));
-        HIPCHK(h, hipStreamWaitEvent(st, h->omega_ev[ob], 0));
         // status cleared, d = ff s, X' = D Omega
         HIPCHK(h, launch_rand_begin(dstat, h->d.as<double>(), s_cur, r, h->ff, L.X, h->omega_dev[ob].as<double>(), n,
                                     l, st));
-        HIPCHK(h, hipEventRecord(h->omega_used[ob], st));
+        if (h->cstream) HIPCHK(h, hipEventRecord(h->omega_used[ob], st));
         const int nlb = ceil_div(l, 64);
-        auto pass = [&](bool bf16, bool want_g) -> int {
-            // P = D C'^T (C' X')  [+ G_Y = Y^T Y]
-            // final pass of the mixed precision: split-BF16 products (FP32-accurate)
+        // Fused passes, one read of the panel each: P = D C'^T (C' X') and, in
+        // the final pass, the kept Y = C' X' and G_Y = Y^T Y.
+        //   mixed: power passes on the FP32 matrix cores (k_fused); the final
+        //          pass on the BF16 matrix cores with every operand split into a
+        //          BF16 pair (k_split64), G_Y from the kept Y (k_gram_kept); FP32
+        //          matrix cores for the final pass on panels k_split64 does not take.
+        //          (Split pairs carry about 2^-17 relative error per operand; in
+        //          the power iterations that error reaches the tail of the sketch
+        //          amplified by (s_1 / s_j)^2, so those passes keep FP32 products.)
+        //   bf16:  power passes on plain BF16 operands (k_sketch_bf16), the final
+        //          pass split-BF16 with a BF16-rounded test matrix (k_final_split)
+        //   fp32:  FP32 matrix cores (k_fused);  fp64: the generic products
+        enum { UNFUSED, SPLIT64, SKETCH_BF16, FINAL_SPLIT, FUSED_F32 };
+        auto pass = [&](bool final_pass) -> int {
             FusedPlan fp;
-            const bool split = !bf16 && want_g && prec == PSVD_PREC_MIXED && nlb == 1 && split_plan(n, &fp);
-            const bool planned = split || (bf16 ? sketch_plan(n, h->opt.tile_rows, &fp) : fused_plan(n, h->opt.tile_rows, &fp));
-            bool fuse_ok = !fp64 && planned && seg_all_f32(C) && (!want_g || nlb == 1) && !(bf16 && want_g);
-            if (fuse_ok) {
+            int kind = UNFUSED;
+            const bool vec = seg_vec_ok(C, false);
+            const int pw = plan_width(h, n);
+            if (!fp64 && seg_all_f32(C)) {
+                if (prec == PSVD_PREC_MIXED && final_pass && nlb == 1 && vec && M >= 4 && split64_plan(pw, &fp))
+                    kind = SPLIT64;
+                else if (prec == PSVD_PREC_BF16 && !final_pass && sketch_plan(pw, h->opt.tile_rows, &fp))
+                    kind = SKETCH_BF16;
+                else if (prec == PSVD_PREC_BF16 && final_pass && nlb == 1 && split_plan(pw, &fp)) kind = FINAL_SPLIT;
+                else if ((!final_pass || nlb == 1) && fused_plan(pw, h->opt.tile_rows, &fp)) kind = FUSED_F32;
+            }
+            if (kind != UNFUSED) {
                 FusedArgs fa;
                 std::memset(&fa, 0, sizeof(fa));
                 fa.seg = C;
@@ -862,17 +933,26 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 fa.nwg = fused_wgs(h, fa.tiles);
                 fa.partP = h->partP.as<float>();
                 fa.partG = h->partG.as<double>();
-                fa.want_g = want_g ? 1 : 0;
-                fa.vec = seg_vec_ok(C, false) ? 1 : 0;
-                if (want_g) {   // keep Y = C X for the lift (U = Y R_Y^-1 U~_K)
+                fa.want_g = (final_pass && kind != SPLIT64) ? 1 : 0;
+                fa.vec = vec ? 1 : 0;
+                if (final_pass) {   // keep Y = C X for the lift (U = Y R_Y^-1 U~_K)
                     fa.yout = h->tall.as<float>();
                     fa.ldy = M;
                 }
-                int pe = prof_begin(h, bf16 ? PSVD_KC_FUSED_BF16 : PSVD_KC_FUSED_F32);
-                if (bf16) HIPCHK(h, launch_sketch_bf16(fa, st));
-                else if (split) HIPCHK(h, launch_final_split(fa, st));
-                else HIPCHK(h, launch_fused(want_g ? 1 : 0, fa, st));
+                const int cls = kind == SKETCH_BF16 ? PSVD_KC_FUSED_BF16
+                                : (kind == SPLIT64 || kind == FINAL_SPLIT) ? PSVD_KC_SPLIT : PSVD_KC_FUSED_F32;
+                int pe = prof_begin(h, cls);
+                if (kind == SPLIT64) HIPCHK(h, launch_split64(fa, st));
+                else if (kind == SKETCH_BF16) HIPCHK(h, launch_sketch_bf16(fa, st));
+                else if (kind == FINAL_SPLIT) HIPCHK(h, launch_final_split(fa, st));
+                else HIPCHK(h, launch_fused(final_pass ? 1 : 0, fa, st));
                 prof_end(h, pe);
+                if (kind == SPLIT64) {
+                    // G_Y from the kept Y, one partial per work-group of the pass
+                    int pg = prof_begin(h, PSVD_KC_TN);
+                    HIPCHK(h, launch_gram_kept(fa.yout, M, M, l, fa.nwg, fa.partG, st));
+                    prof_end(h, pg);
+                }
                 FusedReduceArgs ra;
                 std::memset(&ra, 0, sizeof(ra));
                 ra.row_scale = dsc;
@@ -884,7 +964,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 ra.np = fa.np;
                 ra.n = n;
                 ra.lx = l;
-                ra.want_g = fa.want_g;
+                ra.want_g = final_pass ? 1 : 0;
                 ra.P = L.P;
                 ra.G = L.G_Y;
                 HIPCHK(h, launch_fused_reduce(ra, st));
@@ -901,16 +981,16 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
             seg_add(Y, make_block(h->tall.p, M, tall_dtype, l));
             rc2 = tn_product(h, C, Y, false, fp64, L.P, dsc, r, nullptr, 0);
             if (rc2) return rc2;
-            if (want_g) rc2 = tn_product(h, Y, Y, true, true, L.G_Y, nullptr, 0, nullptr, 0);
+            if (final_pass) rc2 = tn_product(h, Y, Y, true, true, L.G_Y, nullptr, 0, nullptr, 0);
             return rc2;
         };
         for (int it = 0; it < h->q; ++it) {
-            rc = pass(prec == PSVD_PREC_MIXED, false);
+            rc = pass(false);
             if (rc) return rc;
             rc = small_orth(h, L, n, l, L.X, dstat);   // X' = D orth(P)
             if (rc) return rc;
         }
-        rc = pass(false, true);
+        rc = pass(true);
         if (rc) return rc;
         // R_Y, Cholesky-QR2 of P, the small SVD and M2 in one work-group.
         RandFinalArgs rf;
@@ -922,10 +1002,10 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         // FP32 / mixed results carry FP32 rounding: the small SVD stops once a sweep's
         // cosines are below 2^-15 (the next sweep would leave ~2^-30); FP64 runs to m 2^-53
         rf.stop_cos2 = fp64 ? 0.0 : 0x1p-30;
-        // the R factor of P = C^T Y: Cholesky-QR2 in FP64 and FP32; one pass in the mixed
-        // precision, whose BF16 sketch dominates its error (the one-pass factor is off by
-        // about kappa(P)^2 2^-53, ~1e-6 on the smallest retained value of the c2 workload)
-        rf.qr_passes = prec == PSVD_PREC_MIXED ? 1 : 2;
+        // the R factor of P = C^T Y: Cholesky-QR2; one pass with BF16 power passes,
+        // whose sketch error dominates (the one-pass factor is off by about
+        // kappa(P)^2 2^-53, ~1e-6 on the smallest retained value of the c2 workload)
+        rf.qr_passes = prec == PSVD_PREC_BF16 ? 1 : 2;
         rf.P = L.P;
         rf.P1 = L.P1;
         rf.GY = L.G_Y;
@@ -955,7 +1035,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         rc = lift_product(h, Ys, L.M2, l, rk, fp64, nullptr, 0, 0);
         if (rc) return rc;
     }
-    HIPCHK(h, hipEventRecord(h->ev1, st));
+    if (h->ev1) HIPCHK(h, hipEventRecord(h->ev1, st));
     const int prev_r = h->r;
     const int64_t prev_batch = h->batch;
     h->cur = nxt;
@@ -979,7 +1059,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         h->stats.last_sweeps = h->status_host[1];
         if (sv & DEV_FALLBACK) h->stats.fallbacks += 1;
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->stats.last_update_ms = ms;
+        if (h->ev0 && hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->stats.last_update_ms = ms;
         int code = finish_status(h, sv);
         if (code != PSVD_OK) {
             h->cur = cur;
@@ -1063,6 +1143,77 @@ __global__ void k_div_cols(const double* VS, int64_t n, int r, const double* s, 
     else ((float*)V)[i + (size_t)j * ldv] = (float)v;
 }
 
+int call_fail(int code, const char* msg);
+}  // namespace
+
+int psvd::set_call_error(int code, const char* msg) { return call_fail(code, msg); }
+
+void psvd::host_omega(uint64_t seed, int64_t batch, int64_t n, int64_t l, int rounding, double* out) {
+    gen_omega(seed, batch, n, l, rounding, out);
+}
+
+namespace {
+int call_fail(int code, const char* msg) {
+    g_call_err = std::string(status_name(code)) + ": " + msg;
+    return code;
+}
+
+int rsvd_check(const void* A, int64_t M, int64_t N, int64_t lda, int32_t K, int32_t oversampling, int32_t power_iters,
+               const void* U, int64_t ldu, const void* V, int64_t ldv, int32_t out_dtype) {
+    if (!A || M < 1 || N < 1 || K < 1 || K > std::min<int64_t>(M, N) || oversampling < 0 || power_iters < 0)
+        return call_fail(PSVD_E_INVAL, "invalid sizes or null data");
+    if (lda < M || (U && ldu < M) || (V && ldv < N)) return call_fail(PSVD_E_SHAPE, "leading dimension too small");
+    if (out_dtype != PSVD_F32 && out_dtype != PSVD_F64) return call_fail(PSVD_E_DTYPE, "unknown output dtype");
+    return PSVD_OK;
+}
+
+// Partial-sum blocks (64 x 64 FP64 each) that tn_product writes for a
+// reduction over `rows` rows into `nob` output blocks.
+size_t tn_part_bytes(int64_t rows, int nob) {
+    const int64_t chunk = pick_chunk(rows, nob, 64);
+    const int64_t nitems = (rows + chunk - 1) / chunk;
+    return (size_t)nitems * nob * 64 * 64 * sizeof(double);
+}
+
+// The one-shot randomized SVD on a handle made for it (Eqs. 7-11): one update
+// of the empty stream, then the modes (copied unless u_in_place: the update
+// lifted straight into the caller's U), V = A^T U diag(1 / s) through the
+// device buffer vs, and the singular values.
+int rsvd_body(psvd_handle* h, const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype, void* U, int64_t ldu,
+              bool u_in_place, void* V, int64_t ldv, int32_t out_dtype, double* s, int32_t* rank, DevBuf& vs) {
+    int rc = psvd_incorporate_data(h, A, M, N, lda, a_dtype);
+    if (rc) return rc;
+    const int r = h->r;
+    if (rank) *rank = r;
+    if (U && !u_in_place) {
+        rc = psvd_modes(h, U, ldu, out_dtype);
+        if (rc) return rc;
+    }
+    if (V) {
+        // V_K = A^T U_K diag(1 / s): the right factor of Eqs. (9)-(11), since
+        // A^T Q U~ = B^T U~ = V~ S for B = Q^T A.
+        PanelSeg L = make_seg(M);
+        seg_add(L, make_block(A, lda, a_dtype, (int)N));
+        PanelSeg R = make_seg(M);
+        seg_add(R, make_block(h->U[h->cur].p, h->ldu, h->u_dtype, r));
+        if (vs.ensure((size_t)N * r * sizeof(double)) != hipSuccess) return fail(h, PSVD_E_NOMEM, "V workspace");
+        if (h->part.ensure(tn_part_bytes(M, ceil_div((int)N, 64) * ceil_div(r, 64))) != hipSuccess)
+            return fail(h, PSVD_E_NOMEM, "partials");
+        rc = tn_product(h, L, R, false, h->opt.precision == PSVD_PREC_FP64, vs.as<double>(), nullptr, 0, nullptr, 0);
+        if (rc) return rc;
+        const int64_t tot = N * r;
+        hipLaunchKernelGGL(k_div_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream, vs.as<double>(), N,
+                           r, h->s[h->cur].as<double>(), V, ldv, out_dtype);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    if (s) {
+        rc = psvd_singular_values(h, s, h->K, nullptr);
+        if (rc) return rc;
+    }
+    return PSVD_OK;
+}
+
 constexpr char kStateMagic[8] = {'P', 'S', 'V', 'D', 'S', 'T', '0', '1'};
 
 struct StateHeader {
@@ -1085,14 +1236,7 @@ int psvd_rsvd(const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype,
               int32_t power_iters, uint64_t seed, int32_t precision, void* U, int64_t ldu, void* V, int64_t ldv,
               int32_t out_dtype, double* s, int32_t* rank, void* stream) {
     g_call_err.clear();
-    auto bad = [](int code, const char* msg) {
-        g_call_err = std::string(status_name(code)) + ": " + msg;
-        return code;
-    };
-    if (!A || M < 1 || N < 1 || K < 1 || K > std::min<int64_t>(M, N) || oversampling < 0 || power_iters < 0)
-        return bad(PSVD_E_INVAL, "invalid sizes or null data");
-    if (lda < M || (U && ldu < M) || (V && ldv < N)) return bad(PSVD_E_SHAPE, "leading dimension too small");
-    if (out_dtype != PSVD_F32 && out_dtype != PSVD_F64) return bad(PSVD_E_DTYPE, "unknown output dtype");
+    if (int rc = rsvd_check(A, M, N, lda, K, oversampling, power_iters, U, ldu, V, ldv, out_dtype)) return rc;
     psvd_options o;
     psvd_default_options(&o);
     o.method = PSVD_RANDOMIZED;
@@ -1101,49 +1245,143 @@ int psvd_rsvd(const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype,
     o.stream = stream;
     psvd_handle* h = nullptr;
     int rc = psvd_initialize(&h, M, K, 1.0, oversampling, power_iters, &o);
-    if (rc) return bad(rc, "initialisation failed");
-    auto finish = [&](int code) {
-        if (code) g_call_err = h->err;
-        psvd_finalize(h);
-        return code;
-    };
-    rc = psvd_incorporate_data(h, A, M, N, lda, a_dtype);
-    if (rc) return finish(rc);
-    const int r = h->r;
-    if (rank) *rank = r;
-    if (U) {
-        rc = psvd_modes(h, U, ldu, out_dtype);
-        if (rc) return finish(rc);
-    }
-    if (V) {
-        // V_K = A^T U_K diag(1 / s): the right factor of Eqs. (9)-(11), since
-        // A^T Q U~ = B^T U~ = V~ S for B = Q^T A.
-        PanelSeg L = make_seg(M);
-        seg_add(L, make_block(A, lda, a_dtype, (int)N));
-        PanelSeg R = make_seg(M);
-        seg_add(R, make_block(h->U[h->cur].p, h->ldu, h->u_dtype, r));
-        DevBuf vs;
-        struct Release {
-            DevBuf& b;
-            ~Release() { b.release(); }
-        } release_vs{vs};
-        if (vs.ensure((size_t)N * r * sizeof(double)) != hipSuccess) return finish(fail(h, PSVD_E_NOMEM, "V workspace"));
-        const size_t need = (size_t)(2048 + 2 * (size_t)ceil_div((int)N, 64) * ceil_div(r, 64)) * 64 * 64 * sizeof(double);
-        if (h->part.ensure(need) != hipSuccess) return finish(fail(h, PSVD_E_NOMEM, "partials"));
-        rc = tn_product(h, L, R, false, precision == PSVD_PREC_FP64, vs.as<double>(), nullptr, 0, nullptr, 0);
-        if (rc) return finish(rc);
-        const int64_t tot = N * r;
-        hipLaunchKernelGGL(k_div_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream, vs.as<double>(), N,
-                           r, h->s[h->cur].as<double>(), V, ldv, out_dtype);
-        if (hipGetLastError() != hipSuccess) return finish(fail(h, PSVD_E_DEVICE, "V scaling launch"));
-        if (hipStreamSynchronize(h->stream) != hipSuccess) return finish(fail(h, PSVD_E_DEVICE, "V scaling"));
-    }
-    if (s) {
-        rc = psvd_singular_values(h, s, K, nullptr);
-        if (rc) return finish(rc);
-    }
-    return finish(PSVD_OK);
+    if (rc) return call_fail(rc, "initialisation failed");
+    DevBuf vs;
+    rc = rsvd_body(h, A, M, N, lda, a_dtype, U, ldu, false, V, ldv, out_dtype, s, rank, vs);
+    if (rc) g_call_err = h->err;
+    vs.release();
+    psvd_finalize(h);
+    return rc;
 }
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// The one-shot randomized SVD on fixed buffers: every piece of device memory
+// the update needs (partial sums, small matrices, the kept sketch, the test
+// matrix, the status word, V's workspace and, when the caller passes no U, the
+// modes) is carved from one caller-given device region, and the host side uses
+// fixed host buffers; nothing is allocated.  The update lifts the modes straight
+// into the caller's U (its element type must be the state's).
+// ----------------------------------------------------------------------------
+namespace psvd {
+
+int rsvd_fixed(const FixedBuffers& fb, const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype, int32_t K,
+               int32_t oversampling, int32_t power_iters, uint64_t seed, int32_t precision, void* U, int64_t ldu,
+               void* V, int64_t ldv, int32_t out_dtype, double* s, int32_t* rank, void* stream) {
+    g_call_err.clear();
+    if (int rc = rsvd_check(A, M, N, lda, K, oversampling, power_iters, U, ldu, V, ldv, out_dtype)) return rc;
+    if (precision < PSVD_PREC_FP64 || precision > PSVD_PREC_BF16) return call_fail(PSVD_E_INVAL, "unknown precision");
+    const int32_t u_dtype = precision == PSVD_PREC_FP64 ? PSVD_F64 : PSVD_F32;
+    if (a_dtype != PSVD_F32 && a_dtype != PSVD_F64) return call_fail(PSVD_E_DTYPE, "unknown dtype");
+    if (a_dtype == PSVD_F64 && u_dtype != PSVD_F64) return call_fail(PSVD_E_DTYPE, "FP64 data needs FP64 precision");
+    if (U && out_dtype != u_dtype)
+        return call_fail(PSVD_E_DTYPE, "the allocation-free call writes U in the precision's element type");
+    if (N > (1 << 20)) return call_fail(PSVD_E_SHAPE, "batch too wide");
+    const int esz = u_dtype == PSVD_F64 ? 8 : 4;
+    const int n = (int)N;
+    const int ell = K + oversampling;
+    const bool randomized = ell < n;
+    const int l = randomized ? ell : 0;
+    const int r = randomized ? std::min(K, l) : std::min(K, n);
+    const int w = std::max(n, ell);
+
+    // Sizes exactly as the update requests them (ensure_workspace and the
+    // tall temporary), the V workspace and, without a caller U, the modes.
+    size_t part = tn_part_bytes(M, ceil_div(w, 64) * (ceil_div(w, 64) + 1) / 2);
+    part = std::max(part, tn_part_bytes(M, ceil_div(n, 64) * ceil_div(std::max(l, 1), 64)));
+    if (V) part = std::max(part, tn_part_bytes(M, ceil_div(n, 64) * ceil_div(r, 64)));
+    int np = ((n + 63) / 64) * 64;
+    FusedPlan sp;
+    for (int tr : {0, 32})
+        if (sketch_plan(n, tr, &sp)) np = std::max(np, sp.np);
+    if (fused_plan(n, 0, &sp)) np = std::max(np, sp.np);
+    if (split_plan(n, &sp)) np = std::max(np, sp.np);
+    const size_t wgs = std::min<size_t>(256, FU_MAX_WG);   // work-groups of a fused pass (one per CU)
+    const size_t nlb = (size_t)ceil_div(std::max(ell, 1), 64);
+    const int64_t ldu_state = U ? ldu : ((M + 63) / 64) * 64;
+    const size_t need[] = {
+        small_layout(nullptr, n, ell, K).total * sizeof(double),   // 0 small matrices
+        (size_t)(w + 64) * sizeof(int32_t),                         // 1 int scratch
+        part,                                                       // 2 k_tn partials
+        wgs * nlb * np * 64 * sizeof(float),                        // 3 fused partials
+        wgs * 64 * 64 * sizeof(double),                             // 4 fused G partials
+        (size_t)M * (randomized ? ell : n) * esz,                   // 5 tall temporary
+        (size_t)n * std::max(ell, 1) * sizeof(double),              // 6 test matrix
+        3 * (size_t)K * sizeof(double),                             // 7 s (two) and d
+        64,                                                         // 8 status
+        V ? (size_t)n * r * sizeof(double) : 0,                     // 9 V workspace
+        U ? 0 : (size_t)ldu_state * K * esz,                        // 10 modes
+    };
+    constexpr int NB = (int)(sizeof(need) / sizeof(need[0]));
+    size_t off[NB], total = 0;
+    for (int i = 0; i < NB; ++i) {
+        off[i] = total;
+        total += (need[i] + 255) & ~(size_t)255;
+    }
+    if (total > fb.dev_bytes) {
+        char msg[160];
+        std::snprintf(msg, sizeof(msg), "needs %zu bytes of device scratch, the fixed maximum is %zu", total,
+                      fb.dev_bytes);
+        return call_fail(PSVD_E_NOMEM, msg);
+    }
+    if ((size_t)n * std::max(ell, 1) > fb.omega_host_entries)
+        return call_fail(PSVD_E_NOMEM, "test matrix larger than the fixed host buffer");
+
+    unsigned char* base = (unsigned char*)fb.dev;
+    auto region = [&](int i) { return (void*)(base + off[i]); };
+    psvd_handle hs;   // on the stack: no host allocation either
+    psvd_handle* h = &hs;
+    h->M = M;
+    h->K = K;
+    h->ff = 1.0;
+    h->p = oversampling;
+    h->q = power_iters;
+    h->ell = ell;
+    psvd_default_options(&h->opt);
+    h->opt.method = PSVD_RANDOMIZED;
+    h->opt.precision = precision;
+    h->opt.seed = seed;
+    h->opt.stream = stream;
+    h->stream = (hipStream_t)stream;
+    h->u_dtype = u_dtype;
+    h->ldu = ldu_state;
+    std::memset(&h->stats, 0, sizeof(h->stats));
+    if (hipGetDevice(&h->device) != hipSuccess) return call_fail(PSVD_E_DEVICE, "hipGetDevice");
+    void* ubuf = U ? U : region(10);
+    h->U[0].borrow(ubuf, (size_t)ldu_state * K * esz);   // r = 0: the update reads no previous modes
+    h->U[1].borrow(ubuf, (size_t)ldu_state * K * esz);
+    double* sd = (double*)region(7);
+    h->s[0].borrow(sd, K * sizeof(double));
+    h->s[1].borrow(sd + K, K * sizeof(double));
+    h->d.borrow(sd + 2 * K, K * sizeof(double));
+    h->small.borrow(region(0), need[0]);
+    h->ivec.borrow(region(1), need[1]);
+    h->part.borrow(region(2), need[2]);
+    h->partP.borrow(region(3), need[3]);
+    h->partG.borrow(region(4), need[4]);
+    h->tall.borrow(region(5), need[5]);
+    h->omega_dev[0].borrow(region(6), need[6]);
+    h->status.borrow(region(8), need[8]);
+    h->status_host = fb.status_host;
+    h->omega_host[0] = fb.omega_host;
+    h->omega_host_cap = fb.omega_host_entries;
+    h->nmax = n;   // the workspace above is sized for this panel
+    DevBuf vs;
+    vs.borrow(region(9), need[9]);
+    // The region keeps the previous call's contents.  Nothing needs clearing
+    // here: the update's first kernel zeroes the status words, the previous
+    // singular values are read only for r > 0 columns (none), and every partial
+    // sum, small matrix and tall temporary is written before it is read.
+    int rc = rsvd_body(h, A, M, N, lda, a_dtype, U, ldu, true, V, ldv, out_dtype, s, rank, vs);
+    if (rc) g_call_err = h->err;
+    (void)hipStreamSynchronize(h->stream);
+    return rc;
+}
+
+}  // namespace psvd
+
+extern "C" {
 
 int psvd_save_state(const psvd_handle* hc, void* buf, size_t cap, size_t* size) {
     psvd_handle* h = const_cast<psvd_handle*>(hc);
@@ -1303,8 +1541,7 @@ int grad_backward(GradCtx& g, const void* A, int64_t lda, double ff, const doubl
         const void* Ub = (const char*)g.Ust.p + (size_t)b * h->ldu * K * g.esz;
         const double* sb = g.sst.as<double>() + (size_t)b * K;
         const void* Ab = (const char*)A + (size_t)b * g.Nb * lda * g.esz;
-        HIPCHK(h, hipMemsetAsync(dstat, 0, 8, st));
-        HIPCHK(h, launch_make_scale(gd, sb, r, ff, st));
+        HIPCHK(h, launch_make_scale(dstat, gd, sb, r, ff, st));
         PanelSeg C = make_seg(g.M);
         if (r > 0) seg_add(C, make_block(Ub, h->ldu, g.dt, r));
         seg_add(C, make_block(Ab, lda, g.dt, (int)g.Nb));
@@ -1653,7 +1890,10 @@ int psvd_pstream_initialize(psvd_handle** out, int32_t P, const int64_t* M_parts
     psvd_options o;
     psvd_default_options(&o);
     if (opt) o = *opt;
-    if (o.method != PSVD_DETERMINISTIC || o.precision == PSVD_PREC_MIXED) return PSVD_E_INVAL;
+    if (o.precision == PSVD_PREC_MIXED || o.precision == PSVD_PREC_BF16) return PSVD_E_INVAL;
+    // PSVD_RANDOMIZED: the paper's placement of randomization in the parallel
+    // variant -- the SVD of W (initialisation) and of the combined R factor
+    // (updates) by the low-rank SVD with a K-column test matrix (ell = K)
     psvd_handle* h = nullptr;
     int rc = psvd_initialize(&h, M, K, ff, 0, 0, &o);
     if (rc) return rc;
@@ -1697,8 +1937,9 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
             ldu[i] = h->parts[i];
         }
         std::vector<double> lam(h->K);
-        int rc = psvd_apmos_batched(P, A_parts, h->parts.data(), ld_parts, N, dtype, rl, h->K, Up.data(), ldu.data(),
-                                    lam.data(), nullptr, st);
+        const int ell0 = h->ell > 0 ? h->K : 0;
+        int rc = apmos_internal(P, A_parts, h->parts.data(), ld_parts, N, dtype, rl, h->K, ell0, h->opt.seed, h->batch,
+                                Up.data(), ldu.data(), lam.data(), nullptr, st);
         if (rc) return fail(h, rc, std::string("APMOS initialisation: ") + psvd_status_string(rc));
         HIPCHK(h, hipMemcpyAsync(h->s[h->cur].p, lam.data(), sizeof(double) * h->K, hipMemcpyHostToDevice, st));
         HIPCHK(h, hipStreamSynchronize(st));
@@ -1723,8 +1964,7 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     double* s_cur = h->s[cur].as<double>();
     double* s_new = h->s[nxt].as<double>();
     HIPCHK(h, hipEventRecord(h->ev0, st));
-    HIPCHK(h, hipMemsetAsync(dstat, 0, 8, st));
-    HIPCHK(h, launch_make_scale(h->d.as<double>(), s_cur, r, h->ff, st));
+    HIPCHK(h, launch_make_scale(dstat, h->d.as<double>(), s_cur, r, h->ff, st));
     std::vector<PanelSeg> C = part_panels(h, r, A_parts, ld_parts, dtype, (int)N, h->U[cur].p, h->U[nxt].p);
     // Q1_i (tall temporary, partition i at rows poff[i] with leading dimension M_i)
     std::vector<PanelSeg> Q1(P), Qin(P);
@@ -1742,8 +1982,8 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     }
     // descriptors: [C panels | Q1 panels | C panels writing Q1 | Gram chunks | product chunks]
     const int mbl = ceil_div(n, 64), nob = mbl * (mbl + 1) / 2;
-    const std::vector<WorkItem> tit = part_items(h, pick_chunk(h->M, nob, 64));
-    const int64_t nchunk = pick_chunk(h->M, ceil_div(n, 64), 64);
+    const std::vector<WorkItem> tit = part_items(h, pick_chunk(h->M, nob, 64, split_items(h)));
+    const int64_t nchunk = pick_chunk(h->M, ceil_div(n, 64), 64, split_items(h));
     const std::vector<WorkItem> nit = part_items(h, nchunk);
     {
         const size_t bytes = sizeof(PanelSeg) * 3 * P + sizeof(WorkItem) * (tit.size() + nit.size());
@@ -1764,7 +2004,7 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     const PanelSeg* dQin = dQ + P;
     const WorkItem* dT = (const WorkItem*)(dQin + P);
     const WorkItem* dN = dT + tit.size();
-    const int64_t tchunk = pick_chunk(h->M, nob, 64);
+    const int64_t tchunk = pick_chunk(h->M, nob, 64, split_items(h));
     PartLists cg{dC, dT, (int)tit.size(), tchunk}, qg{dQ, dT, (int)tit.size(), tchunk};
     PartLists cn{dC, dN, (int)nit.size(), nchunk}, qn{dQ, dN, (int)nit.size(), nchunk};
     PartLists qin{dQin, dN, (int)nit.size(), nchunk};
@@ -1792,6 +2032,17 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     sa.ivec = h->ivec.as<int32_t>();
     sa.status = dstat;
     sa.sweeps = dstat + 1;
+    const bool low_rank = h->ell > 0;
+    const int ell = std::min(h->K, n);
+    sa.skip_svd = low_rank ? 1 : 0;
+    if (low_rank) {   // the batch's test matrix (n x ell, FP64 values) for the low-rank SVD of R
+        std::vector<double> om((size_t)n * ell);
+        gen_omega(h->opt.seed, h->batch, n, ell, 0, om.data());
+        HIPCHK(h, h->lrom.ensure(om.size() * sizeof(double)));
+        HIPCHK(h, h->lrwork.ensure(low_rank_work_doubles(n, n, ell) * sizeof(double)));
+        HIPCHK(h, hipMemcpyAsync(h->lrom.p, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(h, hipStreamSynchronize(st));   // the host vector goes out of scope
+    }
     {
         int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
         HIPCHK(h, launch_small_det1(sa, st));
@@ -1805,6 +2056,30 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     {
         int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
         HIPCHK(h, launch_small_det2(sa, st));
+        if (low_rank) {
+            // the low-rank SVD of R = R2 R1 (kept in G), T = R2^-1 U~_R for the lift
+            LowRankArgs lr;
+            std::memset(&lr, 0, sizeof(lr));
+            lr.m = n;
+            lr.n = n;
+            lr.l = ell;
+            lr.K = h->K;
+            lr.A = L.G;
+            lr.a_i = 1;
+            lr.a_j = n;
+            lr.Om = h->lrom.as<double>();
+            lr.max_sweeps = h->opt.max_sweeps;
+            lr.work = h->lrwork.as<double>();
+            lr.U = L.sm_u;
+            lr.ldu = n;
+            lr.s = s_new;
+            lr.post = 1;
+            lr.post_R = L.G2;
+            lr.T = L.T;
+            lr.status = dstat;
+            lr.sweeps = dstat + 1;
+            HIPCHK(h, launch_low_rank_small(lr, st));
+        }
         prof_end(h, pes);
     }
     // lift of every partition with the shared small factor (the eigen route

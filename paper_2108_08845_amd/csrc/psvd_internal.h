@@ -202,4 +202,32 @@ enum DevStatus : int32_t {
     DEV_SMALL_LAMBDA = 16
 };
 
+// Fixed buffers of the allocation-free one-shot randomized SVD: a device
+// region (dev_bytes at dev, 256-byte aligned) and host buffers for the test
+// matrix and the status word.
+struct FixedBuffers {
+    void* dev;
+    size_t dev_bytes;
+    double* omega_host;
+    size_t omega_host_entries;
+    int32_t* status_host;   // 16 entries
+};
+
+// psvd_rsvd on FixedBuffers (psvd_host.hip); the error text goes where
+// psvd_last_error(NULL) reads it.
+int rsvd_fixed(const FixedBuffers& fb, const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype, int32_t K,
+               int32_t oversampling, int32_t power_iters, uint64_t seed, int32_t precision, void* U, int64_t ldu,
+               void* V, int64_t ldv, int32_t out_dtype, double* s, int32_t* rank, void* stream);
+// Record the text of a failed call without a handle (psvd_last_error(NULL)).
+int set_call_error(int code, const char* msg);
+// The Gaussian test matrix (n x l, column-major) of call `batch` keyed by seed
+// (Philox4x32-10 + Box-Muller), FP64 values (rounding 0), FP32 (1) or BF16 (2).
+void host_omega(uint64_t seed, int64_t batch, int64_t n, int64_t l, int rounding, double* out);
+// Algorithm 2 (apmos.hip) with the exact SVD of W (ell = 0) or its low-rank SVD
+// with the ell-column test matrix of (seed, batch).
+int apmos_internal(int32_t P, const void* const* A_parts, const int64_t* M_parts, const int64_t* ld_parts, int64_t N,
+                   int32_t dtype, int32_t r, int32_t K, int32_t ell, uint64_t seed, int64_t batch,
+                   void* const* U_parts, const int64_t* ldu_parts, double* Lambda, double* X, void* stream);
+
 }  // namespace psvd
+

@@ -864,6 +864,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
         a.G[e] = (i <= j) ? s : 0.0;
     }
     __syncthreads();
+    if (a.skip_svd) return;
     W = in_lds ? lds : a.Z;
     for (int e = tid; e < n * n; e += SM_THREADS) W[e] = a.G[e];
     __syncthreads();
@@ -992,8 +993,89 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     auto bail = [&]() {
         if (tid == 0) *a.status |= DEV_NONFINITE;
     };
-    // R_Y and R_Y^-1 (V, copied out)
-    if (!chol_shifted(a.GY, W, l, a.status, DEV_FALLBACK, red, staged ? Cn : nullptr)) return bail();
+    // R_Y and R_Y^-1 (V, copied out).  A breakdown of the Cholesky factorisation,
+    // or a pivot with R_jj^2 <= l 2^-33 max_i (G_Y)_ii (Y numerically rank-
+    // deficient: its Cholesky factor would carry errors of order one), takes
+    // the eigen route below instead.
+    bool chol_ok;
+    if (staged) {
+        chol_ok = wg_chol64(a.GY, l, 0.0, Cn, W);
+    } else {
+        for (int e = tid; e < l * l; e += SM_THREADS) W[e] = a.GY[e];
+        __syncthreads();
+        chol_ok = wg_chol_upper(W, l, l);
+    }
+    if (chol_ok) {
+        if (tid == 0) {
+            double gmax = 0.0, pmin = INFINITY;
+            for (int i = 0; i < l; ++i) {
+                gmax = fmax(gmax, a.GY[i + (size_t)i * l]);
+                const double rjj = W[i + (size_t)i * l];
+                pmin = fmin(pmin, rjj * rjj);
+            }
+            sflag = pmin > (double)l * 0x1p-33 * gmax;
+        }
+        __syncthreads();
+        chol_ok = sflag != 0;
+        __syncthreads();
+    }
+    if (!chol_ok) {
+        // Eigen route: G_Y = V diag(lambda) V^T by one-sided Jacobi; the columns
+        // v_j / sqrt(lambda_j) of the eigenpairs above the floor l 2^-33 lambda_max
+        // (descending) replace R_Y^-1, so Q = Y R_Y^-1 is an orthonormal basis of
+        // the numerical range of Y and its null directions drop out.  Then
+        // B = Q^T C = (P W_r)^T: Cholesky QR of P W_r, SVD of its R factor.
+        if (tid == 0) *a.status |= DEV_FALLBACK;
+        for (int e = tid; e < l * l; e += SM_THREADS) W[e] = a.GY[e];
+        __syncthreads();
+        double* sig = vec;
+        double* nrm = sig + l;
+        int* ord = (int*)(nrm + l + 1);
+        const int swe = wg_jacobi(W, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
+        if (tid == 0 && swe > a.max_sweeps) *a.status |= DEV_NOCONV;
+        const double floor_l = (double)l * 0x1p-33 * sig[ord[0]];
+        int rr = 0;
+        for (int k = 0; k < l; ++k) rr += sig[ord[k]] > floor_l ? 1 : 0;
+        for (int e = tid; e < l * l; e += SM_THREADS) {
+            const int i = e % l, k = e / l;
+            const double lam = sig[ord[k]];
+            a.RYi[e] = k < rr ? W[i + (size_t)ord[k] * l] / sqrt(lam) : 0.0;
+            a.RY[e] = 0.0;
+        }
+        __syncthreads();
+        // P1 = P W_r (n x rr), G1 = P1^T P1, R1 = chol(G1)
+        wg_gemm_f64(n, rr, l, a.P, 1, n, a.RYi, 1, l, a.P1, 1, n, nullptr, 0);
+        wg_gemm_f64(rr, rr, n, a.P1, n, 1, a.P1, 1, n, a.G1, 1, rr, nullptr, 0);
+        if (!chol_shifted(a.G1, a.R1, rr, a.status, DEV_FALLBACK, red, nullptr)) return bail();
+        // Z = R1^T (rr x rr) -> left singular vectors of B, singular values
+        for (int e = tid; e < rr * rr; e += SM_THREADS) {
+            const int i = e % rr, j = e / rr;
+            W[e] = a.R1[j + (size_t)i * rr];
+        }
+        __syncthreads();
+        const int sw = wg_jacobi(W, rr, rr, rr, sig, ord, nrm, a.max_sweeps, &sflag);
+        if (tid == 0) {
+            *a.sweeps = sw;
+            if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
+        }
+        const int rq = rk < rr ? rk : rr;
+        // U~ (rr x rq) -> V, sign rule, M2 = W_r U~ (l x rq), zero columns past rq
+        for (int e = tid; e < rr * rq; e += SM_THREADS) {
+            const int i = e % rr, j = e / rr;
+            V[i + (size_t)j * rr] = W[i + (size_t)ord[j] * rr];
+        }
+        for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = j < rq ? sig[ord[j]] : 0.0;
+        __syncthreads();
+        wg_sign_rule(V, rr, rq, rr, nullptr);
+        for (int e = tid; e < l * rk; e += SM_THREADS) {
+            const int i = e % l, j = e / l;
+            a.small_u[e] = (i < rr && j < rq) ? V[i + (size_t)j * rr] : 0.0;
+        }
+        for (int e = tid; e < l * rk; e += SM_THREADS) a.M2[e] = 0.0;
+        __syncthreads();
+        if (rq > 0) wg_gemm_f64(l, rq, rr, a.RYi, 1, l, V, 1, rr, a.M2, 1, l, nullptr, 0);
+        return;
+    }
     for (int e = tid; e < l * l; e += SM_THREADS) a.RY[e] = W[e];
     wg_trinv_upper(W, l, l, V, l, vec);
     for (int e = tid; e < l * l; e += SM_THREADS) a.RYi[e] = V[e];
@@ -1101,10 +1183,109 @@ __global__ void k_rand_begin(int32_t* st, double* d, const double* s, int r, dou
     }
 }
 
-// d[j] = ff * s[j]
-__global__ void k_make_scale(double* d, const double* s, int r, double ff) {
+// Start of a deterministic update: the status words are cleared (st may be
+// null) and d[j] = ff * s[j].
+__global__ void k_make_scale(int32_t* st, double* d, const double* s, int r, double ff) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0 && st != nullptr) {
+        st[0] = 0;
+        st[1] = 0;
+    }
     if (j < r) d[j] = ff * s[j];
+}
+
+// ---------------------------------------------------------------------------
+// The low-rank SVD of a small matrix where the paper randomizes the parallel
+// variant (the SVD of W in Algorithm 2, of the combined R factor in the
+// partitioned update): Eqs. (7)-(11) without power iterations, one work-group,
+// FP64, everything in global scratch.
+//   Y = A Om (m x l);  Q = Y R^-1 by Cholesky QR twice (Q spans range(Y));
+//   B^T = A^T Q (n x l);  one-sided Jacobi on the columns of B^T gives
+//   B^T Z = W diag(s) with W the right singular vectors of B; the left ones
+//   are U~ = B W diag(1 / s) = (B^T)^T W diag(1 / s);  sort, sign rule on U~;
+//   U = Q U~[:, :k], k = min(K, l).
+// ---------------------------------------------------------------------------
+size_t low_rank_work_doubles(int m, int n, int l) {
+    const size_t ll = (size_t)l * l;
+    return (size_t)m * l + 3 * (size_t)n * l + 4 * ll + 4 * (size_t)(m > n ? m : n) + 4 * (size_t)l + 64;
+}
+
+__global__ __launch_bounds__(SM_THREADS) void k_low_rank_small(LowRankArgs a) {
+    __shared__ double red[SM_THREADS];
+    __shared__ int sflag;
+    if (*a.status & (DEV_FALLBACK | DEV_NONFINITE | DEV_BREAKDOWN)) return;
+    const int m = a.m, n = a.n, l = a.l, tid = threadIdx.x;
+    const int k = a.K < l ? a.K : l;
+    const size_t ll = (size_t)l * l;
+    double* Y = a.work;                          // m x l: Y, then Q
+    double* Bt = Y + (size_t)m * l;              // n x l
+    double* Z = Bt + (size_t)n * l;              // n x l (Jacobi work)
+    double* Zs = Z + (size_t)n * l;              // n x l (sorted right vectors)
+    double* G = Zs + (size_t)n * l;              // l x l
+    double* R = G + ll;                          // l x l
+    double* Ri = R + ll;                         // l x l
+    double* Ub = Ri + ll;                        // l x l
+    double* vec = Ub + ll;                       // sig, nrm, ord, rinv
+    double* sig = vec;
+    double* nrm = sig + (m > n ? m : n);
+    int* ord = (int*)(nrm + (m > n ? m : n) + 1);
+    double* rinv = (double*)(ord + (m > n ? m : n) + 2);
+    // Y = A Om
+    wg_gemm_f64(m, l, n, a.A, (int)a.a_i, (int)a.a_j, a.Om, 1, n, Y, 1, m, nullptr, 0);
+    // Q: two Cholesky-QR passes on Y (Bt holds the intermediate factor)
+    for (int pass = 0; pass < 2; ++pass) {
+        double* src = pass == 0 ? Y : Bt;
+        double* dst = pass == 0 ? Bt : Y;
+        wg_gemm_f64(l, l, m, src, m, 1, src, 1, m, G, 1, l, nullptr, 0);
+        // (a shifted retry raises no status bit here: the callers' later kernels
+        // test DEV_FALLBACK for the eigen route of the Cholesky QR of the panel)
+        if (!chol_shifted(G, R, l, a.status, 0, red, nullptr)) {
+            if (tid == 0) *a.status |= DEV_NONFINITE;
+            return;
+        }
+        wg_trinv_upper(R, l, l, Ri, l, rinv);
+        wg_gemm_f64(m, l, l, src, 1, m, Ri, 1, l, dst, 1, m, nullptr, 0);
+    }
+    // B^T = A^T Q, kept, and a working copy for the Jacobi SVD
+    wg_gemm_f64(n, l, m, a.A, (int)a.a_j, (int)a.a_i, Y, 1, m, Bt, 1, n, nullptr, 0);
+    for (int e = tid; e < n * l; e += SM_THREADS) Z[e] = Bt[e];
+    __syncthreads();
+    const int sw = wg_jacobi(Z, n, l, n, sig, ord, nrm, a.max_sweeps, &sflag);
+    if (tid == 0) {
+        atomicMax(a.sweeps, sw);
+        if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
+    }
+    for (int e = tid; e < n * k; e += SM_THREADS) {
+        const int i = e % n, j = e / n;
+        Zs[i + (size_t)j * n] = Z[i + (size_t)ord[j] * n];
+    }
+    for (int j = tid; j < k; j += SM_THREADS) a.s[j] = sig[ord[j]];
+    __syncthreads();
+    // U~ = (B^T)^T W_k diag(1 / s)
+    wg_gemm_f64(l, k, n, Bt, n, 1, Zs, 1, n, Ub, 1, l, nullptr, 0);
+    for (int e = tid; e < l * k; e += SM_THREADS) {
+        const double sj = a.s[e / l];
+        Ub[e] = sj > 0.0 ? Ub[e] / sj : 0.0;
+    }
+    __syncthreads();
+    wg_sign_rule(Ub, l, k, l, nullptr);
+    wg_gemm_f64(m, k, l, Y, 1, m, Ub, 1, l, a.U, 1, (int)a.ldu, nullptr, 0);
+    if (a.post == 1) {
+        wg_trsm_upper(a.post_R, m, m, a.U, (int)a.ldu, a.T, m, k);
+    } else if (a.post == 2) {
+        if (tid == 0 && !(a.s[k - 1] > (double)n * 0x1p-53 * a.s[0])) *a.status |= DEV_SMALL_LAMBDA;
+        for (int e = tid; e < m * k; e += SM_THREADS) {
+            const int i = e % m, j = e / m;
+            const double sj = a.s[j];
+            a.T[e] = sj > 0.0 ? a.U[i + (size_t)j * a.ldu] / sj : 0.0;
+        }
+    }
+}
+
+hipError_t launch_low_rank_small(const LowRankArgs& a, hipStream_t st) {
+    if (a.m < 1 || a.n < 1 || a.l < 1 || a.l > a.m || a.l > a.n || a.K < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_low_rank_small, dim3(1), dim3(SM_THREADS), 0, st, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1234,9 +1415,9 @@ hipError_t launch_rand_begin(int32_t* status, double* d, const double* s, int r,
     hipLaunchKernelGGL(k_rand_begin, dim3((total + 255) / 256), dim3(256), 0, st, status, d, s, r, ff, X, Om, n, l);
     return hipGetLastError();
 }
-hipError_t launch_make_scale(double* d, const double* s, int r, double ff, hipStream_t st) {
-    if (r <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_make_scale, dim3((r + 255) / 256), dim3(256), 0, st, d, s, r, ff);
+hipError_t launch_make_scale(int32_t* status, double* d, const double* s, int r, double ff, hipStream_t st) {
+    if (r <= 0 && status == nullptr) return hipSuccess;
+    hipLaunchKernelGGL(k_make_scale, dim3(((r > 0 ? r : 1) + 255) / 256), dim3(256), 0, st, status, d, s, r, ff);
     return hipGetLastError();
 }
 hipError_t launch_apmos_local(const ApmosLocalArgs& a, hipStream_t st) {

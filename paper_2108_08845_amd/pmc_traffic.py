@@ -29,6 +29,8 @@ KERNEL_SOURCES = {
     "fused_bf16": os.path.join(HERE, "csrc", "panel.hip"),
     "fused_f32": os.path.join(HERE, "csrc", "panel.hip"),
     "lift": os.path.join(HERE, "csrc", "panel.hip"),
+    "split": os.path.join(HERE, "csrc", "panel.hip"),
+    "tn": os.path.join(HERE, "csrc", "panel.hip"),
 }
 COPY_BYTES = 1 << 30
 

@@ -1,12 +1,15 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
 
 Same seeded inputs on both sides; the randomized paths use the identical test
-matrices (bit-checked).  Tolerances (sigma relative error over modes above
-the numerical-rank floor):
-  FP64 path 1e-10, FP32 path 1e-4, mixed path 2e-3 on every mode and 1e-5 on
-  the modes the range finder resolves (relative gap to the sketch tail).
+matrices (bit-checked).  Tolerances (sigma relative error on every mode above
+the numerical-rank floor): FP64 path 1e-10, FP32 path 1e-4, mixed path
+(FP32 power passes, split-BF16 final projection) 1e-5.  The unrefined BF16 sketch (precision "bf16") is
+held to 2e-3 in Weyl's form, |s_hat - s| <= 2e-3 s_1, on every mode (a
+perturbation of the sketch moves every Ritz value by at most its size times
+s_1), and to 2e-3 relative on the leading modes separated by a spectral gap.
 Subspaces are compared by the largest principal angle over leading modes
-separated by a spectral gap; orthonormality ||U^T U - I||_F is checked on the
+separated by a spectral gap, and those modes column by column (both sides
+apply the same sign rule); orthonormality ||U^T U - I||_F is checked on the
 output modes.
 """
 import math
@@ -65,7 +68,25 @@ def compare(U, s, so, tol_sigma, tol_orth, name=""):
         ang = max_principal_angle(U[:, :k], so.modes[:, :k])
         bound = max(10 * tol_sigma * s_ref[0] / gap, 1e-12)
         assert ang <= bound, f"{name}: principal angle {ang:.3e} > {bound:.3e} (k={k})"
+        compare_columns(U, so.modes, s_ref, k, tol_sigma, name)
     return e
+
+
+def compare_columns(U, U_ref, s_ref, k, tol_sigma, name=""):
+    """Modes j < k column by column, without sign alignment: both sides apply
+    the same sign rule, so equal subspaces give equal columns.  A column moves
+    by at most about tol s_1 / gap_j, gap_j the distance of s_j to its
+    neighbours relative to s_1 (the modes inside a cluster are not compared)."""
+    s_ref = np.asarray(s_ref)
+    for j in range(k):
+        lo = s_ref[j - 1] - s_ref[j] if j > 0 else np.inf
+        hi = s_ref[j] - s_ref[j + 1] if j + 1 < len(s_ref) else np.inf
+        gap = min(lo, hi) / s_ref[0]
+        if gap < 1e3 * tol_sigma:
+            continue
+        d = float(np.linalg.norm(U[:, j] - U_ref[:, j]))
+        bound = max(10 * tol_sigma / gap, 1e-12)
+        assert d <= bound, f"{name}: mode {j} differs by {d:.3e} > {bound:.3e} (gap {gap:.2e})"
 
 
 # ----------------------------------------------------------------------------
@@ -200,13 +221,20 @@ def test_randomized_fp32_matches_oracle():
     compare(U, s, so, 1e-4, 1e-5, "rand fp32")
 
 
-def resolved_modes(s_ref, factor):
-    # Leading modes at least `factor` times the smallest retained value.  Modes
-    # near the sketch tail (or inside a noise bulk) are not resolved by the
-    # truncated stream: their Ritz values move at first order with any rounding
-    # difference and are compared with the wide bound only.
-    s_ref = np.asarray(s_ref)
-    return int(np.sum(s_ref >= s_ref[-1] * factor))
+def check_bf16_sketch(U, s, so, name=""):
+    """The unrefined BF16 sketch: every mode within 2e-3 s_1 (Weyl's form) and
+    within 2e-3 relative where s_j >= 10 s_K (modes far above the sketch tail,
+    whose Ritz values the BF16 rounding moves only at second order); orthonormal
+    modes.  The relative error of the tail modes is reported, not bounded:
+    near the noise edge it reaches several 1e-3 (the reason the mixed
+    precision splits every operand)."""
+    s_ref = so.singular_values
+    assert np.max(np.abs(s - s_ref)) <= 2e-3 * s_ref[0], name
+    k = int(np.sum(s_ref >= 10 * s_ref[-1]))
+    assert k >= 1, name
+    assert sigma_rel_err(s[:k], s_ref[:k]) <= 2e-3, name
+    assert orth_err(U) <= 1e-5, name
+    print(f"{name}: sigma rel err all modes {sigma_rel_err(s, s_ref):.2e}, first {k} {sigma_rel_err(s[:k], s_ref[:k]):.2e}")
 
 
 @pytest.mark.parametrize("cfg", ["c2", "c3"])
@@ -218,14 +246,15 @@ def test_mixed_matches_oracle(cfg):
     batches = synth.planted_stream(w)
     svd, U, s = run_gpu(w, batches, "mixed", True)
     so = run_oracle(w, batches, True, oracle.PREC_BF16)
-    s_ref = so.singular_values
-    k3, k10 = resolved_modes(s_ref, 3.0), resolved_modes(s_ref, 10.0)
-    assert k10 >= 8
-    # BF16-sketch bound on the modes clear of the tail, refined bound on the well-resolved ones.
-    assert sigma_rel_err(s[:k3], s_ref[:k3]) <= 2e-3, sigma_rel_err(s[:k3], s_ref[:k3])
-    assert sigma_rel_err(s[:k10], s_ref[:k10]) <= 1e-5, sigma_rel_err(s[:k10], s_ref[:k10])
-    assert sigma_rel_err(s, s_ref) <= 1e-1
-    assert orth_err(U) <= 1e-5
+    compare(U, s, so, 1e-5, 1e-5, f"mixed {cfg}")
+
+
+def test_bf16_sketch_matches_oracle():
+    w = reduced_c2(M=1 << 16, batches=3)
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "bf16", True)
+    so = run_oracle(w, batches, True, oracle.PREC_BF16)
+    check_bf16_sketch(U, s, so, "bf16 c2")
 
 
 @pytest.mark.parametrize("precision", ["fp32", "mixed"])
@@ -233,20 +262,14 @@ def test_mixed_matches_oracle(cfg):
 def test_randomized_ragged_rows(M, precision):
     # M = 3000: float4-aligned panel with a partial last tile (the clamped
     # loads past the end must be zeroed); M = 5001: not a multiple of 4, so the
-    # panel is not float4-aligned and the fused passes take their per-element path.
+    # panel is not float4-aligned and the passes take their per-element path
+    # (the mixed precision then runs on the FP32 matrix cores).
     w = reduced_c2(M=M, batches=3)
     batches = synth.planted_stream(w)
     svd, U, s = run_gpu(w, batches, precision, True)
     so = run_oracle(w, batches, True, oracle.PREC_F32 if precision == "fp32" else oracle.PREC_BF16)
-    if precision == "fp32":
-        compare(U, s, so, 1e-4, 1e-5, f"rand fp32 M={M}")
-    else:
-        s_ref = so.singular_values
-        k10 = resolved_modes(s_ref, 10.0)
-        assert k10 >= 3
-        assert sigma_rel_err(s[:k10], s_ref[:k10]) <= 1e-5, sigma_rel_err(s[:k10], s_ref[:k10])
-        assert sigma_rel_err(s, s_ref) <= 1e-1
-        assert orth_err(U) <= 1e-5
+    tol = 1e-4 if precision == "fp32" else 1e-5
+    compare(U, s, so, tol, 1e-5, f"rand {precision} M={M}")
 
 
 def test_randomized_exact_low_rank_planted():
@@ -280,6 +303,30 @@ def test_apmos_matches_oracle(dtype, tol):
     assert np.abs(np.abs(X) - np.abs(Xo)).max() <= max(1e-9, 1e3 * tol)
 
 
+def test_apmos_graph_replay_with_new_data():
+    # On a stream other than the legacy default one the sequence is captured
+    # into a graph on the first call of a shape; a second call of the same
+    # shape on other partitions (other device pointers, other values) replays
+    # it, and a third call of another shape captures anew: each must match the
+    # oracle.
+    P = lib()
+    w = synth.scaled(synth.c4_apmos(), partitions=6, part_min=700, part_max=2500, dtype=torch.float64)
+    sizes = synth.partition_sizes(w)
+    stream = torch.cuda.Stream()
+    for seed, sz in ((11, sizes), (12, sizes), (13, [m + 5 for m in sizes])):
+        parts = synth.apmos_partitions(synth.scaled(w, seed=seed), sizes=sz)
+        gparts = [to_gpu(p) for p in parts]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            U, Lam, X = P.apmos_batched(gparts, w.local_rank, w.K, stream=stream)
+        stream.synchronize()
+        Uo, Lo, Xo = oracle.apmos([synth.numpy_cm(p) for p in parts], w.local_rank, w.K)
+        assert sigma_rel_err(Lam, Lo) <= 1e-10, seed
+        Ug = np.vstack([u.double().cpu().numpy() for u in U])
+        k = gap_limited_k(Lo, 1e-10, w.K)
+        assert max_principal_angle(Ug[:, :k], np.vstack(Uo)[:, :k]) <= 1e-8, seed
+
+
 def test_apmos_exact_when_local_rank_fits():
     w = synth.scaled(synth.c4_apmos(), partitions=5, part_min=300, part_max=900, N=48, dtype=torch.float64)
     parts = synth.apmos_partitions(w)
@@ -311,21 +358,30 @@ def test_c2_full_size_mixed_vs_oracle():
                              randomized=True, seed=w.seed, omega_precision=oracle.PREC_BF16)
     for b in bs:
         so.incorporate(synth.numpy_cm(b))
-    s_ref = so.singular_values
-    # at 2^20 rows the noise bulk reaches eta sqrt(M) ~ 1e-2, near s_K: only the
-    # leading modes are resolved, and the tolerances apply to those
-    k3, k10 = resolved_modes(s_ref, 3.0), resolved_modes(s_ref, 10.0)
-    assert k10 >= 3
-    assert sigma_rel_err(s[:k3], s_ref[:k3]) <= 2e-3
-    assert sigma_rel_err(s[:k10], s_ref[:k10]) <= 1e-5
-    assert sigma_rel_err(s, s_ref) <= 1e-1
-    # U = Y R_Y^-1 U~_K is lifted in FP32 from a basis Y of condition ~ s_1 / s_l
-    # (about 465 here), so its orthogonality is about eps_32 * 465 per entry.
-    assert orth_err(U) <= 5e-3
-    # the well-separated leading modes span the same subspace as the oracle's
-    k = gap_limited_k(s_ref, 1e-5, k10)
-    if k > 0:
-        assert max_principal_angle(U[:, :k], so.modes[:, :k]) <= 1e-3
+    compare(U, s, so, 1e-5, 1e-5, "c2 full mixed")
+
+
+def test_c3_shape_mixed_vs_oracle():
+    # The widest mixed-precision configuration (batches of N = 512, K = 100,
+    # p = 20 (sketch 120 columns), q = 1, ff = 0.95, spectrum exp(-j/30)) at
+    # 2^17 of its 2^22 rows: the oracle's FP64 randomized step on a 2^22-row
+    # panel of 612 columns takes minutes per batch on the host, 2^17 rows keeps
+    # it to seconds while every tile, column block and small factorisation of
+    # the configuration runs.  Initialisation batch plus one steady-state update.
+    w = synth.scaled(synth.c3_mixed(), M=1 << 17, batches=2)
+    bs = synth.planted_stream(w, device="cuda")
+    P = lib()
+    svd = P.StreamingSVD(w.M, w.K, ff=w.ff, oversampling=w.oversampling, power_iters=w.power_iters,
+                         randomized=True, precision="mixed", seed=w.seed)
+    for b in bs:
+        svd.incorporate_data(b.t())
+    s = svd.singular_values
+    U = svd.modes.double().cpu().numpy()
+    so = oracle.StreamOracle(w.M, w.K, ff=w.ff, oversampling=w.oversampling, power_iters=w.power_iters,
+                             randomized=True, seed=w.seed, omega_precision=oracle.PREC_BF16)
+    for b in bs:
+        so.incorporate(synth.numpy_cm(b))
+    compare(U, s, so, 1e-5, 1e-5, "c3 shape mixed")
 
 
 def test_c4_full_size_apmos_sampled_lift():
@@ -346,3 +402,33 @@ def test_c4_full_size_apmos_sampled_lift():
         ref = oracle.matmul_nn(Ai, X) / Lam
         got = U[i][torch.as_tensor(rows, device="cuda")].double().cpu().numpy()
         assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref)), i
+
+
+def test_c4_partition_subset_vs_oracle():
+    # The first 16 of the 64 partitions of the full workload at their full row
+    # counts (~2.2e6 rows, N = 128, r = K = 20; the oracle's Householder local
+    # SVDs of all 64 would take minutes on the host): Lambda~ and X~ against
+    # the oracle's Algorithm 2, and the lift U_i = A_i X~ / Lambda~ (Eq. (6)) on
+    # sampled rows of three partitions against the oracle's modes.
+    w = synth.c4_apmos()
+    sizes = synth.partition_sizes(w)[:16]
+    w = synth.scaled(w, partitions=16)
+    parts = synth.apmos_partitions(w, device="cuda", sizes=sizes)
+    P = lib()
+    U, Lam, X = P.apmos_batched([p.t() for p in parts], w.local_rank, w.K)
+    Uo, Lo, Xo = oracle.apmos([synth.numpy_cm(p) for p in parts], w.local_rank, w.K)
+    assert sigma_rel_err(Lam, Lo) <= 1e-4
+    assert orth_err(X) <= 1e-12
+    k = gap_limited_k(Lo, 1e-4, w.K)
+    assert k >= 1
+    assert max_principal_angle(X[:, :k], Xo[:, :k]) <= 1e-3
+    # the column signs of X~ (and so of U_i) are fixed by each side's own local
+    # factorisations: align them on X~, then compare the lifts with the same flips
+    flip = np.sign(np.sum(X[:, :k] * Xo[:, :k], axis=0))
+    assert np.max(np.abs(X[:, :k] * flip - Xo[:, :k])) <= 1e-3
+    rng = np.random.default_rng(0)
+    for i in (0, len(parts) // 2, len(parts) - 1):
+        rows = np.sort(rng.choice(sizes[i], size=64, replace=False))
+        got = U[i][torch.as_tensor(rows, device="cuda")].double().cpu().numpy()[:, :k] * flip
+        ref = Uo[i][rows][:, :k]
+        assert np.max(np.abs(got - ref)) <= 1e-3 * np.max(np.abs(ref)), i

@@ -40,11 +40,12 @@ def split_np(A, sizes):
     return out
 
 
-def run_both(w, sizes, precision, r_local, ff):
+def run_both(w, sizes, precision, r_local, ff, low_rank=False, seed=0):
     P = lib()
     batches = synth.planted_stream(w)
-    svd = P.PartitionedStreamingSVD(sizes, w.K, ff=ff, r_local=r_local, precision=precision)
-    po = oracle.PartitionedStreamOracle(sizes, w.K, ff=ff, r_local=r_local)
+    svd = P.PartitionedStreamingSVD(sizes, w.K, ff=ff, r_local=r_local, precision=precision, low_rank=low_rank,
+                                    seed=seed)
+    po = oracle.PartitionedStreamOracle(sizes, w.K, ff=ff, r_local=r_local, low_rank=low_rank, seed=seed)
     for b in batches:
         bg = b.to("cuda")
         svd.incorporate_data(split_gpu(bg, sizes))
@@ -69,6 +70,45 @@ def test_pstream_matches_partitioned_oracle(precision, dtype, tol):
     for i in range(len(sizes)):
         Ui = svd.modes_part(i).double().cpu().numpy()
         assert np.abs(Ui - po.modes_part(i)).max() <= etol, i
+
+
+@pytest.mark.parametrize("precision,dtype,tol", [("fp64", torch.float64, 1e-10), ("fp32", torch.float32, 1e-4)])
+def test_pstream_low_rank_matches_partitioned_oracle(precision, dtype, tol):
+    # The paper's placement of randomization: the SVD of W (APMOS
+    # initialisation) and of every combined R factor by the low-rank SVD with a
+    # K-column test matrix of (seed, batch), against the oracle's low-rank
+    # partitioned stream on the same test matrices.
+    w = synth.scaled(synth.c1_plain_fp64(), M=600, dtype=dtype)
+    sizes = [150, 97, 203, 150]
+    svd, po = run_both(w, sizes, precision, r_local=10, ff=0.9, low_rank=True, seed=11)
+    s, s_ref = svd.singular_values, po.singular_values
+    assert len(s) == len(s_ref) == w.K
+    assert sigma_rel_err(s, s_ref) <= tol, sigma_rel_err(s, s_ref)
+    U = svd.modes.double().cpu().numpy()
+    assert orth_err(U) <= (1e-12 if precision == "fp64" else 1e-5)
+    # the same sign rule on the same sketch basis: modes agree entry by entry
+    etol = 1e-9 if precision == "fp64" else 2e-3
+    for i in range(len(sizes)):
+        Ui = svd.modes_part(i).double().cpu().numpy()
+        assert np.abs(Ui - po.modes_part(i)).max() <= etol, i
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
+def test_apmos_low_rank_matches_oracle(dtype, tol):
+    # Algorithm 2 with the low-rank SVD of W (ell = 24 > K = 20, W of rank 40)
+    w = synth.scaled(synth.c4_apmos(), partitions=8, part_min=500, part_max=3000, dtype=dtype)
+    sizes = synth.partition_sizes(w)
+    parts = synth.apmos_partitions(w, sizes=sizes)
+    P = lib()
+    ell, seed = 24, 17
+    U, Lam, X = P.apmos_batched([p.to("cuda").t() for p in parts], w.local_rank, w.K, low_rank_ell=ell, seed=seed)
+    Om = oracle.omega(seed, 0, len(parts) * w.local_rank, ell, oracle.PREC_F64)
+    Uo, Lo, Xo = oracle.apmos([synth.numpy_cm(p) for p in parts], w.local_rank, w.K, omega=Om)
+    assert sigma_rel_err(Lam, Lo) <= tol
+    # same sketch basis and sign rule: X~ and the lifted modes agree directly
+    assert np.abs(X - Xo).max() <= max(1e-9, 1e2 * tol)
+    Ug = np.vstack([u.double().cpu().numpy() for u in U])
+    assert np.abs(Ug - np.vstack(Uo)).max() <= max(1e-9, 1e2 * tol) * np.abs(np.vstack(Uo)).max()
 
 
 def test_pstream_single_partition_equals_single_panel_stream():
