@@ -229,6 +229,32 @@ int psvd_rsvd(const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype,
               int32_t power_iters, uint64_t seed, int32_t precision, void* U, int64_t ldu, void* V, int64_t ldv,
               int32_t out_dtype, double* s, int32_t* rank, void* stream);
 
+/*
+ * psvd_rsvd without any allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same computation, arguments and results as
+ * psvd_rsvd, with every piece of device workspace taken from a fixed array
+ * of PSVD_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends, and fixed host buffers (a test matrix of at most
+ * PSVD_NOALLOC_OMEGA_ENTRIES = N x (K + p) entries).  The call allocates
+ * nothing: no hipMalloc, hipFree or other allocating routine.  U (if not NULL)
+ * must have out_dtype = the precision's element type (PSVD_F64 for
+ * PSVD_PREC_FP64, PSVD_F32 otherwise); the modes are written into it directly.
+ * The workspace grows with M (K + p) (the kept sketch) plus the partial sums;
+ * a problem that needs more than the fixed array returns PSVD_E_NOMEM with the
+ * required size in psvd_last_error(NULL).  Calls of one process are
+ * serialised by a lock and each synchronises the stream before it returns;
+ * work of another caller left on the array is overwritten (calls that
+ * overlapped on one GPU -- impossible within a process -- would race).
+ * Errors: those of psvd_rsvd, plus PSVD_E_DTYPE (U element type) and
+ * PSVD_E_NOMEM (size beyond the fixed maximum).
+ */
+#define PSVD_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+#define PSVD_NOALLOC_OMEGA_ENTRIES ((size_t)1 << 20)
+int psvd_rsvd_noalloc(const void* A, int64_t M, int64_t N, int64_t lda, int32_t a_dtype, int32_t K,
+                      int32_t oversampling, int32_t power_iters, uint64_t seed, int32_t precision, void* U,
+                      int64_t ldu, void* V, int64_t ldv, int32_t out_dtype, double* s, int32_t* rank, void* stream);
+
 /* Text of the last error on this handle ("" if none).  Owned by the handle.
  * With h == NULL: the last error of a psvd_rsvd call on this host thread. */
 const char* psvd_last_error(const psvd_handle* h);

@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import PsvdError
 
 __all__ = ["StreamingSVD", "PartitionedStreamingSVD", "apmos_batched", "PsvdError", "stream_backward", "loss_and_grad", "StreamingSVDFunction",
-           "rsvd"]
+           "rsvd", "rsvd_noalloc"]
 
 _PREC = {"fp64": _lib.PREC_FP64, "fp32": _lib.PREC_FP32, "mixed": _lib.PREC_MIXED, "bf16": _lib.PREC_BF16}
 
@@ -320,6 +320,31 @@ def rsvd(A, K, oversampling=10, power_iters=2, seed=0, precision="fp32", out_dty
                        s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(rank), _stream_ptr(stream))
     if rc != _lib.PSVD_OK:
         raise PsvdError(rc, "rsvd " + lib.psvd_last_error(None).decode())
+    r = int(rank.value)
+    return U[:r].t(), s[:r].copy(), V[:r].t()
+
+
+def rsvd_noalloc(A, K, oversampling=10, power_iters=2, seed=0, precision="fp32", stream=None):
+    """psvd_rsvd_noalloc: the one-shot randomized SVD with all device workspace taken
+    from the library's fixed scratch array (no allocation inside the call).  The
+    outputs U (M x r), V (N x r) are allocated here, by the caller side, in the
+    precision's element type."""
+    lib = _lib.load()
+    ptr, M, N, lda, code, keep = _as_colmajor(A)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    ocode = _lib.PSVD_F64 if dt == torch.float64 else _lib.PSVD_F32
+    r = min(int(K), N)
+    U = torch.empty((r, M), dtype=dt, device=A.device)
+    V = torch.empty((r, N), dtype=dt, device=A.device)
+    s = np.zeros(max(int(K), 1), dtype=np.float64)
+    rank = ctypes.c_int32()
+    rc = lib.psvd_rsvd_noalloc(ptr, M, N, lda, code, int(K), int(oversampling), int(power_iters),
+                               ctypes.c_uint64(int(seed)), _PREC[precision], ctypes.c_void_p(U.data_ptr()), M,
+                               ctypes.c_void_p(V.data_ptr()), N, ocode,
+                               s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(rank),
+                               _stream_ptr(stream))
+    if rc != _lib.PSVD_OK:
+        raise PsvdError(rc, "rsvd_noalloc " + lib.psvd_last_error(None).decode())
     r = int(rank.value)
     return U[:r].t(), s[:r].copy(), V[:r].t()
 

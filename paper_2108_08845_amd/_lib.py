@@ -27,7 +27,7 @@ EXPORTS = [
     "psvd_modes", "psvd_modes_ptr", "psvd_get_omega", "psvd_stats", "psvd_last_error", "psvd_status_string",
     "psvd_finalize", "psvd_reset_stats", "psvd_apmos_batched", "psvd_stream_backward", "psvd_loss_grad",
     "psvd_save_state", "psvd_load_state", "psvd_rsvd", "psvd_pstream_initialize", "psvd_pstream_incorporate",
-    "psvd_pstream_modes_ptr", "psvd_pstream_modes", "psvd_apmos_low_rank",
+    "psvd_pstream_modes_ptr", "psvd_pstream_modes", "psvd_rsvd_noalloc", "psvd_apmos_low_rank",
     "psvd_set_tuning",
 ]
 
@@ -97,6 +97,7 @@ def load():
     lib.psvd_load_state.argtypes = [H, vp, ctypes.c_size_t]
     lib.psvd_rsvd.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, ctypes.c_uint64, i32, vp, i64, vp, i64, i32, dp,
                               ctypes.POINTER(i32), vp]
+    lib.psvd_rsvd_noalloc.argtypes = lib.psvd_rsvd.argtypes
     lib.psvd_pstream_initialize.argtypes = [ctypes.POINTER(H), i32, ctypes.POINTER(i64), i32, ctypes.c_double, i32,
                                             ctypes.POINTER(Options)]
     lib.psvd_pstream_incorporate.argtypes = [H, ctypes.POINTER(vp), ctypes.POINTER(i64), i64, i32]

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpsvd.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["psvd_host.hip", "panel.hip", "small.hip", "apmos.hip", "grad.hip"]
+SOURCES = ["psvd_host.hip", "panel.hip", "small.hip", "apmos.hip", "grad.hip", "noalloc.hip"]
 ARCH = os.environ.get("PSVD_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
