@@ -448,6 +448,14 @@ __device__ __forceinline__ FusedCoords fused_coords(const FusedArgs& a) {
     return r;
 }
 
+// k index of MFMA k-step s (16x16x4, K = 4 per step) for this lane in the
+// permuted order of the FP32 passes: the 4 steps of a chunk of 16 take, in
+// lane group g = lane >> 4, the indices 16 chunk + 4 g + 0..3 (the plain
+// order takes 4 s + g).  Any fixed assignment of k to (step, group) gives
+// the same sum; this one puts a lane's operands of the 4 steps in 4
+// consecutive elements.
+__device__ __forceinline__ int kperm(int s, int lane) { return 16 * (s >> 2) + 4 * (lane >> 4) + (s & 3); }
+
 // ----------------------------------------------------------------------------
 // k_fused: FP32 passes on the FP32 matrix cores (16x16x4), one read of C.
 // Work-group of 512 threads (8 waves); tile = TM rows x NP columns, NP a
@@ -466,9 +474,17 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     constexpr int CPR = NT / TPC;
     constexpr int RMAX = (NP + CPR - 1) / CPR;
     constexpr int NRBLK = NP / 16;
-    constexpr int QB = (NRBLK + 7) / 8;
+    // Phase B output blocks (16 rows of P x 16 columns), NRBLK x 4 of them, 8
+    // waves with equal shares: wave w owns row blocks w + 8q (q < QF, all 4
+    // column blocks) and, when NRBLK % 8 == 4, column blocks 2 (w & 1) + {0, 1}
+    // of row block 8 QF + (w >> 1).
+    constexpr int QF = NRBLK / 8, RB = NRBLK % 8;
+    static_assert(RB == 0 || RB == 4, "row blocks in multiples of 4");
+    constexpr int NAA = QF + (RB ? 1 : 0);      // row blocks a wave reads
+    constexpr int NACC = QF * 4 + (RB ? 2 : 0); // output blocks a wave owns
     constexpr int ldX = NP + 4, ldC = TM + 4, ldY = TM + 4;
     static_assert(NP % 64 == 0, "panel width padded to 64");
+    static_assert(TM % 16 == 0, "tile rows in chunks of 16");
     extern __shared__ __align__(16) unsigned char smem[];
     float* Xs = (float*)smem;              // X^T: row j = column j of X (64 x NP)
     float* Cs = Xs + FU_LB * ldX;          // tile, column-major (NP x TM)
@@ -489,12 +505,15 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
     if constexpr (XREG) {
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < NP / 4; ++u) xr[u] = Xs[((w & 3) * 16 + (lane & 15)) * ldX + 4 * u + (lane >> 4)];
+        for (int u = 0; u < NP / 4; ++u) xr[u] = Xs[((w & 3) * 16 + (lane & 15)) * ldX + kperm(u, lane)];
     }
 
-    f4_t accP[MODE == 2 ? 1 : QB * 4];
+    f4_t accP[MODE == 2 ? 1 : NACC];
 #pragma unroll
-    for (int t = 0; t < (MODE == 2 ? 1 : QB * 4); ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < (MODE == 2 ? 1 : NACC); ++t) accP[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    // row block of the q-th row block a wave reads; column block of output block e >= 4 QF
+    auto rb_of = [&](int q) { return q < QF ? w + 8 * q : 8 * QF + (w >> 1); };
+    auto jr_of = [&](int e) { return 2 * (w & 1) + (e - 4 * QF); };
     d4_t accG[2];
     accG[0] = d4_t{0, 0, 0, 0};
     accG[1] = d4_t{0, 0, 0, 0};
@@ -537,18 +556,46 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
         }
     };
 
-    int64_t t = wg;
-    if (t < a.tiles) fetch(t);
-    for (; t < a.tiles; t += a.nwg) {
-        lds_barrier();
-        const bool rv = t * TM + tsub * 4 < rows;
+    // The tile's store to LDS (columns >= n and rows past the end zeroed).
+    auto store_tile = [&](float* dst, int64_t tl) {
+        const bool rv = tl * TM + tsub * 4 < rows;
 #pragma unroll
         for (int rr = 0; rr < RMAX; ++rr) {
             const int c = rr * CPR + tcol;
-            if (c < NP) *(f4_t*)&Cs[c * ldC + tsub * 4] = (cv[rr] && rv) ? pf[rr] : f4_t{0.f, 0.f, 0.f, 0.f};
+            if (c < NP) *(f4_t*)&dst[c * ldC + tsub * 4] = (cv[rr] && rv) ? pf[rr] : f4_t{0.f, 0.f, 0.f, 0.f};
         }
-        lds_barrier();
-        if (t + a.nwg < a.tiles) fetch(t + a.nwg);
+    };
+    // With X in registers its LDS copy is free after the start: it becomes a
+    // second tile buffer, and the store of the next tile (whose loads are in
+    // flight) shares the barrier interval of this tile's C^T Y products.
+    constexpr bool DB = XREG && MODE != 2 && FU_LB * ldX >= NP * ldC;
+    // (selects of the two LDS pointers, never an indexed array: the pointers
+    // keep their LDS address space and the accesses stay ds_read / ds_write)
+    int cb = 0;
+    int64_t t = wg;
+    if (t < a.tiles) fetch(t);
+    if constexpr (DB) {
+        if (t < a.tiles) {
+            store_tile(Cs, t);
+            if (t + a.nwg < a.tiles) fetch(t + a.nwg);
+        }
+        lds_barrier();   // the first tile is in Cs, and every wave has read X from Xs
+    }
+    for (; t < a.tiles; t += a.nwg, cb ^= 1) {
+        if constexpr (DB) {
+            // the next tile into the other buffer (read last in the previous
+            // iteration, before its closing barrier), then the loads of the one after it
+            if (t + a.nwg < a.tiles) {
+                store_tile(cb ? Cs : Xs, t + a.nwg);
+                if (t + 2 * a.nwg < a.tiles) fetch(t + 2 * a.nwg);
+            }
+        } else {
+            lds_barrier();
+            store_tile(Cs, t);
+            lds_barrier();
+            if (t + a.nwg < a.tiles) fetch(t + a.nwg);
+        }
+        const float* Ct = (DB && cb) ? Xs : Cs;
 
         // Phase A: Y_tile (TM x 64) = C_tile X_blk; (TM/16) x 4 output blocks over 8 waves.
         constexpr int YT = (TM / 16) * 4;
@@ -568,8 +615,8 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
 #pragma unroll
                     for (int u = 0; u < BA; ++u)
                         if (s0 + u < NS) {
-                            ab[buf][u] = Cs[(4 * (s0 + u) + (lane >> 4)) * ldC + ib * 16 + (lane & 15)];
-                            if constexpr (!XREG) xb[buf][u] = Xs[(jb * 16 + (lane & 15)) * ldX + 4 * (s0 + u) + (lane >> 4)];
+                            ab[buf][u] = Ct[kperm(s0 + u, lane) * ldC + ib * 16 + (lane & 15)];
+                            if constexpr (!XREG) xb[buf][u] = Xs[(jb * 16 + (lane & 15)) * ldX + kperm(s0 + u, lane)];
                         }
                 };
                 load_a(0, 0);
@@ -586,11 +633,11 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
                             acc4[u & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[cb][u], bv, acc4[u & 3], 0, 0, 0);
                         }
                 }
+                {   // rows ib*16 + 4 (lane >> 4) + v, v = 0..3, of column jb*16 + (lane & 15)
+                    f4_t yv;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = ib * 16 + 4 * (lane >> 4) + v;
-                    const int col = jb * 16 + (lane & 15);
-                    Ys[col * ldY + row] = (acc4[0][v] + acc4[1][v]) + (acc4[2][v] + acc4[3][v]);
+                    for (int v = 0; v < 4; ++v) yv[v] = (acc4[0][v] + acc4[1][v]) + (acc4[2][v] + acc4[3][v]);
+                    *(f4_t*)&Ys[(jb * 16 + (lane & 15)) * ldY + ib * 16 + 4 * (lane >> 4)] = yv;
                 }
             }
         }
@@ -620,60 +667,79 @@ __global__ __launch_bounds__(512) void k_fused(FusedArgs a) {
         }
         if constexpr (MODE != 2) {
             // Phase B: P (NP x 64) += C_tile^T Y_tile; wave w owns row blocks w, w + 8, ...
-            // fragments of k-step s + 1 are read while the MFMAs of k-step s issue
-            float bb[2][4], aa[2][QB];
+            // A chunk of 16 tile rows is 4 k-steps; with the permuted k order a
+            // lane's values of the 4 steps are 4 consecutive rows: one 128-bit
+            // read each of C^T and Y per chunk.  Where the registers allow it the
+            // next chunk's reads are in flight while this chunk's MFMAs issue.
+            constexpr int PB = (MODE == 0 && NP <= 320) ? 2 : 1;
+            f4_t bb[PB][4], aa[PB][NAA];
             auto load_b = [&](int buf, int k0) {
+                const int kr = k0 + 4 * (lane >> 4);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) bb[buf][j] = Ys[(j * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+                for (int j = 0; j < 4; ++j) bb[buf][j] = *(const f4_t*)&Ys[(j * 16 + (lane & 15)) * ldY + kr];
 #pragma unroll
-                for (int q = 0; q < QB; ++q)
-                    if (w + 8 * q < NRBLK) aa[buf][q] = Cs[((w + 8 * q) * 16 + (lane & 15)) * ldC + k0 + (lane >> 4)];
+                for (int q = 0; q < NAA; ++q) aa[buf][q] = *(const f4_t*)&Ct[(rb_of(q) * 16 + (lane & 15)) * ldC + kr];
             };
-            load_b(0, 0);
+            if constexpr (PB == 2) load_b(0, 0);
 #pragma unroll
-            for (int k0 = 0; k0 < TM; k0 += 4) {
-                const int cb = (k0 >> 2) & 1;
-                if (k0 + 4 < TM) load_b(cb ^ 1, k0 + 4);
+            for (int k0 = 0; k0 < TM; k0 += 16) {
+                const int cb = PB == 2 ? (k0 >> 4) & 1 : 0;
+                if constexpr (PB == 2) {
+                    if (k0 + 16 < TM) load_b(cb ^ 1, k0 + 16);
+                } else {
+                    load_b(0, k0);
+                }
 #pragma unroll
-                for (int q = 0; q < QB; ++q) {
-                    const int rb = w + 8 * q;
-                    if (rb < NRBLK) {
+                for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                    for (int q = 0; q < QF; ++q)
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
                             accP[q * 4 + j] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(aa[cb][q], bb[cb][j], accP[q * 4 + j], 0, 0, 0);
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(aa[cb][q][u], bb[cb][j][u], accP[q * 4 + j], 0, 0, 0);
+                    if constexpr (RB != 0) {
+                        const bool odd = w & 1;   // wave-uniform
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            const float bv = odd ? bb[cb][2 + e][u] : bb[cb][e][u];
+                            accP[4 * QF + e] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(aa[cb][QF][u], bv, accP[4 * QF + e], 0, 0, 0);
+                        }
                     }
                 }
             }
             if constexpr (MODE == 1) {
-                // G (64 x 64) += Y^T Y in FP64 on the FP32 values; wave w: row block w/2, col blocks (w%2)*2 + {0,1}
+                // G (64 x 64) += Y^T Y in FP64 on the FP32 values; wave w: row block w/2, col blocks
+                // (w%2)*2 + {0,1}; k permuted as in phase B (128-bit reads of 4 consecutive rows)
                 const int gi = w >> 1, gj0 = (w & 1) * 2;
 #pragma unroll
-                for (int k0 = 0; k0 < TM; k0 += 4) {
-                    const double av = (double)Ys[(gi * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
+                for (int k0 = 0; k0 < TM; k0 += 16) {
+                    const int kr = k0 + 4 * (lane >> 4);
+                    const f4_t ga = *(const f4_t*)&Ys[(gi * 16 + (lane & 15)) * ldY + kr];
+                    f4_t gb[2];
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const double bv = (double)Ys[((gj0 + j) * 16 + (lane & 15)) * ldY + k0 + (lane >> 4)];
-                        accG[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accG[j], 0, 0, 0);
-                    }
+                    for (int j = 0; j < 2; ++j) gb[j] = *(const f4_t*)&Ys[((gj0 + j) * 16 + (lane & 15)) * ldY + kr];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            accG[j] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ga[u], (double)gb[j][u], accG[j], 0, 0,
+                                                                          0);
                 }
             }
         }
+        if constexpr (DB) lds_barrier();   // this tile's buffer and Y are free again
     }
     if constexpr (MODE != 2) {
         float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
 #pragma unroll
-        for (int q = 0; q < QB; ++q) {
-            const int rb = w + 8 * q;
-            if (rb < NRBLK) {
+        for (int e = 0; e < NACC; ++e) {
+            const int rb = rb_of(e >> 2), j = e < 4 * QF ? (e & 3) : jr_of(e);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = rb * 16 + 4 * (lane >> 4) + v;
-                        const int col = j * 16 + (lane & 15);
-                        gst(outP + row + (size_t)col * NP, accP[q * 4 + j][v]);
-                    }
+            for (int v = 0; v < 4; ++v) {
+                const int row = rb * 16 + 4 * (lane >> 4) + v;
+                const int col = j * 16 + (lane & 15);
+                gst(outP + row + (size_t)col * NP, accP[e][v]);
             }
         }
     }
