@@ -431,6 +431,12 @@ def main():
         flops = 4.0 * w.M * n * ell
         roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s"}
+    elif dom == "split3":
+        # FP32-accurate power passes on three-term BF16 splits: the method's six
+        # BF16 term products per FP32 product, 6 x 4 M n l, on the BF16 matrix cores
+        flops = 6.0 * 4.0 * w.M * n * ell
+        roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS["bf16"],
+                "unit": "TFLOP/s"}
     elif dom == "nn":
         # generic Y = C X (panel read, sketch written)
         roof = {"bound": "hbm", "achieved": (panel_bytes + w.M * ell * 4) / (avg_ms * 1e-3) / 1e9,

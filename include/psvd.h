@@ -79,14 +79,16 @@ enum {
 enum {
     PSVD_KC_FUSED_BF16 = 0,    /* C^T (C X) in BF16 (power passes, BF16 precision) */
     PSVD_KC_FUSED_F32 = 1,     /* C^T (C X) [and (C X)^T (C X)] on the FP32 matrix
-                                  cores (power passes of FP32 and mixed, FP32 final) */
+                                  cores (power passes and final pass of FP32)      */
     PSVD_KC_LIFT = 2,          /* U <- C T                                         */
     PSVD_KC_TN = 3,            /* reductions over the tall rows (Gram, C^T Y)     */
     PSVD_KC_NN = 4,            /* other tall products (C X written out)           */
     PSVD_KC_SMALL = 5,         /* small-core kernels without an SVD (Cholesky-QR) */
     PSVD_KC_SMALL_SVD = 6,     /* small-core kernels with the one-sided Jacobi SVD */
     PSVD_KC_SPLIT = 7,         /* final passes on split-BF16 operands (C^T Y, Y kept) */
-    PSVD_KC_COUNT = 8
+    PSVD_KC_SPLIT3 = 8,        /* C^T (C X) on three-term BF16 splits: the FP32-
+                                  accurate power passes of the mixed precision     */
+    PSVD_KC_COUNT = 9
 };
 
 typedef struct psvd_options {
@@ -111,8 +113,8 @@ typedef struct psvd_stats_t {
     int32_t last_sweeps;        /* Jacobi sweeps of the last small SVD           */
     int32_t last_path;          /* 0 deterministic, 1 randomized                 */
     double last_update_ms;      /* device time of the last update (events)       */
-    int64_t kernel_launches[8]; /* per kernel class (PSVD_OPT_PROFILE)           */
-    double kernel_ms[8];        /* summed device time per kernel class           */
+    int64_t kernel_launches[9]; /* per kernel class (PSVD_OPT_PROFILE)           */
+    double kernel_ms[9];        /* summed device time per kernel class           */
 } psvd_stats_t;
 
 /* Fill *opt with defaults: deterministic, FP64, seed 0, default stream. */

@@ -248,6 +248,11 @@ hipError_t launch_fused(int mode, const FusedArgs& a, hipStream_t st);   // FP32
 // (a.yout, a BF16 pair per value).
 bool split64_plan(int n, FusedPlan* p);
 hipError_t launch_split64(const FusedArgs& a, hipStream_t st);
+// Fused pass with every operand split into `terms` BF16 terms (k_splitpass),
+// float4-aligned panels, one column block, 32-row tiles; launched with
+// terms = 3: an FP32-accurate power pass (P only, a.yout null).
+bool splitpass_plan(int n, int terms, FusedPlan* p);
+hipError_t launch_splitpass(int terms, const FusedArgs& a, hipStream_t st);
 // G = Y^T Y of the kept sketch into nwg FP64 64 x 64 partials (k_gram_kept).
 hipError_t launch_gram_kept(const float* Y, int64_t rows, int64_t ldy, int lx, int nwg, double* part, hipStream_t st);
 hipError_t launch_fused_reduce(const FusedReduceArgs& a, hipStream_t st);

@@ -1797,6 +1797,294 @@ __global__ __launch_bounds__(512) void k_split64(FusedArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// k_splitpass: a fused pass P = C^T (C X) (and the kept Y = C X) on the BF16
+// matrix cores with every operand v split into S BF16 terms, each term the
+// BF16 rounding of what the earlier terms leave:
+//   S = 3: v1 + v2 + v3 represents v to about 2^-24 |v| (FP32's unit
+//          roundoff); a product a b takes the six term products a_i b_j with
+//          i + j <= 4 (1-based), the dropped ones are below 2^-24 |a| |b|:
+//          FP32-accurate products, the power passes of the mixed precision.
+//   S = 2: the pair split of the final pass: a_1 b_1 + a_1 b_2 + a_2 b_1,
+//          about 2^-16 |a| |b|.
+// Tile of TM = 32 rows, row-major in LDS, one copy per term, with leading
+// dimension ldR = NP + 24: eight consecutive rows fall on distinct 16-byte
+// bank slots (the 128-bit reads of phase A) and rows 8g + 2m (m = 0..3) on
+// distinct 32-byte windows (the transpose loads of phase B).  Each thread
+// moves 4 x 4 blocks (four float4 column segments, split and written as four
+// 8-byte row pieces per term).  Per tile:
+//   phase A  Y (32 x 64) = C X.  Wave w: rows 16 (w & 1), columns 16 (w >> 1).
+//            C fragments by 128-bit reads, X terms 1 .. S-1 in registers for
+//            the whole launch, term S in LDS.
+//   phase B  P (NP x 64) += C^T Y, output blocks dealt to the waves in equal
+//            shares.  The 32 tile rows of a fragment are taken in the order
+//            8g + {0, 2, 4, 6, 1, 3, 5, 7} (g = lane >> 4): C^T by two
+//            transpose loads of four rows each, Y by one 128-bit read of the
+//            Y terms, which phase A stores in that row order.
+// The next tile's loads are in flight during both phases.  Partial sums of P
+// per work-group as k_fused writes them.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void split3_bf16x2(float a, float b, uint32_t* t1, uint32_t* t2, uint32_t* t3) {
+    const uint32_t h = pack_bf16x2(a, b);
+    const float ra = a - __uint_as_float(h << 16), rb = b - __uint_as_float(h & 0xFFFF0000u);
+    const uint32_t m = pack_bf16x2(ra, rb);
+    *t1 = h;
+    *t2 = m;
+    *t3 = pack_bf16x2(ra - __uint_as_float(m << 16), rb - __uint_as_float(m & 0xFFFF0000u));
+}
+
+// Terms of two values (S = 2 or 3), packed two per word: w[t] holds term t.
+template <int S>
+__device__ __forceinline__ void split_terms_x2(float a, float b, uint32_t* w) {
+    if constexpr (S == 3) {
+        split3_bf16x2(a, b, &w[0], &w[1], &w[2]);
+    } else {
+        split_bf16x2(a, b, &w[0], &w[1]);
+    }
+}
+
+// Sum of the terms of the low (sel 0) or high (sel 1) value of packed words.
+template <int S>
+__device__ __forceinline__ float terms_sum(const uint32_t* w, int sel) {
+    float s = 0.f;
+#pragma unroll
+    for (int t = S - 1; t >= 0; --t) s += __uint_as_float(sel ? (w[t] & 0xFFFF0000u) : (w[t] << 16));
+    return s;
+}
+
+// C^T fragment of phase B: lane (l, g) receives rows 8g + {0,2,4,6,1,3,5,7}
+// of column c0 + l of the row-major tile: two transpose loads, lane (l, g)
+// addressing row 8g + 2 (l / 4) (+1 for the second), columns c0 + 4 (l % 4) ..
+__device__ __forceinline__ bf8_t lds_colfrag_eo(const uint16_t* tile, int ld, int c0, int lane) {
+    const int l = lane & 15, g = lane >> 4;
+    const uint16_t* p = tile + (8 * g + 2 * (l >> 2)) * ld + c0 + 4 * (l & 3);
+    const s4v_t e4 = lds_tr16(p), o4 = lds_tr16(p + ld);
+    const s8_t v = (s8_t){e4[0], e4[1], e4[2], e4[3], o4[0], o4[1], o4[2], o4[3]};
+    return __builtin_bit_cast(bf8_t, v);
+}
+
+// The S-term products of one fragment pair into acc (smallest terms first).
+template <int S>
+__device__ __forceinline__ f4_t split_mma(const bf8_t* a, const bf8_t* b, f4_t acc) {
+    if constexpr (S == 3) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc, 0, 0, 0);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc, 0, 0, 0);
+}
+
+template <int NKS, int S>
+constexpr size_t splitpass_lds_bytes() {
+    return ((size_t)S * 32 * (NKS * 32 + 24) + (size_t)S * FU_LB * 40 + (size_t)FU_LB * (NKS * 32 + 8)) * 2;
+}
+
+template <int NKS, int S, bool KEEPY>
+__global__ __launch_bounds__(512) void k_splitpass(FusedArgs a) {
+    constexpr int TM = 32, NT = 512;
+    constexpr int NP = NKS * 32;
+    constexpr int ldR = NP + 24, ldY = TM + 8, ldX = NP + 8;
+    constexpr int NCG = NP / 4;                 // column groups of 4
+    constexpr int NB = 8 * NCG;                 // 4 x 4 blocks of a tile
+    constexpr int RR = (NB + NT - 1) / NT;      // block rounds per thread
+    constexpr int NRBLK = NP / 16;
+    constexpr int QF = NRBLK / 8, RB = NRBLK % 8;
+    static_assert(S == 2 || S == 3, "two or three terms");
+    static_assert(RB == 0 || RB == 4, "row blocks in multiples of 4");
+    constexpr int NAA = QF + (RB ? 1 : 0);
+    constexpr int NACC = QF * 4 + (RB ? 2 : 0);
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* Cr = (uint16_t*)smem;                 // S terms, TM x ldR row-major each
+    uint16_t* Ys = Cr + S * TM * ldR;               // S terms, 64 columns x ldY each
+    uint16_t* Xl = Ys + S * FU_LB * ldY;            // last X term, 64 columns x ldX
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const FusedCoords fc = fused_coords(a);
+    if (fc.wg >= a.nwg) return;
+    const int wg = fc.wg, lb = fc.lb;
+    const int c0 = lb * FU_LB;
+    const int ib = w & 1, jb = w >> 1;
+
+    // X terms 1 .. S-1 into registers (phase A B fragments of column block jb),
+    // term S kept in LDS; the tile buffer stages one term at a time.  Rows
+    // k >= n of X are zero: the panel columns past n (copies of column n - 1,
+    // never zeroed) then add nothing to Y, and the rows of P they produce are
+    // never read back.
+    bf8_t xr[S - 1][NKS];
+#pragma unroll
+    for (int t = 0; t < S - 1; ++t) {
+        uint16_t* Xb = Cr;
+        stage_x<NP, NT>(a, c0, [&](int k, int j, double v) {
+            uint32_t wv[S];
+            split_terms_x2<S>(k < a.n ? (float)v : 0.f, 0.f, wv);
+            Xb[j * ldX + k] = (uint16_t)(wv[t] & 0xFFFF);
+            if (t == 0) Xl[j * ldX + k] = (uint16_t)(wv[S - 1] & 0xFFFF);
+        });
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks)
+            xr[t][ks] = lds_b128(&Xb[(jb * 16 + (lane & 15)) * ldX + ks * 32 + 8 * (lane >> 4)]);
+        __syncthreads();
+    }
+
+    f4_t accP[NACC];
+#pragma unroll
+    for (int e = 0; e < NACC; ++e) accP[e] = f4_t{0.f, 0.f, 0.f, 0.f};
+    auto rb_of = [&](int q) { return q < QF ? w + 8 * q : 8 * QF + (w >> 1); };
+
+    // 4 x 4 blocks: block b -> column group (b & 7) + 8 (b >> 6), row group (b >> 3) & 7
+    // (16 consecutive lanes write two row groups x eight column groups: one
+    // 128-byte window per 8-byte store).  Columns >= n read column n - 1.
+    const float* cp[RR][4];
+    bool bon[RR];
+    int rgb[RR], cgb[RR];
+#pragma unroll
+    for (int rr = 0; rr < RR; ++rr) {
+        const int b = tid + rr * NT;
+        bon[rr] = b < NB;
+        const int bb = bon[rr] ? b : 0;
+        cgb[rr] = (bb & 7) | ((bb >> 6) << 3);
+        rgb[rr] = (bb >> 3) & 7;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = cgb[rr] * 4 + q;
+            cp[rr][q] = fcol(a.seg, c < a.n ? c : a.n - 1);
+        }
+    }
+    const int64_t rows = a.seg.rows;
+    f4_t pf[RR][4];
+    // loads only (rows % 4 == 0: past the end a float4 re-reads the last rows;
+    // those tile rows get zero Y rows, so they add nothing to P)
+    auto fetch = [&](int64_t t) {
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) {
+            const int64_t row = t * TM + rgb[rr] * 4;
+            const int64_t rowc = row < rows ? row : rows - 4;
+            if (bon[rr])
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pf[rr][q] = gld4(cp[rr][q] + rowc);
+        }
+    };
+    // split into terms and store (row pieces of four columns)
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) {
+            if (!bon[rr]) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint32_t w01[S], w23[S];
+                split_terms_x2<S>(pf[rr][0][e], pf[rr][1][e], w01);
+                split_terms_x2<S>(pf[rr][2][e], pf[rr][3][e], w23);
+                const int o = (rgb[rr] * 4 + e) * ldR + cgb[rr] * 4;
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    *(uint64_t*)&Cr[s * TM * ldR + o] = (uint64_t)w01[s] | ((uint64_t)w23[s] << 32);
+            }
+        }
+    };
+
+    const int64_t nwg = a.nwg;
+    int64_t t = wg;
+    if (t < a.tiles) {
+        fetch(t);
+        store_tile();
+        if (t + nwg < a.tiles) fetch(t + nwg);
+        lds_barrier();
+        for (; t < a.tiles; t += nwg) {
+            const bool more = t + nwg < a.tiles;
+            {   // phase A: Y block (ib, jb), terms accumulated apart (largest last)
+                f4_t y0 = f4_t{0.f, 0.f, 0.f, 0.f}, y1 = y0, y2 = y0;
+                const int ro = (ib * 16 + (lane & 15)) * ldR + 8 * (lane >> 4);
+                const int xo = (jb * 16 + (lane & 15)) * ldX + 8 * (lane >> 4);
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) {
+                    bf8_t c[S], x[S];
+#pragma unroll
+                    for (int s = 0; s < S; ++s) c[s] = lds_b128(&Cr[s * TM * ldR + ro + ks * 32]);
+#pragma unroll
+                    for (int s = 0; s < S - 1; ++s) x[s] = xr[s][ks];
+                    x[S - 1] = lds_b128(&Xl[xo + ks * 32]);
+                    if constexpr (S == 3) {
+                        y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[2], x[0], y2, 0, 0, 0);
+                        y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[1], x[1], y2, 0, 0, 0);
+                        y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[2], y2, 0, 0, 0);
+                    }
+                    y1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[1], x[0], y1, 0, 0, 0);
+                    y1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[1], y1, 0, 0, 0);
+                    y0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[0], y0, 0, 0, 0);
+                }
+                f4_t y = y0 + (y1 + y2);
+                // rows r0 + v (r0 = 16 ib + 4 g) of column 16 jb + l, zero past the
+                // end, stored at the positions of the row order 8a + {0,2,4,6,1,3,5,7}:
+                // (v0, v2) and (v1, v3) are adjacent pairs there
+                const int col = jb * 16 + (lane & 15), r0 = ib * 16 + 4 * (lane >> 4);
+                const int64_t row = t * TM + r0;
+                if (row >= rows) y = f4_t{0.f, 0.f, 0.f, 0.f};   // rows % 4 == 0: all four or none
+                const int pe = (r0 & ~7) + ((r0 & 4) ? 2 : 0);
+                uint32_t w02[S], w13[S];
+                split_terms_x2<S>(y[0], y[2], w02);
+                split_terms_x2<S>(y[1], y[3], w13);
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    *(uint32_t*)&Ys[s * FU_LB * ldY + col * ldY + pe] = w02[s];
+                    *(uint32_t*)&Ys[s * FU_LB * ldY + col * ldY + pe + 4] = w13[s];
+                }
+                if constexpr (KEEPY) {
+                    // the kept Y: the sum of the terms the products of P use
+                    if (c0 + col < a.lx && row < rows) {
+                        f4_t yp;
+                        yp[0] = terms_sum<S>(w02, 0);
+                        yp[1] = terms_sum<S>(w13, 0);
+                        yp[2] = terms_sum<S>(w02, 1);
+                        yp[3] = terms_sum<S>(w13, 1);
+                        gst4(a.yout + (size_t)(c0 + col) * (size_t)a.ldy + row, yp);
+                    }
+                }
+            }
+            lds_barrier();
+            {   // phase B
+                const int yo = (lane & 15) * ldY + 8 * (lane >> 4);
+#pragma unroll
+                for (int q = 0; q < NAA; ++q) {
+                    bf8_t cf[S];
+#pragma unroll
+                    for (int s = 0; s < S; ++s) cf[s] = lds_colfrag_eo(Cr + s * TM * ldR, ldR, rb_of(q) * 16, lane);
+                    constexpr int NJ = 4;
+#pragma unroll
+                    for (int jj = 0; jj < (q < QF ? NJ : 2); ++jj) {
+                        const int j = q < QF ? jj : 2 * (w & 1) + jj;
+                        const int e = q < QF ? q * 4 + jj : 4 * QF + jj;
+                        bf8_t yf[S];
+#pragma unroll
+                        for (int s = 0; s < S; ++s) yf[s] = lds_b128(&Ys[s * FU_LB * ldY + j * 16 * ldY + yo]);
+                        accP[e] = split_mma<S>(cf, yf, accP[e]);
+                    }
+                }
+            }
+            lds_barrier();
+            if (more) {
+                store_tile();
+                if (t + 2 * nwg < a.tiles) fetch(t + 2 * nwg);
+            }
+            lds_barrier();
+        }
+    }
+    float* outP = a.partP + ((size_t)wg * a.nlb + lb) * (size_t)NP * FU_LB;
+#pragma unroll
+    for (int e = 0; e < NACC; ++e) {
+        const int rb = rb_of(e >> 2), j = e < 4 * QF ? (e & 3) : 2 * (w & 1) + (e - 4 * QF);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = rb * 16 + 4 * (lane >> 4) + v;
+            const int col = j * 16 + (lane & 15);
+            gst(outP + row + (size_t)col * NP, accP[e][v]);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
 // k_gram_kept: G = Y^T Y of the kept sketch (rows x lx FP32, lx <= 64,
 // column-major with leading dimension ldy; rows and ldy multiples of 4 and a
 // 16-byte aligned base).  Every kept value is a BF16 pair (hi + lo exactly,
@@ -2037,6 +2325,35 @@ hipError_t launch_split64(const FusedArgs& a, hipStream_t st) {
     if (nks == NKS_) return launch_512(k_split64<NKS_>, a, lds, st);
     SP(2) SP(4) SP(6) SP(8) SP(10)
 #undef SP
+    return hipErrorInvalidValue;
+}
+
+static size_t splitpass_lds(int np, int terms) {
+    // terms x (32 x (np + 24)) tile, terms x (64 x 40) Y, 64 x (np + 8) last X term (16-bit each)
+    return ((size_t)terms * 32 * (np + 24) + (size_t)terms * FU_LB * 40 + (size_t)FU_LB * (np + 8)) * 2;
+}
+
+bool splitpass_plan(int n, int terms, FusedPlan* p) {
+    for (int nks : kSplitNks) {
+        if (nks * 32 < n || nks > 10) continue;
+        p->np = nks * 32;
+        p->tm = 32;
+        p->lds = splitpass_lds(p->np, terms);
+        return p->lds <= 160 * 1024;
+    }
+    return false;
+}
+
+hipError_t launch_splitpass(int terms, const FusedArgs& a, hipStream_t st) {
+    // instantiated for the power passes only: three terms, no kept Y
+    if (a.tm != 32 || a.np % 64 || a.nlb != 1 || !a.vec || a.yout != nullptr || terms != 3)
+        return hipErrorInvalidValue;
+    const size_t lds = splitpass_lds(a.np, terms);
+    const int nks = a.np / 32;
+#define SPP(NKS_) \
+    if (nks == NKS_) return launch_512(k_splitpass<NKS_, 3, false>, a, lds, st);
+    SPP(2) SPP(4) SPP(6) SPP(8) SPP(10)
+#undef SPP
     return hipErrorInvalidValue;
 }
 

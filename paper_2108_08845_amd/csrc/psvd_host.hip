@@ -894,24 +894,29 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         const int nlb = ceil_div(l, 64);
         // Fused passes, one read of the panel each: P = D C'^T (C' X') and, in
         // the final pass, the kept Y = C' X' and G_Y = Y^T Y.
-        //   mixed: power passes on the FP32 matrix cores (k_fused); the final
-        //          pass on the BF16 matrix cores with every operand split into a
-        //          BF16 pair (k_split64), G_Y from the kept Y (k_gram_kept); FP32
-        //          matrix cores for the final pass on panels k_split64 does not take.
-        //          (Split pairs carry about 2^-17 relative error per operand; in
-        //          the power iterations that error reaches the tail of the sketch
-        //          amplified by (s_1 / s_j)^2, so those passes keep FP32 products.)
+        //   mixed: power passes on the BF16 matrix cores with every operand
+        //          split into three BF16 terms, six term products: FP32-accurate
+        //          (k_splitpass<., 3>); the final pass with pair splits
+        //          (k_split64), G_Y from the kept Y
+        //          (k_gram_kept); FP32 matrix cores (k_fused) on panels those
+        //          kernels do not take.  (Pairs carry about 2^-17 relative error
+        //          per operand; in the power iterations that error reaches the
+        //          tail of the sketch amplified by (s_1 / s_j)^2, so those passes
+        //          take the three-term split.)
         //   bf16:  power passes on plain BF16 operands (k_sketch_bf16), the final
         //          pass split-BF16 with a BF16-rounded test matrix (k_final_split)
         //   fp32:  FP32 matrix cores (k_fused);  fp64: the generic products
-        enum { UNFUSED, SPLIT64, SKETCH_BF16, FINAL_SPLIT, FUSED_F32 };
+        enum { UNFUSED, SPLIT64, SKETCH_BF16, FINAL_SPLIT, FUSED_F32, SPLIT3 };
         auto pass = [&](bool final_pass) -> int {
             FusedPlan fp;
             int kind = UNFUSED;
             const bool vec = seg_vec_ok(C, false);
             const int pw = plan_width(h, n);
             if (!fp64 && seg_all_f32(C)) {
-                if (prec == PSVD_PREC_MIXED && final_pass && nlb == 1 && vec && M >= 4 && split64_plan(pw, &fp))
+                const bool mixed1 = prec == PSVD_PREC_MIXED && nlb == 1 && vec && M >= 4;
+                if (mixed1 && !final_pass && splitpass_plan(pw, 3, &fp))
+                    kind = SPLIT3;
+                else if (mixed1 && final_pass && split64_plan(pw, &fp))
                     kind = SPLIT64;
                 else if (prec == PSVD_PREC_BF16 && !final_pass && sketch_plan(pw, h->opt.tile_rows, &fp))
                     kind = SKETCH_BF16;
@@ -933,21 +938,25 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
                 fa.nwg = fused_wgs(h, fa.tiles);
                 fa.partP = h->partP.as<float>();
                 fa.partG = h->partG.as<double>();
-                fa.want_g = (final_pass && kind != SPLIT64) ? 1 : 0;
+                const bool kept_gram = kind == SPLIT64;   // G_Y from the kept Y
+                fa.want_g = (final_pass && !kept_gram) ? 1 : 0;
                 fa.vec = vec ? 1 : 0;
                 if (final_pass) {   // keep Y = C X for the lift (U = Y R_Y^-1 U~_K)
                     fa.yout = h->tall.as<float>();
                     fa.ldy = M;
                 }
-                const int cls = kind == SKETCH_BF16 ? PSVD_KC_FUSED_BF16
-                                : (kind == SPLIT64 || kind == FINAL_SPLIT) ? PSVD_KC_SPLIT : PSVD_KC_FUSED_F32;
+                const int cls = kind == SKETCH_BF16                                      ? PSVD_KC_FUSED_BF16
+                                : (kind == SPLIT64 || kind == FINAL_SPLIT)                   ? PSVD_KC_SPLIT
+                                : kind == SPLIT3                                            ? PSVD_KC_SPLIT3
+                                                                                            : PSVD_KC_FUSED_F32;
                 int pe = prof_begin(h, cls);
-                if (kind == SPLIT64) HIPCHK(h, launch_split64(fa, st));
+                if (kind == SPLIT3) HIPCHK(h, launch_splitpass(3, fa, st));
+                else if (kind == SPLIT64) HIPCHK(h, launch_split64(fa, st));
                 else if (kind == SKETCH_BF16) HIPCHK(h, launch_sketch_bf16(fa, st));
                 else if (kind == FINAL_SPLIT) HIPCHK(h, launch_final_split(fa, st));
                 else HIPCHK(h, launch_fused(final_pass ? 1 : 0, fa, st));
                 prof_end(h, pe);
-                if (kind == SPLIT64) {
+                if (kept_gram) {
                     // G_Y from the kept Y, one partial per work-group of the pass
                     int pg = prof_begin(h, PSVD_KC_TN);
                     HIPCHK(h, launch_gram_kept(fa.yout, M, M, l, fa.nwg, fa.partG, st));

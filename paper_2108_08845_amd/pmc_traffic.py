@@ -30,6 +30,7 @@ KERNEL_SOURCES = {
     "fused_f32": os.path.join(HERE, "csrc", "panel.hip"),
     "lift": os.path.join(HERE, "csrc", "panel.hip"),
     "split": os.path.join(HERE, "csrc", "panel.hip"),
+    "split3": os.path.join(HERE, "csrc", "panel.hip"),
     "tn": os.path.join(HERE, "csrc", "panel.hip"),
 }
 COPY_BYTES = 1 << 30
