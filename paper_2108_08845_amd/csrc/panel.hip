@@ -1862,17 +1862,24 @@ __device__ __forceinline__ bf8_t lds_colfrag_eo(const uint16_t* tile, int ld, in
     return __builtin_bit_cast(bf8_t, v);
 }
 
-// The S-term products of one fragment pair into acc (smallest terms first).
-template <int S>
-__device__ __forceinline__ f4_t split_mma(const bf8_t* a, const bf8_t* b, f4_t acc) {
+// The S-term products of one C^T fragment with the Y fragments of nj column
+// blocks, products outermost: consecutive MFMAs go to different accumulators.
+template <int S, int NJ>
+__device__ __forceinline__ void split_mma_rows(const bf8_t* a, const bf8_t (*b)[S], f4_t* acc) {
     if constexpr (S == 3) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][0], acc[j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][1], acc[j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][2], acc[j], 0, 0, 0);
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][0], acc[j], 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][1], acc[j], 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc[j], 0, 0, 0);
 }
 
 template <int NKS, int S>
@@ -2006,14 +2013,13 @@ __global__ __launch_bounds__(512) void k_splitpass(FusedArgs a) {
 #pragma unroll
                     for (int s = 0; s < S - 1; ++s) x[s] = xr[s][ks];
                     x[S - 1] = lds_b128(&Xl[xo + ks * 32]);
-                    if constexpr (S == 3) {
-                        y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[2], x[0], y2, 0, 0, 0);
-                        y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[1], x[1], y2, 0, 0, 0);
-                        y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[2], y2, 0, 0, 0);
-                    }
+                    // chains interleaved: consecutive MFMAs independent where possible
+                    if constexpr (S == 3) y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[2], x[0], y2, 0, 0, 0);
                     y1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[1], x[0], y1, 0, 0, 0);
-                    y1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[1], y1, 0, 0, 0);
                     y0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[0], y0, 0, 0, 0);
+                    if constexpr (S == 3) y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[1], x[1], y2, 0, 0, 0);
+                    y1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[1], y1, 0, 0, 0);
+                    if constexpr (S == 3) y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[2], y2, 0, 0, 0);
                 }
                 f4_t y = y0 + (y1 + y2);
                 // rows r0 + v (r0 = 16 ib + 4 g) of column 16 jb + l, zero past the
@@ -2052,14 +2058,21 @@ __global__ __launch_bounds__(512) void k_splitpass(FusedArgs a) {
 #pragma unroll
                     for (int s = 0; s < S; ++s) cf[s] = lds_colfrag_eo(Cr + s * TM * ldR, ldR, rb_of(q) * 16, lane);
                     constexpr int NJ = 4;
+                    if (q < QF) {
+                        bf8_t yf[NJ][S];
 #pragma unroll
-                    for (int jj = 0; jj < (q < QF ? NJ : 2); ++jj) {
-                        const int j = q < QF ? jj : 2 * (w & 1) + jj;
-                        const int e = q < QF ? q * 4 + jj : 4 * QF + jj;
-                        bf8_t yf[S];
+                        for (int jj = 0; jj < NJ; ++jj)
 #pragma unroll
-                        for (int s = 0; s < S; ++s) yf[s] = lds_b128(&Ys[s * FU_LB * ldY + j * 16 * ldY + yo]);
-                        accP[e] = split_mma<S>(cf, yf, accP[e]);
+                            for (int s = 0; s < S; ++s) yf[jj][s] = lds_b128(&Ys[s * FU_LB * ldY + jj * 16 * ldY + yo]);
+                        split_mma_rows<S, NJ>(cf, yf, &accP[q * 4]);
+                    } else {
+                        bf8_t yf[2][S];
+#pragma unroll
+                        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                            for (int s = 0; s < S; ++s)
+                                yf[jj][s] = lds_b128(&Ys[s * FU_LB * ldY + (2 * (w & 1) + jj) * 16 * ldY + yo]);
+                        split_mma_rows<S, 2>(cf, yf, &accP[4 * QF]);
                     }
                 }
             }
