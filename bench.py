@@ -47,14 +47,15 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the oracle sample (0: all M rows)")
     ap.add_argument("--M", type=int, default=1 << 20)
     ap.add_argument("--workload", default="randomized",
-                    choices=["randomized", "mixed_wide", "partitioned", "burgers", "gradient"],
+                    choices=["randomized", "mixed_wide", "partitioned", "burgers", "gradient", "apmos"],
                     help="randomized: the headline mixed-precision randomized stream (M = 2^20, batches of "
                          "256, K = 50, p = 10, q = 2); mixed_wide: the widest mixed-precision configuration "
                          "(M = 2^22, batches of 512, K = 100, p = 20, q = 1); partitioned: the "
                          "partitioned streaming SVD (APMOS initialisation, partition QR combination); burgers: "
                          "the partitioned stream over the closed-form Burgers snapshots (16384 x 800, FP64); "
                          "gradient: loss and reverse-mode gradient of the streamed truncated SVD (M = 2^18, "
-                         "4 batches of 64, K = 20, FP32)")
+                         "4 batches of 64, K = 20, FP32); apmos: batched APMOS over 64 row partitions "
+                         "(16384 .. 262144 rows each, N = 128 FP32, r = 20, K = 20, one hipGraph)")
     ap.add_argument("--partitions", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibration of the HBM byte counters)")
@@ -370,6 +371,50 @@ def bench_gradient(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_apmos(args):
+    """Batched APMOS (Algorithm 2) on one GPU's share: 64 row partitions with
+    row counts uniform in [16384, 262144], N = 128 FP32 snapshots each, local
+    truncation r = 20, global K = 20, the whole sequence one captured hipGraph
+    (replayed on every call after the first).  One JSON line: snapshot bytes
+    per second through the call (the partitions stay resident in HBM)."""
+    import synth
+    import paper_2108_08845_amd as P
+    w = synth.c4_apmos()
+    sizes = synth.partition_sizes(w)
+    parts = [p.t() for p in synth.apmos_partitions(w, device="cuda", sizes=sizes)]   # M_i x N column-major
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        P.apmos_batched(parts, w.local_rank, w.K, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        U, Lam, X = P.apmos_batched(parts, w.local_rank, w.K, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    rows = int(sum(sizes))
+    snap_bytes = rows * w.N * 4
+    # algorithmic bytes: the local Grams and the lift each read every partition
+    # once; the lift writes the K local modes
+    alg_bytes = 2 * snap_bytes + rows * w.K * 4
+    out = {
+        "metric": "batched APMOS snapshot GB/s (local Grams, eigen-decompositions, global SVD, lift; one hipGraph)",
+        "value": snap_bytes / (ms * 1e-3) / 1e9, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (tall products) / f64 small core", "data": "synthetic",
+        "config": {"workload": w.name, "partitions": w.partitions, "rows_total": rows, "N": w.N,
+                   "local_rank": w.local_rank, "K": w.K, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": alg_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole call (algorithmic bytes of its tall passes / call time)"},
+        "global_singular_values_head": [float(x) for x in Lam[:5]],
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -386,6 +431,9 @@ def main():
         return
     if args.workload == "gradient":
         bench_gradient(args)
+        return
+    if args.workload == "apmos":
+        bench_apmos(args)
         return
     import synth
     import paper_2108_08845_amd as P
