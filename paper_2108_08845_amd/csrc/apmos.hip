@@ -101,6 +101,11 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
         s.ldo = ldu_parts[i];
         s.out_dtype = dtype;
     }
+    // float4 loads in the lift (k_nn_v): FP32 partitions, rows and leading
+    // dimensions multiples of 4, 16-byte aligned bases
+    bool vec_all = !fp64;
+    for (int i = 0; i < P; ++i)
+        vec_all = vec_all && M_parts[i] % 4 == 0 && ld_parts[i] % 4 == 0 && ((uintptr_t)A_parts[i] & 15) == 0;
     const int mb = (int)((N + 63) / 64);
     const int nob = mb * (mb + 1) / 2;
     int64_t chunk = std::max<int64_t>(64, ((Mtot / std::max(1, 2048 / nob) + 63) / 64) * 64);
@@ -212,7 +217,8 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return PSVD_E_DEVICE;
 
-    std::vector<int64_t> key = {P, N, r, K, dtype, nitems, nlitems, (int64_t)(uintptr_t)W.buf, (int64_t)total, ell};
+    std::vector<int64_t> key = {P, N, r, K, dtype, nitems, nlitems, (int64_t)(uintptr_t)W.buf, (int64_t)total, ell,
+                                (int64_t)vec_all};
     for (int i = 0; i < P; ++i) key.push_back(M_parts[i]);
     const bool reuse = W.exec && W.key == key && W.key_stream == st;
 
@@ -339,6 +345,8 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
             na.ldx = N;
             na.n = (int)N;
             na.nx = K;
+            na.all_f32 = fp64 ? 0 : 1;
+            na.vec_f32 = vec_all ? 1 : 0;
             if (ce == hipSuccess) ce = launch_nn(fp64, na, nlitems, s2);
         return ce;
     };

@@ -67,6 +67,9 @@ struct NnArgs {
     int32_t skip_mask;        // do nothing if (*skip & skip_mask)
     int32_t need_mask;        // do nothing unless (*skip & need_mask) (when non-zero)
     int32_t accumulate;       // out += result instead of out = result
+    int32_t all_f32;          // every segment's columns FP32 (k_nn_v)
+    int32_t vec_f32;          // ... and float4-aligned (rows % 4 == 0, 16-byte column starts)
+    int32_t nitems_v;         // work items (set by the launcher)
 };
 
 struct FusedArgs {

@@ -396,6 +396,145 @@ __device__ __forceinline__ const float* fcol(const PanelSeg& s, int c) {
     return (const float*)p;
 }
 
+// ----------------------------------------------------------------------------
+// k_nn_v: out[seg rows, ocols] = C[rows, :] X[:, ocols] (+ row scale, + out)
+// for FP32 panels.  VEC: columns take float4 loads (rows % 4 == 0, 16-byte
+// aligned columns; a thread moves four 4-row column segments per chunk), else
+// one float per lane (a wave moves 64 consecutive rows of one column per
+// load).  One work-group: one 32-column block of X, staged in LDS
+// once (rows k >= n zero, so the padding columns of C -- copies of column
+// n - 1 -- add nothing), and one item's rows in 64-row tiles; C streams in
+// 64-row x 64-column chunks of float4 column segments into two LDS buffers,
+// the next chunk's loads in flight during this chunk's products (one barrier
+// per chunk).  FP32 matrix cores (16x16x4); wave w forms rows 16 w .. of the
+// tile, both 16-column blocks, and stores them straight from its accumulators.
+// Work-group ids: the output blocks of one row chunk take consecutive slots of
+// one XCD (they share the chunk's rows through that XCD's L2).
+// ----------------------------------------------------------------------------
+constexpr int NV_TM = 64, NV_KC = 64, NV_OB = 32, NV_LDC = NV_TM + 4;
+constexpr int NV_NMAX = 1024;   // X block 32 x (1024 + 4) FP32 and the two chunk buffers fit in LDS
+
+__host__ __device__ inline int nv_ldx(int npad) { return npad + 4; }
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    if (a.skip && a.need_mask && !(*a.skip & a.need_mask)) return;
+    extern __shared__ __align__(16) float nvs[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nob = (a.nx + NV_OB - 1) / NV_OB;
+    const int64_t bid = blockIdx.x, slot = bid >> 3;
+    const int64_t item = (slot / nob) * 8 + (bid & 7);
+    const int ob = (int)(slot % nob);
+    if (item >= a.nitems_v) return;
+    const WorkItem it = get_item(a.items, a.chunk, a.seg.rows, item);
+    const PanelSeg S = a.segs ? load_seg(a.segs + it.seg) : a.seg;
+    const int n = a.n;
+    const int npad = (n + NV_KC - 1) / NV_KC * NV_KC;
+    const int ldX = nv_ldx(npad);
+    const int oc0 = ob * NV_OB;
+    float* Xs = nvs;                                  // NV_OB columns x ldX
+    float* Cb = Xs + NV_OB * ldX;                     // 2 buffers x NV_KC columns x NV_LDC
+    for (int idx = tid; idx < NV_OB * npad; idx += 256) {
+        const int k = idx % npad, j = idx / npad;
+        double v = 0.0;
+        if (k < n && oc0 + j < a.nx) v = gldd(a.X + k + (int64_t)(oc0 + j) * a.ldx);
+        Xs[j * ldX + k] = (float)v;
+    }
+    const int nch = npad / NV_KC;
+    const int64_t rows1 = it.row1;
+    if (it.row0 >= rows1) return;
+    const int64_t ntile = (rows1 - it.row0 + NV_TM - 1) / NV_TM;
+    const int64_t nstep = ntile * nch;
+    // VEC load slots: column (tid >> 4) + 16 q of the chunk, rows 4 (tid & 15) .. + 3;
+    // scalar: column w + 4 q, row lane
+    const int lc = VEC ? tid >> 4 : w, lr = VEC ? 4 * (tid & 15) : lane;
+    f4_t pf[4];
+    auto fetch = [&](int64_t s) {
+        const int64_t tl = s / nch;
+        const int kc = (int)(s % nch);
+        const int64_t row = it.row0 + tl * NV_TM + lr;
+        if constexpr (VEC) {
+            const int64_t rowc = row < rows1 ? row : rows1 - 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = kc * NV_KC + lc + 16 * q;
+                pf[q] = gld4(fcol(S, c < n ? c : n - 1) + rowc);
+            }
+        } else {
+            const int64_t rowc = row < rows1 ? row : rows1 - 1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = kc * NV_KC + lc + 4 * (4 * q + e);
+                    pf[q][e] = gld(fcol(S, c < n ? c : n - 1) + rowc);
+                }
+        }
+    };
+    f4_t acc[2];
+    acc[0] = f4_t{0.f, 0.f, 0.f, 0.f};
+    acc[1] = acc[0];
+    fetch(0);
+    for (int64_t s = 0; s < nstep; ++s) {
+        float* cb = Cb + (s & 1) * (NV_KC * NV_LDC);
+        if constexpr (VEC) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) *(f4_t*)&cb[(lc + 16 * q) * NV_LDC + lr] = pf[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) cb[(lc + 4 * (4 * q + e)) * NV_LDC + lr] = pf[q][e];
+        }
+        lds_barrier();   // this chunk stored; X staged (first step)
+        if (s + 1 < nstep) fetch(s + 1);
+        const int kc = (int)(s % nch);
+        // k order within 16: lane group g takes 4 g + 0..3 (kperm), so a
+        // lane's X values of four steps are four consecutive k
+#pragma unroll
+        for (int c4 = 0; c4 < NV_KC / 16; ++c4) {
+            f4_t xb[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                xb[j] = *(const f4_t*)&Xs[(j * 16 + (lane & 15)) * ldX + kc * NV_KC + 16 * c4 + 4 * (lane >> 4)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float av = cb[(16 * c4 + 4 * (lane >> 4) + u) * NV_LDC + w * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xb[j][u], acc[j], 0, 0, 0);
+            }
+        }
+        if (kc == nch - 1) {   // tile complete: rows r0 + 16 w + 4 g + v, columns oc0 + 16 j + l
+            const int64_t r0 = it.row0 + (s / nch) * NV_TM + w * 16 + 4 * (lane >> 4);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = oc0 + j * 16 + (lane & 15);
+                if (col < a.nx) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t row = r0 + v;
+                        if (row < rows1) {
+                            double y = (double)acc[j][v];
+                            if (a.row_scale && row < a.nscale) y *= a.row_scale[row];
+                            const size_t o = (size_t)row + (size_t)col * (size_t)S.ldo;
+                            if (S.out_dtype == PSVD_F64) {
+                                double* po = (double*)S.out + o;
+                                gstd(po, a.accumulate ? gldd(po) + y : y);
+                            } else {
+                                float* po = (float*)S.out + o;
+                                gst(po, a.accumulate ? (float)((double)gld(po) + y) : (float)y);
+                            }
+                        }
+                    }
+                }
+                acc[j] = f4_t{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    }
+}
+
 // X (FP64, column-major) element (min(k, n-1), min(j, lx-1)).  Padding rows
 // k >= n only meet panel columns that are zero, and padding columns j >= lx
 // only feed outputs that are never read back (partials beyond lx, Y columns
@@ -2483,6 +2622,20 @@ hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st) {
 }
 
 hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
+    if (!fp64 && a.all_f32 && a.n >= 1 && a.n <= NV_NMAX) {
+        NnArgs b = a;
+        b.nitems_v = nitems;
+        const int nob = (a.nx + NV_OB - 1) / NV_OB;
+        const int npad = (a.n + NV_KC - 1) / NV_KC * NV_KC;
+        const size_t lds = ((size_t)NV_OB * nv_ldx(npad) + (size_t)2 * NV_KC * NV_LDC) * sizeof(float);
+        const void* fn = a.vec_f32 ? (const void*)k_nn_v<true> : (const void*)k_nn_v<false>;
+        hipError_t e = ensure_lds_attr(fn, lds);
+        if (e != hipSuccess) return e;
+        const int64_t blocks = (int64_t)((nitems + 7) / 8) * 8 * nob;
+        if (a.vec_f32) hipLaunchKernelGGL(k_nn_v<true>, dim3((unsigned)blocks), dim3(256), lds, st, b);
+        else hipLaunchKernelGGL(k_nn_v<false>, dim3((unsigned)blocks), dim3(256), lds, st, b);
+        return hipGetLastError();
+    }
     dim3 grid(nitems, (a.nx + NN_OB - 1) / NN_OB);
     if (fp64) hipLaunchKernelGGL(k_nn<double>, grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL(k_nn<float>, grid, dim3(256), 0, st, a);

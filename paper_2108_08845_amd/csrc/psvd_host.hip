@@ -440,6 +440,22 @@ static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool
     return PSVD_OK;
 }
 
+// float4 loads need 16-byte aligned column starts: rows % 4 == 0 and every
+// leading dimension a multiple of 4 with a 16-byte aligned base.
+static bool seg_vec_ok(const PanelSeg& S, bool check_out) {
+    if (S.rows % 4) return false;
+    for (int b = 0; b < S.nblk; ++b)
+        if ((S.blk[b].ld % 4) || ((uintptr_t)S.blk[b].ptr & 15)) return false;
+    if (check_out && ((S.ldo % 4) || ((uintptr_t)S.out & 15))) return false;
+    return true;
+}
+
+static bool seg_all_f32(const PanelSeg& S) {
+    for (int b = 0; b < S.nblk; ++b)
+        if (S.blk[b].dtype != PSVD_F32) return false;
+    return true;
+}
+
 // out (rows x nx) = S X with X (S.ncols x nx, ld ldx) FP64.
 static int nn_product(psvd_handle* h, const PanelSeg& S, const double* X, int64_t ldx, int nx, bool fp64,
                       const double* row_scale, int nscale, const int32_t* skip, int skip_mask,
@@ -461,6 +477,8 @@ static int nn_product(psvd_handle* h, const PanelSeg& S, const double* X, int64_
     a.skip_mask = skip_mask;
     a.need_mask = need_mask;
     a.accumulate = accumulate;
+    a.all_f32 = (!fp64 && seg_all_f32(S)) ? 1 : 0;
+    a.vec_f32 = (a.all_f32 && seg_vec_ok(S, false)) ? 1 : 0;
     int pe = prof_begin(h, cls);
     HIPCHK(h, launch_nn(fp64, a, nitems, h->stream));
     prof_end(h, pe);
@@ -468,21 +486,6 @@ static int nn_product(psvd_handle* h, const PanelSeg& S, const double* X, int64_
 }
 
 
-// float4 loads need 16-byte aligned column starts: rows % 4 == 0 and every
-// leading dimension a multiple of 4 with a 16-byte aligned base.
-static bool seg_vec_ok(const PanelSeg& S, bool check_out) {
-    if (S.rows % 4) return false;
-    for (int b = 0; b < S.nblk; ++b)
-        if ((S.blk[b].ld % 4) || ((uintptr_t)S.blk[b].ptr & 15)) return false;
-    if (check_out && ((S.ldo % 4) || ((uintptr_t)S.out & 15))) return false;
-    return true;
-}
-
-static bool seg_all_f32(const PanelSeg& S) {
-    for (int b = 0; b < S.nblk; ++b)
-        if (S.blk[b].dtype != PSVD_F32) return false;
-    return true;
-}
 
 // out (S.out) = S T with T (S.ncols x nx FP64): fused FP32 lift when the panel
 // is FP32 and fits, otherwise the generic product.
