@@ -55,10 +55,11 @@ typedef enum psvd_method {
 typedef enum psvd_precision {
     PSVD_PREC_FP64 = 0,     /* every product in FP64; state U in FP64            */
     PSVD_PREC_FP32 = 1,     /* panel products in FP32 (MFMA), small core FP64    */
-    PSVD_PREC_MIXED = 2,    /* power passes on the FP32 matrix cores; the final
-                               projection on the BF16 matrix cores with every
-                               operand split into a BF16 pair (hi + lo), FP32
-                               accumulation; Grams summed in FP64, small core
+    PSVD_PREC_MIXED = 2,    /* power passes FP32-accurate on the BF16 matrix
+                               cores: every operand split into three BF16 terms,
+                               six term products with FP32 accumulation; the final
+                               projection with every operand split into a BF16
+                               pair (hi + lo); Grams summed in FP64, small core
                                FP64; lift FP32                                  */
     PSVD_PREC_BF16 = 3      /* power passes on plain BF16 operands (the
                                unrefined sketch), the final projection as in

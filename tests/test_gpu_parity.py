@@ -3,7 +3,7 @@
 Same seeded inputs on both sides; the randomized paths use the identical test
 matrices (bit-checked).  Tolerances (sigma relative error on every mode above
 the numerical-rank floor): FP64 path 1e-10, FP32 path 1e-4, mixed path
-(FP32 power passes, split-BF16 final projection) 1e-5.  The unrefined BF16 sketch (precision "bf16") is
+(FP32-accurate three-term split power passes, split-BF16 final projection) 1e-5.  The unrefined BF16 sketch (precision "bf16") is
 held to 2e-3 in Weyl's form, |s_hat - s| <= 2e-3 s_1, on every mode (a
 perturbation of the sketch moves every Ritz value by at most its size times
 s_1), and to 2e-3 relative on the leading modes separated by a spectral gap.
