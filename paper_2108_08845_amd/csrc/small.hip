@@ -64,58 +64,130 @@ __device__ __forceinline__ bool wg_chol_upper(double* A, int n, int lda) {
     return true;
 }
 
-// Cholesky for n <= 64 on 1024 threads (a 32 x 32 grid, up to 2 x 2 trailing
-// entries per thread): out = R with G + shift I = R^T R (G read from src, n x n,
-// leading dimension n; out may be src).  The factorisation runs on a copy in S
-// (64 x 65 doubles of LDS; the odd leading dimension spreads a row over the
-// banks) with the same step order as wg_chol_upper, but every LDS read of a
-// step is issued before its arithmetic, so a step costs one LDS round trip
-// and one barrier.  Returns false (uniformly) on a non-positive or
-// non-finite pivot.
+// Leading dimension of the LDS copy of the n <= 64 Cholesky (odd: a row
+// spreads over the banks).
 constexpr int CHOL64_LD = 65;
-__device__ __forceinline__ bool wg_chol64(const double* src, int n, double shift, double* S, double* out) {
-    constexpr int ld = CHOL64_LD;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int i = e % n, j = e / n;
-        S[i + j * ld] = src[e] + (i == j ? shift : 0.0);
+
+// Cholesky for n <= 64, blocked by 16: all threads call it, out = R with
+// G + shift I = R^T R (G read from src, n x n, leading dimension n; out may be
+// src; S: 64 x 65 doubles of LDS); false, uniformly, on a non-positive or
+// non-finite pivot.
+// The matrix is padded to 16 NB rows and columns with the identity.  Per
+// diagonal block b:
+//   1. wave 0 factors the 16 x 16 diagonal block in registers (lane j < 16
+//      holds column 16b + j; the pivot and row of each step come by readlane);
+//   2. R_12 = R_11^-T A_12 for the columns to its right, one lane per column
+//      (forward substitution, R_11 read from LDS by every lane at once);
+//   3. A_22 -= R_12^T R_12 on the FP64 matrix cores, upper 16 x 16 blocks over
+//      the waves.
+// Three barriers per block instead of one per column.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// 1 / sqrt(x) for x > 0: the hardware estimate and two Newton steps (relative
+// error a few units of 2^-53; not the correctly rounded value)
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);   // 1 - x y^2
+        y = fma(0.5 * y, e, y);
     }
+    return y;
+}
+
+__device__ __forceinline__ bool wg_chol64b(const double* src, int n, double shift, double* S, double* out) {
+    constexpr int ld = CHOL64_LD;
+    __shared__ int chol_ok;
+    __shared__ double chol_rinv[64];   // 1 / R_kk
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    const int NB = (n + 15) >> 4, np = NB * 16;
+    for (int e = tid; e < np * np; e += blockDim.x) {
+        const int i = e % np, j = e / np;
+        S[i + j * ld] = (i < n && j < n) ? src[i + j * n] + (i == j ? shift : 0.0) : (i == j ? 1.0 : 0.0);
+    }
+    if (tid == 0) chol_ok = 1;
     __syncthreads();
-    const int ti = tid & 31, tj = tid >> 5;
-    const int i0 = ti, i1 = ti + 32, j0 = tj, j1 = tj + 32;
-    const int i0c = i0 < n ? i0 : n - 1, i1c = i1 < n ? i1 : n - 1;
-    const int j0c = j0 < n ? j0 : n - 1, j1c = j1 < n ? j1 : n - 1;
-    double d_prev = 1.0;
-    bool ok = true;
-    for (int k = 0; k < n; ++k) {
-        const double d = S[k + k * ld];
-        const double aki0 = S[k + i0c * ld], aki1 = S[k + i1c * ld];
-        const double akj0 = S[k + j0c * ld], akj1 = S[k + j1c * ld];
-        const double a00 = S[i0c + j0c * ld], a01 = S[i0c + j1c * ld];
-        const double a10 = S[i1c + j0c * ld], a11 = S[i1c + j1c * ld];
-        const int js = k - 1 + tid;                  // row k - 1 is scaled by threads 0 .. n - k
-        const int jsc = js < n ? js : n - 1;
-        const double sv = S[(k > 0 ? k - 1 : 0) + jsc * ld];
-        ok = ok && (d > 0.0) && finite_d(d);
-        const double invd = 1.0 / d;
-        const double f0 = akj0 * invd, f1 = akj1 * invd;
-        if (k < i0 && i0 <= j0 && j0 < n) S[i0 + j0 * ld] = fma(-aki0, f0, a00);
-        if (k < i0 && i0 <= j1 && j1 < n) S[i0 + j1 * ld] = fma(-aki0, f1, a01);
-        if (k < i1 && i1 <= j0 && j0 < n) S[i1 + j0 * ld] = fma(-aki1, f0, a10);
-        if (k < i1 && i1 <= j1 && j1 < n) S[i1 + j1 * ld] = fma(-aki1, f1, a11);
-        if (k > 0 && js < n) {
-            const double rp = sqrt(d_prev);
-            S[(k - 1) + js * ld] = (js == k - 1) ? rp : sv / rp;
+    for (int b = 0; b < NB; ++b) {
+        const int c0 = 16 * b;
+        if (w == 0) {
+            // 1. diagonal block: lane j < 16 holds column c0 + j, rows c0 .. c0 + 15
+            double a[16];
+            const int jc = c0 + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) a[i] = S[c0 + i + jc * ld];
+            bool ok = true;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const double d = readlane_d(a[k], k);
+                ok = ok && d > 0.0 && isfinite(d);
+                const double ir = rsqrt_nr(d > 0.0 ? d : 1.0);
+                // row k of R: lane k takes sqrt(d) = d / sqrt(d), the others scale.
+                // Lanes j < k change only entries below the diagonal of their
+                // finished columns, and lanes j < i below-diagonal entries of
+                // theirs: no step reads those, so every lane runs every update.
+                a[k] = (lane & 15) == k ? d * ir : a[k] * ir;
+                if (lane == k) chol_rinv[c0 + k] = ir;
+#pragma unroll
+                for (int i = k + 1; i < 16; ++i) a[i] = fma(-readlane_d(a[k], i), a[k], a[i]);   // R[k][c0 + i]
+            }
+            if (lane < 16)
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (i <= lane) S[c0 + i + jc * ld] = a[i];
+            if (lane == 0 && !ok) chol_ok = 0;
         }
         __syncthreads();
-        d_prev = d;
+        if (c0 + 16 < np) {
+            // 2. R_12: column c (right of the block) solves R_11^T x = a_c
+            for (int c = c0 + 16 + tid; c < np; c += blockDim.x) {
+                double x[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) x[i] = S[c0 + i + c * ld];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    double s = x[i];
+#pragma unroll
+                    for (int m = 0; m < i; ++m) s = fma(-S[c0 + m + (c0 + i) * ld], x[m], s);
+                    x[i] = s * chol_rinv[c0 + i];
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) S[c0 + i + c * ld] = x[i];
+            }
+            __syncthreads();
+            // 3. A_22 -= R_12^T R_12: upper 16 x 16 blocks (p <= q) of the trailing matrix
+            const int mb = NB - b - 1;
+            const int nblk = mb * (mb + 1) / 2;
+            for (int t = w; t < nblk; t += nw) {
+                int p = 0, q = t;
+                while (q >= mb - p) { q -= mb - p; ++p; }
+                q += p;                                     // p <= q < mb
+                const int cp = c0 + 16 + 16 * p, cq = c0 + 16 + 16 * q;
+                d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k4 = 0; k4 < 16; k4 += 4) {
+                    const int kk = c0 + k4 + (lane >> 4);
+                    const double av = S[kk + (cp + (lane & 15)) * ld];   // R_12^T (i, k) = R_12 (k, i)
+                    const double bv = S[kk + (cq + (lane & 15)) * ld];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = cp + (lane >> 4) + 4 * v, col = cq + (lane & 15);
+                    S[row + col * ld] -= acc[v];
+                }
+            }
+            __syncthreads();
+        }
     }
-    if (tid == 0 && n > 0) S[(n - 1) + (n - 1) * ld] = sqrt(d_prev);
-    __syncthreads();
     for (int e = tid; e < n * n; e += blockDim.x) {
         const int i = e % n, j = e / n;
         out[e] = i <= j ? S[i + j * ld] : 0.0;
     }
+    const bool ok = chol_ok != 0;
     __syncthreads();
     return ok;
 }
@@ -907,7 +979,7 @@ __device__ __forceinline__ bool chol_shifted(const double* Gsrc, double* W, int 
     const int tid = threadIdx.x;
     const bool fast = S != nullptr && l <= 64 && blockDim.x == 1024;   // S: 64 x 65 doubles of LDS
     if (fast) {
-        if (wg_chol64(Gsrc, l, 0.0, S, W)) return true;
+        if (wg_chol64b(Gsrc, l, 0.0, S, W)) return true;
     } else {
         for (int e = tid; e < l * l; e += blockDim.x) W[e] = Gsrc[e];
         __syncthreads();
@@ -927,7 +999,7 @@ __device__ __forceinline__ bool chol_shifted(const double* Gsrc, double* W, int 
     __syncthreads();
     const double shift = 11.0 * ((double)l * l + l) * 0x1p-53 * red[0];
     __syncthreads();
-    if (fast) return wg_chol64(Gsrc, l, shift, S, W);
+    if (fast) return wg_chol64b(Gsrc, l, shift, S, W);
     for (int e = tid; e < l * l; e += blockDim.x) {
         const int i = e % l, j = e / l;
         W[e] = Gsrc[e] + (i == j ? shift : 0.0);
@@ -999,7 +1071,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     // the eigen route below instead.
     bool chol_ok;
     if (staged) {
-        chol_ok = wg_chol64(a.GY, l, 0.0, Cn, W);
+        chol_ok = wg_chol64b(a.GY, l, 0.0, Cn, W);
     } else {
         for (int e = tid; e < l * l; e += SM_THREADS) W[e] = a.GY[e];
         __syncthreads();
@@ -1092,7 +1164,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
         else wg_gemm_f64(n, l, l, a.P, 1, n, V, 1, l, a.P1, 1, n, nullptr, 0);
         if (staged) wg_gram_tall(n, l, a.P1, n, W, l, Cn);
         else wg_gemm_f64(l, l, n, a.P1, n, 1, a.P1, 1, n, W, 1, l, nullptr, 0);
-        if (!(staged ? wg_chol64(W, l, 0.0, Cn, W) : wg_chol_upper(W, l, l))) return bail();
+        if (!(staged ? wg_chol64b(W, l, 0.0, Cn, W) : wg_chol_upper(W, l, l))) return bail();
         // small operands are read from LDS: R1 goes to the chunk buffer
         const double* R1 = a.R1;
         if (staged) {
