@@ -103,12 +103,17 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
     }
     // float4 loads in the lift (k_nn_v): FP32 partitions, rows and leading
     // dimensions multiples of 4, 16-byte aligned bases
-    bool vec_all = !fp64;
+    bool tn_vec = true;   // 16-byte column loads in the Grams (k_tn_v), either dtype
     for (int i = 0; i < P; ++i)
-        vec_all = vec_all && M_parts[i] % 4 == 0 && ld_parts[i] % 4 == 0 && ((uintptr_t)A_parts[i] & 15) == 0;
+        tn_vec = tn_vec && M_parts[i] % 4 == 0 && ld_parts[i] % 4 == 0 && ((uintptr_t)A_parts[i] & 15) == 0;
+    const bool vec_all = !fp64 && tn_vec;
     const int mb = (int)((N + 63) / 64);
     const int nob = mb * (mb + 1) / 2;
-    int64_t chunk = std::max<int64_t>(64, ((Mtot / std::max(1, 2048 / nob) + 63) / 64) * 64);
+    // about 2048 work-groups for the local Grams, one per (item, output block);
+    // the whole-Gram kernel (N of 65..128 with 16-byte loads) runs one per item
+    // and one per CU: at most 256 items
+    int64_t chunk = (tn_vec && mb == 2) ? chunk_for_items(M_parts, (int)P, 256)
+                                        : std::max<int64_t>(64, ((Mtot / std::max(1, 2048 / nob) + 63) / 64) * 64);
     std::vector<WorkItem> items;
     std::vector<int32_t> seg_item0(P + 1);
     for (int i = 0; i < P; ++i) {
@@ -235,6 +240,8 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
             ta.sym = 1;
             ta.part = d_part;
             ta.nob = nob;
+            ta.vec = tn_vec ? 1 : 0;
+            ta.dtype_all = dtype;
             hipError_t ce = launch_tn(true, ta, nitems, s2);
             TnReduceArgs tr;
             std::memset(&tr, 0, sizeof(tr));
@@ -310,6 +317,8 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
             wa.sym = 1;
             wa.part = d_wwpart;
             wa.nob = nobw;
+            wa.vec = (pr % 4 == 0 && ((uintptr_t)d_Wt & 15) == 0) ? 1 : 0;
+            wa.dtype_all = PSVD_F64;
             if (ce == hipSuccess && ell == 0) ce = launch_tn(true, wa, nwitems, s2);
             TnReduceArgs wr;
             std::memset(&wr, 0, sizeof(wr));
@@ -347,6 +356,7 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
             na.nx = K;
             na.all_f32 = fp64 ? 0 : 1;
             na.vec_f32 = vec_all ? 1 : 0;
+            na.vec16 = tn_vec ? 1 : 0;
             if (ce == hipSuccess) ce = launch_nn(fp64, na, nlitems, s2);
         return ce;
     };

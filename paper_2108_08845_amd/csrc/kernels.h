@@ -22,6 +22,24 @@ __host__ __device__ inline void block_coords(int y, int mbl, int sym, int* bi, i
     *bi = y - j * (j + 1) / 2;
 }
 
+// Row chunk (a multiple of 64) splitting segments of the given row counts, each
+// on its own, into at most `target` work items: the smallest such chunk (one
+// item per segment when there are more segments than that).
+inline int64_t chunk_for_items(const int64_t* rows, int nseg, int64_t target) {
+    int64_t total = 0, most = 64;
+    for (int i = 0; i < nseg; ++i) {
+        total += rows[i];
+        most = rows[i] > most ? rows[i] : most;
+    }
+    int64_t chunk = ((total + target - 1) / (target > 0 ? target : 1) + 63) / 64 * 64;
+    chunk = chunk < 64 ? 64 : chunk;
+    for (;; chunk += 64) {
+        int64_t cnt = 0;
+        for (int i = 0; i < nseg; ++i) cnt += (rows[i] + chunk - 1) / chunk;
+        if (cnt <= target || chunk >= most) return chunk;
+    }
+}
+
 struct TnArgs {
     PanelSeg lseg, rseg;     // single-segment operands (used when lsegs == nullptr)
     const PanelSeg* lsegs;   // L operand segments (device array) or nullptr
@@ -35,6 +53,11 @@ struct TnArgs {
     int32_t skip_mask;
     int32_t nob;
     int32_t nitems;          // work items (set by launch_tn)
+    int32_t vec;             // 16-byte column loads (k_tn_v): every block of both operands
+                             //   16-byte aligned, leading dimensions, segment rows and item
+                             //   row ranges multiples of 4
+    int32_t dtype_all;       // PSVD_F32 / PSVD_F64 when every column of both operands (every
+                             //   segment) has that dtype, else 0 (k_tn_w needs one)
 };
 
 struct TnReduceArgs {
@@ -70,6 +93,8 @@ struct NnArgs {
     int32_t all_f32;          // every segment's columns FP32 (k_nn_v)
     int32_t vec_f32;          // ... and float4-aligned (rows % 4 == 0, 16-byte column starts)
     int32_t nitems_v;         // work items (set by the launcher)
+    int32_t vec16;            // every block 16-byte aligned, leading dimensions, rows and item
+                              //   row ranges multiples of 4 (k_nn_m)
 };
 
 struct FusedArgs {

@@ -261,6 +261,400 @@ __global__ __launch_bounds__(256) void k_tn_reduce(TnReduceArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// k_tn_v: k_tn with 16-byte column-segment loads, for operands whose blocks
+// are 16-byte aligned with leading dimensions and row ranges in multiples of
+// four rows (TnArgs::vec).  Same work items, output blocks, partial layout
+// and skipped sub-blocks as k_tn, with 32-row tiles and a small register
+// footprint, so that four work-groups share a CU and keep four tiles' loads
+// in flight.
+//   loads  a 32-row tile of one operand is 64 columns x 16 parts: an FP64
+//          column takes parts 0..15 (rows 2p, 2p + 1), an FP32 column parts
+//          0..7 (rows 4p .. 4p + 3; parts 8..15 re-read part 7 and are
+//          dropped).  Thread t holds the parts p = t % 16 of the columns
+//          t / 16 + 16 e (e = 0..3): a quarter-wave reads 128 or 256
+//          contiguous bytes of a column per load.  Column addresses are
+//          resolved once per work-group; the next tile is in flight during the
+//          products.
+//   products the formed 16 x 16 sub-blocks of the output block are dealt to
+//          the four waves in turn (a diagonal block's ten upper sub-blocks
+//          3, 3, 2, 2), so the matrix cores of the four SIMDs get equal shares.
+// ----------------------------------------------------------------------------
+constexpr int TV_TM = 32;
+constexpr int TV_NP = 16;   // parts per column and tile
+
+template <class E>
+struct TnvLayout;
+template <>
+struct TnvLayout<double> {
+    static constexpr int LD = TV_TM + 2;   // 16-byte aligned part stores
+};
+template <>
+struct TnvLayout<float> {
+    static constexpr int LD = TV_TM + 4;
+};
+
+template <class MF, int NS>
+__device__ __forceinline__ void tnv_tile(const typename MF::elem* LR, const int* ao, const int* bo, int lane,
+                                         typename MF::acc* acc) {
+    constexpr int LD = TnvLayout<typename MF::elem>::LD;
+    const int lo = (lane & 15) * LD + (lane >> 4);
+#pragma unroll
+    for (int k0 = 0; k0 < TV_TM; k0 += MF::KSTEP) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const typename MF::elem av = LR[ao[s] + lo + k0];
+            const typename MF::elem bv = LR[bo[s] + lo + k0];
+            acc[s] = MF::mma(av, bv, acc[s]);
+        }
+    }
+}
+
+// Store part p of a staged column (NP parts per tile): FP64 data rows 2p,
+// 2p + 1; FP32 data rows 4p .. 4p + 3 (parts p < NP / 2; the lanes of parts
+// p >= NP / 2 hold a copy of part NP / 2 - 1 and write the same values there);
+// zeros where the part is not valid.  No branches: two stores of half a part
+// each (an FP64 part writes the same half twice), so the load waits before it
+// stay exact and the loads of later tiles stay in flight.
+template <class E, int NP>
+__device__ __forceinline__ void tnv_store(E* dst, f4_t v, bool f64, bool ok, int p) {
+    const int pc = p < NP / 2 ? p : NP / 2 - 1;
+    const int o1 = f64 ? 2 * p : 4 * pc, o2 = f64 ? 2 * p : 4 * pc + 2;
+    const d2_t d = __builtin_bit_cast(d2_t, v);
+    if constexpr (sizeof(E) == 8) {
+        d2_t h1 = f64 ? d : d2_t{(double)v[0], (double)v[1]};
+        d2_t h2 = f64 ? d : d2_t{(double)v[2], (double)v[3]};
+        h1 = ok ? h1 : d2_t{0.0, 0.0};
+        h2 = ok ? h2 : d2_t{0.0, 0.0};
+        *(d2_t*)(dst + o1) = h1;
+        *(d2_t*)(dst + o2) = h2;
+    } else {
+        f2_t h1 = f64 ? f2_t{(float)d[0], (float)d[1]} : f2_t{v[0], v[1]};
+        f2_t h2 = f64 ? h1 : f2_t{v[2], v[3]};
+        h1 = ok ? h1 : f2_t{0.f, 0.f};
+        h2 = ok ? h2 : f2_t{0.f, 0.f};
+        *(f2_t*)(dst + o1) = h1;
+        *(f2_t*)(dst + o2) = h2;
+    }
+}
+
+template <class CT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_tn_v(TnArgs a) {
+    using MF = Mfma<CT>;
+    using E = typename MF::elem;
+    constexpr int LD = TnvLayout<E>::LD;
+    constexpr int TSZ = TN_OB * LD;
+    constexpr int GI = TN_OB / 16;                  // sub-block rows (and columns)
+    constexpr int NSMAX = 4;                        // sub-blocks per wave (16 over four waves)
+    constexpr int NE = TN_OB * TV_NP / 256;         // column slots per thread and operand
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    __shared__ __align__(16) E LR[2 * TSZ];   // L tile, then R tile (a diagonal block uses the L tile twice)
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t bid = blockIdx.x, slot = bid >> 3;
+    const int64_t item = (slot / a.nob) * 8 + (bid & 7);
+    const int ob = (int)(slot % a.nob);
+    if (item >= a.nitems) return;
+    const WorkItem it = get_item(a.items, a.chunk, a.lseg.rows, item);
+    const PanelSeg L = a.lsegs ? load_seg(a.lsegs + it.seg) : a.lseg;
+    const PanelSeg R = a.rsegs ? load_seg(a.rsegs + it.seg) : a.rseg;
+    int obi, obj;
+    block_coords(ob, a.mbl, a.sym, &obi, &obj);
+    const int lc0 = obi * TN_OB, rc0 = obj * TN_OB;
+    const bool diag = a.sym && obi == obj;
+
+    // this wave's sub-blocks: the formed ones in row-major order, every fourth
+    // (closed form, no run-time indexed arrays)
+    const int nI = min(GI, (L.ncols - lc0 + 15) >> 4), nJ = min(GI, (R.ncols - rc0 + 15) >> 4);
+    int ns = 0, ao[NSMAX], bo[NSMAX], si[NSMAX], sj[NSMAX];
+#pragma unroll
+    for (int q = 0; q < NSMAX; ++q) {
+        const int idx = w + 4 * q;
+        int base = 0, fi = -1, fj = 0;
+#pragma unroll
+        for (int i = 0; i < GI; ++i) {
+            const int cnt = i < nI ? (diag ? max(nJ - i, 0) : nJ) : 0;
+            if (idx >= base && idx < base + cnt) {
+                fi = i;
+                fj = (diag ? i : 0) + idx - base;
+            }
+            base += cnt;
+        }
+        ns += fi >= 0 ? 1 : 0;
+        si[q] = fi >= 0 ? fi : 0;
+        sj[q] = fj;
+        ao[q] = si[q] * 16 * LD;
+        bo[q] = (diag ? 0 : TSZ) + sj[q] * 16 * LD;
+    }
+
+    // column table in LDS: base address of each column of the operand tiles
+    // (L columns, then R columns), the low bit set for FP64 columns (bases are
+    // 16-byte aligned); columns past the operand read its first column and are
+    // dropped
+    __shared__ uint64_t ctab[2 * TN_OB];
+    __shared__ uint32_t cok[2 * TN_OB];
+    if (tid < 2 * TN_OB) {
+        const int o = tid / TN_OB, c = tid % TN_OB;
+        const PanelSeg& S = o ? R : L;
+        const int cc = (o ? rc0 : lc0) + c;
+        const bool ok = cc < S.ncols && !(o && diag);
+        const ColRef cr = col_ref(S, ok ? cc : 0);
+        ctab[tid] = (uint64_t)(uintptr_t)cr.base | (cr.dtype == PSVD_F64 ? 1u : 0u);
+        cok[tid] = ok ? 1u : 0u;
+    }
+    __syncthreads();
+    const int p = tid % TV_NP, cq = tid / TV_NP;
+    f4_t pl[NE], pr[NE];
+    // rows of part p in the tile at r0: valid when inside the item (row ranges
+    // are multiples of four rows, so a part is wholly inside or outside);
+    // outside parts re-read the item's first rows.  The returned mask has bit
+    // e (L) and bit NE + e (R) for valid parts, bit 2 NE + e / 3 NE + e for FP64.
+    auto fetch = [&](int64_t r0) -> uint32_t {
+        uint32_t m = 0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+                if (o && diag) continue;
+                const int c = cq + 16 * e + o * TN_OB;
+                const uint64_t t = ctab[c];
+                const bool f64 = t & 1;
+                const int pc = f64 ? p : (p < TV_NP / 2 ? p : TV_NP / 2 - 1);
+                const int64_t row = r0 + (f64 ? 2 * pc : 4 * pc);
+                const bool ok = cok[c] && row < it.row1;
+                const int64_t rowc = ok ? row : it.row0;
+                const f4_t v = gld4((const float*)((const char*)(uintptr_t)(t & ~(uint64_t)1) + rowc * (f64 ? 8 : 4)));
+                if (o) pr[e] = v;
+                else pl[e] = v;
+                m |= (ok ? 1u : 0u) << (o * NE + e);
+                m |= (f64 ? 1u : 0u) << (2 * NE + o * NE + e);
+            }
+        return m;
+    };
+
+    // the tile loop per sub-block count: the accumulators of one count stay in
+    // the matrix-core registers for the whole loop
+    auto run = [&](auto nsc) {
+        constexpr int NS = decltype(nsc)::value;
+        typename MF::acc acc[NS > 0 ? NS : 1];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = typename MF::acc{0, 0, 0, 0};
+        uint32_t m = fetch(it.row0);
+        for (int64_t r0 = it.row0; r0 < it.row1; r0 += TV_TM) {
+            lds_barrier();
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int c = cq + 16 * e;
+                tnv_store<E, TV_NP>(LR + c * LD, pl[e], (m >> (2 * NE + e)) & 1, (m >> e) & 1, p);
+                if (!diag)
+                    tnv_store<E, TV_NP>(LR + TSZ + c * LD, pr[e], (m >> (3 * NE + e)) & 1, (m >> (NE + e)) & 1, p);
+            }
+            lds_barrier();
+            if (r0 + TV_TM < it.row1) m = fetch(r0 + TV_TM);
+            if constexpr (NS > 0) tnv_tile<MF, NS>(LR, ao, bo, lane, acc);
+        }
+        double* out = a.part + ((size_t)item * a.nob + ob) * (TN_OB * TN_OB);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = si[s] * 16 + MF::row_of(lane, v);
+                const int col = sj[s] * 16 + (lane & 15);
+                out[row + col * TN_OB] = (double)acc[s][v];
+            }
+    };
+    // waves without a sub-block still stage their share of every tile
+    switch (ns) {
+    case 4: run(std::integral_constant<int, 4>{}); break;
+    case 3: run(std::integral_constant<int, 3>{}); break;
+    case 2: run(std::integral_constant<int, 2>{}); break;
+    case 1: run(std::integral_constant<int, 1>{}); break;
+    default: run(std::integral_constant<int, 0>{}); break;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// k_tn_w: the whole upper triangle of a Gram of 65..128 columns (k_tn's output
+// blocks (0,0), (0,1), (1,1)) per work item, from one 128-column tile, so each
+// row is read once instead of once per output block; partials in k_tn's
+// per-block layout.  Operands as k_tn_v with every column of one dtype DT.
+// 512 threads, 64-row tiles: a tile column is NPART 16-byte parts (FP32: 16
+// parts of four rows, FP64: 32 parts of two rows); thread t holds part
+// t % NPART of the columns t / NPART + (512 / NPART) e.  Column addresses are
+// resolved once per work-group and advance by one tile per step; only the
+// last tile of an item checks rows.  Two tiles' loads are in flight in two
+// register sets while the matrix cores work on a third in one of two LDS
+// buffers (one barrier per tile).  Columns past the panel re-read its first
+// column: they only meet output rows and columns that are dropped.  The
+// formed 16 x 16 sub-blocks (at most 36) are dealt to the eight waves in turn.
+// ----------------------------------------------------------------------------
+constexpr int TW_TM = 64, TW_NC = 2 * TN_OB;
+
+template <class E>
+struct TnwLayout;
+template <>
+struct TnwLayout<double> {
+    static constexpr int LD = TW_TM + 2;
+};
+template <>
+struct TnwLayout<float> {
+    static constexpr int LD = TW_TM + 4;
+};
+
+template <class MF, int NS, int LD>
+__device__ __forceinline__ void tnw_tile(const typename MF::elem* T, const int* ao, const int* bo, int lane,
+                                         typename MF::acc* acc) {
+    const int lo = (lane & 15) * LD + (lane >> 4);
+    // partly unrolled: a full unroll lets the scheduler hoist every operand
+    // read of the tile and run out of registers
+#pragma unroll 4
+    for (int k0 = 0; k0 < TW_TM; k0 += MF::KSTEP) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = MF::mma(T[ao[s] + lo + k0], T[bo[s] + lo + k0], acc[s]);
+    }
+}
+
+template <class CT, bool F64>
+__global__ __launch_bounds__(512) void k_tn_w(TnArgs a) {
+    using MF = Mfma<CT>;
+    using E = typename MF::elem;
+    using D = typename std::conditional<F64, double, float>::type;   // data type
+    constexpr int LD = TnwLayout<E>::LD;
+    constexpr int TSZ = TW_NC * LD;
+    constexpr int GI = TW_NC / 16;                 // 8 sub-block rows and columns
+    constexpr int NSMAX = 5;                       // ceil(36 / 8)
+    constexpr int RPP = 16 / sizeof(D);            // rows per part
+    constexpr int NPART = TW_TM / RPP;             // parts per tile column
+    constexpr int CSTEP = 512 / NPART;             // columns between a thread's slots
+    constexpr int NE = TW_NC / CSTEP;              // slots per thread
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    extern __shared__ __align__(16) unsigned char tws[];
+    E* T0 = (E*)tws;                 // two tile buffers
+    E* T1 = T0 + TSZ;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t item = blockIdx.x;
+    if (item >= a.nitems) return;
+    const WorkItem it = get_item(a.items, a.chunk, a.lseg.rows, item);
+    const PanelSeg L = a.lsegs ? load_seg(a.lsegs + it.seg) : a.lseg;
+
+    // this wave's sub-blocks: the formed ones (i <= j) in row-major order, every eighth
+    const int nI = min(GI, (L.ncols + 15) >> 4);
+    int ns = 0, ao[NSMAX], bo[NSMAX], si[NSMAX], sj[NSMAX];
+#pragma unroll
+    for (int q = 0; q < NSMAX; ++q) {
+        const int idx = w + 8 * q;
+        int base = 0, fi = -1, fj = 0;
+#pragma unroll
+        for (int i = 0; i < GI; ++i) {
+            const int cnt = i < nI ? nI - i : 0;
+            if (idx >= base && idx < base + cnt) {
+                fi = i;
+                fj = i + idx - base;
+            }
+            base += cnt;
+        }
+        ns += fi >= 0 ? 1 : 0;
+        si[q] = fi >= 0 ? fi : 0;
+        sj[q] = fj;
+        ao[q] = si[q] * 16 * LD;
+        bo[q] = sj[q] * 16 * LD;
+    }
+
+    // slots: part p of the columns cq + CSTEP e, addresses at the item's first row
+    const int p = tid % NPART, cq = tid / NPART;
+    const D* ptr[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int c = cq + CSTEP * e;
+        ptr[e] = (const D*)col_ref(L, c < L.ncols ? c : 0).base + it.row0 + RPP * p;
+    }
+    const int64_t nt = (it.row1 - it.row0 + TW_TM - 1) / TW_TM;
+    const int64_t nrows = it.row1 - it.row0;
+    // tile t's loads: a part at or past the item's end (last tile), or a tile
+    // past the item, re-reads the item's first part (dropped); no load leaves
+    // the item's rows
+    auto fetch = [&](int64_t t, f4_t* v) {
+        const int64_t off = (t < nt && RPP * p + t * TW_TM < nrows) ? t * TW_TM : -(int64_t)(RPP * p);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) v[e] = gld4((const float*)(ptr[e] + off));
+    };
+    // tile t into LDS; rows at or past the item's end are zero (last tile only)
+    auto stage = [&](E* T, const f4_t* v, int64_t t) {
+        const bool tail = (t + 1) * TW_TM > nrows;
+        const int64_t rend = nrows - t * TW_TM;   // rows of this tile
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            E* dst = T + (cq + CSTEP * e) * LD + RPP * p;
+            f4_t x = v[e];
+            if (tail && RPP * p >= rend) x = f4_t{0.f, 0.f, 0.f, 0.f};
+            if constexpr (F64) {
+                const d2_t d = __builtin_bit_cast(d2_t, x);
+                if constexpr (sizeof(E) == 8) *(d2_t*)dst = d;
+                else *(f2_t*)dst = f2_t{(float)d[0], (float)d[1]};
+            } else {
+                if constexpr (sizeof(E) == 8) {
+                    *(d2_t*)dst = d2_t{(double)x[0], (double)x[1]};
+                    *(d2_t*)(dst + 2) = d2_t{(double)x[2], (double)x[3]};
+                } else {
+                    *(f4_t*)dst = x;
+                }
+            }
+        }
+    };
+
+    auto run = [&](auto nsc) {
+        constexpr int NS = decltype(nsc)::value;
+        typename MF::acc acc[NS > 0 ? NS : 1];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = typename MF::acc{0, 0, 0, 0};
+        f4_t va[NE], vb[NE];
+        fetch(0, va);
+        fetch(1, vb);
+        // tiles 2 u (set a, buffer 0) and 2 u + 1 (set b, buffer 1); the loads
+        // are unconditional, so every path has the same load order and each
+        // wait covers exactly the set it consumes
+        for (int64_t t = 0; t < nt; t += 2) {
+            stage(T0, va, t);
+            lds_barrier();
+            fetch(t + 2, va);
+            if constexpr (NS > 0) tnw_tile<MF, NS, LD>(T0, ao, bo, lane, acc);
+            if (t + 1 < nt) {
+                stage(T1, vb, t + 1);
+                lds_barrier();
+                if constexpr (NS > 0) tnw_tile<MF, NS, LD>(T1, ao, bo, lane, acc);
+            }
+            fetch(t + 3, vb);
+        }
+        // sub-block (si, sj) lies in output block (si / 4, sj / 4) at rows
+        // 16 (si % 4) .., columns 16 (sj % 4) ..
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int bi = si[s] >> 2, bj = sj[s] >> 2;
+            double* out = a.part + ((size_t)item * a.nob + bj * (bj + 1) / 2 + bi) * (TN_OB * TN_OB);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = (si[s] & 3) * 16 + MF::row_of(lane, v);
+                const int col = (sj[s] & 3) * 16 + (lane & 15);
+                out[row + col * TN_OB] = (double)acc[s][v];
+            }
+        }
+    };
+    switch (ns) {
+    case 5: run(std::integral_constant<int, 5>{}); break;
+    case 4: run(std::integral_constant<int, 4>{}); break;
+    case 3: run(std::integral_constant<int, 3>{}); break;
+    case 2: run(std::integral_constant<int, 2>{}); break;
+    case 1: run(std::integral_constant<int, 1>{}); break;
+    default: run(std::integral_constant<int, 0>{}); break;
+    }
+}
+
+template <class CT>
+constexpr size_t tn_w_lds() {
+    return 2 * (size_t)TW_NC * TnwLayout<CT>::LD * sizeof(CT);
+}
+
+// ----------------------------------------------------------------------------
 // k_nn: out[seg rows, ocols] = C[rows, :] X[:, ocols] (+ optional row scale).
 // grid.x = work items, grid.y = output column blocks of 64.
 // ----------------------------------------------------------------------------
@@ -530,6 +924,139 @@ __global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
                     }
                 }
                 acc[j] = f4_t{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    }
+}
+
+// k_nn_m: k_nn_v's design for panels of FP64 and FP32 blocks taking 16-byte
+// column-segment loads (NnArgs::vec16), with FP32 products (FP32 matrix
+// cores; the FP64 path keeps k_nn, which stages X in 32-row chunks).  One work-group: one 32-column
+// block of X staged in LDS once (rows k >= n zero), one item's rows in 64-row
+// tiles; C streams in 64-row x 64-column chunks into two LDS buffers (column
+// parts as k_tn_v: an FP64 column in 32 parts of two rows, an FP32 column in
+// 16 parts of four rows), the next chunk's loads in flight during this chunk's
+// products.  Wave w forms rows 16 w .. 16 w + 15 of the tile for both
+// 16-column blocks.
+// ----------------------------------------------------------------------------
+constexpr int NM_TM = 64, NM_KC = 64, NM_OB = 32;
+
+template <class E>
+struct NmLayout;
+template <>
+struct NmLayout<float> {
+    static constexpr int LDC = NM_TM + 4;
+    static constexpr int XPAD = 4;
+};
+
+template <class CT>
+__host__ __device__ inline size_t nn_m_lds(int n) {
+    const int npad = (n + NM_KC - 1) / NM_KC * NM_KC;
+    return ((size_t)NM_OB * (npad + NmLayout<CT>::XPAD) + (size_t)2 * NM_KC * NmLayout<CT>::LDC) * sizeof(CT);
+}
+
+template <class CT>
+__global__ __launch_bounds__(256) void k_nn_m(NnArgs a) {
+    using MF = Mfma<CT>;
+    using E = typename MF::elem;
+    constexpr int LDC = NmLayout<E>::LDC;
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    if (a.skip && a.need_mask && !(*a.skip & a.need_mask)) return;
+    extern __shared__ __align__(16) unsigned char nms[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nob = (a.nx + NM_OB - 1) / NM_OB;
+    const int64_t bid = blockIdx.x, slot = bid >> 3;
+    const int64_t item = (slot / nob) * 8 + (bid & 7);
+    const int ob = (int)(slot % nob);
+    if (item >= a.nitems_v) return;
+    const WorkItem it = get_item(a.items, a.chunk, a.seg.rows, item);
+    const PanelSeg S = a.segs ? load_seg(a.segs + it.seg) : a.seg;
+    const int n = a.n;
+    const int npad = (n + NM_KC - 1) / NM_KC * NM_KC;
+    const int ldX = npad + NmLayout<E>::XPAD;
+    const int oc0 = ob * NM_OB;
+    E* Xs = (E*)nms;                                  // NM_OB columns x ldX
+    E* Cb = Xs + NM_OB * ldX;                         // 2 buffers x NM_KC columns x LDC
+    for (int idx = tid; idx < NM_OB * npad; idx += 256) {
+        const int k = idx % npad, j = idx / npad;
+        double v = 0.0;
+        if (k < n && oc0 + j < a.nx) v = gldd(a.X + k + (int64_t)(oc0 + j) * a.ldx);
+        Xs[j * ldX + k] = MF::from_double(v);
+    }
+    const int nch = npad / NM_KC;
+    const int64_t rows1 = it.row1;
+    if (it.row0 >= rows1) return;
+    const int64_t ntile = (rows1 - it.row0 + NM_TM - 1) / NM_TM;
+    const int64_t nstep = ntile * nch;
+    // load slots: parts p = tid % 32 of the chunk columns tid / 32 + 8 e; columns
+    // past n re-read column n - 1 (their X rows are zero)
+    constexpr int NE = NM_KC / 8;
+    const int p = tid & 31, half = tid >> 5;
+    f4_t pf[NE];
+    uint32_t pm = 0;   // bit e: part e valid; bit NE + e: column FP64
+    auto fetch = [&](int64_t s) {
+        const int64_t r0 = it.row0 + (s / nch) * NM_TM;
+        const int kc = (int)(s % nch);
+        pm = 0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int c = kc * NM_KC + half + 8 * e;
+            const ColRef cr = col_ref(S, c < n ? c : n - 1);
+            const bool f64 = cr.dtype == PSVD_F64;
+            const int pc = f64 ? p : (p < 16 ? p : 15);
+            const int64_t row = r0 + (f64 ? 2 * pc : 4 * pc);
+            const bool ok = row < rows1;
+            const int64_t rowc = ok ? row : it.row0;
+            pf[e] = gld4((const float*)(cr.base + rowc * (f64 ? 8 : 4)));
+            pm |= (ok ? 1u : 0u) << e;
+            pm |= (f64 ? 1u : 0u) << (NE + e);
+        }
+    };
+    typename MF::acc acc[2];
+    acc[0] = typename MF::acc{0, 0, 0, 0};
+    acc[1] = acc[0];
+    fetch(0);
+    for (int64_t s = 0; s < nstep; ++s) {
+        E* cb = Cb + (s & 1) * (NM_KC * LDC);
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            tnv_store<E, 32>(cb + (half + 8 * e) * LDC, pf[e], (pm >> (NE + e)) & 1, (pm >> e) & 1, p);
+        lds_barrier();   // this chunk stored; X staged (first step)
+        if (s + 1 < nstep) fetch(s + 1);
+        const int kc = (int)(s % nch);
+        const int xo = (lane & 15) * ldX + kc * NM_KC + (lane >> 4);
+        const int co = (lane >> 4) * LDC + w * 16 + (lane & 15);
+#pragma unroll
+        for (int kk = 0; kk < NM_KC; kk += MF::KSTEP) {
+            const E av = cb[co + kk * LDC];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[j] = MF::mma(av, Xs[xo + j * 16 * ldX + kk], acc[j]);
+        }
+        if (kc == nch - 1) {   // tile complete: rows r0 + 16 w + row_of(lane, v), columns oc0 + 16 j + l
+            const int64_t r0 = it.row0 + (s / nch) * NM_TM + w * 16;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = oc0 + j * 16 + (lane & 15);
+                if (col < a.nx) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t row = r0 + MF::row_of(lane, v);
+                        if (row < rows1) {
+                            double y = (double)acc[j][v];
+                            if (a.row_scale && row < a.nscale) y *= a.row_scale[row];
+                            const size_t o = (size_t)row + (size_t)col * (size_t)S.ldo;
+                            if (S.out_dtype == PSVD_F64) {
+                                double* po = (double*)S.out + o;
+                                gstd(po, a.accumulate ? gldd(po) + y : y);
+                            } else {
+                                float* po = (float*)S.out + o;
+                                gst(po, a.accumulate ? (float)((double)gld(po) + y) : (float)y);
+                            }
+                        }
+                    }
+                }
+                acc[j] = typename MF::acc{0, 0, 0, 0};
             }
         }
     }
@@ -2610,8 +3137,26 @@ hipError_t launch_tn(bool fp64, const TnArgs& args, int nitems, hipStream_t st) 
     if (nitems <= 0 || a.nob <= 0) return hipSuccess;
     if (nwg > INT32_MAX) return hipErrorInvalidValue;
     dim3 grid((unsigned)nwg);
-    if (fp64) hipLaunchKernelGGL(k_tn<double>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(k_tn<float>, grid, dim3(256), 0, st, a);
+    if (a.vec && a.sym && a.mbl == 2 && a.lseg.ncols <= 2 * TN_OB && a.dtype_all) {
+        // the whole Gram per work item (k_tn_w): one work-group per item
+        dim3 gw((unsigned)nitems);
+        const size_t lds = fp64 ? tn_w_lds<double>() : tn_w_lds<float>();
+        const bool d64 = a.dtype_all == PSVD_F64;
+        const void* fn = fp64 ? (d64 ? (const void*)k_tn_w<double, true> : (const void*)k_tn_w<double, false>)
+                              : (d64 ? (const void*)k_tn_w<float, true> : (const void*)k_tn_w<float, false>);
+        hipError_t e = ensure_lds_attr(fn, lds);
+        if (e != hipSuccess) return e;
+        if (fp64 && d64) hipLaunchKernelGGL((k_tn_w<double, true>), gw, dim3(512), lds, st, a);
+        else if (fp64) hipLaunchKernelGGL((k_tn_w<double, false>), gw, dim3(512), lds, st, a);
+        else if (d64) hipLaunchKernelGGL((k_tn_w<float, true>), gw, dim3(512), lds, st, a);
+        else hipLaunchKernelGGL((k_tn_w<float, false>), gw, dim3(512), lds, st, a);
+    } else if (a.vec) {
+        if (fp64) hipLaunchKernelGGL(k_tn_v<double>, grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(k_tn_v<float>, grid, dim3(256), 0, st, a);
+    } else {
+        if (fp64) hipLaunchKernelGGL(k_tn<double>, grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(k_tn<float>, grid, dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -2634,6 +3179,19 @@ hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
         const int64_t blocks = (int64_t)((nitems + 7) / 8) * 8 * nob;
         if (a.vec_f32) hipLaunchKernelGGL(k_nn_v<true>, dim3((unsigned)blocks), dim3(256), lds, st, b);
         else hipLaunchKernelGGL(k_nn_v<false>, dim3((unsigned)blocks), dim3(256), lds, st, b);
+        return hipGetLastError();
+    }
+    // FP32 products on mixed-dtype panels with 16-byte loads: k_nn_m when its
+    // LDS leaves room for two work-groups per CU
+    if (!fp64 && a.vec16 && a.n >= 1 && nn_m_lds<float>(a.n) <= 80 * 1024) {
+        NnArgs b = a;
+        b.nitems_v = nitems;
+        const int nob = (a.nx + NM_OB - 1) / NM_OB;
+        const size_t lds = nn_m_lds<float>(a.n);
+        hipError_t e = ensure_lds_attr((const void*)k_nn_m<float>, lds);
+        if (e != hipSuccess) return e;
+        const int64_t blocks = (int64_t)((nitems + 7) / 8) * 8 * nob;
+        hipLaunchKernelGGL(k_nn_m<float>, dim3((unsigned)blocks), dim3(256), lds, st, b);
         return hipGetLastError();
     }
     dim3 grid(nitems, (a.nx + NN_OB - 1) / NN_OB);

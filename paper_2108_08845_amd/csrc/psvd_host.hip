@@ -392,6 +392,30 @@ static int ensure_workspace(psvd_handle* h, int n) {
 // ----------------------------------------------------------------------------
 // Panel helpers (launch + fixed-order reduction into a dense FP64 result).
 // ----------------------------------------------------------------------------
+// float4 loads need 16-byte aligned column starts: rows % 4 == 0 and every
+// leading dimension a multiple of 4 with a 16-byte aligned base.
+static bool seg_vec_ok(const PanelSeg& S, bool check_out) {
+    if (S.rows % 4) return false;
+    for (int b = 0; b < S.nblk; ++b)
+        if ((S.blk[b].ld % 4) || ((uintptr_t)S.blk[b].ptr & 15)) return false;
+    if (check_out && ((S.ldo % 4) || ((uintptr_t)S.out & 15))) return false;
+    return true;
+}
+
+static bool seg_all_f32(const PanelSeg& S) {
+    for (int b = 0; b < S.nblk; ++b)
+        if (S.blk[b].dtype != PSVD_F32) return false;
+    return true;
+}
+
+// The dtype of every block of S, or 0 when the blocks differ.
+static int seg_dtype_all(const PanelSeg& S) {
+    int d = S.nblk > 0 ? S.blk[0].dtype : 0;
+    for (int b = 1; b < S.nblk; ++b)
+        if (S.blk[b].dtype != d) d = 0;
+    return d;
+}
+
 static int64_t pick_chunk(int64_t rows, int nob, int tm, int items = 1024) {
     int64_t target = std::max<int64_t>(1, items / std::max(1, nob));
     target = std::min<int64_t>(target, items);
@@ -400,12 +424,23 @@ static int64_t pick_chunk(int64_t rows, int nob, int tm, int items = 1024) {
     return std::max<int64_t>(chunk, tm);
 }
 
+// Row chunk of a TN product: k_tn and k_tn_v run one work-group per (item,
+// output block), about `items` in all; k_tn_w (a Gram of 65..128 columns with
+// 16-byte loads) one per item and one per CU, so it takes at most 256 items.
+static bool tn_wide(bool vec, bool sym, int mbl, int dtype_all) { return vec && sym && mbl == 2 && dtype_all != 0; }
+constexpr int TN_WIDE_ITEMS = 256;
+static int64_t tn_chunk(int64_t rows, int nob, bool wide, int items) {
+    return wide ? chunk_for_items(&rows, 1, TN_WIDE_ITEMS) : pick_chunk(rows, nob, 64, items);
+}
+
 // out (nl x nr FP64) = L^T R over all rows of the single-segment operands.
 static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool sym, bool fp64, double* out,
                       const double* row_scale, int nscale, const int32_t* skip, int skip_mask) {
     const int mbl = ceil_div(L.ncols, 64), mbr = ceil_div(R.ncols, 64);
     const int nob = sym ? mbl * (mbl + 1) / 2 : mbl * mbr;
-    int64_t chunk = pick_chunk(L.rows, nob, 64, split_items(h));
+    const bool vec = seg_vec_ok(L, false) && seg_vec_ok(R, false);
+    const int dt = seg_dtype_all(L) == seg_dtype_all(R) ? seg_dtype_all(L) : 0;
+    int64_t chunk = tn_chunk(L.rows, nob, tn_wide(vec, sym, mbl, dt), split_items(h));
     int nitems = ceil_div(L.rows, chunk);
     TnArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -418,6 +453,8 @@ static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool
     a.skip = skip;
     a.skip_mask = skip_mask;
     a.nob = nob;
+    a.vec = vec ? 1 : 0;
+    a.dtype_all = dt;
     int pe = prof_begin(h, PSVD_KC_TN);
     HIPCHK(h, launch_tn(fp64, a, nitems, h->stream));
     prof_end(h, pe);
@@ -438,22 +475,6 @@ static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool
     ra.skip_mask = skip_mask;
     HIPCHK(h, launch_tn_reduce(ra, 1, h->stream));
     return PSVD_OK;
-}
-
-// float4 loads need 16-byte aligned column starts: rows % 4 == 0 and every
-// leading dimension a multiple of 4 with a 16-byte aligned base.
-static bool seg_vec_ok(const PanelSeg& S, bool check_out) {
-    if (S.rows % 4) return false;
-    for (int b = 0; b < S.nblk; ++b)
-        if ((S.blk[b].ld % 4) || ((uintptr_t)S.blk[b].ptr & 15)) return false;
-    if (check_out && ((S.ldo % 4) || ((uintptr_t)S.out & 15))) return false;
-    return true;
-}
-
-static bool seg_all_f32(const PanelSeg& S) {
-    for (int b = 0; b < S.nblk; ++b)
-        if (S.blk[b].dtype != PSVD_F32) return false;
-    return true;
 }
 
 // out (rows x nx) = S X with X (S.ncols x nx, ld ldx) FP64.
@@ -479,6 +500,7 @@ static int nn_product(psvd_handle* h, const PanelSeg& S, const double* X, int64_
     a.accumulate = accumulate;
     a.all_f32 = (!fp64 && seg_all_f32(S)) ? 1 : 0;
     a.vec_f32 = (a.all_f32 && seg_vec_ok(S, false)) ? 1 : 0;
+    a.vec16 = seg_vec_ok(S, false) ? 1 : 0;
     int pe = prof_begin(h, cls);
     HIPCHK(h, launch_nn(fp64, a, nitems, h->stream));
     prof_end(h, pe);
@@ -1182,9 +1204,13 @@ int rsvd_check(const void* A, int64_t M, int64_t N, int64_t lda, int32_t K, int3
 // Partial-sum blocks (64 x 64 FP64 each) that tn_product writes for a
 // reduction over `rows` rows into `nob` output blocks.
 size_t tn_part_bytes(int64_t rows, int nob) {
-    const int64_t chunk = pick_chunk(rows, nob, 64);
-    const int64_t nitems = (rows + chunk - 1) / chunk;
-    return (size_t)nitems * nob * 64 * 64 * sizeof(double);
+    size_t most = 0;
+    for (bool wide : {false, true}) {
+        const int64_t chunk = tn_chunk(rows, nob, wide, 1024);
+        const int64_t nitems = (rows + chunk - 1) / chunk;
+        most = std::max(most, (size_t)nitems * nob * 64 * 64 * sizeof(double));
+    }
+    return most;
 }
 
 // The one-shot randomized SVD on a handle made for it (Eqs. 7-11): one update
@@ -1810,6 +1836,8 @@ struct PartLists {
     const WorkItem* items = nullptr;
     int nitems = 0;
     int64_t chunk = 0;
+    bool vec = false;   // every segment takes 16-byte column loads (seg_vec_ok)
+    int dtype_all = 0;  // the dtype of every column of every segment, or 0
 };
 
 static std::vector<WorkItem> part_items(const psvd_handle* h, int64_t chunk) {
@@ -1845,6 +1873,8 @@ static int tn_product_parts(psvd_handle* h, const PanelSeg& S0, const PartLists&
     a.skip = skip;
     a.skip_mask = skip_mask;
     a.nob = nob;
+    a.vec = pl.vec ? 1 : 0;
+    a.dtype_all = pl.dtype_all;
     int pe = prof_begin(h, PSVD_KC_TN);
     HIPCHK(h, launch_tn(fp64, a, pl.nitems, h->stream));
     prof_end(h, pe);
@@ -1881,6 +1911,7 @@ static int nn_product_parts(psvd_handle* h, const PanelSeg& S0, const PartLists&
     a.skip = skip;
     a.skip_mask = skip_mask;
     a.need_mask = need_mask;
+    a.vec16 = pl.vec ? 1 : 0;
     int pe = prof_begin(h, cls);
     HIPCHK(h, launch_nn(fp64, a, pl.nitems, h->stream));
     prof_end(h, pe);
@@ -1994,7 +2025,20 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     }
     // descriptors: [C panels | Q1 panels | C panels writing Q1 | Gram chunks | product chunks]
     const int mbl = ceil_div(n, 64), nob = mbl * (mbl + 1) / 2;
-    const std::vector<WorkItem> tit = part_items(h, pick_chunk(h->M, nob, 64, split_items(h)));
+    bool cvec = true, qvec = true;   // 16-byte column loads for every partition
+    int cdt = seg_dtype_all(C[0]), qdt = seg_dtype_all(Q1[0]);
+    for (int i = 0; i < P; ++i) {
+        cvec = cvec && seg_vec_ok(C[i], false);
+        qvec = qvec && seg_vec_ok(Q1[i], false);
+        if (seg_dtype_all(C[i]) != cdt) cdt = 0;
+        if (seg_dtype_all(Q1[i]) != qdt) qdt = 0;
+    }
+    // one chunk for both Grams (their items share a descriptor list): the
+    // whole-Gram chunk when both take k_tn_w
+    const int64_t tchunk = (tn_wide(cvec, true, mbl, cdt) && tn_wide(qvec, true, mbl, qdt))
+                               ? chunk_for_items(h->parts.data(), P, TN_WIDE_ITEMS)
+                               : pick_chunk(h->M, nob, 64, split_items(h));
+    const std::vector<WorkItem> tit = part_items(h, tchunk);
     const int64_t nchunk = pick_chunk(h->M, ceil_div(n, 64), 64, split_items(h));
     const std::vector<WorkItem> nit = part_items(h, nchunk);
     {
@@ -2016,10 +2060,13 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     const PanelSeg* dQin = dQ + P;
     const WorkItem* dT = (const WorkItem*)(dQin + P);
     const WorkItem* dN = dT + tit.size();
-    const int64_t tchunk = pick_chunk(h->M, nob, 64, split_items(h));
     PartLists cg{dC, dT, (int)tit.size(), tchunk}, qg{dQ, dT, (int)tit.size(), tchunk};
     PartLists cn{dC, dN, (int)nit.size(), nchunk}, qn{dQ, dN, (int)nit.size(), nchunk};
     PartLists qin{dQin, dN, (int)nit.size(), nchunk};
+    cg.vec = cn.vec = qin.vec = cvec;
+    qg.vec = qn.vec = qvec;
+    cg.dtype_all = cdt;
+    qg.dtype_all = qdt;
     rc = tn_product_parts(h, C[0], cg, nob, mbl, true, L.G, nullptr, 0);
     if (rc) return rc;
     SmallArgs sa;

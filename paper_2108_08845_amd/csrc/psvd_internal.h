@@ -3,6 +3,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -31,6 +32,7 @@ inline hipError_t ensure_lds_attr(const void* fn, size_t lds) {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
 typedef short s4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;

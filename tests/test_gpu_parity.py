@@ -137,6 +137,18 @@ def test_det_fp64_gram_block_edges(M, N, K):
     compare(U, s, so, 1e-10, 1e-12, f"det n={K + N}")
 
 
+@pytest.mark.parametrize("M", [1004, 4100])
+def test_det_fp32_gram_ragged_tail(M):
+    """FP32 panels of n = 80 columns whose rows end inside a 64-row tile: the
+    whole-Gram kernel's last tile (rows past the end read as zero), against the
+    oracle."""
+    w = synth.scaled(synth.c5_gradient(), M=M, N=48, batches=3, K=32)
+    batches = synth.planted_stream(w)
+    svd, U, s = run_gpu(w, batches, "fp32", False)
+    so = run_oracle(w, batches, False, oracle.PREC_F64)
+    compare(U, s, so, 1e-4, 1e-5, f"det fp32 M={M}")
+
+
 def test_det_fp32_c5_shape():
     w = synth.scaled(synth.c5_gradient(), M=1 << 15)
     batches = synth.planted_stream(w)
