@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of the oracle sample (0: all M rows)")
     ap.add_argument("--M", type=int, default=1 << 20)
+    ap.add_argument("--graph", action="store_true",
+                    help="launch each update's kernels as one captured hipGraph instead of one by one")
     ap.add_argument("--workload", default="randomized",
                     choices=["randomized", "mixed_wide", "partitioned", "burgers", "gradient", "apmos"],
                     help="randomized: the headline mixed-precision randomized stream (M = 2^20, batches of "
@@ -81,13 +83,13 @@ def copy_probe(reps=4):
                       "ms_per_copy": ms, "GB_per_s_read_plus_write": 2 * COPY_BYTES / (ms * 1e-3) / 1e9}), flush=True)
 
 
-def run_stream(P, w, batches, precision, steps, warmup, profile):
+def run_stream(P, w, batches, precision, steps, warmup, profile, graph=True):
     """Warm up, then time exactly `steps` updates; returns (ms/step, svd, stats).
     Every precision draws the same BF16-valued test matrices, so their results
     differ only by their arithmetic."""
     svd = P.StreamingSVD(w.M, w.K, ff=w.ff, oversampling=w.oversampling, power_iters=w.power_iters,
                          randomized=True, precision=precision, seed=w.seed, async_updates=True, profile=profile,
-                         omega_bf16=True)
+                         graph=graph, omega_bf16=True)
     nb = len(batches)
     views = [b.t() for b in batches]
     for i in range(warmup):
@@ -451,7 +453,8 @@ def main():
     bytes_per_step = w.M * w.N * 4
 
     log(f"timing {args.precision}: warmup {args.warmup}, steps {args.steps}")
-    ms, svd, _ = run_stream(P, w, batches, args.precision, args.steps, args.warmup, profile=False)
+    ms, svd, _ = run_stream(P, w, batches, args.precision, args.steps, args.warmup, profile=False,
+                            graph=args.graph)
     s_main = svd.singular_values
     svd.close()
     value = bytes_per_step / (ms * 1e-3) / 1e9
@@ -538,7 +541,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "M": w.M, "N": w.N, "batches_cycled": w.batches, "K": w.K,
                    "oversampling": w.oversampling, "power_iters": w.power_iters, "ff": w.ff,
-                   "precision": args.precision, "parallelism": "single GPU"},
+                   "precision": args.precision, "launch": "hipGraph" if args.graph else "stream",
+                   "parallelism": "single GPU"},
         "frac_of_hbm_peak_ingest": value / HBM_PEAK_GBS,
         "roofline": roof,
         "kernels": per_kernel,
@@ -549,7 +553,8 @@ def main():
         # test matrices; the sigma difference over every retained mode is the
         # error of this precision, reported beside the speedup.
         log("timing the FP64 GPU path on the same batches")
-        ms64, svd64, st64 = run_stream(P, w, batches, "fp64", args.steps, args.warmup, profile=False)
+        ms64, svd64, st64 = run_stream(P, w, batches, "fp64", args.steps, args.warmup, profile=False,
+                                       graph=args.graph)
         s64 = svd64.singular_values
         svd64.close()
         out["fp64_ms_per_step"] = ms64
@@ -559,7 +564,8 @@ def main():
         if args.precision == "mixed":
             # the unrefined BF16 sketch (plain BF16 power passes), for comparison
             log("timing the unrefined BF16 sketch on the same batches")
-            msb, svdb, _ = run_stream(P, w, batches, "bf16", args.steps, args.warmup, profile=False)
+            msb, svdb, _ = run_stream(P, w, batches, "bf16", args.steps, args.warmup, profile=False,
+                                      graph=args.graph)
             sb = svdb.singular_values
             svdb.close()
             out["bf16_sketch"] = {"ms_per_step": msb, "GB_per_s": bytes_per_step / (msb * 1e-3) / 1e9,

@@ -71,9 +71,13 @@ enum {
     PSVD_OPT_ASYNC = 1,        /* do not synchronise at the end of each update     */
     PSVD_OPT_NO_FALLBACK = 2,  /* report Cholesky breakdown instead of falling back */
     PSVD_OPT_PROFILE = 4,      /* time each tall-panel kernel with HIP events      */
-    PSVD_OPT_OMEGA_BF16 = 8    /* test matrices rounded to BF16 values whatever the
+    PSVD_OPT_OMEGA_BF16 = 8,   /* test matrices rounded to BF16 values whatever the
                                   precision (the values MIXED and BF16 use), so
                                   precisions can be compared on identical ones    */
+    PSVD_OPT_GRAPH = 16        /* launch a randomized update's kernels as one
+                                  hipGraph (captured on a stream of the library,
+                                  updated in place while only arguments change)
+                                  instead of one by one; not with PSVD_OPT_PROFILE */
 };
 
 /* Kernel classes timed with PSVD_OPT_PROFILE (index into psvd_stats_t arrays). */

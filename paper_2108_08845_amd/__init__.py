@@ -59,7 +59,7 @@ class StreamingSVD:
 
     def __init__(self, M, K, ff=1.0, oversampling=0, power_iters=0, randomized=False, precision="fp64",
                  seed=0, stream=None, async_updates=False, max_sweeps=60, fallback=True, profile=False,
-                 tile_rows=0, wg_per_cu=0, omega_bf16=False, panel_width=0, split_m=0, autotuned=True):
+                 tile_rows=0, wg_per_cu=0, omega_bf16=False, panel_width=0, split_m=0, autotuned=True, graph=False):
         self._libh = _lib.load()
         opt = _lib.Options()
         self._libh.psvd_default_options(ctypes.byref(opt))
@@ -74,7 +74,8 @@ class StreamingSVD:
         opt.panel_width = int(panel_width)
         opt.split_m = int(split_m)
         opt.flags = ((_lib.OPT_ASYNC if async_updates else 0) | (0 if fallback else _lib.OPT_NO_FALLBACK)
-                     | (_lib.OPT_PROFILE if profile else 0) | (_lib.OPT_OMEGA_BF16 if omega_bf16 else 0))
+                     | (_lib.OPT_PROFILE if profile else 0) | (_lib.OPT_OMEGA_BF16 if omega_bf16 else 0)
+                     | (_lib.OPT_GRAPH if graph else 0))
         h = ctypes.c_void_p()
         rc = self._libh.psvd_initialize(ctypes.byref(h), int(M), int(K), float(ff), int(oversampling),
                                         int(power_iters), ctypes.byref(opt))

@@ -19,7 +19,7 @@ globals().update({name: code for code, name in STATUS.items()})   # PSVD_E_INVAL
 PSVD_F32, PSVD_F64 = 1, 2
 DETERMINISTIC, RANDOMIZED = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED, PREC_BF16 = 0, 1, 2, 3
-OPT_ASYNC, OPT_NO_FALLBACK, OPT_PROFILE, OPT_OMEGA_BF16 = 1, 2, 4, 8
+OPT_ASYNC, OPT_NO_FALLBACK, OPT_PROFILE, OPT_OMEGA_BF16, OPT_GRAPH = 1, 2, 4, 8, 16
 KERNEL_CLASSES = ["fused_bf16", "fused_f32", "lift", "tn", "nn", "small", "small_svd", "split", "split3"]
 
 EXPORTS = [

@@ -220,12 +220,14 @@ struct psvd_handle {
     hipEvent_t omega_used[2] = {nullptr, nullptr};  // device buffer b read by its update (main stream)
     DevBuf omega_dev[2];                          // device copies, alternating per update
     hipStream_t cstream = nullptr;                // uploads of the test matrix
+    hipStream_t gstream = nullptr;                // captures a randomized update (never runs work)
     size_t omega_host_cap = 0;
 
     psvd_stats_t stats;
     int32_t async_fallbacks_seen = 0;
     std::string err;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipGraphExec_t rgraph = nullptr;              // the last randomized update's launches (captured)
 
     // PSVD_OPT_PROFILE: event pairs around tall-panel launches, resolved at sync points.
     std::vector<hipEvent_t> prof_ev;
@@ -650,6 +652,7 @@ int psvd_initialize(psvd_handle** out, int64_t M, int32_t K, double ff, int32_t 
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->omega_used[b], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMemsetAsync(h->U[0].p, 0, h->U[0].bytes, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->U[1].p, 0, h->U[1].bytes, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->s[0].p, 0, h->s[0].bytes, h->stream);
@@ -686,6 +689,7 @@ void psvd_finalize(psvd_handle* h) {
         (void)hipStreamSynchronize(h->cstream);
         (void)hipStreamDestroy(h->cstream);
     }
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (int b = 0; b < 2; ++b) {
         if (h->omega_host[b]) (void)hipHostFree(h->omega_host[b]);
         if (h->omega_ev[b]) (void)hipEventDestroy(h->omega_ev[b]);
@@ -695,6 +699,7 @@ void psvd_finalize(psvd_handle* h) {
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->rgraph) (void)hipGraphExecDestroy(h->rgraph);
     delete h;
 }
 
@@ -912,162 +917,206 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
             HIPCHK(h, hipEventRecord(h->omega_ev[ob], h->cstream));
             HIPCHK(h, hipStreamWaitEvent(st, h->omega_ev[ob], 0));
         }
-        // status cleared, d = ff s, X' = D Omega
-        HIPCHK(h, launch_rand_begin(dstat, h->d.as<double>(), s_cur, r, h->ff, L.X, h->omega_dev[ob].as<double>(), n,
-                                    l, st));
-        if (h->cstream) HIPCHK(h, hipEventRecord(h->omega_used[ob], st));
-        const int nlb = ceil_div(l, 64);
-        // Fused passes, one read of the panel each: P = D C'^T (C' X') and, in
-        // the final pass, the kept Y = C' X' and G_Y = Y^T Y.
-        //   mixed: power passes on the BF16 matrix cores with every operand
-        //          split into three BF16 terms, six term products: FP32-accurate
-        //          (k_splitpass<., 3>); the final pass with pair splits
-        //          (k_split64), G_Y from the kept Y
-        //          (k_gram_kept); FP32 matrix cores (k_fused) on panels those
-        //          kernels do not take.  (Pairs carry about 2^-17 relative error
-        //          per operand; in the power iterations that error reaches the
-        //          tail of the sketch amplified by (s_1 / s_j)^2, so those passes
-        //          take the three-term split.)
-        //   bf16:  power passes on plain BF16 operands (k_sketch_bf16), the final
-        //          pass split-BF16 with a BF16-rounded test matrix (k_final_split)
-        //   fp32:  FP32 matrix cores (k_fused);  fp64: the generic products
-        enum { UNFUSED, SPLIT64, SKETCH_BF16, FINAL_SPLIT, FUSED_F32, SPLIT3 };
-        auto pass = [&](bool final_pass) -> int {
-            FusedPlan fp;
-            int kind = UNFUSED;
-            const bool vec = seg_vec_ok(C, false);
-            const int pw = plan_width(h, n);
-            if (!fp64 && seg_all_f32(C)) {
-                const bool mixed1 = prec == PSVD_PREC_MIXED && nlb == 1 && vec && M >= 4;
-                if (mixed1 && !final_pass && splitpass_plan(pw, 3, &fp))
-                    kind = SPLIT3;
-                else if (mixed1 && final_pass && split64_plan(pw, &fp))
-                    kind = SPLIT64;
-                else if (prec == PSVD_PREC_BF16 && !final_pass && sketch_plan(pw, h->opt.tile_rows, &fp))
-                    kind = SKETCH_BF16;
-                else if (prec == PSVD_PREC_BF16 && final_pass && nlb == 1 && split_plan(pw, &fp)) kind = FINAL_SPLIT;
-                else if ((!final_pass || nlb == 1) && fused_plan(pw, h->opt.tile_rows, &fp)) kind = FUSED_F32;
-            }
-            if (kind != UNFUSED) {
-                FusedArgs fa;
-                std::memset(&fa, 0, sizeof(fa));
-                fa.seg = C;
-                fa.X = L.X;
-                fa.ldx = n;
-                fa.n = n;
-                fa.np = fp.np;
-                fa.lx = l;
-                fa.nlb = nlb;
-                fa.tm = fp.tm;
-                fa.tiles = (M + fa.tm - 1) / fa.tm;
-                fa.nwg = fused_wgs(h, fa.tiles);
-                fa.partP = h->partP.as<float>();
-                fa.partG = h->partG.as<double>();
-                const bool kept_gram = kind == SPLIT64;   // G_Y from the kept Y
-                fa.want_g = (final_pass && !kept_gram) ? 1 : 0;
-                fa.vec = vec ? 1 : 0;
-                if (final_pass) {   // keep Y = C X for the lift (U = Y R_Y^-1 U~_K)
-                    fa.yout = h->tall.as<float>();
-                    fa.ldy = M;
+        // The launches of the range finder, lift included.  In the graph form
+        // (PSVD_OPT_GRAPH) they are captured into one hipGraph (the test-matrix
+        // upload and its wait stay outside) and launched as one, the executable
+        // graph updated in place when only the arguments changed (new batch, the
+        // other state buffers).
+        auto enqueue = [&]() -> int {
+            // status cleared, d = ff s, X' = D Omega
+            HIPCHK(h, launch_rand_begin(dstat, h->d.as<double>(), s_cur, r, h->ff, L.X, h->omega_dev[ob].as<double>(), n,
+                                        l, st));
+            const int nlb = ceil_div(l, 64);
+            // Fused passes, one read of the panel each: P = D C'^T (C' X') and, in
+            // the final pass, the kept Y = C' X' and G_Y = Y^T Y.
+            //   mixed: power passes on the BF16 matrix cores with every operand
+            //          split into three BF16 terms, six term products: FP32-accurate
+            //          (k_splitpass<., 3>); the final pass with pair splits
+            //          (k_split64), G_Y from the kept Y
+            //          (k_gram_kept); FP32 matrix cores (k_fused) on panels those
+            //          kernels do not take.  (Pairs carry about 2^-17 relative error
+            //          per operand; in the power iterations that error reaches the
+            //          tail of the sketch amplified by (s_1 / s_j)^2, so those passes
+            //          take the three-term split.)
+            //   bf16:  power passes on plain BF16 operands (k_sketch_bf16), the final
+            //          pass split-BF16 with a BF16-rounded test matrix (k_final_split)
+            //   fp32:  FP32 matrix cores (k_fused);  fp64: the generic products
+            enum { UNFUSED, SPLIT64, SKETCH_BF16, FINAL_SPLIT, FUSED_F32, SPLIT3 };
+            auto pass = [&](bool final_pass) -> int {
+                FusedPlan fp;
+                int kind = UNFUSED;
+                const bool vec = seg_vec_ok(C, false);
+                const int pw = plan_width(h, n);
+                if (!fp64 && seg_all_f32(C)) {
+                    const bool mixed1 = prec == PSVD_PREC_MIXED && nlb == 1 && vec && M >= 4;
+                    if (mixed1 && !final_pass && splitpass_plan(pw, 3, &fp))
+                        kind = SPLIT3;
+                    else if (mixed1 && final_pass && split64_plan(pw, &fp))
+                        kind = SPLIT64;
+                    else if (prec == PSVD_PREC_BF16 && !final_pass && sketch_plan(pw, h->opt.tile_rows, &fp))
+                        kind = SKETCH_BF16;
+                    else if (prec == PSVD_PREC_BF16 && final_pass && nlb == 1 && split_plan(pw, &fp)) kind = FINAL_SPLIT;
+                    else if ((!final_pass || nlb == 1) && fused_plan(pw, h->opt.tile_rows, &fp)) kind = FUSED_F32;
                 }
-                const int cls = kind == SKETCH_BF16                                      ? PSVD_KC_FUSED_BF16
-                                : (kind == SPLIT64 || kind == FINAL_SPLIT)                   ? PSVD_KC_SPLIT
-                                : kind == SPLIT3                                            ? PSVD_KC_SPLIT3
-                                                                                            : PSVD_KC_FUSED_F32;
-                int pe = prof_begin(h, cls);
-                if (kind == SPLIT3) HIPCHK(h, launch_splitpass(3, fa, st));
-                else if (kind == SPLIT64) HIPCHK(h, launch_split64(fa, st));
-                else if (kind == SKETCH_BF16) HIPCHK(h, launch_sketch_bf16(fa, st));
-                else if (kind == FINAL_SPLIT) HIPCHK(h, launch_final_split(fa, st));
-                else HIPCHK(h, launch_fused(final_pass ? 1 : 0, fa, st));
-                prof_end(h, pe);
-                if (kept_gram) {
-                    // G_Y from the kept Y, one partial per work-group of the pass
-                    int pg = prof_begin(h, PSVD_KC_TN);
-                    HIPCHK(h, launch_gram_kept(fa.yout, M, M, l, fa.nwg, fa.partG, st));
-                    prof_end(h, pg);
+                if (kind != UNFUSED) {
+                    FusedArgs fa;
+                    std::memset(&fa, 0, sizeof(fa));
+                    fa.seg = C;
+                    fa.X = L.X;
+                    fa.ldx = n;
+                    fa.n = n;
+                    fa.np = fp.np;
+                    fa.lx = l;
+                    fa.nlb = nlb;
+                    fa.tm = fp.tm;
+                    fa.tiles = (M + fa.tm - 1) / fa.tm;
+                    fa.nwg = fused_wgs(h, fa.tiles);
+                    fa.partP = h->partP.as<float>();
+                    fa.partG = h->partG.as<double>();
+                    const bool kept_gram = kind == SPLIT64;   // G_Y from the kept Y
+                    fa.want_g = (final_pass && !kept_gram) ? 1 : 0;
+                    fa.vec = vec ? 1 : 0;
+                    if (final_pass) {   // keep Y = C X for the lift (U = Y R_Y^-1 U~_K)
+                        fa.yout = h->tall.as<float>();
+                        fa.ldy = M;
+                    }
+                    const int cls = kind == SKETCH_BF16                                      ? PSVD_KC_FUSED_BF16
+                                    : (kind == SPLIT64 || kind == FINAL_SPLIT)                   ? PSVD_KC_SPLIT
+                                    : kind == SPLIT3                                            ? PSVD_KC_SPLIT3
+                                                                                                : PSVD_KC_FUSED_F32;
+                    int pe = prof_begin(h, cls);
+                    if (kind == SPLIT3) HIPCHK(h, launch_splitpass(3, fa, st));
+                    else if (kind == SPLIT64) HIPCHK(h, launch_split64(fa, st));
+                    else if (kind == SKETCH_BF16) HIPCHK(h, launch_sketch_bf16(fa, st));
+                    else if (kind == FINAL_SPLIT) HIPCHK(h, launch_final_split(fa, st));
+                    else HIPCHK(h, launch_fused(final_pass ? 1 : 0, fa, st));
+                    prof_end(h, pe);
+                    if (kept_gram) {
+                        // G_Y from the kept Y, one partial per work-group of the pass
+                        int pg = prof_begin(h, PSVD_KC_TN);
+                        HIPCHK(h, launch_gram_kept(fa.yout, M, M, l, fa.nwg, fa.partG, st));
+                        prof_end(h, pg);
+                    }
+                    FusedReduceArgs ra;
+                    std::memset(&ra, 0, sizeof(ra));
+                    ra.row_scale = dsc;
+                    ra.nscale = r;
+                    ra.partP = h->partP.as<float>();
+                    ra.partG = h->partG.as<double>();
+                    ra.nwg = fa.nwg;
+                    ra.nlb = nlb;
+                    ra.np = fa.np;
+                    ra.n = n;
+                    ra.lx = l;
+                    ra.want_g = final_pass ? 1 : 0;
+                    ra.P = L.P;
+                    ra.G = L.G_Y;
+                    HIPCHK(h, launch_fused_reduce(ra, st));
+                    return PSVD_OK;
                 }
-                FusedReduceArgs ra;
-                std::memset(&ra, 0, sizeof(ra));
-                ra.row_scale = dsc;
-                ra.nscale = r;
-                ra.partP = h->partP.as<float>();
-                ra.partG = h->partG.as<double>();
-                ra.nwg = fa.nwg;
-                ra.nlb = nlb;
-                ra.np = fa.np;
-                ra.n = n;
-                ra.lx = l;
-                ra.want_g = final_pass ? 1 : 0;
-                ra.P = L.P;
-                ra.G = L.G_Y;
-                HIPCHK(h, launch_fused_reduce(ra, st));
-                return PSVD_OK;
+                // Unfused: Y = C X' (tall temporary), P = D C^T Y, G_Y = Y^T Y.
+                PanelSeg Ys = C;
+                Ys.out = h->tall.p;
+                Ys.ldo = M;
+                Ys.out_dtype = tall_dtype;
+                int rc2 = nn_product(h, Ys, L.X, n, l, fp64, nullptr, 0, nullptr, 0);
+                if (rc2) return rc2;
+                PanelSeg Y = make_seg(M);
+                seg_add(Y, make_block(h->tall.p, M, tall_dtype, l));
+                rc2 = tn_product(h, C, Y, false, fp64, L.P, dsc, r, nullptr, 0);
+                if (rc2) return rc2;
+                if (final_pass) rc2 = tn_product(h, Y, Y, true, true, L.G_Y, nullptr, 0, nullptr, 0);
+                return rc2;
+            };
+            for (int it = 0; it < h->q; ++it) {
+                rc = pass(false);
+                if (rc) return rc;
+                rc = small_orth(h, L, n, l, L.X, dstat);   // X' = D orth(P)
+                if (rc) return rc;
             }
-            // Unfused: Y = C X' (tall temporary), P = D C^T Y, G_Y = Y^T Y.
-            PanelSeg Ys = C;
-            Ys.out = h->tall.p;
-            Ys.ldo = M;
-            Ys.out_dtype = tall_dtype;
-            int rc2 = nn_product(h, Ys, L.X, n, l, fp64, nullptr, 0, nullptr, 0);
-            if (rc2) return rc2;
-            PanelSeg Y = make_seg(M);
-            seg_add(Y, make_block(h->tall.p, M, tall_dtype, l));
-            rc2 = tn_product(h, C, Y, false, fp64, L.P, dsc, r, nullptr, 0);
-            if (rc2) return rc2;
-            if (final_pass) rc2 = tn_product(h, Y, Y, true, true, L.G_Y, nullptr, 0, nullptr, 0);
-            return rc2;
+            rc = pass(true);
+            if (rc) return rc;
+            // R_Y, Cholesky-QR2 of P, the small SVD and M2 in one work-group.
+            RandFinalArgs rf;
+            std::memset(&rf, 0, sizeof(rf));
+            rf.n = n;
+            rf.l = l;
+            rf.K = h->K;
+            rf.max_sweeps = h->opt.max_sweeps;
+            // FP32 / mixed results carry FP32 rounding: the small SVD stops once a sweep's
+            // cosines are below 2^-15 (the next sweep would leave ~2^-30); FP64 runs to m 2^-53
+            rf.stop_cos2 = fp64 ? 0.0 : 0x1p-30;
+            // the R factor of P = C^T Y: Cholesky-QR2; one pass with BF16 power passes,
+            // whose sketch error dominates (the one-pass factor is off by about
+            // kappa(P)^2 2^-53, ~1e-6 on the smallest retained value of the c2 workload)
+            rf.qr_passes = prec == PSVD_PREC_BF16 ? 1 : 2;
+            rf.P = L.P;
+            rf.P1 = L.P1;
+            rf.GY = L.G_Y;
+            rf.RY = L.RY;
+            rf.RYi = L.RYi;
+            rf.G1 = L.H;
+            rf.R1 = L.R1b;
+            rf.W = L.H2;
+            rf.V = L.Z;
+            rf.vec = L.vec;
+            rf.M2 = L.M2;
+            rf.s_out = s_new;
+            rf.small_u = L.sm_u;
+            rf.status = dstat;
+            rf.sweeps = dsweeps;
+            {
+                int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
+                HIPCHK(h, launch_small_rand_final(rf, st));
+                prof_end(h, pes);
+            }
+            // Lift from the kept sketch: U_new = Y M2 with Y = C X (= Q R_Y).
+            PanelSeg Ys = make_seg(M);
+            seg_add(Ys, make_block(h->tall.p, M, tall_dtype, l));
+            Ys.out = h->U[nxt].p;
+            Ys.ldo = h->ldu;
+            Ys.out_dtype = h->u_dtype;
+            rc = lift_product(h, Ys, L.M2, l, rk, fp64, nullptr, 0, 0);
+            if (rc) return rc;
+            return PSVD_OK;
         };
-        for (int it = 0; it < h->q; ++it) {
-            rc = pass(false);
+        const bool graph = h->cstream && h->gstream && !profiling(h) && (h->opt.flags & PSVD_OPT_GRAPH);
+        if (!graph) {
+            rc = enqueue();
             if (rc) return rc;
-            rc = small_orth(h, L, n, l, L.X, dstat);   // X' = D orth(P)
-            if (rc) return rc;
+        } else {
+            // captured on the library's own stream (the caller's may be the null
+            // stream, which cannot capture), launched on the caller's
+            hipStream_t user = st;
+            HIPCHK(h, hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+            st = h->stream = h->gstream;
+            rc = enqueue();
+            st = h->stream = user;
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(h->gstream, &g);
+            if (rc || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc ? rc : hip_fail(h, e, "update capture");
+            }
+            if (h->rgraph) {
+                hipGraphNode_t bad = nullptr;
+                hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+                if (hipGraphExecUpdate(h->rgraph, g, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+                    (void)hipGetLastError();
+                    (void)hipGraphExecDestroy(h->rgraph);
+                    h->rgraph = nullptr;
+                }
+            }
+            if (!h->rgraph) e = hipGraphInstantiate(&h->rgraph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                h->rgraph = nullptr;
+                return hip_fail(h, e, "update graph");
+            }
+            HIPCHK(h, hipGraphLaunch(h->rgraph, st));
         }
-        rc = pass(true);
-        if (rc) return rc;
-        // R_Y, Cholesky-QR2 of P, the small SVD and M2 in one work-group.
-        RandFinalArgs rf;
-        std::memset(&rf, 0, sizeof(rf));
-        rf.n = n;
-        rf.l = l;
-        rf.K = h->K;
-        rf.max_sweeps = h->opt.max_sweeps;
-        // FP32 / mixed results carry FP32 rounding: the small SVD stops once a sweep's
-        // cosines are below 2^-15 (the next sweep would leave ~2^-30); FP64 runs to m 2^-53
-        rf.stop_cos2 = fp64 ? 0.0 : 0x1p-30;
-        // the R factor of P = C^T Y: Cholesky-QR2; one pass with BF16 power passes,
-        // whose sketch error dominates (the one-pass factor is off by about
-        // kappa(P)^2 2^-53, ~1e-6 on the smallest retained value of the c2 workload)
-        rf.qr_passes = prec == PSVD_PREC_BF16 ? 1 : 2;
-        rf.P = L.P;
-        rf.P1 = L.P1;
-        rf.GY = L.G_Y;
-        rf.RY = L.RY;
-        rf.RYi = L.RYi;
-        rf.G1 = L.H;
-        rf.R1 = L.R1b;
-        rf.W = L.H2;
-        rf.V = L.Z;
-        rf.vec = L.vec;
-        rf.M2 = L.M2;
-        rf.s_out = s_new;
-        rf.small_u = L.sm_u;
-        rf.status = dstat;
-        rf.sweeps = dsweeps;
-        {
-            int pes = prof_begin(h, PSVD_KC_SMALL_SVD);
-            HIPCHK(h, launch_small_rand_final(rf, st));
-            prof_end(h, pes);
-        }
-        // Lift from the kept sketch: U_new = Y M2 with Y = C X (= Q R_Y).
-        PanelSeg Ys = make_seg(M);
-        seg_add(Ys, make_block(h->tall.p, M, tall_dtype, l));
-        Ys.out = h->U[nxt].p;
-        Ys.ldo = h->ldu;
-        Ys.out_dtype = h->u_dtype;
-        rc = lift_product(h, Ys, L.M2, l, rk, fp64, nullptr, 0, 0);
-        if (rc) return rc;
+        // the test-matrix buffer is free for the upload two batches on
+        if (h->cstream) HIPCHK(h, hipEventRecord(h->omega_used[ob], st));
     }
     if (h->ev1) HIPCHK(h, hipEventRecord(h->ev1, st));
     const int prev_r = h->r;

@@ -119,6 +119,31 @@ def test_checkpoint_resume_is_bitwise(precision, randomized):
     assert np.array_equal(a.singular_values, c.singular_values)
 
 
+@pytest.mark.parametrize("precision,async_updates", [("mixed", True), ("fp32", False), ("fp64", True)])
+def test_graph_updates_match_eager_launches(precision, async_updates):
+    """A randomized update run as one captured hipGraph (graph=True: updated in
+    place when only the batch and the state buffers change) and the same updates
+    launched one by one give bit-identical modes and singular values after every
+    update, with eager work and synchronisation of the program between the
+    replays."""
+    w = synth.scaled(synth.c2_randomized_fp32(), M=1 << 13, N=48, batches=6, K=12)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    bs = [b.to(dt).cuda() for b in synth.planted_stream(w)]
+    P = lib()
+    kw = dict(ff=w.ff, oversampling=6, power_iters=2, randomized=True, precision=precision, seed=5,
+              async_updates=async_updates)
+    g = P.StreamingSVD(w.M, w.K, graph=True, **kw)
+    e = P.StreamingSVD(w.M, w.K, graph=False, **kw)
+    for b in bs + bs[:2]:
+        g.incorporate_data(b.t())
+        scratch = (b.double() * 2.0).sum()   # eager work between the replays
+        e.incorporate_data(b.t())
+        torch.cuda.synchronize()
+        assert torch.isfinite(scratch)
+        assert np.array_equal(g.singular_values, e.singular_values)
+        assert torch.equal(g.modes, e.modes)
+
+
 def test_async_device_error_surfaces_at_next_sync():
     # With asynchronous updates a device-side failure (here NaN data reaching
     # the small factorisation) is reported by the next synchronising call.
