@@ -110,9 +110,9 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
     const int mb = (int)((N + 63) / 64);
     const int nob = mb * (mb + 1) / 2;
     // about 2048 work-groups for the local Grams, one per (item, output block);
-    // the whole-Gram kernel (N of 65..128 with 16-byte loads) runs one per item
-    // and one per CU: at most 256 items
-    int64_t chunk = (tn_vec && mb == 2) ? chunk_for_items(M_parts, (int)P, 256)
+    // the whole-Gram kernel (N of 65..128) runs one per item and one per CU: at
+    // most 256 items
+    int64_t chunk = (mb == 2) ? chunk_for_items(M_parts, (int)P, 256)
                                         : std::max<int64_t>(64, ((Mtot / std::max(1, 2048 / nob) + 63) / 64) * 64);
     std::vector<WorkItem> items;
     std::vector<int32_t> seg_item0(P + 1);

@@ -476,10 +476,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // k_tn_w: the whole upper triangle of a Gram of 65..128 columns (k_tn's output
 // blocks (0,0), (0,1), (1,1)) per work item, from one 128-column tile, so each
 // row is read once instead of once per output block; partials in k_tn's
-// per-block layout.  Operands as k_tn_v with every column of one dtype DT.
-// 512 threads, 64-row tiles: a tile column is NPART 16-byte parts (FP32: 16
-// parts of four rows, FP64: 32 parts of two rows); thread t holds part
-// t % NPART of the columns t / NPART + (512 / NPART) e.  Column addresses are
+// per-block layout.  Every column of one dtype (F64); VEC: operands as k_tn_v
+// (16-byte column loads), else any alignment and row count (one element per
+// lane).  512 threads, 64-row tiles: a tile column is NPART parts of 16 bytes
+// (VEC; FP32: 16 parts of four rows, FP64: 32 parts of two rows) or of one
+// element (64 parts); thread t holds part t % NPART of the columns
+// t / NPART + (512 / NPART) e.  Column addresses are
 // resolved once per work-group and advance by one tile per step; only the
 // last tile of an item checks rows.  Two tiles' loads are in flight in two
 // register sets while the matrix cores work on a third in one of two LDS
@@ -513,16 +515,17 @@ __device__ __forceinline__ void tnw_tile(const typename MF::elem* T, const int* 
     }
 }
 
-template <class CT, bool F64>
+template <class CT, bool F64, bool VEC>
 __global__ __launch_bounds__(512) void k_tn_w(TnArgs a) {
     using MF = Mfma<CT>;
     using E = typename MF::elem;
     using D = typename std::conditional<F64, double, float>::type;   // data type
+    using V = typename std::conditional<VEC, f4_t, D>::type;          // one part
     constexpr int LD = TnwLayout<E>::LD;
     constexpr int TSZ = TW_NC * LD;
     constexpr int GI = TW_NC / 16;                 // 8 sub-block rows and columns
     constexpr int NSMAX = 5;                       // ceil(36 / 8)
-    constexpr int RPP = 16 / sizeof(D);            // rows per part
+    constexpr int RPP = VEC ? 16 / sizeof(D) : 1;  // rows per part
     constexpr int NPART = TW_TM / RPP;             // parts per tile column
     constexpr int CSTEP = 512 / NPART;             // columns between a thread's slots
     constexpr int NE = TW_NC / CSTEP;              // slots per thread
@@ -573,18 +576,25 @@ __global__ __launch_bounds__(512) void k_tn_w(TnArgs a) {
     // tile t's loads: a part at or past the item's end (last tile), or a tile
     // past the item, re-reads the item's first part (dropped); no load leaves
     // the item's rows
-    auto fetch = [&](int64_t t, f4_t* v) {
+    auto fetch = [&](int64_t t, V* v) {
         const int64_t off = (t < nt && RPP * p + t * TW_TM < nrows) ? t * TW_TM : -(int64_t)(RPP * p);
 #pragma unroll
-        for (int e = 0; e < NE; ++e) v[e] = gld4((const float*)(ptr[e] + off));
+        for (int e = 0; e < NE; ++e) {
+            if constexpr (VEC) v[e] = gld4((const float*)(ptr[e] + off));
+            else v[e] = *(const PSVD_GLOBAL D*)(ptr[e] + off);
+        }
     };
     // tile t into LDS; rows at or past the item's end are zero (last tile only)
-    auto stage = [&](E* T, const f4_t* v, int64_t t) {
+    auto stage = [&](E* T, const V* v, int64_t t) {
         const bool tail = (t + 1) * TW_TM > nrows;
         const int64_t rend = nrows - t * TW_TM;   // rows of this tile
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             E* dst = T + (cq + CSTEP * e) * LD + RPP * p;
+            if constexpr (!VEC) {
+                *dst = (tail && p >= rend) ? (E)0 : (E)v[e];
+                continue;
+            }
             f4_t x = v[e];
             if (tail && RPP * p >= rend) x = f4_t{0.f, 0.f, 0.f, 0.f};
             if constexpr (F64) {
@@ -607,7 +617,7 @@ __global__ __launch_bounds__(512) void k_tn_w(TnArgs a) {
         typename MF::acc acc[NS > 0 ? NS : 1];
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc[s] = typename MF::acc{0, 0, 0, 0};
-        f4_t va[NE], vb[NE];
+        V va[NE], vb[NE];
         fetch(0, va);
         fetch(1, vb);
         // tiles 2 u (set a, buffer 0) and 2 u + 1 (set b, buffer 1); the loads
@@ -3137,19 +3147,26 @@ hipError_t launch_tn(bool fp64, const TnArgs& args, int nitems, hipStream_t st) 
     if (nitems <= 0 || a.nob <= 0) return hipSuccess;
     if (nwg > INT32_MAX) return hipErrorInvalidValue;
     dim3 grid((unsigned)nwg);
-    if (a.vec && a.sym && a.mbl == 2 && a.lseg.ncols <= 2 * TN_OB && a.dtype_all) {
+    if (a.sym && a.mbl == 2 && a.lseg.ncols <= 2 * TN_OB && a.dtype_all) {
         // the whole Gram per work item (k_tn_w): one work-group per item
         dim3 gw((unsigned)nitems);
         const size_t lds = fp64 ? tn_w_lds<double>() : tn_w_lds<float>();
         const bool d64 = a.dtype_all == PSVD_F64;
-        const void* fn = fp64 ? (d64 ? (const void*)k_tn_w<double, true> : (const void*)k_tn_w<double, false>)
-                              : (d64 ? (const void*)k_tn_w<float, true> : (const void*)k_tn_w<float, false>);
-        hipError_t e = ensure_lds_attr(fn, lds);
+        auto go = [&](auto kern) -> hipError_t {
+            hipError_t e = ensure_lds_attr((const void*)kern, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kern, gw, dim3(512), lds, st, a);
+            return hipSuccess;
+        };
+        hipError_t e;
+        if (a.vec) {
+            if (fp64) e = d64 ? go(k_tn_w<double, true, true>) : go(k_tn_w<double, false, true>);
+            else e = d64 ? go(k_tn_w<float, true, true>) : go(k_tn_w<float, false, true>);
+        } else {
+            if (fp64) e = d64 ? go(k_tn_w<double, true, false>) : go(k_tn_w<double, false, false>);
+            else e = d64 ? go(k_tn_w<float, true, false>) : go(k_tn_w<float, false, false>);
+        }
         if (e != hipSuccess) return e;
-        if (fp64 && d64) hipLaunchKernelGGL((k_tn_w<double, true>), gw, dim3(512), lds, st, a);
-        else if (fp64) hipLaunchKernelGGL((k_tn_w<double, false>), gw, dim3(512), lds, st, a);
-        else if (d64) hipLaunchKernelGGL((k_tn_w<float, true>), gw, dim3(512), lds, st, a);
-        else hipLaunchKernelGGL((k_tn_w<float, false>), gw, dim3(512), lds, st, a);
     } else if (a.vec) {
         if (fp64) hipLaunchKernelGGL(k_tn_v<double>, grid, dim3(256), 0, st, a);
         else hipLaunchKernelGGL(k_tn_v<float>, grid, dim3(256), 0, st, a);

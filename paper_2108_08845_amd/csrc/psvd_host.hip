@@ -427,9 +427,9 @@ static int64_t pick_chunk(int64_t rows, int nob, int tm, int items = 1024) {
 }
 
 // Row chunk of a TN product: k_tn and k_tn_v run one work-group per (item,
-// output block), about `items` in all; k_tn_w (a Gram of 65..128 columns with
-// 16-byte loads) one per item and one per CU, so it takes at most 256 items.
-static bool tn_wide(bool vec, bool sym, int mbl, int dtype_all) { return vec && sym && mbl == 2 && dtype_all != 0; }
+// output block), about `items` in all; k_tn_w (a Gram of 65..128 columns of
+// one dtype) one per item and one per CU, so it takes at most 256 items.
+static bool tn_wide(bool sym, int mbl, int dtype_all) { return sym && mbl == 2 && dtype_all != 0; }
 constexpr int TN_WIDE_ITEMS = 256;
 static int64_t tn_chunk(int64_t rows, int nob, bool wide, int items) {
     return wide ? chunk_for_items(&rows, 1, TN_WIDE_ITEMS) : pick_chunk(rows, nob, 64, items);
@@ -442,7 +442,7 @@ static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool
     const int nob = sym ? mbl * (mbl + 1) / 2 : mbl * mbr;
     const bool vec = seg_vec_ok(L, false) && seg_vec_ok(R, false);
     const int dt = seg_dtype_all(L) == seg_dtype_all(R) ? seg_dtype_all(L) : 0;
-    int64_t chunk = tn_chunk(L.rows, nob, tn_wide(vec, sym, mbl, dt), split_items(h));
+    int64_t chunk = tn_chunk(L.rows, nob, tn_wide(sym, mbl, dt), split_items(h));
     int nitems = ceil_div(L.rows, chunk);
     TnArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -2084,7 +2084,7 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     }
     // one chunk for both Grams (their items share a descriptor list): the
     // whole-Gram chunk when both take k_tn_w
-    const int64_t tchunk = (tn_wide(cvec, true, mbl, cdt) && tn_wide(qvec, true, mbl, qdt))
+    const int64_t tchunk = (tn_wide(true, mbl, cdt) && tn_wide(true, mbl, qdt))
                                ? chunk_for_items(h->parts.data(), P, TN_WIDE_ITEMS)
                                : pick_chunk(h->M, nob, 64, split_items(h));
     const std::vector<WorkItem> tit = part_items(h, tchunk);
