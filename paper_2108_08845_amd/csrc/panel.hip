@@ -1072,6 +1072,156 @@ __global__ __launch_bounds__(256) void k_nn_m(NnArgs a) {
     }
 }
 
+// k_nn_w: C X with FP64 products (FP64 matrix cores, 16x16x4) on panels of
+// FP64 and FP32 blocks taking 16-byte column-segment loads (NnArgs::vec16), n
+// up to ND_NMAX.  512 threads, one work-group per CU: the work (item, 32-column
+// output block) pairs are dealt to the work-groups in turn, each work-group
+// keeping one output block, so its X block (rows k >= n zero) is staged in LDS
+// once, row-major (the 16-column fragment reads are contiguous); the column
+// addresses of each item's segment sit in an LDS table.  C streams in 64-row x 64-column chunks (column parts as k_nn_m: an
+// FP64 column in 32 parts of two rows, an FP32 column in 16 parts of four
+// rows, four parts per thread): two chunks' loads in flight in two register
+// sets while the matrix cores work on a third in one of two LDS buffers (one
+// barrier per chunk).  Wave w forms rows 16 (w % 4) .. of the tile for the
+// 16-column block w / 4, its k-steps alternating between two accumulators.
+// ----------------------------------------------------------------------------
+constexpr int ND_TM = 64, ND_KC = 64, ND_OB = 32, ND_LDC = ND_TM + 2, ND_NMAX = 320;
+constexpr int ND_WGS = 256;   // work-groups (one per CU)
+
+__host__ __device__ inline size_t nn_w_lds(int n) {
+    const int npad = (n + ND_KC - 1) / ND_KC * ND_KC;
+    return ((size_t)npad * ND_OB + (size_t)2 * ND_KC * ND_LDC) * sizeof(double) + (size_t)npad * sizeof(uint64_t);
+}
+
+__global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    if (a.skip && a.need_mask && !(*a.skip & a.need_mask)) return;
+    extern __shared__ __align__(16) double nws[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nob = (a.nx + ND_OB - 1) / ND_OB;
+    const int64_t nwork = (int64_t)a.nitems_v * nob;
+    const int64_t gstep = gridDim.x;   // a multiple of nob: each work-group keeps one output block
+    if ((int64_t)blockIdx.x >= nwork) return;
+    const int ob = (int)(blockIdx.x % nob);
+    const int n = a.n;
+    const int npad = (n + ND_KC - 1) / ND_KC * ND_KC;
+    const int oc0 = ob * ND_OB;
+    double* Xs = nws;                                 // npad rows x ND_OB (row-major: the
+                                                      // fragment reads of 16 columns are contiguous)
+    double* Cb = Xs + npad * ND_OB;                   // 2 buffers x ND_KC columns x ND_LDC
+    uint64_t* ctab = (uint64_t*)(Cb + 2 * ND_KC * ND_LDC);   // column c: base | FP64 bit (columns past n: n - 1)
+    for (int idx = tid; idx < ND_OB * npad; idx += 512) {
+        const int k = idx % npad, j = idx / npad;
+        double v = 0.0;
+        if (k < n && oc0 + j < a.nx) v = gldd(a.X + k + (int64_t)(oc0 + j) * a.ldx);
+        Xs[k * ND_OB + j] = v;
+    }
+    const int nch = npad / ND_KC;
+    constexpr int NE = ND_KC * 32 / 512;   // slots per thread
+    const int p = tid & 31, cq = tid >> 5;
+    const int rb = w & 3, jb = w >> 2;
+    const int xo = (lane >> 4) * ND_OB + jb * 16 + (lane & 15);
+    const int co = (lane >> 4) * ND_LDC + rb * 16 + (lane & 15);
+
+    for (int64_t wi = blockIdx.x; wi < nwork; wi += gstep) {
+        const int64_t item = wi / nob;
+        const WorkItem it = get_item(a.items, a.chunk, a.seg.rows, item);
+        const PanelSeg S = a.segs ? load_seg(a.segs + it.seg) : a.seg;
+        const int64_t rows1 = it.row1;
+        const int64_t ntile = (rows1 - it.row0 + ND_TM - 1) / ND_TM;
+        const int64_t nstep = ntile * nch;
+        for (int c = tid; c < npad; c += 512) {   // read after the first barrier below
+            const ColRef cr = col_ref(S, c < n ? c : n - 1);
+            ctab[c] = (uint64_t)(uintptr_t)cr.base | (cr.dtype == PSVD_F64 ? 1u : 0u);
+        }
+        __syncthreads();
+        // step s: chunk s % nch of tile s / nch; steps past the item re-read
+        // its first rows, parts at or past its end the item's first part
+        // (both dropped); columns past n re-read column n - 1 (X rows zero)
+        auto fetch = [&](int64_t s, f4_t* v) -> uint32_t {
+            const int64_t sc = s < nstep ? s : 0;
+            const int64_t r0 = it.row0 + (sc / nch) * ND_TM;
+            const int kc = (int)(sc % nch);
+            uint32_t m = 0;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const uint64_t t = ctab[kc * ND_KC + cq + 16 * e];
+                const bool f64 = t & 1;
+                const int pc = f64 ? p : (p < 16 ? p : 15);
+                const int64_t row = r0 + (f64 ? 2 * pc : 4 * pc);
+                const bool ok = s < nstep && row < rows1;
+                const int64_t rowc = ok ? row : it.row0;
+                v[e] = gld4((const float*)((const char*)(uintptr_t)(t & ~(uint64_t)1) + rowc * (f64 ? 8 : 4)));
+                m |= (ok ? 1u : 0u) << e;
+                m |= (f64 ? 1u : 0u) << (NE + e);
+            }
+            return m;
+        };
+        auto stage = [&](double* cb, const f4_t* v, uint32_t m) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e)
+                tnv_store<double, 32>(cb + (cq + 16 * e) * ND_LDC, v[e], (m >> (NE + e)) & 1, (m >> e) & 1, p);
+        };
+        d4_t acc0 = d4_t{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+        auto compute = [&](const double* cb, int64_t s) {
+            const int kc = (int)(s % nch);
+#pragma unroll
+            for (int kk = 0; kk < ND_KC; kk += 8) {
+                const int xk = (kc * ND_KC + kk) * ND_OB;
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[co + kk * ND_LDC], Xs[xo + xk], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[co + (kk + 4) * ND_LDC], Xs[xo + xk + 4 * ND_OB], acc1,
+                                                            0, 0, 0);
+            }
+            if (kc == nch - 1) {   // tile complete: rows r0 + 16 rb + g + 4 v, column oc0 + 16 jb + l
+                const d4_t y4 = acc0 + acc1;
+                acc0 = d4_t{0.0, 0.0, 0.0, 0.0};
+                acc1 = acc0;
+                const int64_t r0 = it.row0 + (s / nch) * ND_TM + rb * 16 + (lane >> 4);
+                const int col = oc0 + jb * 16 + (lane & 15);
+                if (col < a.nx) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t row = r0 + 4 * v;
+                        if (row < rows1) {
+                            double y = y4[v];
+                            if (a.row_scale && row < a.nscale) y *= a.row_scale[row];
+                            const size_t o = (size_t)row + (size_t)col * (size_t)S.ldo;
+                            if (S.out_dtype == PSVD_F64) {
+                                double* po = (double*)S.out + o;
+                                gstd(po, a.accumulate ? gldd(po) + y : y);
+                            } else {
+                                float* po = (float*)S.out + o;
+                                gst(po, a.accumulate ? (float)((double)gld(po) + y) : (float)y);
+                            }
+                        }
+                    }
+                }
+            }
+        };
+        f4_t va[NE], vb[NE];
+        uint32_t ma = fetch(0, va);
+        uint32_t mb = fetch(1, vb);
+        double* C0 = Cb;
+        double* C1 = Cb + ND_KC * ND_LDC;
+        // steps 2 u (set a, buffer 0) and 2 u + 1 (set b, buffer 1); the loads are
+        // unconditional, so each wait covers exactly the set it consumes
+        for (int64_t s = 0; s < nstep; s += 2) {
+            stage(C0, va, ma);
+            lds_barrier();   // chunk s stored (X staged, first step); chunk s - 1 read by all
+            ma = fetch(s + 2, va);
+            compute(C0, s);
+            if (s + 1 < nstep) {
+                stage(C1, vb, mb);
+                lds_barrier();
+                compute(C1, s + 1);
+            }
+            mb = fetch(s + 3, vb);
+        }
+        lds_barrier();   // the last chunks read before the next work pair restages the buffers
+    }
+}
+
 // X (FP64, column-major) element (min(k, n-1), min(j, lx-1)).  Padding rows
 // k >= n only meet panel columns that are zero, and padding columns j >= lx
 // only feed outputs that are never read back (partials beyond lx, Y columns
@@ -3209,6 +3359,19 @@ hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
         if (e != hipSuccess) return e;
         const int64_t blocks = (int64_t)((nitems + 7) / 8) * 8 * nob;
         hipLaunchKernelGGL(k_nn_m<float>, dim3((unsigned)blocks), dim3(256), lds, st, b);
+        return hipGetLastError();
+    }
+    // FP64 products on panels with 16-byte loads: k_nn_w, one work-group per CU
+    if (fp64 && a.vec16 && a.n >= 1 && a.n <= ND_NMAX) {
+        NnArgs b = a;
+        b.nitems_v = nitems;
+        const int nob = (a.nx + ND_OB - 1) / ND_OB;
+        const size_t lds = nn_w_lds(a.n);
+        hipError_t e = ensure_lds_attr((const void*)k_nn_w, lds);
+        if (e != hipSuccess) return e;
+        const int64_t work = (int64_t)nitems * nob;
+        const int64_t wgs = std::min<int64_t>(work, (ND_WGS / nob) * nob);
+        hipLaunchKernelGGL(k_nn_w, dim3((unsigned)wgs), dim3(512), lds, st, b);
         return hipGetLastError();
     }
     dim3 grid(nitems, (a.nx + NN_OB - 1) / NN_OB);
