@@ -94,7 +94,7 @@ struct NnArgs {
     int32_t vec_f32;          // ... and float4-aligned (rows % 4 == 0, 16-byte column starts)
     int32_t nitems_v;         // work items (set by the launcher)
     int32_t vec16;            // every block 16-byte aligned, leading dimensions, rows and item
-                              //   row ranges multiples of 4 (k_nn_m)
+                              //   row ranges multiples of 4 (k_nn_w)
 };
 
 struct FusedArgs {

@@ -939,164 +939,46 @@ __global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
     }
 }
 
-// k_nn_m: k_nn_v's design for panels of FP64 and FP32 blocks taking 16-byte
-// column-segment loads (NnArgs::vec16), with FP32 products (FP32 matrix
-// cores; the FP64 path keeps k_nn, which stages X in 32-row chunks).  One work-group: one 32-column
-// block of X staged in LDS once (rows k >= n zero), one item's rows in 64-row
-// tiles; C streams in 64-row x 64-column chunks into two LDS buffers (column
-// parts as k_tn_v: an FP64 column in 32 parts of two rows, an FP32 column in
-// 16 parts of four rows), the next chunk's loads in flight during this chunk's
-// products.  Wave w forms rows 16 w .. 16 w + 15 of the tile for both
-// 16-column blocks.
-// ----------------------------------------------------------------------------
-constexpr int NM_TM = 64, NM_KC = 64, NM_OB = 32;
 
-template <class E>
-struct NmLayout;
-template <>
-struct NmLayout<float> {
-    static constexpr int LDC = NM_TM + 4;
-    static constexpr int XPAD = 4;
-};
-
-template <class CT>
-__host__ __device__ inline size_t nn_m_lds(int n) {
-    const int npad = (n + NM_KC - 1) / NM_KC * NM_KC;
-    return ((size_t)NM_OB * (npad + NmLayout<CT>::XPAD) + (size_t)2 * NM_KC * NmLayout<CT>::LDC) * sizeof(CT);
-}
-
-template <class CT>
-__global__ __launch_bounds__(256) void k_nn_m(NnArgs a) {
-    using MF = Mfma<CT>;
-    using E = typename MF::elem;
-    constexpr int LDC = NmLayout<E>::LDC;
-    if (a.skip && (*a.skip & a.skip_mask)) return;
-    if (a.skip && a.need_mask && !(*a.skip & a.need_mask)) return;
-    extern __shared__ __align__(16) unsigned char nms[];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nob = (a.nx + NM_OB - 1) / NM_OB;
-    const int64_t bid = blockIdx.x, slot = bid >> 3;
-    const int64_t item = (slot / nob) * 8 + (bid & 7);
-    const int ob = (int)(slot % nob);
-    if (item >= a.nitems_v) return;
-    const WorkItem it = get_item(a.items, a.chunk, a.seg.rows, item);
-    const PanelSeg S = a.segs ? load_seg(a.segs + it.seg) : a.seg;
-    const int n = a.n;
-    const int npad = (n + NM_KC - 1) / NM_KC * NM_KC;
-    const int ldX = npad + NmLayout<E>::XPAD;
-    const int oc0 = ob * NM_OB;
-    E* Xs = (E*)nms;                                  // NM_OB columns x ldX
-    E* Cb = Xs + NM_OB * ldX;                         // 2 buffers x NM_KC columns x LDC
-    for (int idx = tid; idx < NM_OB * npad; idx += 256) {
-        const int k = idx % npad, j = idx / npad;
-        double v = 0.0;
-        if (k < n && oc0 + j < a.nx) v = gldd(a.X + k + (int64_t)(oc0 + j) * a.ldx);
-        Xs[j * ldX + k] = MF::from_double(v);
-    }
-    const int nch = npad / NM_KC;
-    const int64_t rows1 = it.row1;
-    if (it.row0 >= rows1) return;
-    const int64_t ntile = (rows1 - it.row0 + NM_TM - 1) / NM_TM;
-    const int64_t nstep = ntile * nch;
-    // load slots: parts p = tid % 32 of the chunk columns tid / 32 + 8 e; columns
-    // past n re-read column n - 1 (their X rows are zero)
-    constexpr int NE = NM_KC / 8;
-    const int p = tid & 31, half = tid >> 5;
-    f4_t pf[NE];
-    uint32_t pm = 0;   // bit e: part e valid; bit NE + e: column FP64
-    auto fetch = [&](int64_t s) {
-        const int64_t r0 = it.row0 + (s / nch) * NM_TM;
-        const int kc = (int)(s % nch);
-        pm = 0;
-#pragma unroll
-        for (int e = 0; e < NE; ++e) {
-            const int c = kc * NM_KC + half + 8 * e;
-            const ColRef cr = col_ref(S, c < n ? c : n - 1);
-            const bool f64 = cr.dtype == PSVD_F64;
-            const int pc = f64 ? p : (p < 16 ? p : 15);
-            const int64_t row = r0 + (f64 ? 2 * pc : 4 * pc);
-            const bool ok = row < rows1;
-            const int64_t rowc = ok ? row : it.row0;
-            pf[e] = gld4((const float*)(cr.base + rowc * (f64 ? 8 : 4)));
-            pm |= (ok ? 1u : 0u) << e;
-            pm |= (f64 ? 1u : 0u) << (NE + e);
-        }
-    };
-    typename MF::acc acc[2];
-    acc[0] = typename MF::acc{0, 0, 0, 0};
-    acc[1] = acc[0];
-    fetch(0);
-    for (int64_t s = 0; s < nstep; ++s) {
-        E* cb = Cb + (s & 1) * (NM_KC * LDC);
-#pragma unroll
-        for (int e = 0; e < NE; ++e)
-            tnv_store<E, 32>(cb + (half + 8 * e) * LDC, pf[e], (pm >> (NE + e)) & 1, (pm >> e) & 1, p);
-        lds_barrier();   // this chunk stored; X staged (first step)
-        if (s + 1 < nstep) fetch(s + 1);
-        const int kc = (int)(s % nch);
-        const int xo = (lane & 15) * ldX + kc * NM_KC + (lane >> 4);
-        const int co = (lane >> 4) * LDC + w * 16 + (lane & 15);
-#pragma unroll
-        for (int kk = 0; kk < NM_KC; kk += MF::KSTEP) {
-            const E av = cb[co + kk * LDC];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[j] = MF::mma(av, Xs[xo + j * 16 * ldX + kk], acc[j]);
-        }
-        if (kc == nch - 1) {   // tile complete: rows r0 + 16 w + row_of(lane, v), columns oc0 + 16 j + l
-            const int64_t r0 = it.row0 + (s / nch) * NM_TM + w * 16;
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int col = oc0 + j * 16 + (lane & 15);
-                if (col < a.nx) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int64_t row = r0 + MF::row_of(lane, v);
-                        if (row < rows1) {
-                            double y = (double)acc[j][v];
-                            if (a.row_scale && row < a.nscale) y *= a.row_scale[row];
-                            const size_t o = (size_t)row + (size_t)col * (size_t)S.ldo;
-                            if (S.out_dtype == PSVD_F64) {
-                                double* po = (double*)S.out + o;
-                                gstd(po, a.accumulate ? gldd(po) + y : y);
-                            } else {
-                                float* po = (float*)S.out + o;
-                                gst(po, a.accumulate ? (float)((double)gld(po) + y) : (float)y);
-                            }
-                        }
-                    }
-                }
-                acc[j] = typename MF::acc{0, 0, 0, 0};
-            }
-        }
-    }
-}
-
-// k_nn_w: C X with FP64 products (FP64 matrix cores, 16x16x4) on panels of
-// FP64 and FP32 blocks taking 16-byte column-segment loads (NnArgs::vec16), n
-// up to ND_NMAX.  512 threads, one work-group per CU: the work (item, 32-column
-// output block) pairs are dealt to the work-groups in turn, each work-group
-// keeping one output block, so its X block (rows k >= n zero) is staged in LDS
-// once, row-major (the 16-column fragment reads are contiguous); the column
-// addresses of each item's segment sit in an LDS table.  C streams in 64-row x 64-column chunks (column parts as k_nn_m: an
+// k_nn_w: C X with FP64 products (CT = double, FP64 matrix cores) or FP32
+// products (CT = float, FP32 matrix cores), 16x16x4, on panels of FP64 and
+// FP32 blocks taking 16-byte column-segment loads (NnArgs::vec16), n up to
+// ND_NMAX.  512 threads, one work-group per CU (two for FP32): the work
+// (item, 32-column output block) pairs are dealt to the work-groups in turn,
+// each work-group keeping one output block, so its X block (rows k >= n zero)
+// is staged in LDS once, row-major (the 16-column fragment reads are
+// contiguous); the column addresses of each item's segment sit in an LDS
+// table.  C streams in 64-row x 64-column chunks (column parts as k_tn_v: an
 // FP64 column in 32 parts of two rows, an FP32 column in 16 parts of four
 // rows, four parts per thread): two chunks' loads in flight in two register
 // sets while the matrix cores work on a third in one of two LDS buffers (one
 // barrier per chunk).  Wave w forms rows 16 (w % 4) .. of the tile for the
 // 16-column block w / 4, its k-steps alternating between two accumulators.
+// FP64 columns take FP32 products as the FP32 matrix cores do (rounded).
 // ----------------------------------------------------------------------------
-constexpr int ND_TM = 64, ND_KC = 64, ND_OB = 32, ND_LDC = ND_TM + 2, ND_NMAX = 320;
-constexpr int ND_WGS = 256;   // work-groups (one per CU)
+constexpr int ND_TM = 64, ND_KC = 64, ND_OB = 32, ND_NMAX = 320;
 
+template <class CT>
+struct NwLayout {
+    static constexpr int LDC = ND_TM + 16 / (int)sizeof(CT);   // 16-byte aligned part stores
+    static constexpr int WGS = sizeof(CT) == 8 ? 256 : 512;    // work-groups (per CU: 1 or 2)
+};
+
+template <class CT>
 __host__ __device__ inline size_t nn_w_lds(int n) {
     const int npad = (n + ND_KC - 1) / ND_KC * ND_KC;
-    return ((size_t)npad * ND_OB + (size_t)2 * ND_KC * ND_LDC) * sizeof(double) + (size_t)npad * sizeof(uint64_t);
+    return ((size_t)npad * ND_OB + (size_t)2 * ND_KC * NwLayout<CT>::LDC) * sizeof(CT) +
+           (size_t)npad * sizeof(uint64_t);
 }
 
+template <class CT>
 __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
+    using MF = Mfma<CT>;
+    constexpr int ND_LDC = NwLayout<CT>::LDC;
     if (a.skip && (*a.skip & a.skip_mask)) return;
     if (a.skip && a.need_mask && !(*a.skip & a.need_mask)) return;
-    extern __shared__ __align__(16) double nws[];
+    extern __shared__ __align__(16) unsigned char nwsb[];
+    CT* nws = (CT*)nwsb;
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nob = (a.nx + ND_OB - 1) / ND_OB;
@@ -1107,15 +989,15 @@ __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
     const int n = a.n;
     const int npad = (n + ND_KC - 1) / ND_KC * ND_KC;
     const int oc0 = ob * ND_OB;
-    double* Xs = nws;                                 // npad rows x ND_OB (row-major: the
+    CT* Xs = nws;                                     // npad rows x ND_OB (row-major: the
                                                       // fragment reads of 16 columns are contiguous)
-    double* Cb = Xs + npad * ND_OB;                   // 2 buffers x ND_KC columns x ND_LDC
+    CT* Cb = Xs + npad * ND_OB;                       // 2 buffers x ND_KC columns x ND_LDC
     uint64_t* ctab = (uint64_t*)(Cb + 2 * ND_KC * ND_LDC);   // column c: base | FP64 bit (columns past n: n - 1)
     for (int idx = tid; idx < ND_OB * npad; idx += 512) {
         const int k = idx % npad, j = idx / npad;
         double v = 0.0;
         if (k < n && oc0 + j < a.nx) v = gldd(a.X + k + (int64_t)(oc0 + j) * a.ldx);
-        Xs[k * ND_OB + j] = v;
+        Xs[k * ND_OB + j] = MF::from_double(v);
     }
     const int nch = npad / ND_KC;
     constexpr int NE = ND_KC * 32 / 512;   // slots per thread
@@ -1158,33 +1040,32 @@ __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
             }
             return m;
         };
-        auto stage = [&](double* cb, const f4_t* v, uint32_t m) {
+        auto stage = [&](CT* cb, const f4_t* v, uint32_t m) {
 #pragma unroll
             for (int e = 0; e < NE; ++e)
-                tnv_store<double, 32>(cb + (cq + 16 * e) * ND_LDC, v[e], (m >> (NE + e)) & 1, (m >> e) & 1, p);
+                tnv_store<CT, 32>(cb + (cq + 16 * e) * ND_LDC, v[e], (m >> (NE + e)) & 1, (m >> e) & 1, p);
         };
-        d4_t acc0 = d4_t{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-        auto compute = [&](const double* cb, int64_t s) {
+        typename MF::acc acc0 = typename MF::acc{0, 0, 0, 0}, acc1 = acc0;
+        auto compute = [&](const CT* cb, int64_t s) {
             const int kc = (int)(s % nch);
 #pragma unroll
             for (int kk = 0; kk < ND_KC; kk += 8) {
                 const int xk = (kc * ND_KC + kk) * ND_OB;
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[co + kk * ND_LDC], Xs[xo + xk], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[co + (kk + 4) * ND_LDC], Xs[xo + xk + 4 * ND_OB], acc1,
-                                                            0, 0, 0);
+                acc0 = MF::mma(cb[co + kk * ND_LDC], Xs[xo + xk], acc0);
+                acc1 = MF::mma(cb[co + (kk + 4) * ND_LDC], Xs[xo + xk + 4 * ND_OB], acc1);
             }
-            if (kc == nch - 1) {   // tile complete: rows r0 + 16 rb + g + 4 v, column oc0 + 16 jb + l
-                const d4_t y4 = acc0 + acc1;
-                acc0 = d4_t{0.0, 0.0, 0.0, 0.0};
+            if (kc == nch - 1) {   // tile complete: rows r0 + 16 rb + row_of(lane, v), column oc0 + 16 jb + l
+                const typename MF::acc y4 = acc0 + acc1;
+                acc0 = typename MF::acc{0, 0, 0, 0};
                 acc1 = acc0;
-                const int64_t r0 = it.row0 + (s / nch) * ND_TM + rb * 16 + (lane >> 4);
+                const int64_t r0 = it.row0 + (s / nch) * ND_TM + rb * 16;
                 const int col = oc0 + jb * 16 + (lane & 15);
                 if (col < a.nx) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int64_t row = r0 + 4 * v;
+                        const int64_t row = r0 + MF::row_of(lane, v);
                         if (row < rows1) {
-                            double y = y4[v];
+                            double y = (double)y4[v];
                             if (a.row_scale && row < a.nscale) y *= a.row_scale[row];
                             const size_t o = (size_t)row + (size_t)col * (size_t)S.ldo;
                             if (S.out_dtype == PSVD_F64) {
@@ -1202,8 +1083,8 @@ __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
         f4_t va[NE], vb[NE];
         uint32_t ma = fetch(0, va);
         uint32_t mb = fetch(1, vb);
-        double* C0 = Cb;
-        double* C1 = Cb + ND_KC * ND_LDC;
+        CT* C0 = Cb;
+        CT* C1 = Cb + ND_KC * ND_LDC;
         // steps 2 u (set a, buffer 0) and 2 u + 1 (set b, buffer 1); the loads are
         // unconditional, so each wait covers exactly the set it consumes
         for (int64_t s = 0; s < nstep; s += 2) {
@@ -3348,31 +3229,22 @@ hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
         else hipLaunchKernelGGL(k_nn_v<false>, dim3((unsigned)blocks), dim3(256), lds, st, b);
         return hipGetLastError();
     }
-    // FP32 products on mixed-dtype panels with 16-byte loads: k_nn_m when its
-    // LDS leaves room for two work-groups per CU
-    if (!fp64 && a.vec16 && a.n >= 1 && nn_m_lds<float>(a.n) <= 80 * 1024) {
-        NnArgs b = a;
-        b.nitems_v = nitems;
-        const int nob = (a.nx + NM_OB - 1) / NM_OB;
-        const size_t lds = nn_m_lds<float>(a.n);
-        hipError_t e = ensure_lds_attr((const void*)k_nn_m<float>, lds);
-        if (e != hipSuccess) return e;
-        const int64_t blocks = (int64_t)((nitems + 7) / 8) * 8 * nob;
-        hipLaunchKernelGGL(k_nn_m<float>, dim3((unsigned)blocks), dim3(256), lds, st, b);
-        return hipGetLastError();
-    }
-    // FP64 products on panels with 16-byte loads: k_nn_w, one work-group per CU
-    if (fp64 && a.vec16 && a.n >= 1 && a.n <= ND_NMAX) {
+    // panels with 16-byte loads (FP64 products, or FP32 products on mixed-dtype
+    // panels): k_nn_w, 512 threads, one work-group per CU (FP64) or two (FP32)
+    if (a.vec16 && a.n >= 1 && a.n <= ND_NMAX) {
         NnArgs b = a;
         b.nitems_v = nitems;
         const int nob = (a.nx + ND_OB - 1) / ND_OB;
-        const size_t lds = nn_w_lds(a.n);
-        hipError_t e = ensure_lds_attr((const void*)k_nn_w, lds);
-        if (e != hipSuccess) return e;
         const int64_t work = (int64_t)nitems * nob;
-        const int64_t wgs = std::min<int64_t>(work, (ND_WGS / nob) * nob);
-        hipLaunchKernelGGL(k_nn_w, dim3((unsigned)wgs), dim3(512), lds, st, b);
-        return hipGetLastError();
+        auto go = [&](auto kern, size_t lds, int wgmax) -> hipError_t {
+            hipError_t e = ensure_lds_attr((const void*)kern, lds);
+            if (e != hipSuccess) return e;
+            const int64_t wgs = std::min<int64_t>(work, (wgmax / nob) * nob);
+            hipLaunchKernelGGL(kern, dim3((unsigned)wgs), dim3(512), lds, st, b);
+            return hipGetLastError();
+        };
+        if (fp64) return go(k_nn_w<double>, nn_w_lds<double>(a.n), NwLayout<double>::WGS);
+        return go(k_nn_w<float>, nn_w_lds<float>(a.n), NwLayout<float>::WGS);
     }
     dim3 grid(nitems, (a.nx + NN_OB - 1) / NN_OB);
     if (fp64) hipLaunchKernelGGL(k_nn<double>, grid, dim3(256), 0, st, a);
