@@ -802,10 +802,9 @@ __device__ __forceinline__ const float* fcol(const PanelSeg& s, int c) {
 
 // ----------------------------------------------------------------------------
 // k_nn_v: out[seg rows, ocols] = C[rows, :] X[:, ocols] (+ row scale, + out)
-// for FP32 panels.  VEC: columns take float4 loads (rows % 4 == 0, 16-byte
-// aligned columns; a thread moves four 4-row column segments per chunk), else
-// one float per lane (a wave moves 64 consecutive rows of one column per
-// load).  One work-group: one 32-column block of X, staged in LDS
+// for FP32 panels taking float4 loads (rows % 4 == 0, 16-byte aligned columns;
+// a thread moves four 4-row column segments per chunk; other FP32 panels take
+// k_nn_w).  One work-group: one 32-column block of X, staged in LDS
 // once (rows k >= n zero, so the padding columns of C -- copies of column
 // n - 1 -- add nothing), and one item's rows in 64-row tiles; C streams in
 // 64-row x 64-column chunks of float4 column segments into two LDS buffers,
@@ -820,7 +819,6 @@ constexpr int NV_NMAX = 1024;   // X block 32 x (1024 + 4) FP32 and the two chun
 
 __host__ __device__ inline int nv_ldx(int npad) { return npad + 4; }
 
-template <bool VEC>
 __global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
     if (a.skip && (*a.skip & a.skip_mask)) return;
     if (a.skip && a.need_mask && !(*a.skip & a.need_mask)) return;
@@ -851,30 +849,18 @@ __global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
     if (it.row0 >= rows1) return;
     const int64_t ntile = (rows1 - it.row0 + NV_TM - 1) / NV_TM;
     const int64_t nstep = ntile * nch;
-    // VEC load slots: column (tid >> 4) + 16 q of the chunk, rows 4 (tid & 15) .. + 3;
-    // scalar: column w + 4 q, row lane
-    const int lc = VEC ? tid >> 4 : w, lr = VEC ? 4 * (tid & 15) : lane;
+    // load slots: column (tid >> 4) + 16 q of the chunk, rows 4 (tid & 15) .. + 3
+    const int lc = tid >> 4, lr = 4 * (tid & 15);
     f4_t pf[4];
     auto fetch = [&](int64_t s) {
         const int64_t tl = s / nch;
         const int kc = (int)(s % nch);
         const int64_t row = it.row0 + tl * NV_TM + lr;
-        if constexpr (VEC) {
-            const int64_t rowc = row < rows1 ? row : rows1 - 4;
+        const int64_t rowc = row < rows1 ? row : rows1 - 4;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = kc * NV_KC + lc + 16 * q;
-                pf[q] = gld4(fcol(S, c < n ? c : n - 1) + rowc);
-            }
-        } else {
-            const int64_t rowc = row < rows1 ? row : rows1 - 1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int c = kc * NV_KC + lc + 4 * (4 * q + e);
-                    pf[q][e] = gld(fcol(S, c < n ? c : n - 1) + rowc);
-                }
+        for (int q = 0; q < 4; ++q) {
+            const int c = kc * NV_KC + lc + 16 * q;
+            pf[q] = gld4(fcol(S, c < n ? c : n - 1) + rowc);
         }
     };
     f4_t acc[2];
@@ -883,15 +869,8 @@ __global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
     fetch(0);
     for (int64_t s = 0; s < nstep; ++s) {
         float* cb = Cb + (s & 1) * (NV_KC * NV_LDC);
-        if constexpr (VEC) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) *(f4_t*)&cb[(lc + 16 * q) * NV_LDC + lr] = pf[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) cb[(lc + 4 * (4 * q + e)) * NV_LDC + lr] = pf[q][e];
-        }
+        for (int q = 0; q < 4; ++q) *(f4_t*)&cb[(lc + 16 * q) * NV_LDC + lr] = pf[q];
         lds_barrier();   // this chunk stored; X staged (first step)
         if (s + 1 < nstep) fetch(s + 1);
         const int kc = (int)(s % nch);
@@ -942,8 +921,9 @@ __global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
 
 // k_nn_w: C X with FP64 products (CT = double, FP64 matrix cores) or FP32
 // products (CT = float, FP32 matrix cores), 16x16x4, on panels of FP64 and
-// FP32 blocks taking 16-byte column-segment loads (NnArgs::vec16), n up to
-// ND_NMAX.  512 threads, one work-group per CU (two for FP32): the work
+// FP32 blocks taking 16-byte column-segment loads (NnArgs::vec16) or one element
+// per lane (VEC false), n up to
+// NwLayout::NMAX.  512 threads, one or two work-groups per CU (as the LDS allows): the work
 // (item, 32-column output block) pairs are dealt to the work-groups in turn,
 // each work-group keeping one output block, so its X block (rows k >= n zero)
 // is staged in LDS once, row-major (the 16-column fragment reads are
@@ -956,12 +936,12 @@ __global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
 // 16-column block w / 4, its k-steps alternating between two accumulators.
 // FP64 columns take FP32 products as the FP32 matrix cores do (rounded).
 // ----------------------------------------------------------------------------
-constexpr int ND_TM = 64, ND_KC = 64, ND_OB = 32, ND_NMAX = 320;
+constexpr int ND_TM = 64, ND_KC = 64, ND_OB = 32;
 
 template <class CT>
 struct NwLayout {
     static constexpr int LDC = ND_TM + 16 / (int)sizeof(CT);   // 16-byte aligned part stores
-    static constexpr int WGS = sizeof(CT) == 8 ? 256 : 512;    // work-groups (per CU: 1 or 2)
+    static constexpr int NMAX = sizeof(CT) == 8 ? 320 : 640;   // X block and buffers fit in LDS
 };
 
 template <class CT>
@@ -971,9 +951,10 @@ __host__ __device__ inline size_t nn_w_lds(int n) {
            (size_t)npad * sizeof(uint64_t);
 }
 
-template <class CT>
+template <class CT, bool VEC>
 __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
     using MF = Mfma<CT>;
+    using V = typename std::conditional<VEC, f4_t, uint64_t>::type;   // one slot's load
     constexpr int ND_LDC = NwLayout<CT>::LDC;
     if (a.skip && (*a.skip & a.skip_mask)) return;
     if (a.skip && a.need_mask && !(*a.skip & a.need_mask)) return;
@@ -1000,8 +981,11 @@ __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
         Xs[k * ND_OB + j] = MF::from_double(v);
     }
     const int nch = npad / ND_KC;
-    constexpr int NE = ND_KC * 32 / 512;   // slots per thread
-    const int p = tid & 31, cq = tid >> 5;
+    // VEC: part p = t % 32 of the columns t / 32 + 16 e; else row p = t % 64 of
+    // the columns t / 64 + 8 e (one element per lane)
+    constexpr int NPART = VEC ? 32 : 64, CSTEP = 512 / NPART;
+    constexpr int NE = ND_KC / CSTEP;      // slots per thread
+    const int p = tid % NPART, cq = tid / NPART;
     const int rb = w & 3, jb = w >> 2;
     const int xo = (lane >> 4) * ND_OB + jb * 16 + (lane & 15);
     const int co = (lane >> 4) * ND_LDC + rb * 16 + (lane & 15);
@@ -1021,29 +1005,51 @@ __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
         // step s: chunk s % nch of tile s / nch; steps past the item re-read
         // its first rows, parts at or past its end the item's first part
         // (both dropped); columns past n re-read column n - 1 (X rows zero)
-        auto fetch = [&](int64_t s, f4_t* v) -> uint32_t {
+        auto fetch = [&](int64_t s, V* v) -> uint32_t {
             const int64_t sc = s < nstep ? s : 0;
             const int64_t r0 = it.row0 + (sc / nch) * ND_TM;
             const int kc = (int)(sc % nch);
             uint32_t m = 0;
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
-                const uint64_t t = ctab[kc * ND_KC + cq + 16 * e];
+                const uint64_t t = ctab[kc * ND_KC + cq + CSTEP * e];
                 const bool f64 = t & 1;
-                const int pc = f64 ? p : (p < 16 ? p : 15);
-                const int64_t row = r0 + (f64 ? 2 * pc : 4 * pc);
-                const bool ok = s < nstep && row < rows1;
-                const int64_t rowc = ok ? row : it.row0;
-                v[e] = gld4((const float*)((const char*)(uintptr_t)(t & ~(uint64_t)1) + rowc * (f64 ? 8 : 4)));
-                m |= (ok ? 1u : 0u) << e;
+                const char* base = (const char*)(uintptr_t)(t & ~(uint64_t)1);
+                if constexpr (VEC) {
+                    const int pc = f64 ? p : (p < 16 ? p : 15);
+                    const int64_t row = r0 + (f64 ? 2 * pc : 4 * pc);
+                    const bool ok = s < nstep && row < rows1;
+                    const int64_t rowc = ok ? row : it.row0;
+                    v[e] = gld4((const float*)(base + rowc * (f64 ? 8 : 4)));
+                    m |= (ok ? 1u : 0u) << e;
+                } else {
+                    // the same two 32-bit loads for either dtype (an FP32 element
+                    // re-read as its high word): no load sits in a dtype branch
+                    const int64_t row = r0 + p;
+                    const bool ok = s < nstep && row < rows1;
+                    const int64_t rowc = ok ? row : it.row0;
+                    const uint32_t* q = (const uint32_t*)(base + rowc * (f64 ? 8 : 4));
+                    const uint32_t lo = *(const PSVD_GLOBAL uint32_t*)q;
+                    const uint32_t hi = *(const PSVD_GLOBAL uint32_t*)(q + (f64 ? 1 : 0));
+                    v[e] = ((uint64_t)hi << 32) | lo;
+                    m |= (ok ? 1u : 0u) << e;
+                }
                 m |= (f64 ? 1u : 0u) << (NE + e);
             }
             return m;
         };
-        auto stage = [&](CT* cb, const f4_t* v, uint32_t m) {
+        auto stage = [&](CT* cb, const V* v, uint32_t m) {
 #pragma unroll
-            for (int e = 0; e < NE; ++e)
-                tnv_store<CT, 32>(cb + (cq + 16 * e) * ND_LDC, v[e], (m >> (NE + e)) & 1, (m >> e) & 1, p);
+            for (int e = 0; e < NE; ++e) {
+                CT* dst = cb + (cq + CSTEP * e) * ND_LDC;
+                const bool f64 = (m >> (NE + e)) & 1, ok = (m >> e) & 1;
+                if constexpr (VEC) {
+                    tnv_store<CT, 32>(dst, v[e], f64, ok, p);
+                } else {
+                    const double x = f64 ? __longlong_as_double((long long)v[e]) : (double)__uint_as_float((uint32_t)v[e]);
+                    dst[p] = ok ? MF::from_double(x) : (CT)0;
+                }
+            }
         };
         typename MF::acc acc0 = typename MF::acc{0, 0, 0, 0}, acc1 = acc0;
         auto compute = [&](const CT* cb, int64_t s) {
@@ -1080,7 +1086,7 @@ __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
                 }
             }
         };
-        f4_t va[NE], vb[NE];
+        V va[NE], vb[NE];
         uint32_t ma = fetch(0, va);
         uint32_t mb = fetch(1, vb);
         CT* C0 = Cb;
@@ -3215,36 +3221,39 @@ hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st) {
 }
 
 hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
-    if (!fp64 && a.all_f32 && a.n >= 1 && a.n <= NV_NMAX) {
+    if (!fp64 && a.all_f32 && a.vec_f32 && a.n >= 1 && a.n <= NV_NMAX) {
         NnArgs b = a;
         b.nitems_v = nitems;
         const int nob = (a.nx + NV_OB - 1) / NV_OB;
         const int npad = (a.n + NV_KC - 1) / NV_KC * NV_KC;
         const size_t lds = ((size_t)NV_OB * nv_ldx(npad) + (size_t)2 * NV_KC * NV_LDC) * sizeof(float);
-        const void* fn = a.vec_f32 ? (const void*)k_nn_v<true> : (const void*)k_nn_v<false>;
-        hipError_t e = ensure_lds_attr(fn, lds);
+        hipError_t e = ensure_lds_attr((const void*)k_nn_v, lds);
         if (e != hipSuccess) return e;
         const int64_t blocks = (int64_t)((nitems + 7) / 8) * 8 * nob;
-        if (a.vec_f32) hipLaunchKernelGGL(k_nn_v<true>, dim3((unsigned)blocks), dim3(256), lds, st, b);
-        else hipLaunchKernelGGL(k_nn_v<false>, dim3((unsigned)blocks), dim3(256), lds, st, b);
+        hipLaunchKernelGGL(k_nn_v, dim3((unsigned)blocks), dim3(256), lds, st, b);
         return hipGetLastError();
     }
-    // panels with 16-byte loads (FP64 products, or FP32 products on mixed-dtype
-    // panels): k_nn_w, 512 threads, one work-group per CU (FP64) or two (FP32)
-    if (a.vec16 && a.n >= 1 && a.n <= ND_NMAX) {
+    // k_nn_w (512 threads, one or two work-groups per CU as its LDS allows):
+    // FP64 products on panels with 16-byte loads, FP32 products on the other
+    // panels (16-byte loads, or one element per lane)
+    const bool w64 = fp64 && a.vec16 && a.n <= NwLayout<double>::NMAX;
+    const bool w32 = !fp64 && a.n <= NwLayout<float>::NMAX;
+    if (a.n >= 1 && (w64 || w32)) {
         NnArgs b = a;
         b.nitems_v = nitems;
         const int nob = (a.nx + ND_OB - 1) / ND_OB;
         const int64_t work = (int64_t)nitems * nob;
-        auto go = [&](auto kern, size_t lds, int wgmax) -> hipError_t {
+        auto go = [&](auto kern, size_t lds) -> hipError_t {
             hipError_t e = ensure_lds_attr((const void*)kern, lds);
             if (e != hipSuccess) return e;
-            const int64_t wgs = std::min<int64_t>(work, (wgmax / nob) * nob);
+            const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+            const int64_t wgs = std::min<int64_t>(work, ((256 * per_cu) / nob) * nob);
             hipLaunchKernelGGL(kern, dim3((unsigned)wgs), dim3(512), lds, st, b);
             return hipGetLastError();
         };
-        if (fp64) return go(k_nn_w<double>, nn_w_lds<double>(a.n), NwLayout<double>::WGS);
-        return go(k_nn_w<float>, nn_w_lds<float>(a.n), NwLayout<float>::WGS);
+        if (fp64) return go(k_nn_w<double, true>, nn_w_lds<double>(a.n));
+        if (a.vec16) return go(k_nn_w<float, true>, nn_w_lds<float>(a.n));
+        return go(k_nn_w<float, false>, nn_w_lds<float>(a.n));
     }
     dim3 grid(nitems, (a.nx + NN_OB - 1) / NN_OB);
     if (fp64) hipLaunchKernelGGL(k_nn<double>, grid, dim3(256), 0, st, a);
