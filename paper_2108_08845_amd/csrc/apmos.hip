@@ -164,7 +164,7 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
     size_t o_Lam = take(sizeof(double) * K);
     size_t o_X = take(sizeof(double) * (size_t)N * K);
     size_t o_vec = take(sizeof(double) * (size_t)P * (2 * N + 2) + 64);
-    size_t o_ivec = take(sizeof(int32_t) * (size_t)P * N + 64);
+    size_t o_ivec = take(sizeof(int32_t) * 3 * (size_t)P * N + 64);
     size_t o_stat = take(64);
     size_t o_wwpart = take(sizeof(double) * 2048 * (size_t)mbw * (mbw + 1) / 2 * TN_OB * TN_OB);
     size_t o_om = take(sizeof(double) * (size_t)pr * std::max(ell, 1));

@@ -144,7 +144,7 @@ struct SmallArgs {
     double* s_out;        // K new singular values
     double* small_u;      // n x K small left factor after the sign rule (diagnostics)
     double* vec;          // 4n scratch
-    int32_t* ivec;        // n scratch
+    int32_t* ivec;        // 3n scratch
     int32_t* status;      // DevStatus bits
     int32_t* sweeps;      // last Jacobi sweep count
     int32_t skip_svd;     // k_small_det2 stops after R = R2 R1 (the caller takes the SVD of R)
@@ -192,7 +192,7 @@ struct ApmosLocalArgs {
     int32_t N, r, P;
     int32_t max_sweeps;
     double* vec;        // P * 2N
-    int32_t* ivec;      // P * N
+    int32_t* ivec;      // P * 3N
     int32_t* status;
     int32_t* sweeps;
 };
@@ -205,7 +205,7 @@ struct ApmosGlobalArgs {
     double* Lam;        // K
     double* X;          // N x K
     double* vec;        // 2N
-    int32_t* ivec;      // N
+    int32_t* ivec;      // 3N
     int32_t* status;
     int32_t* sweeps;
 };

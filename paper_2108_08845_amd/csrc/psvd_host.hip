@@ -370,7 +370,7 @@ static int ensure_workspace(psvd_handle* h, int n) {
     int w = std::max(n, l);
     SmallLayout L = small_layout(nullptr, n, l, h->K);
     HIPCHK(h, h->small.ensure(L.total * sizeof(double)));
-    HIPCHK(h, h->ivec.ensure((size_t)(w + 64) * sizeof(int32_t)));
+    HIPCHK(h, h->ivec.ensure((size_t)(3 * w + 64) * sizeof(int32_t)));
     // k_tn partials: items x output blocks stays near 1024 (see pick_chunk)
     int nb = ceil_div(w, 64);
     size_t nob = (size_t)nb * nb;
@@ -1389,7 +1389,7 @@ int rsvd_fixed(const FixedBuffers& fb, const void* A, int64_t M, int64_t N, int6
     const int64_t ldu_state = U ? ldu : ((M + 63) / 64) * 64;
     const size_t need[] = {
         small_layout(nullptr, n, ell, K).total * sizeof(double),   // 0 small matrices
-        (size_t)(w + 64) * sizeof(int32_t),                         // 1 int scratch
+        (size_t)(3 * w + 64) * sizeof(int32_t),                     // 1 int scratch
         part,                                                       // 2 k_tn partials
         wgs * nlb * np * 64 * sizeof(float),                        // 3 fused partials
         wgs * 64 * 64 * sizeof(double),                             // 4 fused G partials

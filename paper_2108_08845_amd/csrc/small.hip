@@ -536,10 +536,12 @@ __device__ __forceinline__ void jac_pair_loop(double* zp, double* zq, int m, int
 // ||z_j|| and z_j /= sig[j] (0 columns stay 0).  order[0..n) lists the
 // columns by descending sig (stable).  Parallel round-robin ordering: each
 // round rotates n/2 disjoint pairs, one pair per quarter-wave (16 lanes) at a time.
+// With cmap, column j of the iteration is column cmap[j] of Z (sig, order and
+// nrm stay indexed by j).
 // Returns the number of sweeps (> max_sweeps: not converged).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* order, double* nrm,
-                                         int max_sweeps, int* sflag) {
+                                         int max_sweeps, int* sflag, const int* cmap = nullptr) {
     // One pair per quarter-wave (16 lanes): a round of n/2 disjoint pairs runs
     // in one pass when blockDim.x / 16 >= n / 2.
     const int tid = threadIdx.x;
@@ -549,7 +551,7 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
     int sweep = 0;
     for (;;) {
         for (int j = qw; j < n; j += nq) {
-            const double* z = Z + (size_t)j * ldz;
+            const double* z = Z + (size_t)(cmap ? cmap[j] : j) * ldz;
             double s = 0.0;
             for (int i = ql; i < m; i += 16) s += z[i] * z[i];
             s = q16_sum(s);
@@ -580,8 +582,8 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
                 const int cb = pb == 0 ? 0 : 1 + xb;
                 const int p = ca < cb ? ca : cb, q = ca < cb ? cb : ca;
                 if (q >= n) continue;
-                double* zp = Z + (size_t)p * ldz;
-                double* zq = Z + (size_t)q * ldz;
+                double* zp = Z + (size_t)(cmap ? cmap[p] : p) * ldz;
+                double* zq = Z + (size_t)(cmap ? cmap[q] : q) * ldz;
                 const double al = nrm[p], be = nrm[q];
                 if (m <= 64) jac_pair_regs<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
                 else if (m <= 128) jac_pair_regs<8>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
@@ -596,7 +598,7 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
     }
     // singular values, normalisation
     for (int j = qw; j < n; j += nq) {
-        double* z = Z + (size_t)j * ldz;
+        double* z = Z + (size_t)(cmap ? cmap[j] : j) * ldz;
         double s = 0.0;
         for (int i = ql; i < m; i += 16) s += z[i] * z[i];
         s = sqrt(q16_sum(s));
@@ -749,6 +751,115 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
     return sweep;
 }
 
+// Eigen-decomposition of a symmetric positive semi-definite matrix A (n x n,
+// column-major with leading dimension n, both triangles stored), in place, by
+// a rank-revealing Cholesky factorisation and one-sided Jacobi on the factor
+// (the preconditioned one-sided Jacobi SVD of Drmac and Veselic, applied to
+// the Cholesky factor of A instead of the R of a QR of the data):
+//   1. Diagonal pivoting: step k takes the largest diagonal entry d of the
+//      Schur complement (lowest index p on ties) and subtracts
+//      A(:, p) A(:, p)^T / d from the rows and columns still in play; it stops
+//      once d <= n 2^-53 max_j A_jj (LAPACK's default tolerance for its
+//      pivoted Cholesky, xPSTRF), so the complement left out is within the
+//      backward error of the factorisation.  Column p keeps its step-k entries: at the
+//      rows still in play they are d^(1/2) times row k of the factor R, where
+//      A ~ R^T R over the r pivots.
+//   2. B = R^T (n x r, rows in the original index order, A ~ B B^T) is formed
+//      in place in the pivot columns; every other column is cleared.
+//   3. One-sided Jacobi on the r columns of B: B V = W with orthogonal
+//      columns, A ~ W W^T, so the normalised columns of W are eigenvectors of
+//      A with eigenvalues ||w_j||^2.  The pivoted factor's columns are graded
+//      and there are r <= n of them: far fewer rounds than Jacobi on A.
+// On return, for j in [0, n): column col[j] of A holds the unit eigenvector of
+// the j-th largest eigenvalue sv[j]^2 (sv descending; the n - r columns past
+// the rank are zero, with sv = 0).  Scratch: sig (n doubles), nrm (n + 1
+// doubles, returned as sv), ord, state and cmap (n ints each; state is
+// returned as col).  Returns the Jacobi sweep count (> max_sweeps: not
+// converged).
+__device__ int wg_psd_eig(double* A, int n, double* sig, double* nrm, int* ord, int* state, int* cmap,
+                          int max_sweeps, int* sflag, double** sv, int** col) {
+    const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
+    for (int j = tid; j < n; j += nt) state[j] = -1;   // state[j]: step at which j was pivoted
+    double dm = 0.0;   // largest diagonal entry, by every wave alike
+    for (int j = lane; j < n; j += 64) dm = fmax(dm, A[j + (size_t)j * n]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, 64));
+    const double tol = dm * ((double)n * 0x1p-53);
+    __syncthreads();
+    int r = 0, prev = -1;
+    for (; r < n; ++r) {
+        // Every wave finds the same pivot from the same data.  The pivot of
+        // the step before is excluded by register: thread 0 records it in
+        // state[] during this step, while other waves may still be reading.
+        double bv = -1.0;
+        int bi = n;
+        for (int j = lane; j < n; j += 64) {
+            if (j == prev || state[j] >= 0) continue;
+            const double v = A[j + (size_t)j * n];
+            if (v > bv) {
+                bv = v;
+                bi = j;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (!(bv > tol)) break;
+        const int p = bi;
+        if (tid == 0) {
+            if (prev >= 0) state[prev] = r - 1;
+            cmap[r] = p;
+        }
+        const double inv = 1.0 / bv;
+        const double* ap = A + (size_t)p * n;   // column p: not written in this step
+        for (int j = tid >> 6; j < n; j += nt >> 6) {   // a wave per column still in play
+            if (j == p || j == prev || state[j] >= 0) continue;
+            const double fj = ap[j] * inv;
+            double* aj = A + (size_t)j * n;
+            for (int i = lane; i < n; i += 64)
+                if (i != p && i != prev && state[i] < 0) aj[i] -= ap[i] * fj;
+        }
+        prev = p;
+        __syncthreads();
+    }
+    if (tid == 0 && prev >= 0) state[prev] = r - 1;
+    __syncthreads();
+    for (int k = tid; k < r; k += nt) {   // the pivots d_k
+        const int q = cmap[k];
+        nrm[k] = A[q + (size_t)q * n];
+    }
+    for (int j = tid; j < n; j += nt) {   // indices never pivoted, ascending, after the pivots
+        if (state[j] >= 0) continue;
+        int c = 0;
+        for (int i = 0; i < j; ++i) c += state[i] < 0;
+        cmap[r + c] = j;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nt) {   // B = R^T in the pivot columns
+        const int i = e % n, j = e / n;
+        const int kj = state[j], ki = state[i];
+        double v = 0.0;
+        if (kj >= 0 && (ki < 0 || ki >= kj)) v = A[e] / sqrt(nrm[kj]);
+        A[e] = v;
+    }
+    __syncthreads();
+    const int sw = wg_jacobi(A, n, r, n, sig, ord, nrm, max_sweeps, sflag, cmap);
+    for (int j = tid; j < n; j += nt) {
+        state[j] = j < r ? cmap[ord[j]] : cmap[j];
+        nrm[j] = j < r ? sig[ord[j]] : 0.0;
+    }
+    __syncthreads();
+    *sv = nrm;
+    *col = state;
+    return sw;
+}
+
 // Sign rule: column j of X (rows x k) gets its largest-magnitude entry
 // (lowest index on ties) non-negative; flips recorded in flip[j].
 __device__ __forceinline__ void wg_sign_rule(double* X, int rows, int k, int ldx, double* flip) {
@@ -858,16 +969,18 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
         if (tid == 0) *a.status |= DEV_BREAKDOWN;
         return;
     }
-    // Eigen route: one-sided Jacobi on the PSD Gram G = V diag(lambda) V^T
-    // (G V has orthogonal columns lambda_j v_j); sigma_j = sqrt(lambda_j),
-    // U_new = C V_K diag(1 / sigma_K).
+    // Eigen route: the PSD Gram G = V diag(sigma^2) V^T by pivoted Cholesky
+    // and one-sided Jacobi on its factor (wg_psd_eig: sigma_j is the j-th
+    // singular value of the factor, so of the panel); U_new = C V_K diag(1 / sigma_K).
     if (tid == 0) *a.status |= DEV_FALLBACK;
     for (int e = tid; e < n * n; e += SM_THREADS) W[e] = a.G[e];
     __syncthreads();
     double* sig = in_lds ? lds_vecs(lds, n) : a.vec;
     double* nrm = sig + n;
     int* ord = in_lds ? (int*)(nrm + n + 1) : a.ivec;
-    int sw = wg_jacobi(W, n, n, n, sig, ord, nrm, a.max_sweeps, &sflag);
+    double* sv;
+    int* col;
+    int sw = wg_psd_eig(W, n, sig, nrm, ord, ord + n, ord + 2 * n, a.max_sweeps, &sflag, &sv, &col);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
@@ -875,12 +988,9 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
     const int rk = a.K < n ? a.K : n;
     for (int e = tid; e < n * rk; e += SM_THREADS) {
         const int i = e % n, j = e / n;
-        a.small_u[i + (size_t)j * n] = W[i + (size_t)ord[j] * n];
+        a.small_u[i + (size_t)j * n] = W[i + (size_t)col[j] * n];
     }
-    for (int j = tid; j < rk; j += SM_THREADS) {
-        const double lam = sig[ord[j]];
-        a.s_out[j] = sqrt(lam > 0.0 ? lam : 0.0);
-    }
+    for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sv[j];
     __syncthreads();
     wg_sign_rule(a.small_u, n, rk, n, nullptr);
     for (int e = tid; e < n * rk; e += SM_THREADS) {
@@ -1364,8 +1474,8 @@ hipError_t launch_low_rank_small(const LowRankArgs& a, hipStream_t st) {
 // APMOS small kernels.
 // ---------------------------------------------------------------------------
 
-// One work-group per partition: eigen-decomposition of G_i by one-sided
-// Jacobi; W_i = V_i[:, :r] diag(sqrt(lambda_i[:r])) stored transposed.
+// One work-group per partition: eigen-decomposition of G_i (wg_psd_eig);
+// W_i = V_i[:, :r] diag(sqrt(lambda_i[:r])) stored transposed.
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
     extern __shared__ double lds[];
@@ -1375,22 +1485,21 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
     double* G = stage_in(lds, a.G + (size_t)i * N * N, N, in_lds);
     double* sig = in_lds ? lds_vecs(lds, N) : a.vec + (size_t)i * (2 * N + 2);
     double* nrm = sig + N;
-    int* ord = in_lds ? (int*)(nrm + N + 1) : a.ivec + (size_t)i * N;
-    int sw = wg_jacobi(G, N, N, N, sig, ord, nrm, a.max_sweeps, &sflag);
+    int* ord = in_lds ? (int*)(nrm + N + 1) : a.ivec + (size_t)i * 3 * N;
+    double* sv;
+    int* col;
+    int sw = wg_psd_eig(G, N, sig, nrm, ord, ord + N, ord + 2 * N, a.max_sweeps, &sflag, &sv, &col);
     if (tid == 0 && sw > a.max_sweeps) atomicOr(a.status, (int)DEV_NOCONV);
     if (tid == 0) atomicMax(a.sweeps, sw);
     const int ldw = a.P * a.r;
     for (int e = tid; e < N * a.r; e += SM_THREADS) {
         int k = e % N, j = e / N;
-        int src = ord[j];
-        double lam = sig[src];
-        double sj = sqrt(lam > 0.0 ? lam : 0.0);
-        a.Wt[(size_t)(i * a.r + j) + (size_t)k * ldw] = G[k + (size_t)src * N] * sj;
+        a.Wt[(size_t)(i * a.r + j) + (size_t)k * ldw] = G[k + (size_t)col[j] * N] * sv[j];
     }
 }
 
 
-// W W^T = X Lambda^2 X^T by one-sided Jacobi; keep K; sign rule on X~;
+// W W^T = X Lambda^2 X^T (wg_psd_eig); keep K; sign rule on X~;
 // T = X~ diag(1 / Lambda~) with the guard Lambda~_K > N 2^-53 Lambda~_1.
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_apmos_global(ApmosGlobalArgs a) {
@@ -1402,19 +1511,18 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_global(ApmosGlobalArgs a) 
     double* sig = in_lds ? lds_vecs(lds, N) : a.vec;
     double* nrm = sig + N;
     int* ordv = in_lds ? (int*)(nrm + N + 1) : a.ivec;
-    int sw = wg_jacobi(WW, N, N, N, sig, ordv, nrm, a.max_sweeps, &sflag);
+    double* sv;
+    int* col;
+    int sw = wg_psd_eig(WW, N, sig, nrm, ordv, ordv + N, ordv + 2 * N, a.max_sweeps, &sflag, &sv, &col);
     if (tid == 0) {
         atomicMax(a.sweeps, sw);
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
     }
     for (int e = tid; e < N * a.K; e += SM_THREADS) {
         int k = e % N, j = e / N;
-        a.X[k + (size_t)j * N] = WW[k + (size_t)ordv[j] * N];
+        a.X[k + (size_t)j * N] = WW[k + (size_t)col[j] * N];
     }
-    for (int j = tid; j < a.K; j += SM_THREADS) {
-        double lam = sig[ordv[j]];
-        a.Lam[j] = sqrt(lam > 0.0 ? lam : 0.0);
-    }
+    for (int j = tid; j < a.K; j += SM_THREADS) a.Lam[j] = sv[j];
     __syncthreads();
     wg_sign_rule(a.X, N, a.K, N, nullptr);
     if (tid == 0 && !(a.Lam[a.K - 1] > (double)N * 0x1p-53 * a.Lam[0])) *a.status |= DEV_SMALL_LAMBDA;

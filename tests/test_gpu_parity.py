@@ -174,6 +174,80 @@ def test_det_rank_deficient_falls_back():
     assert max_principal_angle(U, so.modes) <= 1e-8
 
 
+def test_det_eigen_route_rank_below_K():
+    # Rank 3 in 11 snapshots with K = 11: the pivoted Cholesky of the eigen
+    # route stops at the numerical rank (two snapshots are zero, so at least
+    # the last two modes are past it and come out zero with sigma = 0; the
+    # dependent ones leave at most rounding-level pivots); the rank-3 modes
+    # match the oracle, and a following full-rank update (whose panel carries
+    # the zero modes) matches it again.  Both updates take the eigen route,
+    # whose sign rule applies to the eigenvectors of the Gram, not to the left
+    # factor of R as the oracle's does: modes are compared as subspaces.
+    g = torch.Generator().manual_seed(5)
+    M, K = 1500, 11
+    B = torch.randn((3, M), generator=g, dtype=torch.float64)
+    A = torch.cat([B, B[:2] * 2.0, B[1:] - 0.5 * B[:2], B[2:] * -3.0, torch.zeros((2, M), dtype=torch.float64),
+                   B[:1] + B[1:2]])
+    P = lib()
+    svd = P.StreamingSVD(M, K, precision="fp64")
+    so = oracle.StreamOracle(M, K)
+    svd.incorporate_data(to_gpu(A))
+    so.incorporate(synth.numpy_cm(A))
+    assert svd.stats()["fallbacks"] == 1
+    s, s_ref = svd.singular_values, so.singular_values
+    assert sigma_rel_err(s[:3], s_ref[:3]) <= 1e-10
+    assert np.all(s[3:] <= 1e-6 * s[0])
+    U = svd.modes.cpu().numpy()
+    assert max_principal_angle(U[:, :3], so.modes[:, :3]) <= 1e-8
+    zero = s == 0.0
+    assert zero[K - 2:].all()
+    assert np.all(U[:, zero] == 0.0)
+    A2 = torch.randn((10, M), generator=g, dtype=torch.float64)
+    svd.incorporate_data(to_gpu(A2))
+    so.incorporate(synth.numpy_cm(A2))
+    assert svd.stats()["fallbacks"] == 2
+    assert sigma_rel_err(svd.singular_values, so.singular_values) <= 1e-10
+    U2 = svd.modes.cpu().numpy()
+    assert orth_err(U2) <= 1e-12
+    k = gap_limited_k(so.singular_values, 1e-10, K)
+    assert k >= 3 and max_principal_angle(U2[:, :k], so.modes[:, :k]) <= 1e-8
+
+
+def test_det_eigen_route_global_memory():
+    # A 150-column panel of rank 60 (over the 140 columns the small core keeps
+    # in LDS): the eigen route runs on its global-memory buffers (modes
+    # compared as subspaces: the eigen route's sign rule acts on the Gram's
+    # eigenvectors).
+    g = torch.Generator().manual_seed(6)
+    M, K = 1200, 10
+    L = torch.randn((60, M), generator=g, dtype=torch.float64) * torch.logspace(0, -3, 60, dtype=torch.float64)[:, None]
+    A = torch.randn((150, 60), generator=g, dtype=torch.float64) @ L
+    P = lib()
+    svd = P.StreamingSVD(M, K, precision="fp64")
+    svd.incorporate_data(to_gpu(A))
+    assert svd.stats()["fallbacks"] == 1
+    so = oracle.StreamOracle(M, K).incorporate(synth.numpy_cm(A))
+    assert sigma_rel_err(svd.singular_values, so.singular_values) <= 1e-10
+    U = svd.modes.cpu().numpy()
+    assert orth_err(U) <= 1e-12
+    k = gap_limited_k(so.singular_values, 1e-10, K)
+    assert k >= 1 and max_principal_angle(U[:, :k], so.modes[:, :k]) <= 1e-8
+
+
+def test_apmos_global_memory_matches_oracle():
+    # N = 160 snapshots (over the 140 the APMOS small kernels keep in LDS).
+    w = synth.scaled(synth.c4_apmos(), partitions=4, part_min=400, part_max=900, N=160, dtype=torch.float64)
+    parts = synth.apmos_partitions(w)
+    P = lib()
+    U, Lam, X = P.apmos_batched([to_gpu(p) for p in parts], w.local_rank, 10)
+    Uo, Lo, Xo = oracle.apmos([synth.numpy_cm(p) for p in parts], w.local_rank, 10)
+    assert sigma_rel_err(Lam, Lo) <= 1e-10
+    Ug = np.vstack([u.double().cpu().numpy() for u in U])
+    k = gap_limited_k(Lo, 1e-10, 10)
+    assert max_principal_angle(Ug[:, :k], np.vstack(Uo)[:, :k]) <= 1e-8
+    assert np.abs(np.abs(X) - np.abs(Xo)).max() <= 1e-7
+
+
 def test_det_errors_leave_state_unchanged():
     P = lib()
     M = 512
