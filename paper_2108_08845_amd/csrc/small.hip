@@ -585,7 +585,11 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
                 double* zp = Z + (size_t)(cmap ? cmap[p] : p) * ldz;
                 double* zq = Z + (size_t)(cmap ? cmap[q] : q) * ldz;
                 const double al = nrm[p], be = nrm[q];
+                // entries per lane: the fewest that hold m rows
                 if (m <= 64) jac_pair_regs<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                else if (m <= 80) jac_pair_regs<5>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                else if (m <= 96) jac_pair_regs<6>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                else if (m <= 112) jac_pair_regs<7>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
                 else if (m <= 128) jac_pair_regs<8>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
                 else jac_pair_loop(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
             }
