@@ -470,6 +470,37 @@ def test_c3_shape_mixed_vs_oracle():
     compare(U, s, so, 1e-5, 1e-5, "c3 shape mixed")
 
 
+def test_c3_full_size_mixed_vs_fp64_path():
+    # The widest configuration at its full 2^22 rows (batches of 512, K = 100,
+    # p = 20, q = 1): the host oracle's FP64 randomized step on 612-column
+    # panels of 2^22 rows would take the better part of an hour, so the mixed
+    # path is held against the FP64 GPU path on the same batches and the same
+    # (BF16-valued) test matrices; the FP64 path is itself held to the oracle at
+    # this shape on fewer rows (test_randomized_*[c3]).  Initialisation batch
+    # plus one steady-state update; norms and angles in FP64 on the device.
+    w = synth.scaled(synth.c3_mixed(), batches=2)
+    bs = synth.planted_stream(w, device="cuda")
+    P = lib()
+    out = {}
+    for prec in ("mixed", "fp64"):
+        svd = P.StreamingSVD(w.M, w.K, ff=w.ff, oversampling=w.oversampling, power_iters=w.power_iters,
+                             randomized=True, precision=prec, seed=w.seed, omega_bf16=True)
+        for b in bs:
+            svd.incorporate_data(b.t())
+        out[prec] = (svd.singular_values.copy(), svd.modes.to(torch.float64))
+        del svd
+    (sm, Um), (sf, Uf) = out["mixed"], out["fp64"]
+    assert len(sm) == w.K and sigma_rel_err(sm, sf) <= 1e-5
+    eye = torch.eye(w.K, dtype=torch.float64, device="cuda")
+    assert float(torch.linalg.norm(Um.t() @ Um - eye)) <= 1e-5
+    assert float(torch.linalg.norm(Uf.t() @ Uf - eye)) <= 1e-12
+    k = gap_limited_k(sf, 1e-5, w.K)
+    assert k >= 10
+    cos = torch.linalg.svdvals((Um[:, :k].t() @ Uf[:, :k]).cpu()).numpy()
+    gap = (sf[k - 1] - sf[k]) / sf[0]
+    assert math.sqrt(max(0.0, 1.0 - float(cos.min()) ** 2)) <= 10 * 1e-5 / gap
+
+
 def test_c4_full_size_apmos_sampled_lift():
     # 64 partitions of 16384 .. 262144 rows, N = 128, r = K = 20.  The global
     # factors are checked by their invariants; the lift U_i = A_i X~ diag(1 / Lambda~)
