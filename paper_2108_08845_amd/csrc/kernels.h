@@ -253,6 +253,11 @@ hipError_t launch_grad_core(const GradCoreArgs& a, hipStream_t st);
 hipError_t launch_grad_sbar(const double* G, int r, const double* s_prev, double* sbar, hipStream_t st);
 
 hipError_t launch_tn(bool fp64, const TnArgs& a, int nitems, hipStream_t st);
+// k_tn_x: non-symmetric FP32 P = L^T R on float4-aligned FP32 operands, R at
+// most TNX_RCOLS columns; one work-group per (TNX_LCOLS columns of L, slot),
+// slot s covering rows [s chunk, (s + 1) chunk) (chunk a multiple of 64).
+constexpr int TNX_LCOLS = 320, TNX_RCOLS = 128;
+hipError_t launch_tn_x(const TnArgs& a, int nslots, hipStream_t st);
 hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st);
 hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st);
 // Compiled configuration of a fused pass: tile height, padded panel width

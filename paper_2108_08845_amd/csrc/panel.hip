@@ -261,6 +261,141 @@ __global__ __launch_bounds__(256) void k_tn_reduce(TnReduceArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// k_tn_x: P = L^T R for wide FP32 operands with float4-aligned columns (L up
+// to 320 columns per work-group, R up to 128 columns), FP32 products on the
+// FP32 matrix cores (16x16x4), non-symmetric.  Work-group (h, s) takes L's
+// columns 320 h .. and the row share [s chunk, (s + 1) chunk): each 64-row
+// tile of L and R is loaded once (k_tn_v's 64 x 64 output blocks re-read L per
+// block of R and R per block of L), staged row-major in LDS, and the next
+// tile's loads are in flight in registers during the products.  Wave w forms
+// P rows 80 (w % 4) .. + 80 and columns 64 (w / 4) .. + 64 of the part (20
+// accumulators); the four lane groups of one product take rows 4 g + u of
+// each 16-row slice.  Rows past the panel are zero in R (their L rows re-read
+// the last four rows).  The share's sums go to partial slot s in k_tn's
+// layout (64 x 64 FP64 blocks, ob = bi + bj mbl) for k_tn_reduce; parts of
+// blocks past the operands' columns are not written.
+// ----------------------------------------------------------------------------
+constexpr int TX_TM = 64, TX_NL = TNX_LCOLS, TX_NR = TNX_RCOLS;
+constexpr int TX_LDL = TX_NL + 4, TX_LDR = TX_NR + 4;
+
+__global__ __launch_bounds__(512) void k_tn_x(TnArgs a) {
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    extern __shared__ __align__(16) float txs[];
+    float* Ls = txs;                        // TX_TM rows x TX_LDL
+    float* Rs = Ls + TX_TM * TX_LDL;        // TX_TM rows x TX_LDR
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const PanelSeg& L = a.lseg;
+    const PanelSeg& R = a.rseg;
+    const int nparts = (L.ncols + TX_NL - 1) / TX_NL;
+    const int h = (int)(blockIdx.x % nparts);
+    const int64_t slot = blockIdx.x / nparts;
+    if (slot >= a.nitems) return;
+    const int64_t rows = L.rows;
+    const int64_t row0 = slot * a.chunk;
+    const int64_t rend = row0 + a.chunk < rows ? row0 + a.chunk : rows;
+    const int nl = L.ncols, nr = R.ncols, l0 = h * TX_NL;
+    const int pr = 80 * (w & 3), pc = 64 * (w >> 2);
+    const int l15 = lane & 15, g4 = 4 * (lane >> 4);
+    // load slots: columns cs + 32 e, rows 4 rp .. 4 rp + 3 of the tile
+    const int cs = tid >> 4, rp = 4 * (tid & 15);
+    const float* lcol[10];
+    const float* rcol[4];
+#pragma unroll
+    for (int e = 0; e < 10; ++e) {
+        const int c = l0 + cs + 32 * e;
+        lcol[e] = (const float*)col_ref(L, c < nl ? c : nl - 1).base;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int c = cs + 32 * e;
+        rcol[e] = (const float*)col_ref(R, c < nr ? c : nr - 1).base;
+    }
+    f4_t pl[10], prr[4];
+    bool rok = false;
+    auto fetch = [&](int64_t t) {
+        const int64_t row = row0 + t * TX_TM + rp;
+        rok = row < rend;
+        const int64_t rowc = rok ? row : rend - 4;
+#pragma unroll
+        for (int e = 0; e < 10; ++e) pl[e] = gld4(lcol[e] + rowc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) prr[e] = gld4(rcol[e] + rowc);
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int e = 0; e < 10; ++e)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Ls[(rp + v) * TX_LDL + cs + 32 * e] = pl[e][v];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Rs[(rp + v) * TX_LDR + cs + 32 * e] = rok ? prr[e][v] : 0.f;
+    };
+    f4_t acc[5][4];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+    const int64_t ntile = rend > row0 ? (rend - row0 + TX_TM - 1) / TX_TM : 0;
+    if (ntile > 0) fetch(0);
+    for (int64_t t = 0; t < ntile; ++t) {
+        stage();
+        lds_barrier();
+        if (t + 1 < ntile) fetch(t + 1);
+#pragma unroll 1
+        for (int kk = 0; kk < TX_TM; kk += 16) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = kk + g4 + u;
+                float av[5], bv[4];
+#pragma unroll
+                for (int i = 0; i < 5; ++i) av[i] = Ls[k * TX_LDL + pr + 16 * i + l15];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bv[j] = Rs[k * TX_LDR + pc + 16 * j + l15];
+#pragma unroll
+                for (int i = 0; i < 5; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        lds_barrier();   // every wave done with the tile before the next one is staged
+    }
+    // P rows l0 + pr + 16 i + 4 g + v, columns pc + 16 j + l15
+    const int mbl = a.mbl, mbr = (nr + TN_OB - 1) / TN_OB;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gc = pc + 16 * j + l15;
+            const int bj = gc / TN_OB;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gr = l0 + pr + 16 * i + g4 + v;
+                const int bi = gr / TN_OB;
+                if (bi < mbl && bj < mbr) {
+                    double* out = a.part + ((size_t)slot * a.nob + bi + (size_t)bj * mbl) * (TN_OB * TN_OB);
+                    out[(gr % TN_OB) + (gc % TN_OB) * TN_OB] = (double)acc[i][j][v];
+                }
+            }
+        }
+}
+
+size_t tn_x_lds() { return ((size_t)TX_TM * TX_LDL + (size_t)TX_TM * TX_LDR) * sizeof(float); }
+
+hipError_t launch_tn_x(const TnArgs& args, int nslots, hipStream_t st) {
+    TnArgs a = args;
+    a.nitems = nslots;
+    const int nparts = (a.lseg.ncols + TX_NL - 1) / TX_NL;
+    if (nslots <= 0 || a.rseg.ncols > TX_NR || a.chunk % TX_TM) return hipErrorInvalidValue;
+    hipError_t e = ensure_lds_attr((const void*)k_tn_x, tn_x_lds());
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tn_x, dim3((unsigned)(nslots * nparts)), dim3(512), tn_x_lds(), st, a);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
 // k_tn_v: k_tn with 16-byte column-segment loads, for operands whose blocks
 // are 16-byte aligned with leading dimensions and row ranges in multiples of
 // four rows (TnArgs::vec).  Same work items, output blocks, partial layout
@@ -918,6 +1053,142 @@ __global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
     }
 }
 
+
+// ----------------------------------------------------------------------------
+// k_nn_x: out[rows, 0 .. nx) = C X for FP32 panels with float4-aligned columns
+// and 32 < nx <= 128, FP32 products on the FP32 matrix cores (16x16x4).  One
+// output block holds every output column, so the panel is read once (k_nn_v's
+// 32-column blocks read it once per block).  The rows of X a chunk needs are
+// streamed from global memory (L2) alongside C: a work-group takes its items'
+// 256-row tiles in 64-column chunks; per chunk the C part (256 x 64, eight
+// float4 loads per thread) and the X part (64 x 128, FP64 values rounded to
+// FP32, zero past n and nx; a quarter-wave loads 16 consecutive rows of one
+// column) are staged in LDS, and the next chunk's loads are
+// in flight in registers during the products.  Wave w forms the 64 x 64 block
+// at rows 64 (w % 4), columns 64 (w / 4) of the tile (16 accumulators); the
+// four lane groups of one product take k = 4 g + u of each 16-k slice.  Rows
+// past the item's end re-read its last four rows and are never stored.
+// ----------------------------------------------------------------------------
+constexpr int NX_TM = 256, NX_KC = 64, NX_OB = 128;
+constexpr int NX_LDC = NX_TM + 4, NX_LDX = NX_OB + 4;
+
+__global__ __launch_bounds__(512) void k_nn_x(NnArgs a) {
+    if (a.skip && (*a.skip & a.skip_mask)) return;
+    if (a.skip && a.need_mask && !(*a.skip & a.need_mask)) return;
+    extern __shared__ __align__(16) float nxs[];
+    float* Cs = nxs;                       // chunk of C: NX_KC columns x NX_LDC
+    float* Xs = Cs + NX_KC * NX_LDC;       // rows of X: NX_KC x NX_LDX, row-major
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n, nx = a.nx;
+    const int nch = (n + NX_KC - 1) / NX_KC;
+    const int rb = (w & 3) * 64, cb = (w >> 2) * 64;
+    const int l15 = lane & 15, g4 = 4 * (lane >> 4);
+    // load slots: C column lc of the chunk, rows lr + 32 e; X rows xk + 16 e of
+    // the chunk, columns xj + 32 q (16 consecutive rows of a column per
+    // quarter-wave; the row-major stores meet 64 distinct banks)
+    const int lc = tid >> 3, lr = 4 * (tid & 7);
+    const int xk = tid & 15, xj = tid >> 4;
+    for (int64_t item = blockIdx.x; item < a.nitems_v; item += gridDim.x) {
+        const WorkItem it = get_item(a.items, a.chunk, a.seg.rows, item);
+        const PanelSeg S = a.segs ? load_seg(a.segs + it.seg) : a.seg;
+        const int64_t row0 = it.row0, rows1 = it.row1;
+        if (row0 >= rows1) continue;
+        const int64_t nstep = (rows1 - row0 + NX_TM - 1) / NX_TM * nch;
+        f4_t pc[8];
+        double px[16];
+        auto fetch = [&](int64_t s) {
+            const int64_t tl = s / nch;
+            const int kc = (int)(s % nch);
+            const int c = kc * NX_KC + lc;
+            const float* col = fcol(S, c < n ? c : n - 1);
+            const int64_t rbase = row0 + tl * NX_TM + lr;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t row = rbase + 32 * e;
+                pc[e] = gld4(col + (row < rows1 ? row : rows1 - 4));
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = kc * NX_KC + xk + 16 * e;
+                const int kk = k < n ? k : n - 1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int j = xj + 32 * q < nx ? xj + 32 * q : nx - 1;
+                    px[4 * e + q] = gldd(a.X + kk + (int64_t)j * a.ldx);
+                }
+            }
+        };
+        auto stage = [&](int64_t s) {
+            const int kc = (int)(s % nch);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) *(f4_t*)&Cs[lc * NX_LDC + lr + 32 * e] = pc[e];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool krow = kc * NX_KC + xk + 16 * e < n;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    Xs[(xk + 16 * e) * NX_LDX + xj + 32 * q] = (krow && xj + 32 * q < nx) ? (float)px[4 * e + q] : 0.f;
+            }
+        };
+        f4_t acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+        fetch(0);
+        for (int64_t s = 0; s < nstep; ++s) {
+            stage(s);
+            lds_barrier();
+            if (s + 1 < nstep) fetch(s + 1);
+#pragma unroll 1
+            for (int kk = 0; kk < NX_KC; kk += 16) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = kk + g4 + u;
+                    float av[4], bv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) av[i] = Cs[k * NX_LDC + rb + 16 * i + l15];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) bv[j] = Xs[k * NX_LDX + cb + 16 * j + l15];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                }
+            }
+            if ((int)(s % nch) == nch - 1) {   // tile complete: rows .. + 16 i + 4 g + v, columns cb + 16 j + l
+                const int64_t r0 = row0 + (s / nch) * NX_TM + rb + g4;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int col = cb + 16 * j + l15;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int64_t row = r0 + 16 * i + v;
+                            if (col < nx && row < rows1) {
+                                double y = (double)acc[i][j][v];
+                                if (a.row_scale && row < a.nscale) y *= a.row_scale[row];
+                                const size_t o = (size_t)row + (size_t)col * (size_t)S.ldo;
+                                if (S.out_dtype == PSVD_F64) {
+                                    double* po = (double*)S.out + o;
+                                    gstd(po, a.accumulate ? gldd(po) + y : y);
+                                } else {
+                                    float* po = (float*)S.out + o;
+                                    gst(po, a.accumulate ? (float)((double)gld(po) + y) : (float)y);
+                                }
+                            }
+                        }
+                        acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+                    }
+                }
+            }
+            lds_barrier();   // every wave done with the chunk before the next one is staged
+        }
+    }
+}
 
 // k_nn_w: C X with FP64 products (CT = double, FP64 matrix cores) or FP32
 // products (CT = float, FP32 matrix cores), 16x16x4, on panels of FP64 and
@@ -3221,6 +3492,16 @@ hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st) {
 }
 
 hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
+    if (!fp64 && a.all_f32 && a.vec_f32 && a.n >= 1 && a.nx > NV_OB && a.nx <= NX_OB) {
+        // all output columns in one block: one read of the panel (one work-group per CU)
+        NnArgs b = a;
+        b.nitems_v = nitems;
+        const size_t lds = ((size_t)NX_KC * NX_LDC + (size_t)NX_KC * NX_LDX) * sizeof(float);
+        hipError_t e = ensure_lds_attr((const void*)k_nn_x, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_nn_x, dim3((unsigned)std::min(nitems, 256)), dim3(512), lds, st, b);
+        return hipGetLastError();
+    }
     if (!fp64 && a.all_f32 && a.vec_f32 && a.n >= 1 && a.n <= NV_NMAX) {
         NnArgs b = a;
         b.nitems_v = nitems;

@@ -444,6 +444,19 @@ static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool
     const int dt = seg_dtype_all(L) == seg_dtype_all(R) ? seg_dtype_all(L) : 0;
     int64_t chunk = tn_chunk(L.rows, nob, tn_wide(sym, mbl, dt), split_items(h));
     int nitems = ceil_div(L.rows, chunk);
+    // wide FP32 projections (C^T Y of panels wider than the fused passes take):
+    // one read of each operand, a partial slot per row share (k_tn_x), as many
+    // shares as fill the CUs and the partial buffer holds
+    int64_t xslots = 0;
+    if (!sym && !fp64 && vec && dt == PSVD_F32 && L.ncols >= 128 && R.ncols > 32 && R.ncols <= TNX_RCOLS) {
+        const int64_t nparts = ceil_div(L.ncols, TNX_LCOLS);
+        const int64_t cap = (int64_t)(h->part.bytes / (64 * 64 * sizeof(double))) / nob;
+        xslots = std::min<int64_t>(std::max<int64_t>(1, 256 / nparts), cap);
+        if (xslots >= 1) {
+            chunk = (int64_t)ceil_div(ceil_div(L.rows, xslots), 64) * 64;
+            nitems = ceil_div(L.rows, chunk);
+        }
+    }
     TnArgs a;
     std::memset(&a, 0, sizeof(a));
     a.lseg = L;
@@ -458,7 +471,8 @@ static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool
     a.vec = vec ? 1 : 0;
     a.dtype_all = dt;
     int pe = prof_begin(h, PSVD_KC_TN);
-    HIPCHK(h, launch_tn(fp64, a, nitems, h->stream));
+    if (xslots >= 1) HIPCHK(h, launch_tn_x(a, nitems, h->stream));
+    else HIPCHK(h, launch_tn(fp64, a, nitems, h->stream));
     prof_end(h, pe);
     TnReduceArgs ra;
     std::memset(&ra, 0, sizeof(ra));
