@@ -1131,6 +1131,15 @@ __host__ __device__ inline size_t rand_lds_doubles(int l) {
 }
 
 // Power-iteration re-orthonormalisation X = D P R^-1 with R = chol(P^T P).
+// When the randomized small kernels keep their matrices in global memory (l
+// too large for two l x l matrices in LDS), their working matrix (the
+// Cholesky factor; in the final core also R_b^T and its Jacobi) and the
+// vectors still sit in LDS if one l x l matrix and 3 l + 8 doubles fit.
+__host__ __device__ inline size_t rand_jac_lds_bytes(int l) {
+    return ((size_t)l * l + 3 * (size_t)l + 8) * sizeof(double);
+}
+__host__ __device__ inline bool rand_jac_in_lds(int l) { return rand_jac_lds_bytes(l) <= 150 * 1024; }
+
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_orth(OrthArgs a) {
     extern __shared__ double lds[];
@@ -1139,9 +1148,10 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_orth(OrthArgs a) {
     const int l = a.l, n = a.n;
     constexpr bool in_lds = IN_LDS;
     const bool staged = in_lds && l <= 64;
-    double* R = in_lds ? lds : a.R;
+    const bool r_lds = in_lds || rand_jac_in_lds(l);
+    double* R = r_lds ? lds : a.R;
     double* Ri = in_lds ? lds + (size_t)l * l : a.Ri;
-    double* rinv = in_lds ? lds + 2 * (size_t)l * l : a.vec;
+    double* rinv = in_lds ? lds + 2 * (size_t)l * l : r_lds ? lds + (size_t)l * l : a.vec;
     double* Cn = lds + 2 * (size_t)l * l + 3 * (size_t)l + 8;
     // G = P^T P (global scratch, kept for the shifted retry)
     if (staged) wg_gram_tall(n, l, a.P, n, a.G, l, Cn);
@@ -1171,9 +1181,11 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     const bool staged = in_lds && l <= 64;
     // staged: W spans 64 x l so that R_b^T can take leading dimension 64
     const size_t wsz = staged ? 64 * (size_t)l : (size_t)l * l;
-    double* W = in_lds ? lds : a.W;                      // working l x l
+    // global-memory form: the working matrix and the vectors still in LDS when they fit
+    const bool w_lds = in_lds || rand_jac_in_lds(l);
+    double* W = w_lds ? lds : a.W;                       // working l x l
     double* V = in_lds ? lds + wsz : a.V;                // second l x l
-    double* vec = in_lds ? lds + wsz + (size_t)l * l : a.vec;   // 2 l + 1 doubles + l ints
+    double* vec = in_lds ? lds + wsz + (size_t)l * l : w_lds ? lds + (size_t)l * l : a.vec;   // 2 l + 1 doubles + l ints
     double* Cn = lds + wsz + (size_t)l * l + 3 * (size_t)l + 8;   // staging chunk (staged only)
     const int rk = a.K < l ? a.K : l;
     auto bail = [&]() {
@@ -1304,11 +1316,13 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
         __syncthreads();
     }
     wg_gemm_f64(l, l, l, V, 1, l, RYi, 1, l, W, ldw, 1, nullptr, 0);
-    double* sig = vec;
+    double* Wj = W;
+    double* vj = vec;
+    double* sig = vj;
     double* nrm = sig + l;
     int* ord = (int*)(nrm + l + 1);
-    const int sw = staged ? wg_jacobi_pad64(W, l, l, sig, ord, nrm, a.max_sweeps, &sflag, red, a.stop_cos2)
-                          : wg_jacobi(W, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
+    const int sw = staged ? wg_jacobi_pad64(Wj, l, l, sig, ord, nrm, a.max_sweeps, &sflag, red, a.stop_cos2)
+                          : wg_jacobi(Wj, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
@@ -1317,7 +1331,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     double* Us = in_lds ? V : a.small_u;
     for (int e = tid; e < l * rk; e += SM_THREADS) {
         const int i = e % l, j = e / l;
-        Us[i + (size_t)j * l] = W[i + (size_t)ord[j] * ldw];
+        Us[i + (size_t)j * l] = Wj[i + (size_t)ord[j] * ldw];
     }
     for (int j = tid; j < rk; j += SM_THREADS) a.s_out[j] = sig[ord[j]];
     __syncthreads();
@@ -1566,7 +1580,7 @@ static bool rand_in_lds(int l) { return rand_lds_bytes(l) <= 150 * 1024; }
 
 hipError_t launch_small_orth(const OrthArgs& a, hipStream_t st) {
     const bool in_lds = rand_in_lds(a.l);
-    const size_t lds = in_lds ? rand_lds_bytes(a.l) : 64;
+    const size_t lds = in_lds ? rand_lds_bytes(a.l) : rand_jac_in_lds(a.l) ? rand_jac_lds_bytes(a.l) : 64;
     const void* fn = in_lds ? (const void*)k_small_orth<true> : (const void*)k_small_orth<false>;
     hipError_t e = ensure_lds_attr(fn, lds);
     if (e != hipSuccess) return e;
@@ -1576,7 +1590,7 @@ hipError_t launch_small_orth(const OrthArgs& a, hipStream_t st) {
 }
 hipError_t launch_small_rand_final(const RandFinalArgs& a, hipStream_t st) {
     const bool in_lds = rand_in_lds(a.l);
-    const size_t lds = in_lds ? rand_lds_bytes(a.l) : 64;
+    const size_t lds = in_lds ? rand_lds_bytes(a.l) : rand_jac_in_lds(a.l) ? rand_jac_lds_bytes(a.l) : 64;
     const void* fn = in_lds ? (const void*)k_small_rand_final<true> : (const void*)k_small_rand_final<false>;
     hipError_t e = ensure_lds_attr(fn, lds);
     if (e != hipSuccess) return e;
