@@ -488,6 +488,11 @@ def main():
         flops = 6.0 * 4.0 * w.M * n * ell
         roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS["bf16"],
                 "unit": "TFLOP/s"}
+    elif dom == "wide":
+        # wide panels: Y = C X and C^T Y on the FP32 matrix cores, one read of the
+        # panel each, 2 M n l algorithmic flops per launch
+        roof = {"bound": "mfma", "achieved": 2.0 * w.M * n * ell / (avg_ms * 1e-3) / 1e12,
+                "peak": MFMA_PEAK_TFLOPS["f32"], "unit": "TFLOP/s"}
     elif dom == "nn":
         # generic Y = C X (panel read, sketch written)
         roof = {"bound": "hbm", "achieved": (panel_bytes + w.M * ell * 4) / (avg_ms * 1e-3) / 1e9,

@@ -93,7 +93,10 @@ enum {
     PSVD_KC_SPLIT = 7,         /* final passes on split-BF16 operands (C^T Y, Y kept) */
     PSVD_KC_SPLIT3 = 8,        /* C^T (C X) on three-term BF16 splits: the FP32-
                                   accurate power passes of the mixed precision     */
-    PSVD_KC_COUNT = 9
+    PSVD_KC_WIDE = 9,          /* C X and C^T Y on the FP32 matrix cores for panels
+                                  wider than the fused passes take, one read of
+                                  the panel per product                            */
+    PSVD_KC_COUNT = 10
 };
 
 typedef struct psvd_options {
@@ -118,8 +121,8 @@ typedef struct psvd_stats_t {
     int32_t last_sweeps;        /* Jacobi sweeps of the last small SVD           */
     int32_t last_path;          /* 0 deterministic, 1 randomized                 */
     double last_update_ms;      /* device time of the last update (events)       */
-    int64_t kernel_launches[9]; /* per kernel class (PSVD_OPT_PROFILE)           */
-    double kernel_ms[9];        /* summed device time per kernel class           */
+    int64_t kernel_launches[10]; /* per kernel class (PSVD_OPT_PROFILE)          */
+    double kernel_ms[10];        /* summed device time per kernel class          */
 } psvd_stats_t;
 
 /* Fill *opt with defaults: deterministic, FP64, seed 0, default stream. */

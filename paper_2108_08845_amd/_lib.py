@@ -20,7 +20,7 @@ PSVD_F32, PSVD_F64 = 1, 2
 DETERMINISTIC, RANDOMIZED = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED, PREC_BF16 = 0, 1, 2, 3
 OPT_ASYNC, OPT_NO_FALLBACK, OPT_PROFILE, OPT_OMEGA_BF16, OPT_GRAPH = 1, 2, 4, 8, 16
-KERNEL_CLASSES = ["fused_bf16", "fused_f32", "lift", "tn", "nn", "small", "small_svd", "split", "split3"]
+KERNEL_CLASSES = ["fused_bf16", "fused_f32", "lift", "tn", "nn", "small", "small_svd", "split", "split3", "wide"]
 
 EXPORTS = [
     "psvd_default_options", "psvd_initialize", "psvd_incorporate_data", "psvd_rank", "psvd_singular_values",
@@ -45,7 +45,7 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("batches", ctypes.c_int64), ("fallbacks", ctypes.c_int64), ("last_sweeps", ctypes.c_int32),
         ("last_path", ctypes.c_int32), ("last_update_ms", ctypes.c_double),
-        ("kernel_launches", ctypes.c_int64 * 9), ("kernel_ms", ctypes.c_double * 9),
+        ("kernel_launches", ctypes.c_int64 * 10), ("kernel_ms", ctypes.c_double * 10),
     ]
 
 

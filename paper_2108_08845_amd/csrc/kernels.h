@@ -253,6 +253,11 @@ hipError_t launch_grad_core(const GradCoreArgs& a, hipStream_t st);
 hipError_t launch_grad_sbar(const double* G, int r, const double* s_prev, double* sbar, hipStream_t st);
 
 hipError_t launch_tn(bool fp64, const TnArgs& a, int nitems, hipStream_t st);
+// launch_nn takes k_nn_x (one read of the panel, all output columns per
+// work-group) for FP32 products on float4-aligned FP32 panels with 32 < nx <= 128.
+inline bool nn_wide(bool fp64, const NnArgs& a) {
+    return !fp64 && a.all_f32 && a.vec_f32 && a.n >= 1 && a.nx > 32 && a.nx <= 128;
+}
 // k_tn_x: non-symmetric FP32 P = L^T R on float4-aligned FP32 operands, R at
 // most TNX_RCOLS columns; one work-group per (TNX_LCOLS columns of L, slot),
 // slot s covering rows [s chunk, (s + 1) chunk) (chunk a multiple of 64).

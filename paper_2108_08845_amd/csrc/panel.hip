@@ -1069,7 +1069,7 @@ __global__ __launch_bounds__(256) void k_nn_v(NnArgs a) {
 // four lane groups of one product take k = 4 g + u of each 16-k slice.  Rows
 // past the item's end re-read its last four rows and are never stored.
 // ----------------------------------------------------------------------------
-constexpr int NX_TM = 256, NX_KC = 64, NX_OB = 128;
+constexpr int NX_TM = 256, NX_KC = 64, NX_OB = 128;   // nn_wide: NV_OB < nx <= NX_OB
 constexpr int NX_LDC = NX_TM + 4, NX_LDX = NX_OB + 4;
 
 __global__ __launch_bounds__(512) void k_nn_x(NnArgs a) {
@@ -3492,7 +3492,7 @@ hipError_t launch_tn_reduce(const TnReduceArgs& a, int nseg, hipStream_t st) {
 }
 
 hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
-    if (!fp64 && a.all_f32 && a.vec_f32 && a.n >= 1 && a.nx > NV_OB && a.nx <= NX_OB) {
+    if (nn_wide(fp64, a)) {
         // all output columns in one block: one read of the panel (one work-group per CU)
         NnArgs b = a;
         b.nitems_v = nitems;

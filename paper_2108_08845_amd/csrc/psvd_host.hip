@@ -470,7 +470,7 @@ static int tn_product(psvd_handle* h, const PanelSeg& L, const PanelSeg& R, bool
     a.nob = nob;
     a.vec = vec ? 1 : 0;
     a.dtype_all = dt;
-    int pe = prof_begin(h, PSVD_KC_TN);
+    int pe = prof_begin(h, xslots >= 1 ? PSVD_KC_WIDE : PSVD_KC_TN);
     if (xslots >= 1) HIPCHK(h, launch_tn_x(a, nitems, h->stream));
     else HIPCHK(h, launch_tn(fp64, a, nitems, h->stream));
     prof_end(h, pe);
@@ -517,6 +517,7 @@ static int nn_product(psvd_handle* h, const PanelSeg& S, const double* X, int64_
     a.all_f32 = (!fp64 && seg_all_f32(S)) ? 1 : 0;
     a.vec_f32 = (a.all_f32 && seg_vec_ok(S, false)) ? 1 : 0;
     a.vec16 = seg_vec_ok(S, false) ? 1 : 0;
+    if (cls == PSVD_KC_NN && nn_wide(fp64, a)) cls = PSVD_KC_WIDE;   // k_nn_x
     int pe = prof_begin(h, cls);
     HIPCHK(h, launch_nn(fp64, a, nitems, h->stream));
     prof_end(h, pe);
