@@ -374,7 +374,11 @@ static int ensure_workspace(psvd_handle* h, int n) {
     // k_tn partials: items x output blocks stays near 1024 (see pick_chunk)
     int nb = ceil_div(w, 64);
     size_t nob = (size_t)nb * nb;
-    HIPCHK(h, h->part.ensure((size_t)(2 * std::max(1024, split_items(h)) + 2 * nob) * 64 * 64 * sizeof(double)));
+    // k_tn_x: one partial slot per row share, 256 work-groups over the
+    // 320-column parts of a wide panel
+    const size_t xblocks = (size_t)(256 / ceil_div(n, TNX_LCOLS)) * ceil_div(n, 64) * ceil_div(std::min(l, TNX_RCOLS), 64);
+    HIPCHK(h, h->part.ensure(std::max((size_t)(2 * std::max(1024, split_items(h)) + 2 * nob), xblocks) * 64 * 64 *
+                             sizeof(double)));
     // fused-pass partials: one NP x 64 block per (work-group, column block)
     const int pw = plan_width(h, n);
     int np = ((pw + 63) / 64) * 64;
