@@ -1222,7 +1222,7 @@ __host__ __device__ inline size_t nn_w_lds(int n) {
            (size_t)npad * sizeof(uint64_t);
 }
 
-template <class CT, bool VEC>
+template <class CT, bool VEC, bool F32 = false>
 __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
     using MF = Mfma<CT>;
     using V = typename std::conditional<VEC, f4_t, uint64_t>::type;   // one slot's load
@@ -1295,14 +1295,19 @@ __global__ __launch_bounds__(512) void k_nn_w(NnArgs a) {
                     m |= (ok ? 1u : 0u) << e;
                 } else {
                     // the same two 32-bit loads for either dtype (an FP32 element
-                    // re-read as its high word): no load sits in a dtype branch
+                    // re-read as its high word): no load sits in a dtype branch;
+                    // all-FP32 panels (F32) take one load per element
                     const int64_t row = r0 + p;
                     const bool ok = s < nstep && row < rows1;
                     const int64_t rowc = ok ? row : it.row0;
                     const uint32_t* q = (const uint32_t*)(base + rowc * (f64 ? 8 : 4));
                     const uint32_t lo = *(const PSVD_GLOBAL uint32_t*)q;
-                    const uint32_t hi = *(const PSVD_GLOBAL uint32_t*)(q + (f64 ? 1 : 0));
-                    v[e] = ((uint64_t)hi << 32) | lo;
+                    if constexpr (F32) {
+                        v[e] = lo;
+                    } else {
+                        const uint32_t hi = *(const PSVD_GLOBAL uint32_t*)(q + (f64 ? 1 : 0));
+                        v[e] = ((uint64_t)hi << 32) | lo;
+                    }
                     m |= (ok ? 1u : 0u) << e;
                 }
                 m |= (f64 ? 1u : 0u) << (NE + e);
@@ -3534,6 +3539,7 @@ hipError_t launch_nn(bool fp64, const NnArgs& a, int nitems, hipStream_t st) {
         };
         if (fp64) return go(k_nn_w<double, true>, nn_w_lds<double>(a.n));
         if (a.vec16) return go(k_nn_w<float, true>, nn_w_lds<float>(a.n));
+        if (a.all_f32) return go(k_nn_w<float, false, true>, nn_w_lds<float>(a.n));
         return go(k_nn_w<float, false>, nn_w_lds<float>(a.n));
     }
     dim3 grid(nitems, (a.nx + NN_OB - 1) / NN_OB);
