@@ -681,15 +681,15 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
                 const int cb = 1 + xb;                   // pb >= ne / 2 > 0
                 const int p = ca < cb ? ca : cb, q = ca < cb ? cb : ca;
                 if (q < n) {
-                    double* zp = Z + p * ldz + ql;
-                    double* zq = Z + q * ldz + ql;
+                    // lane ql holds rows 2 ql, 2 ql + 1, 32 + 2 ql, 33 + 2 ql: two
+                    // 16-byte accesses per column
+                    double* zp = Z + p * ldz + 2 * ql;
+                    double* zq = Z + q * ldz + 2 * ql;
                     const double al = nrm[p], be = nrm[q];
-                    double xp[4], xq[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        xp[u] = zp[16 * u];
-                        xq[u] = zq[16 * u];
-                    }
+                    const d2_t p0 = *(const d2_t*)zp, p1 = *(const d2_t*)(zp + 32);
+                    const d2_t q0 = *(const d2_t*)zq, q1 = *(const d2_t*)(zq + 32);
+                    const double xp[4] = {p0[0], p0[1], p1[0], p1[1]};
+                    const double xq[4] = {q0[0], q0[1], q1[0], q1[1]};
                     double g0 = xp[0] * xq[0], g1 = xp[1] * xq[1];
                     g0 = fma(xp[2], xq[2], g0);
                     g1 = fma(xp[3], xq[3], g1);
@@ -702,11 +702,10 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
                             const double uu = fabs(dif) + __builtin_amdgcn_sqrt(fma(dif, dif, 4.0 * gg));
                             const double hh = rsqrt(fma(uu, uu, 4.0 * gg));
                             const double c = uu * hh, s = (dif >= 0.0 ? 2.0 * g : -2.0 * g) * hh;
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                zp[16 * u] = c * xp[u] - s * xq[u];
-                                zq[16 * u] = s * xp[u] + c * xq[u];
-                            }
+                            *(d2_t*)zp = d2_t{c * xp[0] - s * xq[0], c * xp[1] - s * xq[1]};
+                            *(d2_t*)(zp + 32) = d2_t{c * xp[2] - s * xq[2], c * xp[3] - s * xq[3]};
+                            *(d2_t*)zq = d2_t{s * xp[0] + c * xq[0], s * xp[1] + c * xq[1]};
+                            *(d2_t*)(zq + 32) = d2_t{s * xp[2] + c * xq[2], s * xp[3] + c * xq[3]};
                             if (ql == 0) {
                                 const double cs2g = 2.0 * c * s * g;
                                 nrm[p] = c * c * al + s * s * be - cs2g;
@@ -935,7 +934,7 @@ __device__ __forceinline__ double dscale(const SmallArgs& a, int j) { return j <
 
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ int sflag;
     __shared__ int nonfinite;
     const int n = a.n, tid = threadIdx.x;
@@ -1009,7 +1008,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
 // T = D R^-1 U~_rk.
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ int sflag;
     if (*a.status & (DEV_FALLBACK | DEV_NONFINITE | DEV_BREAKDOWN)) return;
     const int n = a.n, tid = threadIdx.x;
@@ -1142,7 +1141,7 @@ __host__ __device__ inline bool rand_jac_in_lds(int l) { return rand_jac_lds_byt
 
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_orth(OrthArgs a) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ double red[SM_THREADS];
     if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
     const int l = a.l, n = a.n;
@@ -1172,7 +1171,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_orth(OrthArgs a) {
 //   S;  sort, sign rule, keep rk = min(K, l);  M2 = R_Y^-1 U~_rk.
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ double red[SM_THREADS];
     __shared__ int sflag;
     if (*a.status & (DEV_NONFINITE | DEV_BREAKDOWN)) return;
@@ -1496,7 +1495,7 @@ hipError_t launch_low_rank_small(const LowRankArgs& a, hipStream_t st) {
 // W_i = V_i[:, :r] diag(sqrt(lambda_i[:r])) stored transposed.
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ int sflag;
     const int i = blockIdx.x, N = a.N, tid = threadIdx.x;
     constexpr bool in_lds = IN_LDS;
@@ -1521,7 +1520,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
 // T = X~ diag(1 / Lambda~) with the guard Lambda~_K > N 2^-53 Lambda~_1.
 template <bool IN_LDS>
 __global__ __launch_bounds__(SM_THREADS) void k_apmos_global(ApmosGlobalArgs a) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ int sflag;
     const int N = a.N, tid = threadIdx.x;
     constexpr bool in_lds = IN_LDS;
