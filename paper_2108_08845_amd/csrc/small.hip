@@ -515,6 +515,40 @@ __device__ __forceinline__ void jac_pair_regs(double* zp, double* zq, int m, int
     if (ql == 0) jac_rotate_norms(c, s, g, al, be, np, nq, sflag);
 }
 
+// jac_pair_regs with 16-byte accesses: lane ql holds rows 32 u + 2 ql and the
+// next (u < E2, at most 32 E2 rows); m even and the columns 16-byte aligned.
+template <int E2>
+__device__ __forceinline__ void jac_pair_regs2(double* zp, double* zq, int m, int ql, double al, double be, double negl,
+                                               double tol, double* np, double* nq, int* sflag) {
+    double xp[2 * E2], xq[2 * E2];
+    double g = 0.0;
+#pragma unroll
+    for (int u = 0; u < E2; ++u) {
+        const int i = 32 * u + 2 * ql;
+        const int ic = i < m ? i : m - 2;
+        d2_t a = *(const d2_t*)(zp + ic), b = *(const d2_t*)(zq + ic);
+        if (i >= m) a = b = d2_t{0.0, 0.0};
+        xp[2 * u] = a[0];
+        xp[2 * u + 1] = a[1];
+        xq[2 * u] = b[0];
+        xq[2 * u + 1] = b[1];
+        g = fma(a[0], b[0], g);
+        g = fma(a[1], b[1], g);
+    }
+    g = q16_sum(g);
+    double c, s;
+    if (!jac_angle(g, al, be, negl, tol, &c, &s)) return;
+#pragma unroll
+    for (int u = 0; u < E2; ++u) {
+        const int i = 32 * u + 2 * ql;
+        if (i < m) {
+            *(d2_t*)(zp + i) = d2_t{c * xp[2 * u] - s * xq[2 * u], c * xp[2 * u + 1] - s * xq[2 * u + 1]};
+            *(d2_t*)(zq + i) = d2_t{s * xp[2 * u] + c * xq[2 * u], s * xp[2 * u + 1] + c * xq[2 * u + 1]};
+        }
+    }
+    if (ql == 0) jac_rotate_norms(c, s, g, al, be, np, nq, sflag);
+}
+
 __device__ __forceinline__ void jac_pair_loop(double* zp, double* zq, int m, int ql, double al, double be, double negl,
                                               double tol, double* np, double* nq, int* sflag) {
     double g = 0.0;
@@ -537,17 +571,21 @@ __device__ __forceinline__ void jac_pair_loop(double* zp, double* zq, int m, int
 // columns by descending sig (stable).  Parallel round-robin ordering: each
 // round rotates n/2 disjoint pairs, one pair per quarter-wave (16 lanes) at a time.
 // With cmap, column j of the iteration is column cmap[j] of Z (sig, order and
-// nrm stay indexed by j).
+// nrm stay indexed by j).  acc16 asks for 16-byte accesses (two rows per lane
+// and access; taken when m and ldz are even and Z is 16-byte aligned): faster
+// for the 120 x 120 matrix of the wide randomized core, slower for the 74-row
+// R and the 128-row APMOS factors, so callers choose.
 // Returns the number of sweeps (> max_sweeps: not converged).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* order, double* nrm,
-                                         int max_sweeps, int* sflag, const int* cmap = nullptr) {
+                                         int max_sweeps, int* sflag, const int* cmap = nullptr, bool acc16 = false) {
     // One pair per quarter-wave (16 lanes): a round of n/2 disjoint pairs runs
     // in one pass when blockDim.x / 16 >= n / 2.
     const int tid = threadIdx.x;
     const int ql = tid & 15, qw = tid >> 4, nq = blockDim.x >> 4;
     const double tol = (double)m * 0x1p-53;
     const int ne = n + (n & 1);
+    const bool v2 = acc16 && (m % 2) == 0 && (ldz % 2) == 0 && ((uintptr_t)Z % 16) == 0;
     int sweep = 0;
     for (;;) {
         for (int j = qw; j < n; j += nq) {
@@ -585,8 +623,13 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
                 double* zp = Z + (size_t)(cmap ? cmap[p] : p) * ldz;
                 double* zq = Z + (size_t)(cmap ? cmap[q] : q) * ldz;
                 const double al = nrm[p], be = nrm[q];
-                // entries per lane: the fewest that hold m rows
-                if (m <= 64) jac_pair_regs<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                // entries per lane: the fewest that hold m rows (pairs of rows per
+                // 16-byte access when m and the leading dimension are even)
+                if (v2 && m <= 32) jac_pair_regs2<1>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                else if (v2 && m <= 64) jac_pair_regs2<2>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                else if (v2 && m <= 96) jac_pair_regs2<3>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                else if (v2 && m <= 128) jac_pair_regs2<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                else if (m <= 64) jac_pair_regs<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
                 else if (m <= 80) jac_pair_regs<5>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
                 else if (m <= 96) jac_pair_regs<6>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
                 else if (m <= 112) jac_pair_regs<7>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
@@ -1321,7 +1364,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_rand_final(RandFinalArgs a
     double* nrm = sig + l;
     int* ord = (int*)(nrm + l + 1);
     const int sw = staged ? wg_jacobi_pad64(Wj, l, l, sig, ord, nrm, a.max_sweeps, &sflag, red, a.stop_cos2)
-                          : wg_jacobi(Wj, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag);
+                          : wg_jacobi(Wj, l, l, l, sig, ord, nrm, a.max_sweeps, &sflag, nullptr, true);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
