@@ -263,6 +263,7 @@ static int apmos_run(int32_t P, const void* const* A_parts, const int64_t* M_par
             la.r = r;
             la.P = P;
             la.max_sweeps = 60;
+            la.data_f32 = fp64 ? 0 : 1;
             la.vec = d_vec;
             la.ivec = d_ivec;
             la.status = d_stat;

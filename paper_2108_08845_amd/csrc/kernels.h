@@ -191,6 +191,8 @@ struct ApmosLocalArgs {
     double* Wt;         // (P r) x N, column-major: row block i = W_i^T
     int32_t N, r, P;
     int32_t max_sweeps;
+    int32_t data_f32;   // partitions stored in FP32: the eigen-decompositions' rank
+                        //   tolerance is the data's rounding level (N 2^-48 max diag)
     double* vec;        // P * 2N
     int32_t* ivec;      // P * 3N
     int32_t* status;

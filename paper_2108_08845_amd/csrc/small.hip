@@ -805,9 +805,12 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
 //   1. Diagonal pivoting: step k takes the largest diagonal entry d of the
 //      Schur complement (lowest index p on ties) and subtracts
 //      A(:, p) A(:, p)^T / d from the rows and columns still in play; it stops
-//      once d <= n 2^-53 max_j A_jj (LAPACK's default tolerance for its
-//      pivoted Cholesky, xPSTRF), so the complement left out is within the
-//      backward error of the factorisation.  Column p keeps its step-k entries: at the
+//      once d <= tolf max_j A_jj.  tolf = n 2^-53 is LAPACK's default tolerance
+//      for its pivoted Cholesky (xPSTRF): the complement left out is within
+//      the backward error of the factorisation.  For the Gram of FP32 data,
+//      tolf = n 2^-48: the rounding E of the data (|E| <= 2^-24 |data|) has
+//      ||E||^2 <= 2^-48 trace(A) <= n 2^-48 max_j A_jj, so eigenvalues below
+//      that are the data's rounding.  Column p keeps its step-k entries: at the
 //      rows still in play they are d^(1/2) times row k of the factor R, where
 //      A ~ R^T R over the r pivots.
 //   2. B = R^T (n x r, rows in the original index order, A ~ B B^T) is formed
@@ -823,14 +826,14 @@ __device__ __forceinline__ int wg_jacobi_pad64(double* Z, int m, int n, double* 
 // returned as col).  Returns the Jacobi sweep count (> max_sweeps: not
 // converged).
 __device__ int wg_psd_eig(double* A, int n, double* sig, double* nrm, int* ord, int* state, int* cmap,
-                          int max_sweeps, int* sflag, double** sv, int** col) {
+                          int max_sweeps, int* sflag, double** sv, int** col, double tolf) {
     const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
     for (int j = tid; j < n; j += nt) state[j] = -1;   // state[j]: step at which j was pivoted
     double dm = 0.0;   // largest diagonal entry, by every wave alike
     for (int j = lane; j < n; j += 64) dm = fmax(dm, A[j + (size_t)j * n]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, 64));
-    const double tol = dm * ((double)n * 0x1p-53);
+    const double tol = dm * tolf;
     __syncthreads();
     int r = 0, prev = -1;
     for (; r < n; ++r) {
@@ -1026,7 +1029,8 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det1(SmallArgs a) {
     int* ord = in_lds ? (int*)(nrm + n + 1) : a.ivec;
     double* sv;
     int* col;
-    int sw = wg_psd_eig(W, n, sig, nrm, ord, ord + n, ord + 2 * n, a.max_sweeps, &sflag, &sv, &col);
+    int sw = wg_psd_eig(W, n, sig, nrm, ord, ord + n, ord + 2 * n, a.max_sweeps, &sflag, &sv, &col,
+                        (double)n * 0x1p-53);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
@@ -1548,7 +1552,8 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_local(ApmosLocalArgs a) {
     int* ord = in_lds ? (int*)(nrm + N + 1) : a.ivec + (size_t)i * 3 * N;
     double* sv;
     int* col;
-    int sw = wg_psd_eig(G, N, sig, nrm, ord, ord + N, ord + 2 * N, a.max_sweeps, &sflag, &sv, &col);
+    int sw = wg_psd_eig(G, N, sig, nrm, ord, ord + N, ord + 2 * N, a.max_sweeps, &sflag, &sv, &col,
+                        (double)N * (a.data_f32 ? 0x1p-48 : 0x1p-53));
     if (tid == 0 && sw > a.max_sweeps) atomicOr(a.status, (int)DEV_NOCONV);
     if (tid == 0) atomicMax(a.sweeps, sw);
     const int ldw = a.P * a.r;
@@ -1573,7 +1578,8 @@ __global__ __launch_bounds__(SM_THREADS) void k_apmos_global(ApmosGlobalArgs a) 
     int* ordv = in_lds ? (int*)(nrm + N + 1) : a.ivec;
     double* sv;
     int* col;
-    int sw = wg_psd_eig(WW, N, sig, nrm, ordv, ordv + N, ordv + 2 * N, a.max_sweeps, &sflag, &sv, &col);
+    int sw = wg_psd_eig(WW, N, sig, nrm, ordv, ordv + N, ordv + 2 * N, a.max_sweeps, &sflag, &sv, &col,
+                        (double)N * 0x1p-53);
     if (tid == 0) {
         atomicMax(a.sweeps, sw);
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
