@@ -148,6 +148,8 @@ struct SmallArgs {
     int32_t* status;      // DevStatus bits
     int32_t* sweeps;      // last Jacobi sweep count
     int32_t skip_svd;     // k_small_det2 stops after R = R2 R1 (the caller takes the SVD of R)
+    double stop_cos2;     // > 0: the Jacobi of R ends after a sweep whose largest cos^2 is at
+                          //   most max(this, m 2^-53) (FP32 precision); 0: no early end
 };
 
 struct OrthArgs {

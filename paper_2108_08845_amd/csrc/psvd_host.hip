@@ -840,6 +840,7 @@ int psvd_incorporate_data(psvd_handle* h, const void* A, int64_t M, int64_t N, i
         SmallArgs sa;
         std::memset(&sa, 0, sizeof(sa));
         sa.n = n;
+        sa.stop_cos2 = h->opt.precision == PSVD_PREC_FP64 ? 0.0 : 0x1p-30;
         sa.r = r;
         sa.K = h->K;
         sa.l = 0;
@@ -2140,6 +2141,7 @@ int psvd_pstream_incorporate(psvd_handle* h, const void* const* A_parts, const i
     SmallArgs sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.n = n;
+    sa.stop_cos2 = h->opt.precision == PSVD_PREC_FP64 ? 0.0 : 0x1p-30;
     sa.r = r;
     sa.K = h->K;
     sa.l = 0;

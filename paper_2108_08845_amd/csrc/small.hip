@@ -489,7 +489,7 @@ __device__ __forceinline__ bool jac_angle(double g, double al, double be, double
 
 template <int E>
 __device__ __forceinline__ void jac_pair_regs(double* zp, double* zq, int m, int ql, double al, double be, double negl,
-                                              double tol, double* np, double* nq, int* sflag) {
+                                              double tol, double* np, double* nq, int* sflag, double stop, int* sfar) {
     double xp[E], xq[E];
     double g = 0.0;
 #pragma unroll
@@ -502,6 +502,7 @@ __device__ __forceinline__ void jac_pair_regs(double* zp, double* zq, int m, int
         g += xp[u] * xq[u];
     }
     g = q16_sum(g);
+    if (stop > 0.0 && ql == 0 && al > negl && be > negl && g * g > stop * (al * be)) *sfar = 1;
     double c, s;
     if (!jac_angle(g, al, be, negl, tol, &c, &s)) return;
 #pragma unroll
@@ -519,7 +520,7 @@ __device__ __forceinline__ void jac_pair_regs(double* zp, double* zq, int m, int
 // next (u < E2, at most 32 E2 rows); m even and the columns 16-byte aligned.
 template <int E2>
 __device__ __forceinline__ void jac_pair_regs2(double* zp, double* zq, int m, int ql, double al, double be, double negl,
-                                               double tol, double* np, double* nq, int* sflag) {
+                                               double tol, double* np, double* nq, int* sflag, double stop, int* sfar) {
     double xp[2 * E2], xq[2 * E2];
     double g = 0.0;
 #pragma unroll
@@ -536,6 +537,7 @@ __device__ __forceinline__ void jac_pair_regs2(double* zp, double* zq, int m, in
         g = fma(a[1], b[1], g);
     }
     g = q16_sum(g);
+    if (stop > 0.0 && ql == 0 && al > negl && be > negl && g * g > stop * (al * be)) *sfar = 1;
     double c, s;
     if (!jac_angle(g, al, be, negl, tol, &c, &s)) return;
 #pragma unroll
@@ -550,10 +552,11 @@ __device__ __forceinline__ void jac_pair_regs2(double* zp, double* zq, int m, in
 }
 
 __device__ __forceinline__ void jac_pair_loop(double* zp, double* zq, int m, int ql, double al, double be, double negl,
-                                              double tol, double* np, double* nq, int* sflag) {
+                                              double tol, double* np, double* nq, int* sflag, double stop, int* sfar) {
     double g = 0.0;
     for (int i = ql; i < m; i += 16) g += zp[i] * zq[i];
     g = q16_sum(g);
+    if (stop > 0.0 && ql == 0 && al > negl && be > negl && g * g > stop * (al * be)) *sfar = 1;
     double c, s;
     if (!jac_angle(g, al, be, negl, tol, &c, &s)) return;
     for (int i = ql; i < m; i += 16) {
@@ -574,11 +577,15 @@ __device__ __forceinline__ void jac_pair_loop(double* zp, double* zq, int m, int
 // nrm stay indexed by j).  acc16 asks for 16-byte accesses (two rows per lane
 // and access; taken when m and ldz are even and Z is 16-byte aligned): faster
 // for the 120 x 120 matrix of the wide randomized core, slower for the 74-row
-// R and the 128-row APMOS factors, so callers choose.
+// R and the 128-row APMOS factors, so callers choose.  stop_cos2 > 0 ends the
+// iteration after a sweep whose largest squared cosine g^2 / (al be) is at most
+// max(stop_cos2, tol), as wg_jacobi_pad64 does (convergence is quadratic).
 // Returns the number of sweeps (> max_sweeps: not converged).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, double* sig, int* order, double* nrm,
-                                         int max_sweeps, int* sflag, const int* cmap = nullptr, bool acc16 = false) {
+                                         int max_sweeps, int* sflag, const int* cmap = nullptr, bool acc16 = false,
+                                         double stop_cos2 = 0.0) {
+    __shared__ int jfar;   // a pair of this sweep had cos^2 above the early-end bound
     // One pair per quarter-wave (16 lanes): a round of n/2 disjoint pairs runs
     // in one pass when blockDim.x / 16 >= n / 2.
     const int tid = threadIdx.x;
@@ -586,6 +593,7 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
     const double tol = (double)m * 0x1p-53;
     const int ne = n + (n & 1);
     const bool v2 = acc16 && (m % 2) == 0 && (ldz % 2) == 0 && ((uintptr_t)Z % 16) == 0;
+    const double stop = stop_cos2 > 0.0 ? (stop_cos2 > tol ? stop_cos2 : tol) : 0.0;
     int sweep = 0;
     for (;;) {
         for (int j = qw; j < n; j += nq) {
@@ -595,7 +603,10 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
             s = q16_sum(s);
             if (ql == 0) nrm[j] = s;
         }
-        if (tid == 0) *sflag = 0;
+        if (tid == 0) {
+            *sflag = 0;
+            jfar = 0;
+        }
         __syncthreads();
         if (tid < 64) {   // largest squared norm, by wave 0, broadcast through nrm[n]
             double mx = 0.0;
@@ -625,23 +636,23 @@ __device__ __forceinline__ int wg_jacobi(double* Z, int m, int n, int ldz, doubl
                 const double al = nrm[p], be = nrm[q];
                 // entries per lane: the fewest that hold m rows (pairs of rows per
                 // 16-byte access when m and the leading dimension are even)
-                if (v2 && m <= 32) jac_pair_regs2<1>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
-                else if (v2 && m <= 64) jac_pair_regs2<2>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
-                else if (v2 && m <= 96) jac_pair_regs2<3>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
-                else if (v2 && m <= 128) jac_pair_regs2<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
-                else if (m <= 64) jac_pair_regs<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
-                else if (m <= 80) jac_pair_regs<5>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
-                else if (m <= 96) jac_pair_regs<6>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
-                else if (m <= 112) jac_pair_regs<7>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
-                else if (m <= 128) jac_pair_regs<8>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
-                else jac_pair_loop(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag);
+                if (v2 && m <= 32) jac_pair_regs2<1>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
+                else if (v2 && m <= 64) jac_pair_regs2<2>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
+                else if (v2 && m <= 96) jac_pair_regs2<3>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
+                else if (v2 && m <= 128) jac_pair_regs2<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
+                else if (m <= 64) jac_pair_regs<4>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
+                else if (m <= 80) jac_pair_regs<5>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
+                else if (m <= 96) jac_pair_regs<6>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
+                else if (m <= 112) jac_pair_regs<7>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
+                else if (m <= 128) jac_pair_regs<8>(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
+                else jac_pair_loop(zp, zq, m, ql, al, be, negl, tol, nrm + p, nrm + q, sflag, stop, &jfar);
             }
             __syncthreads();
         }
         ++sweep;
-        const int rotated = *sflag;
+        const int rotated = *sflag, far = jfar;
         __syncthreads();
-        if (!rotated) break;
+        if (!rotated || (stop > 0.0 && !far)) break;
     }
     // singular values, normalisation
     for (int j = qw; j < n; j += nq) {
@@ -1103,7 +1114,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small_det2(SmallArgs a) {
     double* sig = in_lds ? lds_vecs(lds, n) : a.vec;
     double* nrm = sig + n;
     int* ord = in_lds ? (int*)(nrm + n + 1) : a.ivec;
-    int sw = wg_jacobi(W, n, n, n, sig, ord, nrm, a.max_sweeps, &sflag);
+    int sw = wg_jacobi(W, n, n, n, sig, ord, nrm, a.max_sweeps, &sflag, nullptr, false, a.stop_cos2);
     if (tid == 0) {
         *a.sweeps = sw;
         if (sw > a.max_sweeps) *a.status |= DEV_NOCONV;
