@@ -2873,7 +2873,8 @@ __device__ __forceinline__ void split_mma_rows(const bf8_t* a, const bf8_t (*b)[
 
 template <int NKS, int S>
 constexpr size_t splitpass_lds_bytes() {
-    return ((size_t)S * 32 * (NKS * 32 + 24) + (size_t)S * FU_LB * 40 + (size_t)FU_LB * (NKS * 32 + 8)) * 2;
+    return ((size_t)S * 32 * (NKS * 32 + 24) + (size_t)S * FU_LB * 40 + (size_t)FU_LB * (NKS * 32 + 8)) * 2 +
+           (size_t)512 * 16;
 }
 
 template <int NKS, int S, bool KEEPY>
@@ -2894,6 +2895,7 @@ __global__ __launch_bounds__(512) void k_splitpass(FusedArgs a) {
     uint16_t* Cr = (uint16_t*)smem;                 // S terms, TM x ldR row-major each
     uint16_t* Ys = Cr + S * TM * ldR;               // S terms, 64 columns x ldY each
     uint16_t* Xl = Ys + S * FU_LB * ldY;            // last X term, 64 columns x ldX
+    f4_t* Ex = (f4_t*)(Xl + FU_LB * ldX);           // phase-A partial sums, one f4 per thread
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -2901,14 +2903,20 @@ __global__ __launch_bounds__(512) void k_splitpass(FusedArgs a) {
     if (fc.wg >= a.nwg) return;
     const int wg = fc.wg, lb = fc.lb;
     const int c0 = lb * FU_LB;
-    const int ib = w & 1, jb = w >> 1;
+    // phase A: wave w forms the 16 x 16 Y blocks (ib, 2 jp) and (ib, 2 jp + 1) over
+    // the k half kh and completes block (ib, jb = 2 jp + kh) with the partner
+    // wave's half (w ^ 4)
+    constexpr int KH = NKS / 2;
+    static_assert(NKS % 2 == 0, "k halves");
+    const int ib = w & 1, jp = (w >> 1) & 1, kh = w >> 2;
+    const int jb = 2 * jp + kh;
 
     // X terms 1 .. S-1 into registers (phase A B fragments of column block jb),
     // term S kept in LDS; the tile buffer stages one term at a time.  Rows
     // k >= n of X are zero: the panel columns past n (copies of column n - 1,
     // never zeroed) then add nothing to Y, and the rows of P they produce are
     // never read back.
-    bf8_t xr[S - 1][NKS];
+    bf8_t xr[S - 1][2][KH];
 #pragma unroll
     for (int t = 0; t < S - 1; ++t) {
         uint16_t* Xb = Cr;
@@ -2920,8 +2928,11 @@ __global__ __launch_bounds__(512) void k_splitpass(FusedArgs a) {
         });
         __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks)
-            xr[t][ks] = lds_b128(&Xb[(jb * 16 + (lane & 15)) * ldX + ks * 32 + 8 * (lane >> 4)]);
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int kk = 0; kk < KH; ++kk)
+                xr[t][j][kk] =
+                    lds_b128(&Xb[((2 * jp + j) * 16 + (lane & 15)) * ldX + (kh * KH + kk) * 32 + 8 * (lane >> 4)]);
         __syncthreads();
     }
 
@@ -2990,27 +3001,37 @@ __global__ __launch_bounds__(512) void k_splitpass(FusedArgs a) {
         lds_barrier();
         for (; t < a.tiles; t += nwg) {
             const bool more = t + nwg < a.tiles;
-            {   // phase A: Y block (ib, jb), terms accumulated apart (largest last)
-                f4_t y0 = f4_t{0.f, 0.f, 0.f, 0.f}, y1 = y0, y2 = y0;
-                const int ro = (ib * 16 + (lane & 15)) * ldR + 8 * (lane >> 4);
-                const int xo = (jb * 16 + (lane & 15)) * ldX + 8 * (lane >> 4);
+            {   // phase A: Y blocks (ib, 2 jp + j) over the k half, terms accumulated
+                // apart (largest last); the halves are added across the wave pair
+                f4_t y0[2], y1[2], y2[2];
 #pragma unroll
-                for (int ks = 0; ks < NKS; ++ks) {
-                    bf8_t c[S], x[S];
+                for (int j = 0; j < 2; ++j) y0[j] = y1[j] = y2[j] = f4_t{0.f, 0.f, 0.f, 0.f};
+                const int ro = (ib * 16 + (lane & 15)) * ldR + 8 * (lane >> 4);
+                const int xo = (2 * jp * 16 + (lane & 15)) * ldX + 8 * (lane >> 4);
+#pragma unroll
+                for (int kk = 0; kk < KH; ++kk) {
+                    const int ks = kh * KH + kk;
+                    bf8_t c[S];
 #pragma unroll
                     for (int s = 0; s < S; ++s) c[s] = lds_b128(&Cr[s * TM * ldR + ro + ks * 32]);
 #pragma unroll
-                    for (int s = 0; s < S - 1; ++s) x[s] = xr[s][ks];
-                    x[S - 1] = lds_b128(&Xl[xo + ks * 32]);
-                    // chains interleaved: consecutive MFMAs independent where possible
-                    if constexpr (S == 3) y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[2], x[0], y2, 0, 0, 0);
-                    y1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[1], x[0], y1, 0, 0, 0);
-                    y0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[0], y0, 0, 0, 0);
-                    if constexpr (S == 3) y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[1], x[1], y2, 0, 0, 0);
-                    y1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[1], y1, 0, 0, 0);
-                    if constexpr (S == 3) y2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[2], y2, 0, 0, 0);
+                    for (int j = 0; j < 2; ++j) {
+                        bf8_t x[S];
+#pragma unroll
+                        for (int s = 0; s < S - 1; ++s) x[s] = xr[s][j][kk];
+                        x[S - 1] = lds_b128(&Xl[xo + j * 16 * ldX + ks * 32]);
+                        if constexpr (S == 3) y2[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[2], x[0], y2[j], 0, 0, 0);
+                        y1[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[1], x[0], y1[j], 0, 0, 0);
+                        y0[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[0], y0[j], 0, 0, 0);
+                        if constexpr (S == 3) y2[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[1], x[1], y2[j], 0, 0, 0);
+                        y1[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[1], y1[j], 0, 0, 0);
+                        if constexpr (S == 3) y2[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c[0], x[2], y2[j], 0, 0, 0);
+                    }
                 }
-                f4_t y = y0 + (y1 + y2);
+                const f4_t ya = y0[0] + (y1[0] + y2[0]), yb = y0[1] + (y1[1] + y2[1]);
+                Ex[tid] = kh ? ya : yb;   // the half of the partner's block
+                lds_barrier();
+                f4_t y = (kh ? yb : ya) + Ex[tid ^ 256];
                 // rows r0 + v (r0 = 16 ib + 4 g) of column 16 jb + l, zero past the
                 // end, stored at the positions of the row order 8a + {0,2,4,6,1,3,5,7}:
                 // (v0, v2) and (v1, v3) are adjacent pairs there
@@ -3331,8 +3352,10 @@ hipError_t launch_split64(const FusedArgs& a, hipStream_t st) {
 }
 
 static size_t splitpass_lds(int np, int terms) {
-    // terms x (32 x (np + 24)) tile, terms x (64 x 40) Y, 64 x (np + 8) last X term (16-bit each)
-    return ((size_t)terms * 32 * (np + 24) + (size_t)terms * FU_LB * 40 + (size_t)FU_LB * (np + 8)) * 2;
+    // terms x (32 x (np + 24)) tile, terms x (64 x 40) Y, 64 x (np + 8) last X term (16-bit each),
+    // the phase-A partial sums exchanged between the two k halves (512 x 16 bytes)
+    return ((size_t)terms * 32 * (np + 24) + (size_t)terms * FU_LB * 40 + (size_t)FU_LB * (np + 8)) * 2 +
+           (size_t)512 * 16;
 }
 
 bool splitpass_plan(int n, int terms, FusedPlan* p) {
